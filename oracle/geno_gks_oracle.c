@@ -1,0 +1,1206 @@
+/*
+ * CPU FP64 oracle of the compact gas-kinetic scheme with GENO reconstruction
+ * (Zhao & Xu, "A generalized ENO reconstruction in compact GKS for
+ * compressible flow simulations").
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE. Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load this library. It shares
+ * no code, header, table or constant with the HIP library: every weight it
+ * uses is obtained here by solving the defining moment systems, the GKS
+ * moments come from a generic polynomial-times-Maxwellian integrator, and the
+ * micro-slopes are solved by Gaussian elimination rather than closed forms.
+ *
+ * Paper passages followed (equation numbers of the paper):
+ *   Sec. 2   Eq. (1)  finite-volume update; face integrals by Gauss quadrature
+ *   Sec. 2   Eq. (2)  cell-averaged gradients from the Gauss theorem
+ *   Sec. 3   Eq. (3)  GENO blend R = chi q^H + (1-chi) q^L
+ *   Sec. 3.1 Eq. (4)  path function chi = tanh(C alpha)/tanh(C)
+ *   Sec. 3.2 Eq. (5)  ultimate smoothness indicator alpha
+ *   Sec. 3.2 Eq. (6)-(7) IS of Jiang-Shu type; IS^H = Max{IS_k}
+ *   Sec. 3.3 Eq. (8)  ENO low-order combination q^L; Eq. (9) IS^L = Min{IS_k}
+ *   Sec. 4.2 Eq. (13)-(14) 8th-order compact stencils S_0..S_3 and IS^tau
+ * The paper defers the GKS flux, the two-stage fourth-order (S2O4) time
+ * stepping, ghost cells, the collision time and the 2-D structured scheme to
+ * the literature. Those parts follow the standard BGK interface solution of
+ * high-order GKS and are marked "reading" where they are defined below.
+ *
+ * Layout of every state array handed in: SoA, interior cells only,
+ * [field][ny][nx] (1-D: ny = 1). Gradients are physical (not h-scaled).
+ * Fields 1-D: W = (rho, rhoU, rhoE), dW = (d_x W).
+ * Fields 2-D: W = (rho, rhoU, rhoV, rhoE), dW = (d_x W[4], d_y W[4]).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+
+#define OR_OK 0
+#define OR_EINVAL -1
+#define OR_ENOMEM -2
+
+/* ---------------------------------------------------------------------- */
+/* Parameters (plain double array from the caller)                         */
+/* ---------------------------------------------------------------------- */
+enum {
+  PI_GAMMA = 0, PI_CPATH, PI_EPS, PI_R, PI_RL, PI_D1, PI_D2, PI_D3,
+  PI_TAUC1, PI_TAUC2, PI_CFL, PI_BCXL, PI_BCXH, PI_BCYL, PI_BCYH, PI_COUNT
+};
+
+typedef struct {
+  double gamma, Cpath, eps, r, rL, d[3], tc1, tc2, cfl;
+  int bc[4];           /* 0 periodic, 1 transmissive: x-lo, x-hi, y-lo, y-hi */
+  int ndim, nx, ny;
+  double dx, dy;
+  double K;            /* internal degrees of freedom of the BGK model */
+  int nv;              /* conserved variables: 3 in 1-D, 4 in 2-D */
+} ocfg;
+
+static void cfg_from(ocfg *c, int ndim, int nx, int ny, double dx, double dy,
+                     const double *p) {
+  c->gamma = p[PI_GAMMA]; c->Cpath = p[PI_CPATH]; c->eps = p[PI_EPS];
+  c->r = p[PI_R]; c->rL = p[PI_RL];
+  c->d[0] = p[PI_D1]; c->d[1] = p[PI_D2]; c->d[2] = p[PI_D3];
+  c->tc1 = p[PI_TAUC1]; c->tc2 = p[PI_TAUC2]; c->cfl = p[PI_CFL];
+  for (int i = 0; i < 4; ++i) c->bc[i] = (int)p[PI_BCXL + i];
+  c->ndim = ndim; c->nx = nx; c->ny = (ndim == 1) ? 1 : ny;
+  c->dx = dx; c->dy = dy;
+  /* Internal degrees of freedom so that gamma = (K + D + 2)/(K + D) with
+   * D translational dimensions carried explicitly (reading: standard GKS). */
+  c->K = (ndim == 1) ? (3.0 - c->gamma) / (c->gamma - 1.0)
+                     : (4.0 - 2.0 * c->gamma) / (c->gamma - 1.0);
+  c->nv = (ndim == 1) ? 3 : 4;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Small dense solver (Gaussian elimination with partial pivoting)         */
+/* ---------------------------------------------------------------------- */
+/* Solves A x = b in place (A is n x n row-major, destroyed). long double
+ * variant used once at start-up for the reconstruction operators. */
+static int solve_ld(int n, long double *A, long double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabsl(A[i * n + k]) > fabsl(A[piv * n + k])) piv = i;
+    if (A[piv * n + k] == 0.0L) return -1;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) {
+        long double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t;
+      }
+      long double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      long double f = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    long double s = b[k];
+    for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * b[j];
+    b[k] = s / A[k * n + k];
+  }
+  return 0;
+}
+
+/* Same in double, for the per-point 3x3 / 4x4 micro-slope systems. */
+static int solve_d(int n, double *A, double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+    if (A[piv * n + k] == 0.0) return -1;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t;
+      }
+      double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      double f = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * b[j];
+    b[k] = s / A[k * n + k];
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Reconstruction operators, obtained by solving the defining systems       */
+/* ---------------------------------------------------------------------- */
+/* Average over [a, b] of y^k, and of d/dy (y^k). */
+static long double avg_mono(int k, long double a, long double b) {
+  return (powl(b, k + 1) - powl(a, k + 1)) / ((long double)(k + 1) * (b - a));
+}
+static long double avg_dmono(int k, long double a, long double b) {
+  if (k == 0) return 0.0L;
+  return (powl(b, k) - powl(a, k)) / (b - a);
+}
+
+/* Linear high-order reconstruction p^7 (Sec. 4.2, stencil S_0 = {j-1..j+2}):
+ * the degree-7 polynomial whose averages and averaged h-scaled derivatives
+ * match those of the four cells. Coordinate y = (x - x_{j+1/2})/h, cell j-1+m
+ * occupies [m-2, m-1]. Data order: (Q_{-1}, G_{-1}, Q_0, G_0, Q_1, G_1, Q_2, G_2),
+ * G = h * (cell-averaged derivative). H_val / H_der: weights of the face
+ * value and of h times the face derivative. */
+static double H_val[8], H_der[8];
+
+/* Low-order sub-stencil quadratics p_k (Sec. 4.2, S_1 = {j-1, j} with the
+ * gradient of cell j-1, S_2 = {j-1, j, j+1}, S_3 = {j, j+1, j+2}) for the
+ * cell c on side s of the face (s = +1: face on the right of c, left state;
+ * s = -1: face on the left of c, right state; the stencils are mirrored).
+ * Coordinate xi = (x - x_c)/h. SUB[s][k][coef][datum] maps the data of cells
+ * c-2..c+2 (order Q_{c-2}, G_{c-2}, ..., Q_{c+2}, G_{c+2}) to the monomial
+ * coefficients of p_k. */
+static double SUB[2][3][3][10];
+
+/* Quadratic through three averages over [-3/2,-1/2], [-1/2,1/2], [1/2,3/2]
+ * (tangential high-order candidate): TQ[coef][datum]. */
+static double TQ[3][3];
+
+static int ops_ready = 0;
+static void build_psi(void);
+
+static int build_ops(void) {
+  /* p^7 */
+  {
+    long double A[64], rhs[8];
+    double Hv[8], Hd[8];
+    for (int col = 0; col < 8; ++col) {
+      /* column col of the inverse: solve with unit right-hand side */
+      for (int m = 0; m < 4; ++m) {
+        long double a = (long double)(m - 2), b = (long double)(m - 1);
+        for (int k = 0; k < 8; ++k) {
+          A[(2 * m) * 8 + k] = avg_mono(k, a, b);
+          A[(2 * m + 1) * 8 + k] = avg_dmono(k, a, b);
+        }
+      }
+      for (int i = 0; i < 8; ++i) rhs[i] = (i == col) ? 1.0L : 0.0L;
+      if (solve_ld(8, A, rhs)) return -1;
+      Hv[col] = (double)rhs[0];           /* p(0) */
+      Hd[col] = (double)rhs[1];           /* h p'(0) */
+    }
+    memcpy(H_val, Hv, sizeof Hv);
+    memcpy(H_der, Hd, sizeof Hd);
+  }
+  /* quadratics */
+  for (int si = 0; si < 2; ++si) {
+    int s = (si == 0) ? +1 : -1;
+    for (int k = 0; k < 3; ++k) {
+      /* constraints: list of (cell offset, kind) kind 0 = average, 1 = derivative average */
+      int off[3], kind[3];
+      if (k == 0) { off[0] = -s; kind[0] = 0; off[1] = -s; kind[1] = 1; off[2] = 0; kind[2] = 0; }
+      else if (k == 1) { off[0] = -1; kind[0] = 0; off[1] = 0; kind[1] = 0; off[2] = 1; kind[2] = 0; }
+      else { off[0] = 0; kind[0] = 0; off[1] = s; kind[1] = 0; off[2] = 2 * s; kind[2] = 0; }
+      for (int col = 0; col < 3; ++col) {
+        long double A[9], rhs[3];
+        for (int row = 0; row < 3; ++row) {
+          long double a = off[row] - 0.5L, b = off[row] + 0.5L;
+          for (int q = 0; q < 3; ++q)
+            A[row * 3 + q] = kind[row] ? avg_dmono(q, a, b) : avg_mono(q, a, b);
+        }
+        for (int i = 0; i < 3; ++i) rhs[i] = (i == col) ? 1.0L : 0.0L;
+        if (solve_ld(3, A, rhs)) return -1;
+        /* constraint col refers to datum index 2*(off+2) + kind */
+        int datum = 2 * (off[col] + 2) + kind[col];
+        for (int q = 0; q < 3; ++q) {
+          /* accumulate (each datum appears in at most one constraint) */
+          SUB[si][k][q][datum] = (double)rhs[q];
+        }
+      }
+    }
+  }
+  /* tangential quadratic */
+  for (int col = 0; col < 3; ++col) {
+    long double A[9], rhs[3];
+    for (int row = 0; row < 3; ++row)
+      for (int q = 0; q < 3; ++q) A[row * 3 + q] = avg_mono(q, row - 1.5L, row - 0.5L);
+    for (int i = 0; i < 3; ++i) rhs[i] = (i == col) ? 1.0L : 0.0L;
+    if (solve_ld(3, A, rhs)) return -1;
+    for (int q = 0; q < 3; ++q) TQ[q][col] = (double)rhs[q];
+  }
+  build_psi();
+  ops_ready = 1;
+  return 0;
+}
+
+/* 3-point Gauss-Legendre on [-1/2, 1/2]: exact for degree <= 5. */
+static const double GL3_X[3] = {-0.38729833462074168852, 0.0, 0.38729833462074168852};
+static const double GL3_W[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+/* Smoothness indicator of a quadratic c0 + c1 xi + c2 xi^2 on its own cell,
+ * Eq. (6) with m = 1 and derivatives up to order 2 (a quadratic has no
+ * third derivative): sum_l h^(2l-1) int (d^l p/dx^l)^2 dx, in xi units. */
+static double is_quadratic(const double c[3]) {
+  double s = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    double x = GL3_X[q];
+    double d1 = c[1] + 2.0 * c[2] * x;
+    double d2 = 2.0 * c[2];
+    s += GL3_W[q] * (d1 * d1 + d2 * d2);
+  }
+  return s;
+}
+
+/* ---------------------------------------------------------------------- */
+/* GENO at one face for one side and one conserved component               */
+/* ---------------------------------------------------------------------- */
+/* Ultimate smoothness indicator and path function, Eq. (4)-(5). */
+static double path_function(const ocfg *P, double IStau, double ISH, double ISL) {
+  double aH = 1.0 + pow(IStau / (ISH + P->eps), P->r);
+  double aL = 1.0 + pow(IStau / (ISL + P->eps), P->r);
+  double alpha = 2.0 * aH / (aH + aL);
+  return tanh(P->Cpath * alpha) / tanh(P->Cpath);
+}
+
+/* dat: Q_{c-2}, G_{c-2}, ..., Q_{c+2}, G_{c+2} about the reconstructing cell
+ * c; si = 0 for the left state (face at xi = +1/2), 1 for the right state
+ * (face at xi = -1/2). qH, hqH: shared linear value and h * derivative.
+ * Output: value, h * derivative and chi at the face. */
+static void geno_side(const ocfg *P, const double dat[10], int si, double qH, double hqH,
+                      double *val, double *hder, double *chi_out) {
+  double xf = (si == 0) ? 0.5 : -0.5;
+  double c[3][3], IS[3], pv[3], pd[3];
+  for (int k = 0; k < 3; ++k) {
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+      for (int m = 0; m < 10; ++m) s += SUB[si][k][q][m] * dat[m];
+      c[k][q] = s;
+    }
+    IS[k] = is_quadratic(c[k]);
+    pv[k] = c[k][0] + c[k][1] * xf + c[k][2] * xf * xf;
+    pd[k] = c[k][1] + 2.0 * c[k][2] * xf;
+  }
+  /* Eq. (7) and Eq. (9): structured-mesh IS^H and IS^L */
+  double ISH = IS[0], ISL = IS[0];
+  for (int k = 1; k < 3; ++k) { if (IS[k] > ISH) ISH = IS[k]; if (IS[k] < ISL) ISL = IS[k]; }
+  /* Eq. (14): IS^tau of the 8th-order compact scheme */
+  double IStau = fabs((IS[1] + IS[2]) / 2.0 - IS[0]);
+  double chi = path_function(P, IStau, ISH, ISL);
+  /* Eq. (8): ENO combination of the sub-stencil polynomials */
+  double wt[3], wsum = 0.0;
+  for (int k = 0; k < 3; ++k) { wt[k] = P->d[k] / pow(IS[k] + P->eps, P->rL); wsum += wt[k]; }
+  double qL = 0.0, hqL = 0.0;
+  for (int k = 0; k < 3; ++k) { qL += (wt[k] / wsum) * pv[k]; hqL += (wt[k] / wsum) * pd[k]; }
+  /* Eq. (3) and Eq. (13), same weights for the derivative */
+  *val = chi * qH + (1.0 - chi) * qL;
+  *hder = chi * hqH + (1.0 - chi) * hqL;
+  *chi_out = chi;
+}
+
+/* Full GENO at face j+1/2 for one component. q[0..3] = averages of cells
+ * j-1..j+2 (stencil S_0), g[0..3] = their h-scaled averaged derivatives. */
+static void geno_face(const ocfg *P, const double q[4], const double g[4],
+                      double out_l[3], double out_r[3]) {
+  /* linear part: one polynomial per face, shared by both sides (Sec. 4.2) */
+  double qH = 0.0, hqH = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    qH += H_val[2 * m] * q[m] + H_val[2 * m + 1] * g[m];
+    hqH += H_der[2 * m] * q[m] + H_der[2 * m + 1] * g[m];
+  }
+  /* data about the reconstructing cell: left state uses cells j-2..j+2
+   * (j-2 carries zero weight), right state cells j-1..j+3 (j+3 zero weight) */
+  double dl[10] = {0}, dr[10] = {0};
+  for (int m = 0; m < 4; ++m) {
+    dl[2 * (m + 1)] = q[m]; dl[2 * (m + 1) + 1] = g[m];
+    dr[2 * m] = q[m]; dr[2 * m + 1] = g[m];
+  }
+  geno_side(P, dl, 0, qH, hqH, &out_l[0], &out_l[1], &out_l[2]);
+  geno_side(P, dr, 1, qH, hqH, &out_r[0], &out_r[1], &out_r[2]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Ghost cells (reading: the paper only names the boundary conditions)     */
+/* ---------------------------------------------------------------------- */
+#define NG 2
+
+typedef struct {
+  int nxt, nyt;        /* padded sizes */
+  double *W, *dW;      /* [nv][nyt][nxt], [ndim*nv][nyt][nxt] */
+} gstate;
+
+static inline size_t gidx(const gstate *g, int f, int j, int i) {
+  return ((size_t)f * g->nyt + j) * g->nxt + i;
+}
+
+static int gstate_alloc(const ocfg *P, gstate *g) {
+  g->nxt = P->nx + 2 * NG;
+  g->nyt = (P->ndim == 1) ? 1 : P->ny + 2 * NG;
+  size_t n = (size_t)g->nxt * g->nyt;
+  g->W = (double *)calloc(n * P->nv, sizeof(double));
+  g->dW = (double *)calloc(n * P->nv * P->ndim, sizeof(double));
+  return (g->W && g->dW) ? 0 : -1;
+}
+static void gstate_free(gstate *g) { free(g->W); free(g->dW); }
+
+static void gstate_load(const ocfg *P, gstate *g, const double *W, const double *dW) {
+  int oy = (P->ndim == 1) ? 0 : NG;
+  for (int f = 0; f < P->nv; ++f)
+    for (int j = 0; j < P->ny; ++j)
+      for (int i = 0; i < P->nx; ++i)
+        g->W[gidx(g, f, j + oy, i + NG)] = W[((size_t)f * P->ny + j) * P->nx + i];
+  for (int f = 0; f < P->nv * P->ndim; ++f)
+    for (int j = 0; j < P->ny; ++j)
+      for (int i = 0; i < P->nx; ++i)
+        g->dW[gidx(g, f, j + oy, i + NG)] = dW[((size_t)f * P->ny + j) * P->nx + i];
+}
+
+/* Periodic: ghost cells copy the periodic image (values and all gradients).
+ * Transmissive: ghost value = nearest interior cell, ghost gradient normal to
+ * that boundary = 0, tangential gradient = nearest interior cell.
+ * 2-D: x-ghosts of the interior rows first, then y-ghosts of every column,
+ * which fills the corners. */
+static void fill_ghosts(const ocfg *P, gstate *g) {
+  int nv = P->nv, nx = P->nx, ny = P->ny;
+  int oy = (P->ndim == 1) ? 0 : NG;
+  int j0 = oy, j1 = oy + ny;
+  for (int j = j0; j < j1; ++j) {
+    for (int gl = 1; gl <= NG; ++gl) {
+      int il = NG - gl, ih = NG + nx - 1 + gl;          /* ghost columns */
+      int sl, sh;
+      if (P->bc[0] == 0) sl = NG + nx - gl; else sl = NG;
+      if (P->bc[1] == 0) sh = NG + gl - 1; else sh = NG + nx - 1;
+      for (int f = 0; f < nv; ++f) {
+        g->W[gidx(g, f, j, il)] = g->W[gidx(g, f, j, sl)];
+        g->W[gidx(g, f, j, ih)] = g->W[gidx(g, f, j, sh)];
+      }
+      for (int d = 0; d < P->ndim; ++d)
+        for (int f = 0; f < nv; ++f) {
+          int ff = d * nv + f;
+          double vl = g->dW[gidx(g, ff, j, sl)], vh = g->dW[gidx(g, ff, j, sh)];
+          if (d == 0 && P->bc[0] != 0) vl = 0.0;
+          if (d == 0 && P->bc[1] != 0) vh = 0.0;
+          g->dW[gidx(g, ff, j, il)] = vl;
+          g->dW[gidx(g, ff, j, ih)] = vh;
+        }
+    }
+  }
+  if (P->ndim == 1) return;
+  for (int i = 0; i < g->nxt; ++i) {
+    for (int gl = 1; gl <= NG; ++gl) {
+      int jl = NG - gl, jh = NG + ny - 1 + gl;
+      int sl, sh;
+      if (P->bc[2] == 0) sl = NG + ny - gl; else sl = NG;
+      if (P->bc[3] == 0) sh = NG + gl - 1; else sh = NG + ny - 1;
+      for (int f = 0; f < nv; ++f) {
+        g->W[gidx(g, f, jl, i)] = g->W[gidx(g, f, sl, i)];
+        g->W[gidx(g, f, jh, i)] = g->W[gidx(g, f, sh, i)];
+      }
+      for (int d = 0; d < 2; ++d)
+        for (int f = 0; f < nv; ++f) {
+          int ff = d * nv + f;
+          double vl = g->dW[gidx(g, ff, sl, i)], vh = g->dW[gidx(g, ff, sh, i)];
+          if (d == 1 && P->bc[2] != 0) vl = 0.0;
+          if (d == 1 && P->bc[3] != 0) vh = 0.0;
+          g->dW[gidx(g, ff, jl, i)] = vl;
+          g->dW[gidx(g, ff, jh, i)] = vh;
+        }
+    }
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* GKS flux at one point (reading: standard BGK interface solution)        */
+/* ---------------------------------------------------------------------- */
+/* Polynomials in (u, v, z) with z = xi^2 (sum of squared internal
+ * velocities), stored as a list of terms c * u^i v^j z^k.
+ * Degree bounds: u <= 7, v <= 5, z <= 2. */
+#define DU 8
+#define DV 6
+#define DZ 3
+#define MAXT 128
+typedef struct { int n; unsigned char e[MAXT][3]; double c[MAXT]; } poly;
+
+static void poly_zero(poly *p) { p->n = 0; }
+
+/* adds c u^i v^j z^k, merging with an existing term of the same monomial */
+static void poly_add_term(poly *p, int i, int j, int k, double c) {
+  if (i >= DU || j >= DV || k >= DZ) abort();        /* degree bound exceeded */
+  for (int t = 0; t < p->n; ++t)
+    if (p->e[t][0] == i && p->e[t][1] == j && p->e[t][2] == k) { p->c[t] += c; return; }
+  if (p->n >= MAXT) abort();
+  p->e[p->n][0] = (unsigned char)i; p->e[p->n][1] = (unsigned char)j; p->e[p->n][2] = (unsigned char)k;
+  p->c[p->n] = c; ++p->n;
+}
+
+static void poly_add(poly *p, const poly *q, double s) {
+  for (int t = 0; t < q->n; ++t) poly_add_term(p, q->e[t][0], q->e[t][1], q->e[t][2], s * q->c[t]);
+}
+
+static void poly_mul(const poly *a, const poly *b, poly *out) {
+  poly r; poly_zero(&r);
+  for (int x = 0; x < a->n; ++x)
+    for (int y = 0; y < b->n; ++y)
+      poly_add_term(&r, a->e[x][0] + b->e[y][0], a->e[x][1] + b->e[y][1], a->e[x][2] + b->e[y][2],
+                    a->c[x] * b->c[y]);
+  *out = r;
+}
+
+/* Moments of a Maxwellian normalised by its density, over all velocities or
+ * over one half-space of u. */
+typedef struct { double mu[DU], mv[DV], mz[DZ]; } mtab;
+
+/* half: 0 full space, +1 for u > 0, -1 for u < 0 */
+static void moments(double U, double V, double lam, double K, int half, int has_v, mtab *m) {
+  if (half == 0) { m->mu[0] = 1.0; m->mu[1] = U; }
+  else {
+    double t0 = 0.5 * erfc(-half * sqrt(lam) * U);
+    double t1 = exp(-lam * U * U) / (2.0 * sqrt(M_PI * lam));
+    m->mu[0] = t0;
+    m->mu[1] = U * t0 + half * t1;
+  }
+  for (int n = 0; n + 2 < DU; ++n)
+    m->mu[n + 2] = U * m->mu[n + 1] + (n + 1) / (2.0 * lam) * m->mu[n];
+  for (int n = 0; n < DV; ++n) m->mv[n] = 0.0;
+  m->mv[0] = 1.0;
+  if (has_v) {
+    m->mv[1] = V;
+    for (int n = 0; n + 2 < DV; ++n)
+      m->mv[n + 2] = V * m->mv[n + 1] + (n + 1) / (2.0 * lam) * m->mv[n];
+  }
+  m->mz[0] = 1.0;
+  m->mz[1] = K / (2.0 * lam);
+  m->mz[2] = K * (K + 2.0) / (4.0 * lam * lam);
+}
+
+static double poly_moment(const poly *p, const mtab *m) {
+  double s = 0.0;
+  for (int t = 0; t < p->n; ++t) s += p->c[t] * m->mu[p->e[t][0]] * m->mv[p->e[t][1]] * m->mz[p->e[t][2]];
+  return s;
+}
+
+/* collision invariants psi = (1, u, [v,] (u^2 [+ v^2] + z)/2) */
+static void psi_poly(int nv, int k, poly *p) {
+  poly_zero(p);
+  if (k == 0) poly_add_term(p, 0, 0, 0, 1.0);
+  else if (k == 1) poly_add_term(p, 1, 0, 0, 1.0);
+  else if (k == 2 && nv == 4) poly_add_term(p, 0, 1, 0, 1.0);
+  else {
+    poly_add_term(p, 2, 0, 0, 0.5); poly_add_term(p, 0, 0, 1, 0.5);
+    if (nv == 4) poly_add_term(p, 0, 2, 0, 0.5);
+  }
+}
+
+/* psi_k and psi_i psi_k as polynomials, built once (index 0: 1-D, 1: 2-D) */
+static poly PSI[2][4], PSIPSI[2][4][4];
+static void build_psi(void) {
+  for (int d = 0; d < 2; ++d) {
+    int nv = d ? 4 : 3;
+    for (int k = 0; k < nv; ++k) psi_poly(nv, k, &PSI[d][k]);
+    for (int i = 0; i < nv; ++i)
+      for (int k = 0; k < nv; ++k) poly_mul(&PSI[d][i], &PSI[d][k], &PSIPSI[d][i][k]);
+  }
+}
+
+/* a . psi as a polynomial */
+static void slope_poly(int nv, const double *a, poly *p) {
+  poly_zero(p);
+  for (int k = 0; k < nv; ++k) poly_add(p, &PSI[nv == 4][k], a[k]);
+}
+
+/* <w psi_k> for k = 0..nv-1 */
+static void moment_vec(int nv, const poly *w, const mtab *m, double *out) {
+  for (int k = 0; k < nv; ++k) {
+    poly r; poly_mul(w, &PSI[nv == 4][k], &r);
+    out[k] = poly_moment(&r, m);
+  }
+}
+
+typedef struct { double rho, U, V, lam; } prim;
+
+static prim to_prim(const ocfg *P, const double *W) {
+  prim p;
+  p.rho = W[0];
+  p.U = W[1] / W[0];
+  p.V = (P->nv == 4) ? W[2] / W[0] : 0.0;
+  double rE = W[P->nv - 1];
+  double pr = (P->gamma - 1.0) * (rE - 0.5 * p.rho * (p.U * p.U + p.V * p.V));
+  p.lam = p.rho / (2.0 * pr);
+  return p;
+}
+
+/* micro slope a with <a psi> = w over the full-space Maxwellian of pr:
+ * Gaussian elimination on the moment matrix M_ik = <psi_i psi_k>. */
+static void micro_slope(const ocfg *P, const prim *pr, const double *w, double *a) {
+  int nv = P->nv;
+  mtab m; moments(pr->U, pr->V, pr->lam, P->K, 0, nv == 4, &m);
+  double A[16], b[4];
+  for (int i = 0; i < nv; ++i) {
+    for (int k = 0; k < nv; ++k) A[i * nv + k] = poly_moment(&PSIPSI[nv == 4][i][k], &m);
+    b[i] = w[i];
+  }
+  solve_d(nv, A, b);
+  for (int i = 0; i < nv; ++i) a[i] = b[i];
+}
+
+/* Time derivative A from the compatibility condition
+ * <(a u + b v + A) psi> = 0 over the full-space Maxwellian of pr. */
+static void time_slope(const ocfg *P, const prim *pr, const double *a, const double *b, double *At) {
+  int nv = P->nv;
+  mtab m; moments(pr->U, pr->V, pr->lam, P->K, 0, nv == 4, &m);
+  poly pa, pb, ua, vb, s, u1, v1;
+  slope_poly(nv, a, &pa);
+  poly_zero(&u1); poly_add_term(&u1, 1, 0, 0, 1.0);
+  poly_mul(&pa, &u1, &ua);
+  s = ua;
+  if (nv == 4) {
+    slope_poly(nv, b, &pb);
+    poly_zero(&v1); poly_add_term(&v1, 0, 1, 0, 1.0);
+    poly_mul(&pb, &v1, &vb);
+    poly_add(&s, &vb, 1.0);
+  }
+  double rhs[4]; moment_vec(nv, &s, &m, rhs);
+  for (int k = 0; k < nv; ++k) rhs[k] = -rhs[k];
+  micro_slope(P, pr, rhs, At);
+}
+
+/* Integrated flux over [0, delta] and the interface state at t = delta of
+ * the BGK solution
+ *   f = (1 - e) g0 + ((t+tau) e - tau)(abar u + bbar v) g0 + (t - tau(1 - e)) Abar g0
+ *     + e sum_s H_s g_s [1 - (t + tau)(a_s u + b_s v) - tau A_s],  e = exp(-t/tau)
+ * at one point of a face. Inputs are in the face frame (normal velocity
+ * first). dn*, dt*: physical normal / tangential derivatives of the left and
+ * right conserved states. Outputs the fitted F, dF/dt (from delta = dt/2
+ * and dt) and W(dt/2). */
+static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
+                      const double *dnl, const double *dnr, const double *dtl,
+                      const double *dtr, double dt, double *F, double *Ft, double *Wi) {
+  int nv = P->nv, has_v = (nv == 4);
+  double K = P->K;
+  prim pl = to_prim(P, Wl), pr = to_prim(P, Wr);
+  mtab ml_half, mr_half;
+  moments(pl.U, pl.V, pl.lam, K, +1, has_v, &ml_half);
+  moments(pr.U, pr.V, pr.lam, K, -1, has_v, &mr_half);
+  /* interface equilibrium W^c from the half-space sums */
+  poly one; poly_zero(&one); poly_add_term(&one, 0, 0, 0, 1.0);
+  double hl[4], hr[4], Wc[4];
+  moment_vec(nv, &one, &ml_half, hl);
+  moment_vec(nv, &one, &mr_half, hr);
+  for (int k = 0; k < nv; ++k) Wc[k] = pl.rho * hl[k] + pr.rho * hr[k];
+  prim pc = to_prim(P, Wc);
+  mtab mc; moments(pc.U, pc.V, pc.lam, K, 0, has_v, &mc);
+
+  /* spatial micro-slopes */
+  double w[4] = {0, 0, 0, 0}, al[4], ar[4], bl[4] = {0, 0, 0, 0}, br[4] = {0, 0, 0, 0};
+  double ac[4], bc[4] = {0, 0, 0, 0};
+  for (int k = 0; k < nv; ++k) w[k] = dnl[k] / pl.rho;
+  micro_slope(P, &pl, w, al);
+  for (int k = 0; k < nv; ++k) w[k] = dnr[k] / pr.rho;
+  micro_slope(P, &pr, w, ar);
+  for (int k = 0; k < nv; ++k) w[k] = 0.5 * (dnl[k] + dnr[k]) / pc.rho;
+  micro_slope(P, &pc, w, ac);
+  if (has_v) {
+    for (int k = 0; k < nv; ++k) w[k] = dtl[k] / pl.rho;
+    micro_slope(P, &pl, w, bl);
+    for (int k = 0; k < nv; ++k) w[k] = dtr[k] / pr.rho;
+    micro_slope(P, &pr, w, br);
+    for (int k = 0; k < nv; ++k) w[k] = 0.5 * (dtl[k] + dtr[k]) / pc.rho;
+    micro_slope(P, &pc, w, bc);
+  }
+  /* time slopes from compatibility */
+  double Al[4], Ar[4], Ac[4];
+  time_slope(P, &pl, al, bl, Al);
+  time_slope(P, &pr, ar, br, Ar);
+  time_slope(P, &pc, ac, bc, Ac);
+
+  /* moment vectors */
+  poly u1, v1, pa, pb, t1, t2, uone;
+  poly_zero(&u1); poly_add_term(&u1, 1, 0, 0, 1.0);
+  poly_zero(&v1); poly_add_term(&v1, 0, 1, 0, 1.0);
+  uone = u1;
+  /* (a u + b v) polynomial for a given pair */
+  #define SPACE_POLY(A_, B_, OUT_) do { \
+      slope_poly(nv, A_, &pa); poly_mul(&pa, &u1, &t1); OUT_ = t1; \
+      if (has_v) { slope_poly(nv, B_, &pb); poly_mul(&pb, &v1, &t2); poly_add(&OUT_, &t2, 1.0); } \
+    } while (0)
+
+  poly sc, sl, sr, Acp, Alp, Arp, tmp;
+  SPACE_POLY(ac, bc, sc);
+  SPACE_POLY(al, bl, sl);
+  SPACE_POLY(ar, br, sr);
+  slope_poly(nv, Ac, &Acp);
+  slope_poly(nv, Al, &Alp);
+  slope_poly(nv, Ar, &Arp);
+
+  /* flux moments <u X psi> and state moments <X psi> */
+  double c_u[4], c_us[4], c_uA[4], c_1[4], c_s[4], c_A[4];
+  double l_u[4], l_us[4], l_uA[4], l_1[4], l_s[4], l_A[4];
+  double r_u[4], r_us[4], r_uA[4], r_1[4], r_s[4], r_A[4];
+  moment_vec(nv, &uone, &mc, c_u);
+  poly_mul(&sc, &u1, &tmp); moment_vec(nv, &tmp, &mc, c_us);
+  poly_mul(&Acp, &u1, &tmp); moment_vec(nv, &tmp, &mc, c_uA);
+  moment_vec(nv, &one, &mc, c_1);
+  moment_vec(nv, &sc, &mc, c_s);
+  moment_vec(nv, &Acp, &mc, c_A);
+  moment_vec(nv, &uone, &ml_half, l_u);
+  poly_mul(&sl, &u1, &tmp); moment_vec(nv, &tmp, &ml_half, l_us);
+  poly_mul(&Alp, &u1, &tmp); moment_vec(nv, &tmp, &ml_half, l_uA);
+  moment_vec(nv, &one, &ml_half, l_1);
+  moment_vec(nv, &sl, &ml_half, l_s);
+  moment_vec(nv, &Alp, &ml_half, l_A);
+  moment_vec(nv, &uone, &mr_half, r_u);
+  poly_mul(&sr, &u1, &tmp); moment_vec(nv, &tmp, &mr_half, r_us);
+  poly_mul(&Arp, &u1, &tmp); moment_vec(nv, &tmp, &mr_half, r_uA);
+  moment_vec(nv, &one, &mr_half, r_1);
+  moment_vec(nv, &sr, &mr_half, r_s);
+  moment_vec(nv, &Arp, &mr_half, r_A);
+  #undef SPACE_POLY
+
+  /* collision time (reading): tau = C1 dt + C2 dt |pl - pr| / (pl + pr) */
+  double prl = pl.rho / (2.0 * pl.lam), prr = pr.rho / (2.0 * pr.lam);
+  double tau = P->tc1 * dt + P->tc2 * dt * fabs(prl - prr) / (prl + prr);
+
+  double Fd[2][4];
+  for (int q = 0; q < 2; ++q) {
+    double del = (q == 0) ? 0.5 * dt : dt;
+    double c1, c2, c3, c4, c5, c6;
+    if (tau > 0.0) {
+      double e = exp(-del / tau);
+      double em = -expm1(-del / tau);
+      /* time integrals of the weights of the BGK solution over [0, del] */
+      c1 = del - tau * em;
+      c5 = 2.0 * tau * tau - tau * (del + 2.0 * tau) * e;
+      c2 = c5 - tau * del;
+      c3 = 0.5 * del * del - tau * del + tau * tau * em;
+      c4 = tau * em;
+      c6 = tau * tau * em;
+    } else {
+      c1 = del; c2 = 0.0; c3 = 0.5 * del * del; c4 = 0.0; c5 = 0.0; c6 = 0.0;
+    }
+    for (int k = 0; k < nv; ++k) {
+      Fd[q][k] = pc.rho * (c1 * c_u[k] + c2 * c_us[k] + c3 * c_uA[k])
+               + pl.rho * (c4 * l_u[k] - c5 * l_us[k] - c6 * l_uA[k])
+               + pr.rho * (c4 * r_u[k] - c5 * r_us[k] - c6 * r_uA[k]);
+    }
+  }
+  /* fit F(t) = F + t dF/dt to the two integrals */
+  for (int k = 0; k < nv; ++k) {
+    F[k] = (4.0 * Fd[0][k] - Fd[1][k]) / dt;
+    Ft[k] = 4.0 * (Fd[1][k] - 2.0 * Fd[0][k]) / (dt * dt);
+  }
+  /* interface state at t = dt/2 */
+  {
+    double del = 0.5 * dt, e, em, k1, k2, k3, k4, k5;
+    if (tau > 0.0) {
+      e = exp(-del / tau); em = -expm1(-del / tau);
+      k1 = em; k2 = (del + tau) * e - tau; k3 = del - tau * em;
+      k4 = del + tau; k5 = tau;
+    } else {
+      e = 0.0; em = 1.0; k1 = 1.0; k2 = 0.0; k3 = del; k4 = 0.0; k5 = 0.0;
+    }
+    for (int k = 0; k < nv; ++k) {
+      Wi[k] = pc.rho * (k1 * c_1[k] + k2 * c_s[k] + k3 * c_A[k])
+            + e * (pl.rho * (l_1[k] - k4 * l_s[k] - k5 * l_A[k])
+                 + pr.rho * (r_1[k] - k4 * r_s[k] - k5 * r_A[k]));
+    }
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Face states                                                             */
+/* ---------------------------------------------------------------------- */
+/* A reconstructed point state is admissible if rho > 0, p > 0 and finite
+ * (reading; the paper applies no positivity fix-up). */
+static int admissible(const ocfg *P, const double *W) {
+  for (int k = 0; k < P->nv; ++k) if (!isfinite(W[k])) return 0;
+  if (!(W[0] > 0.0)) return 0;
+  double ke = 0.0;
+  for (int k = 1; k < P->nv - 1; ++k) ke += W[k] * W[k];
+  double p = (P->gamma - 1.0) * (W[P->nv - 1] - 0.5 * ke / W[0]);
+  return p > 0.0;
+}
+
+/* Normal GENO for the face between cells (i, j) and (i+1, j) along x (dir 0)
+ * or between (i, j) and (i, j+1) along y (dir 1) in ghosted coordinates.
+ * out[side][quant][var]: quant 0 value, 1 h * normal derivative; chi[side][var]. */
+static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
+                        double out[2][2][4], double chi[2][4]) {
+  int nv = P->nv;
+  for (int v = 0; v < nv; ++v) {
+    double q[4], gg[4];
+    double h = (dir == 0) ? P->dx : P->dy;
+    for (int m = -1; m <= 2; ++m) {
+      int ii = (dir == 0) ? i + m : i, jj = (dir == 0) ? j : j + m;
+      q[m + 1] = g->W[gidx(g, v, jj, ii)];
+      gg[m + 1] = h * g->dW[gidx(g, dir * nv + v, jj, ii)];
+    }
+    double l[3], r[3];
+    geno_face(P, q, gg, l, r);
+    out[0][0][v] = l[0]; out[0][1][v] = l[1]; chi[0][v] = l[2];
+    out[1][0][v] = r[0]; out[1][1][v] = r[1]; chi[1][v] = r[2];
+  }
+}
+
+/* Tangential step to a Gauss point (reading, 2-D only). phi[3] are the
+ * face-averaged values of rows j-1, j, j+1 (one side, one variable); eta is
+ * the Gauss point in units of the face length about the row centre. The
+ * high-order candidate is the quadratic with these three averages; the
+ * low-order one is the ENO combination (d = 1) of the two one-sided linear
+ * polynomials; they are blended with the path function of Eq. (4)-(5) using
+ * IS = h * int (p')^2 of each linear polynomial, IS^H = max, IS^L = min,
+ * IS^tau = |IS_+ - IS_-|. Returns the value; *hder = h * tangential derivative. */
+static double tangential(const ocfg *P, const double phi[3], double eta, double *hder) {
+  double c[3];
+  for (int q = 0; q < 3; ++q) c[q] = TQ[q][0] * phi[0] + TQ[q][1] * phi[1] + TQ[q][2] * phi[2];
+  double vH = c[0] + c[1] * eta + c[2] * eta * eta;
+  double dH = c[1] + 2.0 * c[2] * eta;
+  double sm = phi[1] - phi[0], sp = phi[2] - phi[1];
+  double ISm = sm * sm, ISp = sp * sp;
+  double ISH = ISm > ISp ? ISm : ISp, ISL = ISm < ISp ? ISm : ISp;
+  double chi = path_function(P, fabs(ISp - ISm), ISH, ISL);
+  double wm = 1.0 / pow(ISm + P->eps, P->rL), wp = 1.0 / pow(ISp + P->eps, P->rL);
+  double sL = (wm / (wm + wp)) * sm + (wp / (wm + wp)) * sp;
+  double vL = phi[1] + eta * sL;
+  *hder = chi * dH + (1.0 - chi) * sL;
+  return chi * vH + (1.0 - chi) * vL;
+}
+
+/* Gauss points of a face (reading of the 2-point rule on a face):
+ * +-1/(2 sqrt 3) of the face length about its centre, weights 1/2. */
+static const double GAUSS_ETA[2] = {-0.28867513459481288225, 0.28867513459481288225};
+
+/* ---------------------------------------------------------------------- */
+/* One stage: fluxes, Lagrangian, interface states                         */
+/* ---------------------------------------------------------------------- */
+/* Per-face results for the stage: F, dF/dt and W_int (Gauss-averaged). */
+typedef struct {
+  double *F[2], *Ft[2], *Wi[2];   /* dir x / y: [nv][nfy][nfx] */
+  int nfx[2], nfy[2];
+  long long guard;
+} faceres;
+
+/* Computes all face quantities of a stage from the (ghost-filled) state. */
+static void stage_faces(const ocfg *P, const gstate *g, double dt, faceres *fr) {
+  int nv = P->nv, nx = P->nx, ny = P->ny;
+  long long guard = 0;
+  if (P->ndim == 1) {
+    for (int f = 0; f <= nx; ++f) {
+      int i = NG + f - 1;                 /* left cell of face f */
+      double out[2][2][4], chi[2][4];
+      normal_face(P, g, 0, i, 0, out, chi);
+      double Wl[4], Wr[4], dl[4], dr[4];
+      for (int v = 0; v < nv; ++v) {
+        Wl[v] = out[0][0][v]; dl[v] = out[0][1][v] / P->dx;
+        Wr[v] = out[1][0][v]; dr[v] = out[1][1][v] / P->dx;
+      }
+      if (!admissible(P, Wl)) { ++guard; for (int v = 0; v < nv; ++v) { Wl[v] = g->W[gidx(g, v, 0, i)]; dl[v] = 0.0; } }
+      if (!admissible(P, Wr)) { ++guard; for (int v = 0; v < nv; ++v) { Wr[v] = g->W[gidx(g, v, 0, i + 1)]; dr[v] = 0.0; } }
+      double F[4], Ft[4], Wi[4];
+      gks_point(P, Wl, Wr, dl, dr, NULL, NULL, dt, F, Ft, Wi);
+      for (int v = 0; v < nv; ++v) {
+        fr->F[0][(size_t)v * (nx + 1) + f] = F[v];
+        fr->Ft[0][(size_t)v * (nx + 1) + f] = Ft[v];
+        fr->Wi[0][(size_t)v * (nx + 1) + f] = Wi[v];
+      }
+    }
+    fr->guard += guard;
+    return;
+  }
+  /* 2-D: dir 0 (x-faces) then dir 1 (y-faces) */
+  for (int dir = 0; dir < 2; ++dir) {
+    int nfn = (dir == 0) ? nx + 1 : ny + 1;   /* faces along the normal */
+    int nt = (dir == 0) ? ny : nx;            /* rows along the tangent */
+    double hn = (dir == 0) ? P->dx : P->dy;
+    double ht = (dir == 0) ? P->dy : P->dx;
+    long long gsum = 0;
+#pragma omp parallel for schedule(static) reduction(+ : gsum)
+    for (int t = 0; t < nt; ++t) {
+      for (int f = 0; f < nfn; ++f) {
+        /* normal reconstruction for rows t-1, t, t+1 */
+        double out[3][2][2][4], chi[2][4];
+        for (int dt_ = -1; dt_ <= 1; ++dt_) {
+          int i, j;
+          if (dir == 0) { i = NG + f - 1; j = NG + t + dt_; }
+          else { i = NG + t + dt_; j = NG + f - 1; }
+          normal_face(P, g, dir, i, j, out[dt_ + 1], chi);
+        }
+        /* own cells of the two sides in the centre row */
+        int il, jl, ir, jr;
+        if (dir == 0) { il = NG + f - 1; ir = NG + f; jl = jr = NG + t; }
+        else { jl = NG + f - 1; jr = NG + f; il = ir = NG + t; }
+        double Fs[4] = {0, 0, 0, 0}, Fts[4] = {0, 0, 0, 0}, Wis[4] = {0, 0, 0, 0};
+        for (int gp = 0; gp < 2; ++gp) {
+          double S[2][4], Dn[2][4], Dt[2][4];
+          for (int side = 0; side < 2; ++side) {
+            for (int v = 0; v < nv; ++v) {
+              double phi[3] = {out[0][side][0][v], out[1][side][0][v], out[2][side][0][v]};
+              double hdt;
+              S[side][v] = tangential(P, phi, GAUSS_ETA[gp], &hdt);
+              Dt[side][v] = hdt / ht;
+              Dn[side][v] = out[1][side][1][v] / hn;
+            }
+            if (!admissible(P, S[side])) {
+              ++gsum;
+              int ci = side ? ir : il, cj = side ? jr : jl;
+              for (int v = 0; v < nv; ++v) {
+                S[side][v] = g->W[gidx(g, v, cj, ci)]; Dn[side][v] = 0.0; Dt[side][v] = 0.0;
+              }
+            }
+          }
+          /* rotate into the face frame: normal momentum first */
+          double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
+          int perm[4] = {0, 1, 2, 3};
+          if (dir == 1) { perm[1] = 2; perm[2] = 1; }
+          for (int v = 0; v < 4; ++v) {
+            Wl[v] = S[0][perm[v]]; Wr[v] = S[1][perm[v]];
+            nl[v] = Dn[0][perm[v]]; nr[v] = Dn[1][perm[v]];
+            tl[v] = Dt[0][perm[v]]; tr[v] = Dt[1][perm[v]];
+          }
+          double F[4], Ft[4], Wi[4];
+          gks_point(P, Wl, Wr, nl, nr, tl, tr, dt, F, Ft, Wi);
+          for (int v = 0; v < 4; ++v) {
+            Fs[perm[v]] += 0.5 * F[v];
+            Fts[perm[v]] += 0.5 * Ft[v];
+            Wis[perm[v]] += 0.5 * Wi[v];
+          }
+        }
+        int nfx = fr->nfx[dir];
+        size_t base = (size_t)(dir == 0 ? t : f) * nfx + (dir == 0 ? f : t);
+        size_t plane = (size_t)fr->nfx[dir] * fr->nfy[dir];
+        for (int v = 0; v < 4; ++v) {
+          fr->F[dir][v * plane + base] = Fs[v];
+          fr->Ft[dir][v * plane + base] = Fts[v];
+          fr->Wi[dir][v * plane + base] = Wis[v];
+        }
+      }
+    }
+    guard += gsum;
+  }
+  fr->guard += guard;
+}
+
+static int faceres_alloc(const ocfg *P, faceres *fr) {
+  memset(fr, 0, sizeof *fr);
+  fr->nfx[0] = P->nx + 1; fr->nfy[0] = P->ny;
+  fr->nfx[1] = P->nx; fr->nfy[1] = P->ny + 1;
+  int nd = P->ndim;
+  for (int d = 0; d < nd; ++d) {
+    size_t n = (size_t)fr->nfx[d] * fr->nfy[d] * P->nv;
+    fr->F[d] = (double *)calloc(n, sizeof(double));
+    fr->Ft[d] = (double *)calloc(n, sizeof(double));
+    fr->Wi[d] = (double *)calloc(n, sizeof(double));
+    if (!fr->F[d] || !fr->Ft[d] || !fr->Wi[d]) return -1;
+  }
+  return 0;
+}
+static void faceres_free(faceres *fr) {
+  for (int d = 0; d < 2; ++d) { free(fr->F[d]); free(fr->Ft[d]); free(fr->Wi[d]); }
+}
+
+/* L = -(1/|Omega|) sum faces F.n |Gamma| (Eq. (1)) and its time derivative;
+ * gradients by the Gauss theorem (Eq. (2)) from W_int. */
+static void cell_terms(const ocfg *P, const faceres *fr, double *L, double *Lt, double *G) {
+  int nv = P->nv, nx = P->nx, ny = P->ny;
+  size_t ncell = (size_t)nx * ny;
+  for (int v = 0; v < nv; ++v)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        size_t c = (size_t)v * ncell + (size_t)j * nx + i;
+        size_t px = (size_t)fr->nfx[0] * fr->nfy[0];
+        size_t fxl = v * px + (size_t)j * fr->nfx[0] + i, fxh = fxl + 1;
+        double l = -(fr->F[0][fxh] - fr->F[0][fxl]) / P->dx;
+        double lt = -(fr->Ft[0][fxh] - fr->Ft[0][fxl]) / P->dx;
+        G[c] = (fr->Wi[0][fxh] - fr->Wi[0][fxl]) / P->dx;
+        if (P->ndim == 2) {
+          size_t py = (size_t)fr->nfx[1] * fr->nfy[1];
+          size_t fyl = v * py + (size_t)j * fr->nfx[1] + i, fyh = fyl + fr->nfx[1];
+          l += -(fr->F[1][fyh] - fr->F[1][fyl]) / P->dy;
+          lt += -(fr->Ft[1][fyh] - fr->Ft[1][fyl]) / P->dy;
+          G[(size_t)nv * ncell + c] = (fr->Wi[1][fyh] - fr->Wi[1][fyl]) / P->dy;
+        }
+        L[c] = l; Lt[c] = lt;
+      }
+}
+
+/* CFL time step (Sec. 6 uses CFL >= 0.5; reading of the 2-D form):
+ * dt = CFL * min over cells of min(dx/(|U|+c), dy/(|V|+c)). */
+static double cfl_dt(const ocfg *P, const double *W) {
+  int nv = P->nv;
+  size_t ncell = (size_t)P->nx * P->ny;
+  double m = INFINITY;
+  for (size_t c = 0; c < ncell; ++c) {
+    double rho = W[c], U = W[ncell + c] / rho;
+    double V = (nv == 4) ? W[2 * ncell + c] / rho : 0.0;
+    double p = (P->gamma - 1.0) * (W[(nv - 1) * ncell + c] - 0.5 * rho * (U * U + V * V));
+    double cs = sqrt(P->gamma * p / rho);
+    double t = P->dx / (fabs(U) + cs);
+    if (nv == 4) { double ty = P->dy / (fabs(V) + cs); if (ty < t) t = ty; }
+    if (t < m) m = t;
+  }
+  return P->cfl * m;
+}
+
+/* ====================================================================== */
+/* Exported entry points                                                   */
+/* ====================================================================== */
+
+int oracle_init(void) { return ops_ready ? OR_OK : (build_ops() ? OR_EINVAL : OR_OK); }
+
+/* Linear-operator weights (for the polynomial-reproduction pins). */
+int oracle_linear_weights(double *hval, double *hder) {
+  if (oracle_init()) return OR_EINVAL;
+  memcpy(hval, H_val, sizeof H_val);
+  memcpy(hder, H_der, sizeof H_der);
+  return OR_OK;
+}
+
+/* GENO at one face for one component: q, g = averages and h-scaled averaged
+ * derivatives of cells j-1..j+2. out = (value_l, hder_l, chi_l, value_r,
+ * hder_r, chi_r). */
+int oracle_geno_face(const double *params, const double *q, const double *g, double *out) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, 1, 1, 1, 1.0, 1.0, params);
+  double l[3], r[3];
+  geno_face(&P, q, g, l, r);
+  for (int k = 0; k < 3; ++k) { out[k] = l[k]; out[3 + k] = r[k]; }
+  return OR_OK;
+}
+
+/* Internals of GENO on one side, for the unit pins: dat = Q, G of cells
+ * c-2..c+2 about the reconstructing cell (10 values), si = 0 left state,
+ * 1 right state; qH, hqH the shared linear values. out = IS[3], p_k value[3],
+ * h p_k'[3], omega[3], chi, q^L, h q^L', R, h R' (17 values). */
+int oracle_geno_side_detail(const double *params, const double *dat, int si, double qH,
+                            double hqH, double *out) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, 1, 1, 1, 1.0, 1.0, params);
+  double xf = (si == 0) ? 0.5 : -0.5;
+  double c[3][3], wt[3], wsum = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+      for (int m = 0; m < 10; ++m) s += SUB[si][k][q][m] * dat[m];
+      c[k][q] = s;
+    }
+    out[k] = is_quadratic(c[k]);
+    out[3 + k] = c[k][0] + c[k][1] * xf + c[k][2] * xf * xf;
+    out[6 + k] = c[k][1] + 2.0 * c[k][2] * xf;
+    wt[k] = P.d[k] / pow(out[k] + P.eps, P.rL);
+    wsum += wt[k];
+  }
+  for (int k = 0; k < 3; ++k) out[9 + k] = wt[k] / wsum;
+  double v, hd, chi;
+  geno_side(&P, dat, si, qH, hqH, &v, &hd, &chi);
+  out[12] = chi;
+  out[13] = 0.0; out[14] = 0.0;
+  for (int k = 0; k < 3; ++k) { out[13] += out[9 + k] * out[3 + k]; out[14] += out[9 + k] * out[6 + k]; }
+  out[15] = v; out[16] = hd;
+  return OR_OK;
+}
+
+/* Maxwellian moment table: out = mu[0..7], mv[0..5], mz[0..2]. */
+int oracle_moments(double U, double V, double lam, double K, int half, int has_v, double *out) {
+  mtab m; moments(U, V, lam, K, half, has_v, &m);
+  memcpy(out, m.mu, sizeof m.mu);
+  memcpy(out + DU, m.mv, sizeof m.mv);
+  memcpy(out + DU + DV, m.mz, sizeof m.mz);
+  return OR_OK;
+}
+
+/* GKS flux at npts points (face frame). ndim selects 1-D (3 vars, no
+ * tangential data) or 2-D (4 vars). Arrays are [npts][nv]. */
+int oracle_gks_points(const double *params, int ndim, int npts, const double *Wl,
+                      const double *Wr, const double *dnl, const double *dnr,
+                      const double *dtl, const double *dtr, double dt,
+                      double *F, double *Ft, double *Wi) {
+  if (ndim != 1 && ndim != 2) return OR_EINVAL;
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, ndim, 1, 1, 1.0, 1.0, params);
+  int nv = P.nv;
+  for (int p = 0; p < npts; ++p) {
+    gks_point(&P, Wl + p * nv, Wr + p * nv, dnl + p * nv, dnr + p * nv,
+              ndim == 2 ? dtl + p * nv : NULL, ndim == 2 ? dtr + p * nv : NULL, dt,
+              F + p * nv, Ft + p * nv, Wi + p * nv);
+  }
+  return OR_OK;
+}
+
+/* Normal GENO over all faces of direction dir (after filling ghost cells).
+ * 1-D: faces f = 0..nx; 2-D x-faces: rows j = -1..ny (ny+2) x faces 0..nx;
+ * y-faces: faces 0..ny x columns i = -1..nx (nx+2).
+ * out: [side][quant(2)][var][rows][faces] (x) or [side][quant][var][faces][cols] (y),
+ * chi: [side][var][...]. */
+int oracle_normal_faces(const double *params, int ndim, int nx, int ny, double dx, double dy,
+                        const double *W, const double *dW, int dir, double *out, double *chi) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
+  gstate g;
+  if (gstate_alloc(&P, &g)) return OR_ENOMEM;
+  gstate_load(&P, &g, W, dW);
+  fill_ghosts(&P, &g);
+  int nv = P.nv;
+  int n0, n1;   /* outer (slow) and inner (fast) extents */
+  if (ndim == 1) { n0 = 1; n1 = nx + 1; }
+  else if (dir == 0) { n0 = ny + 2; n1 = nx + 1; }
+  else { n0 = ny + 1; n1 = nx + 2; }
+  size_t plane = (size_t)n0 * n1;
+  for (int a = 0; a < n0; ++a)
+    for (int b = 0; b < n1; ++b) {
+      int i, j;
+      if (ndim == 1) { i = NG + b - 1; j = 0; }
+      else if (dir == 0) { i = NG + b - 1; j = NG + a - 1; }
+      else { i = NG + b - 1; j = NG + a - 1; }
+      double o[2][2][4], c[2][4];
+      normal_face(&P, &g, ndim == 1 ? 0 : dir, i, j, o, c);
+      for (int s = 0; s < 2; ++s)
+        for (int v = 0; v < nv; ++v) {
+          for (int q = 0; q < 2; ++q)
+            out[(((size_t)s * 2 + q) * nv + v) * plane + (size_t)a * n1 + b] = o[s][q][v];
+          chi[((size_t)s * nv + v) * plane + (size_t)a * n1 + b] = c[s][v];
+        }
+    }
+  gstate_free(&g);
+  return OR_OK;
+}
+
+/* Face states at the Gauss points after the tangential step and the
+ * positivity guard (2-D), or at the face (1-D).
+ * out: [side][gauss][quant][var][nfy][nfx], quant = value, h*d_n, h*d_t (2-D)
+ * or value, h*d_n (1-D); variables in the (x, y) frame. */
+int oracle_face_states(const double *params, int ndim, int nx, int ny, double dx, double dy,
+                       const double *W, const double *dW, int dir, double *out, long long *guard) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
+  gstate g;
+  if (gstate_alloc(&P, &g)) return OR_ENOMEM;
+  gstate_load(&P, &g, W, dW);
+  fill_ghosts(&P, &g);
+  int nv = P.nv;
+  long long gcount = 0;
+  if (ndim == 1) {
+    size_t plane = (size_t)(nx + 1);
+    for (int f = 0; f <= nx; ++f) {
+      int i = NG + f - 1;
+      double o[2][2][4], c[2][4];
+      normal_face(&P, &g, 0, i, 0, o, c);
+      for (int s = 0; s < 2; ++s) {
+        double S[4];
+        for (int v = 0; v < nv; ++v) S[v] = o[s][0][v];
+        int ok = admissible(&P, S);
+        if (!ok) ++gcount;
+        for (int v = 0; v < nv; ++v) {
+          double val = ok ? o[s][0][v] : g.W[gidx(&g, v, 0, i + s)];
+          double dn = ok ? o[s][1][v] : 0.0;
+          out[(((size_t)s * 2 + 0) * nv + v) * plane + f] = val;
+          out[(((size_t)s * 2 + 1) * nv + v) * plane + f] = dn;
+        }
+      }
+    }
+  } else {
+    int nfx = (dir == 0) ? nx + 1 : nx, nfy = (dir == 0) ? ny : ny + 1;
+    size_t plane = (size_t)nfx * nfy;
+    for (int a = 0; a < nfy; ++a)
+      for (int b = 0; b < nfx; ++b) {
+        int f = (dir == 0) ? b : a, t = (dir == 0) ? a : b;
+        double o[3][2][2][4], c[2][4];
+        for (int dt_ = -1; dt_ <= 1; ++dt_) {
+          int i, j;
+          if (dir == 0) { i = NG + f - 1; j = NG + t + dt_; }
+          else { i = NG + t + dt_; j = NG + f - 1; }
+          normal_face(&P, &g, dir, i, j, o[dt_ + 1], c);
+        }
+        for (int gp = 0; gp < 2; ++gp)
+          for (int s = 0; s < 2; ++s) {
+            double S[4], Dn[4], Dt[4];
+            for (int v = 0; v < nv; ++v) {
+              double phi[3] = {o[0][s][0][v], o[1][s][0][v], o[2][s][0][v]};
+              S[v] = tangential(&P, phi, GAUSS_ETA[gp], &Dt[v]);
+              Dn[v] = o[1][s][1][v];
+            }
+            if (!admissible(&P, S)) {
+              ++gcount;
+              int ci, cj;
+              if (dir == 0) { ci = NG + f - 1 + s; cj = NG + t; }
+              else { ci = NG + t; cj = NG + f - 1 + s; }
+              for (int v = 0; v < nv; ++v) { S[v] = g.W[gidx(&g, v, cj, ci)]; Dn[v] = 0.0; Dt[v] = 0.0; }
+            }
+            for (int v = 0; v < nv; ++v) {
+              size_t base = (((size_t)s * 2 + gp) * 3) * nv;
+              out[(base + 0 * nv + v) * plane + (size_t)a * nfx + b] = S[v];
+              out[(base + 1 * nv + v) * plane + (size_t)a * nfx + b] = Dn[v];
+              out[(base + 2 * nv + v) * plane + (size_t)a * nfx + b] = Dt[v];
+            }
+          }
+      }
+  }
+  if (guard) *guard = gcount;
+  gstate_free(&g);
+  return OR_OK;
+}
+
+/* nsteps full S2O4 steps in place (reading of the two-stage fourth-order
+ * method: stage 1 W* = W + dt/2 L + dt^2/8 L_t, stage 2
+ * W^{n+1} = W + dt L + dt^2/6 L_t + dt^2/3 L_t*; gradients at the stage
+ * times from W_int(dt/2) of each stage, Eq. (2)).
+ * dt_hist: nsteps doubles (may be NULL). guard: positivity fall-backs.
+ * fixed_dt > 0 overrides the CFL step. */
+int oracle_step(const double *params, int ndim, int nx, int ny, double dx, double dy,
+                double *W, double *dW, int nsteps, double fixed_dt, double *dt_hist,
+                long long *guard) {
+  if (oracle_init()) return OR_EINVAL;
+  if (ndim != 1 && ndim != 2) return OR_EINVAL;
+  ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
+  int nv = P.nv;
+  size_t ncell = (size_t)P.nx * P.ny;
+  size_t nW = ncell * nv, nG = ncell * nv * ndim;
+  double *L = malloc(nW * sizeof(double)), *Lt = malloc(nW * sizeof(double));
+  double *Ws = malloc(nW * sizeof(double)), *Gs = malloc(nG * sizeof(double));
+  double *R = malloc(nW * sizeof(double));
+  gstate g; faceres fr;
+  if (!L || !Lt || !Ws || !Gs || !R || gstate_alloc(&P, &g) || faceres_alloc(&P, &fr)) return OR_ENOMEM;
+  for (int n = 0; n < nsteps; ++n) {
+    double dt = fixed_dt > 0.0 ? fixed_dt : cfl_dt(&P, W);
+    if (dt_hist) dt_hist[n] = dt;
+    /* stage 1 */
+    gstate_load(&P, &g, W, dW);
+    fill_ghosts(&P, &g);
+    stage_faces(&P, &g, dt, &fr);
+    cell_terms(&P, &fr, L, Lt, Gs);
+    for (size_t k = 0; k < nW; ++k) {
+      Ws[k] = W[k] + 0.5 * dt * L[k] + dt * dt / 8.0 * Lt[k];
+      R[k] = W[k] + dt * L[k] + dt * dt / 6.0 * Lt[k];
+    }
+    /* stage 2 */
+    gstate_load(&P, &g, Ws, Gs);
+    fill_ghosts(&P, &g);
+    stage_faces(&P, &g, dt, &fr);
+    cell_terms(&P, &fr, L, Lt, dW);
+    for (size_t k = 0; k < nW; ++k) W[k] = R[k] + dt * dt / 3.0 * Lt[k];
+  }
+  if (guard) *guard = fr.guard;
+  free(L); free(Lt); free(Ws); free(Gs); free(R);
+  gstate_free(&g); faceres_free(&fr);
+  return OR_OK;
+}
+
+/* One stage's face results (for unit parity of the flux over a grid):
+ * F, Ft, Wi for direction dir: [nv][nfy][nfx]. */
+int oracle_stage_faces(const double *params, int ndim, int nx, int ny, double dx, double dy,
+                       const double *W, const double *dW, double dt, int dir,
+                       double *F, double *Ft, double *Wi) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
+  gstate g; faceres fr;
+  if (gstate_alloc(&P, &g) || faceres_alloc(&P, &fr)) return OR_ENOMEM;
+  gstate_load(&P, &g, W, dW);
+  fill_ghosts(&P, &g);
+  stage_faces(&P, &g, dt, &fr);
+  int d = (ndim == 1) ? 0 : dir;
+  size_t n = (size_t)fr.nfx[d] * fr.nfy[d] * P.nv;
+  memcpy(F, fr.F[d], n * sizeof(double));
+  memcpy(Ft, fr.Ft[d], n * sizeof(double));
+  memcpy(Wi, fr.Wi[d], n * sizeof(double));
+  gstate_free(&g); faceres_free(&fr);
+  return OR_OK;
+}
+
+/* CFL time step of a state (interior cells). */
+double oracle_cfl_dt(const double *params, int ndim, int nx, int ny, double dx, double dy,
+                     const double *W) {
+  ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
+  return cfl_dt(&P, W);
+}

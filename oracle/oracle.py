@@ -1,0 +1,216 @@
+"""ctypes wrapper of the CPU FP64 oracle (``geno_gks_oracle.c``).
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE: only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import this module. It shares no
+code with the HIP library or its binding.
+
+Every function takes and returns interior-only SoA float64 arrays
+``W[field, y, x]``, ``dW[d * nv + field, y, x]`` (see ``inputs.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "geno_gks_oracle.c")
+_SO = os.path.join(_HERE, "libgeno_gks_oracle.so")
+_lib = None
+
+# Parameter vector layout of the C oracle.
+P_GAMMA, P_CPATH, P_EPS, P_R, P_RL, P_D1, P_D2, P_D3, P_TAUC1, P_TAUC2, P_CFL = range(11)
+P_BC = 11  # four boundary codes follow: x-lo, x-hi, y-lo, y-hi (0 periodic, 1 transmissive)
+N_PARAMS = 15
+PERIODIC, TRANSMISSIVE = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP over rows)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i, d = ctypes.c_int, ctypes.c_double
+        llp = ctypes.POINTER(ctypes.c_longlong)
+        L.oracle_init.restype = i
+        L.oracle_linear_weights.argtypes = [dp, dp]
+        L.oracle_geno_face.argtypes = [dp, dp, dp, dp]
+        L.oracle_moments.argtypes = [d, d, d, d, i, i, dp]
+        L.oracle_geno_side_detail.argtypes = [dp, dp, i, d, d, dp]
+        L.oracle_gks_points.argtypes = [dp, i, i, dp, dp, dp, dp, dp, dp, d, dp, dp, dp]
+        L.oracle_normal_faces.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, dp]
+        L.oracle_face_states.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, llp]
+        L.oracle_step.argtypes = [dp, i, i, i, d, d, dp, dp, i, d, dp, llp]
+        L.oracle_stage_faces.argtypes = [dp, i, i, i, d, d, dp, dp, d, i, dp, dp, dp]
+        L.oracle_cfl_dt.argtypes = [dp, i, i, i, d, d, dp]
+        L.oracle_cfl_dt.restype = d
+        for name in ("oracle_linear_weights", "oracle_geno_face", "oracle_geno_side_detail", "oracle_moments",
+                     "oracle_gks_points", "oracle_normal_faces", "oracle_face_states",
+                     "oracle_step", "oracle_stage_faces"):
+            getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def params(ndim: int = 2, bc=TRANSMISSIVE, gamma=1.4, C=20.0, eps=1e-15, r=2.0, rL=2.0,
+           d=(1.0, 8.0, 1.0), tau_c1=0.0, tau_c2=1.0, cfl=0.5) -> np.ndarray:
+    """Oracle parameter vector. Paper constants (Sec. 3): C = 20, eps = 1e-15,
+    r = 2 (structured), r^L = 2, central weight C_0 = 8."""
+    p = np.zeros(N_PARAMS)
+    p[P_GAMMA], p[P_CPATH], p[P_EPS], p[P_R], p[P_RL] = gamma, C, eps, r, rL
+    p[P_D1:P_D3 + 1] = d
+    p[P_TAUC1], p[P_TAUC2], p[P_CFL] = tau_c1, tau_c2, cfl
+    bcs = [bc] * 4 if np.isscalar(bc) else list(bc)
+    p[P_BC:P_BC + 4] = bcs
+    return p
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise RuntimeError("%s failed with code %d" % (name, rc))
+
+
+def linear_weights():
+    hv, hd = np.zeros(8), np.zeros(8)
+    _check(lib().oracle_linear_weights(_p(hv), _p(hd)), "oracle_linear_weights")
+    return hv, hd
+
+
+def geno_face(prm, q, g):
+    """GENO at one face for one component; q, g: averages and h-scaled averaged
+    derivatives of cells j-1..j+2. Returns (val_l, hder_l, chi_l, val_r, hder_r, chi_r)."""
+    q, g, out = _c(q), _c(g), np.zeros(6)
+    _check(lib().oracle_geno_face(_p(_c(prm)), _p(q), _p(g), _p(out)), "oracle_geno_face")
+    return out
+
+
+def geno_side_detail(prm, dat, side, qH, hqH):
+    """Internals of one GENO side. dat: (Q, G) pairs of cells c-2..c+2 (10 values);
+    side 0 = left state, 1 = right state. Returns a dict of IS, p, hp, omega, chi,
+    qL, hqL, R, hR."""
+    out = np.zeros(17)
+    _check(lib().oracle_geno_side_detail(_p(_c(prm)), _p(_c(dat)), int(side), float(qH), float(hqH),
+                                         _p(out)), "oracle_geno_side_detail")
+    return dict(IS=out[0:3], p=out[3:6], hp=out[6:9], omega=out[9:12], chi=out[12],
+                qL=out[13], hqL=out[14], R=out[15], hR=out[16])
+
+
+def moments(U, V, lam, K, half, has_v=True):
+    out = np.zeros(8 + 6 + 3)
+    lib().oracle_moments(U, V, lam, K, int(half), int(has_v), _p(out))
+    return out[:8], out[8:14], out[14:]
+
+
+def gks_points(prm, ndim, Wl, Wr, dnl, dnr, dtl=None, dtr=None, dt=1e-3):
+    """GKS flux at points in the face frame; arrays [npts, nv]. Returns F, Ft, Wint."""
+    Wl, Wr, dnl, dnr = map(_c, (Wl, Wr, dnl, dnr))
+    npts, nv = Wl.shape
+    dtl = _c(dtl) if dtl is not None else np.zeros_like(Wl)
+    dtr = _c(dtr) if dtr is not None else np.zeros_like(Wl)
+    F, Ft, Wi = np.zeros_like(Wl), np.zeros_like(Wl), np.zeros_like(Wl)
+    _check(lib().oracle_gks_points(_p(_c(prm)), ndim, npts, _p(Wl), _p(Wr), _p(dnl), _p(dnr),
+                                   _p(dtl), _p(dtr), dt, _p(F), _p(Ft), _p(Wi)), "oracle_gks_points")
+    return F, Ft, Wi
+
+
+def _dims(W):
+    nv, ny, nx = W.shape
+    ndim = 1 if nv == 3 else 2
+    return ndim, nv, ny, nx
+
+
+def normal_faces(prm, W, dW, direction=0, dx=None, dy=None):
+    """Normal GENO on every face of a direction (rows -1..ny for x-faces,
+    columns -1..nx for y-faces). Returns out[side, quant, var, a, b], chi[side, var, a, b]."""
+    W, dW = _c(W), _c(dW)
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    if ndim == 1:
+        n0, n1 = 1, nx + 1
+    elif direction == 0:
+        n0, n1 = ny + 2, nx + 1
+    else:
+        n0, n1 = ny + 1, nx + 2
+    out = np.zeros((2, 2, nv, n0, n1))
+    chi = np.zeros((2, nv, n0, n1))
+    _check(lib().oracle_normal_faces(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), direction,
+                                     _p(out), _p(chi)), "oracle_normal_faces")
+    return out, chi
+
+
+def face_states(prm, W, dW, direction=0, dx=None, dy=None):
+    """Point states on faces after the tangential step and positivity guard.
+    Returns (out[side, gauss, quant, var, nfy, nfx], guard_count)."""
+    W, dW = _c(W), _c(dW)
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    if ndim == 1:
+        out = np.zeros((2, 1, 2, nv, 1, nx + 1))
+    else:
+        nfx, nfy = (nx + 1, ny) if direction == 0 else (nx, ny + 1)
+        out = np.zeros((2, 2, 3, nv, nfy, nfx))
+    g = ctypes.c_longlong(0)
+    _check(lib().oracle_face_states(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), direction,
+                                    _p(out), ctypes.byref(g)), "oracle_face_states")
+    return out, g.value
+
+
+def stage_faces(prm, W, dW, dt, direction=0, dx=None, dy=None):
+    """Gauss-averaged F, dF/dt and W_int(dt/2) on every face of a direction: [nv, nfy, nfx]."""
+    W, dW = _c(W), _c(dW)
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    if ndim == 1 or direction == 0:
+        shape = (nv, ny, nx + 1)
+    else:
+        shape = (nv, ny + 1, nx)
+    F, Ft, Wi = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    _check(lib().oracle_stage_faces(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), dt, direction,
+                                    _p(F), _p(Ft), _p(Wi)), "oracle_stage_faces")
+    return F, Ft, Wi
+
+
+def step(prm, W, dW, nsteps, dx=None, dy=None, fixed_dt=0.0):
+    """nsteps S2O4 steps; returns (W, dW, dt_history, guard_count) (inputs untouched)."""
+    W, dW = _c(W).copy(), _c(dW).copy()
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    dts = np.zeros(max(nsteps, 1))
+    g = ctypes.c_longlong(0)
+    _check(lib().oracle_step(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), nsteps,
+                             float(fixed_dt), _p(dts), ctypes.byref(g)), "oracle_step")
+    return W, dW, dts[:nsteps], g.value
+
+
+def cfl_dt(prm, W, dx=None, dy=None):
+    W = _c(W)
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    return lib().oracle_cfl_dt(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W))

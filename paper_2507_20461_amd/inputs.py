@@ -1,0 +1,213 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module holds initial data only (cell averages and cell-averaged
+gradients of analytic or seeded piecewise-constant states); it contains none
+of the reconstruction, flux or time-stepping arithmetic.
+
+Arrays are interior-only SoA, ``W[field, y, x]`` and ``dW[d * nv + field, y, x]``
+(``d`` = 0 for d/dx, 1 for d/dy), float64. In 1-D, ``ny = 1``.
+Fields: 1-D ``(rho, rhoU, rhoE)``; 2-D ``(rho, rhoU, rhoV, rhoE)``.
+
+Workloads (sizes of the paper's structured tests are 1-D; the 2-D and batched
+recipes are synthetic stand-ins for throughput measurement):
+
+* ``sine_1d``: density wave rho = 1 + 0.2 sin(2 pi x), U = 1, p = 1 on [0, 1],
+  periodic (the 1-D accuracy test of Sec. 6.1 rescaled from [0, 2]).
+* ``jump_1d``: one jump at x = 1/2 between two seeded states.
+* ``quadrants_2d``: four seeded constant quadrants, jumps on the lines x = 1/2
+  and y = 1/2.
+* ``vortex_2d``: ``quadrants_2d`` plus a smooth vortex perturbation of the
+  velocity.
+* ``batched_grids``: many independent quadrant grids of seeded sizes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def _cons_1d(rho, u, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def _cons_2d(rho, u, v, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def sine_1d(nx: int, amp: float = 0.2, gamma: float = GAMMA):
+    """Exact cell averages and averaged gradients of rho = 1 + amp sin(2 pi x), U = p = 1."""
+    h = 1.0 / nx
+    xl = np.arange(nx) * h
+    xr = xl + h
+    k = 2.0 * math.pi
+    rho_avg = 1.0 + amp * (np.cos(k * xl) - np.cos(k * xr)) / (k * h)
+    W = _cons_1d(rho_avg, np.ones(nx), np.ones(nx), gamma)
+    # rhoU = rho and rhoE = p/(g-1) + rho/2 are affine in rho: averages are exact.
+    W[1] = rho_avg
+    W[2] = 1.0 / (gamma - 1.0) + 0.5 * rho_avg
+
+    def point(x):
+        r = 1.0 + amp * np.sin(k * x)
+        return np.stack([r, r, 1.0 / (gamma - 1.0) + 0.5 * r])
+
+    dW = (point(xr) - point(xl)) / h
+    return W.reshape(3, 1, nx), dW.reshape(3, 1, nx)
+
+
+def sine_1d_exact(nx: int, t: float, amp: float = 0.2, gamma: float = GAMMA):
+    """Exact cell averages of the advected sine at time t (U = 1, period 1)."""
+    h = 1.0 / nx
+    xl = np.arange(nx) * h - t
+    xr = xl + h
+    k = 2.0 * math.pi
+    rho_avg = 1.0 + amp * (np.cos(k * xl) - np.cos(k * xr)) / (k * h)
+    return np.stack([rho_avg, rho_avg, 1.0 / (gamma - 1.0) + 0.5 * rho_avg]).reshape(3, 1, nx)
+
+
+def jump_1d(nx: int, seed: int, gamma: float = GAMMA):
+    """Jump at x = 1/2 between (rho, u, p)_L and (rho, u, p)_R; rho, p ~ U[0.1, 1.5],
+    u ~ U[-0.5, 0.5], drawn left state first in the order (rho, u, p)."""
+    rng = np.random.default_rng(seed)
+    states = []
+    for _ in range(2):
+        rho = rng.uniform(0.1, 1.5)
+        u = rng.uniform(-0.5, 0.5)
+        p = rng.uniform(0.1, 1.5)
+        states.append((rho, u, p))
+    xc = (np.arange(nx) + 0.5) / nx
+    left = xc < 0.5
+    rho = np.where(left, states[0][0], states[1][0])
+    u = np.where(left, states[0][1], states[1][1])
+    p = np.where(left, states[0][2], states[1][2])
+    W = _cons_1d(rho, u, p, gamma).reshape(3, 1, nx)
+    return W, np.zeros_like(W), states
+
+
+def quadrant_states(rng):
+    """Four (rho, u, v, p) states in the order q1 (x>1/2, y>1/2), q2 (x<1/2, y>1/2),
+    q3 (x<1/2, y<1/2), q4 (x>1/2, y<1/2); rho ~ U[0.5,1.5], u, v ~ U[-0.5,0.5],
+    p ~ U[0.1,1.0]."""
+    out = []
+    for _ in range(4):
+        rho = rng.uniform(0.5, 1.5)
+        u = rng.uniform(-0.5, 0.5)
+        v = rng.uniform(-0.5, 0.5)
+        p = rng.uniform(0.1, 1.0)
+        out.append((rho, u, v, p))
+    return out
+
+
+def _quadrant_fields(nx, ny, states):
+    xc = (np.arange(nx) + 0.5) / nx
+    yc = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    q = np.where(Y > 0.5, np.where(X > 0.5, 0, 1), np.where(X < 0.5, 2, 3))
+    st = np.array(states)
+    return [st[q, k] for k in range(4)], q
+
+
+def quadrants_2d(nx: int, ny: int, seed: int, gamma: float = GAMMA):
+    """Four seeded constant quadrants on [0,1]^2 (jumps on cell faces when nx, ny are even)."""
+    rng = np.random.default_rng(seed)
+    states = quadrant_states(rng)
+    (rho, u, v, p), _ = _quadrant_fields(nx, ny, states)
+    W = _cons_2d(rho, u, v, p, gamma)
+    return W, np.zeros((8, ny, nx)), states
+
+
+_GL4_X = np.array([-0.8611363115940526, -0.3399810435848563, 0.3399810435848563, 0.8611363115940526])
+_GL4_W = np.array([0.3478548451374538, 0.6521451548625461, 0.6521451548625461, 0.3478548451374538])
+
+
+def vortex_2d(nx: int, ny: int, seed: int, amp: float = 0.1, centre=(0.25, 0.25),
+              radius: float = 0.05, gamma: float = GAMMA):
+    """Seeded quadrants plus the velocity perturbation
+    du = -A (y - yc)/R exp((1 - r^2/R^2)/2), dv = +A (x - xc)/R exp((1 - r^2/R^2)/2);
+    rho and p keep their quadrant values. Cell averages by 4x4 Gauss-Legendre,
+    averaged gradients by the Gauss theorem with 4-point face quadrature; each
+    cell takes the constant state of the quadrant that contains its centre."""
+    rng = np.random.default_rng(seed)
+    states = quadrant_states(rng)
+    (rho_q, u_q, v_q, p_q), _ = _quadrant_fields(nx, ny, states)
+    hx, hy = 1.0 / nx, 1.0 / ny
+    xl = (np.arange(nx) * hx)[None, :]
+    yl = (np.arange(ny) * hy)[:, None]
+
+    def cons_at(x, y):
+        rx, ry = x - centre[0], y - centre[1]
+        e = np.exp(0.5 * (1.0 - (rx * rx + ry * ry) / (radius * radius)))
+        u = u_q - amp * ry / radius * e
+        v = v_q + amp * rx / radius * e
+        return _cons_2d(rho_q, u, v, p_q, gamma)
+
+    W = np.zeros((4, ny, nx))
+    for a, wa in zip(_GL4_X, _GL4_W):
+        for b, wb in zip(_GL4_X, _GL4_W):
+            W += 0.25 * wa * wb * cons_at(xl + hx * (0.5 + 0.5 * a), yl + hy * (0.5 + 0.5 * b))
+    dW = np.zeros((8, ny, nx))
+    for a, wa in zip(_GL4_X, _GL4_W):
+        ys = yl + hy * (0.5 + 0.5 * a)
+        xs = xl + hx * (0.5 + 0.5 * a)
+        dW[0:4] += 0.5 * wa * (cons_at(xl + hx, ys) - cons_at(xl, ys)) / hx
+        dW[4:8] += 0.5 * wa * (cons_at(xs, yl + hy) - cons_at(xs, yl)) / hy
+    return W, dW, states
+
+
+BATCH_SIDES = (128, 256, 512, 1024)
+
+
+def batched_grids(seed: int, n: int = 64, sides=BATCH_SIDES):
+    """``n`` independent square quadrant grids: the sides are drawn first (uniform over
+    ``sides``), then the four quadrant states of each grid in order."""
+    rng = np.random.default_rng(seed)
+    picks = rng.integers(0, len(sides), size=n)
+    grids = []
+    for k in range(n):
+        s = int(sides[picks[k]])
+        states = quadrant_states(rng)
+        (rho, u, v, p), _ = _quadrant_fields(s, s, states)
+        grids.append((s, _cons_2d(rho, u, v, p), np.zeros((8, s, s)), states))
+    return grids
+
+
+def random_smooth_2d(nx: int, ny: int, seed: int, gamma: float = GAMMA, modes: int = 3):
+    """Smooth periodic 2-D state (a few seeded Fourier modes per primitive) with exact
+    cell averages (by 4x4 Gauss-Legendre) and Gauss-theorem gradients; used for
+    parity on smooth data."""
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, size=(4, modes, modes, 2))
+    base = np.array([1.0, 0.3, -0.2, 1.0])
+    scale = np.array([0.1, 0.1, 0.1, 0.1])
+    hx, hy = 1.0 / nx, 1.0 / ny
+    xl = (np.arange(nx) * hx)[None, :]
+    yl = (np.arange(ny) * hy)[:, None]
+
+    def prim(x, y):
+        out = []
+        for f in range(4):
+            s = base[f] + 0.0 * x * y
+            for a in range(modes):
+                for b in range(modes):
+                    ph = 2 * math.pi * ((a + 1) * x + b * y)
+                    s = s + scale[f] / (1 + a + b) * (coef[f, a, b, 0] * np.sin(ph) + coef[f, a, b, 1] * np.cos(ph))
+            out.append(s)
+        return out
+
+    def cons_at(x, y):
+        rho, u, v, p = prim(x, y)
+        return _cons_2d(rho, u, v, p, gamma)
+
+    W = np.zeros((4, ny, nx))
+    for a, wa in zip(_GL4_X, _GL4_W):
+        for b, wb in zip(_GL4_X, _GL4_W):
+            W += 0.25 * wa * wb * cons_at(xl + hx * (0.5 + 0.5 * a), yl + hy * (0.5 + 0.5 * b))
+    dW = np.zeros((8, ny, nx))
+    for a, wa in zip(_GL4_X, _GL4_W):
+        ys = yl + hy * (0.5 + 0.5 * a)
+        xs = xl + hx * (0.5 + 0.5 * a)
+        dW[0:4] += 0.5 * wa * (cons_at(xl + hx, ys) - cons_at(xl, ys)) / hx
+        dW[4:8] += 0.5 * wa * (cons_at(xs, yl + hy) - cons_at(xs, yl)) / hy
+    return W, dW

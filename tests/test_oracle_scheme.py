@@ -1,0 +1,159 @@
+"""Pins of the oracle's full compact-GKS update (no GPU): invariants of the
+finite-volume method (Sec. 2, Eq. (1)-(2)), symmetries, convergence orders and
+non-oscillation at jumps, each against a fact the mathematics fixes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2507_20461_amd import inputs
+from tests import riemann_exact
+
+
+def _fsum(a):
+    return math.fsum(np.asarray(a).ravel())
+
+
+@pytest.mark.parametrize("case", ["sine", "jumps"])
+def test_conservation_periodic_1d(oracle, case):
+    n = 64
+    if case == "sine":
+        W, dW = inputs.sine_1d(n)
+    else:
+        W, dW, _ = inputs.jump_1d(n, 3)
+    prm = oracle.params(ndim=1, bc=oracle.PERIODIC)
+    W1, _, _, _ = oracle.step(prm, W, dW, 40)
+    for k in range(3):
+        assert abs(_fsum(W1[k]) - _fsum(W[k])) <= 1e-13 * n * np.abs(W[k]).max()
+
+
+@pytest.mark.parametrize("case", ["smooth", "quadrants"])
+def test_conservation_periodic_2d(oracle, case):
+    nx, ny = 16, 12
+    if case == "smooth":
+        W, dW = inputs.random_smooth_2d(nx, ny, 1)
+    else:
+        W, dW, _ = inputs.quadrants_2d(nx, ny, 2)
+    prm = oracle.params(ndim=2, bc=oracle.PERIODIC)
+    W1, _, _, _ = oracle.step(prm, W, dW, 4)
+    for k in range(4):
+        assert abs(_fsum(W1[k]) - _fsum(W[k])) <= 1e-13 * nx * ny * np.abs(W).max()
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_constant_state_bitwise(oracle, bc):
+    W = np.empty((3, 1, 24))
+    W[:] = np.array([1.3, -0.4, 2.9])[:, None, None]
+    W1, dW1, _, _ = oracle.step(oracle.params(ndim=1, bc=bc), W, np.zeros_like(W), 5)
+    assert np.array_equal(W1, W) and np.all(dW1 == 0.0)
+    W2 = np.empty((4, 10, 12))
+    W2[:] = np.array([0.8, 0.3, -0.2, 2.1])[:, None, None]
+    W3, dW3, _, _ = oracle.step(oracle.params(ndim=2, bc=bc), W2, np.zeros((8, 10, 12)), 3)
+    assert np.array_equal(W3, W2) and np.all(dW3 == 0.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_y_invariant_2d_equals_1d(oracle, seed):
+    n = 40
+    W1, dW1, _ = inputs.jump_1d(n, seed)
+    ny = 4
+    W2 = np.zeros((4, ny, n))
+    W2[0], W2[1], W2[3] = W1[0], W1[1], W1[2]
+    dW2 = np.zeros((8, ny, n))
+    dx = 1.0 / n
+    ra, _, _, _ = oracle.step(oracle.params(ndim=1, bc=oracle.TRANSMISSIVE), W1, dW1, 10, dx=dx)
+    prm2 = oracle.params(ndim=2, bc=(oracle.TRANSMISSIVE, oracle.TRANSMISSIVE, oracle.PERIODIC, oracle.PERIODIC))
+    rb, _, _, _ = oracle.step(prm2, W2, dW2, 10, dx=dx, dy=dx)
+    for j in range(ny):
+        for a, b in ((0, 0), (1, 1), (2, 3)):
+            np.testing.assert_allclose(rb[b, j], ra[a, 0], rtol=1e-12, atol=1e-13)
+    assert np.abs(rb[2]).max() < 1e-13
+
+
+def test_transpose_symmetry_bitwise(oracle):
+    W, dW, _ = inputs.quadrants_2d(16, 16, 4)
+    W, dW = W.copy(), dW.copy()
+    # add smooth gradients so that the tangential and gradient paths are exercised
+    Ws, dWs = inputs.random_smooth_2d(16, 16, 5)
+    W += 0.1 * (Ws - Ws.mean(axis=(1, 2), keepdims=True))
+    dW += 0.1 * dWs
+    prm = oracle.params(ndim=2, bc=oracle.TRANSMISSIVE)
+    a, da, _, _ = oracle.step(prm, W, dW, 3)
+    Wt = np.stack([W[0].T, W[2].T, W[1].T, W[3].T])
+    dWt = np.concatenate([np.stack([dW[4 + k].T for k in (0, 2, 1, 3)]),
+                          np.stack([dW[k].T for k in (0, 2, 1, 3)])])
+    b, db, _, _ = oracle.step(prm, Wt, dWt, 3)
+    assert np.array_equal(b, np.stack([a[0].T, a[2].T, a[1].T, a[3].T]))
+    assert np.array_equal(db[:4], np.stack([da[4 + k].T for k in (0, 2, 1, 3)]))
+
+
+def _sine_error(oracle, n, T, dt):
+    W, dW = inputs.sine_1d(n)
+    steps = int(round(T / dt))
+    W1, _, _, _ = oracle.step(oracle.params(ndim=1, bc=oracle.PERIODIC), W, dW, steps, fixed_dt=T / steps)
+    return np.abs(W1[0] - inputs.sine_1d_exact(n, T)[0]).mean()
+
+
+def test_convergence_order_spatial(oracle):
+    # dt = 0.4 h^2 makes the time error O(h^(2q)) for a time order q; the
+    # reconstruction alone is 8th order (see the reconstruction pins). The
+    # compact gradient update takes the interface values at the stage time from
+    # the linear-in-time BGK solution, which bounds the time order to q = 3:
+    # the measured order is 6 (2q), the time-limited design order.
+    e = [_sine_error(oracle, n, 0.1, 0.4 / n ** 2) for n in (8, 16, 32)]
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all(orders > 5.6), (e, orders)
+
+
+def test_convergence_order_space_time(oracle):
+    # at CFL 0.5 the time error dominates: third order (see above)
+    p = oracle.params(ndim=1, bc=oracle.PERIODIC)
+    e = []
+    for n in (32, 64, 128):
+        W, dW = inputs.sine_1d(n)
+        steps = int(math.ceil(0.5 / oracle.cfl_dt(p, W)))
+        e.append(_sine_error(oracle, n, 0.5, 0.5 / steps))
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all(np.abs(orders - 3.0) < 0.25), (e, orders)
+
+
+def test_isolated_contact_no_new_extrema(oracle):
+    # a density jump carried by U = 1, p = 1: GENO keeps the over/undershoot
+    # small and far below the linear scheme's (eps = 1e30 gives chi = 1)
+    n = 200
+    xc = (np.arange(n) + 0.5) / n
+    rho = np.where(xc < 0.3, 1.0, 0.25)
+    W = np.stack([rho, rho, 1.0 / 0.4 + 0.5 * rho]).reshape(3, 1, n)
+    res = {}
+    for name, eps in (("geno", 1e-15), ("linear", 1e30)):
+        W1, _, _, g = oracle.step(oracle.params(ndim=1, bc=oracle.TRANSMISSIVE, eps=eps), W, np.zeros_like(W), 100)
+        r = W1[0, 0]
+        res[name] = max(r.max() - 1.0, 0.25 - r.min())
+    assert res["geno"] < 0.03 * 0.75
+    assert res["geno"] < 0.25 * res["linear"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_riemann_jump_within_exact_bounds(oracle, seed):
+    # the seeded jump run: density and pressure stay within the exact solution's
+    # range up to 15 % of that range (component-wise reconstruction, no
+    # collision-time floor: start-up ripples of the jump stay bounded),
+    # up to 200 steps or until the fastest wave is 0.4 away from the jump
+    W, dW, st = inputs.jump_1d(200, seed)
+    L, R = st[0], st[1]
+    rmin, rmax, pmin, pmax = riemann_exact.bounds(L, R)
+    t_end = 0.4 / riemann_exact.wave_extent(L, R)
+    prm = oracle.params(ndim=1, bc=oracle.TRANSMISSIVE)
+    W1, dW1, t = W, dW, 0.0
+    for _ in range(200):
+        dt = oracle.cfl_dt(prm, W1)
+        if t + dt > t_end:
+            break
+        W1, dW1, _, _ = oracle.step(prm, W1, dW1, 1, fixed_dt=dt)
+        t += dt
+    rho = W1[0, 0]
+    p = 0.4 * (W1[2, 0] - 0.5 * W1[1, 0] ** 2 / rho)
+    tr, tp = 0.15 * (rmax - rmin), 0.15 * (pmax - pmin)
+    assert rmin - tr <= rho.min() and rho.max() <= rmax + tr
+    assert pmin - tp <= p.min() and p.max() <= pmax + tp
