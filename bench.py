@@ -1,0 +1,134 @@
+"""Benchmark of the compact-GKS GENO hot path on one MI355X.
+
+Workload (default): the 2-D Euler grid of 512 x 512 cells on [0,1]^2, FP64,
+transmissive boundaries, four seeded constant quadrants (rho ~ U[0.5,1.5],
+p ~ U[0.1,1.0], u, v ~ U[-0.5,0.5], seed 0), CFL 0.5. One benchmark step is
+one full two-stage GKS step (both stages: ghost cells, GENO reconstruction,
+tangential step, gas-kinetic flux at the Gauss points, update and gradient
+update, device-side dt). Inputs are resident in HBM before timing.
+
+Metric: million cell-updates per second per stage (interior cells x 2 stages
+x steps / time).
+
+Prints one JSON line (rank 0). `--gpus N` with N > 1 is rejected: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512, help="cells per side")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(W, dW, n):
+    """The oracle timed on the host: one full step of the same workload state
+    (2 x n^2 cell-stages)."""
+    from oracle import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    prm = oracle.params(ndim=2, bc=oracle.TRANSMISSIVE)
+    t0 = time.perf_counter()
+    oracle.step(prm, W, dW, 1)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * n * n / dt / 1e6, "unit": "Mcell-updates/s per stage", "cores": threads,
+            "kind": "oracle", "sample": "1 S2O4 step (2 stages) of the %dx%d quadrant state, %.1f s wall" % (n, n, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d); "
+              "the multi-GPU sharding is a design note, not a runnable path" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2507_20461_amd import geno_gks as G
+    from paper_2507_20461_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.n
+    W, dW, _ = inputs.quadrants_2d(n, n, args.seed)
+    grid = G.Grid(2, n, n, bc=G.BC_TRANSMISSIVE)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    stream = torch.cuda.current_stream()
+    # warm-up steps (not timed), then restart from the initial state
+    if args.warmup > 0:
+        G.gks_step(grid, Wd, dWd, ws, args.warmup)
+    Wd.copy_(grid.to_device(W))
+    dWd.copy_(grid.to_device(dW))
+    torch.cuda.synchronize()
+    if not args.no_kernel_timing:
+        G.timing_enable(16 * args.steps + 16)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    G.gks_step(grid, Wd, dWd, ws, args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    kt = G.timing_read() if not args.no_kernel_timing else {}
+    if not args.no_kernel_timing:
+        G.timing_enable(0)
+    Wend = grid.interior(Wd)
+    assert np.isfinite(Wend).all() and (Wend[0] > 0).all(), "non-physical state after the run"
+
+    cell_stages = 2.0 * n * n * args.steps
+    value = cell_stages / (ms / 1e3) / 1e6
+    kernels = {k: {"ms_total": round(v[0], 4), "launches": v[1],
+                   "us_avg": round(1e3 * v[0] / v[1], 3) if v[1] else None} for k, v in kt.items() if v[1]}
+    dominant = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
+    roofline = None
+    if dominant:
+        roofline = {"bound": "alu", "kernel": dominant, "achieved": None,
+                    "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": None, "traffic": None}
+    out = {
+        "metric": "Mcell-updates/s per stage (2-D Euler, compact GKS + GENO, FP64)",
+        "value": round(value, 3),
+        "unit": "Mcell-updates/s per stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2d-euler-%dx%d-quadrants-fp64" % (n, n), "nx": n, "ny": n, "steps": args.steps,
+                   "cfl": 0.5, "bc": "transmissive", "seed": args.seed, "precision": "fp64",
+                   "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, dW, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

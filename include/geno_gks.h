@@ -1,0 +1,198 @@
+/*
+ * geno_gks.h - C ABI of the MI355X (gfx950) library for the compact
+ * gas-kinetic scheme with GENO reconstruction (Zhao & Xu, "A generalized ENO
+ * reconstruction in compact GKS for compressible flow simulations").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers. Arrays named W, dW, face_state, chi, F, Ft, Wint, ws are DEVICE
+ *   pointers owned by the caller (the library never frees them). Structs
+ *   (geno_params, geno_grid, geno_stats) are HOST pointers.
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream). Every call only enqueues work on that stream and returns; the
+ *   library allocates nothing and synchronises nothing, except gks_step when a
+ *   geno_stats pointer is given (it then waits for the stream to read the
+ *   counters back).
+ * Errors. Every call returns 0 (GENO_OK) or a negative code; no exception
+ *   crosses the ABI. geno_last_error() returns a thread-local message for the
+ *   last failure on the calling thread.
+ * Layout of the state. Structure of arrays, float64, planar
+ *   [field][row][column] with NG = 2 ghost cells on every side of the grid:
+ *   element (field f, interior row j in [-2, ny+2), interior column i in
+ *   [-2, nx+2)) sits at index (f * rows + (j + 2)) * pitch + (i + 2), where
+ *   pitch and rows come from geno_grid_init (1-D: rows = 1, j = 0 only).
+ *   Fields: 1-D W = (rho, rhoU, rhoE) and dW = (d/dx of each);
+ *           2-D W = (rho, rhoU, rhoV, rhoE) and dW = (d/dx of the four
+ *           fields, then d/dy of the four fields).
+ *   dW holds physical cell-averaged gradients (not scaled by the cell size).
+ *   Ghost cells belong to the library: calls overwrite them; interior cells
+ *   are written only by gks_step.
+ */
+#ifndef GENO_GKS_H
+#define GENO_GKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GENO_ABI_VERSION 1
+
+/* error codes */
+#define GENO_OK 0
+#define GENO_EINVAL (-1)     /* null pointer, bad size, unsupported parameter */
+#define GENO_EVERSION (-2)   /* geno_params.version != GENO_ABI_VERSION */
+#define GENO_EHIP (-3)       /* a HIP runtime call failed */
+#define GENO_ENONPHYS (-4)   /* non-finite state found when stats were read */
+
+/* boundary conditions (per side) */
+#define GENO_BC_PERIODIC 0
+#define GENO_BC_TRANSMISSIVE 1
+
+/* arithmetic of the reconstruction and the flux */
+#define GENO_F64 0
+
+/* Method parameters.
+ * C, eps, r, rL, d: GENO constants of Sec. 3 (Eq. (4), (5), (8)): the paper
+ *   uses C = 20, eps = 1e-15, r = 2 on structured meshes, r^L = 2 and the
+ *   central sub-stencil weight C_0 = 8, i.e. d = (1, 8, 1) for the 8th-order
+ *   compact stencils S_1, S_2, S_3 of Sec. 4.2. This library implements
+ *   r = rL = 2 only (other values give GENO_EINVAL).
+ * gamma: ratio of specific heats.
+ * tau_c1, tau_c2: collision time of the BGK flux,
+ *   tau = tau_c1 dt + tau_c2 dt |p_l - p_r| / (p_l + p_r).
+ * cfl: dt = cfl * min over interior cells of min(dx/(|U|+c), dy/(|V|+c)).
+ * bc: x-low, x-high, y-low, y-high (GENO_BC_*); periodic must be set on both
+ *   sides of an axis. */
+typedef struct geno_params {
+  int version;
+  int precision;   /* GENO_F64 */
+  double gamma;
+  double C;
+  double eps;
+  double r;
+  double rL;
+  double d[3];
+  double tau_c1;
+  double tau_c2;
+  double cfl;
+  int bc[4];
+} geno_params;
+
+/* Grid description filled by geno_grid_init. */
+typedef struct geno_grid {
+  int ndim;        /* 1 or 2 */
+  int nx, ny;      /* interior cells (ny = 1 in 1-D) */
+  int pitch;       /* elements per padded row (>= nx + 4, multiple of 16) */
+  int rows;        /* padded rows per field (ny + 4 in 2-D, 1 in 1-D) */
+  double x0, x1, y0, y1;
+  double dx, dy;
+  geno_params params;
+} geno_grid;
+
+/* Counters returned by gks_step when asked for. */
+typedef struct geno_stats {
+  long long guard;      /* point states replaced by their cell average (rho<=0, p<=0 or non-finite) */
+  long long nonfinite;  /* non-finite interior cells after the last step */
+  double last_dt;       /* time step of the last step */
+} geno_stats;
+
+/* Library ABI version (GENO_ABI_VERSION). */
+int geno_abi_version(void);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* geno_last_error(void);
+
+/* Default parameters: the paper's GENO constants (Sec. 3), gamma = 1.4,
+ * tau_c1 = 0, tau_c2 = 1, cfl = 0.5, transmissive boundaries, FP64. */
+int geno_params_default(geno_params* p);
+
+/* Fills *g for an ndim-dimensional uniform grid of nx (x ny) cells on
+ * [x0, x1] (x [y0, y1]); copies *p. GENO_EINVAL for sizes < 1 (1-D: ny is
+ * ignored), inverted intervals or unsupported parameters. */
+int geno_grid_init(geno_grid* g, int ndim, int nx, int ny, double x0, double x1,
+                   double y0, double y1, const geno_params* p);
+
+/* Number of doubles of one state array (W: nv fields; dW: ndim * nv). */
+size_t geno_state_elems(const geno_grid* g, int nfields);
+
+/* Bytes of the device workspace needed by gks_step / gks_flux. */
+size_t gks_workspace_bytes(const geno_grid* g);
+
+/* GENO reconstruction (Sec. 3, Eq. (3)-(9); 8th-order compact stencils of
+ * Sec. 4.2, Eq. (13)-(14)) on every face of direction dir (0: x, 1: y; 1-D:
+ * 0) after filling the ghost cells of W and dW in place.
+ * face_state (device, caller-allocated): per face, per Gauss point, per side,
+ *   the reconstructed state at the point after the positivity guard:
+ *   [side(2)][gauss(G)][quant(Q)][var(nv)][nfy][nfx] doubles with
+ *   1-D: G = 1, Q = 2 (value, h * d/dn), nfy = 1, nfx = nx + 1;
+ *   2-D: G = 2 (the points +-h/(2 sqrt 3) about the face centre, the
+ *        negative tangential offset first), Q = 3 (value, h * d/dn,
+ *        h * d/dt), x-faces nfy = ny, nfx = nx + 1; y-faces nfy = ny + 1,
+ *        nfx = nx. Face (a, b) of x lies between cells (b-1, a) and (b, a);
+ *        of y between (b, a-1) and (b, a). Side 0 = the lower-index cell.
+ *   h is the cell size along the normal (d/dn) or the tangent (d/dt).
+ *   Variables stay in the (x, y) frame.
+ * chi (device, may be NULL): path function of the normal reconstruction per
+ *   [side][var][row][face] over the rows the tangential step reads:
+ *   1-D 1 x (nx+1); x-faces (ny+2) x (nx+1) (rows -1..ny); y-faces
+ *   (ny+1) x (nx+2) (columns -1..nx) - the same face-row layout with rows and
+ *   faces swapped, i.e. [side][var][face a][column b].
+ * ws: workspace of gks_workspace_bytes(g) bytes. */
+int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_state,
+                     void* chi, void* ws, void* stream);
+
+/* Gas-kinetic interface flux (BGK solution of the standard high-order GKS;
+ * the paper defers its details to the literature, Sec. 2) at every point of
+ * face_state (layout of geno_reconstruct), with time step dt and the
+ * collision time of geno_params. Outputs per face, averaged over the Gauss
+ * points with weights 1/2 (Sec. 2 face quadrature), [var][nfy][nfx]:
+ *   F    = flux at the start of the step, from fitting F + t dF/dt to the
+ *          time integrals of the flux over dt/2 and dt;
+ *   Ft   = dF/dt of that fit;
+ *   Wint = conserved state of the interface solution at t = dt/2.
+ * Any of F, Ft, Wint may be NULL. dir as in geno_reconstruct. */
+int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, void* F,
+             void* Ft, void* Wint, void* stream);
+
+/* nsteps steps of the two-stage fourth-order GKS update of W and dW in place
+ * (Eq. (1): face fluxes; Eq. (2): cell-averaged gradients from the interface
+ * states by the Gauss theorem). Each step: dt from the CFL condition on the
+ * current state; stage 1 W* = W + dt/2 L + dt^2/8 dL/dt and gradients from
+ * the interface states at dt/2; stage 2 W = W + dt L + dt^2/6 dL/dt +
+ * dt^2/3 dL/dt(W*) with gradients from the stage-2 interface states at dt/2.
+ * ws: workspace of gks_workspace_bytes(g) bytes.
+ * dt_out (device, may be NULL): nsteps doubles, the step sizes.
+ * stats (host, may be NULL): if given, the call waits for the stream and
+ *   fills the counters; returns GENO_ENONPHYS if a non-finite cell is found. */
+int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
+             geno_stats* stats, void* stream);
+
+/* ---- measurement support ------------------------------------------------
+ * Kernel kinds reported by geno_timing_read. */
+enum {
+  GENO_K_GHOST_X = 0, GENO_K_GHOST_Y, GENO_K_NORMAL_X, GENO_K_NORMAL_Y, GENO_K_FACES_X, GENO_K_FACES_Y,
+  GENO_K_UPDATE_1, GENO_K_UPDATE_2, GENO_K_DT_INIT, GENO_K_FACES_1D, GENO_NKERNELS
+};
+
+/* Enables per-kernel timing of gks_step: HIP events are recorded on the
+ * call's stream around each of its first max_launches launches (events are
+ * created here, once; 0 disables timing and releases them). Not thread-safe:
+ * intended for benchmarks. */
+int geno_timing_enable(int max_launches);
+
+/* Waits for the recorded events, writes per kernel kind the summed duration
+ * in milliseconds and the launch count (arrays of nkinds entries, host), and
+ * starts a new recording. */
+int geno_timing_read(int nkinds, double* ms_total, long long* launches);
+
+/* Name of a kernel kind ("" if out of range). */
+const char* geno_kernel_name(int kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENO_GKS_H */

@@ -1,0 +1,211 @@
+"""Python binding of the HIP library ``libgeno_gks.so`` (C ABI in ``include/geno_gks.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+kernels. torch provides device memory and the current HIP stream. The
+library is required: importing this module on a machine without the built
+library, or calling it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
+
+GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+F64 = 0
+ABI_VERSION = 1
+NG = 2
+
+
+class geno_params(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int), ("precision", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("C", ctypes.c_double), ("eps", ctypes.c_double), ("r", ctypes.c_double),
+                ("rL", ctypes.c_double), ("d", ctypes.c_double * 3), ("tau_c1", ctypes.c_double),
+                ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4)]
+
+
+class geno_grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("pitch", ctypes.c_int), ("rows", ctypes.c_int), ("x0", ctypes.c_double),
+                ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("params", geno_params)]
+
+
+class geno_stats(ctypes.Structure):
+    _fields_ = [("guard", ctypes.c_longlong), ("nonfinite", ctypes.c_longlong),
+                ("last_dt", ctypes.c_double)]
+
+
+EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_grid_init",
+           "geno_state_elems", "gks_workspace_bytes", "geno_reconstruct", "gks_flux", "gks_step",
+           "geno_timing_enable", "geno_timing_read", "geno_kernel_name")
+KERNELS = ("ghost_x", "ghost_y", "normal_x", "normal_y", "faces_x", "faces_y", "update_1", "update_2",
+           "dt_init", "faces_1d")
+
+_lib = None
+
+
+class GenoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("geno error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.geno_abi_version.restype = i
+        L.geno_last_error.restype = ctypes.c_char_p
+        L.geno_params_default.argtypes = [ctypes.POINTER(geno_params)]
+        L.geno_grid_init.argtypes = [ctypes.POINTER(geno_grid), i, i, i, d, d, d, d,
+                                     ctypes.POINTER(geno_params)]
+        L.geno_state_elems.argtypes = [ctypes.POINTER(geno_grid), i]
+        L.geno_state_elems.restype = ctypes.c_size_t
+        L.gks_workspace_bytes.argtypes = [ctypes.POINTER(geno_grid)]
+        L.gks_workspace_bytes.restype = ctypes.c_size_t
+        L.geno_reconstruct.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, vp, vp, vp]
+        L.gks_flux.argtypes = [ctypes.POINTER(geno_grid), vp, d, i, vp, vp, vp, vp]
+        L.gks_step.argtypes = [ctypes.POINTER(geno_grid), vp, vp, vp, i, vp,
+                               ctypes.POINTER(geno_stats), vp]
+        L.geno_timing_enable.argtypes = [i]
+        L.geno_timing_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+        L.geno_kernel_name.argtypes = [i]
+        L.geno_kernel_name.restype = ctypes.c_char_p
+        for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
+                     "geno_timing_enable", "geno_timing_read"):
+            getattr(L, name).restype = i
+        if L.geno_abi_version() != ABI_VERSION:
+            raise RuntimeError("library ABI %d != binding ABI %d" % (L.geno_abi_version(), ABI_VERSION))
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != GENO_OK:
+        raise GenoError(rc, lib().geno_last_error().decode())
+
+
+def default_params(**kw) -> geno_params:
+    p = geno_params()
+    _check(lib().geno_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "bc":
+            bcs = [v] * 4 if np.isscalar(v) else list(v)
+            for j in range(4):
+                p.bc[j] = int(bcs[j])
+        elif k == "d":
+            for j in range(3):
+                p.d[j] = float(v[j])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Grid:
+    """A uniform 1-D or 2-D grid and its padded state layout."""
+
+    def __init__(self, ndim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, params=None, **kw):
+        self.params = params if params is not None else default_params(**kw)
+        self.g = geno_grid()
+        _check(lib().geno_grid_init(ctypes.byref(self.g), ndim, nx, ny, x0, x1, y0, y1,
+                                    ctypes.byref(self.params)))
+        self.ndim, self.nx, self.ny = ndim, nx, self.g.ny
+        self.nv = 3 if ndim == 1 else 4
+        self.pitch, self.rows = self.g.pitch, self.g.rows
+        self.yoff = NG if ndim == 2 else 0
+
+    @property
+    def dx(self):
+        return self.g.dx
+
+    @property
+    def dy(self):
+        return self.g.dy
+
+    def workspace(self, device="cuda"):
+        n = lib().gks_workspace_bytes(ctypes.byref(self.g))
+        return torch.empty(n, dtype=torch.uint8, device=device)
+
+    def empty_state(self, nfields, device="cuda"):
+        return torch.zeros((nfields, self.rows, self.pitch), dtype=torch.float64, device=device)
+
+    def to_device(self, A, device="cuda"):
+        """Interior array [f, ny, nx] -> padded device tensor [f, rows, pitch]."""
+        A = np.asarray(A, dtype=np.float64)
+        out = np.zeros((A.shape[0], self.rows, self.pitch))
+        out[:, self.yoff:self.yoff + self.ny, NG:NG + self.nx] = A
+        return torch.from_numpy(out).to(device)
+
+    def interior(self, T):
+        """Padded tensor -> interior numpy array [f, ny, nx]."""
+        A = T.detach().cpu().numpy()
+        return A[:, self.yoff:self.yoff + self.ny, NG:NG + self.nx].copy()
+
+    def face_state_shape(self, direction=0):
+        if self.ndim == 1:
+            return (2, 1, 2, 3, 1, self.nx + 1)
+        nfx, nfy = (self.nx + 1, self.ny) if direction == 0 else (self.nx, self.ny + 1)
+        return (2, 2, 3, 4, nfy, nfx)
+
+    def chi_shape(self, direction=0):
+        if self.ndim == 1:
+            return (2, 3, 1, self.nx + 1)
+        return (2, 4, self.ny + 2, self.nx + 1) if direction == 0 else (2, 4, self.ny + 1, self.nx + 2)
+
+    def flux_shape(self, direction=0):
+        if self.ndim == 1:
+            return (3, 1, self.nx + 1)
+        return (4, self.ny, self.nx + 1) if direction == 0 else (4, self.ny + 1, self.nx)
+
+
+def geno_reconstruct(grid, W, dW, direction, face_state, chi, ws, stream=None):
+    _check(lib().geno_reconstruct(ctypes.byref(grid.g), _ptr(W), _ptr(dW), int(direction),
+                                  _ptr(face_state), _ptr(chi), _ptr(ws), _stream(stream)))
+
+
+def gks_flux(grid, face_state, dt, direction, F, Ft, Wint, stream=None):
+    _check(lib().gks_flux(ctypes.byref(grid.g), _ptr(face_state), float(dt), int(direction),
+                          _ptr(F), _ptr(Ft), _ptr(Wint), _stream(stream)))
+
+
+def gks_step(grid, W, dW, ws, nsteps, dt_out=None, stats=False, stream=None):
+    """nsteps S2O4 steps in place. Returns a geno_stats if stats=True (synchronises)."""
+    st = geno_stats() if stats else None
+    rc = lib().gks_step(ctypes.byref(grid.g), _ptr(W), _ptr(dW), _ptr(ws), int(nsteps), _ptr(dt_out),
+                        ctypes.byref(st) if st is not None else None, _stream(stream))
+    _check(rc)
+    return st
+
+
+def timing_enable(max_launches):
+    _check(lib().geno_timing_enable(int(max_launches)))
+
+
+def timing_read():
+    """{kernel name: (total ms, launches)} of the launches recorded since the last read."""
+    n = len(KERNELS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    _check(lib().geno_timing_read(n, ms, cnt))
+    return {lib().geno_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
