@@ -76,36 +76,76 @@ def main():
     Wd, dWd = grid.to_device(W), grid.to_device(dW)
     ws = grid.workspace()
     stream = torch.cuda.current_stream()
-    # warm-up steps (not timed), then restart from the initial state
+    # a plain device copy of known size (HBM traffic calibration for counter
+    # profiles; not timed)
+    cal = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
+    cal2 = torch.empty_like(cal)
+    cal2.copy_(cal)
+    del cal, cal2
+    # warm-up steps (not timed)
     if args.warmup > 0:
         G.gks_step(grid, Wd, dWd, ws, args.warmup)
-    Wd.copy_(grid.to_device(W))
-    dWd.copy_(grid.to_device(dW))
-    torch.cuda.synchronize()
-    if not args.no_kernel_timing:
-        G.timing_enable(16 * args.steps + 16)
+
+    def restart():
+        Wd.copy_(grid.to_device(W))
+        dWd.copy_(grid.to_device(dW))
+        torch.cuda.synchronize()
+
+    # 1) timed region: K steps from the initial state, no per-kernel events
+    restart()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     start.record(stream)
     G.gks_step(grid, Wd, dWd, ws, args.steps)
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
-    kt = G.timing_read() if not args.no_kernel_timing else {}
-    if not args.no_kernel_timing:
-        G.timing_enable(0)
     Wend = grid.interior(Wd)
     assert np.isfinite(Wend).all() and (Wend[0] > 0).all(), "non-physical state after the run"
+    kt, work, costs = {}, {}, G.op_costs(grid)
+    ms_events = None
+    if not args.no_kernel_timing:
+        # 2) the same K steps with HIP events around every launch (on the
+        # stream the kernels run on): per-kernel durations
+        restart()
+        G.timing_enable(16 * args.steps + 16)
+        start.record(stream)
+        G.gks_step(grid, Wd, dWd, ws, args.steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms_events = start.elapsed_time(end)
+        kt = G.timing_read()
+        G.timing_enable(0)
+        # 3) untimed replay with work counting (the update is deterministic,
+        # so the counts are those of the timed run)
+        restart()
+        G.count_enable(True)
+        G.gks_step(grid, Wd, dWd, ws, args.steps)
+        G.count_enable(False)
+        work = G.work_read(grid, ws)
+        assert np.array_equal(grid.interior(Wd), Wend), "replay differs from the timed run"
 
     cell_stages = 2.0 * n * n * args.steps
     value = cell_stages / (ms / 1e3) / 1e6
-    kernels = {k: {"ms_total": round(v[0], 4), "launches": v[1],
-                   "us_avg": round(1e3 * v[0] / v[1], 3) if v[1] else None} for k, v in kt.items() if v[1]}
+    kernels = {}
+    for k, (kms, nl) in kt.items():
+        if not nl:
+            continue
+        flops = sum(work[k][c] * costs[k][c] for c in costs[k])
+        kernels[k] = {"ms_total": round(kms, 4), "launches": nl, "us_avg": round(1e3 * kms / nl, 3),
+                      "gflop_per_launch": round(flops / nl / 1e9, 6),
+                      "tflops": round(flops / (kms / 1e3) / 1e12, 4) if kms > 0 else None,
+                      "work": {c: work[k][c] for c in work[k] if work[k][c]}}
     dominant = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
     roofline = None
     if dominant:
-        roofline = {"bound": "alu", "kernel": dominant, "achieved": None,
-                    "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": None, "traffic": None}
+        d = kernels[dominant]
+        achieved = d["tflops"]
+        roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved,
+                    "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 5) if achieved else None,
+                    "traffic": None,
+                    "flop_convention": "add/sub/mul/div/sqrt and each exp/expm1/erfc/tanh call = 1 FP64 op",
+                    "gflop_per_launch": d["gflop_per_launch"], "us_per_launch": d["us_avg"]}
     out = {
         "metric": "Mcell-updates/s per stage (2-D Euler, compact GKS + GENO, FP64)",
         "value": round(value, 3),
@@ -124,6 +164,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": roofline,
         "kernels": kernels,
+        "ms_per_step_with_kernel_events": round(ms_events / args.steps, 5) if ms_events else None,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)

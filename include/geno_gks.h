@@ -171,22 +171,60 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
              geno_stats* stats, void* stream);
 
 /* ---- measurement support ------------------------------------------------
- * Kernel kinds reported by geno_timing_read. */
+ * Kernel kinds of gks_step reported by geno_timing_read / geno_work_read. */
 enum {
-  GENO_K_GHOST_X = 0, GENO_K_GHOST_Y, GENO_K_NORMAL_X, GENO_K_NORMAL_Y, GENO_K_FACES_X, GENO_K_FACES_Y,
-  GENO_K_UPDATE_1, GENO_K_UPDATE_2, GENO_K_DT_INIT, GENO_K_FACES_1D, GENO_NKERNELS
+  GENO_K_INIT = 0,     /* ghost cells of the initial state + its CFL partial minima */
+  GENO_K_NORMAL_X,     /* normal GENO on x-face rows */
+  GENO_K_NORMAL_Y,     /* normal GENO on y-face columns */
+  GENO_K_FACES_X,      /* tangential step + gas-kinetic flux, x-faces with tau = 0 */
+  GENO_K_FACES_Y,
+  GENO_K_SLOW_X,       /* the same for the x-faces queued with tau > 0 */
+  GENO_K_SLOW_Y,
+  GENO_K_UPDATE_1,     /* stage-1 update, gradients, ghost cells of the stage state */
+  GENO_K_UPDATE_2,     /* stage-2 update, gradients, ghost cells, CFL partial minima */
+  GENO_K_FACES_1D,     /* 1-D: GENO + flux per face */
+  GENO_NKERNELS
 };
 
-/* Enables per-kernel timing of gks_step: HIP events are recorded on the
+/* Work classes counted per kernel kind while timing is enabled. */
+enum {
+  GENO_W_UNITS = 0,    /* threads' work units: face-rows, faces, cells */
+  GENO_W_TANH,         /* path-function evaluations that call tanh */
+  GENO_W_LOW,          /* reconstructions that form the low-order part (chi < 1) */
+  GENO_W_FAST,         /* gas-kinetic points evaluated with tau = 0 */
+  GENO_W_SLOW,         /* gas-kinetic points evaluated with tau > 0 */
+  GENO_W_GUARD,        /* point states replaced by the cell average */
+  GENO_NCLASS
+};
+
+/* Enables per-kernel timing in gks_step: HIP events are recorded on the
  * call's stream around each of its first max_launches launches (events are
- * created here, once; 0 disables timing and releases them). Not thread-safe:
+ * created here, once; 0 disables and releases them). Not thread-safe:
  * intended for benchmarks. */
 int geno_timing_enable(int max_launches);
+
+/* Enables (on != 0) or disables counting of the work classes in gks_step.
+ * Counting adds one atomic per wave and class, so it is meant for a separate,
+ * untimed replay of a timed run (the update is deterministic). */
+int geno_count_enable(int on);
 
 /* Waits for the recorded events, writes per kernel kind the summed duration
  * in milliseconds and the launch count (arrays of nkinds entries, host), and
  * starts a new recording. */
 int geno_timing_read(int nkinds, double* ms_total, long long* launches);
+
+/* Work counts of the last gks_step call on workspace ws (counted only while
+ * counting is enabled): counts[kind * nclass + class], host array. Waits for
+ * the stream. */
+int geno_work_read(const geno_grid* g, const void* ws, int nkinds, int nclass, long long* counts,
+                   void* stream);
+
+/* Floating-point operations per work item of each class and kernel kind, as
+ * executed by the device functions (add, sub, mul, div, sqrt, compare-free;
+ * each elementary function call counts 1): costs[kind * nclass + class] for
+ * the grid's dimension. Units: the per-unit cost excludes the optional
+ * branches, which the other classes add. */
+int geno_op_costs(const geno_grid* g, int nkinds, int nclass, double* costs);
 
 /* Name of a kernel kind ("" if out of range). */
 const char* geno_kernel_name(int kind);

@@ -8,6 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "geno_gks.hip")
+SRCS = [SRC, os.path.join(PKG, "csrc", "opcount.hip")]
 HEADERS = [os.path.join(PKG, "csrc", h) for h in ("geno_device.hpp", "gks_device.hpp")] + [
     os.path.join(ROOT, "include", "geno_gks.h")]
 LIB = os.path.join(PKG, "libgeno_gks.so")
@@ -15,6 +16,9 @@ ARCH = "gfx950"
 
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    # contract a*b+c into FMA only within one expression, so that the x and y
+    # instantiations of a kernel round identically (bitwise transpose symmetry)
+    "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"),
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -24,7 +28,7 @@ FLAGS = [
 def build(extra=(), verbose=False) -> str:
     """Compile the library (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["/opt/rocm/bin/hipcc", *FLAGS, *extra, "-o", tmp, SRC]
+    cmd = ["/opt/rocm/bin/hipcc", *FLAGS, *extra, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -36,7 +40,7 @@ def stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in [SRC, *HEADERS])
+    return any(os.path.getmtime(p) > t for p in [*SRCS, *HEADERS])
 
 
 if __name__ == "__main__":

@@ -1,9 +1,18 @@
 // Device functions of the GENO reconstruction (Zhao & Xu, Sec. 3 and Sec. 4.2)
-// for gfx950. Scalar per-thread code: one thread owns one face (or one
-// face-row) and keeps every intermediate in registers.
+// for gfx950. Scalar per-thread code: one thread owns one face-row (normal
+// step) or one (face, side, variable) (tangential step) and keeps every
+// intermediate in registers.
+//
+// Templated on the arithmetic type R of the reconstruction (double, float)
+// and on the type D of the small-epsilon divisions of the smoothness
+// indicators (always double on the GPU: eps = 1e-15 and IS^2 ~ 1e-30 are
+// out of FP32 range). The functions are host+device so that the same code can
+// be instantiated with an operation-counting type on the host.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#define GENO_HD __host__ __device__ __forceinline__
 
 namespace geno {
 
@@ -25,14 +34,14 @@ struct KParams {
 // evaluated over the common denominator (IS^H+eps)^2 (IS^L+eps)^2 so that a
 // single division remains. tanh(x) rounds to 1 for x > 19.8 (its distance to
 // 1 is below 1e-17), so the call is skipped there.
-__device__ __forceinline__ double path_chi(double IStau, double ISH, double ISL,
-                                           const KParams& k) {
-  const double a = ISH + k.eps, b = ISL + k.eps, t2 = IStau * IStau;
-  const double a2 = a * a, b2 = b * b;
-  const double num = (a2 + t2) * b2;
-  const double alpha = 2.0 * num / (num + (b2 + t2) * a2);
-  const double x = k.C * alpha;
-  const double th = (x > 19.8) ? 1.0 : tanh(x);
+template <typename D>
+GENO_HD D path_chi(D IStau, D ISH, D ISL, const KParams& k) {
+  const D a = ISH + k.eps, b = ISL + k.eps, t2 = IStau * IStau;
+  const D a2 = a * a, b2 = b * b;
+  const D num = (a2 + t2) * b2;
+  const D alpha = 2.0 * num / (num + (b2 + t2) * a2);
+  const D x = k.C * alpha;
+  const D th = (x > 19.8) ? D(1.0) : tanh(x);
   return (k.tanhC == 1.0) ? th : th / k.tanhC;
 }
 
@@ -40,13 +49,12 @@ __device__ __forceinline__ double path_chi(double IStau, double ISH, double ISL,
 // at x_{j+1/2}: value and h * derivative of the degree-7 polynomial whose cell
 // averages and averaged h-scaled derivatives match those of the four cells.
 // Written in symmetric pairs so that the mirrored evaluation is exact.
-__device__ __forceinline__ void linear_p7(double Qm, double Q0, double Q1, double Q2, double Gm,
-                                          double G0, double G1, double G2, double& qH,
-                                          double& hqH) {
-  qH = (5.0 * (Qm + Q2) + 37.0 * (Q0 + Q1)) * (1.0 / 84.0) +
-       ((Gm - G2) + 17.0 * (G0 - G1)) * (1.0 / 70.0);
-  hqH = 7.0 * (Q2 - Qm) * (1.0 / 54.0) + 2.5 * (Q1 - Q0) -
-        ((Gm + G2) * (1.0 / 36.0) + 11.0 * (G0 + G1) * (1.0 / 12.0));
+template <typename R>
+GENO_HD void linear_p7(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2, R& qH, R& hqH) {
+  qH = (R(5.0) * (Qm + Q2) + R(37.0) * (Q0 + Q1)) * R(1.0 / 84.0) +
+       ((Gm - G2) + R(17.0) * (G0 - G1)) * R(1.0 / 70.0);
+  hqH = R(7.0) * (Q2 - Qm) * R(1.0 / 54.0) + R(2.5) * (Q1 - Q0) -
+        ((Gm + G2) * R(1.0 / 36.0) + R(11.0) * (G0 + G1) * R(1.0 / 12.0));
 }
 
 // GENO value and h * derivative at the face on the right of cell j (the
@@ -58,55 +66,59 @@ __device__ __forceinline__ void linear_p7(double Qm, double Q0, double Q1, doubl
 // IS^H = max, IS^L = min, IS^tau = |(IS_2 + IS_3)/2 - IS_1|; ENO weights
 // d_k/(IS_k + eps)^2 normalised (Eq. (8)), evaluated over a common
 // denominator. When chi == 1 exactly the low-order part carries weight 0 and
-// is not formed.
-__device__ __forceinline__ void geno_side(double Qm, double Q0, double Q1, double Q2, double Gm,
-                                          double qH, double hqH, const KParams& k,
-                                          double& val, double& hder, double& chi) {
-  const double B1 = 2.0 * (Q0 - Qm) - Gm, C1 = (Q0 - Qm) - Gm;
-  const double B2 = 0.5 * (Q1 - Qm), C2 = 0.5 * (Q1 - 2.0 * Q0 + Qm);
-  const double B3 = 0.5 * (4.0 * Q1 - 3.0 * Q0 - Q2), C3 = 0.5 * (Q0 - 2.0 * Q1 + Q2);
-  const double c13 = 13.0 / 3.0;
-  const double IS1 = B1 * B1 + c13 * (C1 * C1);
-  const double IS2 = B2 * B2 + c13 * (C2 * C2);
-  const double IS3 = B3 * B3 + c13 * (C3 * C3);
-  const double ISH = fmax(IS1, fmax(IS2, IS3));
-  const double ISL = fmin(IS1, fmin(IS2, IS3));
-  const double IStau = fabs(0.5 * (IS2 + IS3) - IS1);
-  chi = path_chi(IStau, ISH, ISL, k);
+// is not formed. Returns true on the low-order branch (chi < 1).
+template <typename R, typename D>
+GENO_HD bool geno_side(R Qm, R Q0, R Q1, R Q2, R Gm, R qH, R hqH, const KParams& k, R& val,
+                       R& hder, D& chi) {
+  const R B1 = R(2.0) * (Q0 - Qm) - Gm, C1 = (Q0 - Qm) - Gm;
+  const R B2 = R(0.5) * (Q1 - Qm), C2 = R(0.5) * (Q1 - R(2.0) * Q0 + Qm);
+  const R B3 = R(0.5) * (R(4.0) * Q1 - R(3.0) * Q0 - Q2), C3 = R(0.5) * (Q0 - R(2.0) * Q1 + Q2);
+  const R c13 = R(13.0 / 3.0);
+  const D IS1 = D(B1 * B1 + c13 * (C1 * C1));
+  const D IS2 = D(B2 * B2 + c13 * (C2 * C2));
+  const D IS3 = D(B3 * B3 + c13 * (C3 * C3));
+  const D ISH = fmax(IS1, fmax(IS2, IS3));
+  const D ISL = fmin(IS1, fmin(IS2, IS3));
+  const D IStau = fabs(0.5 * (IS2 + IS3) - IS1);
+  chi = path_chi<D>(IStau, ISH, ISL, k);
   if (chi == 1.0) {
     val = qH;
     hder = hqH;
-    return;
+    return false;
   }
-  double e1 = IS1 + k.eps, e2 = IS2 + k.eps, e3 = IS3 + k.eps;
-  e1 *= e1;
-  e2 *= e2;
-  e3 *= e3;
-  const double w1 = k.d1 * (e2 * e3), w2 = k.d2 * (e1 * e3), w3 = k.d3 * (e1 * e2);
-  const double inv = 1.0 / (w1 + w2 + w3);
-  const double s6 = 1.0 / 6.0;
-  const double p1 = Q0 + 0.5 * B1 + s6 * C1;
-  const double p2 = Q0 + 0.5 * B2 + s6 * C2;
-  const double p3 = Q0 + 0.5 * B3 + s6 * C3;
-  const double qL = (w1 * p1 + w2 * p2 + w3 * p3) * inv;
-  const double hqL = (w1 * (B1 + C1) + w2 * (B2 + C2) + w3 * (B3 + C3)) * inv;
-  val = chi * qH + (1.0 - chi) * qL;
-  hder = chi * hqH + (1.0 - chi) * hqL;
+  D e1 = IS1 + k.eps, e2 = IS2 + k.eps, e3 = IS3 + k.eps;
+  e1 = e1 * e1;
+  e2 = e2 * e2;
+  e3 = e3 * e3;
+  const D w1 = k.d1 * (e2 * e3), w2 = k.d2 * (e1 * e3), w3 = k.d3 * (e1 * e2);
+  const D inv = 1.0 / (w1 + w2 + w3);
+  const R o1 = R(w1 * inv), o2 = R(w2 * inv), o3 = R(w3 * inv);
+  const R s6 = R(1.0 / 6.0);
+  const R p1 = Q0 + R(0.5) * B1 + s6 * C1;
+  const R p2 = Q0 + R(0.5) * B2 + s6 * C2;
+  const R p3 = Q0 + R(0.5) * B3 + s6 * C3;
+  const R qL = o1 * p1 + o2 * p2 + o3 * p3;
+  const R hqL = o1 * (B1 + C1) + o2 * (B2 + C2) + o3 * (B3 + C3);
+  const R x = R(chi), xm = R(1.0 - chi);
+  val = x * qH + xm * qL;
+  hder = x * hqH + xm * hqL;
+  return true;
 }
 
 // Both states at face j+1/2 for one component from cells j-1..j+2. The right
 // state (cell j+1) is the left-state formula applied to the data reflected
 // about the face: Q~_m = Q_{1-m}, G~_m = -G_{1-m}; its derivative changes sign.
-__device__ __forceinline__ void geno_face(double Qm, double Q0, double Q1, double Q2, double Gm,
-                                          double G0, double G1, double G2, const KParams& k,
-                                          double& vl, double& dl, double& xl, double& vr,
-                                          double& dr, double& xr) {
-  double qH, hqH;
-  linear_p7(Qm, Q0, Q1, Q2, Gm, G0, G1, G2, qH, hqH);
-  geno_side(Qm, Q0, Q1, Q2, Gm, qH, hqH, k, vl, dl, xl);
-  double dm;
-  geno_side(Q2, Q1, Q0, Qm, -G2, qH, -hqH, k, vr, dm, xr);
+// Returns the number of sides on the low-order branch.
+template <typename R, typename D>
+GENO_HD int geno_face(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2, const KParams& k, R& vl,
+                      R& dl, D& xl, R& vr, R& dr, D& xr) {
+  R qH, hqH;
+  linear_p7<R>(Qm, Q0, Q1, Q2, Gm, G0, G1, G2, qH, hqH);
+  int n = geno_side<R, D>(Qm, Q0, Q1, Q2, Gm, qH, hqH, k, vl, dl, xl);
+  R dm;
+  n += geno_side<R, D>(Q2, Q1, Q0, Qm, -G2, qH, -hqH, k, vr, dm, xr);
   dr = -dm;
+  return n;
 }
 
 // Gauss points of a face: +-1/(2 sqrt 3) of its length about its centre.
@@ -120,31 +132,52 @@ __device__ __forceinline__ void geno_face(double Qm, double Q0, double Q1, doubl
 // one the ENO combination (d = 1, r^L = 2) of the slopes s_- and s_+; the two
 // are blended by the path function with IS_+- = s_+-^2, IS^H = max,
 // IS^L = min, IS^tau = |IS_+ - IS_-|. Point 0 is at -eta, point 1 at +eta.
-__device__ __forceinline__ void tangential(double phm, double ph0, double php, const KParams& k,
-                                           double& v0, double& v1, double& t0, double& t1) {
-  const double sm = ph0 - phm, sp = php - ph0;
-  const double sc = 0.5 * (sm + sp), d2 = sp - sm;
-  const double ISm = sm * sm, ISp = sp * sp;
-  const double chi = path_chi(fabs(ISp - ISm), fmax(ISm, ISp), fmin(ISm, ISp), k);
-  double s, th0, th1;
+// Returns true on the low-order branch.
+template <typename R, typename D>
+GENO_HD bool tangential(R phm, R ph0, R php, const KParams& k, R& v0, R& v1, R& t0, R& t1) {
+  const R sm = ph0 - phm, sp = php - ph0;
+  const R sc = R(0.5) * (sm + sp), d2 = sp - sm;
+  const D ISm = D(sm * sm), ISp = D(sp * sp);
+  const D chi = path_chi<D>(fabs(ISp - ISm), fmax(ISm, ISp), fmin(ISm, ISp), k);
+  const R eta = R(GENO_ETA);
+  R s, th0, th1;
+  bool low = false;
   if (chi == 1.0) {
     s = sc;
-    th0 = sc - GENO_ETA * d2;
-    th1 = sc + GENO_ETA * d2;
+    th0 = sc - eta * d2;
+    th1 = sc + eta * d2;
   } else {
-    double em = ISm + k.eps, ep = ISp + k.eps;
-    em *= em;
-    ep *= ep;
+    low = true;
+    D em = ISm + k.eps, ep = ISp + k.eps;
+    em = em * em;
+    ep = ep * ep;
     // weights 1/(IS_-+eps)^2 and 1/(IS_++eps)^2 over a common denominator
-    const double sL = (ep * sm + em * sp) / (ep + em);
-    s = chi * sc + (1.0 - chi) * sL;
-    th0 = chi * (sc - GENO_ETA * d2) + (1.0 - chi) * sL;
-    th1 = chi * (sc + GENO_ETA * d2) + (1.0 - chi) * sL;
+    const D inv = 1.0 / (ep + em);
+    const R wm = R(ep * inv), wp = R(em * inv);
+    const R sL = wm * sm + wp * sp;
+    const R x = R(chi), xm = R(1.0 - chi);
+    s = x * sc + xm * sL;
+    th0 = x * (sc - eta * d2) + xm * sL;
+    th1 = x * (sc + eta * d2) + xm * sL;
   }
-  v0 = ph0 - GENO_ETA * s;
-  v1 = ph0 + GENO_ETA * s;
+  v0 = ph0 - eta * s;
+  v1 = ph0 + eta * s;
   t0 = th0;
   t1 = th1;
+  return low;
+}
+
+// Point state admissible for the flux: finite, rho > 0, p > 0.
+template <int NV, typename R>
+GENO_HD bool admissible(const R* W, double gamma) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    if (!isfinite(W[v])) return false;
+  if (!(W[0] > R(0.0))) return false;
+  R ke = W[1] * W[1];
+  if constexpr (NV == 4) ke = ke + W[2] * W[2];
+  const R p = R(gamma - 1.0) * (W[NV - 1] - R(0.5) * ke / W[0]);
+  return p > R(0.0);
 }
 
 }  // namespace geno

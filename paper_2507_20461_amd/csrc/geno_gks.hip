@@ -1,22 +1,26 @@
 // HIP kernels and C ABI of the compact gas-kinetic scheme with GENO
 // reconstruction for gfx950 (declarations and conventions: geno_gks.h).
 //
-// One S2O4 stage on a 2-D grid is seven launches on the caller's stream:
-//   ghost_x, ghost_y   ghost layers of the stage state (periodic/transmissive)
-//   normal<x>          GENO along x on every x-face of rows -1..ny -> face-row buffer
-//   faces<x>           tangential step, positivity guard and the gas-kinetic
-//                      flux at both Gauss points of every x-face -> F, dF/dt, W(dt/2)
-//   normal<y>, faces<y>  the same for y-faces
-//   update<stage>      Eq. (1) and the S2O4 stage, gradients by Eq. (2), and
-//                      (stage 2) the CFL minimum for the next step
-// The time step lives on the device (two ping-pong slots holding the bit
-// pattern of min(dx/(|U|+c), dy/(|V|+c))), so a run of steps never waits
-// for the host.
+// One S2O4 stage on a 2-D grid, per direction d in {x, y}:
+//   normal<d>   GENO along d on every face-row the tangential step reads
+//               -> face-row buffer (value and h*d/dn per side and variable)
+//   faces<d>    two lanes per face, one per Gauss point: tangential step,
+//               positivity guard and the gas-kinetic flux for tau = 0; faces
+//               with tau > 0 at either point go to a queue
+//   slow<d>     the queued faces with the full BGK solution (tau > 0)
+// then update<stage>: Eq. (1) with the S2O4 stage, the gradients by Eq. (2),
+// the ghost cells of the new state (every interior cell writes its ghost
+// images) and, in stage 2, per-block CFL minima for the next step, reduced
+// by the next step's first kernel. The time step therefore never leaves the
+// device and a run of steps never waits for the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "geno_device.hpp"
@@ -27,6 +31,7 @@ namespace {
 
 constexpr int NG = 2;
 constexpr int BLOCK = 256;
+constexpr int SLOW_BLOCKS = 1024;   // fixed grid of the queue kernels (grid-stride)
 
 thread_local char g_err[512] = "";
 
@@ -38,9 +43,9 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
     if (e_ != hipSuccess) return fail(GENO_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
@@ -54,9 +59,11 @@ struct Timing {
   int cap = 0, used = 0;
 };
 Timing g_tim;
+int g_count = 0;   // work counting in gks_step (geno_count_enable)
 
-const char* const KNAMES[GENO_NKERNELS] = {"ghost_x", "ghost_y", "normal_x", "normal_y", "faces_x",
-                                           "faces_y", "update_1", "update_2", "dt_init", "faces_1d"};
+const char* const KNAMES[GENO_NKERNELS] = {"init",   "normal_x", "normal_y", "faces_x",
+                                           "faces_y", "slow_x",  "slow_y",   "update_1",
+                                           "update_2", "faces_1d"};
 
 inline void tim_begin(int kind, hipStream_t s) {
   if (g_tim.used < g_tim.cap) {
@@ -78,85 +85,152 @@ struct Geo {
   double dx, dy;
 };
 
-__device__ __forceinline__ size_t at(const Geo& g, int f, int j, int i) {
+__host__ __device__ __forceinline__ size_t at(const Geo& g, int f, int j, int i) {
   return ((size_t)f * g.rows + (j + g.yoff)) * g.pitch + (i + NG);
 }
 
-// control block at the start of the workspace
+// Control block at the start of the workspace.
 struct Ctrl {
-  unsigned long long tmin[2];   // CFL minimum per step slot (bit pattern of a positive double)
-  unsigned long long guard;     // positivity fall-backs
-  unsigned long long nonfinite; // non-finite cells after a stage-2 update
+  unsigned long long tmin;                         // CFL minimum of the current step (bits of a double)
+  unsigned long long guard;                        // positivity fall-backs
+  unsigned long long nonfinite;                    // non-finite cells after a stage-2 update
+  unsigned int qcount[2];                          // queued tau > 0 faces per direction
+  unsigned long long work[GENO_NKERNELS][GENO_NCLASS];
 };
 
-__device__ __forceinline__ double dt_of(const Ctrl* c, int slot, double cfl, double dt_fixed) {
-  return c ? cfl * __longlong_as_double((long long)c->tmin[slot]) : dt_fixed;
+__device__ __forceinline__ double dt_of(const Ctrl* c, double cfl) {
+  return cfl * __longlong_as_double((long long)c->tmin);
 }
 
-template <int NV>
-__device__ __forceinline__ bool admissible(const double* W, double gamma) {
+// wave-level sum of a per-lane count, one atomic per wave
+__device__ __forceinline__ void wave_count(unsigned long long* dst, unsigned int x) {
+  unsigned int s = x;
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
-    if (!isfinite(W[v])) return false;
-  if (!(W[0] > 0.0)) return false;
-  double ke = W[1] * W[1];
-  if constexpr (NV == 4) ke += W[2] * W[2];
-  const double p = (gamma - 1.0) * (W[NV - 1] - 0.5 * ke / W[0]);
-  return p > 0.0;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
 }
 
 // ---------------------------------------------------------------------------
 // Ghost cells. Periodic: copy of the periodic image (values and gradients).
-// Transmissive: nearest interior cell, gradient normal to the boundary = 0.
-// x-ghosts of the interior rows first, then y-ghosts of every column.
+// Transmissive: nearest interior cell, gradient normal to that boundary = 0.
+// A corner takes both rules (the same as filling x-ghosts of the interior rows
+// and then y-ghosts of every column). Every interior cell writes the ghost
+// cells whose source it is.
 // ---------------------------------------------------------------------------
-__global__ void k_ghost_x(Geo g, double* __restrict__ W, double* __restrict__ dW, int ndim,
-                          Ctrl* ctrl, int step_slot, double cfl, double* dt_out, int step) {
-  const int nf = g.nv * (1 + ndim);
-  const int total = g.ny * 4 * nf;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ctrl && t == 0) {
-    // start of a step: record dt and clear the other slot for the next minimum
-    if (dt_out) dt_out[step] = cfl * __longlong_as_double((long long)ctrl->tmin[step_slot]);
-    ctrl->tmin[step_slot ^ 1] = 0x7ff0000000000000ull;   // +inf
+__device__ __forceinline__ int ghost_src(int gi, int n, bool per) {
+  if (gi < 0) return per ? gi + n : 0;
+  return per ? gi - n : n - 1;
+}
+
+template <int NDIM, typename T>
+__device__ __forceinline__ void scatter_ghosts(const Geo& g, double* __restrict__ W,
+                                               T* __restrict__ dW, int j, int i, const double* w,
+                                               const T* dw) {
+  constexpr int NV = NDIM == 2 ? 4 : 3;
+  const bool px = g.bc[0] == GENO_BC_PERIODIC;
+  const bool py = NDIM == 2 && g.bc[2] == GENO_BC_PERIODIC;
+  // ghost columns / rows whose source is this cell, as bit masks
+  const int cx[4] = {-2, -1, g.nx, g.nx + 1};
+  const int cy[4] = {-2, -1, g.ny, g.ny + 1};
+  unsigned mx = 0, my = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (ghost_src(cx[q], g.nx, px) == i) mx |= 1u << q;
+    if (NDIM == 2 && ghost_src(cy[q], g.ny, py) == j) my |= 1u << q;
   }
-  if (t >= total) return;
-  const int f = t % nf;
-  const int q = (t / nf) % 4;
-  const int j = t / (nf * 4);
-  const int i = (q == 0) ? -2 : (q == 1) ? -1 : (q == 2) ? g.nx : g.nx + 1;
-  const bool lo = q < 2;
-  const bool per = g.bc[lo ? 0 : 1] == GENO_BC_PERIODIC;
-  const int src = per ? (lo ? i + g.nx : i - g.nx) : (lo ? 0 : g.nx - 1);
-  if (f < g.nv) {
-    W[at(g, f, j, i)] = W[at(g, f, j, src)];
-  } else {
-    const int fd = f - g.nv;
-    const bool normal = (fd / g.nv) == 0;
-    dW[at(g, fd, j, i)] = (!per && normal) ? 0.0 : dW[at(g, fd, j, src)];
+  if (!mx && !my) return;
+  // index 4 stands for the cell's own row / column
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    if (a < 4 && !((my >> a) & 1u)) continue;
+    const int jj = a == 4 ? j : cy[a];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      if ((b < 4 && !((mx >> b) & 1u)) || (a == 4 && b == 4)) continue;
+      const int ii = b == 4 ? i : cx[b];
+      const bool zx = b < 4 && !px;   // zero d/dx at transmissive x-ghosts
+      const bool zy = a < 4 && !py;   // zero d/dy at transmissive y-ghosts
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        W[at(g, v, jj, ii)] = w[v];
+        dW[at(g, v, jj, ii)] = zx ? T(0) : dw[v];
+        if constexpr (NDIM == 2) dW[at(g, NV + v, jj, ii)] = zy ? T(0) : dw[NV + v];
+      }
+    }
   }
 }
 
-__global__ void k_ghost_y(Geo g, double* __restrict__ W, double* __restrict__ dW) {
-  const int nf = g.nv * 3;
-  const int ncol = g.nx + 4;
-  const int total = ncol * 4 * nf;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int f = t % nf;
-  const int q = (t / nf) % 4;
-  const int i = t / (nf * 4) - 2;
-  const int j = (q == 0) ? -2 : (q == 1) ? -1 : (q == 2) ? g.ny : g.ny + 1;
-  const bool lo = q < 2;
-  const bool per = g.bc[lo ? 2 : 3] == GENO_BC_PERIODIC;
-  const int src = per ? (lo ? j + g.ny : j - g.ny) : (lo ? 0 : g.ny - 1);
-  if (f < g.nv) {
-    W[at(g, f, j, i)] = W[at(g, f, src, i)];
-  } else {
-    const int fd = f - g.nv;
-    const bool normal = (fd / g.nv) == 1;
-    dW[at(g, fd, j, i)] = (!per && normal) ? 0.0 : dW[at(g, fd, src, i)];
+// CFL bound of one cell: min(dx/(|U|+c), dy/(|V|+c)).
+template <int NDIM>
+__device__ __forceinline__ double cell_tmin(const Geo& g, const double* w, double gamma) {
+  constexpr int NV = NDIM == 2 ? 4 : 3;
+  const double rho = w[0], U = w[1] / rho;
+  const double V = NV == 4 ? w[2] / rho : 0.0;
+  const double p = (gamma - 1.0) * (w[NV - 1] - 0.5 * rho * (U * U + V * V));
+  const double c = sqrt(gamma * p / rho);
+  double t = g.dx / (fabs(U) + c);
+  if constexpr (NDIM == 2) t = fmin(t, g.dy / (fabs(V) + c));
+  return (t > 0.0) ? t : 0.0;   // a NaN state gives a zero step (flagged by the caller)
+}
+
+// block minimum of t into part[blockIdx.x]
+__device__ __forceinline__ void block_min(double t, double* part) {
+  __shared__ double red[BLOCK / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t = fmin(t, __shfl_xor(t, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < BLOCK / 64; ++w) m = fmin(m, red[w]);
+    part[blockIdx.x] = m;
   }
+}
+
+// minimum of the npart partials into ctrl->tmin (one block); records dt
+__device__ __forceinline__ void reduce_dt(const double* part, int npart, Ctrl* ctrl, double cfl,
+                                          double* dt_out, int step) {
+  __shared__ double red[BLOCK / 64];
+  double m = INFINITY;
+  for (int q = threadIdx.x; q < npart; q += blockDim.x) m = fmin(m, part[q]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = red[0];
+    for (int w = 1; w < BLOCK / 64; ++w) m = fmin(m, red[w]);
+    ctrl->tmin = (unsigned long long)__double_as_longlong(m);
+    if (dt_out) dt_out[step] = cfl * m;
+  }
+}
+
+// Start of gks_step: ghost cells of the initial state, per-block CFL minima,
+// cleared counters.
+template <int NDIM>
+__global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __restrict__ W,
+                                                double* __restrict__ dW, double* __restrict__ part,
+                                                Ctrl* ctrl) {
+  constexpr int NV = NDIM == 2 ? 4 : 3;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) {
+    unsigned long long* z = &ctrl->guard;
+    const int nz = (int)((sizeof(Ctrl) - offsetof(Ctrl, guard)) / sizeof(unsigned long long));
+    for (int q = threadIdx.x; q < nz; q += blockDim.x) z[q] = 0;
+  }
+  double tl = INFINITY;
+  if (t < g.nx * g.ny) {
+    const int j = t / g.nx, i = t % g.nx;
+    double w[NV], dw[NV * NDIM];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = W[at(g, v, j, i)];
+#pragma unroll
+    for (int v = 0; v < NV * NDIM; ++v) dw[v] = dW[at(g, v, j, i)];
+    scatter_ghosts<NDIM, double>(g, W, dW, j, i, w, dw);
+    tl = cell_tmin<NDIM>(g, w, gamma);
+  }
+  block_min(tl, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,158 +238,339 @@ __global__ void k_ghost_y(Geo g, double* __restrict__ W, double* __restrict__ dW
 // b = 0..nx (between cells b-1 and b). DIR 1: faces a = 0..ny (between rows
 // a-1 and a), columns b = 0..nx+1 (i = b-1).
 // fr: [side][quant(value, h d/dn)][var][a][b]; chi: [side][var][a][b].
+// With part (first kernel of a step), block 0 also reduces the CFL partial
+// minima of the previous kernel into ctrl->tmin and records dt.
 // ---------------------------------------------------------------------------
 template <int DIR>
 __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                                                     const double* __restrict__ W,
                                                     const double* __restrict__ dW,
                                                     double* __restrict__ fr,
-                                                    double* __restrict__ chi) {
+                                                    double* __restrict__ chi, Ctrl* ctrl,
+                                                    const double* __restrict__ part, int npart,
+                                                    double* dt_out, int step, int count) {
+  if (part && blockIdx.x == 0) reduce_dt(part, npart, ctrl, k.cfl, dt_out, step);
+  if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) ctrl->qcount[DIR] = 0;
   const int n1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
   const int n0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n0 * n1) return;
-  const int a = t / n1, b = t % n1;
-  const size_t plane = (size_t)n0 * n1;
-  const size_t o = (size_t)a * n1 + b;
-  const double h = DIR == 0 ? g.dx : g.dy;
+  unsigned int nlow = 0;
+  if (t < n0 * n1) {
+    const int a = t / n1, b = t % n1;
+    const size_t plane = (size_t)n0 * n1;
+    const size_t o = (size_t)a * n1 + b;
+    const double h = DIR == 0 ? g.dx : g.dy;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    double Q[4], G[4];
+    for (int v = 0; v < 4; ++v) {
+      double Q[4], G[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      size_t id;
-      if (DIR == 0) id = at(g, v, a - 1, b - 2 + m);
-      else id = at(g, v, a - 2 + m, b - 1);
-      Q[m] = W[id];
-      G[m] = h * dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+      for (int m = 0; m < 4; ++m) {
+        size_t id;
+        if (DIR == 0) id = at(g, v, a - 1, b - 2 + m);
+        else id = at(g, v, a - 2 + m, b - 1);
+        Q[m] = W[id];
+        G[m] = h * dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+      }
+      double vl, dl, xl, vr, dr, xr;
+      nlow += geno::geno_face<double, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
+                                              vl, dl, xl, vr, dr, xr);
+      fr[(size_t)(0 * 4 + v) * plane + o] = vl;
+      fr[(size_t)(1 * 4 + v) * plane + o] = dl;
+      fr[(size_t)(2 * 4 + v) * plane + o] = vr;
+      fr[(size_t)(3 * 4 + v) * plane + o] = dr;
+      if (chi) {
+        chi[(size_t)(0 * 4 + v) * plane + o] = xl;
+        chi[(size_t)(1 * 4 + v) * plane + o] = xr;
+      }
     }
-    double vl, dl, xl, vr, dr, xr;
-    geno::geno_face(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl, xl, vr, dr, xr);
-    fr[(size_t)(0 * 4 + v) * plane + o] = vl;
-    fr[(size_t)(1 * 4 + v) * plane + o] = dl;
-    fr[(size_t)(2 * 4 + v) * plane + o] = vr;
-    fr[(size_t)(3 * 4 + v) * plane + o] = dr;
-    if (chi) {
-      chi[(size_t)(0 * 4 + v) * plane + o] = xl;
-      chi[(size_t)(1 * 4 + v) * plane + o] = xr;
-    }
+  }
+  if (count) {
+    const int kind = DIR == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y;
+    wave_count(&ctrl->work[kind][GENO_W_UNITS], t < n0 * n1 ? 1u : 0u);
+    wave_count(&ctrl->work[kind][GENO_W_LOW], nlow);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Faces (2-D): tangential step, positivity guard, then either the point
-// states (MODE 0, geno_reconstruct) or the Gauss-averaged flux (MODE 1).
-// DIR 0: a = row t (0..ny-1), b = face (0..nx); DIR 1: a = face (0..ny),
-// b = column t (0..nx-1).
+// Faces (2-D), two lanes per face: lane q owns Gauss point q and computes the
+// tangential step of side q for both points; the halves are exchanged with
+// the partner lane. DIR 0: face (a = row t, b = face 0..nx); DIR 1: face
+// (a = face 0..ny, b = column t).
+// MODE 0: write the point states (geno_reconstruct).
+// MODE 1: flux for tau = 0; faces with tau > 0 at either point are queued.
+// MODE 2: flux of the queued faces with the full solution (grid-stride).
 // ---------------------------------------------------------------------------
+template <int DIR>
+struct FaceGeo {
+  int n0, n1, r0, r1;
+  __device__ explicit FaceGeo(const Geo& g) {
+    n1 = DIR == 0 ? g.nx + 1 : g.nx;
+    n0 = DIR == 0 ? g.ny : g.ny + 1;
+    r1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
+    r0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
+  }
+};
+
+template <int DIR, int MODE>
+__device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
+                                          const double* __restrict__ W,
+                                          const double* __restrict__ fr, double* __restrict__ out,
+                                          Ctrl* ctrl, int want_F, int count, int face, bool valid,
+                                          unsigned int* __restrict__ queue) {
+  const FaceGeo<DIR> fg(g);
+  const int q = threadIdx.x & 1;
+  const int nfaces = fg.n0 * fg.n1;
+  const int fc = valid ? face : nfaces - 1;
+  const int a = fc / fg.n1, b = fc % fg.n1;
+  const size_t rplane = (size_t)fg.r0 * fg.r1;
+  const size_t rm = (size_t)a * fg.r1 + b;
+  const size_t rc = DIR == 0 ? rm + fg.r1 : rm + 1;
+  const size_t rp = DIR == 0 ? rc + fg.r1 : rc + 1;
+  // tangential step of side q for both points
+  double own_v[4], own_t[4], snd_v[4], snd_t[4], dn[4];
+  unsigned int nlow = 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double* p = fr + (size_t)((2 * q + 0) * 4 + v) * rplane;
+    double v0, v1, t0, t1;
+    nlow += geno::tangential<double, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1);
+    own_v[v] = q ? v1 : v0;
+    own_t[v] = q ? t1 : t0;
+    snd_v[v] = q ? v0 : v1;
+    snd_t[v] = q ? t0 : t1;
+    dn[v] = fr[(size_t)((2 * q + 1) * 4 + v) * rplane + rc];
+  }
+  // states of both sides at this lane's point
+  double S[2][4], Dn[2][4], Dt[2][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double rv = __shfl_xor(snd_v[v], 1, 64);
+    const double rt = __shfl_xor(snd_t[v], 1, 64);
+    const double rd = __shfl_xor(dn[v], 1, 64);
+    S[0][v] = q ? rv : own_v[v];
+    S[1][v] = q ? own_v[v] : rv;
+    Dt[0][v] = q ? rt : own_t[v];
+    Dt[1][v] = q ? own_t[v] : rt;
+    Dn[0][v] = q ? rd : dn[v];
+    Dn[1][v] = q ? dn[v] : rd;
+  }
+  // positivity guard per side: fall back to the own cell average
+  unsigned int nguard = 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (!geno::admissible<4, double>(S[s], k.gamma)) {
+      ++nguard;
+      const int ci = DIR == 0 ? b - 1 + s : b;
+      const int cj = DIR == 0 ? a : a - 1 + s;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        S[s][v] = W[at(g, v, cj, ci)];
+        Dn[s][v] = 0.0;
+        Dt[s][v] = 0.0;
+      }
+    }
+  }
+  if (!valid) nguard = nlow = 0;
+  const size_t plane = (size_t)nfaces;
+  const size_t o = (size_t)fc;
+  if constexpr (MODE == 0) {
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const size_t base = (size_t)(((s * 2 + q) * 3) * 4);
+          out[(base + 0 * 4 + v) * plane + o] = S[s][v];
+          out[(base + 1 * 4 + v) * plane + o] = Dn[s][v];
+          out[(base + 2 * 4 + v) * plane + o] = Dt[s][v];
+        }
+    }
+  } else {
+    const double dt = dt_of(ctrl, k.cfl);
+    const double hn = DIR == 0 ? g.dx : g.dy, ht = DIR == 0 ? g.dy : g.dx;
+    const double ihn = 1.0 / hn, iht = 1.0 / ht;
+    constexpr int p1 = DIR == 0 ? 1 : 2, p2 = DIR == 0 ? 2 : 1;
+    constexpr int perm[4] = {0, p1, p2, 3};
+    double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wl[v] = S[0][perm[v]];
+      Wr[v] = S[1][perm[v]];
+      nl[v] = Dn[0][perm[v]] * ihn;
+      nr[v] = Dn[1][perm[v]] * ihn;
+      tl[v] = Dt[0][perm[v]] * iht;
+      tr[v] = Dt[1][perm[v]] * iht;
+    }
+    double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
+    bool slow;   // MODE 1: tau > 0, not evaluated; MODE 2: evaluated, tau > 0
+    if constexpr (MODE == 1)
+      slow = gks::point_flux<4, false, double>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5, want_F != 0,
+                                               F, Ft, Wi);
+    else
+      slow = gks::point_flux<4, true, double>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5, want_F != 0,
+                                              F, Ft, Wi);
+    bool pair_slow = false;
+    if constexpr (MODE == 1) {
+      // every lane takes part in the exchange (no short-circuit around it:
+      // a lane that skips a cross-lane read leaves its partner reading an
+      // inactive lane)
+      const int partner_slow = __shfl_xor(slow ? 1 : 0, 1, 64);
+      pair_slow = slow || partner_slow != 0;
+      // queue the faces that need the full solution (one atomic per wave)
+      const bool enq = valid && q == 0 && pair_slow;
+      const unsigned long long m = __ballot(enq);
+      unsigned int base = 0;
+      if ((threadIdx.x & 63) == 0 && m)
+        base = atomicAdd(&ctrl->qcount[DIR], (unsigned int)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (enq) {
+        const unsigned int rank = (unsigned int)__popcll(m & ((1ull << (threadIdx.x & 63)) - 1));
+        queue[base + rank] = (unsigned int)face;
+      }
+    }
+    if (nguard && (MODE == 2 || !pair_slow)) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
+    // Gauss average: add the partner's half
+    double So[12];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      So[v] = F[v] + __shfl_xor(F[v], 1, 64);
+      So[4 + v] = Ft[v] + __shfl_xor(Ft[v], 1, 64);
+      So[8 + v] = Wi[v] + __shfl_xor(Wi[v], 1, 64);
+    }
+    if (valid && !pair_slow) {
+      // back to the (x, y) frame; lane 0 writes F and Ft, lane 1 writes W_int
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pv = perm[v];
+        if (q == 0) {
+          if (want_F) out[(size_t)(0 * 4 + pv) * plane + o] = So[v];
+          out[(size_t)(1 * 4 + pv) * plane + o] = So[4 + v];
+        } else {
+          out[(size_t)(2 * 4 + pv) * plane + o] = So[8 + v];
+        }
+      }
+    }
+    if (count) {
+      const int kind = MODE == 1 ? (DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y)
+                                 : (DIR == 0 ? GENO_K_SLOW_X : GENO_K_SLOW_Y);
+      const bool ev = valid && !pair_slow;   // this lane's point was evaluated here
+      wave_count(&ctrl->work[kind][GENO_W_UNITS], (ev && q == 0) ? 1u : 0u);
+      wave_count(&ctrl->work[kind][GENO_W_FAST], (ev && !slow) ? 1u : 0u);
+      wave_count(&ctrl->work[kind][GENO_W_SLOW], (ev && slow) ? 1u : 0u);
+      wave_count(&ctrl->work[kind][GENO_W_LOW], ev ? nlow : 0u);
+      wave_count(&ctrl->work[kind][GENO_W_GUARD], ev ? nguard : 0u);
+    }
+  }
+}
+
+// One thread per queued face (tau > 0 at one of its points): tangential
+// step of both sides, guard, and the full solution at both Gauss points. No
+// cross-lane exchange, so register spills of this heavy path stay local.
+template <int DIR>
+__device__ __forceinline__ void face_full(const Geo& g, const geno::KParams& k,
+                                          const double* __restrict__ W,
+                                          const double* __restrict__ fr, double* __restrict__ out,
+                                          Ctrl* ctrl, int want_F, int count, int face) {
+  const FaceGeo<DIR> fg(g);
+  const int a = face / fg.n1, b = face % fg.n1;
+  const size_t rplane = (size_t)fg.r0 * fg.r1;
+  const size_t rm = (size_t)a * fg.r1 + b;
+  const size_t rc = DIR == 0 ? rm + fg.r1 : rm + 1;
+  const size_t rp = DIR == 0 ? rc + fg.r1 : rc + 1;
+  const double dt = dt_of(ctrl, k.cfl);
+  const double hn = DIR == 0 ? g.dx : g.dy, ht = DIR == 0 ? g.dy : g.dx;
+  const double ihn = 1.0 / hn, iht = 1.0 / ht;
+  constexpr int p1 = DIR == 0 ? 1 : 2, p2 = DIR == 0 ? 2 : 1;
+  constexpr int perm[4] = {0, p1, p2, 3};
+  double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
+  unsigned int nlow = 0, nguard = 0, nfast = 0, nslow = 0;
+#pragma unroll 1
+  for (int q = 0; q < 2; ++q) {
+    double S[2][4], Dn[2][4], Dt[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double* p = fr + (size_t)((2 * s + 0) * 4 + v) * rplane;
+        double v0, v1, t0, t1;
+        nlow += geno::tangential<double, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1);
+        S[s][v] = q ? v1 : v0;
+        Dt[s][v] = q ? t1 : t0;
+        Dn[s][v] = fr[(size_t)((2 * s + 1) * 4 + v) * rplane + rc];
+      }
+      if (!geno::admissible<4, double>(S[s], k.gamma)) {
+        ++nguard;
+        const int ci = DIR == 0 ? b - 1 + s : b;
+        const int cj = DIR == 0 ? a : a - 1 + s;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          S[s][v] = W[at(g, v, cj, ci)];
+          Dn[s][v] = 0.0;
+          Dt[s][v] = 0.0;
+        }
+      }
+    }
+    double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wl[v] = S[0][perm[v]];
+      Wr[v] = S[1][perm[v]];
+      nl[v] = Dn[0][perm[v]] * ihn;
+      nr[v] = Dn[1][perm[v]] * ihn;
+      tl[v] = Dt[0][perm[v]] * iht;
+      tr[v] = Dt[1][perm[v]] * iht;
+    }
+    double Fq[4] = {0, 0, 0, 0}, Ftq[4] = {0, 0, 0, 0}, Wiq[4] = {0, 0, 0, 0};
+    const bool sl = gks::point_flux<4, true, double>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5,
+                                                     want_F != 0, Fq, Ftq, Wiq);
+    nslow += sl ? 1u : 0u;
+    nfast += sl ? 0u : 1u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      F[v] += Fq[v];
+      Ft[v] += Ftq[v];
+      Wi[v] += Wiq[v];
+    }
+  }
+  if (nguard) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
+  const size_t plane = (size_t)fg.n0 * fg.n1;
+  const size_t o = (size_t)face;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int pv = perm[v];
+    if (want_F) out[(size_t)(0 * 4 + pv) * plane + o] = F[v];
+    out[(size_t)(1 * 4 + pv) * plane + o] = Ft[v];
+    out[(size_t)(2 * 4 + pv) * plane + o] = Wi[v];
+  }
+  if (count) {
+    const int kind = DIR == 0 ? GENO_K_SLOW_X : GENO_K_SLOW_Y;
+    atomicAdd(&ctrl->work[kind][GENO_W_UNITS], 1ull);
+    atomicAdd(&ctrl->work[kind][GENO_W_FAST], (unsigned long long)nfast);
+    atomicAdd(&ctrl->work[kind][GENO_W_SLOW], (unsigned long long)nslow);
+    atomicAdd(&ctrl->work[kind][GENO_W_LOW], (unsigned long long)nlow);
+    if (nguard) atomicAdd(&ctrl->work[kind][GENO_W_GUARD], (unsigned long long)nguard);
+  }
+}
+
 template <int DIR, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
                                                    const double* __restrict__ W,
                                                    const double* __restrict__ fr,
                                                    double* __restrict__ out, Ctrl* ctrl,
-                                                   int slot, double dt_fixed, int want_F) {
-  const int n1 = DIR == 0 ? g.nx + 1 : g.nx;
-  const int n0 = DIR == 0 ? g.ny : g.ny + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n0 * n1) return;
-  const int a = t / n1, b = t % n1;
-  // face-row buffer geometry
-  const int r1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
-  const int r0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
-  const size_t rplane = (size_t)r0 * r1;
-  // rows t-1, t, t+1 of this face in the face-row buffer
-  size_t rm, rc, rp;
-  if (DIR == 0) {
-    rm = (size_t)a * r1 + b;
-    rc = rm + r1;
-    rp = rc + r1;
+                                                   int want_F, int count,
+                                                   unsigned int* __restrict__ queue) {
+  const FaceGeo<DIR> fg(g);
+  const int nfaces = fg.n0 * fg.n1;
+  if constexpr (MODE == 2) {
+    // grid-stride over the queue, one thread per face
+    const unsigned int nq = ctrl->qcount[DIR];
+    const unsigned int stride = gridDim.x * blockDim.x;
+    for (unsigned int e = blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += stride)
+      face_full<DIR>(g, k, W, fr, out, ctrl, want_F, count, (int)queue[e]);
   } else {
-    rm = (size_t)a * r1 + b;
-    rc = rm + 1;
-    rp = rc + 1;
-  }
-  // S[side][gauss][var], Dn[side][var], Dt[side][gauss][var] (h-scaled)
-  double S[2][2][4], Dn[2][4], Dt[2][2][4];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double* p = fr + (size_t)((2 * s + 0) * 4 + v) * rplane;
-      geno::tangential(p[rm], p[rc], p[rp], k, S[s][0][v], S[s][1][v], Dt[s][0][v], Dt[s][1][v]);
-      Dn[s][v] = fr[(size_t)((2 * s + 1) * 4 + v) * rplane + rc];
-    }
-  }
-  // positivity guard per side and point: fall back to the own cell average
-  const double gamma = k.gamma;
-  int nguard = 0;
-  double Dnp[2][2][4];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const bool ok = admissible<4>(S[s][q], gamma);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Dnp[s][q][v] = ok ? Dn[s][v] : 0.0;
-      if (!ok) {
-        ++nguard;
-        int ci, cj;
-        if (DIR == 0) { ci = b - 1 + s; cj = a; }
-        else { ci = b; cj = a - 1 + s; }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          S[s][q][v] = W[at(g, v, cj, ci)];
-          Dt[s][q][v] = 0.0;
-        }
-      }
-    }
-  }
-  if (nguard && ctrl) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
-  const size_t plane = (size_t)n0 * n1;
-  const size_t o = (size_t)a * n1 + b;
-  if constexpr (MODE == 0) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const size_t base = (size_t)(((s * 2 + q) * 3) * 4);
-          out[(base + 0 * 4 + v) * plane + o] = S[s][q][v];
-          out[(base + 1 * 4 + v) * plane + o] = Dnp[s][q][v];
-          out[(base + 2 * 4 + v) * plane + o] = Dt[s][q][v];
-        }
-  } else {
-    const double dt = dt_of(ctrl, slot, k.cfl, dt_fixed);
-    const double hn = DIR == 0 ? g.dx : g.dy, ht = DIR == 0 ? g.dy : g.dx;
-    const double ihn = 1.0 / hn, iht = 1.0 / ht;
-    // face frame: normal momentum first
-    constexpr int p1 = DIR == 0 ? 1 : 2, p2 = DIR == 0 ? 2 : 1;
-    double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
-      const int perm[4] = {0, p1, p2, 3};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Wl[v] = S[0][q][perm[v]];
-        Wr[v] = S[1][q][perm[v]];
-        nl[v] = Dnp[0][q][perm[v]] * ihn;
-        nr[v] = Dnp[1][q][perm[v]] * ihn;
-        tl[v] = Dt[0][q][perm[v]] * iht;
-        tr[v] = Dt[1][q][perm[v]] * iht;
-      }
-      gks::point_flux<4>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5, want_F != 0, F, Ft, Wi);
-    }
-    const double Fo[4] = {F[0], DIR == 0 ? F[1] : F[2], DIR == 0 ? F[2] : F[1], F[3]};
-    const double Fto[4] = {Ft[0], DIR == 0 ? Ft[1] : Ft[2], DIR == 0 ? Ft[2] : Ft[1], Ft[3]};
-    const double Wio[4] = {Wi[0], DIR == 0 ? Wi[1] : Wi[2], DIR == 0 ? Wi[2] : Wi[1], Wi[3]};
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if (want_F) out[(size_t)(0 * 4 + v) * plane + o] = Fo[v];
-      out[(size_t)(1 * 4 + v) * plane + o] = Fto[v];
-      out[(size_t)(2 * 4 + v) * plane + o] = Wio[v];
-    }
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int face = t >> 1;
+    face_pair<DIR, MODE>(g, k, W, fr, out, ctrl, want_F, count, face, face < nfaces, queue);
   }
 }
 
@@ -323,6 +578,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
 // 1-D faces: normal GENO of the three variables at face f (cells f-2..f+1),
 // guard, then states (MODE 0) or flux (MODE 1). out as the 2-D layouts with
 // one Gauss point: states [side][quant(2)][var][f], flux [kind][var][f].
+// The 1-D step is reduced before this kernel (k_dt1d).
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
@@ -330,67 +586,83 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
                                                    const double* __restrict__ dW,
                                                    double* __restrict__ out,
                                                    double* __restrict__ chi, Ctrl* ctrl,
-                                                   int slot, double dt_fixed, int want_F) {
+                                                   int want_F, int count) {
   const int nfc = g.nx + 1;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nfc) return;
-  double S[2][3], Dn[2][3];
+  unsigned int nlow = 0, nguard = 0, nslow = 0;
+  if (f < nfc) {
+    double S[2][3], Dn[2][3];
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    double Q[4], G[4];
+    for (int v = 0; v < 3; ++v) {
+      double Q[4], G[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const size_t id = at(g, v, 0, f - 2 + m);
-      Q[m] = W[id];
-      G[m] = g.dx * dW[id];
+      for (int m = 0; m < 4; ++m) {
+        const size_t id = at(g, v, 0, f - 2 + m);
+        Q[m] = W[id];
+        G[m] = g.dx * dW[id];
+      }
+      double xl, xr;
+      nlow += geno::geno_face<double, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
+                                              S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr);
+      if (chi) {
+        chi[(size_t)(0 * 3 + v) * nfc + f] = xl;
+        chi[(size_t)(1 * 3 + v) * nfc + f] = xr;
+      }
     }
-    double xl, xr;
-    geno::geno_face(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, S[0][v], Dn[0][v], xl,
-                    S[1][v], Dn[1][v], xr);
-    if (chi) {
-      chi[(size_t)(0 * 3 + v) * nfc + f] = xl;
-      chi[(size_t)(1 * 3 + v) * nfc + f] = xr;
-    }
-  }
-  int nguard = 0;
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    if (!admissible<3>(S[s], k.gamma)) {
-      ++nguard;
+    for (int s = 0; s < 2; ++s) {
+      if (!geno::admissible<3, double>(S[s], k.gamma)) {
+        ++nguard;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          S[s][v] = W[at(g, v, 0, f - 1 + s)];
+          Dn[s][v] = 0.0;
+        }
+      }
+    }
+    if (nguard && ctrl) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          out[(size_t)((s * 2 + 0) * 3 + v) * nfc + f] = S[s][v];
+          out[(size_t)((s * 2 + 1) * 3 + v) * nfc + f] = Dn[s][v];
+        }
+    } else {
+      const double dt = dt_of(ctrl, k.cfl);
+      const double ih = 1.0 / g.dx;
+      double nl[3], nr[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        S[s][v] = W[at(g, v, 0, f - 1 + s)];
-        Dn[s][v] = 0.0;
+        nl[v] = Dn[0][v] * ih;
+        nr[v] = Dn[1][v] * ih;
+      }
+      double F[3] = {0, 0, 0}, Ft[3] = {0, 0, 0}, Wi[3] = {0, 0, 0};
+      const bool sl = gks::point_flux<3, true, double>(S[0], S[1], nl, nr, nullptr, nullptr, dt,
+                                                       k, 1.0, want_F != 0, F, Ft, Wi);
+      nslow = sl ? 1u : 0u;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        if (want_F) out[(size_t)(0 * 3 + v) * nfc + f] = F[v];
+        out[(size_t)(1 * 3 + v) * nfc + f] = Ft[v];
+        out[(size_t)(2 * 3 + v) * nfc + f] = Wi[v];
       }
     }
   }
-  if (nguard && ctrl) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
-  if constexpr (MODE == 0) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        out[(size_t)((s * 2 + 0) * 3 + v) * nfc + f] = S[s][v];
-        out[(size_t)((s * 2 + 1) * 3 + v) * nfc + f] = Dn[s][v];
-      }
-  } else {
-    const double dt = dt_of(ctrl, slot, k.cfl, dt_fixed);
-    const double ih = 1.0 / g.dx;
-    double nl[3], nr[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      nl[v] = Dn[0][v] * ih;
-      nr[v] = Dn[1][v] * ih;
-    }
-    double F[3] = {0, 0, 0}, Ft[3] = {0, 0, 0}, Wi[3] = {0, 0, 0};
-    gks::point_flux<3>(S[0], S[1], nl, nr, nullptr, nullptr, dt, k, 1.0, want_F != 0, F, Ft, Wi);
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      if (want_F) out[(size_t)(0 * 3 + v) * nfc + f] = F[v];
-      out[(size_t)(1 * 3 + v) * nfc + f] = Ft[v];
-      out[(size_t)(2 * 3 + v) * nfc + f] = Wi[v];
-    }
+  if (count && MODE == 1) {
+    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_UNITS], f < nfc ? 1u : 0u);
+    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_LOW], nlow);
+    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_FAST], (f < nfc && !nslow) ? 1u : 0u);
+    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_SLOW], nslow);
+    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_GUARD], nguard);
   }
+}
+
+// 1-D: reduce the CFL partials of the previous kernel (single block).
+__global__ void __launch_bounds__(BLOCK) k_dt1d(const double* __restrict__ part, int npart,
+                                                Ctrl* ctrl, double cfl, double* dt_out, int step) {
+  reduce_dt(part, npart, ctrl, cfl, dt_out, step);
 }
 
 // gks_flux on caller-given point states (layout of geno_reconstruct).
@@ -421,7 +693,8 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
         ns[s][v] = st[(base + 1 * NV + pv) * nfaces + o] / hn;
         ts[s][v] = NV == 4 ? st[(base + 2 * NV + pv) * nfaces + o] / ht : 0.0;
       }
-    gks::point_flux<NV>(Ws[0], Ws[1], ns[0], ns[1], ts[0], ts[1], dt, k, w, true, Fa, Fta, Wia);
+    gks::point_flux<NV, true, double>(Ws[0], Ws[1], ns[0], ns[1], ts[0], ts[1], dt, k, w, true,
+                                      Fa, Fta, Wia);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -435,12 +708,9 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
 // ---------------------------------------------------------------------------
 // Cell update. STAGE 1: W* = W + dt/2 L + dt^2/8 Lt, R = W + dt L + dt^2/6 Lt,
 // grad* from W_int (Eq. (2)). STAGE 2: W = R + dt^2/3 Lt*, grad from the
-// stage-2 W_int, and the CFL minimum of the new state into the next slot.
+// stage-2 W_int, and the CFL minima of the new state per block. Both write
+// the ghost cells of the state they produce.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void atomic_min_pos(unsigned long long* p, double x) {
-  atomicMin(p, (unsigned long long)__double_as_longlong(x));
-}
-
 template <int NDIM, int STAGE>
 __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
                                                   const double* __restrict__ Win,
@@ -449,118 +719,86 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
                                                   double* __restrict__ R,
                                                   const double* __restrict__ fx,
                                                   const double* __restrict__ fy, Ctrl* ctrl,
-                                                  int slot) {
+                                                  double* __restrict__ part, int count) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.nx * g.ny;
-  const double dt = dt_of(ctrl, slot, k.cfl, 0.0);
+  const double dt = dt_of(ctrl, k.cfl);
   double tloc = INFINITY;
-  bool bad = false;
   if (t < n) {
     const int j = t / g.nx, i = t % g.nx;
     const size_t px = (size_t)(g.nx + 1) * g.ny;
     const size_t py = (size_t)g.nx * (g.ny + 1);
     const size_t ox = (size_t)j * (g.nx + 1) + i;
     const size_t oy = (size_t)j * g.nx + i;
-    double Wn[NV];
+    double w[NV], dw[NV * NDIM];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double l = -(fx[(0 * NV + v) * px + ox + 1] - fx[(0 * NV + v) * px + ox]) / g.dx;
       double lt = -(fx[(1 * NV + v) * px + ox + 1] - fx[(1 * NV + v) * px + ox]) / g.dx;
-      const double gx = (fx[(2 * NV + v) * px + ox + 1] - fx[(2 * NV + v) * px + ox]) / g.dx;
-      double gy = 0.0;
+      dw[v] = (fx[(2 * NV + v) * px + ox + 1] - fx[(2 * NV + v) * px + ox]) / g.dx;
       if constexpr (NDIM == 2) {
         l += -(fy[(0 * NV + v) * py + oy + g.nx] - fy[(0 * NV + v) * py + oy]) / g.dy;
         lt += -(fy[(1 * NV + v) * py + oy + g.nx] - fy[(1 * NV + v) * py + oy]) / g.dy;
-        gy = (fy[(2 * NV + v) * py + oy + g.nx] - fy[(2 * NV + v) * py + oy]) / g.dy;
+        dw[NV + v] = (fy[(2 * NV + v) * py + oy + g.nx] - fy[(2 * NV + v) * py + oy]) / g.dy;
       }
       const size_t c = at(g, v, j, i);
       if constexpr (STAGE == 1) {
-        const double w = Win[c];
-        Wout[c] = w + 0.5 * dt * l + dt * dt / 8.0 * lt;
-        R[c] = w + dt * l + dt * dt / 6.0 * lt;
+        const double w0 = Win[c];
+        w[v] = w0 + 0.5 * dt * l + dt * dt / 8.0 * lt;
+        R[c] = w0 + dt * l + dt * dt / 6.0 * lt;
       } else {
-        Wn[v] = R[c] + dt * dt / 3.0 * lt;
-        Wout[c] = Wn[v];
+        (void)l;
+        w[v] = R[c] + dt * dt / 3.0 * lt;
       }
-      dWout[at(g, v, j, i)] = gx;
-      if constexpr (NDIM == 2) dWout[at(g, NV + v, j, i)] = gy;
+      Wout[c] = w[v];
     }
+#pragma unroll
+    for (int v = 0; v < NV * NDIM; ++v) dWout[at(g, v, j, i)] = dw[v];
+    scatter_ghosts<NDIM, double>(g, Wout, dWout, j, i, w, dw);
     if constexpr (STAGE == 2) {
+      bool bad = false;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) bad |= !isfinite(Wn[v]);
-      const double rho = Wn[0], U = Wn[1] / rho;
-      const double V = NV == 4 ? Wn[2] / rho : 0.0;
-      const double p = (k.gamma - 1.0) * (Wn[NV - 1] - 0.5 * rho * (U * U + V * V));
-      const double c = sqrt(k.gamma * p / rho);
-      tloc = g.dx / (fabs(U) + c);
-      if constexpr (NDIM == 2) tloc = fmin(tloc, g.dy / (fabs(V) + c));
-      if (!(tloc > 0.0)) tloc = 0.0;   // NaN state: zero step, flagged below
+      for (int v = 0; v < NV; ++v) bad |= !isfinite(w[v]);
+      if (bad) atomicAdd(&ctrl->nonfinite, 1ull);
+      tloc = cell_tmin<NDIM>(g, w, k.gamma);
     }
   }
-  if constexpr (STAGE == 2) {
-    // wavefront minimum, then one atomic per wave
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) tloc = fmin(tloc, __shfl_xor(tloc, off, 64));
-    const unsigned long long nb = __ballot(bad);
-    if ((threadIdx.x & 63) == 0 && ctrl) {
-      if (tloc < INFINITY) atomic_min_pos(&ctrl->tmin[slot ^ 1], tloc);
-      if (nb) atomicAdd(&ctrl->nonfinite, (unsigned long long)__popcll(nb));
-    }
-  }
-}
-
-// CFL minimum of the initial state into slot 0 (one workgroup).
-template <int NDIM>
-__global__ void __launch_bounds__(1024) k_dt_init(Geo g, geno::KParams k,
-                                                  const double* __restrict__ W, Ctrl* ctrl) {
-  constexpr int NV = NDIM == 2 ? 4 : 3;
-  __shared__ double red[16];
-  double tloc = INFINITY;
-  const int n = g.nx * g.ny;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    const int j = t / g.nx, i = t % g.nx;
-    const double rho = W[at(g, 0, j, i)];
-    const double U = W[at(g, 1, j, i)] / rho;
-    const double V = NV == 4 ? W[at(g, 2, j, i)] / rho : 0.0;
-    const double p = (k.gamma - 1.0) * (W[at(g, NV - 1, j, i)] - 0.5 * rho * (U * U + V * V));
-    const double c = sqrt(k.gamma * p / rho);
-    double tt = g.dx / (fabs(U) + c);
-    if constexpr (NDIM == 2) tt = fmin(tt, g.dy / (fabs(V) + c));
-    if (!(tt > 0.0)) tt = 0.0;
-    tloc = fmin(tloc, tt);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) tloc = fmin(tloc, __shfl_xor(tloc, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tloc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmin(m, red[w]);
-    ctrl->tmin[0] = (unsigned long long)__double_as_longlong(m);
-    ctrl->tmin[1] = 0x7ff0000000000000ull;
-    ctrl->guard = 0;
-    ctrl->nonfinite = 0;
-  }
+  if constexpr (STAGE == 2) block_min(tloc, part);
+  if (count)
+    wave_count(&ctrl->work[STAGE == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2][GENO_W_UNITS],
+               t < n ? 1u : 0u);
 }
 
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t ctrl, wst, dwst, r, fr[2], fl[2], total;
+  size_t ctrl, part, queue[2], wst, dwst, r, fr[2], fl[2], total;
   size_t nstate;   // doubles per field plane
+  int npart;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline unsigned nblocks(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
 Layout layout_of(const geno_grid* g) {
   Layout L{};
   const int nv = g->ndim == 2 ? 4 : 3;
   L.nstate = (size_t)g->rows * g->pitch;
+  L.npart = (int)nblocks((size_t)g->nx * g->ny);
   size_t off = 0;
   L.ctrl = off;
   off = align256(off + sizeof(Ctrl));
+  L.part = off;
+  off = align256(off + (size_t)L.npart * sizeof(double));
+  if (g->ndim == 2) {
+    L.queue[0] = off;
+    off = align256(off + (size_t)g->ny * (g->nx + 1) * sizeof(unsigned int));
+    L.queue[1] = off;
+    off = align256(off + (size_t)(g->ny + 1) * g->nx * sizeof(unsigned int));
+  }
   L.wst = off;
   off = align256(off + L.nstate * nv * sizeof(double));
   L.dwst = off;
@@ -577,10 +815,8 @@ Layout layout_of(const geno_grid* g) {
     L.fl[1] = off;
     off = align256(off + (size_t)12 * (g->ny + 1) * g->nx * sizeof(double));
   } else {
-    L.fr[0] = L.fr[1] = 0;
     L.fl[0] = off;
     off = align256(off + (size_t)9 * (g->nx + 1) * sizeof(double));
-    L.fl[1] = 0;
   }
   L.total = off;
   return L;
@@ -620,6 +856,7 @@ int check_grid(const geno_grid* g) {
   if ((g->params.bc[0] == GENO_BC_PERIODIC && g->nx < NG) ||
       (g->ndim == 2 && g->params.bc[2] == GENO_BC_PERIODIC && g->ny < NG))
     return fail(GENO_EINVAL, "periodic axis needs at least %d cells", NG);
+  // 32-bit thread indexing: two lanes per face and 16 face-row planes
   if ((size_t)(g->nx + 4) * (g->ny + 4) * 16 > (size_t)0x7fffffff)
     return fail(GENO_EINVAL, "grid too large for 32-bit thread indexing");
   if (!(g->dx > 0.0) || !(g->dy > 0.0)) return fail(GENO_EINVAL, "bad cell size");
@@ -657,64 +894,91 @@ Geo geo_of(const geno_grid* g) {
   return o;
 }
 
-inline unsigned nblocks(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+struct Bufs {
+  Ctrl* ctrl;
+  double* part;
+  unsigned int* queue[2];
+  double *wst, *dwst, *r, *fr[2], *fl[2];
+};
 
-// ghost fill of one state (W, dW)
-int launch_ghosts(const geno_grid* g, const Geo& geo, double* W, double* dW, hipStream_t s,
-                  Ctrl* ctrl, int slot, double cfl, double* dt_out, int step) {
-  const int nv = geo.nv;
-  const size_t nx_items = (size_t)g->ny * 4 * nv * (1 + g->ndim);
-  tim_begin(GENO_K_GHOST_X, s);
-  hipLaunchKernelGGL(k_ghost_x, dim3(nblocks(nx_items)), dim3(BLOCK), 0, s, geo, W, dW, g->ndim,
-                     ctrl, slot, cfl, dt_out, step);
-  tim_end(s);
-  if (g->ndim == 2) {
-    const size_t ny_items = (size_t)(g->nx + 4) * 4 * 12;
-    tim_begin(GENO_K_GHOST_Y, s);
-    hipLaunchKernelGGL(k_ghost_y, dim3(nblocks(ny_items)), dim3(BLOCK), 0, s, geo, W, dW);
-    tim_end(s);
+Bufs bufs_of(char* ws, const Layout& L, int ndim) {
+  Bufs b{};
+  b.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  b.part = reinterpret_cast<double*>(ws + L.part);
+  b.wst = reinterpret_cast<double*>(ws + L.wst);
+  b.dwst = reinterpret_cast<double*>(ws + L.dwst);
+  b.r = reinterpret_cast<double*>(ws + L.r);
+  b.fl[0] = reinterpret_cast<double*>(ws + L.fl[0]);
+  if (ndim == 2) {
+    b.queue[0] = reinterpret_cast<unsigned int*>(ws + L.queue[0]);
+    b.queue[1] = reinterpret_cast<unsigned int*>(ws + L.queue[1]);
+    b.fr[0] = reinterpret_cast<double*>(ws + L.fr[0]);
+    b.fr[1] = reinterpret_cast<double*>(ws + L.fr[1]);
+    b.fl[1] = reinterpret_cast<double*>(ws + L.fl[1]);
   }
+  return b;
+}
+
+int launch_init(const geno_grid* g, const Geo& geo, double gamma, double* W, double* dW,
+                const Bufs& B, hipStream_t s) {
+  const size_t n = (size_t)g->nx * g->ny;
+  tim_begin(GENO_K_INIT, s);
+  if (g->ndim == 2)
+    hipLaunchKernelGGL(k_init<2>, dim3(nblocks(n)), dim3(BLOCK), 0, s, geo, gamma, W, dW, B.part,
+                       B.ctrl);
+  else
+    hipLaunchKernelGGL(k_init<1>, dim3(nblocks(n)), dim3(BLOCK), 0, s, geo, gamma, W, dW, B.part,
+                       B.ctrl);
+  tim_end(s);
   HIP_TRY(hipGetLastError());
   return GENO_OK;
 }
 
 // one stage of gks_step: faces and update
-int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, char* ws,
-                 const Layout& L, double* Win, double* dWin, int stage, int slot, double* dt_out,
-                 int step, double* Wfinal, double* dWfinal, hipStream_t s) {
-  Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
-  double* Wst = reinterpret_cast<double*>(ws + L.wst);
-  double* dWst = reinterpret_cast<double*>(ws + L.dwst);
-  double* R = reinterpret_cast<double*>(ws + L.r);
-  double* fl0 = reinterpret_cast<double*>(ws + L.fl[0]);
-  double* fl1 = g->ndim == 2 ? reinterpret_cast<double*>(ws + L.fl[1]) : nullptr;
-  int rc = launch_ghosts(g, geo, Win, dWin, s, stage == 1 ? ctrl : nullptr, slot, k.cfl,
-                         dt_out, step);
-  if (rc) return rc;
+int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, const Bufs& B,
+                 int npart, double* Win, double* dWin, int stage, double* dt_out, int step,
+                 double* Wfinal, double* dWfinal, int count, hipStream_t s) {
   const int want_F = stage == 1;
+  const double* part = stage == 1 ? B.part : nullptr;   // dt of the step is reduced once
   if (g->ndim == 2) {
-    double* fr0 = reinterpret_cast<double*>(ws + L.fr[0]);
-    double* fr1 = reinterpret_cast<double*>(ws + L.fr[1]);
-    tim_begin(GENO_K_NORMAL_X, s);
-    hipLaunchKernelGGL(k_normal2d<0>, dim3(nblocks((size_t)(g->ny + 2) * (g->nx + 1))),
-                       dim3(BLOCK), 0, s, geo, k, Win, dWin, fr0, nullptr);
-    tim_end(s);
-    tim_begin(GENO_K_FACES_X, s);
-    hipLaunchKernelGGL((k_faces2d<0, 1>), dim3(nblocks((size_t)g->ny * (g->nx + 1))), dim3(BLOCK),
-                       0, s, geo, k, Win, fr0, fl0, ctrl, slot, 0.0, want_F);
-    tim_end(s);
-    tim_begin(GENO_K_NORMAL_Y, s);
-    hipLaunchKernelGGL(k_normal2d<1>, dim3(nblocks((size_t)(g->ny + 1) * (g->nx + 2))),
-                       dim3(BLOCK), 0, s, geo, k, Win, dWin, fr1, nullptr);
-    tim_end(s);
-    tim_begin(GENO_K_FACES_Y, s);
-    hipLaunchKernelGGL((k_faces2d<1, 1>), dim3(nblocks((size_t)(g->ny + 1) * g->nx)), dim3(BLOCK),
-                       0, s, geo, k, Win, fr1, fl1, ctrl, slot, 0.0, want_F);
-    tim_end(s);
+    for (int dir = 0; dir < 2; ++dir) {
+      const size_t nrows =
+          dir == 0 ? (size_t)(g->ny + 2) * (g->nx + 1) : (size_t)(g->ny + 1) * (g->nx + 2);
+      const size_t nfaces = dir == 0 ? (size_t)g->ny * (g->nx + 1) : (size_t)(g->ny + 1) * g->nx;
+      tim_begin(dir == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y, s);
+      if (dir == 0)
+        hipLaunchKernelGGL(k_normal2d<0>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Win,
+                           dWin, B.fr[0], nullptr, B.ctrl, part, npart, dt_out, step, count);
+      else
+        hipLaunchKernelGGL(k_normal2d<1>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Win,
+                           dWin, B.fr[1], nullptr, B.ctrl, nullptr, 0, nullptr, 0, count);
+      tim_end(s);
+      tim_begin(dir == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, s);
+      if (dir == 0)
+        hipLaunchKernelGGL((k_faces2d<0, 1>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo,
+                           k, Win, B.fr[0], B.fl[0], B.ctrl, want_F, count, B.queue[0]);
+      else
+        hipLaunchKernelGGL((k_faces2d<1, 1>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo,
+                           k, Win, B.fr[1], B.fl[1], B.ctrl, want_F, count, B.queue[1]);
+      tim_end(s);
+      const unsigned sb = (unsigned)std::min<size_t>(SLOW_BLOCKS, nblocks(nfaces));
+      tim_begin(dir == 0 ? GENO_K_SLOW_X : GENO_K_SLOW_Y, s);
+      if (dir == 0)
+        hipLaunchKernelGGL((k_faces2d<0, 2>), dim3(sb), dim3(BLOCK), 0, s, geo, k, Win, B.fr[0],
+                           B.fl[0], B.ctrl, want_F, count, B.queue[0]);
+      else
+        hipLaunchKernelGGL((k_faces2d<1, 2>), dim3(sb), dim3(BLOCK), 0, s, geo, k, Win, B.fr[1],
+                           B.fl[1], B.ctrl, want_F, count, B.queue[1]);
+      tim_end(s);
+    }
   } else {
+    if (part) {
+      hipLaunchKernelGGL(k_dt1d, dim3(1), dim3(BLOCK), 0, s, B.part, npart, B.ctrl, k.cfl, dt_out,
+                         step);
+    }
     tim_begin(GENO_K_FACES_1D, s);
     hipLaunchKernelGGL(k_faces1d<1>, dim3(nblocks((size_t)g->nx + 1)), dim3(BLOCK), 0, s, geo, k,
-                       Win, dWin, fl0, nullptr, ctrl, slot, 0.0, want_F);
+                       Win, dWin, B.fl[0], nullptr, B.ctrl, want_F, count);
     tim_end(s);
   }
   const size_t ncell = (size_t)g->nx * g->ny;
@@ -722,17 +986,17 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, cha
   if (g->ndim == 2) {
     if (stage == 1)
       hipLaunchKernelGGL((k_update<2, 1>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         Wst, dWst, R, fl0, fl1, ctrl, slot);
+                         B.wst, B.dwst, B.r, B.fl[0], B.fl[1], B.ctrl, B.part, count);
     else
       hipLaunchKernelGGL((k_update<2, 2>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         Wfinal, dWfinal, R, fl0, fl1, ctrl, slot);
+                         Wfinal, dWfinal, B.r, B.fl[0], B.fl[1], B.ctrl, B.part, count);
   } else {
     if (stage == 1)
       hipLaunchKernelGGL((k_update<1, 1>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         Wst, dWst, R, fl0, fl1, ctrl, slot);
+                         B.wst, B.dwst, B.r, B.fl[0], nullptr, B.ctrl, B.part, count);
     else
       hipLaunchKernelGGL((k_update<1, 2>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         Wfinal, dWfinal, R, fl0, fl1, ctrl, slot);
+                         Wfinal, dWfinal, B.r, B.fl[0], nullptr, B.ctrl, B.part, count);
   }
   tim_end(s);
   HIP_TRY(hipGetLastError());
@@ -740,6 +1004,9 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, cha
 }
 
 }  // namespace
+
+// operation costs per work class (opcount.hip)
+int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* costs);
 
 // ===========================================================================
 // C ABI
@@ -768,6 +1035,11 @@ int geno_timing_enable(int max_launches) {
   return GENO_OK;
 }
 
+int geno_count_enable(int on) {
+  g_count = on ? 1 : 0;
+  return GENO_OK;
+}
+
 int geno_timing_read(int nkinds, double* ms_total, long long* launches) {
   if (!ms_total || !launches || nkinds < 1) return fail(GENO_EINVAL, "null argument");
   for (int k = 0; k < nkinds; ++k) {
@@ -786,6 +1058,30 @@ int geno_timing_read(int nkinds, double* ms_total, long long* launches) {
   }
   g_tim.used = 0;
   return GENO_OK;
+}
+
+int geno_work_read(const geno_grid* g, const void* ws, int nkinds, int nclass, long long* counts,
+                   void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!ws || !counts || nkinds < 1 || nclass < 1) return fail(GENO_EINVAL, "null argument");
+  const Layout L = layout_of(g);
+  Ctrl h;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(&h, (const char*)ws + L.ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int a = 0; a < nkinds; ++a)
+    for (int c = 0; c < nclass; ++c)
+      counts[a * nclass + c] =
+          (a < GENO_NKERNELS && c < GENO_NCLASS) ? (long long)h.work[a][c] : 0;
+  return GENO_OK;
+}
+
+int geno_op_costs(const geno_grid* g, int nkinds, int nclass, double* costs) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!costs || nkinds < 1 || nclass < 1) return fail(GENO_EINVAL, "null argument");
+  return geno_op_costs_impl(g->ndim, g->params.gamma, nkinds, nclass, costs);
 }
 
 const char* geno_kernel_name(int kind) {
@@ -858,28 +1154,28 @@ int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_
   const Geo geo = geo_of(g);
   const geno::KParams k = kparams(g);
   const Layout L = layout_of(g);
-  char* w = (char*)ws;
+  const Bufs B = bufs_of((char*)ws, L, g->ndim);
   double* Wd = (double*)W;
   double* dWd = (double*)dW;
-  rc = launch_ghosts(g, geo, Wd, dWd, s, nullptr, 0, 0.0, nullptr, 0);
+  rc = launch_init(g, geo, k.gamma, Wd, dWd, B, s);
   if (rc) return rc;
   if (g->ndim == 1) {
     hipLaunchKernelGGL(k_faces1d<0>, dim3(nblocks((size_t)g->nx + 1)), dim3(BLOCK), 0, s, geo, k,
-                       Wd, dWd, (double*)face_state, (double*)chi, nullptr, 0, 0.0, 0);
+                       Wd, dWd, (double*)face_state, (double*)chi, nullptr, 0, 0);
   } else {
-    double* fr = (double*)(w + L.fr[dir]);
+    const size_t nrows =
+        dir == 0 ? (size_t)(g->ny + 2) * (g->nx + 1) : (size_t)(g->ny + 1) * (g->nx + 2);
+    const size_t nfaces = dir == 0 ? (size_t)g->ny * (g->nx + 1) : (size_t)(g->ny + 1) * g->nx;
     if (dir == 0) {
-      hipLaunchKernelGGL(k_normal2d<0>, dim3(nblocks((size_t)(g->ny + 2) * (g->nx + 1))),
-                         dim3(BLOCK), 0, s, geo, k, Wd, dWd, fr, (double*)chi);
-      hipLaunchKernelGGL((k_faces2d<0, 0>), dim3(nblocks((size_t)g->ny * (g->nx + 1))),
-                         dim3(BLOCK), 0, s, geo, k, Wd, fr, (double*)face_state, nullptr, 0, 0.0,
-                         0);
+      hipLaunchKernelGGL(k_normal2d<0>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Wd, dWd,
+                         B.fr[0], (double*)chi, nullptr, nullptr, 0, nullptr, 0, 0);
+      hipLaunchKernelGGL((k_faces2d<0, 0>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo, k,
+                         Wd, B.fr[0], (double*)face_state, nullptr, 0, 0, nullptr);
     } else {
-      hipLaunchKernelGGL(k_normal2d<1>, dim3(nblocks((size_t)(g->ny + 1) * (g->nx + 2))),
-                         dim3(BLOCK), 0, s, geo, k, Wd, dWd, fr, (double*)chi);
-      hipLaunchKernelGGL((k_faces2d<1, 0>), dim3(nblocks((size_t)(g->ny + 1) * g->nx)),
-                         dim3(BLOCK), 0, s, geo, k, Wd, fr, (double*)face_state, nullptr, 0, 0.0,
-                         0);
+      hipLaunchKernelGGL(k_normal2d<1>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Wd, dWd,
+                         B.fr[1], (double*)chi, nullptr, nullptr, 0, nullptr, 0, 0);
+      hipLaunchKernelGGL((k_faces2d<1, 0>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo, k,
+                         Wd, B.fr[1], (double*)face_state, nullptr, 0, 0, nullptr);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -921,36 +1217,27 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
   const Geo geo = geo_of(g);
   const geno::KParams k = kparams(g);
   const Layout L = layout_of(g);
-  char* w = (char*)ws;
-  Ctrl* ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
+  const Bufs B = bufs_of((char*)ws, L, g->ndim);
+  const int count = g_count;
   double* Wd = (double*)W;
   double* dWd = (double*)dW;
-  double* Wst = reinterpret_cast<double*>(w + L.wst);
-  double* dWst = reinterpret_cast<double*>(w + L.dwst);
-  tim_begin(GENO_K_DT_INIT, s);
-  if (g->ndim == 2)
-    hipLaunchKernelGGL(k_dt_init<2>, dim3(1), dim3(1024), 0, s, geo, k, Wd, ctrl);
-  else
-    hipLaunchKernelGGL(k_dt_init<1>, dim3(1), dim3(1024), 0, s, geo, k, Wd, ctrl);
-  tim_end(s);
-  HIP_TRY(hipGetLastError());
+  rc = launch_init(g, geo, k.gamma, Wd, dWd, B, s);
+  if (rc) return rc;
   for (int n = 0; n < nsteps; ++n) {
-    const int slot = n & 1;
-    rc = launch_stage(g, geo, k, w, L, Wd, dWd, 1, slot, dt_out, n, nullptr, nullptr, s);
+    rc = launch_stage(g, geo, k, B, L.npart, Wd, dWd, 1, dt_out, n, nullptr, nullptr, count, s);
     if (rc) return rc;
-    rc = launch_stage(g, geo, k, w, L, Wst, dWst, 2, slot, nullptr, n, Wd, dWd, s);
+    rc = launch_stage(g, geo, k, B, L.npart, B.wst, B.dwst, 2, nullptr, n, Wd, dWd, count, s);
     if (rc) return rc;
   }
   if (stats) {
     Ctrl h;
-    HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h, B.ctrl, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stats->guard = (long long)h.guard;
     stats->nonfinite = (long long)h.nonfinite;
-    const int last = nsteps > 0 ? (nsteps - 1) & 1 : 0;
-    double tm;
-    memcpy(&tm, &h.tmin[last], sizeof tm);
-    stats->last_dt = nsteps > 0 ? k.cfl * tm : 0.0;
+    double last;
+    memcpy(&last, &h.tmin, sizeof last);
+    stats->last_dt = nsteps > 0 ? k.cfl * last : 0.0;
     if (h.nonfinite) return fail(GENO_ENONPHYS, "%llu non-finite cells", h.nonfinite);
   }
   return GENO_OK;

@@ -19,6 +19,9 @@
 // rho_c <(abar u + bbar v) psi>_c = -W_t and rho_c <Abar psi>_c = W_t.
 // With tau = 0 the solution reduces exactly to F = F_Euler(W_c),
 // dF/dt = J_x(W_c) W_t and W(t) = W_c + t W_t.
+//
+// Templated on the arithmetic type R (double; float in the mixed form) and
+// host+device so that an operation-counting type can be substituted.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,26 +32,29 @@ namespace gks {
 
 using geno::KParams;
 
-template <int NV>
+template <typename R>
 struct Prim {
-  double rho, U, V, p, lam;
+  R rho, U, V, p, lam;
 };
 
-template <int NV>
-__device__ __forceinline__ Prim<NV> prim(const double* W, double gamma) {
-  Prim<NV> q;
+template <int NV, typename R>
+GENO_HD Prim<R> prim(const R* W, double gamma) {
+  Prim<R> q;
   q.rho = W[0];
-  const double ir = 1.0 / W[0];
+  const R ir = R(1.0) / W[0];
   q.U = W[1] * ir;
-  q.V = (NV == 4) ? W[2] * ir : 0.0;
-  q.p = (gamma - 1.0) * (W[NV - 1] - 0.5 * q.rho * (q.U * q.U + q.V * q.V));
-  q.lam = q.rho / (2.0 * q.p);
+  if constexpr (NV == 4) q.V = W[2] * ir;
+  else q.V = R(0.0);
+  R ke = q.U * q.U;
+  if constexpr (NV == 4) ke = ke + q.V * q.V;
+  q.p = R(gamma - 1.0) * (W[NV - 1] - R(0.5) * q.rho * ke);
+  q.lam = q.rho / (R(2.0) * q.p);
   return q;
 }
 
 // Euler flux along the first velocity component (face frame).
-template <int NV>
-__device__ __forceinline__ void euler_flux(const double* W, const Prim<NV>& q, double* F) {
+template <int NV, typename R>
+GENO_HD void euler_flux(const R* W, const Prim<R>& q, R* F) {
   F[0] = W[1];
   F[1] = W[1] * q.U + q.p;
   if constexpr (NV == 4) F[2] = W[2] * q.U;
@@ -56,29 +62,29 @@ __device__ __forceinline__ void euler_flux(const double* W, const Prim<NV>& q, d
 }
 
 // J_x(W) dW and J_y(W) dW of the Euler fluxes (face frame: x normal).
-template <int NV>
-__device__ __forceinline__ void jac_x(const double* W, const Prim<NV>& q, const double* d,
-                                      double gamma, double* out) {
-  const double ir = 1.0 / q.rho;
-  const double dU = (d[1] - q.U * d[0]) * ir;
-  double dp;
+template <int NV, typename R>
+GENO_HD void jac_x(const R* W, const Prim<R>& q, const R* d, double gamma, R* out) {
+  const R ir = R(1.0) / q.rho;
+  const R dU = (d[1] - q.U * d[0]) * ir;
+  R dp;
   if constexpr (NV == 4) {
-    dp = (gamma - 1.0) * (d[3] - q.U * d[1] - q.V * d[2] + 0.5 * (q.U * q.U + q.V * q.V) * d[0]);
+    dp = R(gamma - 1.0) *
+         (d[3] - q.U * d[1] - q.V * d[2] + R(0.5) * (q.U * q.U + q.V * q.V) * d[0]);
     out[2] = d[2] * q.U + W[2] * dU;
   } else {
-    dp = (gamma - 1.0) * (d[2] - q.U * d[1] + 0.5 * q.U * q.U * d[0]);
+    dp = R(gamma - 1.0) * (d[2] - q.U * d[1] + R(0.5) * q.U * q.U * d[0]);
   }
   out[0] = d[1];
   out[1] = d[1] * q.U + W[1] * dU + dp;
   out[NV - 1] = dU * (W[NV - 1] + q.p) + q.U * (d[NV - 1] + dp);
 }
 
-__device__ __forceinline__ void jac_y(const double* W, const Prim<4>& q, const double* d,
-                                      double gamma, double* out) {
-  const double ir = 1.0 / q.rho;
-  const double dV = (d[2] - q.V * d[0]) * ir;
-  const double dp =
-      (gamma - 1.0) * (d[3] - q.U * d[1] - q.V * d[2] + 0.5 * (q.U * q.U + q.V * q.V) * d[0]);
+template <typename R>
+GENO_HD void jac_y(const R* W, const Prim<R>& q, const R* d, double gamma, R* out) {
+  const R ir = R(1.0) / q.rho;
+  const R dV = (d[2] - q.V * d[0]) * ir;
+  const R dp = R(gamma - 1.0) *
+               (d[3] - q.U * d[1] - q.V * d[2] + R(0.5) * (q.U * q.U + q.V * q.V) * d[0]);
   out[0] = d[2];
   out[1] = d[1] * q.V + W[1] * dV;
   out[2] = d[2] * q.V + W[2] * dV + dp;
@@ -87,266 +93,273 @@ __device__ __forceinline__ void jac_y(const double* W, const Prim<4>& q, const d
 
 // Micro-slope a with <a psi> = w over the Maxwellian (U, V, lam), closed form
 // of the 4x4 (3x3 in 1-D) moment system.
-template <int NV>
-__device__ __forceinline__ void micro_slope(const Prim<NV>& q, double K, const double* w,
-                                            double* a) {
-  const double il = 1.0 / q.lam;
+template <int NV, typename R>
+GENO_HD void micro_slope(const Prim<R>& q, double K, const R* w, R* a) {
+  const R il = R(1.0) / q.lam;
+  const R l2 = R(2.0) * q.lam;
   if constexpr (NV == 4) {
-    const double B = q.U * q.U + q.V * q.V + 0.5 * (K + 2.0) * il;
-    const double R4 = 2.0 * w[3] - B * w[0];
-    const double R3 = w[2] - q.V * w[0];
-    const double R2 = w[1] - q.U * w[0];
-    a[3] = 4.0 * q.lam * q.lam / (K + 2.0) * (R4 - 2.0 * q.U * R2 - 2.0 * q.V * R3);
-    a[2] = 2.0 * q.lam * R3 - q.V * a[3];
-    a[1] = 2.0 * q.lam * R2 - q.U * a[3];
-    a[0] = w[0] - q.U * a[1] - q.V * a[2] - 0.5 * a[3] * B;
+    const R B = q.U * q.U + q.V * q.V + R(0.5 * (K + 2.0)) * il;
+    const R R4 = R(2.0) * w[3] - B * w[0];
+    const R R3 = w[2] - q.V * w[0];
+    const R R2 = w[1] - q.U * w[0];
+    a[3] = q.lam * q.lam * R(4.0 / (K + 2.0)) * (R4 - R(2.0) * q.U * R2 - R(2.0) * q.V * R3);
+    a[2] = l2 * R3 - q.V * a[3];
+    a[1] = l2 * R2 - q.U * a[3];
+    a[0] = w[0] - q.U * a[1] - q.V * a[2] - R(0.5) * a[3] * B;
   } else {
-    const double B = q.U * q.U + 0.5 * (K + 1.0) * il;
-    const double R3 = 2.0 * w[2] - B * w[0];
-    const double R2 = w[1] - q.U * w[0];
-    a[2] = 4.0 * q.lam * q.lam / (K + 1.0) * (R3 - 2.0 * q.U * R2);
-    a[1] = 2.0 * q.lam * R2 - q.U * a[2];
-    a[0] = w[0] - q.U * a[1] - 0.5 * a[2] * B;
+    const R B = q.U * q.U + R(0.5 * (K + 1.0)) * il;
+    const R R3 = R(2.0) * w[2] - B * w[0];
+    const R R2 = w[1] - q.U * w[0];
+    a[2] = q.lam * q.lam * R(4.0 / (K + 1.0)) * (R3 - R(2.0) * q.U * R2);
+    a[1] = l2 * R2 - q.U * a[2];
+    a[0] = w[0] - q.U * a[1] - R(0.5) * a[2] * B;
   }
 }
 
 // Moments of a Maxwellian normalised by its density: u^n (n <= 6) over the
 // whole space or one half-space, v^m (m <= 5) over the whole space, and the
 // internal energy moments <xi^2>, <xi^4>.
-template <int NV>
+template <typename R>
 struct Mom {
-  double u[7];
-  double v[6];
-  double x2, x4;
+  R u[7];
+  R v[6];
+  R x2, x4;
 };
 
 // Fills u[2..6], v[*] and the xi moments from u[0], u[1].
-template <int NV>
-__device__ __forceinline__ void fill_moments(Mom<NV>& m, const Prim<NV>& q, double K) {
-  const double h = 0.5 / q.lam;
+template <int NV, typename R>
+GENO_HD void fill_moments(Mom<R>& m, const Prim<R>& q, double K) {
+  const R h = R(0.5) / q.lam;
 #pragma unroll
-  for (int n = 0; n < 5; ++n) m.u[n + 2] = q.U * m.u[n + 1] + (n + 1) * h * m.u[n];
-  m.v[0] = 1.0;
+  for (int n = 0; n < 5; ++n) m.u[n + 2] = q.U * m.u[n + 1] + R(n + 1) * h * m.u[n];
+  m.v[0] = R(1.0);
   if constexpr (NV == 4) {
     m.v[1] = q.V;
 #pragma unroll
-    for (int n = 0; n < 4; ++n) m.v[n + 2] = q.V * m.v[n + 1] + (n + 1) * h * m.v[n];
+    for (int n = 0; n < 4; ++n) m.v[n + 2] = q.V * m.v[n + 1] + R(n + 1) * h * m.v[n];
   } else {
 #pragma unroll
-    for (int n = 1; n < 6; ++n) m.v[n] = 0.0;
+    for (int n = 1; n < 6; ++n) m.v[n] = R(0.0);
   }
-  m.x2 = K * h;
-  m.x4 = K * (K + 2.0) * h * h;
+  m.x2 = R(K) * h;
+  m.x4 = R(K * (K + 2.0)) * h * h;
 }
 
-// <u^i v^j psi> into out (NV components); zx = 0 / 1 adds a factor xi^2.
-template <int NV>
-__device__ __forceinline__ void mom_psi(const Mom<NV>& m, int i, int j, int zx, double* out) {
-  const double z0 = zx ? m.x2 : 1.0, z1 = zx ? m.x4 : m.x2;
-  const double g = m.u[i] * m.v[j];
-  out[0] = g * z0;
-  out[1] = m.u[i + 1] * m.v[j] * z0;
+// <u^i v^j psi> into out (NV components); ZX adds a factor xi^2.
+template <int NV, int ZX, typename R>
+GENO_HD void mom_psi(const Mom<R>& m, int i, int j, R* out) {
+  const R z0 = ZX ? m.x2 : R(1.0), z1 = ZX ? m.x4 : m.x2;
+  const R g = m.u[i] * m.v[j];
+  out[0] = ZX ? g * z0 : g;
+  out[1] = ZX ? m.u[i + 1] * m.v[j] * z0 : m.u[i + 1] * m.v[j];
   if constexpr (NV == 4) {
-    out[2] = m.u[i] * m.v[j + 1] * z0;
-    out[3] = 0.5 * ((m.u[i + 2] * m.v[j] + m.u[i] * m.v[j + 2]) * z0 + g * z1);
+    out[2] = ZX ? m.u[i] * m.v[j + 1] * z0 : m.u[i] * m.v[j + 1];
+    const R s = m.u[i + 2] * m.v[j] + m.u[i] * m.v[j + 2];
+    out[3] = R(0.5) * ((ZX ? s * z0 : s) + g * z1);
   } else {
-    out[2] = 0.5 * (m.u[i + 2] * z0 + m.u[i] * z1);
+    out[2] = R(0.5) * ((ZX ? m.u[i + 2] * z0 : m.u[i + 2]) + m.u[i] * z1);
   }
 }
 
 // <u^i v^j (a.psi) psi>, psi = (1, u, [v,] (u^2 [+ v^2] + xi^2)/2).
-template <int NV>
-__device__ __forceinline__ void mom_a(const Mom<NV>& m, const double* a, int i, int j,
-                                      double* out) {
-  double t0[NV], t1[NV], t2[NV], t3[NV], t4[NV], t5[NV];
-  mom_psi<NV>(m, i, j, 0, t0);
-  mom_psi<NV>(m, i + 1, j, 0, t1);
-  mom_psi<NV>(m, i + 2, j, 0, t3);
-  mom_psi<NV>(m, i, j, 1, t5);
+template <int NV, typename R>
+GENO_HD void mom_a(const Mom<R>& m, const R* a, int i, int j, R* out) {
+  R t0[NV], t1[NV], t2[NV], t3[NV], t4[NV], t5[NV];
+  mom_psi<NV, 0>(m, i, j, t0);
+  mom_psi<NV, 0>(m, i + 1, j, t1);
+  mom_psi<NV, 0>(m, i + 2, j, t3);
+  mom_psi<NV, 1>(m, i, j, t5);
   if constexpr (NV == 4) {
-    mom_psi<NV>(m, i, j + 1, 0, t2);
-    mom_psi<NV>(m, i, j + 2, 0, t4);
+    mom_psi<NV, 0>(m, i, j + 1, t2);
+    mom_psi<NV, 0>(m, i, j + 2, t4);
   }
-  const double aE = 0.5 * a[NV - 1];
+  const R aE = R(0.5) * a[NV - 1];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = a[0] * t0[k] + a[1] * t1[k];
-    if constexpr (NV == 4) s += a[2] * t2[k] + aE * (t3[k] + t4[k] + t5[k]);
-    else s += aE * (t3[k] + t5[k]);
+    R s = a[0] * t0[k] + a[1] * t1[k];
+    if constexpr (NV == 4) s = s + a[2] * t2[k] + aE * (t3[k] + t4[k] + t5[k]);
+    else s = s + aE * (t3[k] + t5[k]);
     out[k] = s;
   }
 }
 
 // Point flux. Wl, Wr: states (face frame, normal momentum first); nl, nr,
 // tl, tr: physical normal / tangential derivatives (tl, tr unused in 1-D).
-// Accumulates w * F, w * dF/dt and w * W(dt/2) into F, Ft, Wi (F may be
-// skipped with want_F = false).
-template <int NV>
-__device__ __forceinline__ void point_flux(const double* Wl, const double* Wr, const double* nl,
-                                           const double* nr, const double* tl, const double* tr,
-                                           double dt, const KParams& k, double w, bool want_F,
-                                           double* F, double* Ft, double* Wi) {
+// Accumulates w * F, w * dF/dt and w * W(dt/2) into F, Ft, Wi (F skipped
+// unless want_F). Returns whether the collision time is positive. With
+// FULL = false such a point is not evaluated and nothing is accumulated (the
+// caller hands the face to the full path).
+template <int NV, bool FULL, typename R>
+GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const R* tl,
+                        const R* tr, R dt, const KParams& k, R w, bool want_F, R* F, R* Ft,
+                        R* Wi) {
   const double g = k.gamma, K = k.K;
-  const Prim<NV> pl = prim<NV>(Wl, g), pr = prim<NV>(Wr, g);
+  const Prim<R> pl = prim<NV, R>(Wl, g), pr = prim<NV, R>(Wr, g);
+  const R tau = R(k.tc1) * dt + R(k.tc2) * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
+  const bool slow = tau > R(0.0);
+  if (!FULL && slow) return true;
   // half-space u^0, u^1 moments of both sides
-  const double sl = sqrt(pl.lam), sr = sqrt(pr.lam);
-  const double tl0 = 0.5 * erfc(-sl * pl.U), tr0 = 0.5 * erfc(sr * pr.U);
-  const double isp = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
-  const double tl1 = exp(-pl.lam * pl.U * pl.U) * isp / sl;
-  const double tr1 = exp(-pr.lam * pr.U * pr.U) * isp / sr;
-  const double lu0 = tl0, lu1 = pl.U * tl0 + tl1;
-  const double ru0 = tr0, ru1 = pr.U * tr0 - tr1;
-  const double hl = 0.5 / pl.lam, hr = 0.5 / pr.lam;
-  const double lu2 = pl.U * lu1 + hl * lu0, ru2 = pr.U * ru1 + hr * ru0;
+  const R sl = sqrt(pl.lam), sr = sqrt(pr.lam);
+  const R tl0 = R(0.5) * erfc(-sl * pl.U), tr0 = R(0.5) * erfc(sr * pr.U);
+  const R isp = R(0.28209479177387814347);  // 1 / (2 sqrt(pi))
+  const R tl1 = exp(-pl.lam * pl.U * pl.U) * isp / sl;
+  const R tr1 = exp(-pr.lam * pr.U * pr.U) * isp / sr;
+  const R lu0 = tl0, lu1 = pl.U * tl0 + tl1;
+  const R ru0 = tr0, ru1 = pr.U * tr0 - tr1;
+  const R hl = R(0.5) / pl.lam, hr = R(0.5) / pr.lam;
+  const R lu2 = pl.U * lu1 + hl * lu0, ru2 = pr.U * ru1 + hr * ru0;
   // interface equilibrium W_c = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}
-  double Wc[NV];
+  R Wc[NV];
   Wc[0] = pl.rho * lu0 + pr.rho * ru0;
   Wc[1] = pl.rho * lu1 + pr.rho * ru1;
   if constexpr (NV == 4) {
     Wc[2] = pl.rho * pl.V * lu0 + pr.rho * pr.V * ru0;
-    Wc[3] = 0.5 * (pl.rho * (lu2 + (pl.V * pl.V + hl + K * hl) * lu0) +
-                   pr.rho * (ru2 + (pr.V * pr.V + hr + K * hr) * ru0));
+    Wc[3] = R(0.5) * (pl.rho * (lu2 + (pl.V * pl.V + hl + R(K) * hl) * lu0) +
+                      pr.rho * (ru2 + (pr.V * pr.V + hr + R(K) * hr) * ru0));
   } else {
-    Wc[2] = 0.5 * (pl.rho * (lu2 + K * hl * lu0) + pr.rho * (ru2 + K * hr * ru0));
+    Wc[2] = R(0.5) * (pl.rho * (lu2 + R(K) * hl * lu0) + pr.rho * (ru2 + R(K) * hr * ru0));
   }
-  const Prim<NV> pc = prim<NV>(Wc, g);
+  const Prim<R> pc = prim<NV, R>(Wc, g);
   // averaged derivatives and the equilibrium time derivative
-  double dn[NV], dtn[NV], Wt[NV], tmp[NV];
+  R dn[NV], dtn[NV], Wt[NV], tmp[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    dn[v] = 0.5 * (nl[v] + nr[v]);
-    dtn[v] = (NV == 4) ? 0.5 * (tl[v] + tr[v]) : 0.0;
+    dn[v] = R(0.5) * (nl[v] + nr[v]);
+    if constexpr (NV == 4) dtn[v] = R(0.5) * (tl[v] + tr[v]);
+    else dtn[v] = R(0.0);
   }
-  jac_x<NV>(Wc, pc, dn, g, Wt);
+  jac_x<NV, R>(Wc, pc, dn, g, Wt);
   if constexpr (NV == 4) {
-    jac_y(Wc, *reinterpret_cast<const Prim<4>*>(&pc), dtn, g, tmp);
+    jac_y<R>(Wc, pc, dtn, g, tmp);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Wt[v] = -(Wt[v] + tmp[v]);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Wt[v] = -Wt[v];
   }
-  double Fe[NV], JW[NV];
-  euler_flux<NV>(Wc, pc, Fe);
-  jac_x<NV>(Wc, pc, Wt, g, JW);
-
-  const double tau = k.tc1 * dt + k.tc2 * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
-  const double h = 0.5 * dt;
-  if (!(tau > 0.0)) {
+  R Fe[NV], JW[NV];
+  euler_flux<NV, R>(Wc, pc, Fe);
+  jac_x<NV, R>(Wc, pc, Wt, g, JW);
+  const R h = R(0.5) * dt;
+  if (!slow) {
     // tau = 0: exact limits of the time integrals
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      if (want_F) F[v] += w * Fe[v];
-      Ft[v] += w * JW[v];
-      Wi[v] += w * (Wc[v] + h * Wt[v]);
+      if (want_F) F[v] = F[v] + w * Fe[v];
+      Ft[v] = Ft[v] + w * JW[v];
+      Wi[v] = Wi[v] + w * (Wc[v] + h * Wt[v]);
     }
-    return;
+    return false;
   }
-  // ---- tau > 0 ----
-  // time integrals over [0, d] of the weights of the solution, d = dt/2, dt
-  const double xh = h / tau;
-  const double eh = exp(-xh), emh = -expm1(-xh);
-  const double ef = eh * eh, emf = emh * (2.0 - emh);
-  const double tt = tau * tau;
-  const double c1h = h - tau * emh, c1f = dt - tau * emf;
-  const double c5h = 2.0 * tt - tau * (h + 2.0 * tau) * eh;
-  const double c5f = 2.0 * tt - tau * (dt + 2.0 * tau) * ef;
-  const double c2h = c5h - tau * h, c2f = c5f - tau * dt;
-  const double c3h = 0.5 * h * h - tau * h + tt * emh, c3f = 0.5 * dt * dt - tau * dt + tt * emf;
-  const double c4h = tau * emh, c4f = tau * emf;
-  const double c6h = tt * emh, c6f = tt * emf;
-  // least-squares-free fit F(t) = F + t dF/dt to the two integrals
-  const double idt = 1.0 / dt, idt2 = 4.0 * idt * idt;
-  const double f1 = (4.0 * c1h - c1f) * idt, g1 = (c1f - 2.0 * c1h) * idt2;
-  const double f2 = (4.0 * c2h - c2f) * idt, g2 = (c2f - 2.0 * c2h) * idt2;
-  const double f3 = (4.0 * c3h - c3f) * idt, g3 = (c3f - 2.0 * c3h) * idt2;
-  const double f4 = (4.0 * c4h - c4f) * idt, g4 = (c4f - 2.0 * c4h) * idt2;
-  const double f5 = (4.0 * c5h - c5f) * idt, g5 = (c5f - 2.0 * c5h) * idt2;
-  const double f6 = (4.0 * c6h - c6f) * idt, g6 = (c6f - 2.0 * c6h) * idt2;
-  // interface state at dt/2
-  const double k1 = emh, k2 = (h + tau) * eh - tau, k3 = h - tau * emh, k4 = h + tau;
+  if constexpr (FULL) {
+    // ---- tau > 0 ----
+    // time integrals over [0, d] of the weights of the solution, d = dt/2, dt
+    const R xh = h / tau;
+    const R eh = exp(-xh), emh = -expm1(-xh);
+    const R ef = eh * eh, emf = emh * (R(2.0) - emh);
+    const R tt = tau * tau;
+    const R c1h = h - tau * emh, c1f = dt - tau * emf;
+    const R c5h = R(2.0) * tt - tau * (h + R(2.0) * tau) * eh;
+    const R c5f = R(2.0) * tt - tau * (dt + R(2.0) * tau) * ef;
+    const R c2h = c5h - tau * h, c2f = c5f - tau * dt;
+    const R c3h = R(0.5) * h * h - tau * h + tt * emh;
+    const R c3f = R(0.5) * dt * dt - tau * dt + tt * emf;
+    const R c4h = tau * emh, c4f = tau * emf;
+    const R c6h = tt * emh, c6f = tt * emf;
+    // fit F(t) = F + t dF/dt to the two integrals
+    const R idt = R(1.0) / dt, idt2 = R(4.0) * idt * idt;
+    const R f1 = (R(4.0) * c1h - c1f) * idt, g1 = (c1f - R(2.0) * c1h) * idt2;
+    const R f2 = (R(4.0) * c2h - c2f) * idt, g2 = (c2f - R(2.0) * c2h) * idt2;
+    const R f3 = (R(4.0) * c3h - c3f) * idt, g3 = (c3f - R(2.0) * c3h) * idt2;
+    const R f4 = (R(4.0) * c4h - c4f) * idt, g4 = (c4f - R(2.0) * c4h) * idt2;
+    const R f5 = (R(4.0) * c5h - c5f) * idt, g5 = (c5f - R(2.0) * c5h) * idt2;
+    const R f6 = (R(4.0) * c6h - c6f) * idt, g6 = (c6f - R(2.0) * c6h) * idt2;
+    // interface state at dt/2
+    const R k1 = emh, k2 = (h + tau) * eh - tau, k3 = h - tau * emh, k4 = h + tau;
 
-  // equilibrium part: <u (abar u + bbar v) psi>_c needs the moments of g_c
-  {
-    Mom<NV> mc;
-    mc.u[0] = 1.0;
-    mc.u[1] = pc.U;
-    fill_moments<NV>(mc, pc, K);
-    double wv[NV], ab[NV], X2[NV];
-    const double irc = 1.0 / pc.rho;
+    // equilibrium part: <u (abar u + bbar v) psi>_c needs the moments of g_c
+    {
+      Mom<R> mc;
+      mc.u[0] = R(1.0);
+      mc.u[1] = pc.U;
+      fill_moments<NV, R>(mc, pc, K);
+      R wv[NV], ab[NV], X2[NV];
+      const R irc = R(1.0) / pc.rho;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) wv[v] = dn[v] * irc;
-    micro_slope<NV>(pc, K, wv, ab);
-    mom_a<NV>(mc, ab, 2, 0, X2);
-    if constexpr (NV == 4) {
-      double bb[NV];
+      for (int v = 0; v < NV; ++v) wv[v] = dn[v] * irc;
+      micro_slope<NV, R>(pc, K, wv, ab);
+      mom_a<NV, R>(mc, ab, 2, 0, X2);
+      if constexpr (NV == 4) {
+        R bb[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) wv[v] = dtn[v] * irc;
-      micro_slope<NV>(pc, K, wv, bb);
-      mom_a<NV>(mc, bb, 1, 1, tmp);
+        for (int v = 0; v < NV; ++v) wv[v] = dtn[v] * irc;
+        micro_slope<NV, R>(pc, K, wv, bb);
+        mom_a<NV, R>(mc, bb, 1, 1, tmp);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) X2[v] += tmp[v];
+        for (int v = 0; v < NV; ++v) X2[v] = X2[v] + tmp[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const R x2 = pc.rho * X2[v];
+        if (want_F) F[v] = F[v] + w * (f1 * Fe[v] + f2 * x2 + f3 * JW[v]);
+        Ft[v] = Ft[v] + w * (g1 * Fe[v] + g2 * x2 + g3 * JW[v]);
+        Wi[v] = Wi[v] + w * (k1 * Wc[v] + (k3 - k2) * Wt[v]);
+      }
     }
+    // non-equilibrium part, one side at a time
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double x2 = pc.rho * X2[v];
-      if (want_F) F[v] += w * (f1 * Fe[v] + f2 * x2 + f3 * JW[v]);
-      Ft[v] += w * (g1 * Fe[v] + g2 * x2 + g3 * JW[v]);
-      Wi[v] += w * (k1 * Wc[v] + (k3 - k2) * Wt[v]);
+    for (int side = 0; side < 2; ++side) {
+      const Prim<R>& ps = side ? pr : pl;
+      const R* Ws = side ? Wr : Wl;
+      const R* ns = side ? nr : nl;
+      const R* ts = side ? tr : tl;
+      Mom<R> ms;
+      ms.u[0] = side ? ru0 : lu0;
+      ms.u[1] = side ? ru1 : lu1;
+      fill_moments<NV, R>(ms, ps, K);
+      const R irs = R(1.0) / ps.rho;
+      R wv[NV], as[NV], bs[NV], As[NV], Ws_t[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) wv[v] = ns[v] * irs;
+      micro_slope<NV, R>(ps, K, wv, as);
+      jac_x<NV, R>(Ws, ps, ns, g, Ws_t);
+      if constexpr (NV == 4) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) wv[v] = ts[v] * irs;
+        micro_slope<NV, R>(ps, K, wv, bs);
+        jac_y<R>(Ws, ps, ts, g, tmp);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ws_t[v] = -(Ws_t[v] + tmp[v]) * irs;
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ws_t[v] = -Ws_t[v] * irs;
+      }
+      micro_slope<NV, R>(ps, K, Ws_t, As);
+      R U1[NV], Xs[NV], Ys[NV], P0[NV], Zs[NV], A0[NV];
+      mom_psi<NV, 0>(ms, 1, 0, U1);  // <u psi>
+      mom_a<NV, R>(ms, as, 2, 0, Xs);  // <u^2 (a.psi) psi>
+      mom_a<NV, R>(ms, As, 1, 0, Ys);  // <u (A.psi) psi>
+      mom_psi<NV, 0>(ms, 0, 0, P0);  // <psi>
+      mom_a<NV, R>(ms, as, 1, 0, Zs);  // <u (a.psi) psi>
+      mom_a<NV, R>(ms, As, 0, 0, A0);  // <(A.psi) psi>
+      if constexpr (NV == 4) {
+        mom_a<NV, R>(ms, bs, 1, 1, tmp);  // <u v (b.psi) psi>
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Xs[v] = Xs[v] + tmp[v];
+        mom_a<NV, R>(ms, bs, 0, 1, tmp);  // <v (b.psi) psi>
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Zs[v] = Zs[v] + tmp[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const R r = ps.rho;
+        if (want_F) F[v] = F[v] + w * r * (f4 * U1[v] - f5 * Xs[v] - f6 * Ys[v]);
+        Ft[v] = Ft[v] + w * r * (g4 * U1[v] - g5 * Xs[v] - g6 * Ys[v]);
+        Wi[v] = Wi[v] + w * eh * r * (P0[v] - k4 * Zs[v] - tau * A0[v]);
+      }
     }
   }
-  // non-equilibrium part, one side at a time
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const Prim<NV>& ps = side ? pr : pl;
-    const double* Ws = side ? Wr : Wl;
-    const double* ns = side ? nr : nl;
-    const double* ts = side ? tr : tl;
-    Mom<NV> ms;
-    ms.u[0] = side ? ru0 : lu0;
-    ms.u[1] = side ? ru1 : lu1;
-    fill_moments<NV>(ms, ps, K);
-    const double irs = 1.0 / ps.rho;
-    double wv[NV], as[NV], bs[NV], As[NV], Ws_t[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) wv[v] = ns[v] * irs;
-    micro_slope<NV>(ps, K, wv, as);
-    jac_x<NV>(Ws, ps, ns, g, Ws_t);
-    if constexpr (NV == 4) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) wv[v] = ts[v] * irs;
-      micro_slope<NV>(ps, K, wv, bs);
-      jac_y(Ws, *reinterpret_cast<const Prim<4>*>(&ps), ts, g, tmp);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Ws_t[v] = -(Ws_t[v] + tmp[v]) * irs;
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Ws_t[v] = -Ws_t[v] * irs;
-    }
-    micro_slope<NV>(ps, K, Ws_t, As);
-    double U1[NV], Xs[NV], Ys[NV], P0[NV], Zs[NV], A0[NV];
-    mom_psi<NV>(ms, 1, 0, 0, U1);   // <u psi>
-    mom_a<NV>(ms, as, 2, 0, Xs);    // <u^2 (a.psi) psi>
-    mom_a<NV>(ms, As, 1, 0, Ys);    // <u (A.psi) psi>
-    mom_psi<NV>(ms, 0, 0, 0, P0);   // <psi>
-    mom_a<NV>(ms, as, 1, 0, Zs);    // <u (a.psi) psi>
-    mom_a<NV>(ms, As, 0, 0, A0);    // <(A.psi) psi>
-    if constexpr (NV == 4) {
-      mom_a<NV>(ms, bs, 1, 1, tmp);  // <u v (b.psi) psi>
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Xs[v] += tmp[v];
-      mom_a<NV>(ms, bs, 0, 1, tmp);  // <v (b.psi) psi>
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Zs[v] += tmp[v];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double r = ps.rho;
-      if (want_F) F[v] += w * r * (f4 * U1[v] - f5 * Xs[v] - f6 * Ys[v]);
-      Ft[v] += w * r * (g4 * U1[v] - g5 * Xs[v] - g6 * Ys[v]);
-      Wi[v] += w * eh * r * (P0[v] - k4 * Zs[v] - tau * A0[v]);
-    }
-  }
+  return slow;
 }
 
 }  // namespace gks

@@ -1,0 +1,168 @@
+// Floating-point operation counts of the device functions, obtained by
+// executing the same templates on the host with a counting scalar type.
+//
+// Convention: every add, subtract, multiply, divide and square root counts
+// one operation, and so does each call of an elementary function (exp,
+// expm1, erfc, tanh); negation, absolute value, min/max and comparisons are
+// not counted. The counts are those of the formulas as the kernels evaluate
+// them (constants folded at compile time are not counted).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "geno_device.hpp"
+#include "geno_gks.h"
+#include "gks_device.hpp"
+
+namespace opcount {
+
+long long g_ops = 0;
+
+// counting double
+struct C {
+  double v;
+  C() : v(0.0) {}
+  C(double x) : v(x) {}  // NOLINT: implicit from constants
+  explicit operator double() const { return v; }
+};
+
+inline C operator+(C a, C b) { ++g_ops; return C(a.v + b.v); }
+inline C operator-(C a, C b) { ++g_ops; return C(a.v - b.v); }
+inline C operator*(C a, C b) { ++g_ops; return C(a.v * b.v); }
+inline C operator/(C a, C b) { ++g_ops; return C(a.v / b.v); }
+inline C operator-(C a) { return C(-a.v); }
+inline bool operator>(C a, C b) { return a.v > b.v; }
+inline bool operator<(C a, C b) { return a.v < b.v; }
+inline bool operator==(C a, C b) { return a.v == b.v; }
+inline C sqrt(C a) { ++g_ops; return C(std::sqrt(a.v)); }
+inline C exp(C a) { ++g_ops; return C(std::exp(a.v)); }
+inline C expm1(C a) { ++g_ops; return C(std::expm1(a.v)); }
+inline C erfc(C a) { ++g_ops; return C(std::erfc(a.v)); }
+inline C tanh(C a) { ++g_ops; return C(std::tanh(a.v)); }
+inline C fabs(C a) { return C(std::fabs(a.v)); }
+inline C fmax(C a, C b) { return C(std::fmax(a.v, b.v)); }
+inline C fmin(C a, C b) { return C(std::fmin(a.v, b.v)); }
+inline bool isfinite(C a) { return std::isfinite(a.v); }
+
+template <typename F>
+long long count(F f) {
+  g_ops = 0;
+  f();
+  return g_ops;
+}
+
+geno::KParams params(int ndim, double gamma) {
+  geno::KParams k;
+  k.C = 20.0;
+  k.tanhC = std::tanh(20.0);
+  k.eps = 1e-15;
+  k.d1 = 1.0;
+  k.d2 = 8.0;
+  k.d3 = 1.0;
+  k.gamma = gamma;
+  k.K = ndim == 1 ? (3.0 - gamma) / (gamma - 1.0) : (4.0 - 2.0 * gamma) / (gamma - 1.0);
+  k.tc1 = 0.0;
+  k.tc2 = 1.0;
+  k.cfl = 0.5;
+  return k;
+}
+
+}  // namespace opcount
+
+int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* costs) {
+  using opcount::C;
+  using opcount::count;
+  const geno::KParams k = opcount::params(ndim, gamma);
+  for (int i = 0; i < nkinds * nclass; ++i) costs[i] = 0.0;
+  auto set = [&](int kind, int cls, double v) {
+    if (kind < nkinds && cls < nclass) costs[kind * nclass + cls] = v;
+  };
+  // normal GENO: linear part per variable and face, one side on its two branches
+  const long long lin = count([&] {
+    C qH, hqH;
+    geno::linear_p7<C>(1.0, 1.1, 1.2, 1.3, 0.1, 0.1, 0.1, 0.1, qH, hqH);
+  });
+  const long long side_hi = count([&] {   // linear data: IS_tau = 0, chi = 1 without tanh
+    C v, d, x;
+    geno::geno_side<C, C>(1.0, 1.1, 1.2, 1.3, 0.1, 1.15, 0.1, k, v, d, x);
+  });
+  const long long side_lo = count([&] {   // a step: chi < 1, low-order part formed
+    C v, d, x;
+    geno::geno_side<C, C>(0.0, 0.0, 1.0, 1.0, 0.0, 0.5, 0.0, k, v, d, x);
+  });
+  const long long tan_hi = count([&] {
+    C v0, v1, t0, t1;
+    geno::tangential<C, C>(1.0, 1.1, 1.2, k, v0, v1, t0, t1);
+  });
+  const long long tan_lo = count([&] {
+    C v0, v1, t0, t1;
+    geno::tangential<C, C>(0.0, 0.0, 1.0, k, v0, v1, t0, t1);
+  });
+  const int nv = ndim == 2 ? 4 : 3;
+  const long long adm = count([&] {
+    C w[4] = {1.0, 0.1, 0.2, 2.5};
+    if (nv == 4) (void)geno::admissible<4, C>(w, gamma);
+    else (void)geno::admissible<3, C>(w, gamma);
+  });
+  // gas-kinetic point: tau = 0 (equal pressures) and tau > 0
+  long long pfast = 0, pslow = 0;
+  if (ndim == 2) {
+    C Wl[4] = {1.0, 0.2, -0.1, 2.6}, Wr[4] = {1.0, 0.2, -0.1, 2.6};
+    C Wr2[4] = {0.8, 0.1, 0.1, 2.0};
+    C n[4] = {0.1, 0.2, 0.3, 0.4}, t[4] = {0.2, 0.1, 0.0, -0.1};
+    pfast = count([&] {
+      C F[4], Ft[4], Wi[4];
+      gks::point_flux<4, true, C>(Wl, Wr, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
+    });
+    pslow = count([&] {
+      C F[4], Ft[4], Wi[4];
+      gks::point_flux<4, true, C>(Wl, Wr2, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
+    });
+  } else {
+    C Wl[3] = {1.0, 0.2, 2.6}, Wr[3] = {1.0, 0.2, 2.6}, Wr2[3] = {0.8, 0.1, 2.0};
+    C n[3] = {0.1, 0.2, 0.3};
+    pfast = count([&] {
+      C F[3], Ft[3], Wi[3];
+      gks::point_flux<3, true, C>(Wl, Wr, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
+                                  Ft, Wi);
+    });
+    pslow = count([&] {
+      C F[3], Ft[3], Wi[3];
+      gks::point_flux<3, true, C>(Wl, Wr2, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
+                                  Ft, Wi);
+    });
+  }
+  if (ndim == 2) {
+    // face-row: 4 variables x (h*gradient scaling 4 + linear part + two sides)
+    const double row = 4.0 * (4 + lin + 2 * side_hi);
+    for (int kind : {GENO_K_NORMAL_X, GENO_K_NORMAL_Y}) {
+      set(kind, GENO_W_UNITS, row);
+      set(kind, GENO_W_LOW, (double)(side_lo - side_hi));
+    }
+    // face: 8 tangential steps, 4 guard checks, derivative scaling (2 points x
+    // 3 arrays x 2 sides x 4 variables, of which the two h*d/dn arrays per
+    // point) and the Gauss average (12 additions)
+    const double face = 8.0 * tan_hi + 4.0 * adm + 2.0 * 16.0 + 12.0;
+    for (int kind : {GENO_K_FACES_X, GENO_K_FACES_Y, GENO_K_SLOW_X, GENO_K_SLOW_Y}) {
+      set(kind, GENO_W_UNITS, face);
+      set(kind, GENO_W_LOW, (double)(tan_lo - tan_hi));
+      set(kind, GENO_W_FAST, (double)pfast);
+      set(kind, GENO_W_SLOW, (double)pslow);
+    }
+    // update per cell and variable: stage 1 L (5), L_t (5), gradients (4),
+    // W* (7), R (6); stage 2 L_t (5), gradients (4), W (4) and the CFL bound
+    set(GENO_K_UPDATE_1, GENO_W_UNITS, 4.0 * 27.0);
+    set(GENO_K_UPDATE_2, GENO_W_UNITS, 4.0 * 13.0 + 17.0);
+    set(GENO_K_INIT, GENO_W_UNITS, 17.0);
+  } else {
+    const double face = 3.0 * (4 + lin + 2 * side_hi) + 2.0 * adm + 6.0;
+    set(GENO_K_FACES_1D, GENO_W_UNITS, face);
+    set(GENO_K_FACES_1D, GENO_W_LOW, (double)(side_lo - side_hi));
+    set(GENO_K_FACES_1D, GENO_W_FAST, (double)pfast);
+    set(GENO_K_FACES_1D, GENO_W_SLOW, (double)pslow);
+    set(GENO_K_UPDATE_1, GENO_W_UNITS, 3.0 * 19.0);
+    set(GENO_K_UPDATE_2, GENO_W_UNITS, 3.0 * 8.0 + 11.0);
+    set(GENO_K_INIT, GENO_W_UNITS, 11.0);
+  }
+  return 0;
+}

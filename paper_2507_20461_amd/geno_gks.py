@@ -44,9 +44,11 @@ class geno_stats(ctypes.Structure):
 
 EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_grid_init",
            "geno_state_elems", "gks_workspace_bytes", "geno_reconstruct", "gks_flux", "gks_step",
-           "geno_timing_enable", "geno_timing_read", "geno_kernel_name")
-KERNELS = ("ghost_x", "ghost_y", "normal_x", "normal_y", "faces_x", "faces_y", "update_1", "update_2",
-           "dt_init", "faces_1d")
+           "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
+           "geno_kernel_name")
+KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow_x", "slow_y", "update_1", "update_2",
+           "faces_1d")
+WORK_CLASSES = ("units", "tanh", "low", "fast", "slow", "guard")
 
 _lib = None
 
@@ -79,11 +81,15 @@ def lib():
         L.gks_step.argtypes = [ctypes.POINTER(geno_grid), vp, vp, vp, i, vp,
                                ctypes.POINTER(geno_stats), vp]
         L.geno_timing_enable.argtypes = [i]
+        L.geno_count_enable.argtypes = [i]
         L.geno_timing_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
         L.geno_kernel_name.argtypes = [i]
         L.geno_kernel_name.restype = ctypes.c_char_p
+        L.geno_work_read.argtypes = [ctypes.POINTER(geno_grid), vp, i, i, ctypes.POINTER(ctypes.c_longlong), vp]
+        L.geno_op_costs.argtypes = [ctypes.POINTER(geno_grid), i, i, ctypes.POINTER(ctypes.c_double)]
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
-                     "geno_timing_enable", "geno_timing_read"):
+                     "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
+                     "geno_op_costs"):
             getattr(L, name).restype = i
         if L.geno_abi_version() != ABI_VERSION:
             raise RuntimeError("library ABI %d != binding ABI %d" % (L.geno_abi_version(), ABI_VERSION))
@@ -202,6 +208,10 @@ def timing_enable(max_launches):
     _check(lib().geno_timing_enable(int(max_launches)))
 
 
+def count_enable(on=True):
+    _check(lib().geno_count_enable(1 if on else 0))
+
+
 def timing_read():
     """{kernel name: (total ms, launches)} of the launches recorded since the last read."""
     n = len(KERNELS)
@@ -209,3 +219,19 @@ def timing_read():
     cnt = (ctypes.c_longlong * n)()
     _check(lib().geno_timing_read(n, ms, cnt))
     return {lib().geno_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
+
+
+def work_read(grid, ws, stream=None):
+    """{kernel: {class: count}} counted during the last gks_step on ws (timing enabled)."""
+    nk, nc = len(KERNELS), len(WORK_CLASSES)
+    out = (ctypes.c_longlong * (nk * nc))()
+    _check(lib().geno_work_read(ctypes.byref(grid.g), _ptr(ws), nk, nc, out, _stream(stream)))
+    return {KERNELS[a]: {WORK_CLASSES[c]: out[a * nc + c] for c in range(nc)} for a in range(nk)}
+
+
+def op_costs(grid):
+    """{kernel: {class: floating-point operations per counted item}} (host-side count)."""
+    nk, nc = len(KERNELS), len(WORK_CLASSES)
+    out = (ctypes.c_double * (nk * nc))()
+    _check(lib().geno_op_costs(ctypes.byref(grid.g), nk, nc, out))
+    return {KERNELS[a]: {WORK_CLASSES[c]: out[a * nc + c] for c in range(nc)} for a in range(nk)}
