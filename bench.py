@@ -29,6 +29,12 @@ if ROOT not in sys.path:
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# rocprofv3 kernel names of the measured kernel kinds (2-D path)
+ROCPROF_NAMES = {"init": "k_init<2>", "normal_x": "k_normal2d<0>", "normal_y": "k_normal2d<1>",
+                 "faces_x": "k_faces2d<0, 1>", "faces_y": "k_faces2d<1, 1>", "slow": "k_slow2d",
+                 "update_1": "k_update<2, 1>", "update_2": "k_update<2, 2>"}
+COUNTERS = os.path.join(ROOT, "profiles", "faces_fp64_512_counters.json")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -40,6 +46,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     return ap.parse_args()
+
+
+def traffic(kind, n):
+    """HBM bytes per launch of one kernel from the committed FETCH_SIZE and
+    WRITE_SIZE counter passes, each scaled by the same counter's reading for a
+    256 MiB device copy. None when the counters were taken on other kernel
+    sources or another workload."""
+    from paper_2507_20461_amd import profiling
+    if n != 512 or not os.path.exists(COUNTERS):
+        return None, None
+    meta = json.load(open(COUNTERS))
+    if meta.get("source_hash") != profiling.source_hash():
+        return None, "counters taken on other kernel sources"
+    row = meta["kernels"].get(ROCPROF_NAMES.get(kind, ""))
+    if not row or row.get("fetch_bytes_cal") is None or row.get("write_bytes_cal") is None:
+        return None, None
+    return row["fetch_bytes_cal"] + row["write_bytes_cal"], {
+        "fetch_bytes": round(row["fetch_bytes_cal"]), "write_bytes": round(row["write_bytes_cal"]),
+        "calibration": meta["calibration"], "rocprof_avg_us": meta["ktrace_avg_us"].get(ROCPROF_NAMES[kind]),
+        "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def cpu_baseline(W, dW, n):
@@ -104,24 +130,22 @@ def main():
     kt, work, costs = {}, {}, G.op_costs(grid)
     ms_events = None
     if not args.no_kernel_timing:
-        # 2) the same K steps with HIP events around every launch (on the
-        # stream the kernels run on): per-kernel durations
+        # 2) the same K steps again with start/stop events bound to every
+        # kernel dispatch (on the stream the kernels run on) and per-block
+        # work counting: per-kernel durations and work. The update is
+        # deterministic, so this replay reproduces the timed run exactly.
         restart()
         G.timing_enable(16 * args.steps + 16)
+        G.count_enable(True)
         start.record(stream)
         G.gks_step(grid, Wd, dWd, ws, args.steps)
         end.record(stream)
         torch.cuda.synchronize()
         ms_events = start.elapsed_time(end)
         kt = G.timing_read()
+        work = G.work_read()
         G.timing_enable(0)
-        # 3) untimed replay with work counting (the update is deterministic,
-        # so the counts are those of the timed run)
-        restart()
-        G.count_enable(True)
-        G.gks_step(grid, Wd, dWd, ws, args.steps)
         G.count_enable(False)
-        work = G.work_read(grid, ws)
         assert np.array_equal(grid.interior(Wd), Wend), "replay differs from the timed run"
 
     cell_stages = 2.0 * n * n * args.steps
@@ -140,10 +164,12 @@ def main():
     if dominant:
         d = kernels[dominant]
         achieved = d["tflops"]
+        tbytes, tdetail = traffic(dominant, n)
         roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved,
                     "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 5) if achieved else None,
-                    "traffic": None,
+                    "traffic": round(tbytes) if tbytes else None, "traffic_detail": tdetail,
+                    "hbm_gbs_at_traffic": round(tbytes / (d["us_avg"] * 1e-6) / 1e9, 1) if tbytes else None,
                     "flop_convention": "add/sub/mul/div/sqrt and each exp/expm1/erfc/tanh call = 1 FP64 op",
                     "gflop_per_launch": d["gflop_per_launch"], "us_per_launch": d["us_avg"]}
     out = {

@@ -178,18 +178,18 @@ enum {
   GENO_K_NORMAL_Y,     /* normal GENO on y-face columns */
   GENO_K_FACES_X,      /* tangential step + gas-kinetic flux, x-faces with tau = 0 */
   GENO_K_FACES_Y,
-  GENO_K_SLOW_X,       /* the same for the x-faces queued with tau > 0 */
-  GENO_K_SLOW_Y,
+  GENO_K_SLOW,         /* the same for the faces of both directions queued with
+                          tau > 0 at a Gauss point (full BGK solution) */
   GENO_K_UPDATE_1,     /* stage-1 update, gradients, ghost cells of the stage state */
   GENO_K_UPDATE_2,     /* stage-2 update, gradients, ghost cells, CFL partial minima */
   GENO_K_FACES_1D,     /* 1-D: GENO + flux per face */
   GENO_NKERNELS
 };
 
-/* Work classes counted per kernel kind while timing is enabled. */
+/* Work classes counted per kernel kind while counting is enabled. */
 enum {
-  GENO_W_UNITS = 0,    /* threads' work units: face-rows, faces, cells */
-  GENO_W_TANH,         /* path-function evaluations that call tanh */
+  GENO_W_UNITS = 0,    /* threads' work units: face-row variables, faces, cells */
+  GENO_W_TANH,         /* reserved (not counted) */
   GENO_W_LOW,          /* reconstructions that form the low-order part (chi < 1) */
   GENO_W_FAST,         /* gas-kinetic points evaluated with tau = 0 */
   GENO_W_SLOW,         /* gas-kinetic points evaluated with tau > 0 */
@@ -197,15 +197,18 @@ enum {
   GENO_NCLASS
 };
 
-/* Enables per-kernel timing in gks_step: HIP events are recorded on the
- * call's stream around each of its first max_launches launches (events are
- * created here, once; 0 disables and releases them). Not thread-safe:
- * intended for benchmarks. */
+/* Enables per-kernel timing in gks_step: each of the next max_launches
+ * launches is made with a start and a stop event bound to the kernel's own
+ * dispatch (hipExtLaunchKernel), so the recorded interval is the kernel's
+ * execution, not the queue around it. Events are created here, once; 0
+ * disables and releases them. Not thread-safe: intended for benchmarks. */
 int geno_timing_enable(int max_launches);
 
 /* Enables (on != 0) or disables counting of the work classes in gks_step.
- * Counting adds one atomic per wave and class, so it is meant for a separate,
- * untimed replay of a timed run (the update is deterministic). */
+ * Each work-group adds its sums to its own slot of a device buffer (no
+ * atomics), so counting hardly changes kernel durations; the buffer is
+ * allocated on the current device by the first counted gks_step call and
+ * cleared at the start of every counted call. Not thread-safe. */
 int geno_count_enable(int on);
 
 /* Waits for the recorded events, writes per kernel kind the summed duration
@@ -213,11 +216,9 @@ int geno_count_enable(int on);
  * starts a new recording. */
 int geno_timing_read(int nkinds, double* ms_total, long long* launches);
 
-/* Work counts of the last gks_step call on workspace ws (counted only while
- * counting is enabled): counts[kind * nclass + class], host array. Waits for
- * the stream. */
-int geno_work_read(const geno_grid* g, const void* ws, int nkinds, int nclass, long long* counts,
-                   void* stream);
+/* Work counts of the last counted gks_step call: counts[kind * nclass +
+ * class], host array (zeros if none). Waits for the stream. */
+int geno_work_read(int nkinds, int nclass, long long* counts, void* stream);
 
 /* Floating-point operations per work item of each class and kernel kind, as
  * executed by the device functions (add, sub, mul, div, sqrt, compare-free;

@@ -7,12 +7,13 @@
 //   faces<d>    two lanes per face, one per Gauss point: tangential step,
 //               positivity guard and the gas-kinetic flux for tau = 0; faces
 //               with tau > 0 at either point go to a queue
-//   slow<d>     the queued faces with the full BGK solution (tau > 0)
-// then update<stage>: Eq. (1) with the S2O4 stage, the gradients by Eq. (2),
+// then slow: the queued faces of both directions with the full BGK solution
+// (tau > 0), and update<stage>: Eq. (1) with the S2O4 stage, the gradients by Eq. (2),
 // the ghost cells of the new state (every interior cell writes its ghost
 // images) and, in stage 2, per-block CFL minima for the next step, reduced
 // by the next step's first kernel. The time step therefore never leaves the
 // device and a run of steps never waits for the host.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
 
 #include "geno_device.hpp"
 #include "geno_gks.h"
@@ -50,8 +52,8 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// Optional per-kernel timing: events recorded around every launch of
-// gks_step while enabled (measurement support; not thread-safe).
+// Optional per-kernel timing: start/stop events bound to the dispatch of each
+// launch of gks_step while enabled (measurement support; not thread-safe).
 // ---------------------------------------------------------------------------
 struct Timing {
   hipEvent_t* ev = nullptr;
@@ -59,23 +61,68 @@ struct Timing {
   int cap = 0, used = 0;
 };
 Timing g_tim;
-int g_count = 0;   // work counting in gks_step (geno_count_enable)
 
-const char* const KNAMES[GENO_NKERNELS] = {"init",   "normal_x", "normal_y", "faces_x",
-                                           "faces_y", "slow_x",  "slow_y",   "update_1",
-                                           "update_2", "faces_1d"};
+const char* const KNAMES[GENO_NKERNELS] = {"init",    "normal_x", "normal_y", "faces_x", "faces_y",
+                                           "slow",    "update_1", "update_2", "faces_1d"};
 
-inline void tim_begin(int kind, hipStream_t s) {
-  if (g_tim.used < g_tim.cap) {
-    g_tim.kind[g_tim.used] = kind;
-    hipEventRecord(g_tim.ev[2 * g_tim.used], s);
+// Every launch goes through here: a kernel of kind >= 0 is timed while
+// timing is enabled (events bound to the dispatch itself).
+template <typename... KArgs, typename... Args>
+hipError_t launch(int kind, void (*kern)(KArgs...), unsigned grid, hipStream_t s, Args&&... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kind >= 0 && g_tim.used < g_tim.cap) {
+    const int u = g_tim.used++;
+    g_tim.kind[u] = kind;
+    e0 = g_tim.ev[2 * u];
+    e1 = g_tim.ev[2 * u + 1];
+  }
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), 0, s, e0, e1, 0, std::forward<Args>(args)...);
+  return hipGetLastError();
+}
+
+// Work counting: per-block sums of the work classes, [kind][class][cap]
+// slots, one slot per work-group of a launch (no atomics). p == nullptr when
+// counting is off.
+struct Cnt {
+  unsigned long long* p;
+  int cap;
+};
+struct CountBuf {
+  unsigned long long* p = nullptr;
+  int cap = 0;
+  int on = 0;
+  int dev = -1;
+};
+CountBuf g_cnt;
+
+__device__ void block_count(const Cnt& c, int kind, const unsigned int (&v)[GENO_NCLASS]) {
+  __shared__ unsigned int red[BLOCK / 64][GENO_NCLASS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < GENO_NCLASS; ++q) {
+    unsigned int x = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[w][q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < GENO_NCLASS) {
+    unsigned long long x = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) x += red[i][threadIdx.x];
+    if (x) c.p[((size_t)kind * GENO_NCLASS + threadIdx.x) * c.cap + blockIdx.x] += x;
   }
 }
-inline void tim_end(hipStream_t s) {
-  if (g_tim.used < g_tim.cap) {
-    hipEventRecord(g_tim.ev[2 * g_tim.used + 1], s);
-    ++g_tim.used;
-  }
+
+// Work-group index remapped so that each of the 8 XCDs (which receive the
+// work-groups of a launch round-robin and each have their own L2) processes
+// one contiguous slab of the index space: neighbouring rows, which share
+// stencil data, then meet in the same L2.
+__device__ __forceinline__ int xcd_block() {
+  constexpr int NXCD = 8;
+  const int nb = (int)gridDim.x, p = (int)blockIdx.x;
+  const int per = nb / NXCD, rem = nb % NXCD, x = p % NXCD;
+  return x * per + min(x, rem) + p / NXCD;
 }
 
 // Geometry passed to the kernels by value.
@@ -95,19 +142,10 @@ struct Ctrl {
   unsigned long long guard;                        // positivity fall-backs
   unsigned long long nonfinite;                    // non-finite cells after a stage-2 update
   unsigned int qcount[2];                          // queued tau > 0 faces per direction
-  unsigned long long work[GENO_NKERNELS][GENO_NCLASS];
 };
 
 __device__ __forceinline__ double dt_of(const Ctrl* c, double cfl) {
   return cfl * __longlong_as_double((long long)c->tmin);
-}
-
-// wave-level sum of a per-lane count, one atomic per wave
-__device__ __forceinline__ void wave_count(unsigned long long* dst, unsigned int x) {
-  unsigned int s = x;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,9 +272,11 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
 }
 
 // ---------------------------------------------------------------------------
-// Normal GENO on face-rows (2-D). DIR 0: rows a = 0..ny+1 (j = a-1), faces
-// b = 0..nx (between cells b-1 and b). DIR 1: faces a = 0..ny (between rows
-// a-1 and a), columns b = 0..nx+1 (i = b-1).
+// Normal GENO on face-rows (2-D), one thread per (variable, face-row entry).
+// DIR 0: rows a = 0..ny+1 (j = a-1), faces b = 0..nx (between cells b-1 and
+// b). DIR 1: faces a = 0..ny (between rows a-1 and a), columns b = 0..nx+1
+// (i = b-1). Thread index (v, a, b) with b fastest, so that a wave reads and
+// writes 64 consecutive entries of one plane.
 // fr: [side][quant(value, h d/dn)][var][a][b]; chi: [side][var][a][b].
 // With part (first kernel of a step), block 0 also reduces the CFL partial
 // minima of the previous kernel into ctrl->tmin and records dt.
@@ -248,46 +288,44 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                                                     double* __restrict__ fr,
                                                     double* __restrict__ chi, Ctrl* ctrl,
                                                     const double* __restrict__ part, int npart,
-                                                    double* dt_out, int step, int count) {
+                                                    double* dt_out, int step, Cnt cnt) {
   if (part && blockIdx.x == 0) reduce_dt(part, npart, ctrl, k.cfl, dt_out, step);
   if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) ctrl->qcount[DIR] = 0;
   const int n1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
   const int n0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = n0 * n1;
+  const int t = xcd_block() * BLOCK + threadIdx.x;
   unsigned int nlow = 0;
-  if (t < n0 * n1) {
-    const int a = t / n1, b = t % n1;
-    const size_t plane = (size_t)n0 * n1;
-    const size_t o = (size_t)a * n1 + b;
+  if (t < 4 * plane) {
+    const int v = t / plane, o = t - v * plane;
+    const int a = o / n1, b = o - a * n1;
     const double h = DIR == 0 ? g.dx : g.dy;
+    double Q[4], G[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double Q[4], G[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        size_t id;
-        if (DIR == 0) id = at(g, v, a - 1, b - 2 + m);
-        else id = at(g, v, a - 2 + m, b - 1);
-        Q[m] = W[id];
-        G[m] = h * dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
-      }
-      double vl, dl, xl, vr, dr, xr;
-      nlow += geno::geno_face<double, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
-                                              vl, dl, xl, vr, dr, xr);
-      fr[(size_t)(0 * 4 + v) * plane + o] = vl;
-      fr[(size_t)(1 * 4 + v) * plane + o] = dl;
-      fr[(size_t)(2 * 4 + v) * plane + o] = vr;
-      fr[(size_t)(3 * 4 + v) * plane + o] = dr;
-      if (chi) {
-        chi[(size_t)(0 * 4 + v) * plane + o] = xl;
-        chi[(size_t)(1 * 4 + v) * plane + o] = xr;
-      }
+    for (int m = 0; m < 4; ++m) {
+      size_t id;
+      if (DIR == 0) id = at(g, v, a - 1, b - 2 + m);
+      else id = at(g, v, a - 2 + m, b - 1);
+      Q[m] = W[id];
+      G[m] = h * dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+    }
+    double vl, dl, xl, vr, dr, xr;
+    nlow = geno::geno_face<double, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl,
+                                           dl, xl, vr, dr, xr);
+    fr[(size_t)(0 * 4 + v) * plane + o] = vl;
+    fr[(size_t)(1 * 4 + v) * plane + o] = dl;
+    fr[(size_t)(2 * 4 + v) * plane + o] = vr;
+    fr[(size_t)(3 * 4 + v) * plane + o] = dr;
+    if (chi) {
+      chi[(size_t)(0 * 4 + v) * plane + o] = xl;
+      chi[(size_t)(1 * 4 + v) * plane + o] = xr;
     }
   }
-  if (count) {
-    const int kind = DIR == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y;
-    wave_count(&ctrl->work[kind][GENO_W_UNITS], t < n0 * n1 ? 1u : 0u);
-    wave_count(&ctrl->work[kind][GENO_W_LOW], nlow);
+  if (cnt.p) {
+    unsigned int wc[GENO_NCLASS] = {};
+    wc[GENO_W_UNITS] = t < 4 * plane ? 1u : 0u;
+    wc[GENO_W_LOW] = nlow;
+    block_count(cnt, DIR == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y, wc);
   }
 }
 
@@ -315,8 +353,8 @@ template <int DIR, int MODE>
 __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
                                           const double* __restrict__ W,
                                           const double* __restrict__ fr, double* __restrict__ out,
-                                          Ctrl* ctrl, int want_F, int count, int face, bool valid,
-                                          unsigned int* __restrict__ queue) {
+                                          Ctrl* ctrl, int want_F, unsigned int (&wc)[GENO_NCLASS],
+                                          int face, bool valid, unsigned int* __restrict__ queue) {
   const FaceGeo<DIR> fg(g);
   const int q = threadIdx.x & 1;
   const int nfaces = fg.n0 * fg.n1;
@@ -450,105 +488,14 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
         }
       }
     }
-    if (count) {
-      const int kind = MODE == 1 ? (DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y)
-                                 : (DIR == 0 ? GENO_K_SLOW_X : GENO_K_SLOW_Y);
-      const bool ev = valid && !pair_slow;   // this lane's point was evaluated here
-      wave_count(&ctrl->work[kind][GENO_W_UNITS], (ev && q == 0) ? 1u : 0u);
-      wave_count(&ctrl->work[kind][GENO_W_FAST], (ev && !slow) ? 1u : 0u);
-      wave_count(&ctrl->work[kind][GENO_W_SLOW], (ev && slow) ? 1u : 0u);
-      wave_count(&ctrl->work[kind][GENO_W_LOW], ev ? nlow : 0u);
-      wave_count(&ctrl->work[kind][GENO_W_GUARD], ev ? nguard : 0u);
-    }
-  }
-}
-
-// One thread per queued face (tau > 0 at one of its points): tangential
-// step of both sides, guard, and the full solution at both Gauss points. No
-// cross-lane exchange, so register spills of this heavy path stay local.
-template <int DIR>
-__device__ __forceinline__ void face_full(const Geo& g, const geno::KParams& k,
-                                          const double* __restrict__ W,
-                                          const double* __restrict__ fr, double* __restrict__ out,
-                                          Ctrl* ctrl, int want_F, int count, int face) {
-  const FaceGeo<DIR> fg(g);
-  const int a = face / fg.n1, b = face % fg.n1;
-  const size_t rplane = (size_t)fg.r0 * fg.r1;
-  const size_t rm = (size_t)a * fg.r1 + b;
-  const size_t rc = DIR == 0 ? rm + fg.r1 : rm + 1;
-  const size_t rp = DIR == 0 ? rc + fg.r1 : rc + 1;
-  const double dt = dt_of(ctrl, k.cfl);
-  const double hn = DIR == 0 ? g.dx : g.dy, ht = DIR == 0 ? g.dy : g.dx;
-  const double ihn = 1.0 / hn, iht = 1.0 / ht;
-  constexpr int p1 = DIR == 0 ? 1 : 2, p2 = DIR == 0 ? 2 : 1;
-  constexpr int perm[4] = {0, p1, p2, 3};
-  double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
-  unsigned int nlow = 0, nguard = 0, nfast = 0, nslow = 0;
-#pragma unroll 1
-  for (int q = 0; q < 2; ++q) {
-    double S[2][4], Dn[2][4], Dt[2][4];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double* p = fr + (size_t)((2 * s + 0) * 4 + v) * rplane;
-        double v0, v1, t0, t1;
-        nlow += geno::tangential<double, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1);
-        S[s][v] = q ? v1 : v0;
-        Dt[s][v] = q ? t1 : t0;
-        Dn[s][v] = fr[(size_t)((2 * s + 1) * 4 + v) * rplane + rc];
-      }
-      if (!geno::admissible<4, double>(S[s], k.gamma)) {
-        ++nguard;
-        const int ci = DIR == 0 ? b - 1 + s : b;
-        const int cj = DIR == 0 ? a : a - 1 + s;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          S[s][v] = W[at(g, v, cj, ci)];
-          Dn[s][v] = 0.0;
-          Dt[s][v] = 0.0;
-        }
-      }
-    }
-    double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Wl[v] = S[0][perm[v]];
-      Wr[v] = S[1][perm[v]];
-      nl[v] = Dn[0][perm[v]] * ihn;
-      nr[v] = Dn[1][perm[v]] * ihn;
-      tl[v] = Dt[0][perm[v]] * iht;
-      tr[v] = Dt[1][perm[v]] * iht;
-    }
-    double Fq[4] = {0, 0, 0, 0}, Ftq[4] = {0, 0, 0, 0}, Wiq[4] = {0, 0, 0, 0};
-    const bool sl = gks::point_flux<4, true, double>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5,
-                                                     want_F != 0, Fq, Ftq, Wiq);
-    nslow += sl ? 1u : 0u;
-    nfast += sl ? 0u : 1u;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      F[v] += Fq[v];
-      Ft[v] += Ftq[v];
-      Wi[v] += Wiq[v];
-    }
-  }
-  if (nguard) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
-  const size_t plane = (size_t)fg.n0 * fg.n1;
-  const size_t o = (size_t)face;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int pv = perm[v];
-    if (want_F) out[(size_t)(0 * 4 + pv) * plane + o] = F[v];
-    out[(size_t)(1 * 4 + pv) * plane + o] = Ft[v];
-    out[(size_t)(2 * 4 + pv) * plane + o] = Wi[v];
-  }
-  if (count) {
-    const int kind = DIR == 0 ? GENO_K_SLOW_X : GENO_K_SLOW_Y;
-    atomicAdd(&ctrl->work[kind][GENO_W_UNITS], 1ull);
-    atomicAdd(&ctrl->work[kind][GENO_W_FAST], (unsigned long long)nfast);
-    atomicAdd(&ctrl->work[kind][GENO_W_SLOW], (unsigned long long)nslow);
-    atomicAdd(&ctrl->work[kind][GENO_W_LOW], (unsigned long long)nlow);
-    if (nguard) atomicAdd(&ctrl->work[kind][GENO_W_GUARD], (unsigned long long)nguard);
+    // work classes of this lane (a pair queued for the full solution is
+    // counted where it is evaluated)
+    const bool ev = valid && !pair_slow;
+    wc[GENO_W_UNITS] += (ev && q == 0) ? 1u : 0u;
+    wc[GENO_W_FAST] += (ev && !slow) ? 1u : 0u;
+    wc[GENO_W_SLOW] += (ev && slow) ? 1u : 0u;
+    wc[GENO_W_LOW] += ev ? nlow : 0u;
+    wc[GENO_W_GUARD] += ev ? nguard : 0u;
   }
 }
 
@@ -557,21 +504,42 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
                                                    const double* __restrict__ W,
                                                    const double* __restrict__ fr,
                                                    double* __restrict__ out, Ctrl* ctrl,
-                                                   int want_F, int count,
+                                                   int want_F, Cnt cnt,
                                                    unsigned int* __restrict__ queue) {
   const FaceGeo<DIR> fg(g);
   const int nfaces = fg.n0 * fg.n1;
-  if constexpr (MODE == 2) {
-    // grid-stride over the queue, one thread per face
-    const unsigned int nq = ctrl->qcount[DIR];
-    const unsigned int stride = gridDim.x * blockDim.x;
-    for (unsigned int e = blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += stride)
-      face_full<DIR>(g, k, W, fr, out, ctrl, want_F, count, (int)queue[e]);
-  } else {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int face = t >> 1;
-    face_pair<DIR, MODE>(g, k, W, fr, out, ctrl, want_F, count, face, face < nfaces, queue);
+  const int t = xcd_block() * BLOCK + threadIdx.x;
+  const int face = t >> 1;
+  unsigned int wc[GENO_NCLASS] = {};
+  face_pair<DIR, MODE>(g, k, W, fr, out, ctrl, want_F, wc, face, face < nfaces, queue);
+  if (MODE == 1 && cnt.p) block_count(cnt, DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, wc);
+}
+
+// The faces of both directions queued by k_faces2d<DIR, 1> (tau > 0 at one
+// of their Gauss points), with the full solution: lane pairs as there,
+// grid-stride over the pairs; pairs [0, nqx) are x-faces, the rest y-faces.
+// Both lanes of a pair always take the same branch and trip count, so each
+// cross-lane read finds its partner active.
+__global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
+                                                  const double* __restrict__ W,
+                                                  const double* __restrict__ frx,
+                                                  const double* __restrict__ fry,
+                                                  double* __restrict__ outx,
+                                                  double* __restrict__ outy, Ctrl* ctrl,
+                                                  int want_F, Cnt cnt,
+                                                  const unsigned int* __restrict__ qx,
+                                                  const unsigned int* __restrict__ qy) {
+  const unsigned int nqx = ctrl->qcount[0];
+  const unsigned int nq = nqx + ctrl->qcount[1];
+  const unsigned int stride = gridDim.x * blockDim.x / 2;
+  unsigned int wc[GENO_NCLASS] = {};
+  for (unsigned int e = (blockIdx.x * blockDim.x + threadIdx.x) >> 1; e < nq; e += stride) {
+    if (e < nqx)
+      face_pair<0, 2>(g, k, W, frx, outx, ctrl, want_F, wc, (int)qx[e], true, nullptr);
+    else
+      face_pair<1, 2>(g, k, W, fry, outy, ctrl, want_F, wc, (int)qy[e - nqx], true, nullptr);
   }
+  if (cnt.p) block_count(cnt, GENO_K_SLOW, wc);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,7 +554,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
                                                    const double* __restrict__ dW,
                                                    double* __restrict__ out,
                                                    double* __restrict__ chi, Ctrl* ctrl,
-                                                   int want_F, int count) {
+                                                   int want_F, Cnt cnt) {
   const int nfc = g.nx + 1;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned int nlow = 0, nguard = 0, nslow = 0;
@@ -650,12 +618,14 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
       }
     }
   }
-  if (count && MODE == 1) {
-    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_UNITS], f < nfc ? 1u : 0u);
-    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_LOW], nlow);
-    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_FAST], (f < nfc && !nslow) ? 1u : 0u);
-    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_SLOW], nslow);
-    wave_count(&ctrl->work[GENO_K_FACES_1D][GENO_W_GUARD], nguard);
+  if (MODE == 1 && cnt.p) {
+    unsigned int wc[GENO_NCLASS] = {};
+    wc[GENO_W_UNITS] = f < nfc ? 1u : 0u;
+    wc[GENO_W_LOW] = nlow;
+    wc[GENO_W_FAST] = (f < nfc && !nslow) ? 1u : 0u;
+    wc[GENO_W_SLOW] = nslow;
+    wc[GENO_W_GUARD] = nguard;
+    block_count(cnt, GENO_K_FACES_1D, wc);
   }
 }
 
@@ -719,9 +689,9 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
                                                   double* __restrict__ R,
                                                   const double* __restrict__ fx,
                                                   const double* __restrict__ fy, Ctrl* ctrl,
-                                                  double* __restrict__ part, int count) {
+                                                  double* __restrict__ part, Cnt cnt) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * BLOCK + threadIdx.x;
   const int n = g.nx * g.ny;
   const double dt = dt_of(ctrl, k.cfl);
   double tloc = INFINITY;
@@ -765,9 +735,11 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
     }
   }
   if constexpr (STAGE == 2) block_min(tloc, part);
-  if (count)
-    wave_count(&ctrl->work[STAGE == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2][GENO_W_UNITS],
-               t < n ? 1u : 0u);
+  if (cnt.p) {
+    unsigned int wc[GENO_NCLASS] = {};
+    wc[GENO_W_UNITS] = t < n ? 1u : 0u;
+    block_count(cnt, STAGE == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2, wc);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -922,84 +894,78 @@ Bufs bufs_of(char* ws, const Layout& L, int ndim) {
 int launch_init(const geno_grid* g, const Geo& geo, double gamma, double* W, double* dW,
                 const Bufs& B, hipStream_t s) {
   const size_t n = (size_t)g->nx * g->ny;
-  tim_begin(GENO_K_INIT, s);
   if (g->ndim == 2)
-    hipLaunchKernelGGL(k_init<2>, dim3(nblocks(n)), dim3(BLOCK), 0, s, geo, gamma, W, dW, B.part,
-                       B.ctrl);
+    HIP_TRY(launch(GENO_K_INIT, k_init<2>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
   else
-    hipLaunchKernelGGL(k_init<1>, dim3(nblocks(n)), dim3(BLOCK), 0, s, geo, gamma, W, dW, B.part,
-                       B.ctrl);
-  tim_end(s);
-  HIP_TRY(hipGetLastError());
+    HIP_TRY(launch(GENO_K_INIT, k_init<1>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
   return GENO_OK;
+}
+
+// launch sizes of gks_step
+size_t face_rows(const geno_grid* g, int dir) {
+  return dir == 0 ? (size_t)(g->ny + 2) * (g->nx + 1) : (size_t)(g->ny + 1) * (g->nx + 2);
+}
+size_t faces_of(const geno_grid* g, int dir) {
+  return dir == 0 ? (size_t)g->ny * (g->nx + 1) : (size_t)(g->ny + 1) * g->nx;
+}
+unsigned slow_blocks(const geno_grid* g) {
+  return (unsigned)std::min<size_t>(SLOW_BLOCKS, nblocks(faces_of(g, 0) + faces_of(g, 1)));
+}
+// the largest grid of a counted launch (slots per kind and class)
+int count_cap(const geno_grid* g) {
+  size_t m = nblocks((size_t)g->nx * g->ny);
+  if (g->ndim == 2) {
+    for (int d = 0; d < 2; ++d) {
+      m = std::max<size_t>(m, nblocks(4 * face_rows(g, d)));
+      m = std::max<size_t>(m, nblocks(2 * faces_of(g, d)));
+    }
+    m = std::max<size_t>(m, slow_blocks(g));
+  } else {
+    m = std::max<size_t>(m, nblocks((size_t)g->nx + 1));
+  }
+  return (int)m;
 }
 
 // one stage of gks_step: faces and update
 int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, const Bufs& B,
                  int npart, double* Win, double* dWin, int stage, double* dt_out, int step,
-                 double* Wfinal, double* dWfinal, int count, hipStream_t s) {
+                 double* Wfinal, double* dWfinal, const Cnt& cnt, hipStream_t s) {
   const int want_F = stage == 1;
   const double* part = stage == 1 ? B.part : nullptr;   // dt of the step is reduced once
   if (g->ndim == 2) {
-    for (int dir = 0; dir < 2; ++dir) {
-      const size_t nrows =
-          dir == 0 ? (size_t)(g->ny + 2) * (g->nx + 1) : (size_t)(g->ny + 1) * (g->nx + 2);
-      const size_t nfaces = dir == 0 ? (size_t)g->ny * (g->nx + 1) : (size_t)(g->ny + 1) * g->nx;
-      tim_begin(dir == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y, s);
-      if (dir == 0)
-        hipLaunchKernelGGL(k_normal2d<0>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Win,
-                           dWin, B.fr[0], nullptr, B.ctrl, part, npart, dt_out, step, count);
-      else
-        hipLaunchKernelGGL(k_normal2d<1>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Win,
-                           dWin, B.fr[1], nullptr, B.ctrl, nullptr, 0, nullptr, 0, count);
-      tim_end(s);
-      tim_begin(dir == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, s);
-      if (dir == 0)
-        hipLaunchKernelGGL((k_faces2d<0, 1>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo,
-                           k, Win, B.fr[0], B.fl[0], B.ctrl, want_F, count, B.queue[0]);
-      else
-        hipLaunchKernelGGL((k_faces2d<1, 1>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo,
-                           k, Win, B.fr[1], B.fl[1], B.ctrl, want_F, count, B.queue[1]);
-      tim_end(s);
-      const unsigned sb = (unsigned)std::min<size_t>(SLOW_BLOCKS, nblocks(nfaces));
-      tim_begin(dir == 0 ? GENO_K_SLOW_X : GENO_K_SLOW_Y, s);
-      if (dir == 0)
-        hipLaunchKernelGGL((k_faces2d<0, 2>), dim3(sb), dim3(BLOCK), 0, s, geo, k, Win, B.fr[0],
-                           B.fl[0], B.ctrl, want_F, count, B.queue[0]);
-      else
-        hipLaunchKernelGGL((k_faces2d<1, 2>), dim3(sb), dim3(BLOCK), 0, s, geo, k, Win, B.fr[1],
-                           B.fl[1], B.ctrl, want_F, count, B.queue[1]);
-      tim_end(s);
-    }
+    HIP_TRY(launch(GENO_K_NORMAL_X, k_normal2d<0>, nblocks(4 * face_rows(g, 0)), s, geo, k, Win,
+                   dWin, B.fr[0], nullptr, B.ctrl, part, npart, dt_out, step, cnt));
+    HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
+                   B.fr[0], B.fl[0], B.ctrl, want_F, cnt, B.queue[0]));
+    HIP_TRY(launch(GENO_K_NORMAL_Y, k_normal2d<1>, nblocks(4 * face_rows(g, 1)), s, geo, k, Win,
+                   dWin, B.fr[1], nullptr, B.ctrl, nullptr, 0, nullptr, 0, cnt));
+    HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
+                   B.fr[1], B.fl[1], B.ctrl, want_F, cnt, B.queue[1]));
+    HIP_TRY(launch(GENO_K_SLOW, k_slow2d, slow_blocks(g), s, geo, k, Win, B.fr[0], B.fr[1],
+                   B.fl[0], B.fl[1], B.ctrl, want_F, cnt, B.queue[0], B.queue[1]));
   } else {
-    if (part) {
-      hipLaunchKernelGGL(k_dt1d, dim3(1), dim3(BLOCK), 0, s, B.part, npart, B.ctrl, k.cfl, dt_out,
-                         step);
-    }
-    tim_begin(GENO_K_FACES_1D, s);
-    hipLaunchKernelGGL(k_faces1d<1>, dim3(nblocks((size_t)g->nx + 1)), dim3(BLOCK), 0, s, geo, k,
-                       Win, dWin, B.fl[0], nullptr, B.ctrl, want_F, count);
-    tim_end(s);
+    if (part) HIP_TRY(launch(-1, k_dt1d, 1, s, B.part, npart, B.ctrl, k.cfl, dt_out, step));
+    HIP_TRY(launch(GENO_K_FACES_1D, k_faces1d<1>, nblocks((size_t)g->nx + 1), s, geo, k, Win, dWin,
+                   B.fl[0], nullptr, B.ctrl, want_F, cnt));
   }
-  const size_t ncell = (size_t)g->nx * g->ny;
-  tim_begin(stage == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2, s);
+  const unsigned nc = nblocks((size_t)g->nx * g->ny);
+  const int kind = stage == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2;
+  double* fy = g->ndim == 2 ? B.fl[1] : nullptr;
   if (g->ndim == 2) {
     if (stage == 1)
-      hipLaunchKernelGGL((k_update<2, 1>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         B.wst, B.dwst, B.r, B.fl[0], B.fl[1], B.ctrl, B.part, count);
+      HIP_TRY(launch(kind, k_update<2, 1>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
+                     B.ctrl, B.part, cnt));
     else
-      hipLaunchKernelGGL((k_update<2, 2>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         Wfinal, dWfinal, B.r, B.fl[0], B.fl[1], B.ctrl, B.part, count);
+      HIP_TRY(launch(kind, k_update<2, 2>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0], fy,
+                     B.ctrl, B.part, cnt));
   } else {
     if (stage == 1)
-      hipLaunchKernelGGL((k_update<1, 1>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         B.wst, B.dwst, B.r, B.fl[0], nullptr, B.ctrl, B.part, count);
+      HIP_TRY(launch(kind, k_update<1, 1>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
+                     B.ctrl, B.part, cnt));
     else
-      hipLaunchKernelGGL((k_update<1, 2>), dim3(nblocks(ncell)), dim3(BLOCK), 0, s, geo, k, Win,
-                         Wfinal, dWfinal, B.r, B.fl[0], nullptr, B.ctrl, B.part, count);
+      HIP_TRY(launch(kind, k_update<1, 2>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0], fy,
+                     B.ctrl, B.part, cnt));
   }
-  tim_end(s);
-  HIP_TRY(hipGetLastError());
   return GENO_OK;
 }
 
@@ -1016,7 +982,7 @@ extern "C" {
 int geno_abi_version(void) { return GENO_ABI_VERSION; }
 
 int geno_timing_enable(int max_launches) {
-  for (int i = 0; i < 2 * g_tim.cap; ++i) hipEventDestroy(g_tim.ev[i]);
+  for (int i = 0; i < 2 * g_tim.cap; ++i) (void)hipEventDestroy(g_tim.ev[i]);
   free(g_tim.ev);
   free(g_tim.kind);
   g_tim = Timing{};
@@ -1036,7 +1002,7 @@ int geno_timing_enable(int max_launches) {
 }
 
 int geno_count_enable(int on) {
-  g_count = on ? 1 : 0;
+  g_cnt.on = on ? 1 : 0;
   return GENO_OK;
 }
 
@@ -1060,20 +1026,28 @@ int geno_timing_read(int nkinds, double* ms_total, long long* launches) {
   return GENO_OK;
 }
 
-int geno_work_read(const geno_grid* g, const void* ws, int nkinds, int nclass, long long* counts,
-                   void* stream) {
-  int rc = check_grid(g);
-  if (rc) return rc;
-  if (!ws || !counts || nkinds < 1 || nclass < 1) return fail(GENO_EINVAL, "null argument");
-  const Layout L = layout_of(g);
-  Ctrl h;
+int geno_work_read(int nkinds, int nclass, long long* counts, void* stream) {
+  if (!counts || nkinds < 1 || nclass < 1) return fail(GENO_EINVAL, "null argument");
+  for (int i = 0; i < nkinds * nclass; ++i) counts[i] = 0;
+  if (!g_cnt.p) return GENO_OK;
+  const size_t n = (size_t)GENO_NKERNELS * GENO_NCLASS * g_cnt.cap;
+  unsigned long long* h = (unsigned long long*)malloc(n * sizeof *h);
+  if (!h) return fail(GENO_EINVAL, "out of host memory");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(&h, (const char*)ws + L.ctrl, sizeof h, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  for (int a = 0; a < nkinds; ++a)
-    for (int c = 0; c < nclass; ++c)
-      counts[a * nclass + c] =
-          (a < GENO_NKERNELS && c < GENO_NCLASS) ? (long long)h.work[a][c] : 0;
+  hipError_t e = hipMemcpyAsync(h, g_cnt.p, n * sizeof *h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free(h);
+    return fail(GENO_EHIP, "work counters: %s", hipGetErrorString(e));
+  }
+  for (int a = 0; a < nkinds && a < GENO_NKERNELS; ++a)
+    for (int c = 0; c < nclass && c < GENO_NCLASS; ++c) {
+      unsigned long long t = 0;
+      const unsigned long long* p = h + ((size_t)a * GENO_NCLASS + c) * g_cnt.cap;
+      for (int i = 0; i < g_cnt.cap; ++i) t += p[i];
+      counts[a * nclass + c] = (long long)t;
+    }
+  free(h);
   return GENO_OK;
 }
 
@@ -1159,26 +1133,23 @@ int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_
   double* dWd = (double*)dW;
   rc = launch_init(g, geo, k.gamma, Wd, dWd, B, s);
   if (rc) return rc;
+  const Cnt none{nullptr, 0};
   if (g->ndim == 1) {
-    hipLaunchKernelGGL(k_faces1d<0>, dim3(nblocks((size_t)g->nx + 1)), dim3(BLOCK), 0, s, geo, k,
-                       Wd, dWd, (double*)face_state, (double*)chi, nullptr, 0, 0);
+    HIP_TRY(launch(-1, k_faces1d<0>, nblocks((size_t)g->nx + 1), s, geo, k, (const double*)Wd,
+                   (const double*)dWd, (double*)face_state, (double*)chi, (Ctrl*)nullptr, 0, none));
+  } else if (dir == 0) {
+    HIP_TRY(launch(-1, k_normal2d<0>, nblocks(4 * face_rows(g, 0)), s, geo, k, Wd, dWd, B.fr[0],
+                   (double*)chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
+                   none));
+    HIP_TRY(launch(-1, k_faces2d<0, 0>, nblocks(2 * faces_of(g, 0)), s, geo, k, Wd, B.fr[0],
+                   (double*)face_state, (Ctrl*)nullptr, 0, none, (unsigned int*)nullptr));
   } else {
-    const size_t nrows =
-        dir == 0 ? (size_t)(g->ny + 2) * (g->nx + 1) : (size_t)(g->ny + 1) * (g->nx + 2);
-    const size_t nfaces = dir == 0 ? (size_t)g->ny * (g->nx + 1) : (size_t)(g->ny + 1) * g->nx;
-    if (dir == 0) {
-      hipLaunchKernelGGL(k_normal2d<0>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Wd, dWd,
-                         B.fr[0], (double*)chi, nullptr, nullptr, 0, nullptr, 0, 0);
-      hipLaunchKernelGGL((k_faces2d<0, 0>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo, k,
-                         Wd, B.fr[0], (double*)face_state, nullptr, 0, 0, nullptr);
-    } else {
-      hipLaunchKernelGGL(k_normal2d<1>, dim3(nblocks(nrows)), dim3(BLOCK), 0, s, geo, k, Wd, dWd,
-                         B.fr[1], (double*)chi, nullptr, nullptr, 0, nullptr, 0, 0);
-      hipLaunchKernelGGL((k_faces2d<1, 0>), dim3(nblocks(2 * nfaces)), dim3(BLOCK), 0, s, geo, k,
-                         Wd, B.fr[1], (double*)face_state, nullptr, 0, 0, nullptr);
-    }
+    HIP_TRY(launch(-1, k_normal2d<1>, nblocks(4 * face_rows(g, 1)), s, geo, k, Wd, dWd, B.fr[1],
+                   (double*)chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
+                   none));
+    HIP_TRY(launch(-1, k_faces2d<1, 0>, nblocks(2 * faces_of(g, 1)), s, geo, k, Wd, B.fr[1],
+                   (double*)face_state, (Ctrl*)nullptr, 0, none, (unsigned int*)nullptr));
   }
-  HIP_TRY(hipGetLastError());
   return GENO_OK;
 }
 
@@ -1193,17 +1164,14 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
   const geno::KParams k = kparams(g);
   if (g->ndim == 1) {
     const int nf = g->nx + 1;
-    hipLaunchKernelGGL(k_flux_points<3>, dim3(nblocks(nf)), dim3(BLOCK), 0, s, nf, 1, 0, k, g->dx,
-                       g->dy, dt, (const double*)face_state, (double*)F, (double*)Ft,
-                       (double*)Wint);
+    HIP_TRY(launch(-1, k_flux_points<3>, nblocks(nf), s, nf, 1, 0, k, g->dx, g->dy, dt,
+                   (const double*)face_state, (double*)F, (double*)Ft, (double*)Wint));
   } else {
     const int nf = dir == 0 ? g->ny * (g->nx + 1) : (g->ny + 1) * g->nx;
     const double hn = dir == 0 ? g->dx : g->dy, ht = dir == 0 ? g->dy : g->dx;
-    hipLaunchKernelGGL(k_flux_points<4>, dim3(nblocks(nf)), dim3(BLOCK), 0, s, nf, 2, dir, k, hn,
-                       ht, dt, (const double*)face_state, (double*)F, (double*)Ft,
-                       (double*)Wint);
+    HIP_TRY(launch(-1, k_flux_points<4>, nblocks(nf), s, nf, 2, dir, k, hn, ht, dt,
+                   (const double*)face_state, (double*)F, (double*)Ft, (double*)Wint));
   }
-  HIP_TRY(hipGetLastError());
   return GENO_OK;
 }
 
@@ -1218,15 +1186,37 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
   const geno::KParams k = kparams(g);
   const Layout L = layout_of(g);
   const Bufs B = bufs_of((char*)ws, L, g->ndim);
-  const int count = g_count;
+  Cnt cnt{nullptr, 0};
+  if (g_cnt.on) {
+    // measurement mode: (re)allocate the per-block count slots and clear them
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const int cap = count_cap(g);
+    if (!g_cnt.p || cap > g_cnt.cap || dev != g_cnt.dev) {
+      if (g_cnt.p) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(g_cnt.p));
+        g_cnt.p = nullptr;
+      }
+      HIP_TRY(hipMalloc((void**)&g_cnt.p,
+                        (size_t)GENO_NKERNELS * GENO_NCLASS * cap * sizeof(unsigned long long)));
+      g_cnt.cap = cap;
+      g_cnt.dev = dev;
+    }
+    HIP_TRY(hipMemsetAsync(g_cnt.p, 0,
+                           (size_t)GENO_NKERNELS * GENO_NCLASS * g_cnt.cap *
+                               sizeof(unsigned long long),
+                           s));
+    cnt = Cnt{g_cnt.p, g_cnt.cap};
+  }
   double* Wd = (double*)W;
   double* dWd = (double*)dW;
   rc = launch_init(g, geo, k.gamma, Wd, dWd, B, s);
   if (rc) return rc;
   for (int n = 0; n < nsteps; ++n) {
-    rc = launch_stage(g, geo, k, B, L.npart, Wd, dWd, 1, dt_out, n, nullptr, nullptr, count, s);
+    rc = launch_stage(g, geo, k, B, L.npart, Wd, dWd, 1, dt_out, n, nullptr, nullptr, cnt, s);
     if (rc) return rc;
-    rc = launch_stage(g, geo, k, B, L.npart, B.wst, B.dwst, 2, nullptr, n, Wd, dWd, count, s);
+    rc = launch_stage(g, geo, k, B, L.npart, B.wst, B.dwst, 2, nullptr, n, Wd, dWd, cnt, s);
     if (rc) return rc;
   }
   if (stats) {

@@ -133,8 +133,9 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     });
   }
   if (ndim == 2) {
-    // face-row: 4 variables x (h*gradient scaling 4 + linear part + two sides)
-    const double row = 4.0 * (4 + lin + 2 * side_hi);
+    // face-row entry of one variable: h*gradient scaling (4), linear part,
+    // two sides
+    const double row = 4 + lin + 2 * side_hi;
     for (int kind : {GENO_K_NORMAL_X, GENO_K_NORMAL_Y}) {
       set(kind, GENO_W_UNITS, row);
       set(kind, GENO_W_LOW, (double)(side_lo - side_hi));
@@ -143,7 +144,7 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     // 3 arrays x 2 sides x 4 variables, of which the two h*d/dn arrays per
     // point) and the Gauss average (12 additions)
     const double face = 8.0 * tan_hi + 4.0 * adm + 2.0 * 16.0 + 12.0;
-    for (int kind : {GENO_K_FACES_X, GENO_K_FACES_Y, GENO_K_SLOW_X, GENO_K_SLOW_Y}) {
+    for (int kind : {GENO_K_FACES_X, GENO_K_FACES_Y, GENO_K_SLOW}) {
       set(kind, GENO_W_UNITS, face);
       set(kind, GENO_W_LOW, (double)(tan_lo - tan_hi));
       set(kind, GENO_W_FAST, (double)pfast);

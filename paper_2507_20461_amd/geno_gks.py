@@ -46,8 +46,7 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_state_elems", "gks_workspace_bytes", "geno_reconstruct", "gks_flux", "gks_step",
            "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
            "geno_kernel_name")
-KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow_x", "slow_y", "update_1", "update_2",
-           "faces_1d")
+KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d")
 WORK_CLASSES = ("units", "tanh", "low", "fast", "slow", "guard")
 
 _lib = None
@@ -85,7 +84,7 @@ def lib():
         L.geno_timing_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
         L.geno_kernel_name.argtypes = [i]
         L.geno_kernel_name.restype = ctypes.c_char_p
-        L.geno_work_read.argtypes = [ctypes.POINTER(geno_grid), vp, i, i, ctypes.POINTER(ctypes.c_longlong), vp]
+        L.geno_work_read.argtypes = [i, i, ctypes.POINTER(ctypes.c_longlong), vp]
         L.geno_op_costs.argtypes = [ctypes.POINTER(geno_grid), i, i, ctypes.POINTER(ctypes.c_double)]
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
                      "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
@@ -221,11 +220,11 @@ def timing_read():
     return {lib().geno_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
 
 
-def work_read(grid, ws, stream=None):
-    """{kernel: {class: count}} counted during the last gks_step on ws (timing enabled)."""
+def work_read(stream=None):
+    """{kernel: {class: count}} counted during the last gks_step made with counting enabled."""
     nk, nc = len(KERNELS), len(WORK_CLASSES)
     out = (ctypes.c_longlong * (nk * nc))()
-    _check(lib().geno_work_read(ctypes.byref(grid.g), _ptr(ws), nk, nc, out, _stream(stream)))
+    _check(lib().geno_work_read(nk, nc, out, _stream(stream)))
     return {KERNELS[a]: {WORK_CLASSES[c]: out[a * nc + c] for c in range(nc)} for a in range(nk)}
 
 

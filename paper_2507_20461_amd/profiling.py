@@ -1,0 +1,170 @@
+"""rocprofv3 profiling of the benchmark and text summaries for ``profiles/``.
+
+Usage on a GPU machine (from the repository root)::
+
+    python -m paper_2507_20461_amd.profiling run       # kernel trace + counter passes
+    python -m paper_2507_20461_amd.profiling summarize # write profiles/*.txt
+
+Each counter pass is its own rocprofv3 run (FETCH_SIZE, WRITE_SIZE, VALU
+activity). Summaries record the commands, the per-kernel averages and a hash of
+the kernel sources, so that the benchmark reports HBM traffic only for the
+kernels the counters were taken on.
+
+HBM traffic calibration: the benchmark runs one plain device-to-device copy of
+256 MiB (the runtime's copy kernel: 256 MiB read, 256 MiB written) before
+anything else; the ratio of its counted FETCH_SIZE / WRITE_SIZE to that size
+scales the counts of the method's kernels.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+OUT = os.path.join(ROOT, "gpurun_out")
+PROFILES = os.path.join(ROOT, "profiles")
+CAL_BYTES = 256 * 1024 * 1024
+CAL_ELEMS = CAL_BYTES // 8
+
+BENCH_FULL = ["python3", os.path.join(ROOT, "bench.py")]
+BENCH_SHORT = ["python3", os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
+               "--no-cpu-baseline", "--no-kernel-timing"]
+PASSES = {
+    "ktrace": (["--kernel-trace", "--stats"], BENCH_FULL),
+    "fetch": (["--pmc", "FETCH_SIZE"], BENCH_SHORT),
+    "write": (["--pmc", "WRITE_SIZE"], BENCH_SHORT),
+    "valu": (["--pmc", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE"], BENCH_SHORT),
+}
+XCDS = 8          # GRBM_GUI_ACTIVE is summed over the XCDs of the device
+SIMDS = 256 * 4   # 256 CUs x 4 SIMDs
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def command(name, extra=()):
+    opts, bench = PASSES[name]
+    return (["rocprofv3", *opts, "--output-format", "csv", "-d", os.path.join(OUT, "prof_" + name), "-o", "run",
+             "--", *bench, *extra])
+
+
+def run(extra=()):
+    """One rocprofv3 run per pass. Stops at the first pass that fails, except
+    for a segmentation fault of the profiler after the program has finished
+    and the result file is complete."""
+    os.makedirs(OUT, exist_ok=True)
+    env = dict(os.environ, TMPDIR="/tmp")
+    for name in PASSES:
+        cmd = command(name, extra)
+        print("==", " ".join(cmd), flush=True)
+        with open(os.path.join(OUT, "prof_%s.log" % name), "w") as log:
+            rc = subprocess.run(["timeout", "-s", "KILL", "240", *cmd], stdout=log, stderr=log, env=env).returncode
+        res = os.path.join(OUT, "prof_" + name, "run_kernel_stats.csv" if name == "ktrace"
+                           else "run_counter_collection.csv")
+        print("   exit %d, results %s" % (rc, "present" if os.path.exists(res) else "missing"), flush=True)
+        if rc != 0 and not (rc in (139, -11) and os.path.exists(res)):
+            sys.exit(rc if rc > 0 else 1)
+
+
+def _short(name):
+    n = name.replace("void (anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    return n.split("(")[0].strip()
+
+
+def _counters(path, counter):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            d[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return d
+
+
+def _cal_scale(path, counter):
+    best = 0.0
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter and not _short(r["Kernel_Name"]).startswith("k_"):
+            best = max(best, float(r["Counter_Value"]) * 1024)
+    if abs(best - CAL_BYTES) > 0.75 * CAL_BYTES:
+        return None
+    return best / CAL_BYTES
+
+
+def summarize(tag="faces_fp64_512"):
+    os.makedirs(PROFILES, exist_ok=True)
+    sh = source_hash()
+    lines = []
+    # kernel trace stats
+    stats = list(csv.DictReader(open(os.path.join(OUT, "prof_ktrace", "run_kernel_stats.csv"))))
+    lines.append("# rocprofv3 kernel-trace statistics, 2-D Euler 512x512 FP64 quadrants (bench.py default)")
+    lines.append("# command: " + " ".join(command("ktrace")).replace(ROOT + "/", ""))
+    lines.append("# kernel sources sha256[:16]: " + sh)
+    lines.append("%-26s %7s %12s %12s %8s" % ("kernel", "calls", "avg_us", "total_ms", "pct"))
+    ktrace = {}
+    for r in stats:
+        k = _short(r["Name"])
+        ktrace[k] = float(r["AverageNs"]) / 1e3
+        lines.append("%-26s %7s %12.2f %12.3f %8s" % (k[:26], r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                      float(r["TotalDurationNs"]) / 1e6, r["Percentage"]))
+    open(os.path.join(PROFILES, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
+    # counters
+    F = _counters(os.path.join(OUT, "prof_fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    Wr = _counters(os.path.join(OUT, "prof_write", "run_counter_collection.csv"), "WRITE_SIZE")
+    V = {c: _counters(os.path.join(OUT, "prof_valu", "run_counter_collection.csv"), c)
+         for c in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE")}
+    # the calibration copy is the largest dispatch that is not one of the method's kernels
+    fcal = _cal_scale(os.path.join(OUT, "prof_fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    wcal = _cal_scale(os.path.join(OUT, "prof_write", "run_counter_collection.csv"), "WRITE_SIZE")
+    avg = lambda v: sum(v) / len(v)
+    rows = {}
+    for k in sorted(F):
+        if not k.startswith("k_"):
+            continue
+        f, w = avg(F[k]) * 1024, avg(Wr.get(k, [0.0])) * 1024
+        insts = avg(V["SQ_INSTS_VALU"].get(k, [0.0]))
+        active = avg(V["SQ_ACTIVE_INST_VALU"].get(k, [0.0]))
+        waves = avg(V["SQ_WAVES"].get(k, [0.0]))
+        gui = avg(V["GRBM_GUI_ACTIVE"].get(k, [1.0])) / XCDS
+        rows[k] = {"fetch_bytes": f, "write_bytes": w,
+                   "fetch_bytes_cal": f / fcal if fcal else None, "write_bytes_cal": w / wcal if wcal else None,
+                   "valu_insts_per_wave": insts / waves if waves else None,
+                   "valu_busy": 4.0 * active / SIMDS / gui if gui else None}
+    lines = ["# rocprofv3 counters per dispatch (3 separate --pmc passes), 2-D Euler 512x512 FP64",
+             "# commands:"]
+    for name in ("fetch", "write", "valu"):
+        lines.append("#   " + " ".join(command(name)).replace(ROOT + "/", ""))
+    lines.append("# kernel sources sha256[:16]: " + sh)
+    lines.append("# calibration: device copy of 256 MiB: FETCH scale %s, WRITE scale %s"
+                 % ("%.4f" % fcal if fcal else "n/a", "%.4f" % wcal if wcal else "n/a"))
+    lines.append("# valu_busy = 4 * SQ_ACTIVE_INST_VALU / (1024 SIMDs * GRBM_GUI_ACTIVE / 8 XCDs)")
+    lines.append("%-22s %12s %12s %12s %12s %10s %9s" % ("kernel", "FETCH_MB", "WRITE_MB", "FETCH_cal", "WRITE_cal",
+                                                        "valu/wave", "valu_busy"))
+    for k, r in rows.items():
+        lines.append("%-22s %12.2f %12.2f %12s %12s %10.0f %9.3f" % (
+            k[:22], r["fetch_bytes"] / 1e6, r["write_bytes"] / 1e6,
+            "%.2f" % (r["fetch_bytes_cal"] / 1e6) if r["fetch_bytes_cal"] else "n/a",
+            "%.2f" % (r["write_bytes_cal"] / 1e6) if r["write_bytes_cal"] else "n/a",
+            r["valu_insts_per_wave"] or 0, r["valu_busy"] or 0))
+    open(os.path.join(PROFILES, "%s_counters.txt" % tag), "w").write("\n".join(lines) + "\n")
+    meta = {"source_hash": sh, "calibration": {"fetch": fcal, "write": wcal}, "kernels": rows,
+            "ktrace_avg_us": ktrace}
+    open(os.path.join(PROFILES, "%s_counters.json" % tag), "w").write(json.dumps(meta, indent=1) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "summarize"
+    if what == "run":
+        run(sys.argv[2:])
+    else:
+        summarize()
