@@ -16,7 +16,7 @@
  * Errors. Every call returns 0 (GENO_OK) or a negative code; no exception
  *   crosses the ABI. geno_last_error() returns a thread-local message for the
  *   last failure on the calling thread.
- * Layout of the state. Structure of arrays, float64, planar
+ * Layout of the state. Structure of arrays, planar
  *   [field][row][column] with NG = 2 ghost cells on every side of the grid:
  *   element (field f, interior row j in [-2, ny+2), interior column i in
  *   [-2, nx+2)) sits at index (f * rows + (j + 2)) * pitch + (i + 2), where
@@ -25,6 +25,9 @@
  *           2-D W = (rho, rhoU, rhoV, rhoE) and dW = (d/dx of the four
  *           fields, then d/dy of the four fields).
  *   dW holds physical cell-averaged gradients (not scaled by the cell size).
+ *   Element types: W is float64 in every precision mode. dW, face_state,
+ *   F, Ft and Wint are float64 with GENO_F64 and float32 with GENO_MIXED;
+ *   chi is float64 in both.
  *   Ghost cells belong to the library: calls overwrite them; interior cells
  *   are written only by gks_step.
  */
@@ -52,7 +55,13 @@ extern "C" {
 #define GENO_BC_TRANSMISSIVE 1
 
 /* arithmetic of the reconstruction and the flux */
-#define GENO_F64 0
+#define GENO_F64 0     /* everything in float64 */
+#define GENO_MIXED 1   /* reconstruction, tangential step and gas-kinetic flux in
+                          float32, and dW and the face buffers stored in float32;
+                          the small-eps divisions of the smoothness indicators
+                          (Eq. (5), (8)), the time-fit coefficients of the flux,
+                          the conservative update of W, the stored stage
+                          combination and dt stay in float64 */
 
 /* Method parameters.
  * C, eps, r, rL, d: GENO constants of Sec. 3 (Eq. (4), (5), (8)): the paper
@@ -65,10 +74,12 @@ extern "C" {
  *   tau = tau_c1 dt + tau_c2 dt |p_l - p_r| / (p_l + p_r).
  * cfl: dt = cfl * min over interior cells of min(dx/(|U|+c), dy/(|V|+c)).
  * bc: x-low, x-high, y-low, y-high (GENO_BC_*); periodic must be set on both
- *   sides of an axis. */
+ *   sides of an axis.
+ * dt_fixed: if > 0, every step of gks_step uses this dt instead of the CFL
+ *   condition (the default is 0). */
 typedef struct geno_params {
   int version;
-  int precision;   /* GENO_F64 */
+  int precision;   /* GENO_F64 or GENO_MIXED */
   double gamma;
   double C;
   double eps;
@@ -79,6 +90,7 @@ typedef struct geno_params {
   double tau_c2;
   double cfl;
   int bc[4];
+  double dt_fixed;
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */
@@ -115,7 +127,8 @@ int geno_params_default(geno_params* p);
 int geno_grid_init(geno_grid* g, int ndim, int nx, int ny, double x0, double x1,
                    double y0, double y1, const geno_params* p);
 
-/* Number of doubles of one state array (W: nv fields; dW: ndim * nv). */
+/* Number of elements of one state array (W: nv fields; dW: ndim * nv); the
+ * element type follows the precision mode (see the layout above). */
 size_t geno_state_elems(const geno_grid* g, int nfields);
 
 /* Bytes of the device workspace needed by gks_step / gks_flux. */
@@ -126,7 +139,7 @@ size_t gks_workspace_bytes(const geno_grid* g);
  * 0) after filling the ghost cells of W and dW in place.
  * face_state (device, caller-allocated): per face, per Gauss point, per side,
  *   the reconstructed state at the point after the positivity guard:
- *   [side(2)][gauss(G)][quant(Q)][var(nv)][nfy][nfx] doubles with
+ *   [side(2)][gauss(G)][quant(Q)][var(nv)][nfy][nfx] elements with
  *   1-D: G = 1, Q = 2 (value, h * d/dn), nfy = 1, nfx = nx + 1;
  *   2-D: G = 2 (the points +-h/(2 sqrt 3) about the face centre, the
  *        negative tangential offset first), Q = 3 (value, h * d/dn,

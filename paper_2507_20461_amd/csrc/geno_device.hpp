@@ -26,6 +26,7 @@ struct KParams {
   double K;       // internal degrees of freedom of the BGK model
   double tc1, tc2;    // collision time coefficients
   double cfl;
+  double dt_fixed;    // > 0: fixed time step instead of the CFL condition
 };
 
 // Path function chi = tanh(C alpha)/tanh(C) (Eq. (4)) of the ultimate

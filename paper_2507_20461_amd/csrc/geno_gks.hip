@@ -138,15 +138,13 @@ __host__ __device__ __forceinline__ size_t at(const Geo& g, int f, int j, int i)
 
 // Control block at the start of the workspace.
 struct Ctrl {
-  unsigned long long tmin;                         // CFL minimum of the current step (bits of a double)
-  unsigned long long guard;                        // positivity fall-backs
-  unsigned long long nonfinite;                    // non-finite cells after a stage-2 update
-  unsigned int qcount[2];                          // queued tau > 0 faces per direction
+  double dt;                        // time step of the current step
+  unsigned long long guard;         // positivity fall-backs
+  unsigned long long nonfinite;     // non-finite cells after a stage-2 update
+  unsigned int qcount[2];           // queued tau > 0 faces per direction
 };
 
-__device__ __forceinline__ double dt_of(const Ctrl* c, double cfl) {
-  return cfl * __longlong_as_double((long long)c->tmin);
-}
+__device__ __forceinline__ double dt_of(const Ctrl* c) { return c->dt; }
 
 // ---------------------------------------------------------------------------
 // Ghost cells. Periodic: copy of the periodic image (values and gradients).
@@ -226,9 +224,10 @@ __device__ __forceinline__ void block_min(double t, double* part) {
   }
 }
 
-// minimum of the npart partials into ctrl->tmin (one block); records dt
+// dt of the step into ctrl->dt (one block): cfl times the minimum of the
+// npart partials, or dt_fixed if positive; records dt
 __device__ __forceinline__ void reduce_dt(const double* part, int npart, Ctrl* ctrl, double cfl,
-                                          double* dt_out, int step) {
+                                          double dt_fixed, double* dt_out, int step) {
   __shared__ double red[BLOCK / 64];
   double m = INFINITY;
   for (int q = threadIdx.x; q < npart; q += blockDim.x) m = fmin(m, part[q]);
@@ -239,16 +238,17 @@ __device__ __forceinline__ void reduce_dt(const double* part, int npart, Ctrl* c
   if (threadIdx.x == 0) {
     m = red[0];
     for (int w = 1; w < BLOCK / 64; ++w) m = fmin(m, red[w]);
-    ctrl->tmin = (unsigned long long)__double_as_longlong(m);
-    if (dt_out) dt_out[step] = cfl * m;
+    const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * m;
+    ctrl->dt = dt;
+    if (dt_out) dt_out[step] = dt;
   }
 }
 
 // Start of gks_step: ghost cells of the initial state, per-block CFL minima,
 // cleared counters.
-template <int NDIM>
+template <int NDIM, typename T>
 __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __restrict__ W,
-                                                double* __restrict__ dW, double* __restrict__ part,
+                                                T* __restrict__ dW, double* __restrict__ part,
                                                 Ctrl* ctrl) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,12 +260,13 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
   double tl = INFINITY;
   if (t < g.nx * g.ny) {
     const int j = t / g.nx, i = t % g.nx;
-    double w[NV], dw[NV * NDIM];
+    double w[NV];
+    T dw[NV * NDIM];
 #pragma unroll
     for (int v = 0; v < NV; ++v) w[v] = W[at(g, v, j, i)];
 #pragma unroll
     for (int v = 0; v < NV * NDIM; ++v) dw[v] = dW[at(g, v, j, i)];
-    scatter_ghosts<NDIM, double>(g, W, dW, j, i, w, dw);
+    scatter_ghosts<NDIM, T>(g, W, dW, j, i, w, dw);
     tl = cell_tmin<NDIM>(g, w, gamma);
   }
   block_min(tl, part);
@@ -281,15 +282,15 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
 // With part (first kernel of a step), block 0 also reduces the CFL partial
 // minima of the previous kernel into ctrl->tmin and records dt.
 // ---------------------------------------------------------------------------
-template <int DIR>
+template <int DIR, typename T>
 __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                                                     const double* __restrict__ W,
-                                                    const double* __restrict__ dW,
-                                                    double* __restrict__ fr,
+                                                    const T* __restrict__ dW,
+                                                    T* __restrict__ fr,
                                                     double* __restrict__ chi, Ctrl* ctrl,
                                                     const double* __restrict__ part, int npart,
                                                     double* dt_out, int step, Cnt cnt) {
-  if (part && blockIdx.x == 0) reduce_dt(part, npart, ctrl, k.cfl, dt_out, step);
+  if (part && blockIdx.x == 0) reduce_dt(part, npart, ctrl, k.cfl, k.dt_fixed, dt_out, step);
   if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) ctrl->qcount[DIR] = 0;
   const int n1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
   const int n0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
@@ -300,18 +301,19 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
     const int v = t / plane, o = t - v * plane;
     const int a = o / n1, b = o - a * n1;
     const double h = DIR == 0 ? g.dx : g.dy;
-    double Q[4], G[4];
+    T Q[4], G[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       size_t id;
       if (DIR == 0) id = at(g, v, a - 1, b - 2 + m);
       else id = at(g, v, a - 2 + m, b - 1);
-      Q[m] = W[id];
-      G[m] = h * dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+      Q[m] = T(W[id]);
+      G[m] = T(h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch]);
     }
-    double vl, dl, xl, vr, dr, xr;
-    nlow = geno::geno_face<double, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl,
-                                           dl, xl, vr, dr, xr);
+    T vl, dl, vr, dr;
+    double xl, xr;
+    nlow = geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl,
+                                      xl, vr, dr, xr);
     fr[(size_t)(0 * 4 + v) * plane + o] = vl;
     fr[(size_t)(1 * 4 + v) * plane + o] = dl;
     fr[(size_t)(2 * 4 + v) * plane + o] = vr;
@@ -349,10 +351,10 @@ struct FaceGeo {
   }
 };
 
-template <int DIR, int MODE>
+template <int DIR, int MODE, typename T>
 __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
                                           const double* __restrict__ W,
-                                          const double* __restrict__ fr, double* __restrict__ out,
+                                          const T* __restrict__ fr, T* __restrict__ out,
                                           Ctrl* ctrl, int want_F, unsigned int (&wc)[GENO_NCLASS],
                                           int face, bool valid, unsigned int* __restrict__ queue) {
   const FaceGeo<DIR> fg(g);
@@ -365,13 +367,13 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   const size_t rc = DIR == 0 ? rm + fg.r1 : rm + 1;
   const size_t rp = DIR == 0 ? rc + fg.r1 : rc + 1;
   // tangential step of side q for both points
-  double own_v[4], own_t[4], snd_v[4], snd_t[4], dn[4];
+  T own_v[4], own_t[4], snd_v[4], snd_t[4], dn[4];
   unsigned int nlow = 0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double* p = fr + (size_t)((2 * q + 0) * 4 + v) * rplane;
-    double v0, v1, t0, t1;
-    nlow += geno::tangential<double, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1);
+    const T* p = fr + (size_t)((2 * q + 0) * 4 + v) * rplane;
+    T v0, v1, t0, t1;
+    nlow += geno::tangential<T, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1);
     own_v[v] = q ? v1 : v0;
     own_t[v] = q ? t1 : t0;
     snd_v[v] = q ? v0 : v1;
@@ -379,12 +381,12 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
     dn[v] = fr[(size_t)((2 * q + 1) * 4 + v) * rplane + rc];
   }
   // states of both sides at this lane's point
-  double S[2][4], Dn[2][4], Dt[2][4];
+  T S[2][4], Dn[2][4], Dt[2][4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double rv = __shfl_xor(snd_v[v], 1, 64);
-    const double rt = __shfl_xor(snd_t[v], 1, 64);
-    const double rd = __shfl_xor(dn[v], 1, 64);
+    const T rv = __shfl_xor(snd_v[v], 1, 64);
+    const T rt = __shfl_xor(snd_t[v], 1, 64);
+    const T rd = __shfl_xor(dn[v], 1, 64);
     S[0][v] = q ? rv : own_v[v];
     S[1][v] = q ? own_v[v] : rv;
     Dt[0][v] = q ? rt : own_t[v];
@@ -396,15 +398,15 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   unsigned int nguard = 0;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    if (!geno::admissible<4, double>(S[s], k.gamma)) {
+    if (!geno::admissible<4, T>(S[s], k.gamma)) {
       ++nguard;
       const int ci = DIR == 0 ? b - 1 + s : b;
       const int cj = DIR == 0 ? a : a - 1 + s;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        S[s][v] = W[at(g, v, cj, ci)];
-        Dn[s][v] = 0.0;
-        Dt[s][v] = 0.0;
+        S[s][v] = T(W[at(g, v, cj, ci)]);
+        Dn[s][v] = T(0);
+        Dt[s][v] = T(0);
       }
     }
   }
@@ -424,12 +426,12 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
         }
     }
   } else {
-    const double dt = dt_of(ctrl, k.cfl);
+    const double dt = dt_of(ctrl);
     const double hn = DIR == 0 ? g.dx : g.dy, ht = DIR == 0 ? g.dy : g.dx;
-    const double ihn = 1.0 / hn, iht = 1.0 / ht;
+    const T ihn = T(1.0 / hn), iht = T(1.0 / ht);
     constexpr int p1 = DIR == 0 ? 1 : 2, p2 = DIR == 0 ? 2 : 1;
     constexpr int perm[4] = {0, p1, p2, 3};
-    double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
+    T Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       Wl[v] = S[0][perm[v]];
@@ -439,14 +441,14 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       tl[v] = Dt[0][perm[v]] * iht;
       tr[v] = Dt[1][perm[v]] * iht;
     }
-    double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
+    T F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
     bool slow;   // MODE 1: tau > 0, not evaluated; MODE 2: evaluated, tau > 0
     if constexpr (MODE == 1)
-      slow = gks::point_flux<4, false, double>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5, want_F != 0,
-                                               F, Ft, Wi);
+      slow = gks::point_flux<4, false, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F,
+                                          Ft, Wi);
     else
-      slow = gks::point_flux<4, true, double>(Wl, Wr, nl, nr, tl, tr, dt, k, 0.5, want_F != 0,
-                                              F, Ft, Wi);
+      slow = gks::point_flux<4, true, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F,
+                                         Ft, Wi);
     bool pair_slow = false;
     if constexpr (MODE == 1) {
       // every lane takes part in the exchange (no short-circuit around it:
@@ -468,7 +470,7 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
     }
     if (nguard && (MODE == 2 || !pair_slow)) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
     // Gauss average: add the partner's half
-    double So[12];
+    T So[12];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       So[v] = F[v] + __shfl_xor(F[v], 1, 64);
@@ -499,11 +501,11 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   }
 }
 
-template <int DIR, int MODE>
+template <int DIR, int MODE, typename T>
 __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
                                                    const double* __restrict__ W,
-                                                   const double* __restrict__ fr,
-                                                   double* __restrict__ out, Ctrl* ctrl,
+                                                   const T* __restrict__ fr,
+                                                   T* __restrict__ out, Ctrl* ctrl,
                                                    int want_F, Cnt cnt,
                                                    unsigned int* __restrict__ queue) {
   const FaceGeo<DIR> fg(g);
@@ -511,7 +513,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
   const int t = xcd_block() * BLOCK + threadIdx.x;
   const int face = t >> 1;
   unsigned int wc[GENO_NCLASS] = {};
-  face_pair<DIR, MODE>(g, k, W, fr, out, ctrl, want_F, wc, face, face < nfaces, queue);
+  face_pair<DIR, MODE, T>(g, k, W, fr, out, ctrl, want_F, wc, face, face < nfaces, queue);
   if (MODE == 1 && cnt.p) block_count(cnt, DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, wc);
 }
 
@@ -520,12 +522,13 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
 // grid-stride over the pairs; pairs [0, nqx) are x-faces, the rest y-faces.
 // Both lanes of a pair always take the same branch and trip count, so each
 // cross-lane read finds its partner active.
+template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
                                                   const double* __restrict__ W,
-                                                  const double* __restrict__ frx,
-                                                  const double* __restrict__ fry,
-                                                  double* __restrict__ outx,
-                                                  double* __restrict__ outy, Ctrl* ctrl,
+                                                  const T* __restrict__ frx,
+                                                  const T* __restrict__ fry,
+                                                  T* __restrict__ outx, T* __restrict__ outy,
+                                                  Ctrl* ctrl,
                                                   int want_F, Cnt cnt,
                                                   const unsigned int* __restrict__ qx,
                                                   const unsigned int* __restrict__ qy) {
@@ -535,9 +538,9 @@ __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
   unsigned int wc[GENO_NCLASS] = {};
   for (unsigned int e = (blockIdx.x * blockDim.x + threadIdx.x) >> 1; e < nq; e += stride) {
     if (e < nqx)
-      face_pair<0, 2>(g, k, W, frx, outx, ctrl, want_F, wc, (int)qx[e], true, nullptr);
+      face_pair<0, 2, T>(g, k, W, frx, outx, ctrl, want_F, wc, (int)qx[e], true, nullptr);
     else
-      face_pair<1, 2>(g, k, W, fry, outy, ctrl, want_F, wc, (int)qy[e - nqx], true, nullptr);
+      face_pair<1, 2, T>(g, k, W, fry, outy, ctrl, want_F, wc, (int)qy[e - nqx], true, nullptr);
   }
   if (cnt.p) block_count(cnt, GENO_K_SLOW, wc);
 }
@@ -548,30 +551,30 @@ __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
 // one Gauss point: states [side][quant(2)][var][f], flux [kind][var][f].
 // The 1-D step is reduced before this kernel (k_dt1d).
 // ---------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, typename T>
 __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
                                                    const double* __restrict__ W,
-                                                   const double* __restrict__ dW,
-                                                   double* __restrict__ out,
+                                                   const T* __restrict__ dW,
+                                                   T* __restrict__ out,
                                                    double* __restrict__ chi, Ctrl* ctrl,
                                                    int want_F, Cnt cnt) {
   const int nfc = g.nx + 1;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned int nlow = 0, nguard = 0, nslow = 0;
   if (f < nfc) {
-    double S[2][3], Dn[2][3];
+    T S[2][3], Dn[2][3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-      double Q[4], G[4];
+      T Q[4], G[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const size_t id = at(g, v, 0, f - 2 + m);
-        Q[m] = W[id];
-        G[m] = g.dx * dW[id];
+        Q[m] = T(W[id]);
+        G[m] = T(g.dx * (double)dW[id]);
       }
       double xl, xr;
-      nlow += geno::geno_face<double, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
-                                              S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr);
+      nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
+                                         S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr);
       if (chi) {
         chi[(size_t)(0 * 3 + v) * nfc + f] = xl;
         chi[(size_t)(1 * 3 + v) * nfc + f] = xr;
@@ -579,12 +582,12 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      if (!geno::admissible<3, double>(S[s], k.gamma)) {
+      if (!geno::admissible<3, T>(S[s], k.gamma)) {
         ++nguard;
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-          S[s][v] = W[at(g, v, 0, f - 1 + s)];
-          Dn[s][v] = 0.0;
+          S[s][v] = T(W[at(g, v, 0, f - 1 + s)]);
+          Dn[s][v] = T(0);
         }
       }
     }
@@ -598,17 +601,17 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
           out[(size_t)((s * 2 + 1) * 3 + v) * nfc + f] = Dn[s][v];
         }
     } else {
-      const double dt = dt_of(ctrl, k.cfl);
-      const double ih = 1.0 / g.dx;
-      double nl[3], nr[3];
+      const double dt = dt_of(ctrl);
+      const T ih = T(1.0 / g.dx);
+      T nl[3], nr[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         nl[v] = Dn[0][v] * ih;
         nr[v] = Dn[1][v] * ih;
       }
-      double F[3] = {0, 0, 0}, Ft[3] = {0, 0, 0}, Wi[3] = {0, 0, 0};
-      const bool sl = gks::point_flux<3, true, double>(S[0], S[1], nl, nr, nullptr, nullptr, dt,
-                                                       k, 1.0, want_F != 0, F, Ft, Wi);
+      T F[3] = {0, 0, 0}, Ft[3] = {0, 0, 0}, Wi[3] = {0, 0, 0};
+      const bool sl = gks::point_flux<3, true, T>(S[0], S[1], nl, nr, nullptr, nullptr, dt, k,
+                                                  T(1.0), want_F != 0, F, Ft, Wi);
       nslow = sl ? 1u : 0u;
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
@@ -631,28 +634,29 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
 
 // 1-D: reduce the CFL partials of the previous kernel (single block).
 __global__ void __launch_bounds__(BLOCK) k_dt1d(const double* __restrict__ part, int npart,
-                                                Ctrl* ctrl, double cfl, double* dt_out, int step) {
-  reduce_dt(part, npart, ctrl, cfl, dt_out, step);
+                                                Ctrl* ctrl, double cfl, double dt_fixed,
+                                                double* dt_out, int step) {
+  reduce_dt(part, npart, ctrl, cfl, dt_fixed, dt_out, step);
 }
 
 // gks_flux on caller-given point states (layout of geno_reconstruct).
-template <int NV>
+template <int NV, typename T>
 __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, int dir,
                                                        geno::KParams k, double hn, double ht,
-                                                       double dt, const double* __restrict__ st,
-                                                       double* __restrict__ F,
-                                                       double* __restrict__ Ft,
-                                                       double* __restrict__ Wi) {
+                                                       double dt, const T* __restrict__ st,
+                                                       T* __restrict__ F, T* __restrict__ Ft,
+                                                       T* __restrict__ Wi) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= nfaces) return;
   constexpr int Q = NV == 4 ? 3 : 2;
-  const double w = 1.0 / ngauss;
+  const T w = T(1.0 / ngauss);
+  const T ihn = T(1.0 / hn), iht = T(1.0 / ht);
   const int perm[4] = {0, dir == 0 ? 1 : 2, dir == 0 ? 2 : 1, 3};
-  double Fa[NV], Fta[NV], Wia[NV];
+  T Fa[NV], Fta[NV], Wia[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Fa[v] = Fta[v] = Wia[v] = 0.0;
+  for (int v = 0; v < NV; ++v) Fa[v] = Fta[v] = Wia[v] = T(0);
   for (int q = 0; q < ngauss; ++q) {
-    double Ws[2][NV], ns[2][NV], ts[2][NV];
+    T Ws[2][NV], ns[2][NV], ts[2][NV];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -660,11 +664,11 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
         const int pv = NV == 4 ? perm[v] : v;
         const size_t base = (size_t)((s * ngauss + q) * Q) * NV;
         Ws[s][v] = st[(base + 0 * NV + pv) * nfaces + o];
-        ns[s][v] = st[(base + 1 * NV + pv) * nfaces + o] / hn;
-        ts[s][v] = NV == 4 ? st[(base + 2 * NV + pv) * nfaces + o] / ht : 0.0;
+        ns[s][v] = st[(base + 1 * NV + pv) * nfaces + o] * ihn;
+        ts[s][v] = NV == 4 ? st[(base + 2 * NV + pv) * nfaces + o] * iht : T(0);
       }
-    gks::point_flux<NV, true, double>(Ws[0], Ws[1], ns[0], ns[1], ts[0], ts[1], dt, k, w, true,
-                                      Fa, Fta, Wia);
+    gks::point_flux<NV, true, T>(Ws[0], Ws[1], ns[0], ns[1], ts[0], ts[1], dt, k, w, true, Fa,
+                                 Fta, Wia);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -681,19 +685,19 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
 // stage-2 W_int, and the CFL minima of the new state per block. Both write
 // the ghost cells of the state they produce.
 // ---------------------------------------------------------------------------
-template <int NDIM, int STAGE>
+template <int NDIM, int STAGE, typename T>
 __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
                                                   const double* __restrict__ Win,
                                                   double* __restrict__ Wout,
-                                                  double* __restrict__ dWout,
+                                                  T* __restrict__ dWout,
                                                   double* __restrict__ R,
-                                                  const double* __restrict__ fx,
-                                                  const double* __restrict__ fy, Ctrl* ctrl,
+                                                  const T* __restrict__ fx,
+                                                  const T* __restrict__ fy, Ctrl* ctrl,
                                                   double* __restrict__ part, Cnt cnt) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
   const int t = xcd_block() * BLOCK + threadIdx.x;
   const int n = g.nx * g.ny;
-  const double dt = dt_of(ctrl, k.cfl);
+  const double dt = dt_of(ctrl);
   double tloc = INFINITY;
   if (t < n) {
     const int j = t / g.nx, i = t % g.nx;
@@ -701,16 +705,20 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
     const size_t py = (size_t)g.nx * (g.ny + 1);
     const size_t ox = (size_t)j * (g.nx + 1) + i;
     const size_t oy = (size_t)j * g.nx + i;
-    double w[NV], dw[NV * NDIM];
+    // flux differences and gradients in float64 whatever the storage type
+    const auto X = [&](int plane, size_t o) { return (double)fx[plane * px + o]; };
+    const auto Y = [&](int plane, size_t o) { return (double)fy[plane * py + o]; };
+    double w[NV];
+    T dw[NV * NDIM];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double l = -(fx[(0 * NV + v) * px + ox + 1] - fx[(0 * NV + v) * px + ox]) / g.dx;
-      double lt = -(fx[(1 * NV + v) * px + ox + 1] - fx[(1 * NV + v) * px + ox]) / g.dx;
-      dw[v] = (fx[(2 * NV + v) * px + ox + 1] - fx[(2 * NV + v) * px + ox]) / g.dx;
+      double l = -(X(0 * NV + v, ox + 1) - X(0 * NV + v, ox)) / g.dx;
+      double lt = -(X(1 * NV + v, ox + 1) - X(1 * NV + v, ox)) / g.dx;
+      dw[v] = T((X(2 * NV + v, ox + 1) - X(2 * NV + v, ox)) / g.dx);
       if constexpr (NDIM == 2) {
-        l += -(fy[(0 * NV + v) * py + oy + g.nx] - fy[(0 * NV + v) * py + oy]) / g.dy;
-        lt += -(fy[(1 * NV + v) * py + oy + g.nx] - fy[(1 * NV + v) * py + oy]) / g.dy;
-        dw[NV + v] = (fy[(2 * NV + v) * py + oy + g.nx] - fy[(2 * NV + v) * py + oy]) / g.dy;
+        l += -(Y(0 * NV + v, oy + g.nx) - Y(0 * NV + v, oy)) / g.dy;
+        lt += -(Y(1 * NV + v, oy + g.nx) - Y(1 * NV + v, oy)) / g.dy;
+        dw[NV + v] = T((Y(2 * NV + v, oy + g.nx) - Y(2 * NV + v, oy)) / g.dy);
       }
       const size_t c = at(g, v, j, i);
       if constexpr (STAGE == 1) {
@@ -725,7 +733,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
     }
 #pragma unroll
     for (int v = 0; v < NV * NDIM; ++v) dWout[at(g, v, j, i)] = dw[v];
-    scatter_ghosts<NDIM, double>(g, Wout, dWout, j, i, w, dw);
+    scatter_ghosts<NDIM, T>(g, Wout, dWout, j, i, w, dw);
     if constexpr (STAGE == 2) {
       bool bad = false;
 #pragma unroll
@@ -747,9 +755,14 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t ctrl, part, queue[2], wst, dwst, r, fr[2], fl[2], total;
-  size_t nstate;   // doubles per field plane
+  size_t nstate;   // elements per field plane
   int npart;
 };
+
+// bytes of one element of dW and of the face buffers
+size_t elem_bytes(const geno_grid* g) {
+  return g->params.precision == GENO_MIXED ? sizeof(float) : sizeof(double);
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -758,6 +771,7 @@ inline unsigned nblocks(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); 
 Layout layout_of(const geno_grid* g) {
   Layout L{};
   const int nv = g->ndim == 2 ? 4 : 3;
+  const size_t es = elem_bytes(g);
   L.nstate = (size_t)g->rows * g->pitch;
   L.npart = (int)nblocks((size_t)g->nx * g->ny);
   size_t off = 0;
@@ -774,21 +788,21 @@ Layout layout_of(const geno_grid* g) {
   L.wst = off;
   off = align256(off + L.nstate * nv * sizeof(double));
   L.dwst = off;
-  off = align256(off + L.nstate * nv * g->ndim * sizeof(double));
+  off = align256(off + L.nstate * nv * g->ndim * es);
   L.r = off;
   off = align256(off + L.nstate * nv * sizeof(double));
   if (g->ndim == 2) {
     L.fr[0] = off;
-    off = align256(off + (size_t)16 * (g->ny + 2) * (g->nx + 1) * sizeof(double));
+    off = align256(off + (size_t)16 * (g->ny + 2) * (g->nx + 1) * es);
     L.fr[1] = off;
-    off = align256(off + (size_t)16 * (g->ny + 1) * (g->nx + 2) * sizeof(double));
+    off = align256(off + (size_t)16 * (g->ny + 1) * (g->nx + 2) * es);
     L.fl[0] = off;
-    off = align256(off + (size_t)12 * g->ny * (g->nx + 1) * sizeof(double));
+    off = align256(off + (size_t)12 * g->ny * (g->nx + 1) * es);
     L.fl[1] = off;
-    off = align256(off + (size_t)12 * (g->ny + 1) * g->nx * sizeof(double));
+    off = align256(off + (size_t)12 * (g->ny + 1) * g->nx * es);
   } else {
     L.fl[0] = off;
-    off = align256(off + (size_t)9 * (g->nx + 1) * sizeof(double));
+    off = align256(off + (size_t)9 * (g->nx + 1) * es);
   }
   L.total = off;
   return L;
@@ -798,7 +812,9 @@ int check_params(const geno_params* p) {
   if (!p) return fail(GENO_EINVAL, "null params");
   if (p->version != GENO_ABI_VERSION)
     return fail(GENO_EVERSION, "params version %d != %d", p->version, GENO_ABI_VERSION);
-  if (p->precision != GENO_F64) return fail(GENO_EINVAL, "unsupported precision %d", p->precision);
+  if (p->precision != GENO_F64 && p->precision != GENO_MIXED)
+    return fail(GENO_EINVAL, "unsupported precision %d", p->precision);
+  if (!(p->dt_fixed >= 0.0)) return fail(GENO_EINVAL, "dt_fixed must be >= 0");
   if (p->r != 2.0 || p->rL != 2.0) return fail(GENO_EINVAL, "only r = rL = 2 are implemented");
   if (!(p->gamma > 1.0) || !(p->eps > 0.0) || !(p->C > 0.0) || !(p->cfl > 0.0))
     return fail(GENO_EINVAL, "gamma > 1, eps > 0, C > 0 and cfl > 0 are required");
@@ -849,6 +865,7 @@ geno::KParams kparams(const geno_grid* g) {
   k.tc1 = p.tau_c1;
   k.tc2 = p.tau_c2;
   k.cfl = p.cfl;
+  k.dt_fixed = p.dt_fixed;
   return k;
 }
 
@@ -866,38 +883,42 @@ Geo geo_of(const geno_grid* g) {
   return o;
 }
 
+template <typename T>
 struct Bufs {
   Ctrl* ctrl;
   double* part;
   unsigned int* queue[2];
-  double *wst, *dwst, *r, *fr[2], *fl[2];
+  double *wst, *r;
+  T *dwst, *fr[2], *fl[2];
 };
 
-Bufs bufs_of(char* ws, const Layout& L, int ndim) {
-  Bufs b{};
+template <typename T>
+Bufs<T> bufs_of(char* ws, const Layout& L, int ndim) {
+  Bufs<T> b{};
   b.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
   b.part = reinterpret_cast<double*>(ws + L.part);
   b.wst = reinterpret_cast<double*>(ws + L.wst);
-  b.dwst = reinterpret_cast<double*>(ws + L.dwst);
+  b.dwst = reinterpret_cast<T*>(ws + L.dwst);
   b.r = reinterpret_cast<double*>(ws + L.r);
-  b.fl[0] = reinterpret_cast<double*>(ws + L.fl[0]);
+  b.fl[0] = reinterpret_cast<T*>(ws + L.fl[0]);
   if (ndim == 2) {
     b.queue[0] = reinterpret_cast<unsigned int*>(ws + L.queue[0]);
     b.queue[1] = reinterpret_cast<unsigned int*>(ws + L.queue[1]);
-    b.fr[0] = reinterpret_cast<double*>(ws + L.fr[0]);
-    b.fr[1] = reinterpret_cast<double*>(ws + L.fr[1]);
-    b.fl[1] = reinterpret_cast<double*>(ws + L.fl[1]);
+    b.fr[0] = reinterpret_cast<T*>(ws + L.fr[0]);
+    b.fr[1] = reinterpret_cast<T*>(ws + L.fr[1]);
+    b.fl[1] = reinterpret_cast<T*>(ws + L.fl[1]);
   }
   return b;
 }
 
-int launch_init(const geno_grid* g, const Geo& geo, double gamma, double* W, double* dW,
-                const Bufs& B, hipStream_t s) {
+template <typename T>
+int launch_init(const geno_grid* g, const Geo& geo, double gamma, double* W, T* dW,
+                const Bufs<T>& B, hipStream_t s) {
   const size_t n = (size_t)g->nx * g->ny;
   if (g->ndim == 2)
-    HIP_TRY(launch(GENO_K_INIT, k_init<2>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
+    HIP_TRY(launch(GENO_K_INIT, k_init<2, T>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
   else
-    HIP_TRY(launch(GENO_K_INIT, k_init<1>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
+    HIP_TRY(launch(GENO_K_INIT, k_init<1, T>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
   return GENO_OK;
 }
 
@@ -927,44 +948,114 @@ int count_cap(const geno_grid* g) {
 }
 
 // one stage of gks_step: faces and update
-int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, const Bufs& B,
-                 int npart, double* Win, double* dWin, int stage, double* dt_out, int step,
-                 double* Wfinal, double* dWfinal, const Cnt& cnt, hipStream_t s) {
+template <typename T>
+int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, const Bufs<T>& B,
+                 int npart, const double* Win, const T* dWin, int stage, double* dt_out, int step,
+                 double* Wfinal, T* dWfinal, const Cnt& cnt, hipStream_t s) {
   const int want_F = stage == 1;
   const double* part = stage == 1 ? B.part : nullptr;   // dt of the step is reduced once
   if (g->ndim == 2) {
-    HIP_TRY(launch(GENO_K_NORMAL_X, k_normal2d<0>, nblocks(4 * face_rows(g, 0)), s, geo, k, Win,
-                   dWin, B.fr[0], nullptr, B.ctrl, part, npart, dt_out, step, cnt));
-    HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
+    HIP_TRY(launch(GENO_K_NORMAL_X, k_normal2d<0, T>, nblocks(4 * face_rows(g, 0)), s, geo, k,
+                   Win, dWin, B.fr[0], (double*)nullptr, B.ctrl, part, npart, dt_out, step, cnt));
+    HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
                    B.fr[0], B.fl[0], B.ctrl, want_F, cnt, B.queue[0]));
-    HIP_TRY(launch(GENO_K_NORMAL_Y, k_normal2d<1>, nblocks(4 * face_rows(g, 1)), s, geo, k, Win,
-                   dWin, B.fr[1], nullptr, B.ctrl, nullptr, 0, nullptr, 0, cnt));
-    HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
+    HIP_TRY(launch(GENO_K_NORMAL_Y, k_normal2d<1, T>, nblocks(4 * face_rows(g, 1)), s, geo, k,
+                   Win, dWin, B.fr[1], (double*)nullptr, B.ctrl, (const double*)nullptr, 0,
+                   (double*)nullptr, 0, cnt));
+    HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
                    B.fr[1], B.fl[1], B.ctrl, want_F, cnt, B.queue[1]));
-    HIP_TRY(launch(GENO_K_SLOW, k_slow2d, slow_blocks(g), s, geo, k, Win, B.fr[0], B.fr[1],
+    HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T>, slow_blocks(g), s, geo, k, Win, B.fr[0], B.fr[1],
                    B.fl[0], B.fl[1], B.ctrl, want_F, cnt, B.queue[0], B.queue[1]));
   } else {
-    if (part) HIP_TRY(launch(-1, k_dt1d, 1, s, B.part, npart, B.ctrl, k.cfl, dt_out, step));
-    HIP_TRY(launch(GENO_K_FACES_1D, k_faces1d<1>, nblocks((size_t)g->nx + 1), s, geo, k, Win, dWin,
-                   B.fl[0], nullptr, B.ctrl, want_F, cnt));
+    if (part)
+      HIP_TRY(launch(-1, k_dt1d, 1, s, B.part, npart, B.ctrl, k.cfl, k.dt_fixed, dt_out, step));
+    HIP_TRY(launch(GENO_K_FACES_1D, k_faces1d<1, T>, nblocks((size_t)g->nx + 1), s, geo, k, Win,
+                   dWin, B.fl[0], (double*)nullptr, B.ctrl, want_F, cnt));
   }
   const unsigned nc = nblocks((size_t)g->nx * g->ny);
   const int kind = stage == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2;
-  double* fy = g->ndim == 2 ? B.fl[1] : nullptr;
+  const T* fy = g->ndim == 2 ? B.fl[1] : nullptr;
   if (g->ndim == 2) {
     if (stage == 1)
-      HIP_TRY(launch(kind, k_update<2, 1>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
+      HIP_TRY(launch(kind, k_update<2, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
                      B.ctrl, B.part, cnt));
     else
-      HIP_TRY(launch(kind, k_update<2, 2>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0], fy,
-                     B.ctrl, B.part, cnt));
+      HIP_TRY(launch(kind, k_update<2, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0],
+                     fy, B.ctrl, B.part, cnt));
   } else {
     if (stage == 1)
-      HIP_TRY(launch(kind, k_update<1, 1>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
+      HIP_TRY(launch(kind, k_update<1, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
                      B.ctrl, B.part, cnt));
     else
-      HIP_TRY(launch(kind, k_update<1, 2>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0], fy,
-                     B.ctrl, B.part, cnt));
+      HIP_TRY(launch(kind, k_update<1, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0],
+                     fy, B.ctrl, B.part, cnt));
+  }
+  return GENO_OK;
+}
+
+template <typename T>
+int reconstruct_t(const geno_grid* g, double* W, T* dW, int dir, T* face_state, double* chi,
+                  void* ws, hipStream_t s) {
+  const Geo geo = geo_of(g);
+  const geno::KParams k = kparams(g);
+  const Layout L = layout_of(g);
+  const Bufs<T> B = bufs_of<T>((char*)ws, L, g->ndim);
+  int rc = launch_init<T>(g, geo, k.gamma, W, dW, B, s);
+  if (rc) return rc;
+  const Cnt none{nullptr, 0};
+  if (g->ndim == 1) {
+    HIP_TRY(launch(-1, k_faces1d<0, T>, nblocks((size_t)g->nx + 1), s, geo, k, (const double*)W,
+                   (const T*)dW, face_state, chi, (Ctrl*)nullptr, 0, none));
+  } else if (dir == 0) {
+    HIP_TRY(launch(-1, k_normal2d<0, T>, nblocks(4 * face_rows(g, 0)), s, geo, k, (const double*)W,
+                   (const T*)dW, B.fr[0], chi, (Ctrl*)nullptr, (const double*)nullptr, 0,
+                   (double*)nullptr, 0, none));
+    HIP_TRY(launch(-1, k_faces2d<0, 0, T>, nblocks(2 * faces_of(g, 0)), s, geo, k,
+                   (const double*)W, (const T*)B.fr[0], face_state, (Ctrl*)nullptr, 0, none,
+                   (unsigned int*)nullptr));
+  } else {
+    HIP_TRY(launch(-1, k_normal2d<1, T>, nblocks(4 * face_rows(g, 1)), s, geo, k, (const double*)W,
+                   (const T*)dW, B.fr[1], chi, (Ctrl*)nullptr, (const double*)nullptr, 0,
+                   (double*)nullptr, 0, none));
+    HIP_TRY(launch(-1, k_faces2d<1, 0, T>, nblocks(2 * faces_of(g, 1)), s, geo, k,
+                   (const double*)W, (const T*)B.fr[1], face_state, (Ctrl*)nullptr, 0, none,
+                   (unsigned int*)nullptr));
+  }
+  return GENO_OK;
+}
+
+template <typename T>
+int flux_t(const geno_grid* g, const T* face_state, double dt, int dir, T* F, T* Ft, T* Wint,
+           hipStream_t s) {
+  const geno::KParams k = kparams(g);
+  if (g->ndim == 1) {
+    const int nf = g->nx + 1;
+    HIP_TRY(launch(-1, k_flux_points<3, T>, nblocks(nf), s, nf, 1, 0, k, g->dx, g->dy, dt,
+                   face_state, F, Ft, Wint));
+  } else {
+    const int nf = dir == 0 ? g->ny * (g->nx + 1) : (g->ny + 1) * g->nx;
+    const double hn = dir == 0 ? g->dx : g->dy, ht = dir == 0 ? g->dy : g->dx;
+    HIP_TRY(launch(-1, k_flux_points<4, T>, nblocks(nf), s, nf, 2, dir, k, hn, ht, dt, face_state,
+                   F, Ft, Wint));
+  }
+  return GENO_OK;
+}
+
+template <typename T>
+int step_t(const geno_grid* g, double* W, T* dW, void* ws, int nsteps, double* dt_out,
+           const Cnt& cnt, hipStream_t s, Ctrl** ctrl_out) {
+  const Geo geo = geo_of(g);
+  const geno::KParams k = kparams(g);
+  const Layout L = layout_of(g);
+  const Bufs<T> B = bufs_of<T>((char*)ws, L, g->ndim);
+  *ctrl_out = B.ctrl;
+  int rc = launch_init<T>(g, geo, k.gamma, W, dW, B, s);
+  if (rc) return rc;
+  for (int n = 0; n < nsteps; ++n) {
+    rc = launch_stage<T>(g, geo, k, B, L.npart, W, dW, 1, dt_out, n, nullptr, nullptr, cnt, s);
+    if (rc) return rc;
+    rc = launch_stage<T>(g, geo, k, B, L.npart, B.wst, B.dwst, 2, nullptr, n, W, dW, cnt, s);
+    if (rc) return rc;
   }
   return GENO_OK;
 }
@@ -1125,32 +1216,11 @@ int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_
   if (!W || !dW || !face_state || !ws) return fail(GENO_EINVAL, "null pointer");
   if (dir != 0 && !(g->ndim == 2 && dir == 1)) return fail(GENO_EINVAL, "bad direction %d", dir);
   hipStream_t s = (hipStream_t)stream;
-  const Geo geo = geo_of(g);
-  const geno::KParams k = kparams(g);
-  const Layout L = layout_of(g);
-  const Bufs B = bufs_of((char*)ws, L, g->ndim);
-  double* Wd = (double*)W;
-  double* dWd = (double*)dW;
-  rc = launch_init(g, geo, k.gamma, Wd, dWd, B, s);
-  if (rc) return rc;
-  const Cnt none{nullptr, 0};
-  if (g->ndim == 1) {
-    HIP_TRY(launch(-1, k_faces1d<0>, nblocks((size_t)g->nx + 1), s, geo, k, (const double*)Wd,
-                   (const double*)dWd, (double*)face_state, (double*)chi, (Ctrl*)nullptr, 0, none));
-  } else if (dir == 0) {
-    HIP_TRY(launch(-1, k_normal2d<0>, nblocks(4 * face_rows(g, 0)), s, geo, k, Wd, dWd, B.fr[0],
-                   (double*)chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
-                   none));
-    HIP_TRY(launch(-1, k_faces2d<0, 0>, nblocks(2 * faces_of(g, 0)), s, geo, k, Wd, B.fr[0],
-                   (double*)face_state, (Ctrl*)nullptr, 0, none, (unsigned int*)nullptr));
-  } else {
-    HIP_TRY(launch(-1, k_normal2d<1>, nblocks(4 * face_rows(g, 1)), s, geo, k, Wd, dWd, B.fr[1],
-                   (double*)chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
-                   none));
-    HIP_TRY(launch(-1, k_faces2d<1, 0>, nblocks(2 * faces_of(g, 1)), s, geo, k, Wd, B.fr[1],
-                   (double*)face_state, (Ctrl*)nullptr, 0, none, (unsigned int*)nullptr));
-  }
-  return GENO_OK;
+  if (g->params.precision == GENO_MIXED)
+    return reconstruct_t<float>(g, (double*)W, (float*)dW, dir, (float*)face_state, (double*)chi,
+                                ws, s);
+  return reconstruct_t<double>(g, (double*)W, (double*)dW, dir, (double*)face_state,
+                               (double*)chi, ws, s);
 }
 
 int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, void* F, void* Ft,
@@ -1161,18 +1231,11 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
   if (!(dt > 0.0)) return fail(GENO_EINVAL, "dt must be positive");
   if (dir != 0 && !(g->ndim == 2 && dir == 1)) return fail(GENO_EINVAL, "bad direction %d", dir);
   hipStream_t s = (hipStream_t)stream;
-  const geno::KParams k = kparams(g);
-  if (g->ndim == 1) {
-    const int nf = g->nx + 1;
-    HIP_TRY(launch(-1, k_flux_points<3>, nblocks(nf), s, nf, 1, 0, k, g->dx, g->dy, dt,
-                   (const double*)face_state, (double*)F, (double*)Ft, (double*)Wint));
-  } else {
-    const int nf = dir == 0 ? g->ny * (g->nx + 1) : (g->ny + 1) * g->nx;
-    const double hn = dir == 0 ? g->dx : g->dy, ht = dir == 0 ? g->dy : g->dx;
-    HIP_TRY(launch(-1, k_flux_points<4>, nblocks(nf), s, nf, 2, dir, k, hn, ht, dt,
-                   (const double*)face_state, (double*)F, (double*)Ft, (double*)Wint));
-  }
-  return GENO_OK;
+  if (g->params.precision == GENO_MIXED)
+    return flux_t<float>(g, (const float*)face_state, dt, dir, (float*)F, (float*)Ft,
+                         (float*)Wint, s);
+  return flux_t<double>(g, (const double*)face_state, dt, dir, (double*)F, (double*)Ft,
+                        (double*)Wint, s);
 }
 
 int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
@@ -1182,10 +1245,6 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
   if (!W || !dW || !ws) return fail(GENO_EINVAL, "null pointer");
   if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
   hipStream_t s = (hipStream_t)stream;
-  const Geo geo = geo_of(g);
-  const geno::KParams k = kparams(g);
-  const Layout L = layout_of(g);
-  const Bufs B = bufs_of((char*)ws, L, g->ndim);
   Cnt cnt{nullptr, 0};
   if (g_cnt.on) {
     // measurement mode: (re)allocate the per-block count slots and clear them
@@ -1209,25 +1268,19 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
                            s));
     cnt = Cnt{g_cnt.p, g_cnt.cap};
   }
-  double* Wd = (double*)W;
-  double* dWd = (double*)dW;
-  rc = launch_init(g, geo, k.gamma, Wd, dWd, B, s);
+  Ctrl* ctrl = nullptr;
+  if (g->params.precision == GENO_MIXED)
+    rc = step_t<float>(g, (double*)W, (float*)dW, ws, nsteps, dt_out, cnt, s, &ctrl);
+  else
+    rc = step_t<double>(g, (double*)W, (double*)dW, ws, nsteps, dt_out, cnt, s, &ctrl);
   if (rc) return rc;
-  for (int n = 0; n < nsteps; ++n) {
-    rc = launch_stage(g, geo, k, B, L.npart, Wd, dWd, 1, dt_out, n, nullptr, nullptr, cnt, s);
-    if (rc) return rc;
-    rc = launch_stage(g, geo, k, B, L.npart, B.wst, B.dwst, 2, nullptr, n, Wd, dWd, cnt, s);
-    if (rc) return rc;
-  }
   if (stats) {
     Ctrl h;
-    HIP_TRY(hipMemcpyAsync(&h, B.ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stats->guard = (long long)h.guard;
     stats->nonfinite = (long long)h.nonfinite;
-    double last;
-    memcpy(&last, &h.tmin, sizeof last);
-    stats->last_dt = nsteps > 0 ? k.cfl * last : 0.0;
+    stats->last_dt = nsteps > 0 ? h.dt : 0.0;
     if (h.nonfinite) return fail(GENO_ENONPHYS, "%llu non-finite cells", h.nonfinite);
   }
   return GENO_OK;

@@ -32,6 +32,18 @@ namespace gks {
 
 using geno::KParams;
 
+// Type of the time-fit scalars: float64 when the point arithmetic is float32
+// (the fit differences of the time integrals cancel to O(dt^2)), otherwise the
+// arithmetic type itself.
+template <typename R>
+struct Wide {
+  using type = R;
+};
+template <>
+struct Wide<float> {
+  using type = double;
+};
+
 template <typename R>
 struct Prim {
   R rho, U, V, p, lam;
@@ -191,10 +203,12 @@ GENO_HD void mom_a(const Mom<R>& m, const R* a, int i, int j, R* out) {
 // caller hands the face to the full path).
 template <int NV, bool FULL, typename R>
 GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const R* tl,
-                        const R* tr, R dt, const KParams& k, R w, bool want_F, R* F, R* Ft,
-                        R* Wi) {
+                        const R* tr, typename Wide<R>::type dt_w, const KParams& k, R w,
+                        bool want_F, R* F, R* Ft, R* Wi) {
+  using D = typename Wide<R>::type;
   const double g = k.gamma, K = k.K;
   const Prim<R> pl = prim<NV, R>(Wl, g), pr = prim<NV, R>(Wr, g);
+  const R dt = R(dt_w);
   const R tau = R(k.tc1) * dt + R(k.tc2) * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
   const bool slow = tau > R(0.0);
   if (!FULL && slow) return true;
@@ -254,28 +268,30 @@ GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, cons
   if constexpr (FULL) {
     // ---- tau > 0 ----
     // time integrals over [0, d] of the weights of the solution, d = dt/2, dt
-    const R xh = h / tau;
-    const R eh = exp(-xh), emh = -expm1(-xh);
-    const R ef = eh * eh, emf = emh * (R(2.0) - emh);
-    const R tt = tau * tau;
-    const R c1h = h - tau * emh, c1f = dt - tau * emf;
-    const R c5h = R(2.0) * tt - tau * (h + R(2.0) * tau) * eh;
-    const R c5f = R(2.0) * tt - tau * (dt + R(2.0) * tau) * ef;
-    const R c2h = c5h - tau * h, c2f = c5f - tau * dt;
-    const R c3h = R(0.5) * h * h - tau * h + tt * emh;
-    const R c3f = R(0.5) * dt * dt - tau * dt + tt * emf;
-    const R c4h = tau * emh, c4f = tau * emf;
-    const R c6h = tt * emh, c6f = tt * emf;
+    const D dd = dt_w, td = D(tau), hh = D(0.5) * dd;
+    const D xh = hh / td;
+    const D eh = exp(-xh), emh = -expm1(-xh);
+    const D ef = eh * eh, emf = emh * (D(2.0) - emh);
+    const D tt = td * td;
+    const D c1h = hh - td * emh, c1f = dd - td * emf;
+    const D c5h = D(2.0) * tt - td * (hh + D(2.0) * td) * eh;
+    const D c5f = D(2.0) * tt - td * (dd + D(2.0) * td) * ef;
+    const D c2h = c5h - td * hh, c2f = c5f - td * dd;
+    const D c3h = D(0.5) * hh * hh - td * hh + tt * emh;
+    const D c3f = D(0.5) * dd * dd - td * dd + tt * emf;
+    const D c4h = td * emh, c4f = td * emf;
+    const D c6h = tt * emh, c6f = tt * emf;
     // fit F(t) = F + t dF/dt to the two integrals
-    const R idt = R(1.0) / dt, idt2 = R(4.0) * idt * idt;
-    const R f1 = (R(4.0) * c1h - c1f) * idt, g1 = (c1f - R(2.0) * c1h) * idt2;
-    const R f2 = (R(4.0) * c2h - c2f) * idt, g2 = (c2f - R(2.0) * c2h) * idt2;
-    const R f3 = (R(4.0) * c3h - c3f) * idt, g3 = (c3f - R(2.0) * c3h) * idt2;
-    const R f4 = (R(4.0) * c4h - c4f) * idt, g4 = (c4f - R(2.0) * c4h) * idt2;
-    const R f5 = (R(4.0) * c5h - c5f) * idt, g5 = (c5f - R(2.0) * c5h) * idt2;
-    const R f6 = (R(4.0) * c6h - c6f) * idt, g6 = (c6f - R(2.0) * c6h) * idt2;
+    const D idt = D(1.0) / dd, idt2 = D(4.0) * idt * idt;
+    const R f1 = R((D(4.0) * c1h - c1f) * idt), g1 = R((c1f - D(2.0) * c1h) * idt2);
+    const R f2 = R((D(4.0) * c2h - c2f) * idt), g2 = R((c2f - D(2.0) * c2h) * idt2);
+    const R f3 = R((D(4.0) * c3h - c3f) * idt), g3 = R((c3f - D(2.0) * c3h) * idt2);
+    const R f4 = R((D(4.0) * c4h - c4f) * idt), g4 = R((c4f - D(2.0) * c4h) * idt2);
+    const R f5 = R((D(4.0) * c5h - c5f) * idt), g5 = R((c5f - D(2.0) * c5h) * idt2);
+    const R f6 = R((D(4.0) * c6h - c6f) * idt), g6 = R((c6f - D(2.0) * c6h) * idt2);
     // interface state at dt/2
-    const R k1 = emh, k2 = (h + tau) * eh - tau, k3 = h - tau * emh, k4 = h + tau;
+    const R k1 = R(emh), k2 = R((hh + td) * eh - td), k3 = R(hh - td * emh), k4 = R(hh + td);
+    const R ehr = R(eh);
 
     // equilibrium part: <u (abar u + bbar v) psi>_c needs the moments of g_c
     {
@@ -355,7 +371,7 @@ GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, cons
         const R r = ps.rho;
         if (want_F) F[v] = F[v] + w * r * (f4 * U1[v] - f5 * Xs[v] - f6 * Ys[v]);
         Ft[v] = Ft[v] + w * r * (g4 * U1[v] - g5 * Xs[v] - g6 * Ys[v]);
-        Wi[v] = Wi[v] + w * eh * r * (P0[v] - k4 * Zs[v] - tau * A0[v]);
+        Wi[v] = Wi[v] + w * ehr * r * (P0[v] - k4 * Zs[v] - tau * A0[v]);
       }
     }
   }

@@ -64,6 +64,7 @@ geno::KParams params(int ndim, double gamma) {
   k.tc1 = 0.0;
   k.tc2 = 1.0;
   k.cfl = 0.5;
+  k.dt_fixed = 0.0;
   return k;
 }
 

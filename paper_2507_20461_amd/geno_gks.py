@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
-F64 = 0
+F64, MIXED = 0, 1
 ABI_VERSION = 1
 NG = 2
 
@@ -27,7 +27,8 @@ class geno_params(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int), ("precision", ctypes.c_int), ("gamma", ctypes.c_double),
                 ("C", ctypes.c_double), ("eps", ctypes.c_double), ("r", ctypes.c_double),
                 ("rL", ctypes.c_double), ("d", ctypes.c_double * 3), ("tau_c1", ctypes.c_double),
-                ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4)]
+                ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4),
+                ("dt_fixed", ctypes.c_double)]
 
 
 class geno_grid(ctypes.Structure):
@@ -121,6 +122,17 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _need(t, dtype, nelem, name, optional=False):
+    """The library takes plain pointers: check type, device, contiguity and size here."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError("%s is required" % name)
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() < nelem:
+        raise ValueError("%s must be a contiguous CUDA %s tensor of >= %d elements (got %s %s %s)"
+                         % (name, dtype, nelem, t.dtype, tuple(t.shape), t.device))
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -139,6 +151,9 @@ class Grid:
         self.nv = 3 if ndim == 1 else 4
         self.pitch, self.rows = self.g.pitch, self.g.rows
         self.yoff = NG if ndim == 2 else 0
+        self.mixed = self.params.precision == MIXED
+        # element type of dW, face states and face fluxes (W is always float64)
+        self.fdtype = torch.float32 if self.mixed else torch.float64
 
     @property
     def dx(self):
@@ -155,12 +170,16 @@ class Grid:
     def empty_state(self, nfields, device="cuda"):
         return torch.zeros((nfields, self.rows, self.pitch), dtype=torch.float64, device=device)
 
-    def to_device(self, A, device="cuda"):
+    def to_device(self, A, device="cuda", dtype=torch.float64):
         """Interior array [f, ny, nx] -> padded device tensor [f, rows, pitch]."""
         A = np.asarray(A, dtype=np.float64)
         out = np.zeros((A.shape[0], self.rows, self.pitch))
         out[:, self.yoff:self.yoff + self.ny, NG:NG + self.nx] = A
-        return torch.from_numpy(out).to(device)
+        return torch.from_numpy(out).to(device=device, dtype=dtype)
+
+    def grad_to_device(self, A, device="cuda"):
+        """Interior gradients [ndim * nv, ny, nx] -> padded device tensor of the grid's dW type."""
+        return self.to_device(A, device, self.fdtype)
 
     def interior(self, T):
         """Padded tensor -> interior numpy array [f, ny, nx]."""
@@ -184,18 +203,38 @@ class Grid:
         return (4, self.ny, self.nx + 1) if direction == 0 else (4, self.ny + 1, self.nx)
 
 
+def _prod(shape):
+    return int(np.prod(shape))
+
+
+def _check_state(grid, W, dW, ws=None):
+    _need(W, torch.float64, grid.nv * grid.rows * grid.pitch, "W")
+    _need(dW, grid.fdtype, grid.ndim * grid.nv * grid.rows * grid.pitch, "dW")
+    if ws is not None:
+        _need(ws, torch.uint8, lib().gks_workspace_bytes(ctypes.byref(grid.g)), "ws")
+
+
 def geno_reconstruct(grid, W, dW, direction, face_state, chi, ws, stream=None):
+    _check_state(grid, W, dW, ws)
+    _need(face_state, grid.fdtype, _prod(grid.face_state_shape(direction)), "face_state")
+    _need(chi, torch.float64, _prod(grid.chi_shape(direction)), "chi", optional=True)
     _check(lib().geno_reconstruct(ctypes.byref(grid.g), _ptr(W), _ptr(dW), int(direction),
                                   _ptr(face_state), _ptr(chi), _ptr(ws), _stream(stream)))
 
 
 def gks_flux(grid, face_state, dt, direction, F, Ft, Wint, stream=None):
+    _need(face_state, grid.fdtype, _prod(grid.face_state_shape(direction)), "face_state")
+    for name, t in (("F", F), ("Ft", Ft), ("Wint", Wint)):
+        _need(t, grid.fdtype, _prod(grid.flux_shape(direction)), name, optional=True)
     _check(lib().gks_flux(ctypes.byref(grid.g), _ptr(face_state), float(dt), int(direction),
                           _ptr(F), _ptr(Ft), _ptr(Wint), _stream(stream)))
 
 
 def gks_step(grid, W, dW, ws, nsteps, dt_out=None, stats=False, stream=None):
     """nsteps S2O4 steps in place. Returns a geno_stats if stats=True (synchronises)."""
+    _check_state(grid, W, dW, ws)
+    if dt_out is not None:
+        _need(dt_out, torch.float64, int(nsteps), "dt_out")
     st = geno_stats() if stats else None
     rc = lib().gks_step(ctypes.byref(grid.g), _ptr(W), _ptr(dW), _ptr(ws), int(nsteps), _ptr(dt_out),
                         ctypes.byref(st) if st is not None else None, _stream(stream))

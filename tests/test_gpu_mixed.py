@@ -1,0 +1,180 @@
+"""The mixed-precision form (GENO_MIXED) against the CPU FP64 oracle, through
+the C ABI, plus the fixed-dt option.
+
+In the mixed form the reconstruction, tangential step and gas-kinetic flux run
+in float32 and dW and the face buffers are stored in float32, while the
+smoothness indicators' small-eps divisions, the time-fit coefficients, the
+conservative update of W and dt stay in float64. Its results therefore differ
+from the FP64 method by float32 rounding, amplified by the cancellations the
+method contains (differences of neighbouring averages, of face values in the
+gradient update). The bounds below are stated relative to each field's
+scale (its largest |value|; gradients: field scale / cell size):
+
+* one step from the same state: W within MIX_W, dW within MIX_DW. Each face
+  value is a combination of O(10) inputs with weights of O(1) summing to one,
+  so its float32 error is a few units of 2^-24 of the field scale; dt/dx
+  times the flux difference keeps W's change at that level per step
+  (MIX_W = 2e-6; measured up to 3.8e-7). dW is a difference of two face
+  states divided by h, i.e. float32 rounding of the state over h: a few units
+  of 2^-24 of scale/h (MIX_DW = 5e-6; measured up to 1.1e-6).
+* conservation on periodic grids and constant-state preservation are exact
+  (the float32 face fluxes are shared by both neighbours and their
+  differences are exact in float64).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2507_20461_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MIX_W = 2e-6
+MIX_DW = 5e-6
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_20461_amd import geno_gks
+    geno_gks.lib()
+    return geno_gks
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def field_scale(o):
+    o = np.asarray(o, dtype=np.float64)
+    s = np.abs(o.reshape(o.shape[0], -1)).max(axis=1)
+    return np.where(s > 0, s, 1.0)
+
+
+def rel_err(g, o, scale=None):
+    g = np.asarray(g, dtype=np.float64).reshape(np.shape(o)[0], -1)
+    o = np.asarray(o, dtype=np.float64)
+    sc = field_scale(o) if scale is None else np.asarray(scale, dtype=np.float64)
+    o2 = o.reshape(o.shape[0], -1)
+    return float((np.abs(g - o2) / np.maximum(np.abs(o2), sc[:, None])).max())
+
+
+def _case(kind, nx, ny, seed):
+    if kind == "quadrants":
+        W, dW, _ = inputs.quadrants_2d(nx, ny, seed)
+    elif kind == "vortex":
+        W, dW, _ = inputs.vortex_2d(nx, ny, seed, centre=(0.3, 0.35), radius=0.15)
+    else:
+        W, dW = inputs.random_smooth_2d(nx, ny, seed)
+    return W, dW
+
+
+def _grid(G, nx, ny, bc, **kw):
+    return G.Grid(2, nx, ny, bc=bc, precision=G.MIXED, **kw)
+
+
+@pytest.mark.parametrize("kind,bc", [("quadrants", 1), ("smooth", 0), ("vortex", 1)])
+def test_mixed_shadowed_steps(G, oracle, kind, bc):
+    # every mixed step is compared with the oracle's FP64 step from the same
+    # state (the state carried forward is the GPU's own)
+    nx, ny, steps = 48, 40, 12
+    _say("mixed shadow", kind, bc)
+    W, dW = _case(kind, nx, ny, 3)
+    grid = _grid(G, nx, ny, bc)
+    Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prm = oracle.params(ndim=2, bc=bc)
+    worst = [0.0, 0.0, 0.0]
+    for n in range(steps):
+        W0, dW0 = grid.interior(Wd), grid.interior(dWd).astype(np.float64)
+        st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        assert st.nonfinite == 0
+        oW, odW, odt, _ = oracle.step(prm, W0, dW0, 1, dx=grid.dx, dy=grid.dy)
+        gW, gdW = grid.interior(Wd), grid.interior(dWd)
+        gs = np.concatenate([field_scale(oW) / grid.dx] * 2)
+        e = (rel_err(gW, oW), rel_err(gdW, odW, gs), rel_err(dts.cpu().numpy(), odt))
+        worst = [max(a, b) for a, b in zip(worst, e)]
+    _say("mixed shadowed %s: worst W %.3e dW %.3e dt %.3e" % (kind, *worst))
+    assert worst[0] < MIX_W and worst[1] < MIX_DW and worst[2] < MIX_W, worst
+
+
+def test_mixed_reconstruct_matches_oracle(G, oracle):
+    nx, ny = 40, 36
+    W, dW = _case("vortex", nx, ny, 5)
+    grid = _grid(G, nx, ny, 1)
+    Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
+    ws = grid.workspace()
+    prm = oracle.params(ndim=2, bc=1)
+    for d in (0, 1):
+        fs = torch.empty(grid.face_state_shape(d), dtype=torch.float32, device="cuda")
+        G.geno_reconstruct(grid, Wd, dWd, d, fs, None, ws)
+        torch.cuda.synchronize()
+        ref, _ = oracle.face_states(prm, W, dW.astype(np.float32).astype(np.float64), d,
+                                    dx=grid.dx, dy=grid.dy)
+        got = fs.cpu().numpy().astype(np.float64)
+        # [side][gauss][quant][var][...]: compare per (quant, var) on the
+        # field's scale
+        sc = field_scale(W)
+        for q in range(3):
+            g = np.moveaxis(got[:, :, q], 2, 0).reshape(4, -1)
+            o = np.moveaxis(ref[:, :, q], 2, 0).reshape(4, -1)
+            e = rel_err(g, o, sc)
+            _say("mixed reconstruct dir %d quant %d: %.3e" % (d, q, e))
+            assert e < (MIX_W if q == 0 else MIX_DW), (d, q, e)
+
+
+def test_mixed_conservation_periodic(G):
+    nx, ny = 32, 28
+    W, dW, _ = inputs.quadrants_2d(nx, ny, 2)
+    grid = _grid(G, nx, ny, 0)
+    Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
+    st = G.gks_step(grid, Wd, dWd, grid.workspace(), 20, stats=True)
+    assert st.nonfinite == 0
+    gW = grid.interior(Wd)
+    for k in range(4):
+        assert abs(math.fsum(gW[k].ravel()) - math.fsum(W[k].ravel())) < 1e-13 * W[k].size * np.abs(W[k]).max()
+
+
+def test_mixed_constant_state_exact(G):
+    W = np.empty((4, 10, 14))
+    W[:] = np.array([0.8, 0.3, -0.2, 2.1])[:, None, None]
+    grid = _grid(G, 14, 10, 1)
+    Wd, dWd = grid.to_device(W), grid.grad_to_device(np.zeros((8, 10, 14)))
+    G.gks_step(grid, Wd, dWd, grid.workspace(), 5, stats=True)
+    assert np.array_equal(grid.interior(Wd), W) and np.all(grid.interior(dWd) == 0.0)
+
+
+def test_mixed_rejects_fp64_gradients(G):
+    grid = _grid(G, 16, 16, 1)
+    W, dW, _ = inputs.quadrants_2d(16, 16, 0)
+    with pytest.raises(ValueError):
+        G.gks_step(grid, grid.to_device(W), grid.to_device(dW), grid.workspace(), 1)
+
+
+def test_fixed_dt_matches_oracle(G, oracle):
+    # dt_fixed > 0 replaces the CFL step on both sides (FP64 parity bar)
+    nx, ny = 32, 24
+    W, dW, _ = inputs.quadrants_2d(nx, ny, 6)
+    dt = 0.4 / nx * 0.5
+    grid = G.Grid(2, nx, ny, bc=1, dt_fixed=dt)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    dts = torch.zeros(6, dtype=torch.float64, device="cuda")
+    G.gks_step(grid, Wd, dWd, grid.workspace(), 6, dt_out=dts, stats=True)
+    assert np.all(dts.cpu().numpy() == dt)
+    # shadow the last step against the oracle with the same fixed dt
+    oW, odW, odt, _ = oracle.step(oracle.params(ndim=2, bc=1), W, dW, 6, fixed_dt=dt)
+    assert np.all(odt == dt)
+    gW = grid.interior(Wd)
+    # a whole 6-step run: the quadrant jumps amplify rounding only mildly in
+    # so few steps
+    e = rel_err(gW, oW)
+    _say("fixed dt 6 steps: %.3e" % e)
+    assert e < 1e-10
