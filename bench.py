@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -30,9 +31,10 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # rocprofv3 kernel names of the measured kernel kinds (2-D path)
-ROCPROF_NAMES = {"init": "k_init<2>", "normal_x": "k_normal2d<0>", "normal_y": "k_normal2d<1>",
-                 "faces_x": "k_faces2d<0, 1>", "faces_y": "k_faces2d<1, 1>", "slow": "k_slow2d",
-                 "update_1": "k_update<2, 1>", "update_2": "k_update<2, 2>"}
+ROCPROF_NAMES = {"init": "k_init<2, double>", "normal_x": "k_normal2d<0, double>",
+                 "normal_y": "k_normal2d<1, double>", "faces_x": "k_faces2d<0, 1, double>",
+                 "faces_y": "k_faces2d<1, 1, double>", "slow": "k_slow2d<double>",
+                 "update_1": "k_update<2, 1, double>", "update_2": "k_update<2, 2, double>"}
 COUNTERS = os.path.join(ROOT, "profiles", "faces_fp64_512_counters.json")
 
 
@@ -45,6 +47,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP64 vs mixed comparison at 2048^2")
     return ap.parse_args()
 
 
@@ -86,6 +89,98 @@ def cpu_baseline(W, dW, n, min_seconds=10.0):
             "kind": "oracle",
             "sample": "%d S2O4 steps (2 stages each) of the %dx%d quadrant state from its initial data, %.1f s wall"
                       % (steps, n, n, dt)}
+
+
+def _finite(x):
+    """JSON-safe copy: non-finite floats become None."""
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
+
+
+def forms_comparison(G, inputs, np, torch, seed, n=2048, steps=200, acc_steps=100):
+    """FP64 and mixed-precision forms on the 2048^2 quadrants + vortex grid
+    (transmissive, CFL 0.5): throughput of each over 200 steps, their
+    difference after those steps, and the L1 error of each after 100 steps
+    against the FP64 solution on the 2x refined grid (4096^2, restricted by
+    2x2 averaging) at the same time. The refined run takes a fixed dt of
+    0.8 x half the smallest coarse step (fine CFL <= 0.4) and one last shorter
+    step to end exactly at the coarse run's time. (Later in this flow,
+    resolved shear-layer vortices reach near-zero pressure, and the 4096^2 run
+    loses positivity between t = 0.035 and 0.04; the accuracy comparison is
+    therefore taken at t ~ 0.018.)"""
+    W, dW, _ = inputs.vortex_2d(n, n, seed)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res, finals, early = {}, {}, {}
+    for name, prec in (("fp64", G.F64), ("mixed", G.MIXED)):
+        grid = G.Grid(2, n, n, bc=G.BC_TRANSMISSIVE, precision=prec)
+        ws = grid.workspace()
+        Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
+        dts = torch.zeros(steps, dtype=torch.float64, device="cuda")
+        # untimed: acc_steps steps for the accuracy comparison
+        G.gks_step(grid, Wd, dWd, ws, acc_steps, dt_out=dts, stats=True)
+        early[name] = grid.interior(Wd)
+        d_early = dts[:acc_steps].cpu().numpy()
+        # timed: steps steps from the initial data
+        Wd.copy_(grid.to_device(W))
+        dWd.copy_(grid.grad_to_device(dW))
+        torch.cuda.synchronize()
+        e0.record()
+        G.gks_step(grid, Wd, dWd, ws, steps, dt_out=dts)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        finals[name] = grid.interior(Wd)
+        phys = bool(np.isfinite(finals[name]).all() and (finals[name][0] > 0).all())
+        dth = dts.cpu().numpy()
+        res[name] = {"value": round(2.0 * n * n * steps / (ms / 1e3) / 1e6, 3),
+                     "ms_per_step": round(ms / steps, 5), "t_end": float(dth.sum()),
+                     "rho_range": [float(finals[name][0].min()), float(finals[name][0].max())],
+                     "t_acc": float(d_early.sum()), "dt_min_acc": float(d_early.min()),
+                     "physical_after_run": phys}
+        if prec == G.MIXED:
+            res[name]["eps_ulps"] = grid.params.eps_ulps
+        del ws, Wd, dWd
+    out = {"workload": "2d-euler-%dx%d-quadrants+vortex" % (n, n), "steps": steps, "cfl": 0.5, "seed": seed,
+           "fp64": res["fp64"], "mixed": res["mixed"],
+           "speedup_mixed_vs_fp64": round(res["mixed"]["value"] / res["fp64"]["value"], 4)}
+    fields = ("rho", "rhoU", "rhoV", "rhoE")
+    d = finals["mixed"] - finals["fp64"]
+    out["mixed_minus_fp64_after_%d_steps" % steps] = {
+        "l1": dict(zip(fields, map(float, np.abs(d).mean(axis=(1, 2))))),
+        "linf": dict(zip(fields, map(float, np.abs(d).max(axis=(1, 2)))))}
+    # reference: FP64 on the 2x refined grid to the FP64 run's time after acc_steps
+    m = 2 * n
+    Wf, dWf, _ = inputs.vortex_2d(m, m, seed)
+    T = res["fp64"]["t_acc"]
+    dt_f = 0.8 * 0.5 * res["fp64"]["dt_min_acc"]
+    n_f = int(T // dt_f)
+    rest = T - n_f * dt_f
+    grid = G.Grid(2, m, m, bc=G.BC_TRANSMISSIVE, dt_fixed=dt_f)
+    ws = grid.workspace()
+    Wd, dWd = grid.to_device(Wf), grid.to_device(dWf)
+    out["accuracy"] = {"steps": acc_steps, "t": T,
+                       "reference": "FP64 on %dx%d, %d steps of dt %.6g + 1 of %.6g, 2x2 averaged"
+                                    % (m, m, n_f, dt_f, rest)}
+    try:
+        G.gks_step(grid, Wd, dWd, ws, n_f, stats=True)
+        if rest > 1e-6 * dt_f:
+            G.gks_step(G.Grid(2, m, m, bc=G.BC_TRANSMISSIVE, dt_fixed=rest), Wd, dWd, ws, 1, stats=True)
+    except G.GenoError as e:
+        out["accuracy"]["reference_error"] = str(e)
+        return out
+    ref = grid.interior(Wd).reshape(4, n, 2, n, 2).mean(axis=(2, 4))
+    del ws, Wd, dWd
+    l1 = {k: np.abs(early[k] - ref).mean(axis=(1, 2)) for k in early}
+    rel = abs(l1["mixed"][0] - l1["fp64"][0]) / l1["fp64"][0]
+    out["accuracy"]["l1_vs_refined_fp64"] = {k: dict(zip(fields, map(float, l1[k]))) for k in l1}
+    out["accuracy"]["equal_l1_density"] = bool(rel <= 0.05)
+    out["accuracy"]["l1_density_rel_diff"] = float(rel)
+    return out
 
 
 def main():
@@ -198,6 +293,9 @@ def main():
         "kernels": kernels,
         "ms_per_step_with_kernel_events": round(ms_events / args.steps, 5) if ms_events else None,
     }
+    if not args.no_forms:
+        del ws, Wd, dWd
+        out["forms"] = _finite(forms_comparison(G, inputs, np, torch, args.seed))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)
     print(json.dumps(out), flush=True)

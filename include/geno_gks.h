@@ -48,7 +48,7 @@ extern "C" {
 #define GENO_EINVAL (-1)     /* null pointer, bad size, unsupported parameter */
 #define GENO_EVERSION (-2)   /* geno_params.version != GENO_ABI_VERSION */
 #define GENO_EHIP (-3)       /* a HIP runtime call failed */
-#define GENO_ENONPHYS (-4)   /* non-finite state found when stats were read */
+#define GENO_ENONPHYS (-4)   /* non-physical state found when stats were read */
 
 /* boundary conditions (per side) */
 #define GENO_BC_PERIODIC 0
@@ -76,7 +76,15 @@ extern "C" {
  * bc: x-low, x-high, y-low, y-high (GENO_BC_*); periodic must be set on both
  *   sides of an axis.
  * dt_fixed: if > 0, every step of gks_step uses this dt instead of the CFL
- *   condition (the default is 0). */
+ *   condition (the default is 0).
+ * eps_ulps: GENO_MIXED only. float32 face values and the gradients formed
+ *   from their differences carry rounding of several units in the last place,
+ *   and with eps = 1e-15 the indicators of that noise read as discontinuities.
+ *   The mixed form therefore uses eps + (eps_ulps * 2^-24 * qmax)^2 in Eq. (5)
+ *   and (8), qmax the largest |value| of the stencil (0 gives the plain eps).
+ *   In a run, the float32 fluxes also leave rounding of about one unit in the
+ *   last place per step in W (dt/dx times the rounding of F), which
+ *   accumulates over the steps; the default is 64. */
 typedef struct geno_params {
   int version;
   int precision;   /* GENO_F64 or GENO_MIXED */
@@ -91,6 +99,7 @@ typedef struct geno_params {
   double cfl;
   int bc[4];
   double dt_fixed;
+  double eps_ulps;
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */
@@ -107,7 +116,8 @@ typedef struct geno_grid {
 /* Counters returned by gks_step when asked for. */
 typedef struct geno_stats {
   long long guard;      /* point states replaced by their cell average (rho<=0, p<=0 or non-finite) */
-  long long nonfinite;  /* non-finite interior cells after the last step */
+  long long nonfinite;  /* non-physical interior cells (non-finite, rho <= 0 or p <= 0) summed
+                           over the steps of the call */
   double last_dt;       /* time step of the last step */
 } geno_stats;
 
@@ -179,7 +189,8 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
  * ws: workspace of gks_workspace_bytes(g) bytes.
  * dt_out (device, may be NULL): nsteps doubles, the step sizes.
  * stats (host, may be NULL): if given, the call waits for the stream and
- *   fills the counters; returns GENO_ENONPHYS if a non-finite cell is found. */
+ *   fills the counters; returns GENO_ENONPHYS if a non-physical cell
+ *   (non-finite, rho <= 0 or p <= 0) was found after any step. */
 int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
              geno_stats* stats, void* stream);
 
@@ -202,9 +213,10 @@ enum {
 /* Work classes counted per kernel kind while counting is enabled. */
 enum {
   GENO_W_UNITS = 0,    /* threads' work units: face-row variables, faces, cells */
-  GENO_W_TANH,         /* reserved (not counted) */
+  GENO_W_EQUAL,        /* gas-kinetic points with tau = 0 and equal states (no
+                          half-space moments) */
   GENO_W_LOW,          /* reconstructions that form the low-order part (chi < 1) */
-  GENO_W_FAST,         /* gas-kinetic points evaluated with tau = 0 */
+  GENO_W_FAST,         /* gas-kinetic points with tau = 0 and different states */
   GENO_W_SLOW,         /* gas-kinetic points evaluated with tau > 0 */
   GENO_W_GUARD,        /* point states replaced by the cell average */
   GENO_NCLASS

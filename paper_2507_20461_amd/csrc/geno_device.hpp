@@ -4,13 +4,18 @@
 // intermediate in registers.
 //
 // Templated on the arithmetic type R of the reconstruction (double, float)
-// and on the type D of the small-epsilon divisions of the smoothness
-// indicators (always double on the GPU: eps = 1e-15 and IS^2 ~ 1e-30 are
-// out of FP32 range). The functions are host+device so that the same code can
-// be instantiated with an operation-counting type on the host.
+// and on the type D of the smoothness indicators (always double on the GPU:
+// eps = 1e-15 and IS^2 ~ 1e-30 are out of FP32 range, and the indicators of
+// the normal step are formed from the float64 cell data, because rounding
+// nearly constant data to float32 leaves steps of one unit in the last place
+// whose indicators, ~1e-15 |q|^2, would read as discontinuities). The
+// functions are host+device so that the same code can be instantiated with an
+// operation-counting type on the host.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #define GENO_HD __host__ __device__ __forceinline__
 
@@ -27,6 +32,7 @@ struct KParams {
   double tc1, tc2;    // collision time coefficients
   double cfl;
   double dt_fixed;    // > 0: fixed time step instead of the CFL condition
+  double eps_ulps;    // float32 data: eps floor in units of 2^-24 of the stencil magnitude
 };
 
 // Path function chi = tanh(C alpha)/tanh(C) (Eq. (4)) of the ultimate
@@ -36,14 +42,33 @@ struct KParams {
 // single division remains. tanh(x) rounds to 1 for x > 19.8 (its distance to
 // 1 is below 1e-17), so the call is skipped there.
 template <typename D>
-GENO_HD D path_chi(D IStau, D ISH, D ISL, const KParams& k) {
-  const D a = ISH + k.eps, b = ISL + k.eps, t2 = IStau * IStau;
+GENO_HD D path_chi(D IStau, D ISH, D ISL, D eps, const KParams& k) {
+  const D a = ISH + eps, b = ISL + eps, t2 = IStau * IStau;
   const D a2 = a * a, b2 = b * b;
   const D num = (a2 + t2) * b2;
   const D alpha = 2.0 * num / (num + (b2 + t2) * a2);
   const D x = k.C * alpha;
   const D th = (x > 19.8) ? D(1.0) : tanh(x);
   return (k.tanhC == 1.0) ? th : th / k.tanhC;
+}
+
+// eps of Eq. (5) and (8). With float32 reconstruction data (the mixed form)
+// the absolute 1e-15 lies below the data's own rounding: float32 face values,
+// and the gradients formed from differences of them, carry rounding of a few
+// to ~10 units in the last place of |q| (2^-24 |q|) from the few dozen
+// operations that produce them, and indicators of that noise (>= 4e-15 |q|^2)
+// would read as discontinuities. There eps is raised by
+// (eps_ulps 2^-24 qmax)^2, qmax the largest |value| of the stencil; float64
+// data keep the plain eps.
+template <typename R, typename D>
+GENO_HD D eps_of(D qmax, const KParams& k) {
+  if constexpr (std::is_same<R, float>::value) {
+    const D f = D(k.eps_ulps * (1.0 / 16777216.0)) * qmax;
+    return k.eps + f * f;
+  } else {
+    (void)qmax;
+    return D(k.eps);
+  }
 }
 
 // Linear high-order reconstruction p^7 on S_0 = {j-1, j, j+1, j+2} (Sec. 4.2)
@@ -69,35 +94,37 @@ GENO_HD void linear_p7(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2, R& qH, R&
 // denominator. When chi == 1 exactly the low-order part carries weight 0 and
 // is not formed. Returns true on the low-order branch (chi < 1).
 template <typename R, typename D>
-GENO_HD bool geno_side(R Qm, R Q0, R Q1, R Q2, R Gm, R qH, R hqH, const KParams& k, R& val,
+GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, const KParams& k, R& val,
                        R& hder, D& chi) {
-  const R B1 = R(2.0) * (Q0 - Qm) - Gm, C1 = (Q0 - Qm) - Gm;
-  const R B2 = R(0.5) * (Q1 - Qm), C2 = R(0.5) * (Q1 - R(2.0) * Q0 + Qm);
-  const R B3 = R(0.5) * (R(4.0) * Q1 - R(3.0) * Q0 - Q2), C3 = R(0.5) * (Q0 - R(2.0) * Q1 + Q2);
-  const R c13 = R(13.0 / 3.0);
-  const D IS1 = D(B1 * B1 + c13 * (C1 * C1));
-  const D IS2 = D(B2 * B2 + c13 * (C2 * C2));
-  const D IS3 = D(B3 * B3 + c13 * (C3 * C3));
+  const D Bd1 = D(2.0) * (Q0 - Qm) - Gm, Cd1 = (Q0 - Qm) - Gm;
+  const D Bd2 = D(0.5) * (Q1 - Qm), Cd2 = D(0.5) * (Q1 - D(2.0) * Q0 + Qm);
+  const D Bd3 = D(0.5) * (D(4.0) * Q1 - D(3.0) * Q0 - Q2), Cd3 = D(0.5) * (Q0 - D(2.0) * Q1 + Q2);
+  const D c13 = D(13.0 / 3.0);
+  const D IS1 = Bd1 * Bd1 + c13 * (Cd1 * Cd1);
+  const D IS2 = Bd2 * Bd2 + c13 * (Cd2 * Cd2);
+  const D IS3 = Bd3 * Bd3 + c13 * (Cd3 * Cd3);
   const D ISH = fmax(IS1, fmax(IS2, IS3));
   const D ISL = fmin(IS1, fmin(IS2, IS3));
   const D IStau = fabs(0.5 * (IS2 + IS3) - IS1);
-  chi = path_chi<D>(IStau, ISH, ISL, k);
+  const D eps = eps_of<R, D>(fmax(fmax(fabs(Qm), fabs(Q0)), fmax(fabs(Q1), fabs(Q2))), k);
+  chi = path_chi<D>(IStau, ISH, ISL, eps, k);
   if (chi == 1.0) {
     val = qH;
     hder = hqH;
     return false;
   }
-  D e1 = IS1 + k.eps, e2 = IS2 + k.eps, e3 = IS3 + k.eps;
+  D e1 = IS1 + eps, e2 = IS2 + eps, e3 = IS3 + eps;
   e1 = e1 * e1;
   e2 = e2 * e2;
   e3 = e3 * e3;
   const D w1 = k.d1 * (e2 * e3), w2 = k.d2 * (e1 * e3), w3 = k.d3 * (e1 * e2);
   const D inv = 1.0 / (w1 + w2 + w3);
   const R o1 = R(w1 * inv), o2 = R(w2 * inv), o3 = R(w3 * inv);
-  const R s6 = R(1.0 / 6.0);
-  const R p1 = Q0 + R(0.5) * B1 + s6 * C1;
-  const R p2 = Q0 + R(0.5) * B2 + s6 * C2;
-  const R p3 = Q0 + R(0.5) * B3 + s6 * C3;
+  const R B1 = R(Bd1), C1 = R(Cd1), B2 = R(Bd2), C2 = R(Cd2), B3 = R(Bd3), C3 = R(Cd3);
+  const R q0 = R(Q0), s6 = R(1.0 / 6.0);
+  const R p1 = q0 + R(0.5) * B1 + s6 * C1;
+  const R p2 = q0 + R(0.5) * B2 + s6 * C2;
+  const R p3 = q0 + R(0.5) * B3 + s6 * C3;
   const R qL = o1 * p1 + o2 * p2 + o3 * p3;
   const R hqL = o1 * (B1 + C1) + o2 * (B2 + C2) + o3 * (B3 + C3);
   const R x = R(chi), xm = R(1.0 - chi);
@@ -106,15 +133,16 @@ GENO_HD bool geno_side(R Qm, R Q0, R Q1, R Q2, R Gm, R qH, R hqH, const KParams&
   return true;
 }
 
-// Both states at face j+1/2 for one component from cells j-1..j+2. The right
-// state (cell j+1) is the left-state formula applied to the data reflected
-// about the face: Q~_m = Q_{1-m}, G~_m = -G_{1-m}; its derivative changes sign.
+// Both states at face j+1/2 for one component from cells j-1..j+2 (data in
+// the indicator type D, the linear part evaluated in R). The right state
+// (cell j+1) is the left-state formula applied to the data reflected about
+// the face: Q~_m = Q_{1-m}, G~_m = -G_{1-m}; its derivative changes sign.
 // Returns the number of sides on the low-order branch.
 template <typename R, typename D>
-GENO_HD int geno_face(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2, const KParams& k, R& vl,
+GENO_HD int geno_face(D Qm, D Q0, D Q1, D Q2, D Gm, D G0, D G1, D G2, const KParams& k, R& vl,
                       R& dl, D& xl, R& vr, R& dr, D& xr) {
   R qH, hqH;
-  linear_p7<R>(Qm, Q0, Q1, Q2, Gm, G0, G1, G2, qH, hqH);
+  linear_p7<R>(R(Qm), R(Q0), R(Q1), R(Q2), R(Gm), R(G0), R(G1), R(G2), qH, hqH);
   int n = geno_side<R, D>(Qm, Q0, Q1, Q2, Gm, qH, hqH, k, vl, dl, xl);
   R dm;
   n += geno_side<R, D>(Q2, Q1, Q0, Qm, -G2, qH, -hqH, k, vr, dm, xr);
@@ -139,7 +167,8 @@ GENO_HD bool tangential(R phm, R ph0, R php, const KParams& k, R& v0, R& v1, R& 
   const R sm = ph0 - phm, sp = php - ph0;
   const R sc = R(0.5) * (sm + sp), d2 = sp - sm;
   const D ISm = D(sm * sm), ISp = D(sp * sp);
-  const D chi = path_chi<D>(fabs(ISp - ISm), fmax(ISm, ISp), fmin(ISm, ISp), k);
+  const D eps = eps_of<R, D>(D(fmax(fmax(fabs(phm), fabs(ph0)), fabs(php))), k);
+  const D chi = path_chi<D>(fabs(ISp - ISm), fmax(ISm, ISp), fmin(ISm, ISp), eps, k);
   const R eta = R(GENO_ETA);
   R s, th0, th1;
   bool low = false;
@@ -149,7 +178,7 @@ GENO_HD bool tangential(R phm, R ph0, R php, const KParams& k, R& v0, R& v1, R& 
     th1 = sc + eta * d2;
   } else {
     low = true;
-    D em = ISm + k.eps, ep = ISp + k.eps;
+    D em = ISm + eps, ep = ISp + eps;
     em = em * em;
     ep = ep * ep;
     // weights 1/(IS_-+eps)^2 and 1/(IS_++eps)^2 over a common denominator

@@ -140,7 +140,7 @@ __host__ __device__ __forceinline__ size_t at(const Geo& g, int f, int j, int i)
 struct Ctrl {
   double dt;                        // time step of the current step
   unsigned long long guard;         // positivity fall-backs
-  unsigned long long nonfinite;     // non-finite cells after a stage-2 update
+  unsigned long long nonfinite;     // non-physical cells (non-finite, rho <= 0 or p <= 0) after a stage-2 update
   unsigned int qcount[2];           // queued tau > 0 faces per direction
 };
 
@@ -301,14 +301,14 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
     const int v = t / plane, o = t - v * plane;
     const int a = o / n1, b = o - a * n1;
     const double h = DIR == 0 ? g.dx : g.dy;
-    T Q[4], G[4];
+    double Q[4], G[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       size_t id;
       if (DIR == 0) id = at(g, v, a - 1, b - 2 + m);
       else id = at(g, v, a - 2 + m, b - 1);
-      Q[m] = T(W[id]);
-      G[m] = T(h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch]);
+      Q[m] = W[id];
+      G[m] = h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
     }
     T vl, dl, vr, dr;
     double xl, xr;
@@ -442,13 +442,14 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       tr[v] = Dt[1][perm[v]] * iht;
     }
     T F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
-    bool slow;   // MODE 1: tau > 0, not evaluated; MODE 2: evaluated, tau > 0
+    int pk;   // point kind; MODE 1: PT_SLOW not evaluated; MODE 2: evaluated
     if constexpr (MODE == 1)
-      slow = gks::point_flux<4, false, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F,
-                                          Ft, Wi);
+      pk = gks::point_flux<4, false, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F, Ft,
+                                        Wi);
     else
-      slow = gks::point_flux<4, true, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F,
-                                         Ft, Wi);
+      pk = gks::point_flux<4, true, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F, Ft,
+                                       Wi);
+    const bool slow = pk == gks::PT_SLOW;
     bool pair_slow = false;
     if constexpr (MODE == 1) {
       // every lane takes part in the exchange (no short-circuit around it:
@@ -494,7 +495,8 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
     // counted where it is evaluated)
     const bool ev = valid && !pair_slow;
     wc[GENO_W_UNITS] += (ev && q == 0) ? 1u : 0u;
-    wc[GENO_W_FAST] += (ev && !slow) ? 1u : 0u;
+    wc[GENO_W_EQUAL] += (ev && pk == gks::PT_EQUAL) ? 1u : 0u;
+    wc[GENO_W_FAST] += (ev && pk == gks::PT_FAST) ? 1u : 0u;
     wc[GENO_W_SLOW] += (ev && slow) ? 1u : 0u;
     wc[GENO_W_LOW] += ev ? nlow : 0u;
     wc[GENO_W_GUARD] += ev ? nguard : 0u;
@@ -560,17 +562,18 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
                                                    int want_F, Cnt cnt) {
   const int nfc = g.nx + 1;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned int nlow = 0, nguard = 0, nslow = 0;
+  unsigned int nlow = 0, nguard = 0;
+  int pk = -1;
   if (f < nfc) {
     T S[2][3], Dn[2][3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-      T Q[4], G[4];
+      double Q[4], G[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const size_t id = at(g, v, 0, f - 2 + m);
-        Q[m] = T(W[id]);
-        G[m] = T(g.dx * (double)dW[id]);
+        Q[m] = W[id];
+        G[m] = g.dx * (double)dW[id];
       }
       double xl, xr;
       nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
@@ -610,9 +613,8 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
         nr[v] = Dn[1][v] * ih;
       }
       T F[3] = {0, 0, 0}, Ft[3] = {0, 0, 0}, Wi[3] = {0, 0, 0};
-      const bool sl = gks::point_flux<3, true, T>(S[0], S[1], nl, nr, nullptr, nullptr, dt, k,
-                                                  T(1.0), want_F != 0, F, Ft, Wi);
-      nslow = sl ? 1u : 0u;
+      pk = gks::point_flux<3, true, T>(S[0], S[1], nl, nr, nullptr, nullptr, dt, k, T(1.0),
+                                       want_F != 0, F, Ft, Wi);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         if (want_F) out[(size_t)(0 * 3 + v) * nfc + f] = F[v];
@@ -625,8 +627,9 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
     unsigned int wc[GENO_NCLASS] = {};
     wc[GENO_W_UNITS] = f < nfc ? 1u : 0u;
     wc[GENO_W_LOW] = nlow;
-    wc[GENO_W_FAST] = (f < nfc && !nslow) ? 1u : 0u;
-    wc[GENO_W_SLOW] = nslow;
+    wc[GENO_W_EQUAL] = pk == gks::PT_EQUAL ? 1u : 0u;
+    wc[GENO_W_FAST] = pk == gks::PT_FAST ? 1u : 0u;
+    wc[GENO_W_SLOW] = pk == gks::PT_SLOW ? 1u : 0u;
     wc[GENO_W_GUARD] = nguard;
     block_count(cnt, GENO_K_FACES_1D, wc);
   }
@@ -735,9 +738,13 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
     for (int v = 0; v < NV * NDIM; ++v) dWout[at(g, v, j, i)] = dw[v];
     scatter_ghosts<NDIM, T>(g, Wout, dWout, j, i, w, dw);
     if constexpr (STAGE == 2) {
+      // non-physical cell: a non-finite value, rho <= 0 or p <= 0
       bool bad = false;
 #pragma unroll
       for (int v = 0; v < NV; ++v) bad |= !isfinite(w[v]);
+      double ke = w[1] * w[1];
+      if constexpr (NV == 4) ke += w[2] * w[2];
+      bad |= !(w[0] > 0.0) || !((k.gamma - 1.0) * (w[NV - 1] - 0.5 * ke / w[0]) > 0.0);
       if (bad) atomicAdd(&ctrl->nonfinite, 1ull);
       tloc = cell_tmin<NDIM>(g, w, k.gamma);
     }
@@ -815,6 +822,7 @@ int check_params(const geno_params* p) {
   if (p->precision != GENO_F64 && p->precision != GENO_MIXED)
     return fail(GENO_EINVAL, "unsupported precision %d", p->precision);
   if (!(p->dt_fixed >= 0.0)) return fail(GENO_EINVAL, "dt_fixed must be >= 0");
+  if (!(p->eps_ulps >= 0.0)) return fail(GENO_EINVAL, "eps_ulps must be >= 0");
   if (p->r != 2.0 || p->rL != 2.0) return fail(GENO_EINVAL, "only r = rL = 2 are implemented");
   if (!(p->gamma > 1.0) || !(p->eps > 0.0) || !(p->C > 0.0) || !(p->cfl > 0.0))
     return fail(GENO_EINVAL, "gamma > 1, eps > 0, C > 0 and cfl > 0 are required");
@@ -866,6 +874,7 @@ geno::KParams kparams(const geno_grid* g) {
   k.tc2 = p.tau_c2;
   k.cfl = p.cfl;
   k.dt_fixed = p.dt_fixed;
+  k.eps_ulps = p.eps_ulps;
   return k;
 }
 
@@ -1172,6 +1181,7 @@ int geno_params_default(geno_params* p) {
   p->tau_c2 = 1.0;
   p->cfl = 0.5;
   for (int i = 0; i < 4; ++i) p->bc[i] = GENO_BC_TRANSMISSIVE;
+  p->eps_ulps = 64.0;
   return GENO_OK;
 }
 
@@ -1281,7 +1291,9 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
     stats->guard = (long long)h.guard;
     stats->nonfinite = (long long)h.nonfinite;
     stats->last_dt = nsteps > 0 ? h.dt : 0.0;
-    if (h.nonfinite) return fail(GENO_ENONPHYS, "%llu non-finite cells", h.nonfinite);
+    if (h.nonfinite)
+      return fail(GENO_ENONPHYS, "%llu non-physical cells (non-finite, rho <= 0 or p <= 0)",
+                  h.nonfinite);
   }
   return GENO_OK;
 }

@@ -195,14 +195,18 @@ GENO_HD void mom_a(const Mom<R>& m, const R* a, int i, int j, R* out) {
   }
 }
 
+// Kinds of gas-kinetic point, returned by point_flux.
+enum { PT_EQUAL = 0, PT_FAST = 1, PT_SLOW = 2 };
+
 // Point flux. Wl, Wr: states (face frame, normal momentum first); nl, nr,
 // tl, tr: physical normal / tangential derivatives (tl, tr unused in 1-D).
 // Accumulates w * F, w * dF/dt and w * W(dt/2) into F, Ft, Wi (F skipped
-// unless want_F). Returns whether the collision time is positive. With
-// FULL = false such a point is not evaluated and nothing is accumulated (the
-// caller hands the face to the full path).
+// unless want_F). Returns PT_SLOW if the collision time is positive, else
+// PT_EQUAL for equal states and PT_FAST otherwise. With FULL = false a
+// PT_SLOW point is not evaluated and nothing is accumulated (the caller hands
+// the face to the full path).
 template <int NV, bool FULL, typename R>
-GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const R* tl,
+GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const R* tl,
                         const R* tr, typename Wide<R>::type dt_w, const KParams& k, R w,
                         bool want_F, R* F, R* Ft, R* Wi) {
   using D = typename Wide<R>::type;
@@ -211,29 +215,42 @@ GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, cons
   const R dt = R(dt_w);
   const R tau = R(k.tc1) * dt + R(k.tc2) * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
   const bool slow = tau > R(0.0);
-  if (!FULL && slow) return true;
-  // half-space u^0, u^1 moments of both sides
-  const R sl = sqrt(pl.lam), sr = sqrt(pr.lam);
-  const R tl0 = R(0.5) * erfc(-sl * pl.U), tr0 = R(0.5) * erfc(sr * pr.U);
-  const R isp = R(0.28209479177387814347);  // 1 / (2 sqrt(pi))
-  const R tl1 = exp(-pl.lam * pl.U * pl.U) * isp / sl;
-  const R tr1 = exp(-pr.lam * pr.U * pr.U) * isp / sr;
-  const R lu0 = tl0, lu1 = pl.U * tl0 + tl1;
-  const R ru0 = tr0, ru1 = pr.U * tr0 - tr1;
-  const R hl = R(0.5) / pl.lam, hr = R(0.5) / pr.lam;
-  const R lu2 = pl.U * lu1 + hl * lu0, ru2 = pr.U * ru1 + hr * ru0;
-  // interface equilibrium W_c = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}
+  if (!FULL && slow) return PT_SLOW;
+  // interface equilibrium W_c = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}.
+  // Equal states give W_c = W_l exactly (the two half-space moments add up
+  // to the full ones), so the half-space moments are only formed when the
+  // states differ or the full solution needs them.
+  bool same = true;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) same = same && (Wl[v] == Wr[v]);
+  R lu0 = R(0), lu1 = R(0), ru0 = R(0), ru1 = R(0);
   R Wc[NV];
-  Wc[0] = pl.rho * lu0 + pr.rho * ru0;
-  Wc[1] = pl.rho * lu1 + pr.rho * ru1;
-  if constexpr (NV == 4) {
-    Wc[2] = pl.rho * pl.V * lu0 + pr.rho * pr.V * ru0;
-    Wc[3] = R(0.5) * (pl.rho * (lu2 + (pl.V * pl.V + hl + R(K) * hl) * lu0) +
-                      pr.rho * (ru2 + (pr.V * pr.V + hr + R(K) * hr) * ru0));
+  if (same && !slow) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wc[v] = Wl[v];
   } else {
-    Wc[2] = R(0.5) * (pl.rho * (lu2 + R(K) * hl * lu0) + pr.rho * (ru2 + R(K) * hr * ru0));
+    const R sl = sqrt(pl.lam), sr = sqrt(pr.lam);
+    const R tl0 = R(0.5) * erfc(-sl * pl.U), tr0 = R(0.5) * erfc(sr * pr.U);
+    const R isp = R(0.28209479177387814347);  // 1 / (2 sqrt(pi))
+    const R tl1 = exp(-pl.lam * pl.U * pl.U) * isp / sl;
+    const R tr1 = exp(-pr.lam * pr.U * pr.U) * isp / sr;
+    lu0 = tl0;
+    lu1 = pl.U * tl0 + tl1;
+    ru0 = tr0;
+    ru1 = pr.U * tr0 - tr1;
+    const R hl = R(0.5) / pl.lam, hr = R(0.5) / pr.lam;
+    const R lu2 = pl.U * lu1 + hl * lu0, ru2 = pr.U * ru1 + hr * ru0;
+    Wc[0] = pl.rho * lu0 + pr.rho * ru0;
+    Wc[1] = pl.rho * lu1 + pr.rho * ru1;
+    if constexpr (NV == 4) {
+      Wc[2] = pl.rho * pl.V * lu0 + pr.rho * pr.V * ru0;
+      Wc[3] = R(0.5) * (pl.rho * (lu2 + (pl.V * pl.V + hl + R(K) * hl) * lu0) +
+                        pr.rho * (ru2 + (pr.V * pr.V + hr + R(K) * hr) * ru0));
+    } else {
+      Wc[2] = R(0.5) * (pl.rho * (lu2 + R(K) * hl * lu0) + pr.rho * (ru2 + R(K) * hr * ru0));
+    }
   }
-  const Prim<R> pc = prim<NV, R>(Wc, g);
+  const Prim<R> pc = (same && !slow) ? pl : prim<NV, R>(Wc, g);
   // averaged derivatives and the equilibrium time derivative
   R dn[NV], dtn[NV], Wt[NV], tmp[NV];
 #pragma unroll
@@ -263,7 +280,7 @@ GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, cons
       Ft[v] = Ft[v] + w * JW[v];
       Wi[v] = Wi[v] + w * (Wc[v] + h * Wt[v]);
     }
-    return false;
+    return same ? PT_EQUAL : PT_FAST;
   }
   if constexpr (FULL) {
     // ---- tau > 0 ----
@@ -375,7 +392,7 @@ GENO_HD bool point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, cons
       }
     }
   }
-  return slow;
+  return PT_SLOW;
 }
 
 }  // namespace gks

@@ -65,6 +65,7 @@ geno::KParams params(int ndim, double gamma) {
   k.tc2 = 1.0;
   k.cfl = 0.5;
   k.dt_fixed = 0.0;
+  k.eps_ulps = 0.0;
   return k;
 }
 
@@ -105,12 +106,18 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     if (nv == 4) (void)geno::admissible<4, C>(w, gamma);
     else (void)geno::admissible<3, C>(w, gamma);
   });
-  // gas-kinetic point: tau = 0 (equal pressures) and tau > 0
-  long long pfast = 0, pslow = 0;
+  // gas-kinetic point: tau = 0 with equal states, tau = 0 with different
+  // states of equal pressure (a contact; the values are exact in binary so
+  // that both pressures round alike), tau > 0
+  long long pequal = 0, pfast = 0, pslow = 0;
   if (ndim == 2) {
-    C Wl[4] = {1.0, 0.2, -0.1, 2.6}, Wr[4] = {1.0, 0.2, -0.1, 2.6};
+    C Wl[4] = {1.0, 0.25, -0.125, 2.5390625}, Wr[4] = {0.5, 0.125, -0.0625, 2.51953125};
     C Wr2[4] = {0.8, 0.1, 0.1, 2.0};
     C n[4] = {0.1, 0.2, 0.3, 0.4}, t[4] = {0.2, 0.1, 0.0, -0.1};
+    pequal = count([&] {
+      C F[4], Ft[4], Wi[4];
+      gks::point_flux<4, true, C>(Wl, Wl, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
+    });
     pfast = count([&] {
       C F[4], Ft[4], Wi[4];
       gks::point_flux<4, true, C>(Wl, Wr, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
@@ -120,8 +127,13 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
       gks::point_flux<4, true, C>(Wl, Wr2, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
     });
   } else {
-    C Wl[3] = {1.0, 0.2, 2.6}, Wr[3] = {1.0, 0.2, 2.6}, Wr2[3] = {0.8, 0.1, 2.0};
+    C Wl[3] = {1.0, 0.25, 2.53125}, Wr[3] = {0.5, 0.125, 2.515625}, Wr2[3] = {0.8, 0.1, 2.0};
     C n[3] = {0.1, 0.2, 0.3};
+    pequal = count([&] {
+      C F[3], Ft[3], Wi[3];
+      gks::point_flux<3, true, C>(Wl, Wl, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
+                                  Ft, Wi);
+    });
     pfast = count([&] {
       C F[3], Ft[3], Wi[3];
       gks::point_flux<3, true, C>(Wl, Wr, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
@@ -148,6 +160,7 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     for (int kind : {GENO_K_FACES_X, GENO_K_FACES_Y, GENO_K_SLOW}) {
       set(kind, GENO_W_UNITS, face);
       set(kind, GENO_W_LOW, (double)(tan_lo - tan_hi));
+      set(kind, GENO_W_EQUAL, (double)pequal);
       set(kind, GENO_W_FAST, (double)pfast);
       set(kind, GENO_W_SLOW, (double)pslow);
     }
@@ -160,6 +173,7 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     const double face = 3.0 * (4 + lin + 2 * side_hi) + 2.0 * adm + 6.0;
     set(GENO_K_FACES_1D, GENO_W_UNITS, face);
     set(GENO_K_FACES_1D, GENO_W_LOW, (double)(side_lo - side_hi));
+    set(GENO_K_FACES_1D, GENO_W_EQUAL, (double)pequal);
     set(GENO_K_FACES_1D, GENO_W_FAST, (double)pfast);
     set(GENO_K_FACES_1D, GENO_W_SLOW, (double)pslow);
     set(GENO_K_UPDATE_1, GENO_W_UNITS, 3.0 * 19.0);

@@ -28,7 +28,7 @@ class geno_params(ctypes.Structure):
                 ("C", ctypes.c_double), ("eps", ctypes.c_double), ("r", ctypes.c_double),
                 ("rL", ctypes.c_double), ("d", ctypes.c_double * 3), ("tau_c1", ctypes.c_double),
                 ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4),
-                ("dt_fixed", ctypes.c_double)]
+                ("dt_fixed", ctypes.c_double), ("eps_ulps", ctypes.c_double)]
 
 
 class geno_grid(ctypes.Structure):
@@ -48,7 +48,7 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
            "geno_kernel_name")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d")
-WORK_CLASSES = ("units", "tanh", "low", "fast", "slow", "guard")
+WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard")
 
 _lib = None
 

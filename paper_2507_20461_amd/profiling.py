@@ -35,7 +35,7 @@ CAL_ELEMS = CAL_BYTES // 8
 
 BENCH_FULL = ["python3", os.path.join(ROOT, "bench.py")]
 BENCH_SHORT = ["python3", os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
-               "--no-cpu-baseline", "--no-kernel-timing"]
+               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms"]
 PASSES = {
     "ktrace": (["--kernel-trace", "--stats"], BENCH_FULL),
     "fetch": (["--pmc", "FETCH_SIZE"], BENCH_SHORT),
@@ -69,7 +69,7 @@ def run(extra=()):
         cmd = command(name, extra)
         print("==", " ".join(cmd), flush=True)
         with open(os.path.join(OUT, "prof_%s.log" % name), "w") as log:
-            rc = subprocess.run(["timeout", "-s", "KILL", "240", *cmd], stdout=log, stderr=log, env=env).returncode
+            rc = subprocess.run(["timeout", "-s", "KILL", "420" if name == "ktrace" else "120", *cmd], stdout=log, stderr=log, env=env).returncode
         res = os.path.join(OUT, "prof_" + name, "run_kernel_stats.csv" if name == "ktrace"
                            else "run_counter_collection.csv")
         print("   exit %d, results %s" % (rc, "present" if os.path.exists(res) else "missing"), flush=True)
@@ -104,18 +104,37 @@ def summarize(tag="faces_fp64_512"):
     os.makedirs(PROFILES, exist_ok=True)
     sh = source_hash()
     lines = []
-    # kernel trace stats
-    stats = list(csv.DictReader(open(os.path.join(OUT, "prof_ktrace", "run_kernel_stats.csv"))))
-    lines.append("# rocprofv3 kernel-trace statistics, 2-D Euler 512x512 FP64 quadrants (bench.py default)")
+    # kernel trace, per workload: every gks_step call starts with k_init, so
+    # the dispatches from one k_init to the next belong to one call; calls
+    # are labelled by the element type and grid of their k_init
+    trace = sorted(csv.DictReader(open(os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv"))),
+                   key=lambda r: int(r["Dispatch_Id"]))
+    label, per = None, collections.OrderedDict()
+    for r in trace:
+        k = _short(r["Kernel_Name"])
+        cells = int(r["Grid_Size_X"])
+        if k.startswith("k_init<2"):
+            n = int(round(cells ** 0.5))
+            label = "%s %dx%d" % ("mixed" if "float" in k else "fp64", n, n)
+        if label is None or not k.startswith("k_"):
+            continue
+        per.setdefault(label, collections.OrderedDict()).setdefault(k, []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines.append("# rocprofv3 kernel trace of bench.py (default run), per workload")
     lines.append("# command: " + " ".join(command("ktrace")).replace(ROOT + "/", ""))
     lines.append("# kernel sources sha256[:16]: " + sh)
-    lines.append("%-26s %7s %12s %12s %8s" % ("kernel", "calls", "avg_us", "total_ms", "pct"))
+    lines.append("# workload labels: element type and grid of the gks_step call (k_init grid size = cells,")
+    lines.append("# rounded to the next work-group); the bench's 512x512 workload is 'fp64 512x512'")
     ktrace = {}
-    for r in stats:
-        k = _short(r["Name"])
-        ktrace[k] = float(r["AverageNs"]) / 1e3
-        lines.append("%-26s %7s %12.2f %12.3f %8s" % (k[:26], r["Calls"], float(r["AverageNs"]) / 1e3,
-                                                      float(r["TotalDurationNs"]) / 1e6, r["Percentage"]))
+    for lab, ks in per.items():
+        lines.append("")
+        lines.append("[%s]" % lab)
+        lines.append("%-28s %7s %10s %10s" % ("kernel", "calls", "avg_us", "total_ms"))
+        for k, v in sorted(ks.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("%-28s %7d %10.2f %10.3f" % (k[:28], len(v), sum(v) / len(v), sum(v) / 1e3))
+            if lab.startswith("fp64 512x512"):
+                ktrace.setdefault(k, []).extend(v)
+    ktrace = {k: sum(v) / len(v) for k, v in ktrace.items()}
     open(os.path.join(PROFILES, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
     # counters
     F = _counters(os.path.join(OUT, "prof_fetch", "run_counter_collection.csv"), "FETCH_SIZE")

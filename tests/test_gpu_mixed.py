@@ -77,6 +77,9 @@ def _case(kind, nx, ny, seed):
 
 
 def _grid(G, nx, ny, bc, **kw):
+    # the plain eps (no float32 noise floor): the float32 arithmetic of the
+    # method itself, comparable with the oracle
+    kw.setdefault("eps_ulps", 0.0)
     return G.Grid(2, nx, ny, bc=bc, precision=G.MIXED, **kw)
 
 
@@ -159,6 +162,27 @@ def test_mixed_rejects_fp64_gradients(G):
         G.gks_step(grid, grid.to_device(W), grid.to_device(dW), grid.workspace(), 1)
 
 
+def test_mixed_default_floor_close_to_fp64(G):
+    # the default eps floor of the mixed form (eps_ulps) changes chi only where
+    # indicators are at float32 noise level; on smooth periodic data its
+    # solution stays at float32 rounding distance from the FP64 path (near
+    # jumps the method's sensitivity to rounding makes any two precisions
+    # drift apart, and accuracy is compared against a refined solution
+    # instead, in the benchmark)
+    n, steps = 64, 30
+    W, dW = _case("smooth", n, n, 2)
+    out = {}
+    for prec in (G.F64, G.MIXED):
+        grid = G.Grid(2, n, n, bc=0, precision=prec)
+        Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
+        st = G.gks_step(grid, Wd, dWd, grid.workspace(), steps, stats=True)
+        assert st.nonfinite == 0
+        out[prec] = grid.interior(Wd)
+    d = np.abs(out[G.MIXED] - out[G.F64]).mean(axis=(1, 2)) / np.abs(out[G.F64]).max(axis=(1, 2))
+    _say("mixed (default floor) vs fp64 on smooth data, L1 / field scale after %d steps: %s" % (steps, d))
+    assert d.max() < MIX_W, d
+
+
 def test_fixed_dt_matches_oracle(G, oracle):
     # dt_fixed > 0 replaces the CFL step on both sides (FP64 parity bar)
     nx, ny = 32, 24
@@ -169,7 +193,7 @@ def test_fixed_dt_matches_oracle(G, oracle):
     dts = torch.zeros(6, dtype=torch.float64, device="cuda")
     G.gks_step(grid, Wd, dWd, grid.workspace(), 6, dt_out=dts, stats=True)
     assert np.all(dts.cpu().numpy() == dt)
-    # shadow the last step against the oracle with the same fixed dt
+    # the whole 6-step run against the oracle with the same fixed dt
     oW, odW, odt, _ = oracle.step(oracle.params(ndim=2, bc=1), W, dW, 6, fixed_dt=dt)
     assert np.all(odt == dt)
     gW = grid.interior(Wd)
