@@ -194,6 +194,70 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
 int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
              geno_stats* stats, void* stream);
 
+/* ---- batched form --------------------------------------------------------
+ * Many independent 2-D grids advanced together: each kernel kind runs as one
+ * launch over the work of every grid (work-group ranges concatenated; each
+ * work-group looks up its grid), and one step of the whole batch is captured
+ * once as a HIP graph and replayed. Grids may differ in size and boundary
+ * conditions; every other field of geno_params (method constants, precision,
+ * cfl, dt_fixed, eps_ulps) must be equal across the batch. Each grid keeps its
+ * own time step (its own CFL condition). Results are identical to gks_step on
+ * each grid alone. */
+
+/* Work-group shapes of the batched launches (chosen by geno_autotune_batched
+ * or given by the caller). block_*: threads per work-group of the normal GENO,
+ * face, tau > 0 and update launches: 128, 256 or 512 (0 = 256). The update's
+ * size also serves the start-of-call launch. slow_faces_per_block: the tau > 0
+ * launch gives each grid ceil(faces / slow_faces_per_block) work-groups
+ * (between 1 and 1024; 0 = 2048). */
+typedef struct geno_tuning {
+  int version;
+  int block_normal;
+  int block_faces;
+  int block_slow;
+  int block_update;
+  int slow_faces_per_block;
+} geno_tuning;
+
+/* Defaults: 256-thread work-groups, 2048 faces per tau > 0 work-group. */
+int geno_tuning_default(geno_tuning* t);
+
+/* Largest batch accepted by the batched calls. */
+#define GENO_BATCH_MAX 4096
+
+/* Bytes of the device workspace of a batch of ngrids grids (grids: host
+ * array); 0 if the batch is invalid. */
+size_t gks_batched_workspace_bytes(int ngrids, const geno_grid* grids);
+
+/* nsteps steps of every grid of the batch in place (the two-stage update of
+ * gks_step on each grid).
+ * grids: host array of ngrids grid descriptions (2-D only).
+ * W, dW: host arrays of ngrids device pointers, each laid out as for
+ *   gks_step on its grid (element types of the batch's precision).
+ * ws: workspace of gks_batched_workspace_bytes bytes.
+ * tune: work-group shapes (NULL = defaults).
+ * use_graph: if non-zero, one step of the batch is captured into a HIP graph
+ *   and the graph is launched nsteps times; the stream must then not be the
+ *   NULL stream (GENO_EINVAL otherwise).
+ * step_ms (host, may be NULL): nsteps floats, the duration of each step from
+ *   events recorded between the steps on the stream.
+ * stats (host, may be NULL): counters summed over the grids.
+ * The call waits for the stream (it copies the batch table to ws first and
+ * reads the timings or counters back when asked). */
+int gks_step_batched(int ngrids, const geno_grid* grids, void* const* W, void* const* dW, void* ws,
+                     int nsteps, const geno_tuning* tune, int use_graph, float* step_ms,
+                     geno_stats* stats, void* stream);
+
+/* Autotuner of the batched work-group shapes: for each launch kind in turn
+ * (normal GENO, faces, tau > 0 faces, update) it runs trial_steps steps of
+ * the batch with every candidate shape (block sizes 128, 256, 512; for the
+ * tau > 0 launch also 512, 2048 and 8192 faces per work-group) and keeps the
+ * one with the least summed kernel time (events bound to the dispatches).
+ * The trials advance the given state: pass a copy. Writes the choice to
+ * *out. */
+int geno_autotune_batched(int ngrids, const geno_grid* grids, void* const* W, void* const* dW,
+                          void* ws, int trial_steps, geno_tuning* out, void* stream);
+
 /* ---- measurement support ------------------------------------------------
  * Kernel kinds of gks_step reported by geno_timing_read / geno_work_read. */
 enum {

@@ -23,7 +23,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <tuple>
 #include <utility>
+#include <vector>
 
 #include "geno_device.hpp"
 #include "geno_gks.h"
@@ -32,7 +34,8 @@
 namespace {
 
 constexpr int NG = 2;
-constexpr int BLOCK = 256;
+constexpr int BLOCK = 256;          // work-group size of the single-grid launches
+constexpr int MAXWAVES = 16;        // waves of the largest work-group (1024 lanes)
 constexpr int SLOW_BLOCKS = 1024;   // fixed grid of the queue kernels (grid-stride)
 
 thread_local char g_err[512] = "";
@@ -61,6 +64,7 @@ struct Timing {
   int cap = 0, used = 0;
 };
 Timing g_tim;
+int g_tim_suspend = 0;   // set while a launch sequence is captured into a graph
 
 const char* const KNAMES[GENO_NKERNELS] = {"init",    "normal_x", "normal_y", "faces_x", "faces_y",
                                            "slow",    "update_1", "update_2", "faces_1d"};
@@ -68,16 +72,23 @@ const char* const KNAMES[GENO_NKERNELS] = {"init",    "normal_x", "normal_y", "f
 // Every launch goes through here: a kernel of kind >= 0 is timed while
 // timing is enabled (events bound to the dispatch itself).
 template <typename... KArgs, typename... Args>
-hipError_t launch(int kind, void (*kern)(KArgs...), unsigned grid, hipStream_t s, Args&&... args) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (kind >= 0 && g_tim.used < g_tim.cap) {
+hipError_t launch_bs(int kind, void (*kern)(KArgs...), unsigned grid, unsigned bs, hipStream_t s,
+                     Args&&... args) {
+  std::tuple<KArgs...> tup = validateArgsCountType(kern, std::tuple<Args...>{args...});
+  void* argv[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+  pArgs<0>(tup, argv);
+  if (kind >= 0 && !g_tim_suspend && g_tim.used < g_tim.cap) {
     const int u = g_tim.used++;
     g_tim.kind[u] = kind;
-    e0 = g_tim.ev[2 * u];
-    e1 = g_tim.ev[2 * u + 1];
+    return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(bs), argv, 0,
+                              s, g_tim.ev[2 * u], g_tim.ev[2 * u + 1], 0);
   }
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), 0, s, e0, e1, 0, std::forward<Args>(args)...);
-  return hipGetLastError();
+  return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(bs), argv, 0, s);
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch(int kind, void (*kern)(KArgs...), unsigned grid, hipStream_t s, Args&&... args) {
+  return launch_bs(kind, kern, grid, BLOCK, s, std::forward<Args>(args)...);
 }
 
 // Work counting: per-block sums of the work classes, [kind][class][cap]
@@ -96,7 +107,8 @@ struct CountBuf {
 CountBuf g_cnt;
 
 __device__ void block_count(const Cnt& c, int kind, const unsigned int (&v)[GENO_NCLASS]) {
-  __shared__ unsigned int red[BLOCK / 64][GENO_NCLASS];
+  __shared__ unsigned int red[MAXWAVES][GENO_NCLASS];
+  const int nw = (int)(blockDim.x >> 6);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < GENO_NCLASS; ++q) {
@@ -109,7 +121,7 @@ __device__ void block_count(const Cnt& c, int kind, const unsigned int (&v)[GENO
   if (threadIdx.x < GENO_NCLASS) {
     unsigned long long x = 0;
 #pragma unroll
-    for (int i = 0; i < BLOCK / 64; ++i) x += red[i][threadIdx.x];
+    for (int i = 0; i < nw; ++i) x += red[i][threadIdx.x];
     if (x) c.p[((size_t)kind * GENO_NCLASS + threadIdx.x) * c.cap + blockIdx.x] += x;
   }
 }
@@ -209,9 +221,10 @@ __device__ __forceinline__ double cell_tmin(const Geo& g, const double* w, doubl
   return (t > 0.0) ? t : 0.0;   // a NaN state gives a zero step (flagged by the caller)
 }
 
-// block minimum of t into part[blockIdx.x]
-__device__ __forceinline__ void block_min(double t, double* part) {
-  __shared__ double red[BLOCK / 64];
+// block minimum of t into part[slot]
+__device__ __forceinline__ void block_min(double t, double* part, int slot) {
+  __shared__ double red[MAXWAVES];
+  const int nw = (int)(blockDim.x >> 6);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t = fmin(t, __shfl_xor(t, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
@@ -219,8 +232,8 @@ __device__ __forceinline__ void block_min(double t, double* part) {
   if (threadIdx.x == 0) {
     double m = red[0];
 #pragma unroll
-    for (int w = 1; w < BLOCK / 64; ++w) m = fmin(m, red[w]);
-    part[blockIdx.x] = m;
+    for (int w = 1; w < nw; ++w) m = fmin(m, red[w]);
+    part[slot] = m;
   }
 }
 
@@ -228,7 +241,8 @@ __device__ __forceinline__ void block_min(double t, double* part) {
 // npart partials, or dt_fixed if positive; records dt
 __device__ __forceinline__ void reduce_dt(const double* part, int npart, Ctrl* ctrl, double cfl,
                                           double dt_fixed, double* dt_out, int step) {
-  __shared__ double red[BLOCK / 64];
+  __shared__ double red[MAXWAVES];
+  const int nw = (int)(blockDim.x >> 6);
   double m = INFINITY;
   for (int q = threadIdx.x; q < npart; q += blockDim.x) m = fmin(m, part[q]);
 #pragma unroll
@@ -237,7 +251,7 @@ __device__ __forceinline__ void reduce_dt(const double* part, int npart, Ctrl* c
   __syncthreads();
   if (threadIdx.x == 0) {
     m = red[0];
-    for (int w = 1; w < BLOCK / 64; ++w) m = fmin(m, red[w]);
+    for (int w = 1; w < nw; ++w) m = fmin(m, red[w]);
     const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * m;
     ctrl->dt = dt;
     if (dt_out) dt_out[step] = dt;
@@ -246,13 +260,15 @@ __device__ __forceinline__ void reduce_dt(const double* part, int npart, Ctrl* c
 
 // Start of gks_step: ghost cells of the initial state, per-block CFL minima,
 // cleared counters.
+// (lb: the work-group's index within this grid's launch range; the kernel
+// bodies below all take one.)
 template <int NDIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __restrict__ W,
-                                                T* __restrict__ dW, double* __restrict__ part,
-                                                Ctrl* ctrl) {
+__device__ __forceinline__ void init_body(const Geo& g, double gamma, double* __restrict__ W,
+                                          T* __restrict__ dW, double* __restrict__ part,
+                                          Ctrl* ctrl, int lb) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0) {
+  const int t = lb * (int)blockDim.x + (int)threadIdx.x;
+  if (lb == 0) {
     unsigned long long* z = &ctrl->guard;
     const int nz = (int)((sizeof(Ctrl) - offsetof(Ctrl, guard)) / sizeof(unsigned long long));
     for (int q = threadIdx.x; q < nz; q += blockDim.x) z[q] = 0;
@@ -269,7 +285,14 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
     scatter_ghosts<NDIM, T>(g, W, dW, j, i, w, dw);
     tl = cell_tmin<NDIM>(g, w, gamma);
   }
-  block_min(tl, part);
+  block_min(tl, part, lb);
+}
+
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __restrict__ W,
+                                                T* __restrict__ dW, double* __restrict__ part,
+                                                Ctrl* ctrl) {
+  init_body<NDIM, T>(g, gamma, W, dW, part, ctrl, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,19 +306,18 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
 // minima of the previous kernel into ctrl->tmin and records dt.
 // ---------------------------------------------------------------------------
 template <int DIR, typename T>
-__global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
-                                                    const double* __restrict__ W,
-                                                    const T* __restrict__ dW,
-                                                    T* __restrict__ fr,
-                                                    double* __restrict__ chi, Ctrl* ctrl,
-                                                    const double* __restrict__ part, int npart,
-                                                    double* dt_out, int step, Cnt cnt) {
-  if (part && blockIdx.x == 0) reduce_dt(part, npart, ctrl, k.cfl, k.dt_fixed, dt_out, step);
-  if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) ctrl->qcount[DIR] = 0;
+__device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k,
+                                            const double* __restrict__ W,
+                                            const T* __restrict__ dW, T* __restrict__ fr,
+                                            double* __restrict__ chi, Ctrl* ctrl,
+                                            const double* __restrict__ part, int npart,
+                                            double* dt_out, int step, const Cnt& cnt, int lb) {
+  if (part && lb == 0) reduce_dt(part, npart, ctrl, k.cfl, k.dt_fixed, dt_out, step);
+  if (ctrl && lb == 0 && threadIdx.x == 0) ctrl->qcount[DIR] = 0;
   const int n1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
   const int n0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
   const int plane = n0 * n1;
-  const int t = xcd_block() * BLOCK + threadIdx.x;
+  const int t = lb * (int)blockDim.x + (int)threadIdx.x;
   unsigned int nlow = 0;
   if (t < 4 * plane) {
     const int v = t / plane, o = t - v * plane;
@@ -329,6 +351,17 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
     wc[GENO_W_LOW] = nlow;
     block_count(cnt, DIR == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y, wc);
   }
+}
+
+template <int DIR, typename T>
+__global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
+                                                    const double* __restrict__ W,
+                                                    const T* __restrict__ dW,
+                                                    T* __restrict__ fr,
+                                                    double* __restrict__ chi, Ctrl* ctrl,
+                                                    const double* __restrict__ part, int npart,
+                                                    double* dt_out, int step, Cnt cnt) {
+  normal_body<DIR, T>(g, k, W, dW, fr, chi, ctrl, part, npart, dt_out, step, cnt, xcd_block());
 }
 
 // ---------------------------------------------------------------------------
@@ -504,19 +537,28 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
 }
 
 template <int DIR, int MODE, typename T>
+__device__ __forceinline__ void faces_body(const Geo& g, const geno::KParams& k,
+                                           const double* __restrict__ W,
+                                           const T* __restrict__ fr, T* __restrict__ out,
+                                           Ctrl* ctrl, int want_F, const Cnt& cnt,
+                                           unsigned int* __restrict__ queue, int lb) {
+  const FaceGeo<DIR> fg(g);
+  const int nfaces = fg.n0 * fg.n1;
+  const int t = lb * (int)blockDim.x + (int)threadIdx.x;
+  const int face = t >> 1;
+  unsigned int wc[GENO_NCLASS] = {};
+  face_pair<DIR, MODE, T>(g, k, W, fr, out, ctrl, want_F, wc, face, face < nfaces, queue);
+  if (MODE == 1 && cnt.p) block_count(cnt, DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, wc);
+}
+
+template <int DIR, int MODE, typename T>
 __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
                                                    const double* __restrict__ W,
                                                    const T* __restrict__ fr,
                                                    T* __restrict__ out, Ctrl* ctrl,
                                                    int want_F, Cnt cnt,
                                                    unsigned int* __restrict__ queue) {
-  const FaceGeo<DIR> fg(g);
-  const int nfaces = fg.n0 * fg.n1;
-  const int t = xcd_block() * BLOCK + threadIdx.x;
-  const int face = t >> 1;
-  unsigned int wc[GENO_NCLASS] = {};
-  face_pair<DIR, MODE, T>(g, k, W, fr, out, ctrl, want_F, wc, face, face < nfaces, queue);
-  if (MODE == 1 && cnt.p) block_count(cnt, DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, wc);
+  faces_body<DIR, MODE, T>(g, k, W, fr, out, ctrl, want_F, cnt, queue, xcd_block());
 }
 
 // The faces of both directions queued by k_faces2d<DIR, 1> (tau > 0 at one
@@ -524,6 +566,28 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
 // grid-stride over the pairs; pairs [0, nqx) are x-faces, the rest y-faces.
 // Both lanes of a pair always take the same branch and trip count, so each
 // cross-lane read finds its partner active.
+// (lb, nb: this work-group's index among the nb work-groups serving the grid)
+template <typename T>
+__device__ __forceinline__ void slow_body(const Geo& g, const geno::KParams& k,
+                                          const double* __restrict__ W,
+                                          const T* __restrict__ frx, const T* __restrict__ fry,
+                                          T* __restrict__ outx, T* __restrict__ outy, Ctrl* ctrl,
+                                          int want_F, const Cnt& cnt,
+                                          const unsigned int* __restrict__ qx,
+                                          const unsigned int* __restrict__ qy, int lb, int nb) {
+  const unsigned int nqx = ctrl->qcount[0];
+  const unsigned int nq = nqx + ctrl->qcount[1];
+  const unsigned int stride = (unsigned int)nb * blockDim.x / 2;
+  unsigned int wc[GENO_NCLASS] = {};
+  for (unsigned int e = ((unsigned int)lb * blockDim.x + threadIdx.x) >> 1; e < nq; e += stride) {
+    if (e < nqx)
+      face_pair<0, 2, T>(g, k, W, frx, outx, ctrl, want_F, wc, (int)qx[e], true, nullptr);
+    else
+      face_pair<1, 2, T>(g, k, W, fry, outy, ctrl, want_F, wc, (int)qy[e - nqx], true, nullptr);
+  }
+  if (cnt.p) block_count(cnt, GENO_K_SLOW, wc);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
                                                   const double* __restrict__ W,
@@ -534,17 +598,8 @@ __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
                                                   int want_F, Cnt cnt,
                                                   const unsigned int* __restrict__ qx,
                                                   const unsigned int* __restrict__ qy) {
-  const unsigned int nqx = ctrl->qcount[0];
-  const unsigned int nq = nqx + ctrl->qcount[1];
-  const unsigned int stride = gridDim.x * blockDim.x / 2;
-  unsigned int wc[GENO_NCLASS] = {};
-  for (unsigned int e = (blockIdx.x * blockDim.x + threadIdx.x) >> 1; e < nq; e += stride) {
-    if (e < nqx)
-      face_pair<0, 2, T>(g, k, W, frx, outx, ctrl, want_F, wc, (int)qx[e], true, nullptr);
-    else
-      face_pair<1, 2, T>(g, k, W, fry, outy, ctrl, want_F, wc, (int)qy[e - nqx], true, nullptr);
-  }
-  if (cnt.p) block_count(cnt, GENO_K_SLOW, wc);
+  slow_body<T>(g, k, W, frx, fry, outx, outy, ctrl, want_F, cnt, qx, qy, (int)blockIdx.x,
+               (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,16 +744,14 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
 // the ghost cells of the state they produce.
 // ---------------------------------------------------------------------------
 template <int NDIM, int STAGE, typename T>
-__global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
-                                                  const double* __restrict__ Win,
-                                                  double* __restrict__ Wout,
-                                                  T* __restrict__ dWout,
-                                                  double* __restrict__ R,
-                                                  const T* __restrict__ fx,
-                                                  const T* __restrict__ fy, Ctrl* ctrl,
-                                                  double* __restrict__ part, Cnt cnt) {
+__device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k,
+                                            const double* __restrict__ Win,
+                                            double* __restrict__ Wout, T* __restrict__ dWout,
+                                            double* __restrict__ R, const T* __restrict__ fx,
+                                            const T* __restrict__ fy, Ctrl* ctrl,
+                                            double* __restrict__ part, const Cnt& cnt, int lb) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
-  const int t = xcd_block() * BLOCK + threadIdx.x;
+  const int t = lb * (int)blockDim.x + (int)threadIdx.x;
   const int n = g.nx * g.ny;
   const double dt = dt_of(ctrl);
   double tloc = INFINITY;
@@ -749,12 +802,129 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
       tloc = cell_tmin<NDIM>(g, w, k.gamma);
     }
   }
-  if constexpr (STAGE == 2) block_min(tloc, part);
+  if constexpr (STAGE == 2) block_min(tloc, part, lb);
   if (cnt.p) {
     unsigned int wc[GENO_NCLASS] = {};
     wc[GENO_W_UNITS] = t < n ? 1u : 0u;
     block_count(cnt, STAGE == 1 ? GENO_K_UPDATE_1 : GENO_K_UPDATE_2, wc);
   }
+}
+
+template <int NDIM, int STAGE, typename T>
+__global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
+                                                  const double* __restrict__ Win,
+                                                  double* __restrict__ Wout,
+                                                  T* __restrict__ dWout,
+                                                  double* __restrict__ R,
+                                                  const T* __restrict__ fx,
+                                                  const T* __restrict__ fy, Ctrl* ctrl,
+                                                  double* __restrict__ part, Cnt cnt) {
+  update_body<NDIM, STAGE, T>(g, k, Win, Wout, dWout, R, fx, fy, ctrl, part, cnt, xcd_block());
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: many independent 2-D grids advanced together. Each launch
+// runs one kernel kind for every grid: the grids' work-group ranges are
+// concatenated, and a work-group finds its grid by binary search over the
+// range starts. The search takes the XCD slab index, so each XCD works on
+// neighbouring ranges of one or a few grids. Work-group size BS is a template
+// parameter chosen per kind by the caller (autotuned).
+// ---------------------------------------------------------------------------
+enum { BK_INIT = 0, BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE, BK_N };
+
+struct BEntry {
+  Geo geo;
+  double* W;
+  void* dW;
+  Ctrl* ctrl;
+  double* part;
+  unsigned int* queue[2];
+  double* wst;
+  double* r;
+  void* dwst;
+  void* fr[2];
+  void* fl[2];
+  int npart;     // update work-groups of this grid (CFL partials)
+  int slow_nb;   // work-groups serving this grid in the tau > 0 launch
+};
+
+// index of the grid whose range [start[g], start[g+1]) holds global work-group gb
+__device__ __forceinline__ int find_grid(const int* __restrict__ start, int ngrids, int gb) {
+  int lo = 0, hi = ngrids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= gb) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) kb_init(const BEntry* __restrict__ tab,
+                                              const int* __restrict__ offs, int ngrids,
+                                              double gamma) {
+  const int* st = offs + BK_INIT * (ngrids + 1);
+  const int gb = xcd_block();
+  const int gi = find_grid(st, ngrids, gb);
+  const BEntry& e = tab[gi];
+  init_body<2, T>(e.geo, gamma, e.W, (T*)e.dW, e.part, e.ctrl, gb - st[gi]);
+}
+
+template <int DIR, typename T, int BS>
+__global__ void __launch_bounds__(BS) kb_normal(const BEntry* __restrict__ tab,
+                                                const int* __restrict__ offs, int ngrids,
+                                                geno::KParams k, int stage, Cnt cnt) {
+  const int* st = offs + (DIR == 0 ? BK_NORMAL_X : BK_NORMAL_Y) * (ngrids + 1);
+  const int gb = xcd_block();
+  const int gi = find_grid(st, ngrids, gb);
+  const BEntry& e = tab[gi];
+  const double* W = stage == 1 ? e.W : e.wst;
+  const T* dW = (const T*)(stage == 1 ? e.dW : e.dwst);
+  const double* part = (DIR == 0 && stage == 1) ? e.part : nullptr;
+  normal_body<DIR, T>(e.geo, k, W, dW, (T*)e.fr[DIR], nullptr, e.ctrl, part, e.npart, nullptr, 0,
+                      cnt, gb - st[gi]);
+}
+
+template <int DIR, typename T, int BS>
+__global__ void __launch_bounds__(BS) kb_faces(const BEntry* __restrict__ tab,
+                                               const int* __restrict__ offs, int ngrids,
+                                               geno::KParams k, int stage, Cnt cnt) {
+  const int* st = offs + (DIR == 0 ? BK_FACES_X : BK_FACES_Y) * (ngrids + 1);
+  const int gb = xcd_block();
+  const int gi = find_grid(st, ngrids, gb);
+  const BEntry& e = tab[gi];
+  const double* W = stage == 1 ? e.W : e.wst;
+  faces_body<DIR, 1, T>(e.geo, k, W, (const T*)e.fr[DIR], (T*)e.fl[DIR], e.ctrl, stage == 1, cnt,
+                        e.queue[DIR], gb - st[gi]);
+}
+
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) kb_slow(const BEntry* __restrict__ tab,
+                                              const int* __restrict__ offs, int ngrids,
+                                              geno::KParams k, int stage, Cnt cnt) {
+  const int* st = offs + BK_SLOW * (ngrids + 1);
+  const int gb = (int)blockIdx.x;
+  const int gi = find_grid(st, ngrids, gb);
+  const BEntry& e = tab[gi];
+  const double* W = stage == 1 ? e.W : e.wst;
+  slow_body<T>(e.geo, k, W, (const T*)e.fr[0], (const T*)e.fr[1], (T*)e.fl[0], (T*)e.fl[1],
+               e.ctrl, stage == 1, cnt, e.queue[0], e.queue[1], gb - st[gi], e.slow_nb);
+}
+
+template <int STAGE, typename T, int BS>
+__global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
+                                                const int* __restrict__ offs, int ngrids,
+                                                geno::KParams k, Cnt cnt) {
+  const int* st = offs + BK_UPDATE * (ngrids + 1);
+  const int gb = xcd_block();
+  const int gi = find_grid(st, ngrids, gb);
+  const BEntry& e = tab[gi];
+  if (STAGE == 1)
+    update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (const T*)e.fl[0],
+                         (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
+  else
+    update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (const T*)e.fl[0],
+                         (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
 }
 
 // ---------------------------------------------------------------------------
@@ -784,8 +954,8 @@ Layout layout_of(const geno_grid* g) {
   size_t off = 0;
   L.ctrl = off;
   off = align256(off + sizeof(Ctrl));
-  L.part = off;
-  off = align256(off + (size_t)L.npart * sizeof(double));
+  L.part = off;   // room for the partials of work-groups as small as 64 lanes
+  off = align256(off + ((size_t)g->nx * g->ny / 64 + 1) * sizeof(double));
   if (g->ndim == 2) {
     L.queue[0] = off;
     off = align256(off + (size_t)g->ny * (g->nx + 1) * sizeof(unsigned int));
@@ -1069,6 +1239,310 @@ int step_t(const geno_grid* g, double* W, T* dW, void* ws, int nsteps, double* d
   return GENO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched host side
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  int ngrids = 0;
+  int bs[BK_N] = {};
+  int nb[BK_N] = {};             // work-groups of each launch kind (all grids)
+  std::vector<BEntry> tab;
+  std::vector<int> offs;         // [kind][ngrids + 1] range starts
+  std::vector<size_t> goff;      // workspace offset of each grid
+  size_t tab_off = 0, offs_off = 0, total = 0;
+};
+
+bool bs_ok(int b) { return b == 128 || b == 256 || b == 512; }
+unsigned nblocks_bs(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+int tuning_of(const geno_tuning* t, geno_tuning* out) {
+  geno_tuning d{GENO_ABI_VERSION, 256, 256, 256, 256, 2048};
+  if (t) {
+    if (t->version != GENO_ABI_VERSION)
+      return fail(GENO_EVERSION, "tuning version %d != %d", t->version, GENO_ABI_VERSION);
+    if (t->block_normal) d.block_normal = t->block_normal;
+    if (t->block_faces) d.block_faces = t->block_faces;
+    if (t->block_slow) d.block_slow = t->block_slow;
+    if (t->block_update) d.block_update = t->block_update;
+    if (t->slow_faces_per_block) d.slow_faces_per_block = t->slow_faces_per_block;
+  }
+  if (!bs_ok(d.block_normal) || !bs_ok(d.block_faces) || !bs_ok(d.block_slow) ||
+      !bs_ok(d.block_update))
+    return fail(GENO_EINVAL, "work-group sizes must be 128, 256 or 512");
+  if (d.slow_faces_per_block < 1) return fail(GENO_EINVAL, "slow_faces_per_block must be >= 1");
+  *out = d;
+  return GENO_OK;
+}
+
+// the method parameters every grid of a batch shares (all but bc)
+bool same_method(const geno_params& a, const geno_params& b) {
+  return a.version == b.version && a.precision == b.precision && a.gamma == b.gamma &&
+         a.C == b.C && a.eps == b.eps && a.r == b.r && a.rL == b.rL && a.d[0] == b.d[0] &&
+         a.d[1] == b.d[1] && a.d[2] == b.d[2] && a.tau_c1 == b.tau_c1 &&
+         a.tau_c2 == b.tau_c2 && a.cfl == b.cfl && a.dt_fixed == b.dt_fixed &&
+         a.eps_ulps == b.eps_ulps;
+}
+
+int check_batch(int ngrids, const geno_grid* grids) {
+  if (ngrids < 1 || ngrids > GENO_BATCH_MAX)
+    return fail(GENO_EINVAL, "ngrids must be in [1, %d]", GENO_BATCH_MAX);
+  if (!grids) return fail(GENO_EINVAL, "null grids");
+  for (int i = 0; i < ngrids; ++i) {
+    int rc = check_grid(&grids[i]);
+    if (rc) return rc;
+    if (grids[i].ndim != 2) return fail(GENO_EINVAL, "batched grids must be 2-D (grid %d)", i);
+    if (!same_method(grids[i].params, grids[0].params))
+      return fail(GENO_EINVAL, "grid %d: method parameters differ from grid 0", i);
+  }
+  return GENO_OK;
+}
+
+// Work-group ranges, table and workspace layout of a batch (no device access).
+int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPlan* P) {
+  P->ngrids = ngrids;
+  P->bs[BK_INIT] = P->bs[BK_UPDATE] = t.block_update;
+  P->bs[BK_NORMAL_X] = P->bs[BK_NORMAL_Y] = t.block_normal;
+  P->bs[BK_FACES_X] = P->bs[BK_FACES_Y] = t.block_faces;
+  P->bs[BK_SLOW] = t.block_slow;
+  P->offs.assign((size_t)BK_N * (ngrids + 1), 0);
+  P->tab.assign(ngrids, BEntry{});
+  P->goff.assign(ngrids, 0);
+  size_t off = 0;
+  P->tab_off = off;
+  off = align256(off + sizeof(BEntry) * ngrids);
+  P->offs_off = off;
+  off = align256(off + sizeof(int) * P->offs.size());
+  long long cnt[BK_N] = {};
+  for (int i = 0; i < ngrids; ++i) {
+    const geno_grid* g = &grids[i];
+    const size_t ncell = (size_t)g->nx * g->ny;
+    const size_t f = faces_of(g, 0) + faces_of(g, 1);
+    const long long nbk[BK_N] = {
+        nblocks_bs(ncell, t.block_update),
+        nblocks_bs(4 * face_rows(g, 0), t.block_normal),
+        nblocks_bs(2 * faces_of(g, 0), t.block_faces),
+        nblocks_bs(4 * face_rows(g, 1), t.block_normal),
+        nblocks_bs(2 * faces_of(g, 1), t.block_faces),
+        std::min<long long>(1024, std::max<long long>(1, (long long)((f + t.slow_faces_per_block - 1) /
+                                                                  t.slow_faces_per_block))),
+        nblocks_bs(ncell, t.block_update)};
+    for (int k = 0; k < BK_N; ++k) {
+      P->offs[(size_t)k * (ngrids + 1) + i] = (int)cnt[k];
+      cnt[k] += nbk[k];
+      if (cnt[k] > 0x7fffffff / 1024) return fail(GENO_EINVAL, "batch too large");
+    }
+    P->goff[i] = off;
+    const Layout L = layout_of(g);
+    off = align256(off + L.total);
+    BEntry& e = P->tab[i];
+    e.geo = geo_of(g);
+    e.npart = (int)nbk[BK_UPDATE];
+    e.slow_nb = (int)nbk[BK_SLOW];
+  }
+  for (int k = 0; k < BK_N; ++k) {
+    P->offs[(size_t)k * (ngrids + 1) + ngrids] = (int)cnt[k];
+    P->nb[k] = (int)cnt[k];
+  }
+  P->total = off;
+  return GENO_OK;
+}
+
+// Device pointers of the table entries for workspace ws.
+void bind_batch(BatchPlan* P, char* ws, void* const* W, void* const* dW, const geno_grid* grids) {
+  for (int i = 0; i < P->ngrids; ++i) {
+    const Layout L = layout_of(&grids[i]);
+    char* b = ws + P->goff[i];
+    BEntry& e = P->tab[i];
+    e.W = (double*)W[i];
+    e.dW = dW[i];
+    e.ctrl = reinterpret_cast<Ctrl*>(b + L.ctrl);
+    e.part = reinterpret_cast<double*>(b + L.part);
+    e.queue[0] = reinterpret_cast<unsigned int*>(b + L.queue[0]);
+    e.queue[1] = reinterpret_cast<unsigned int*>(b + L.queue[1]);
+    e.wst = reinterpret_cast<double*>(b + L.wst);
+    e.r = reinterpret_cast<double*>(b + L.r);
+    e.dwst = b + L.dwst;
+    e.fr[0] = b + L.fr[0];
+    e.fr[1] = b + L.fr[1];
+    e.fl[0] = b + L.fl[0];
+    e.fl[1] = b + L.fl[1];
+  }
+}
+
+#define GO_BS(BSV, KIND, KERN, NB, ...)                                                  \
+  switch (BSV) {                                                                         \
+    case 128: return launch_bs(KIND, KERN<128>, NB, 128, s, __VA_ARGS__);                \
+    case 512: return launch_bs(KIND, KERN<512>, NB, 512, s, __VA_ARGS__);                \
+    default: return launch_bs(KIND, KERN<256>, NB, 256, s, __VA_ARGS__);                 \
+  }
+
+template <typename T>
+struct BatchK {
+  template <int BS> static constexpr auto init = kb_init<T, BS>;
+  template <int BS> static constexpr auto nx = kb_normal<0, T, BS>;
+  template <int BS> static constexpr auto ny = kb_normal<1, T, BS>;
+  template <int BS> static constexpr auto fx = kb_faces<0, T, BS>;
+  template <int BS> static constexpr auto fy = kb_faces<1, T, BS>;
+  template <int BS> static constexpr auto slow = kb_slow<T, BS>;
+  template <int BS> static constexpr auto up1 = kb_update<1, T, BS>;
+  template <int BS> static constexpr auto up2 = kb_update<2, T, BS>;
+};
+
+template <typename T>
+hipError_t go_init(const BatchPlan& P, const BEntry* tab, const int* offs, double gamma,
+                   hipStream_t s) {
+  GO_BS(P.bs[BK_INIT], GENO_K_INIT, BatchK<T>::template init, P.nb[BK_INIT], tab, offs, P.ngrids,
+        gamma)
+}
+
+template <typename T>
+hipError_t go_phase(int phase, const BatchPlan& P, const BEntry* tab, const int* offs,
+                    const geno::KParams& k, int stage, const Cnt& cnt, hipStream_t s) {
+  const int ng = P.ngrids;
+  switch (phase) {
+    case BK_NORMAL_X:
+      GO_BS(P.bs[phase], GENO_K_NORMAL_X, BatchK<T>::template nx, P.nb[phase], tab, offs, ng, k,
+            stage, cnt)
+    case BK_FACES_X:
+      GO_BS(P.bs[phase], GENO_K_FACES_X, BatchK<T>::template fx, P.nb[phase], tab, offs, ng, k,
+            stage, cnt)
+    case BK_NORMAL_Y:
+      GO_BS(P.bs[phase], GENO_K_NORMAL_Y, BatchK<T>::template ny, P.nb[phase], tab, offs, ng, k,
+            stage, cnt)
+    case BK_FACES_Y:
+      GO_BS(P.bs[phase], GENO_K_FACES_Y, BatchK<T>::template fy, P.nb[phase], tab, offs, ng, k,
+            stage, cnt)
+    case BK_SLOW:
+      GO_BS(P.bs[phase], GENO_K_SLOW, BatchK<T>::template slow, P.nb[phase], tab, offs, ng, k,
+            stage, cnt)
+    default:
+      if (stage == 1) {
+        GO_BS(P.bs[BK_UPDATE], GENO_K_UPDATE_1, BatchK<T>::template up1, P.nb[BK_UPDATE], tab,
+              offs, ng, k, cnt)
+      } else {
+        GO_BS(P.bs[BK_UPDATE], GENO_K_UPDATE_2, BatchK<T>::template up2, P.nb[BK_UPDATE], tab,
+              offs, ng, k, cnt)
+      }
+  }
+}
+
+template <typename T>
+int batch_step(const BatchPlan& P, const BEntry* tab, const int* offs, const geno::KParams& k,
+               const Cnt& cnt, hipStream_t s) {
+  for (int stage = 1; stage <= 2; ++stage)
+    for (int phase : {BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE})
+      HIP_TRY(go_phase<T>(phase, P, tab, offs, k, stage, cnt, s));
+  return GENO_OK;
+}
+
+// nsteps steps of a planned, bound batch whose table is in ws
+template <typename T>
+int batch_run(const BatchPlan& P, char* ws, const geno_grid* g0, int nsteps, int use_graph,
+              float* step_ms, const Cnt& cnt, hipStream_t s) {
+  const BEntry* tab = reinterpret_cast<const BEntry*>(ws + P.tab_off);
+  const int* offs = reinterpret_cast<const int*>(ws + P.offs_off);
+  const geno::KParams k = kparams(g0);
+  HIP_TRY(go_init<T>(P, tab, offs, k.gamma, s));
+  std::vector<hipEvent_t> ev;
+  if (step_ms && nsteps > 0) {
+    ev.assign(nsteps + 1, nullptr);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  }
+  int rc = GENO_OK;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph && nsteps > 0) {
+    g_tim_suspend = 1;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      rc = batch_step<T>(P, tab, offs, k, cnt, s);
+      hipError_t e2 = hipStreamEndCapture(s, &graph);
+      if (rc == GENO_OK && e2 != hipSuccess)
+        rc = fail(GENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+      if (rc == GENO_OK) {
+        e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e2 != hipSuccess) rc = fail(GENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+      }
+    } else {
+      rc = fail(GENO_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    g_tim_suspend = 0;
+  }
+  for (int n = 0; rc == GENO_OK && n < nsteps; ++n) {
+    if (!ev.empty() && n == 0) {
+      hipError_t e = hipEventRecord(ev[0], s);
+      if (e != hipSuccess) rc = fail(GENO_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
+    }
+    if (exec) {
+      hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) rc = fail(GENO_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    } else if (rc == GENO_OK) {
+      rc = batch_step<T>(P, tab, offs, k, cnt, s);
+    }
+    if (rc == GENO_OK && !ev.empty()) {
+      hipError_t e = hipEventRecord(ev[n + 1], s);
+      if (e != hipSuccess) rc = fail(GENO_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
+    }
+  }
+  if (exec || !ev.empty()) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (rc == GENO_OK && e != hipSuccess) rc = fail(GENO_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  if (rc == GENO_OK && !ev.empty())
+    for (int n = 0; n < nsteps; ++n) {
+      hipError_t e = hipEventElapsedTime(&step_ms[n], ev[n], ev[n + 1]);
+      if (e != hipSuccess) {
+        rc = fail(GENO_EHIP, "hipEventElapsedTime: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  return rc;
+}
+
+// plan, bind and upload the batch table (the call waits for the copy)
+int prepare_batch(int ngrids, const geno_grid* grids, void* const* W, void* const* dW, void* ws,
+                  const geno_tuning* tune, BatchPlan* P, hipStream_t s) {
+  int rc = check_batch(ngrids, grids);
+  if (rc) return rc;
+  if (!W || !dW || !ws) return fail(GENO_EINVAL, "null pointer");
+  for (int i = 0; i < ngrids; ++i)
+    if (!W[i] || !dW[i]) return fail(GENO_EINVAL, "null state pointer of grid %d", i);
+  geno_tuning t;
+  rc = tuning_of(tune, &t);
+  if (rc) return rc;
+  rc = plan_batch(ngrids, grids, t, P);
+  if (rc) return rc;
+  bind_batch(P, (char*)ws, W, dW, grids);
+  HIP_TRY(hipMemcpyAsync((char*)ws + P->tab_off, P->tab.data(), sizeof(BEntry) * ngrids,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync((char*)ws + P->offs_off, P->offs.data(), sizeof(int) * P->offs.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return GENO_OK;
+}
+
+int batch_stats(const BatchPlan& P, char* ws, const geno_grid* grids, geno_stats* stats,
+                hipStream_t s) {
+  stats->guard = 0;
+  stats->nonfinite = 0;
+  stats->last_dt = 0.0;
+  for (int i = 0; i < P.ngrids; ++i) {
+    const Layout L = layout_of(&grids[i]);
+    Ctrl h;
+    HIP_TRY(hipMemcpyAsync(&h, ws + P.goff[i] + L.ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stats->guard += (long long)h.guard;
+    stats->nonfinite += (long long)h.nonfinite;
+    if (i == 0) stats->last_dt = h.dt;
+  }
+  if (stats->nonfinite)
+    return fail(GENO_ENONPHYS, "%lld non-physical cells in the batch", stats->nonfinite);
+  return GENO_OK;
+}
+
 }  // namespace
 
 // operation costs per work class (opcount.hip)
@@ -1295,6 +1769,134 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
       return fail(GENO_ENONPHYS, "%llu non-physical cells (non-finite, rho <= 0 or p <= 0)",
                   h.nonfinite);
   }
+  return GENO_OK;
+}
+
+int geno_tuning_default(geno_tuning* t) {
+  if (!t) return fail(GENO_EINVAL, "null tuning");
+  return tuning_of(nullptr, t);
+}
+
+size_t gks_batched_workspace_bytes(int ngrids, const geno_grid* grids) {
+  if (check_batch(ngrids, grids)) return 0;
+  geno_tuning t;
+  tuning_of(nullptr, &t);
+  BatchPlan P;
+  if (plan_batch(ngrids, grids, t, &P)) return 0;
+  return P.total;
+}
+
+int gks_step_batched(int ngrids, const geno_grid* grids, void* const* W, void* const* dW, void* ws,
+                     int nsteps, const geno_tuning* tune, int use_graph, float* step_ms,
+                     geno_stats* stats, void* stream) {
+  if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  if (use_graph && s == nullptr)
+    return fail(GENO_EINVAL, "graph mode needs a stream other than the NULL stream");
+  BatchPlan P;
+  int rc = prepare_batch(ngrids, grids, W, dW, ws, tune, &P, s);
+  if (rc) return rc;
+  Cnt cnt{nullptr, 0};
+  if (g_cnt.on) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int cap = 1;
+    for (int k = 0; k < BK_N; ++k) cap = std::max(cap, P.nb[k]);
+    if (!g_cnt.p || cap > g_cnt.cap || dev != g_cnt.dev) {
+      if (g_cnt.p) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(g_cnt.p));
+        g_cnt.p = nullptr;
+      }
+      HIP_TRY(hipMalloc((void**)&g_cnt.p,
+                        (size_t)GENO_NKERNELS * GENO_NCLASS * cap * sizeof(unsigned long long)));
+      g_cnt.cap = cap;
+      g_cnt.dev = dev;
+    }
+    HIP_TRY(hipMemsetAsync(g_cnt.p, 0,
+                           (size_t)GENO_NKERNELS * GENO_NCLASS * g_cnt.cap *
+                               sizeof(unsigned long long),
+                           s));
+    cnt = Cnt{g_cnt.p, g_cnt.cap};
+  }
+  if (grids[0].params.precision == GENO_MIXED)
+    rc = batch_run<float>(P, (char*)ws, &grids[0], nsteps, use_graph, step_ms, cnt, s);
+  else
+    rc = batch_run<double>(P, (char*)ws, &grids[0], nsteps, use_graph, step_ms, cnt, s);
+  if (rc) return rc;
+  if (stats) return batch_stats(P, (char*)ws, grids, stats, s);
+  return GENO_OK;
+}
+
+int geno_autotune_batched(int ngrids, const geno_grid* grids, void* const* W, void* const* dW,
+                          void* ws, int trial_steps, geno_tuning* out, void* stream) {
+  if (!out) return fail(GENO_EINVAL, "null tuning");
+  if (trial_steps < 1) return fail(GENO_EINVAL, "trial_steps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  geno_tuning best;
+  tuning_of(nullptr, &best);
+  const bool mixed = check_batch(ngrids, grids) == GENO_OK && grids[0].params.precision == GENO_MIXED;
+  const Cnt none{nullptr, 0};
+  // one run of a candidate: summed kernel time of the given kinds
+  auto trial = [&](const geno_tuning& t, std::initializer_list<int> kinds, double* ms) -> int {
+    BatchPlan P;
+    int rc = prepare_batch(ngrids, grids, W, dW, ws, &t, &P, s);
+    if (rc) return rc;
+    rc = geno_timing_enable(12 * trial_steps + 4);
+    if (rc) return rc;
+    rc = mixed ? batch_run<float>(P, (char*)ws, &grids[0], trial_steps, 0, nullptr, none, s)
+               : batch_run<double>(P, (char*)ws, &grids[0], trial_steps, 0, nullptr, none, s);
+    double tot[GENO_NKERNELS];
+    long long nl[GENO_NKERNELS];
+    if (rc == GENO_OK) rc = geno_timing_read(GENO_NKERNELS, tot, nl);
+    geno_timing_enable(0);
+    if (rc) return rc;
+    *ms = 0.0;
+    for (int k : kinds) *ms += tot[k];
+    return GENO_OK;
+  };
+  double ms = 0.0;
+  int rc = trial(best, {GENO_K_INIT}, &ms);   // warm-up
+  if (rc) return rc;
+  const int sizes[3] = {128, 256, 512};
+  struct Field {
+    int geno_tuning::*f;
+    std::initializer_list<int> kinds;
+  };
+  const Field fields[3] = {{&geno_tuning::block_normal, {GENO_K_NORMAL_X, GENO_K_NORMAL_Y}},
+                           {&geno_tuning::block_faces, {GENO_K_FACES_X, GENO_K_FACES_Y}},
+                           {&geno_tuning::block_update,
+                            {GENO_K_UPDATE_1, GENO_K_UPDATE_2, GENO_K_INIT}}};
+  for (const Field& fd : fields) {
+    double bms = 1e300;
+    int bsz = best.*fd.f;
+    for (int b : sizes) {
+      geno_tuning t = best;
+      t.*fd.f = b;
+      rc = trial(t, fd.kinds, &ms);
+      if (rc) return rc;
+      if (ms < bms) {
+        bms = ms;
+        bsz = b;
+      }
+    }
+    best.*fd.f = bsz;
+  }
+  double bms = 1e300;
+  geno_tuning bslow = best;
+  for (int b : sizes)
+    for (int fpb : {512, 2048, 8192}) {
+      geno_tuning t = best;
+      t.block_slow = b;
+      t.slow_faces_per_block = fpb;
+      rc = trial(t, {GENO_K_SLOW}, &ms);
+      if (rc) return rc;
+      if (ms < bms) {
+        bms = ms;
+        bslow = t;
+      }
+    }
+  *out = bslow;
   return GENO_OK;
 }
 

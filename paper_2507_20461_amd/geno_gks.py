@@ -38,6 +38,15 @@ class geno_grid(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("params", geno_params)]
 
 
+class geno_tuning(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int), ("block_normal", ctypes.c_int), ("block_faces", ctypes.c_int),
+                ("block_slow", ctypes.c_int), ("block_update", ctypes.c_int),
+                ("slow_faces_per_block", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "version"}
+
+
 class geno_stats(ctypes.Structure):
     _fields_ = [("guard", ctypes.c_longlong), ("nonfinite", ctypes.c_longlong),
                 ("last_dt", ctypes.c_double)]
@@ -46,7 +55,8 @@ class geno_stats(ctypes.Structure):
 EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_grid_init",
            "geno_state_elems", "gks_workspace_bytes", "geno_reconstruct", "gks_flux", "gks_step",
            "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
-           "geno_kernel_name")
+           "geno_kernel_name", "geno_tuning_default", "gks_batched_workspace_bytes", "gks_step_batched",
+           "geno_autotune_batched")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d")
 WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard")
 
@@ -87,6 +97,16 @@ def lib():
         L.geno_kernel_name.restype = ctypes.c_char_p
         L.geno_work_read.argtypes = [i, i, ctypes.POINTER(ctypes.c_longlong), vp]
         L.geno_op_costs.argtypes = [ctypes.POINTER(geno_grid), i, i, ctypes.POINTER(ctypes.c_double)]
+        L.geno_tuning_default.argtypes = [ctypes.POINTER(geno_tuning)]
+        L.gks_batched_workspace_bytes.argtypes = [i, ctypes.POINTER(geno_grid)]
+        L.gks_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.gks_step_batched.argtypes = [i, ctypes.POINTER(geno_grid), ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i,
+                                       ctypes.POINTER(geno_tuning), i, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(geno_stats), vp]
+        L.geno_autotune_batched.argtypes = [i, ctypes.POINTER(geno_grid), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                            vp, i, ctypes.POINTER(geno_tuning), vp]
+        for name in ("geno_tuning_default", "gks_step_batched", "geno_autotune_batched"):
+            getattr(L, name).restype = i
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
                      "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
                      "geno_op_costs"):
@@ -273,3 +293,64 @@ def op_costs(grid):
     out = (ctypes.c_double * (nk * nc))()
     _check(lib().geno_op_costs(ctypes.byref(grid.g), nk, nc, out))
     return {KERNELS[a]: {WORK_CLASSES[c]: out[a * nc + c] for c in range(nc)} for a in range(nk)}
+
+
+# ------------------------------------------------------------------ batched form
+def default_tuning():
+    t = geno_tuning()
+    _check(lib().geno_tuning_default(ctypes.byref(t)))
+    return t
+
+
+class Batch:
+    """Independent 2-D grids advanced together by gks_step_batched. Grids may
+    differ in size and boundary conditions; all other parameters must match."""
+
+    def __init__(self, grids):
+        self.grids = list(grids)
+        n = len(self.grids)
+        self.garr = (geno_grid * n)(*[g.g for g in self.grids])
+        self.n = n
+
+    def workspace(self, device="cuda"):
+        nb = lib().gks_batched_workspace_bytes(self.n, self.garr)
+        if nb == 0:
+            raise GenoError(GENO_EINVAL, lib().geno_last_error().decode())
+        return torch.empty(nb, dtype=torch.uint8, device=device)
+
+    def _ptrs(self, Ws, dWs, ws):
+        if len(Ws) != self.n or len(dWs) != self.n:
+            raise ValueError("one W and one dW per grid")
+        for g, W, dW in zip(self.grids, Ws, dWs):
+            _check_state(g, W, dW)
+        _need(ws, torch.uint8, lib().gks_batched_workspace_bytes(self.n, self.garr), "ws")
+        pw = (ctypes.c_void_p * self.n)(*[W.data_ptr() for W in Ws])
+        pd = (ctypes.c_void_p * self.n)(*[d.data_ptr() for d in dWs])
+        return pw, pd
+
+    def step(self, Ws, dWs, ws, nsteps, tuning=None, graph=True, step_times=False, stats=False, stream=None):
+        """nsteps steps of every grid in place; returns (step_ms array or None, geno_stats or None).
+        Graph mode runs on a side stream (the NULL stream cannot be captured)."""
+        pw, pd = self._ptrs(Ws, dWs, ws)
+        if stream is None:
+            stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        ms = (ctypes.c_float * max(int(nsteps), 1))() if step_times else None
+        st = geno_stats() if stats else None
+        _check(lib().gks_step_batched(self.n, self.garr, pw, pd, _ptr(ws), int(nsteps),
+                                      ctypes.byref(tuning) if tuning is not None else None, 1 if graph else 0,
+                                      ms, ctypes.byref(st) if st is not None else None,
+                                      ctypes.c_void_p(stream.cuda_stream)))
+        torch.cuda.current_stream().wait_stream(stream)
+        return (np.array(ms[:nsteps], dtype=np.float64) if step_times else None), st
+
+    def autotune(self, Ws, dWs, ws, trial_steps=3, stream=None):
+        """Autotuned work-group shapes (the trials advance the given state: pass copies)."""
+        pw, pd = self._ptrs(Ws, dWs, ws)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        t = geno_tuning()
+        _check(lib().geno_autotune_batched(self.n, self.garr, pw, pd, _ptr(ws), int(trial_steps),
+                                           ctypes.byref(t), ctypes.c_void_p(stream.cuda_stream)))
+        return t
+

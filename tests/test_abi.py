@@ -68,3 +68,25 @@ def test_host_side_validation(so):
     # null pointers are rejected before any launch
     assert G.lib().gks_step(ctypes.byref(g.g), None, None, None, 1, None, None, None) == G.GENO_EINVAL
     assert G.lib().geno_reconstruct(ctypes.byref(g.g), None, None, 0, None, None, None, None) == G.GENO_EINVAL
+
+
+def test_batched_host_side_validation(so):
+    from paper_2507_20461_amd import geno_gks as G
+    t = G.default_tuning()
+    assert (t.block_normal, t.block_faces, t.block_slow, t.block_update, t.slow_faces_per_block) == (256, 256, 256, 256, 2048)
+    a, b = G.Grid(2, 32, 24, bc=1), G.Grid(2, 40, 16, bc=0)
+    B = G.Batch([a, b])
+    single = sum(G.lib().gks_workspace_bytes(ctypes.byref(g.g)) for g in (a, b))
+    assert G.lib().gks_batched_workspace_bytes(2, B.garr) >= single
+    # mismatched method parameters, 1-D grids and empty batches are rejected
+    for bad in ([a, G.Grid(2, 8, 8, cfl=0.3)], [G.Grid(1, 16)]):
+        assert G.lib().gks_batched_workspace_bytes(len(bad), G.Batch(bad).garr) == 0
+    assert G.lib().gks_batched_workspace_bytes(0, B.garr) == 0
+    # null pointers and graph mode on the NULL stream fail before any launch
+    assert G.lib().gks_step_batched(2, B.garr, None, None, None, 1, None, 0, None, None, None) == G.GENO_EINVAL
+    assert G.lib().gks_step_batched(2, B.garr, None, None, None, 1, None, 1, None, None, None) == G.GENO_EINVAL
+    bad_t = G.default_tuning()
+    bad_t.block_faces = 96
+    vp = (ctypes.c_void_p * 2)(1, 1)
+    assert G.lib().gks_step_batched(2, B.garr, vp, vp, ctypes.c_void_p(1), 1, ctypes.byref(bad_t), 0, None, None,
+                                    None) == G.GENO_EINVAL

@@ -1,0 +1,147 @@
+"""The batched form (gks_step_batched) through the C ABI: identical results to
+gks_step on each grid alone, in eager and graph mode, for every work-group
+shape, and a working autotuner.
+
+The batched launches run the same per-cell arithmetic as the single-grid
+launches (only the mapping of work-groups to grids differs, and the CFL
+minimum does not depend on the order of its reduction), so the comparison is
+bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2507_20461_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_20461_amd import geno_gks
+    geno_gks.lib()
+    return geno_gks
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# (nx, ny, bc, seed): uneven sizes, one periodic grid
+SHAPES = [(32, 32, 1, 0), (48, 40, 1, 1), (64, 24, 0, 2), (20, 56, 1, 3), (72, 72, 1, 4)]
+
+
+def _make(G, prec):
+    grids, data = [], []
+    for nx, ny, bc, seed in SHAPES:
+        W, dW, _ = inputs.quadrants_2d(nx, ny, seed)
+        Ws, dWs = inputs.random_smooth_2d(nx, ny, seed + 5)
+        W = W + 0.05 * (Ws - Ws.mean(axis=(1, 2), keepdims=True))
+        dW = dW + 0.05 * dWs
+        grids.append(G.Grid(2, nx, ny, bc=bc, precision=prec))
+        data.append((W, dW))
+    return grids, data
+
+
+def _upload(grids, data):
+    return ([g.to_device(W) for g, (W, _) in zip(grids, data)],
+            [g.grad_to_device(dW) for g, (_, dW) in zip(grids, data)])
+
+
+def _single(G, grids, data, nsteps):
+    out = []
+    for g, (W, dW) in zip(grids, data):
+        Wd, dWd = g.to_device(W), g.grad_to_device(dW)
+        st = G.gks_step(g, Wd, dWd, g.workspace(), nsteps, stats=True)
+        assert st.nonfinite == 0
+        out.append((g.interior(Wd), g.interior(dWd)))
+    return out
+
+
+def _same(grids, Ws, dWs, ref):
+    for g, W, dW, (rW, rdW) in zip(grids, Ws, dWs, ref):
+        if not (np.array_equal(g.interior(W), rW) and np.array_equal(g.interior(dW), rdW)):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_equals_single_grid(G, mixed):
+    prec = G.MIXED if mixed else G.F64
+    grids, data = _make(G, prec)
+    ref = _single(G, grids, data, 4)
+    B = G.Batch(grids)
+    ws = B.workspace()
+    for graph in (False, True):
+        Ws, dWs = _upload(grids, data)
+        _, st = B.step(Ws, dWs, ws, 4, graph=graph, stats=True)
+        assert st.nonfinite == 0
+        _say("batched (%s, graph=%s) vs single grids" % ("mixed" if mixed else "fp64", graph))
+        assert _same(grids, Ws, dWs, ref)
+
+
+def test_graph_replays_match_eager(G):
+    # every replay count 1..4 of the captured step equals as many eager steps;
+    # eager work and synchronisations of the program run between the calls
+    grids, data = _make(G, G.MIXED)
+    B = G.Batch(grids)
+    ws = B.workspace()
+    scratch = torch.randn(1 << 20, device="cuda")
+    for n in range(1, 5):
+        Ws, dWs = _upload(grids, data)
+        B.step(Ws, dWs, ws, n, graph=False)
+        ref = [(g.interior(W), g.interior(dW)) for g, W, dW in zip(grids, Ws, dWs)]
+        scratch.mul_(1.0001).add_(0.5)
+        torch.cuda.synchronize()
+        Ws, dWs = _upload(grids, data)
+        ms, _ = B.step(Ws, dWs, ws, n, graph=True, step_times=True)
+        assert len(ms) == n and np.all(ms > 0)
+        assert _same(grids, Ws, dWs, ref), n
+
+
+def test_every_work_group_shape_gives_the_same_result(G):
+    grids, data = _make(G, G.MIXED)
+    B = G.Batch(grids)
+    ws = B.workspace()
+    ref = None
+    for bs, fpb in ((128, 512), (256, 2048), (512, 8192), (512, 64)):
+        t = G.default_tuning()
+        t.block_normal = t.block_faces = t.block_slow = t.block_update = bs
+        t.slow_faces_per_block = fpb
+        Ws, dWs = _upload(grids, data)
+        B.step(Ws, dWs, ws, 3, tuning=t, graph=True)
+        got = [(g.interior(W), g.interior(dW)) for g, W, dW in zip(grids, Ws, dWs)]
+        if ref is None:
+            ref = got
+        else:
+            assert all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(got, ref)), bs
+
+
+def test_autotune_gives_a_valid_tuning(G):
+    grids, data = _make(G, G.MIXED)
+    B = G.Batch(grids)
+    ws = B.workspace()
+    Ws, dWs = _upload(grids, data)
+    t = B.autotune(Ws, dWs, ws, trial_steps=2)
+    _say("autotuned:", t.as_dict())
+    assert t.block_normal in (128, 256, 512) and t.block_faces in (128, 256, 512)
+    assert t.block_slow in (128, 256, 512) and t.block_update in (128, 256, 512)
+    assert t.slow_faces_per_block in (512, 2048, 8192)
+    ref = _single(G, grids, data, 2)
+    Ws, dWs = _upload(grids, data)
+    B.step(Ws, dWs, ws, 2, tuning=t, graph=True)
+    assert _same(grids, Ws, dWs, ref)
+
+
+def test_batched_rejects_mismatched_parameters(G):
+    a = G.Grid(2, 16, 16, bc=1)
+    b = G.Grid(2, 16, 16, bc=1, cfl=0.4)
+    B = G.Batch([a, b])
+    with pytest.raises(G.GenoError):
+        B.workspace()
