@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP64 vs mixed comparison at 2048^2")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched workload")
     return ap.parse_args()
 
 
@@ -183,6 +184,57 @@ def forms_comparison(G, inputs, np, torch, seed, n=2048, steps=200, acc_steps=10
     return out
 
 
+def batched_workload(G, inputs, np, torch, seed, ngrids=64, steps=100):
+    """64 independent quadrant grids of seeded sizes in {128, 256, 512,
+    1024}^2 (mixed precision, transmissive, CFL 0.5) advanced 100 steps by
+    gks_step_batched: one graph launch per step, work-group shapes from the
+    autotuner (tuned on a copy of the initial state). Throughput over the
+    whole batch and per-step p50/p99 from events between the graph launches;
+    beside it, the same grids advanced one after another by gks_step."""
+    spec = inputs.batched_grids(seed, ngrids)
+    grids = [G.Grid(2, s, s, bc=G.BC_TRANSMISSIVE, precision=G.MIXED) for s, _, _, _ in spec]
+    B = G.Batch(grids)
+    ws = B.workspace()
+    cells = sum(s * s for s, _, _, _ in spec)
+
+    def upload():
+        return ([g.to_device(W) for g, (_, W, _, _) in zip(grids, spec)],
+                [g.grad_to_device(dW) for g, (_, _, dW, _) in zip(grids, spec)])
+
+    Ws, dWs = upload()
+    tune = B.autotune(Ws, dWs, ws, trial_steps=2)
+    Ws, dWs = upload()
+    B.step(Ws, dWs, ws, 2, tuning=tune, graph=True)          # warm-up
+    Ws, dWs = upload()
+    torch.cuda.synchronize()
+    ms, st = B.step(Ws, dWs, ws, steps, tuning=tune, graph=True, step_times=True, stats=True)
+    total = float(ms.sum())
+    sides, counts = np.unique([s for s, _, _, _ in spec], return_counts=True)
+    out = {"workload": "%d grids (%s), %d cells, mixed precision, %d steps" % (
+               ngrids, ", ".join("%dx%d^2" % (int(c), int(s)) for s, c in zip(sides, counts)), cells, steps),
+           "value": round(2.0 * cells * steps / (total / 1e3) / 1e6, 3), "unit": "Mcell-updates/s per stage",
+           "ms_total": round(total, 3), "step_ms_p50": round(float(np.percentile(ms, 50)), 4),
+           "step_ms_p99": round(float(np.percentile(ms, 99)), 4), "step_ms_max": round(float(ms.max()), 4),
+           "tuning": {k: int(v) for k, v in tune.as_dict().items()}, "guard": st.guard}
+    del ws, Ws, dWs
+    # the same grids one after another (one gks_step call of all steps per grid)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    seq = 0.0
+    for g, (_, W, dW, _) in zip(grids, spec):
+        w1, d1, ws1 = g.to_device(W), g.grad_to_device(dW), g.workspace()
+        torch.cuda.synchronize()
+        e0.record()
+        G.gks_step(g, w1, d1, ws1, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        seq += e0.elapsed_time(e1)
+        del w1, d1, ws1
+    out["sequential_per_grid"] = {"value": round(2.0 * cells * steps / (seq / 1e3) / 1e6, 3),
+                                  "ms_total": round(seq, 3)}
+    out["speedup_vs_sequential"] = round(seq / total, 4)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -296,6 +348,8 @@ def main():
     if not args.no_forms:
         del ws, Wd, dWd
         out["forms"] = _finite(forms_comparison(G, inputs, np, torch, args.seed))
+    if not args.no_batched:
+        out["batched"] = _finite(batched_workload(G, inputs, np, torch, args.seed))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)
     print(json.dumps(out), flush=True)

@@ -35,7 +35,7 @@ CAL_ELEMS = CAL_BYTES // 8
 
 BENCH_FULL = ["python3", os.path.join(ROOT, "bench.py")]
 BENCH_SHORT = ["python3", os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
-               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms"]
+               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms", "--no-batched"]
 PASSES = {
     "ktrace": (["--kernel-trace", "--stats"], BENCH_FULL),
     "fetch": (["--pmc", "FETCH_SIZE"], BENCH_SHORT),
@@ -116,9 +116,13 @@ def summarize(tag="faces_fp64_512"):
         if k.startswith("k_init<2"):
             n = int(round(cells ** 0.5))
             label = "%s %dx%d" % ("mixed" if "float" in k else "fp64", n, n)
-        if label is None or not k.startswith("k_"):
+        if k.startswith("kb_"):
+            lab = "batched (mixed)"
+        elif label is None or not k.startswith("k_"):
             continue
-        per.setdefault(label, collections.OrderedDict()).setdefault(k, []).append(
+        else:
+            lab = label
+        per.setdefault(lab, collections.OrderedDict()).setdefault(k, []).append(
             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     lines.append("# rocprofv3 kernel trace of bench.py (default run), per workload")
     lines.append("# command: " + " ".join(command("ktrace")).replace(ROOT + "/", ""))
