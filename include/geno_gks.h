@@ -84,7 +84,13 @@ extern "C" {
  *   and (8), qmax the largest |value| of the stencil (0 gives the plain eps).
  *   In a run, the float32 fluxes also leave rounding of about one unit in the
  *   last place per step in W (dt/dx times the rounding of F), which
- *   accumulates over the steps; the default is 64. */
+ *   accumulates over the steps; the default is 64.
+ * gate_delta: learned gate (2-D gks_step only). If > 0, before the normal
+ *   reconstruction of each direction and stage the loaded network
+ *   (geno_mlp_load) predicts chi of every cell from its stencil, and where the
+ *   prediction is >= 1 - gate_delta the cell's two face-sides of that
+ *   direction take chi = 1 (the linear reconstruction) without forming the
+ *   smoothness indicators; elsewhere plain GENO decides. 0 (default) = off. */
 typedef struct geno_params {
   int version;
   int precision;   /* GENO_F64 or GENO_MIXED */
@@ -100,6 +106,7 @@ typedef struct geno_params {
   int bc[4];
   double dt_fixed;
   double eps_ulps;
+  double gate_delta;
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */
@@ -258,6 +265,62 @@ int gks_step_batched(int ngrids, const geno_grid* grids, void* const* W, void* c
 int geno_autotune_batched(int ngrids, const geno_grid* grids, void* const* W, void* const* dW,
                           void* ws, int trial_steps, geno_tuning* out, void* stream);
 
+/* ---- learned gate ---------------------------------------------------------
+ * A small network predicts the path function chi (Eq. (4)) of a cell and
+ * direction from its normalised 5-cell stencil; it is trained on stencils the
+ * solver harvests, and plain GENO is the fallback wherever the prediction is
+ * below 1 - gate_delta.
+ * Network: 40 inputs -> 64 -> 64 (GELU, tanh form) -> 1 (sigmoid);
+ * parameters are 6849 floats in the order W1[64][40], b1[64], W2[64][64],
+ * b2[64], w3[64], b3.
+ * Input of cell j along a direction (face frame: normal momentum second): per
+ * conserved variable q, den = max - min of q over cells j-2..j+2 +
+ * 1e-12 |q_j| + 1e-300; features (q_m - q_j)/den, m = -2..2, then
+ * h (dq/dn)_m / den, m = -2..2, each clipped to [-64, 64]; variable-major.
+ * Target: the smallest plain-GENO chi over the cell's two face-sides of the
+ * direction (left state of its face j+1/2, right state of its face j-1/2) and
+ * the four variables. */
+#define GENO_MLP_NIN 40
+#define GENO_MLP_NPARAM 6849
+
+/* Network input X[ncell][40] (float) and target y[ncell] (float, may be NULL)
+ * of every interior cell (row-major, x fastest) for direction dir of a 2-D
+ * grid, after filling the ghost cells of W and dW in place; targets from
+ * float64 plain GENO. ws: workspace of gks_workspace_bytes(g). */
+int geno_harvest(const geno_grid* g, void* W, void* dW, int dir, float* X, float* y, void* ws,
+                 void* stream);
+
+/* Device scratch of geno_mlp_grad for a minibatch of n samples. */
+size_t geno_mlp_train_workspace_bytes(int n);
+
+/* Training in float32 (device pointers): gradient of the mean binary
+ * cross-entropy of the network (params) on X[n][40], y[n] into grad[6849],
+ * and the loss itself into loss[0] (may be NULL). Deterministic. */
+int geno_mlp_grad(const float* params, const float* X, const float* y, int n, float* grad,
+                  float* loss, void* ws, void* stream);
+
+/* One Adam step on params with moments m, v (t counts from 1). */
+int geno_mlp_adam(float* params, const float* grad, float* m, float* v, int t, float lr,
+                  float beta1, float beta2, float eps, void* stream);
+
+/* Float32 forward pass (reference of the training kernels): prob[n]. */
+int geno_mlp_forward(const float* params, const float* X, int n, float* prob, void* stream);
+
+/* Loads a trained network (device float params[6849]) as the library's
+ * bfloat16 copy used by the gate and geno_mlp_infer, on the current device.
+ * Waits for the stream. */
+int geno_mlp_load(const float* params, void* stream);
+
+/* Inference with the loaded network on bfloat16 matrix cores (float32
+ * accumulation): prob[n] for X[n][40] (device). */
+int geno_mlp_infer(const float* X, int n, float* prob, void* stream);
+
+/* The gate's prediction for every interior cell of a 2-D grid and direction
+ * (inputs built on the device from W, dW as geno_harvest does; ghost cells
+ * filled in place): prob[ncell]. */
+int geno_gate_prob(const geno_grid* g, void* W, void* dW, int dir, float* prob, void* ws,
+                   void* stream);
+
 /* ---- measurement support ------------------------------------------------
  * Kernel kinds of gks_step reported by geno_timing_read / geno_work_read. */
 enum {
@@ -271,6 +334,7 @@ enum {
   GENO_K_UPDATE_1,     /* stage-1 update, gradients, ghost cells of the stage state */
   GENO_K_UPDATE_2,     /* stage-2 update, gradients, ghost cells, CFL partial minima */
   GENO_K_FACES_1D,     /* 1-D: GENO + flux per face */
+  GENO_K_GATE,         /* learned gate of both directions (network inference) */
   GENO_NKERNELS
 };
 
@@ -283,6 +347,7 @@ enum {
   GENO_W_FAST,         /* gas-kinetic points with tau = 0 and different states */
   GENO_W_SLOW,         /* gas-kinetic points evaluated with tau > 0 */
   GENO_W_GUARD,        /* point states replaced by the cell average */
+  GENO_W_GATED,        /* face-sides whose indicators the gate skipped */
   GENO_NCLASS
 };
 

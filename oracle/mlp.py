@@ -133,7 +133,9 @@ def harvest(W, dW, direction, bc, h, chi=None):
     Frame: the conserved variables in the face frame of the direction (normal
     momentum second). Per variable q: den = max - min of q over the 5 cells
     j-2..j+2 along the direction + 1e-12 |q_j| + 1e-300; features
-    (q_m - q_j)/den, m = -2..2, then h * (dq/dn)_m / den, m = -2..2.
+    (q_m - q_j)/den, m = -2..2, then h * (dq/dn)_m / den, m = -2..2, each
+    clipped to [-64, 64] (gradients of nearly constant data can be large
+    relative to den).
     Feature order: variable-major, 10 per variable.
     Target: min over the cell's two face-sides (the left state of its face
     j+1/2, the right state of its face j-1/2) and the four variables of the
@@ -165,7 +167,7 @@ def harvest(W, dW, direction, bc, h, chi=None):
         den = (qs.max(axis=0) - qs.min(axis=0)) + 1e-12 * np.abs(q0) + 1e-300
         X[:, :, v, 0:5] = np.moveaxis((qs - q0) / den, 0, -1)
         X[:, :, v, 5:10] = np.moveaxis(gs / den, 0, -1)
-    X = X.reshape(ny * nx, 40)
+    X = np.clip(X, -64.0, 64.0).reshape(ny * nx, 40)
     if chi is None:
         return X, None
     chi = np.asarray(chi)

@@ -33,6 +33,8 @@ struct KParams {
   double cfl;
   double dt_fixed;    // > 0: fixed time step instead of the CFL condition
   double eps_ulps;    // float32 data: eps floor in units of 2^-24 of the stencil magnitude
+  double gate_thr;    // learned gate: a prediction >= gate_thr sets chi = 1
+  int gate;           // learned gate enabled
 };
 
 // Path function chi = tanh(C alpha)/tanh(C) (Eq. (4)) of the ultimate
@@ -137,16 +139,32 @@ GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, const KParams&
 // the indicator type D, the linear part evaluated in R). The right state
 // (cell j+1) is the left-state formula applied to the data reflected about
 // the face: Q~_m = Q_{1-m}, G~_m = -G_{1-m}; its derivative changes sign.
-// Returns the number of sides on the low-order branch.
+// A side marked skip (by the learned gate) takes chi = 1, the linear
+// reconstruction, without its indicators. Returns the number of sides on the
+// low-order branch.
 template <typename R, typename D>
 GENO_HD int geno_face(D Qm, D Q0, D Q1, D Q2, D Gm, D G0, D G1, D G2, const KParams& k, R& vl,
-                      R& dl, D& xl, R& vr, R& dr, D& xr) {
+                      R& dl, D& xl, R& vr, R& dr, D& xr, bool skipL = false,
+                      bool skipR = false) {
   R qH, hqH;
   linear_p7<R>(R(Qm), R(Q0), R(Q1), R(Q2), R(Gm), R(G0), R(G1), R(G2), qH, hqH);
-  int n = geno_side<R, D>(Qm, Q0, Q1, Q2, Gm, qH, hqH, k, vl, dl, xl);
-  R dm;
-  n += geno_side<R, D>(Q2, Q1, Q0, Qm, -G2, qH, -hqH, k, vr, dm, xr);
-  dr = -dm;
+  int n = 0;
+  if (skipL) {
+    vl = qH;
+    dl = hqH;
+    xl = D(1.0);
+  } else {
+    n += geno_side<R, D>(Qm, Q0, Q1, Q2, Gm, qH, hqH, k, vl, dl, xl);
+  }
+  if (skipR) {
+    vr = qH;
+    dr = hqH;
+    xr = D(1.0);
+  } else {
+    R dm;
+    n += geno_side<R, D>(Q2, Q1, Q0, Qm, -G2, qH, -hqH, k, vr, dm, xr);
+    dr = -dm;
+  }
   return n;
 }
 

@@ -30,6 +30,20 @@
 #include "geno_device.hpp"
 #include "geno_gks.h"
 #include "gks_device.hpp"
+#include "mlp_device.hpp"
+
+// error message of the last failed call on this thread (geno_last_error),
+// shared with the other source files of the library
+namespace geno_err {
+thread_local char g_err[512] = "";
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+}  // namespace geno_err
 
 namespace {
 
@@ -38,15 +52,7 @@ constexpr int BLOCK = 256;          // work-group size of the single-grid launch
 constexpr int MAXWAVES = 16;        // waves of the largest work-group (1024 lanes)
 constexpr int SLOW_BLOCKS = 1024;   // fixed grid of the queue kernels (grid-stride)
 
-thread_local char g_err[512] = "";
-
-int fail(int code, const char* fmt, ...) {
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(g_err, sizeof g_err, fmt, ap);
-  va_end(ap);
-  return code;
-}
+using geno_err::fail;
 
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
@@ -66,8 +72,9 @@ struct Timing {
 Timing g_tim;
 int g_tim_suspend = 0;   // set while a launch sequence is captured into a graph
 
-const char* const KNAMES[GENO_NKERNELS] = {"init",    "normal_x", "normal_y", "faces_x", "faces_y",
-                                           "slow",    "update_1", "update_2", "faces_1d"};
+const char* const KNAMES[GENO_NKERNELS] = {"init",     "normal_x", "normal_y", "faces_x",
+                                           "faces_y",  "slow",     "update_1", "update_2",
+                                           "faces_1d", "gate"};
 
 // Every launch goes through here: a kernel of kind >= 0 is timed while
 // timing is enabled (events bound to the dispatch itself).
@@ -305,24 +312,36 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
 // With part (first kernel of a step), block 0 also reduces the CFL partial
 // minima of the previous kernel into ctrl->tmin and records dt.
 // ---------------------------------------------------------------------------
+// gate: the learned gate's flags of the interior cells for this direction
+// ([ny][nx], 1 = chi of the cell's sides is 1), or nullptr.
 template <int DIR, typename T>
 __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k,
                                             const double* __restrict__ W,
                                             const T* __restrict__ dW, T* __restrict__ fr,
                                             double* __restrict__ chi, Ctrl* ctrl,
                                             const double* __restrict__ part, int npart,
-                                            double* dt_out, int step, const Cnt& cnt, int lb) {
+                                            double* dt_out, int step, const Cnt& cnt, int lb,
+                                            const unsigned char* __restrict__ gate = nullptr) {
   if (part && lb == 0) reduce_dt(part, npart, ctrl, k.cfl, k.dt_fixed, dt_out, step);
   if (ctrl && lb == 0 && threadIdx.x == 0) ctrl->qcount[DIR] = 0;
   const int n1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
   const int n0 = DIR == 0 ? g.ny + 2 : g.ny + 1;
   const int plane = n0 * n1;
   const int t = lb * (int)blockDim.x + (int)threadIdx.x;
-  unsigned int nlow = 0;
+  unsigned int nlow = 0, ngated = 0;
   if (t < 4 * plane) {
     const int v = t / plane, o = t - v * plane;
     const int a = o / n1, b = o - a * n1;
     const double h = DIR == 0 ? g.dx : g.dy;
+    bool skipL = false, skipR = false;
+    if (gate) {
+      // cells of the two sides: DIR 0 (row a-1; columns b-1, b), DIR 1 (rows a-1, a; column b-1)
+      const int jl = DIR == 0 ? a - 1 : a - 1, il = DIR == 0 ? b - 1 : b - 1;
+      const int jr = DIR == 0 ? a - 1 : a, ir = DIR == 0 ? b : b - 1;
+      if (jl >= 0 && jl < g.ny && il >= 0 && il < g.nx) skipL = gate[jl * g.nx + il] != 0;
+      if (jr >= 0 && jr < g.ny && ir >= 0 && ir < g.nx) skipR = gate[jr * g.nx + ir] != 0;
+      ngated = (skipL ? 1u : 0u) + (skipR ? 1u : 0u);
+    }
     double Q[4], G[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -335,7 +354,7 @@ __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k
     T vl, dl, vr, dr;
     double xl, xr;
     nlow = geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl,
-                                      xl, vr, dr, xr);
+                                      xl, vr, dr, xr, skipL, skipR);
     fr[(size_t)(0 * 4 + v) * plane + o] = vl;
     fr[(size_t)(1 * 4 + v) * plane + o] = dl;
     fr[(size_t)(2 * 4 + v) * plane + o] = vr;
@@ -349,6 +368,7 @@ __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k
     unsigned int wc[GENO_NCLASS] = {};
     wc[GENO_W_UNITS] = t < 4 * plane ? 1u : 0u;
     wc[GENO_W_LOW] = nlow;
+    wc[GENO_W_GATED] = ngated;
     block_count(cnt, DIR == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y, wc);
   }
 }
@@ -360,8 +380,10 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                                                     T* __restrict__ fr,
                                                     double* __restrict__ chi, Ctrl* ctrl,
                                                     const double* __restrict__ part, int npart,
-                                                    double* dt_out, int step, Cnt cnt) {
-  normal_body<DIR, T>(g, k, W, dW, fr, chi, ctrl, part, npart, dt_out, step, cnt, xcd_block());
+                                                    double* dt_out, int step, Cnt cnt,
+                                                    const unsigned char* __restrict__ gate) {
+  normal_body<DIR, T>(g, k, W, dW, fr, chi, ctrl, part, npart, dt_out, step, cnt, xcd_block(),
+                      gate);
 }
 
 // ---------------------------------------------------------------------------
@@ -823,6 +845,223 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
 }
 
 // ---------------------------------------------------------------------------
+// Learned gate. The loaded network lives in device globals as bfloat16
+// fragments of the B operands of v_mfma_f32_16x16x32_bf16, in lane order:
+// g_mlp_frag[layer * 8 + kb * 4 + nt][lane] holds B[k][n] for k = kb * 32 +
+// 8 * (lane / 16) + e (e = 0..7), n = nt * 16 + lane % 16, with B = W1^T
+// (inputs padded from 40 to 64 with zeros) or W2^T. One wave evaluates 16
+// samples per tile: the A operand lane (r = lane % 16, g = lane / 16) holds
+// X[r][kb * 32 + 8 g + e], and the accumulator lane holds rows 4 g + e of
+// column lane % 16. The weights stay in registers across tiles; the
+// transposes between layers go through LDS.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ bf16x8 g_mlp_frag[16][64];
+__device__ float g_mlp_vec[3 * mlp::NH + 1];   // b1, b2, w3, b3
+
+struct MlpRegs {
+  bf16x8 w[16];
+  float b1[4], b2[4], w3[4], b3;
+};
+
+__device__ __forceinline__ void mlp_regs(MlpRegs& R) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+#pragma unroll
+  for (int f = 0; f < 16; ++f) R.w[f] = g_mlp_frag[f][lane];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    R.b1[nt] = g_mlp_vec[nt * 16 + r];
+    R.b2[nt] = g_mlp_vec[mlp::NH + nt * 16 + r];
+    R.w3[nt] = g_mlp_vec[2 * mlp::NH + nt * 16 + r];
+  }
+  R.b3 = g_mlp_vec[3 * mlp::NH];
+}
+
+// Network on the 16 samples of this wave's tile: xs, hs are the wave's LDS
+// tiles [16][64] (xs filled by the caller, columns 40..63 zero). Every wave
+// of the work-group calls this together (it synchronises the work-group).
+// Returns the probabilities of samples 4 (lane / 16) + e in p[e].
+__device__ __forceinline__ void mlp_tile(const MlpRegs& R, const __bf16* xs, __bf16* hs,
+                                         float (&p)[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  bf16x8 a0 = *reinterpret_cast<const bf16x8*>(xs + r * 64 + 8 * g);
+  bf16x8 a1 = *reinterpret_cast<const bf16x8*>(xs + r * 64 + 32 + 8 * g);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, R.w[nt], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, R.w[4 + nt], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) hs[(4 * g + e) * 64 + nt * 16 + r] = (__bf16)mlp::gelu(acc[e] + R.b1[nt]);
+  }
+  __syncthreads();
+  a0 = *reinterpret_cast<const bf16x8*>(hs + r * 64 + 8 * g);
+  a1 = *reinterpret_cast<const bf16x8*>(hs + r * 64 + 32 + 8 * g);
+  float zs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, R.w[8 + nt], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, R.w[12 + nt], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) zs[e] += mlp::gelu(acc[e] + R.b2[nt]) * R.w3[nt];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float z = zs[e];
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) z += __shfl_xor(z, off, 64);
+    p[e] = mlp::sigmoid(z + R.b3);
+  }
+}
+
+// The 10 features of variable v (face frame) of cell (j, i) along DIR.
+template <int DIR, typename T>
+__device__ __forceinline__ void gate_features(const Geo& g, const double* __restrict__ W,
+                                              const T* __restrict__ dW, int j, int i, int v,
+                                              float* f) {
+  const int vv = DIR == 0 ? v : (v == 1 ? 2 : (v == 2 ? 1 : v));
+  const double h = DIR == 0 ? g.dx : g.dy;
+  const size_t gplane = (size_t)(DIR * 4) * g.rows * g.pitch;
+  double q[5], d[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const size_t id = DIR == 0 ? at(g, vv, j, i - 2 + m) : at(g, vv, j - 2 + m, i);
+    q[m] = W[id];
+    d[m] = h * (double)dW[id + gplane];
+  }
+  double mx = q[0], mn = q[0];
+#pragma unroll
+  for (int m = 1; m < 5; ++m) {
+    mx = fmax(mx, q[m]);
+    mn = fmin(mn, q[m]);
+  }
+  const double inv = 1.0 / ((mx - mn) + 1e-12 * fabs(q[2]) + 1e-300);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    f[m] = (float)fmin(64.0, fmax(-64.0, (q[m] - q[2]) * inv));
+    f[5 + m] = (float)fmin(64.0, fmax(-64.0, d[m] * inv));
+  }
+}
+
+constexpr int GATE_TILES = 8;   // tiles of 16 cells per wave of a gate work-group
+
+// Gate of every interior cell for DIR: flags (PROB = 0: out[c] = p >= thr)
+// or probabilities (PROB = 1: outp[c] = p). Work-group = 4 waves; every wave
+// runs GATE_TILES tiles (all waves the same count: mlp_tile synchronises).
+template <int DIR, typename T, int PROB>
+__global__ void __launch_bounds__(256) k_gate(Geo g, const double* __restrict__ W,
+                                              const T* __restrict__ dW, float thr,
+                                              unsigned char* __restrict__ out,
+                                              float* __restrict__ outp) {
+  __shared__ __align__(16) __bf16 xs[4][16 * 64];
+  __shared__ __align__(16) __bf16 hs[4][16 * 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  MlpRegs R;
+  mlp_regs(R);
+  const int ncell = g.nx * g.ny;
+  const int s = lane >> 2, v = lane & 3;
+  for (int it = 0; it < GATE_TILES; ++it) {
+    const int tile = (blockIdx.x * GATE_TILES + it) * 4 + w;
+    const int c = tile * 16 + s;
+    float f[10];
+    if (c < ncell) {
+      gate_features<DIR, T>(g, W, dW, c / g.nx, c % g.nx, v, f);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 10; ++m) f[m] = 0.0f;
+    }
+#pragma unroll
+    for (int m = 0; m < 10; ++m) xs[w][s * 64 + v * 10 + m] = (__bf16)f[m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) xs[w][s * 64 + 40 + v * 6 + m] = (__bf16)0.0f;
+    __syncthreads();
+    float p[4];
+    mlp_tile(R, xs[w], hs[w], p);
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c2 = tile * 16 + 4 * (lane >> 4) + e;
+        if (c2 < ncell) {
+          if (PROB) outp[c2] = p[e];
+          else out[c2] = p[e] >= thr ? 1 : 0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// the network on given inputs X[n][40] (float), for tests of the inference
+__global__ void __launch_bounds__(256) k_mlp_infer(const float* __restrict__ X, int n,
+                                                   float* __restrict__ prob) {
+  __shared__ __align__(16) __bf16 xs[4][16 * 64];
+  __shared__ __align__(16) __bf16 hs[4][16 * 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  MlpRegs R;
+  mlp_regs(R);
+  const int s = lane >> 2, v = lane & 3;
+  const int tile = blockIdx.x * 4 + w;
+  const int c = tile * 16 + s;
+#pragma unroll
+  for (int m = 0; m < 10; ++m)
+    xs[w][s * 64 + v * 10 + m] = (__bf16)(c < n ? X[(size_t)c * mlp::NIN + v * 10 + m] : 0.0f);
+#pragma unroll
+  for (int m = 0; m < 6; ++m) xs[w][s * 64 + 40 + v * 6 + m] = (__bf16)0.0f;
+  __syncthreads();
+  float p[4];
+  mlp_tile(R, xs[w], hs[w], p);
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c2 = tile * 16 + 4 * (lane >> 4) + e;
+      if (c2 < n) prob[c2] = p[e];
+    }
+  }
+}
+
+// Harvest: features (float) and the plain-GENO target (float64 indicators)
+// of every interior cell for DIR.
+template <int DIR, typename T>
+__global__ void __launch_bounds__(BLOCK) k_harvest(Geo g, geno::KParams k,
+                                                   const double* __restrict__ W,
+                                                   const T* __restrict__ dW,
+                                                   float* __restrict__ X, float* __restrict__ y) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.nx * g.ny) return;
+  const int j = c / g.nx, i = c % g.nx;
+  double tmin = 1.0;
+#pragma unroll 1
+  for (int v = 0; v < 4; ++v) {
+    float f[10];
+    gate_features<DIR, T>(g, W, dW, j, i, v, f);
+#pragma unroll
+    for (int m = 0; m < 10; ++m) X[(size_t)c * mlp::NIN + v * 10 + m] = f[m];
+    if (y) {
+      const int vv = DIR == 0 ? v : (v == 1 ? 2 : (v == 2 ? 1 : v));
+      const double h = DIR == 0 ? g.dx : g.dy;
+      const size_t gplane = (size_t)(DIR * 4) * g.rows * g.pitch;
+      double q[5], d[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const size_t id = DIR == 0 ? at(g, vv, j, i - 2 + m) : at(g, vv, j - 2 + m, i);
+        q[m] = W[id];
+        d[m] = h * (double)dW[id + gplane];
+      }
+      double val, der, xl, xr;
+      // left state of face j+1/2 (cells j-1..j+2) and right state of face j-1/2
+      // (cells j-2..j+1 reflected about that face)
+      geno::geno_side<double, double>(q[1], q[2], q[3], q[4], d[1], 0.0, 0.0, k, val, der, xl);
+      geno::geno_side<double, double>(q[3], q[2], q[1], q[0], -d[3], 0.0, 0.0, k, val, der, xr);
+      tmin = fmin(tmin, fmin(xl, xr));
+    }
+  }
+  if (y) y[c] = (float)tmin;
+}
+
+// ---------------------------------------------------------------------------
 // Batched launches: many independent 2-D grids advanced together. Each launch
 // runs one kernel kind for every grid: the grids' work-group ranges are
 // concatenated, and a work-group finds its grid by binary search over the
@@ -931,7 +1170,7 @@ __global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
 // host helpers
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t ctrl, part, queue[2], wst, dwst, r, fr[2], fl[2], total;
+  size_t ctrl, part, queue[2], gate, wst, dwst, r, fr[2], fl[2], total;
   size_t nstate;   // elements per field plane
   int npart;
 };
@@ -961,6 +1200,8 @@ Layout layout_of(const geno_grid* g) {
     off = align256(off + (size_t)g->ny * (g->nx + 1) * sizeof(unsigned int));
     L.queue[1] = off;
     off = align256(off + (size_t)(g->ny + 1) * g->nx * sizeof(unsigned int));
+    L.gate = off;   // learned-gate flags, [dir][ny][nx]
+    off = align256(off + 2 * (size_t)g->nx * g->ny);
   }
   L.wst = off;
   off = align256(off + L.nstate * nv * sizeof(double));
@@ -993,6 +1234,8 @@ int check_params(const geno_params* p) {
     return fail(GENO_EINVAL, "unsupported precision %d", p->precision);
   if (!(p->dt_fixed >= 0.0)) return fail(GENO_EINVAL, "dt_fixed must be >= 0");
   if (!(p->eps_ulps >= 0.0)) return fail(GENO_EINVAL, "eps_ulps must be >= 0");
+  if (!(p->gate_delta >= 0.0 && p->gate_delta < 1.0))
+    return fail(GENO_EINVAL, "gate_delta must be in [0, 1)");
   if (p->r != 2.0 || p->rL != 2.0) return fail(GENO_EINVAL, "only r = rL = 2 are implemented");
   if (!(p->gamma > 1.0) || !(p->eps > 0.0) || !(p->C > 0.0) || !(p->cfl > 0.0))
     return fail(GENO_EINVAL, "gamma > 1, eps > 0, C > 0 and cfl > 0 are required");
@@ -1045,6 +1288,8 @@ geno::KParams kparams(const geno_grid* g) {
   k.cfl = p.cfl;
   k.dt_fixed = p.dt_fixed;
   k.eps_ulps = p.eps_ulps;
+  k.gate = (p.gate_delta > 0.0 && g->ndim == 2) ? 1 : 0;
+  k.gate_thr = 1.0 - p.gate_delta;
   return k;
 }
 
@@ -1067,6 +1312,7 @@ struct Bufs {
   Ctrl* ctrl;
   double* part;
   unsigned int* queue[2];
+  unsigned char* gate;
   double *wst, *r;
   T *dwst, *fr[2], *fl[2];
 };
@@ -1083,6 +1329,7 @@ Bufs<T> bufs_of(char* ws, const Layout& L, int ndim) {
   if (ndim == 2) {
     b.queue[0] = reinterpret_cast<unsigned int*>(ws + L.queue[0]);
     b.queue[1] = reinterpret_cast<unsigned int*>(ws + L.queue[1]);
+    b.gate = reinterpret_cast<unsigned char*>(ws + L.gate);
     b.fr[0] = reinterpret_cast<T*>(ws + L.fr[0]);
     b.fr[1] = reinterpret_cast<T*>(ws + L.fr[1]);
     b.fl[1] = reinterpret_cast<T*>(ws + L.fl[1]);
@@ -1126,6 +1373,12 @@ int count_cap(const geno_grid* g) {
   return (int)m;
 }
 
+// work-groups of a gate launch over nc cells
+unsigned gate_blocks(size_t nc) {
+  const size_t tiles = (nc + 15) / 16;
+  return (unsigned)((tiles + 4 * GATE_TILES - 1) / (4 * GATE_TILES));
+}
+
 // one stage of gks_step: faces and update
 template <typename T>
 int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, const Bufs<T>& B,
@@ -1134,13 +1387,26 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
   const int want_F = stage == 1;
   const double* part = stage == 1 ? B.part : nullptr;   // dt of the step is reduced once
   if (g->ndim == 2) {
+    const unsigned char* gx = nullptr;
+    const unsigned char* gy = nullptr;
+    if (k.gate) {
+      const size_t nc = (size_t)g->nx * g->ny;
+      const unsigned nbg = gate_blocks(nc);
+      HIP_TRY(launch(GENO_K_GATE, k_gate<0, T, 0>, nbg, s, geo, Win, dWin, (float)k.gate_thr,
+                     B.gate, (float*)nullptr));
+      HIP_TRY(launch(GENO_K_GATE, k_gate<1, T, 0>, nbg, s, geo, Win, dWin, (float)k.gate_thr,
+                     B.gate + nc, (float*)nullptr));
+      gx = B.gate;
+      gy = B.gate + nc;
+    }
     HIP_TRY(launch(GENO_K_NORMAL_X, k_normal2d<0, T>, nblocks(4 * face_rows(g, 0)), s, geo, k,
-                   Win, dWin, B.fr[0], (double*)nullptr, B.ctrl, part, npart, dt_out, step, cnt));
+                   Win, dWin, B.fr[0], (double*)nullptr, B.ctrl, part, npart, dt_out, step, cnt,
+                   gx));
     HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
                    B.fr[0], B.fl[0], B.ctrl, want_F, cnt, B.queue[0]));
     HIP_TRY(launch(GENO_K_NORMAL_Y, k_normal2d<1, T>, nblocks(4 * face_rows(g, 1)), s, geo, k,
                    Win, dWin, B.fr[1], (double*)nullptr, B.ctrl, (const double*)nullptr, 0,
-                   (double*)nullptr, 0, cnt));
+                   (double*)nullptr, 0, cnt, gy));
     HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
                    B.fr[1], B.fl[1], B.ctrl, want_F, cnt, B.queue[1]));
     HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T>, slow_blocks(g), s, geo, k, Win, B.fr[0], B.fr[1],
@@ -1188,14 +1454,14 @@ int reconstruct_t(const geno_grid* g, double* W, T* dW, int dir, T* face_state, 
   } else if (dir == 0) {
     HIP_TRY(launch(-1, k_normal2d<0, T>, nblocks(4 * face_rows(g, 0)), s, geo, k, (const double*)W,
                    (const T*)dW, B.fr[0], chi, (Ctrl*)nullptr, (const double*)nullptr, 0,
-                   (double*)nullptr, 0, none));
+                   (double*)nullptr, 0, none, (const unsigned char*)nullptr));
     HIP_TRY(launch(-1, k_faces2d<0, 0, T>, nblocks(2 * faces_of(g, 0)), s, geo, k,
                    (const double*)W, (const T*)B.fr[0], face_state, (Ctrl*)nullptr, 0, none,
                    (unsigned int*)nullptr));
   } else {
     HIP_TRY(launch(-1, k_normal2d<1, T>, nblocks(4 * face_rows(g, 1)), s, geo, k, (const double*)W,
                    (const T*)dW, B.fr[1], chi, (Ctrl*)nullptr, (const double*)nullptr, 0,
-                   (double*)nullptr, 0, none));
+                   (double*)nullptr, 0, none, (const unsigned char*)nullptr));
     HIP_TRY(launch(-1, k_faces2d<1, 0, T>, nblocks(2 * faces_of(g, 1)), s, geo, k,
                    (const double*)W, (const T*)B.fr[1], face_state, (Ctrl*)nullptr, 0, none,
                    (unsigned int*)nullptr));
@@ -1283,6 +1549,28 @@ bool same_method(const geno_params& a, const geno_params& b) {
          a.eps_ulps == b.eps_ulps;
 }
 
+// devices on which a network has been loaded (geno_mlp_load)
+bool g_mlp_loaded[64] = {};
+
+int check_gate(const geno_grid* g) {
+  if (g->params.gate_delta > 0.0 && g->ndim == 2) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64 || !g_mlp_loaded[dev])
+      return fail(GENO_EINVAL, "gate_delta > 0 but no network is loaded (geno_mlp_load)");
+  }
+  return GENO_OK;
+}
+
+// float to bfloat16 bits, rounding to nearest even
+unsigned short f2bf(float f) {
+  unsigned int u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
 int check_batch(int ngrids, const geno_grid* grids) {
   if (ngrids < 1 || ngrids > GENO_BATCH_MAX)
     return fail(GENO_EINVAL, "ngrids must be in [1, %d]", GENO_BATCH_MAX);
@@ -1293,6 +1581,8 @@ int check_batch(int ngrids, const geno_grid* grids) {
     if (grids[i].ndim != 2) return fail(GENO_EINVAL, "batched grids must be 2-D (grid %d)", i);
     if (!same_method(grids[i].params, grids[0].params))
       return fail(GENO_EINVAL, "grid %d: method parameters differ from grid 0", i);
+    if (grids[i].params.gate_delta > 0.0)
+      return fail(GENO_EINVAL, "the learned gate is not available in batched steps");
   }
   return GENO_OK;
 }
@@ -1636,7 +1926,7 @@ const char* geno_kernel_name(int kind) {
   return (kind >= 0 && kind < GENO_NKERNELS) ? KNAMES[kind] : "";
 }
 
-const char* geno_last_error(void) { return g_err; }
+const char* geno_last_error(void) { return geno_err::g_err; }
 
 int geno_params_default(geno_params* p) {
   if (!p) return fail(GENO_EINVAL, "null params");
@@ -1728,6 +2018,8 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
   if (rc) return rc;
   if (!W || !dW || !ws) return fail(GENO_EINVAL, "null pointer");
   if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
+  rc = check_gate(g);
+  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   Cnt cnt{nullptr, 0};
   if (g_cnt.on) {
@@ -1897,6 +2189,127 @@ int geno_autotune_batched(int ngrids, const geno_grid* grids, void* const* W, vo
       }
     }
   *out = bslow;
+  return GENO_OK;
+}
+
+int geno_mlp_load(const float* params, void* stream) {
+  if (!params) return fail(GENO_EINVAL, "null params");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float> p(mlp::NPARAM);
+  HIP_TRY(hipMemcpyAsync(p.data(), params, sizeof(float) * mlp::NPARAM, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (float x : p)
+    if (!std::isfinite(x)) return fail(GENO_EINVAL, "non-finite network parameter");
+  // B fragments of both layers in lane order (see g_mlp_frag)
+  std::vector<unsigned short> frag(16 * 64 * 8, 0);
+  for (int layer = 0; layer < 2; ++layer)
+    for (int kb = 0; kb < 2; ++kb)
+      for (int nt = 0; nt < 4; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < 8; ++e) {
+            const int kk = kb * 32 + 8 * (lane / 16) + e, n = nt * 16 + lane % 16;
+            float w = 0.0f;
+            if (layer == 0 && kk < mlp::NIN) w = p[mlp::OW1 + n * mlp::NIN + kk];
+            if (layer == 1) w = p[mlp::OW2 + n * mlp::NH + kk];
+            frag[(((size_t)(layer * 8 + kb * 4 + nt) * 64) + lane) * 8 + e] = f2bf(w);
+          }
+  std::vector<float> vec(3 * mlp::NH + 1);
+  for (int q = 0; q < mlp::NH; ++q) {
+    vec[q] = p[mlp::OB1 + q];
+    vec[mlp::NH + q] = p[mlp::OB2 + q];
+    vec[2 * mlp::NH + q] = p[mlp::OW3 + q];
+  }
+  vec[3 * mlp::NH] = p[mlp::OB3];
+  HIP_TRY(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_mlp_frag), frag.data(),
+                                 sizeof(unsigned short) * frag.size(), 0, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_mlp_vec), vec.data(), sizeof(float) * vec.size(), 0,
+                                 hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64) g_mlp_loaded[dev] = true;
+  return GENO_OK;
+}
+
+int geno_mlp_infer(const float* X, int n, float* prob, void* stream) {
+  if (!X || !prob) return fail(GENO_EINVAL, "null pointer");
+  if (n < 0) return fail(GENO_EINVAL, "n must be >= 0");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64 || !g_mlp_loaded[dev]) return fail(GENO_EINVAL, "no network loaded");
+  if (n == 0) return GENO_OK;
+  const unsigned nb = (unsigned)(((size_t)n + 63) / 64);
+  HIP_TRY(launch(-1, k_mlp_infer, nb, (hipStream_t)stream, X, n, prob));
+  return GENO_OK;
+}
+
+int geno_gate_prob(const geno_grid* g, void* W, void* dW, int dir, float* prob, void* ws,
+                   void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (g->ndim != 2) return fail(GENO_EINVAL, "the gate is 2-D only");
+  if (!W || !dW || !prob || !ws) return fail(GENO_EINVAL, "null pointer");
+  if (dir != 0 && dir != 1) return fail(GENO_EINVAL, "bad direction %d", dir);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64 || !g_mlp_loaded[dev]) return fail(GENO_EINVAL, "no network loaded");
+  hipStream_t s = (hipStream_t)stream;
+  const Geo geo = geo_of(g);
+  const size_t nc = (size_t)g->nx * g->ny;
+  const Layout L = layout_of(g);
+  if (g->params.precision == GENO_MIXED) {
+    const Bufs<float> B = bufs_of<float>((char*)ws, L, 2);
+    rc = launch_init<float>(g, geo, g->params.gamma, (double*)W, (float*)dW, B, s);
+    if (rc) return rc;
+    if (dir == 0)
+      HIP_TRY(launch(-1, k_gate<0, float, 1>, gate_blocks(nc), s, geo, (const double*)W,
+                     (const float*)dW, 0.0f, (unsigned char*)nullptr, prob));
+    else
+      HIP_TRY(launch(-1, k_gate<1, float, 1>, gate_blocks(nc), s, geo, (const double*)W,
+                     (const float*)dW, 0.0f, (unsigned char*)nullptr, prob));
+  } else {
+    const Bufs<double> B = bufs_of<double>((char*)ws, L, 2);
+    rc = launch_init<double>(g, geo, g->params.gamma, (double*)W, (double*)dW, B, s);
+    if (rc) return rc;
+    if (dir == 0)
+      HIP_TRY(launch(-1, k_gate<0, double, 1>, gate_blocks(nc), s, geo, (const double*)W,
+                     (const double*)dW, 0.0f, (unsigned char*)nullptr, prob));
+    else
+      HIP_TRY(launch(-1, k_gate<1, double, 1>, gate_blocks(nc), s, geo, (const double*)W,
+                     (const double*)dW, 0.0f, (unsigned char*)nullptr, prob));
+  }
+  return GENO_OK;
+}
+
+int geno_harvest(const geno_grid* g, void* W, void* dW, int dir, float* X, float* y, void* ws,
+                 void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (g->ndim != 2) return fail(GENO_EINVAL, "harvest is 2-D only");
+  if (!W || !dW || !X || !ws) return fail(GENO_EINVAL, "null pointer");
+  if (dir != 0 && dir != 1) return fail(GENO_EINVAL, "bad direction %d", dir);
+  hipStream_t s = (hipStream_t)stream;
+  const Geo geo = geo_of(g);
+  const geno::KParams k = kparams(g);
+  const Layout L = layout_of(g);
+  const unsigned nb = nblocks((size_t)g->nx * g->ny);
+  if (g->params.precision == GENO_MIXED) {
+    const Bufs<float> B = bufs_of<float>((char*)ws, L, 2);
+    rc = launch_init<float>(g, geo, k.gamma, (double*)W, (float*)dW, B, s);
+    if (rc) return rc;
+    if (dir == 0)
+      HIP_TRY(launch(-1, k_harvest<0, float>, nb, s, geo, k, (const double*)W, (const float*)dW, X, y));
+    else
+      HIP_TRY(launch(-1, k_harvest<1, float>, nb, s, geo, k, (const double*)W, (const float*)dW, X, y));
+  } else {
+    const Bufs<double> B = bufs_of<double>((char*)ws, L, 2);
+    rc = launch_init<double>(g, geo, k.gamma, (double*)W, (double*)dW, B, s);
+    if (rc) return rc;
+    if (dir == 0)
+      HIP_TRY(launch(-1, k_harvest<0, double>, nb, s, geo, k, (const double*)W, (const double*)dW, X, y));
+    else
+      HIP_TRY(launch(-1, k_harvest<1, double>, nb, s, geo, k, (const double*)W, (const double*)dW, X, y));
+  }
   return GENO_OK;
 }
 

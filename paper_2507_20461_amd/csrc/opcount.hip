@@ -66,6 +66,8 @@ geno::KParams params(int ndim, double gamma) {
   k.cfl = 0.5;
   k.dt_fixed = 0.0;
   k.eps_ulps = 0.0;
+  k.gate_thr = 1.0;
+  k.gate = 0;
   return k;
 }
 

@@ -28,7 +28,7 @@ class geno_params(ctypes.Structure):
                 ("C", ctypes.c_double), ("eps", ctypes.c_double), ("r", ctypes.c_double),
                 ("rL", ctypes.c_double), ("d", ctypes.c_double * 3), ("tau_c1", ctypes.c_double),
                 ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4),
-                ("dt_fixed", ctypes.c_double), ("eps_ulps", ctypes.c_double)]
+                ("dt_fixed", ctypes.c_double), ("eps_ulps", ctypes.c_double), ("gate_delta", ctypes.c_double)]
 
 
 class geno_grid(ctypes.Structure):
@@ -56,9 +56,12 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_state_elems", "gks_workspace_bytes", "geno_reconstruct", "gks_flux", "gks_step",
            "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
            "geno_kernel_name", "geno_tuning_default", "gks_batched_workspace_bytes", "gks_step_batched",
-           "geno_autotune_batched")
-KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d")
-WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard")
+           "geno_autotune_batched", "geno_harvest", "geno_mlp_train_workspace_bytes", "geno_mlp_grad",
+           "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob")
+KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d",
+           "gate")
+WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard", "gated")
+MLP_NIN, MLP_NPARAM = 40, 6849
 
 _lib = None
 
@@ -106,6 +109,19 @@ def lib():
         L.geno_autotune_batched.argtypes = [i, ctypes.POINTER(geno_grid), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                             vp, i, ctypes.POINTER(geno_tuning), vp]
         for name in ("geno_tuning_default", "gks_step_batched", "geno_autotune_batched"):
+            getattr(L, name).restype = i
+        L.geno_harvest.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, vp, vp, vp]
+        L.geno_mlp_train_workspace_bytes.argtypes = [i]
+        L.geno_mlp_train_workspace_bytes.restype = ctypes.c_size_t
+        L.geno_mlp_grad.argtypes = [vp, vp, vp, i, vp, vp, vp, vp]
+        L.geno_mlp_adam.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, vp]
+        L.geno_mlp_forward.argtypes = [vp, vp, i, vp, vp]
+        L.geno_mlp_load.argtypes = [vp, vp]
+        L.geno_mlp_infer.argtypes = [vp, i, vp, vp]
+        L.geno_gate_prob.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, vp, vp]
+        for name in ("geno_harvest", "geno_mlp_grad", "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load",
+                     "geno_mlp_infer", "geno_gate_prob"):
             getattr(L, name).restype = i
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
                      "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
@@ -353,4 +369,73 @@ class Batch:
         _check(lib().geno_autotune_batched(self.n, self.garr, pw, pd, _ptr(ws), int(trial_steps),
                                            ctypes.byref(t), ctypes.c_void_p(stream.cuda_stream)))
         return t
+
+
+# ------------------------------------------------------------------ learned gate
+def harvest(grid, W, dW, ws, direction, with_target=True, stream=None):
+    """(X[ncell, 40], y[ncell] or None) float32 device tensors for one direction."""
+    _check_state(grid, W, dW, ws)
+    nc = grid.nx * grid.ny
+    X = torch.empty((nc, MLP_NIN), dtype=torch.float32, device=W.device)
+    y = torch.empty(nc, dtype=torch.float32, device=W.device) if with_target else None
+    _check(lib().geno_harvest(ctypes.byref(grid.g), _ptr(W), _ptr(dW), int(direction), _ptr(X), _ptr(y),
+                              _ptr(ws), _stream(stream)))
+    return X, y
+
+
+def _need_mlp(params):
+    _need(params, torch.float32, MLP_NPARAM, "params")
+
+
+def mlp_train_workspace(n, device="cuda"):
+    return torch.empty(lib().geno_mlp_train_workspace_bytes(int(n)), dtype=torch.uint8, device=device)
+
+
+def mlp_grad(params, X, y, grad, loss, ws, stream=None):
+    _need_mlp(params)
+    n = X.shape[0]
+    _need(X, torch.float32, n * MLP_NIN, "X")
+    _need(y, torch.float32, n, "y")
+    _need(grad, torch.float32, MLP_NPARAM, "grad")
+    _need(loss, torch.float32, 1, "loss", optional=True)
+    _need(ws, torch.uint8, lib().geno_mlp_train_workspace_bytes(int(n)), "ws")
+    _check(lib().geno_mlp_grad(_ptr(params), _ptr(X), _ptr(y), int(n), _ptr(grad), _ptr(loss), _ptr(ws),
+                               _stream(stream)))
+
+
+def mlp_adam(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for name, x in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _need(x, torch.float32, MLP_NPARAM, name)
+    _check(lib().geno_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr), float(beta1),
+                               float(beta2), float(eps), _stream(stream)))
+
+
+def mlp_forward(params, X, stream=None):
+    _need_mlp(params)
+    n = X.shape[0]
+    _need(X, torch.float32, n * MLP_NIN, "X")
+    p = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().geno_mlp_forward(_ptr(params), _ptr(X), int(n), _ptr(p), _stream(stream)))
+    return p
+
+
+def mlp_load(params, stream=None):
+    _need_mlp(params)
+    _check(lib().geno_mlp_load(_ptr(params), _stream(stream)))
+
+
+def mlp_infer(X, stream=None):
+    n = X.shape[0]
+    _need(X, torch.float32, n * MLP_NIN, "X")
+    p = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().geno_mlp_infer(_ptr(X), int(n), _ptr(p), _stream(stream)))
+    return p
+
+
+def gate_prob(grid, W, dW, ws, direction, stream=None):
+    _check_state(grid, W, dW, ws)
+    p = torch.empty(grid.nx * grid.ny, dtype=torch.float32, device=W.device)
+    _check(lib().geno_gate_prob(ctypes.byref(grid.g), _ptr(W), _ptr(dW), int(direction), _ptr(p), _ptr(ws),
+                                _stream(stream)))
+    return p
 

@@ -1,0 +1,214 @@
+"""The learned gate's kernels against the CPU float64 oracle (oracle/mlp.py):
+harvest inputs and targets, the float32 training kernels (forward, gradient,
+Adam), the bfloat16 matrix-core inference, the gate inside gks_step, and what
+a trained network gains over plain GENO.
+
+Tolerances: the training kernels compute in float32 (unit roundoff 6e-8) with
+float64 reductions over the samples: forward probabilities within 2e-6,
+gradients within 1e-5 of the largest gradient, an Adam step within 1e-6.
+Inference uses bfloat16 inputs, weights and first-layer activations with
+float32 accumulation: against the oracle evaluated on the same bfloat16
+values it agrees within 2e-3 (float32 accumulation, and first-layer
+activations that round to a neighbouring bfloat16 value near ties).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp as M
+from paper_2507_20461_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_20461_amd import geno_gks
+    geno_gks.lib()
+    return geno_gks
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _net(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    p = M.init(seed)
+    p[M.NHID * M.NIN:M.NHID * M.NIN + M.NHID] = scale * rng.standard_normal(M.NHID)   # b1
+    return p
+
+
+def _bf16(a):
+    """Round float64 values to bfloat16 (nearest even) and back."""
+    a32 = np.asarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _oracle_bf16_forward(p, X):
+    W1, b1, W2, b2, w3, b3 = M.unpack(p)
+    h1 = _bf16(M.gelu(_bf16(X) @ _bf16(W1).T + b1))
+    h2 = M.gelu(h1 @ _bf16(W2).T + b2)
+    return M.sigmoid(h2 @ w3 + b3)
+
+
+def test_forward_gradient_and_adam_match_oracle(G):
+    rng = np.random.default_rng(0)
+    p = _net(1)
+    n = 777
+    X = rng.standard_normal((n, 40))
+    X[:, ::3] *= 5.0
+    y = rng.uniform(0, 1, n)
+    y[::4] = 1.0
+    pd = torch.tensor(p, dtype=torch.float32, device="cuda")
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    yd = torch.tensor(y, dtype=torch.float32, device="cuda")
+    p32, X32, y32 = (t.cpu().numpy().astype(np.float64) for t in (pd, Xd, yd))
+    prob = G.mlp_forward(pd, Xd).cpu().numpy()
+    zo, _ = M.forward(p32, X32)
+    e = np.abs(prob - M.sigmoid(zo)).max()
+    _say("forward max |dp| %.2e" % e)
+    assert e < 2e-6
+    grad = torch.empty_like(pd)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    G.mlp_grad(pd, Xd, yd, grad, loss, G.mlp_train_workspace(n))
+    go = M.grad(p32, X32, y32)
+    eg = np.abs(grad.cpu().numpy() - go).max() / np.abs(go).max()
+    el = abs(float(loss.item()) - M.loss(p32, X32, y32))
+    _say("gradient rel %.2e loss %.2e" % (eg, el))
+    assert eg < 1e-5 and el < 2e-6
+    # deterministic: a second evaluation is bitwise equal
+    grad2 = torch.empty_like(pd)
+    G.mlp_grad(pd, Xd, yd, grad2, None, G.mlp_train_workspace(n))
+    assert torch.equal(grad, grad2)
+    m = torch.tensor(rng.standard_normal(M.NPARAM) * 1e-3, dtype=torch.float32, device="cuda")
+    v = torch.tensor(rng.uniform(0, 1e-5, M.NPARAM), dtype=torch.float32, device="cuda")
+    mo, vo = m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+    g32 = grad.cpu().numpy().astype(np.float64)
+    po, _, _ = M.adam(p32, g32, mo, vo, 3, 1e-3)
+    G.mlp_adam(pd, grad, m, v, 3, 1e-3)
+    ea = np.abs(pd.cpu().numpy() - po).max()
+    _say("adam %.2e" % ea)
+    assert ea < 1e-6
+
+
+def test_bf16_inference_matches_oracle(G):
+    rng = np.random.default_rng(2)
+    p = _net(3)
+    n = 1000 + 13
+    X = rng.uniform(-1, 1, (n, 40))
+    X[:, 5::10] *= 8.0
+    G.mlp_load(torch.tensor(p, dtype=torch.float32, device="cuda"))
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    prob = G.mlp_infer(Xd).cpu().numpy()
+    ref = _oracle_bf16_forward(p, Xd.cpu().numpy().astype(np.float64))
+    full = M.sigmoid(M.forward(p, Xd.cpu().numpy().astype(np.float64))[0])
+    e, ef = np.abs(prob - ref).max(), np.abs(prob - full).max()
+    _say("bf16 inference vs oracle on bf16 values %.2e, vs float64 network %.2e" % (e, ef))
+    assert e < 2e-3
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_harvest_matches_oracle(G, oracle, direction):
+    nx, ny = 40, 36
+    W, dW, _ = inputs.quadrants_2d(nx, ny, 5)
+    Ws, dWs = inputs.random_smooth_2d(nx, ny, 6)
+    W = W + 0.05 * (Ws - Ws.mean(axis=(1, 2), keepdims=True))
+    dW = dW + 0.05 * dWs
+    grid = G.Grid(2, nx, ny, bc=1)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    X, y = G.harvest(grid, Wd, dWd, grid.workspace(), direction)
+    _, chi = oracle.normal_faces(oracle.params(ndim=2, bc=1), W, dW, direction)
+    h = grid.dx if direction == 0 else grid.dy
+    Xo, yo = M.harvest(W, dW, direction, 1, h, chi)
+    ex = np.abs(X.cpu().numpy() - Xo).max() / max(1.0, np.abs(Xo).max())
+    ey = np.abs(y.cpu().numpy() - yo).max()
+    _say("harvest dir %d: X %.2e y %.2e, chi<0.999 share %.3f" % (direction, ex, ey, (yo < 0.999).mean()))
+    assert ex < 1e-6 and ey < 1e-6
+
+
+def test_gate_features_equal_harvest_inputs(G):
+    # the gate builds its inputs inside the kernel; on the harvested inputs the
+    # same network gives the same probabilities bit for bit
+    nx, ny = 48, 40
+    W, dW, _ = inputs.vortex_2d(nx, ny, 2, centre=(0.3, 0.35), radius=0.15)
+    grid = G.Grid(2, nx, ny, bc=1)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    G.mlp_load(torch.tensor(_net(7), dtype=torch.float32, device="cuda"))
+    for d in (0, 1):
+        X, _ = G.harvest(grid, Wd, dWd, ws, d, with_target=False)
+        assert torch.equal(G.gate_prob(grid, Wd, dWd, ws, d), G.mlp_infer(X))
+
+
+def _step(G, grid, W, dW, n):
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    G.count_enable(True)
+    st = G.gks_step(grid, Wd, dWd, grid.workspace(), n, stats=True)
+    G.count_enable(False)
+    wk = G.work_read()
+    assert st.nonfinite == 0
+    return grid.interior(Wd), wk
+
+
+def test_gate_never_on_is_plain_geno(G):
+    # a network that predicts 0 everywhere leaves gks_step bitwise unchanged
+    nx, ny = 40, 36
+    W, dW, _ = inputs.quadrants_2d(nx, ny, 1)
+    p = np.zeros(M.NPARAM)
+    p[-1] = -50.0
+    G.mlp_load(torch.tensor(p, dtype=torch.float32, device="cuda"))
+    plain, _ = _step(G, G.Grid(2, nx, ny, bc=1), W, dW, 3)
+    gated, wk = _step(G, G.Grid(2, nx, ny, bc=1, gate_delta=0.01), W, dW, 3)
+    assert np.array_equal(plain, gated)
+    assert wk["normal_x"]["gated"] == 0 and wk["normal_y"]["gated"] == 0
+
+
+def test_gate_always_on_skips_every_indicator(G):
+    nx, ny = 40, 36
+    W, dW, _ = inputs.quadrants_2d(nx, ny, 1)
+    p = np.zeros(M.NPARAM)
+    p[-1] = 50.0
+    G.mlp_load(torch.tensor(p, dtype=torch.float32, device="cuda"))
+    _, wk = _step(G, G.Grid(2, nx, ny, bc=1, gate_delta=0.01), W, dW, 2)
+    # every face-side owned by an interior cell: x: ny rows x 2 nx sides, y:
+    # nx columns x 2 ny sides, four variables, two stages, two steps
+    assert wk["normal_x"]["gated"] == 2 * 2 * 4 * 2 * nx * ny
+    assert wk["normal_y"]["gated"] == 2 * 2 * 4 * 2 * nx * ny
+
+
+def test_trained_gate_gains(G):
+    # harvest, train and choose delta with the library's kernels on a small
+    # set; the trained gate must skip most indicator work on a fresh state
+    # while its misgates stay rare and the solution close to plain GENO's
+    from paper_2507_20461_amd import learned
+    X, y = learned.harvest_dataset(n2d=128, seeds=(0, 1), steps=40, every=8)
+    Xs, ys = learned.stratify(X, y)
+    _say("harvest %d stencils, stratified %d, rough share %.3f" % (X.shape[0], Xs.shape[0],
+                                                                 float((ys < 0.999).float().mean())))
+    p, hist = learned.train(Xs, ys, epochs=4, batch=2048, lr=3e-3, log=_say)
+    assert hist[-1] < hist[0]
+    G.mlp_load(p)
+    Xh, yh = learned.harvest_dataset(n2d=128, seeds=(9,), steps=40, every=8)
+    prob = G.mlp_infer(Xh)
+    delta, info = learned.choose_delta(prob, yh)
+    _say("held-out:", info)
+    assert delta > 0 and info["gated"] > 0.5
+    n = 256
+    W, dW, _ = inputs.quadrants_2d(n, n, 11)
+    plain, wp = _step(G, G.Grid(2, n, n, bc=1), W, dW, 10)
+    gated, wg = _step(G, G.Grid(2, n, n, bc=1, gate_delta=delta), W, dW, 10)
+    sides = 2 * 2 * 4 * 2 * n * n * 10
+    share = (wg["normal_x"]["gated"] + wg["normal_y"]["gated"]) / sides
+    l1 = np.abs(gated - plain).mean(axis=(1, 2)) / np.abs(plain).mean(axis=(1, 2))
+    _say("gated share of face-sides %.3f, low-order plain %d gated %d, relative L1 change %s" % (
+        share, wp["normal_x"]["low"] + wp["normal_y"]["low"], wg["normal_x"]["low"] + wg["normal_y"]["low"], l1))
+    assert share > 0.5 and l1.max() < 1e-3
