@@ -41,16 +41,23 @@ struct KParams {
 // smoothness indicator alpha = 2 alpha^H/(alpha^H + alpha^L) with
 // alpha^{H,L} = 1 + (IS^tau/(IS^{H,L} + eps))^2 (Eq. (5), r = 2). alpha is
 // evaluated over the common denominator (IS^H+eps)^2 (IS^L+eps)^2 so that a
-// single division remains. tanh(x) rounds to 1 for x > 19.8 (its distance to
-// 1 is below 1e-17), so the call is skipped there.
+// single division remains. tanh(x) rounds to 1 in float64 for x > 19.1, so
+// once C alpha > 19.8 chi is tanh(C)^-1 exactly; that test is made on the
+// numerator and denominator of alpha, without the division (near the
+// threshold both ways give tanh(x) = 1).
 template <typename D>
 GENO_HD D path_chi(D IStau, D ISH, D ISL, D eps, const KParams& k) {
   const D a = ISH + eps, b = ISL + eps, t2 = IStau * IStau;
   const D a2 = a * a, b2 = b * b;
   const D num = (a2 + t2) * b2;
-  const D alpha = 2.0 * num / (num + (b2 + t2) * a2);
-  const D x = k.C * alpha;
-  const D th = (x > 19.8) ? D(1.0) : tanh(x);
+  const D den = num + (b2 + t2) * a2;
+  D th;
+  if (D(2.0 * k.C) * num > D(19.8) * den) {
+    th = D(1.0);
+  } else {
+    const D alpha = 2.0 * num / den;
+    th = tanh(k.C * alpha);
+  }
   return (k.tanhC == 1.0) ? th : th / k.tanhC;
 }
 
@@ -224,8 +231,9 @@ GENO_HD bool admissible(const R* W, double gamma) {
   if (!(W[0] > R(0.0))) return false;
   R ke = W[1] * W[1];
   if constexpr (NV == 4) ke = ke + W[2] * W[2];
-  const R p = R(gamma - 1.0) * (W[NV - 1] - R(0.5) * ke / W[0]);
-  return p > R(0.0);
+  // p = (gamma - 1)(rhoE - |m|^2 / (2 rho)) > 0  <=>  rho rhoE - |m|^2 / 2 > 0 (rho > 0)
+  (void)gamma;
+  return W[0] * W[NV - 1] - R(0.5) * ke > R(0.0);
 }
 
 }  // namespace geno

@@ -215,16 +215,26 @@ __device__ __forceinline__ void scatter_ghosts(const Geo& g, double* __restrict_
   }
 }
 
+// a x + b y with both products rounded before the sum (no fused multiply-add),
+// so swapping the pairs (x and y directions of a transposed grid) gives the
+// same bits
+__device__ __forceinline__ double dot2(double a, double x, double b, double y) {
+#pragma clang fp contract(off)
+  return a * x + b * y;
+}
+
 // CFL bound of one cell: min(dx/(|U|+c), dy/(|V|+c)).
 template <int NDIM>
 __device__ __forceinline__ double cell_tmin(const Geo& g, const double* w, double gamma) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
-  const double rho = w[0], U = w[1] / rho;
-  const double V = NV == 4 ? w[2] / rho : 0.0;
-  const double p = (gamma - 1.0) * (w[NV - 1] - 0.5 * rho * (U * U + V * V));
-  const double c = sqrt(gamma * p / rho);
-  double t = g.dx / (fabs(U) + c);
-  if constexpr (NDIM == 2) t = fmin(t, g.dy / (fabs(V) + c));
+  const double rho = w[0], ir = 1.0 / rho, U = w[1] * ir;
+  const double V = NV == 4 ? w[2] * ir : 0.0;
+  const double p = (gamma - 1.0) * (w[NV - 1] - 0.5 * rho * dot2(U, U, V, V));
+  const double c = sqrt(gamma * p * ir);
+  // min(dx / (|U| + c), dy / (|V| + c)) over the common numerator dx dy
+  double t;
+  if constexpr (NDIM == 2) t = (g.dx * g.dy) / fmax((fabs(U) + c) * g.dy, (fabs(V) + c) * g.dx);
+  else t = g.dx / (fabs(U) + c);
   return (t > 0.0) ? t : 0.0;   // a NaN state gives a zero step (flagged by the caller)
 }
 
@@ -786,17 +796,22 @@ __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k
     // flux differences and gradients in float64 whatever the storage type
     const auto X = [&](int plane, size_t o) { return (double)fx[plane * px + o]; };
     const auto Y = [&](int plane, size_t o) { return (double)fy[plane * py + o]; };
+    const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
     double w[NV];
     T dw[NV * NDIM];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double l = -(X(0 * NV + v, ox + 1) - X(0 * NV + v, ox)) / g.dx;
-      double lt = -(X(1 * NV + v, ox + 1) - X(1 * NV + v, ox)) / g.dx;
-      dw[v] = T((X(2 * NV + v, ox + 1) - X(2 * NV + v, ox)) / g.dx);
+      double l, lt;
+      dw[v] = T((X(2 * NV + v, ox + 1) - X(2 * NV + v, ox)) * idx);
       if constexpr (NDIM == 2) {
-        l += -(Y(0 * NV + v, oy + g.nx) - Y(0 * NV + v, oy)) / g.dy;
-        lt += -(Y(1 * NV + v, oy + g.nx) - Y(1 * NV + v, oy)) / g.dy;
-        dw[NV + v] = T((Y(2 * NV + v, oy + g.nx) - Y(2 * NV + v, oy)) / g.dy);
+        l = -dot2(X(0 * NV + v, ox + 1) - X(0 * NV + v, ox), idx,
+                  Y(0 * NV + v, oy + g.nx) - Y(0 * NV + v, oy), idy);
+        lt = -dot2(X(1 * NV + v, ox + 1) - X(1 * NV + v, ox), idx,
+                   Y(1 * NV + v, oy + g.nx) - Y(1 * NV + v, oy), idy);
+        dw[NV + v] = T((Y(2 * NV + v, oy + g.nx) - Y(2 * NV + v, oy)) * idy);
+      } else {
+        l = -(X(0 * NV + v, ox + 1) - X(0 * NV + v, ox)) * idx;
+        lt = -(X(1 * NV + v, ox + 1) - X(1 * NV + v, ox)) * idx;
       }
       const size_t c = at(g, v, j, i);
       if constexpr (STAGE == 1) {
@@ -817,9 +832,9 @@ __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k
       bool bad = false;
 #pragma unroll
       for (int v = 0; v < NV; ++v) bad |= !isfinite(w[v]);
-      double ke = w[1] * w[1];
-      if constexpr (NV == 4) ke += w[2] * w[2];
-      bad |= !(w[0] > 0.0) || !((k.gamma - 1.0) * (w[NV - 1] - 0.5 * ke / w[0]) > 0.0);
+      const double ke = NV == 4 ? dot2(w[1], w[1], w[2], w[2]) : w[1] * w[1];
+      // p > 0 <=> rho rhoE - |m|^2 / 2 > 0 once rho > 0
+      bad |= !(w[0] > 0.0) || !(w[0] * w[NV - 1] - 0.5 * ke > 0.0);
       if (bad) atomicAdd(&ctrl->nonfinite, 1ull);
       tloc = cell_tmin<NDIM>(g, w, k.gamma);
     }

@@ -44,24 +44,30 @@ struct Wide<float> {
   using type = double;
 };
 
+// primitive variables; ir = 1/rho; lam = rho/(2p) only after with_lam()
 template <typename R>
 struct Prim {
-  R rho, U, V, p, lam;
+  R rho, ir, U, V, p, lam;
 };
 
 template <int NV, typename R>
 GENO_HD Prim<R> prim(const R* W, double gamma) {
   Prim<R> q;
   q.rho = W[0];
-  const R ir = R(1.0) / W[0];
-  q.U = W[1] * ir;
-  if constexpr (NV == 4) q.V = W[2] * ir;
+  q.ir = R(1.0) / W[0];
+  q.U = W[1] * q.ir;
+  if constexpr (NV == 4) q.V = W[2] * q.ir;
   else q.V = R(0.0);
   R ke = q.U * q.U;
   if constexpr (NV == 4) ke = ke + q.V * q.V;
   q.p = R(gamma - 1.0) * (W[NV - 1] - R(0.5) * q.rho * ke);
-  q.lam = q.rho / (R(2.0) * q.p);
+  q.lam = R(0.0);
   return q;
+}
+
+template <typename R>
+GENO_HD void with_lam(Prim<R>& q) {
+  q.lam = q.rho / (R(2.0) * q.p);
 }
 
 // Euler flux along the first velocity component (face frame).
@@ -76,7 +82,7 @@ GENO_HD void euler_flux(const R* W, const Prim<R>& q, R* F) {
 // J_x(W) dW and J_y(W) dW of the Euler fluxes (face frame: x normal).
 template <int NV, typename R>
 GENO_HD void jac_x(const R* W, const Prim<R>& q, const R* d, double gamma, R* out) {
-  const R ir = R(1.0) / q.rho;
+  const R ir = q.ir;
   const R dU = (d[1] - q.U * d[0]) * ir;
   R dp;
   if constexpr (NV == 4) {
@@ -93,7 +99,7 @@ GENO_HD void jac_x(const R* W, const Prim<R>& q, const R* d, double gamma, R* ou
 
 template <typename R>
 GENO_HD void jac_y(const R* W, const Prim<R>& q, const R* d, double gamma, R* out) {
-  const R ir = R(1.0) / q.rho;
+  const R ir = q.ir;
   const R dV = (d[2] - q.V * d[0]) * ir;
   const R dp = R(gamma - 1.0) *
                (d[3] - q.U * d[1] - q.V * d[2] + R(0.5) * (q.U * q.U + q.V * q.V) * d[0]);
@@ -211,7 +217,7 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
                         bool want_F, R* F, R* Ft, R* Wi) {
   using D = typename Wide<R>::type;
   const double g = k.gamma, K = k.K;
-  const Prim<R> pl = prim<NV, R>(Wl, g), pr = prim<NV, R>(Wr, g);
+  Prim<R> pl = prim<NV, R>(Wl, g), pr = prim<NV, R>(Wr, g);
   const R dt = R(dt_w);
   const R tau = R(k.tc1) * dt + R(k.tc2) * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
   const bool slow = tau > R(0.0);
@@ -229,6 +235,8 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
 #pragma unroll
     for (int v = 0; v < NV; ++v) Wc[v] = Wl[v];
   } else {
+    with_lam(pl);
+    with_lam(pr);
     const R sl = sqrt(pl.lam), sr = sqrt(pr.lam);
     const R tl0 = R(0.5) * erfc(-sl * pl.U), tr0 = R(0.5) * erfc(sr * pr.U);
     const R isp = R(0.28209479177387814347);  // 1 / (2 sqrt(pi))
@@ -250,7 +258,11 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
       Wc[2] = R(0.5) * (pl.rho * (lu2 + R(K) * hl * lu0) + pr.rho * (ru2 + R(K) * hr * ru0));
     }
   }
-  const Prim<R> pc = (same && !slow) ? pl : prim<NV, R>(Wc, g);
+  Prim<R> pc = pl;
+  if (!(same && !slow)) {
+    pc = prim<NV, R>(Wc, g);
+    with_lam(pc);
+  }
   // averaged derivatives and the equilibrium time derivative
   R dn[NV], dtn[NV], Wt[NV], tmp[NV];
 #pragma unroll
@@ -317,7 +329,7 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
       mc.u[1] = pc.U;
       fill_moments<NV, R>(mc, pc, K);
       R wv[NV], ab[NV], X2[NV];
-      const R irc = R(1.0) / pc.rho;
+      const R irc = pc.ir;
 #pragma unroll
       for (int v = 0; v < NV; ++v) wv[v] = dn[v] * irc;
       micro_slope<NV, R>(pc, K, wv, ab);
@@ -350,7 +362,7 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
       ms.u[0] = side ? ru0 : lu0;
       ms.u[1] = side ? ru1 : lu1;
       fill_moments<NV, R>(ms, ps, K);
-      const R irs = R(1.0) / ps.rho;
+      const R irs = ps.ir;
       R wv[NV], as[NV], bs[NV], As[NV], Ws_t[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) wv[v] = ns[v] * irs;

@@ -154,6 +154,8 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     for (int kind : {GENO_K_NORMAL_X, GENO_K_NORMAL_Y}) {
       set(kind, GENO_W_UNITS, row);
       set(kind, GENO_W_LOW, (double)(side_lo - side_hi));
+      // a gated side skips its indicators (work counted with the unit)
+      set(kind, GENO_W_GATED, -(double)side_hi);
     }
     // face: 8 tangential steps, 4 guard checks, derivative scaling (2 points x
     // 3 arrays x 2 sides x 4 variables, of which the two h*d/dn arrays per

@@ -41,6 +41,9 @@ PASSES = {
     "fetch": (["--pmc", "FETCH_SIZE"], BENCH_SHORT),
     "write": (["--pmc", "WRITE_SIZE"], BENCH_SHORT),
     "valu": (["--pmc", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE"], BENCH_SHORT),
+    "stall": (["--pmc", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY",
+               "SQ_ACTIVE_INST_VMEM", "SQ_LEVEL_WAVES", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VMEM_RD"],
+              BENCH_SHORT),
 }
 XCDS = 8          # GRBM_GUI_ACTIVE is summed over the XCDs of the device
 SIMDS = 256 * 4   # 256 CUs x 4 SIMDs
@@ -178,6 +181,25 @@ def summarize(tag="faces_fp64_512"):
             "%.2f" % (r["fetch_bytes_cal"] / 1e6) if r["fetch_bytes_cal"] else "n/a",
             "%.2f" % (r["write_bytes_cal"] / 1e6) if r["write_bytes_cal"] else "n/a",
             r["valu_insts_per_wave"] or 0, r["valu_busy"] or 0))
+    spath = os.path.join(OUT, "prof_stall", "run_counter_collection.csv")
+    if os.path.exists(spath):
+        S = {c: _counters(spath, c) for c in ("SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                                               "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VMEM", "SQ_LEVEL_WAVES",
+                                               "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VMEM_RD")}
+        lines.append("")
+        lines.append("# per-wave shares of wave-cycles (one more --pmc pass):")
+        lines.append("#   " + " ".join(command("stall")).replace(ROOT + "/", ""))
+        lines.append("%-22s %9s %9s %9s %9s %11s %9s" % ("kernel", "wait_any", "wait_inst", "active", "vmem_act",
+                                                       "trans64/wv", "vmemrd/wv"))
+        for k in sorted(S["SQ_WAVE_CYCLES"]):
+            if not k.startswith("k_"):
+                continue
+            wc = avg(S["SQ_WAVE_CYCLES"][k]) or 1.0
+            nw = avg(V["SQ_WAVES"].get(k, [1.0])) or 1.0
+            lines.append("%-22s %9.3f %9.3f %9.3f %9.3f %11.1f %9.1f" % (
+                k[:22], avg(S["SQ_WAIT_ANY"][k]) / wc, avg(S["SQ_WAIT_INST_ANY"][k]) / wc,
+                avg(S["SQ_ACTIVE_INST_ANY"][k]) / wc, avg(S["SQ_ACTIVE_INST_VMEM"][k]) / wc,
+                avg(S["SQ_INSTS_VALU_TRANS_F64"][k]) / nw, avg(S["SQ_INSTS_VMEM_RD"][k]) / nw))
     open(os.path.join(PROFILES, "%s_counters.txt" % tag), "w").write("\n".join(lines) + "\n")
     meta = {"source_hash": sh, "calibration": {"fetch": fcal, "write": wcal}, "kernels": rows,
             "ktrace_avg_us": ktrace}
