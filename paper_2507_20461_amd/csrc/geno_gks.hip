@@ -405,6 +405,22 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
 // MODE 1: flux for tau = 0; faces with tau > 0 at either point are queued.
 // MODE 2: flux of the queued faces with the full solution (grid-stride).
 // ---------------------------------------------------------------------------
+// Value of the partner lane (lane ^ 1) by a DPP quad permutation [1, 0, 3, 2]
+// (a VALU move, no trip through LDS). Both lanes of a pair are always active
+// together.
+__device__ __forceinline__ int pair_swap(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(pair_swap(__float_as_int(x)));
+}
+__device__ __forceinline__ double pair_swap(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned int lo = (unsigned int)pair_swap((int)(unsigned int)(u & 0xffffffffull));
+  const unsigned int hi = (unsigned int)pair_swap((int)(unsigned int)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <int DIR>
 struct FaceGeo {
   int n0, n1, r0, r1;
@@ -449,9 +465,9 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   T S[2][4], Dn[2][4], Dt[2][4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const T rv = __shfl_xor(snd_v[v], 1, 64);
-    const T rt = __shfl_xor(snd_t[v], 1, 64);
-    const T rd = __shfl_xor(dn[v], 1, 64);
+    const T rv = pair_swap(snd_v[v]);
+    const T rt = pair_swap(snd_t[v]);
+    const T rd = pair_swap(dn[v]);
     S[0][v] = q ? rv : own_v[v];
     S[1][v] = q ? own_v[v] : rv;
     Dt[0][v] = q ? rt : own_t[v];
@@ -520,7 +536,7 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       // every lane takes part in the exchange (no short-circuit around it:
       // a lane that skips a cross-lane read leaves its partner reading an
       // inactive lane)
-      const int partner_slow = __shfl_xor(slow ? 1 : 0, 1, 64);
+      const int partner_slow = pair_swap(slow ? 1 : 0);
       pair_slow = slow || partner_slow != 0;
       // queue the faces that need the full solution (one atomic per wave)
       const bool enq = valid && q == 0 && pair_slow;
@@ -539,9 +555,9 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
     T So[12];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      So[v] = F[v] + __shfl_xor(F[v], 1, 64);
-      So[4 + v] = Ft[v] + __shfl_xor(Ft[v], 1, 64);
-      So[8 + v] = Wi[v] + __shfl_xor(Wi[v], 1, 64);
+      So[v] = F[v] + pair_swap(F[v]);
+      So[4 + v] = Ft[v] + pair_swap(Ft[v]);
+      So[8 + v] = Wi[v] + pair_swap(Wi[v]);
     }
     if (valid && !pair_slow) {
       // back to the (x, y) frame; lane 0 writes F and Ft, lane 1 writes W_int

@@ -173,11 +173,11 @@ def summarize(tag="faces_fp64_512"):
     lines.append("# calibration: device copy of 256 MiB: FETCH scale %s, WRITE scale %s"
                  % ("%.4f" % fcal if fcal else "n/a", "%.4f" % wcal if wcal else "n/a"))
     lines.append("# valu_busy = 4 * SQ_ACTIVE_INST_VALU / (1024 SIMDs * GRBM_GUI_ACTIVE / 8 XCDs)")
-    lines.append("%-22s %12s %12s %12s %12s %10s %9s" % ("kernel", "FETCH_MB", "WRITE_MB", "FETCH_cal", "WRITE_cal",
+    lines.append("%-28s %12s %12s %12s %12s %10s %9s" % ("kernel", "FETCH_MB", "WRITE_MB", "FETCH_cal", "WRITE_cal",
                                                         "valu/wave", "valu_busy"))
     for k, r in rows.items():
-        lines.append("%-22s %12.2f %12.2f %12s %12s %10.0f %9.3f" % (
-            k[:22], r["fetch_bytes"] / 1e6, r["write_bytes"] / 1e6,
+        lines.append("%-28s %12.2f %12.2f %12s %12s %10.0f %9.3f" % (
+            k[:28], r["fetch_bytes"] / 1e6, r["write_bytes"] / 1e6,
             "%.2f" % (r["fetch_bytes_cal"] / 1e6) if r["fetch_bytes_cal"] else "n/a",
             "%.2f" % (r["write_bytes_cal"] / 1e6) if r["write_bytes_cal"] else "n/a",
             r["valu_insts_per_wave"] or 0, r["valu_busy"] or 0))
@@ -189,15 +189,15 @@ def summarize(tag="faces_fp64_512"):
         lines.append("")
         lines.append("# per-wave shares of wave-cycles (one more --pmc pass):")
         lines.append("#   " + " ".join(command("stall")).replace(ROOT + "/", ""))
-        lines.append("%-22s %9s %9s %9s %9s %11s %9s" % ("kernel", "wait_any", "wait_inst", "active", "vmem_act",
+        lines.append("%-28s %9s %9s %9s %9s %11s %9s" % ("kernel", "wait_any", "wait_inst", "active", "vmem_act",
                                                        "trans64/wv", "vmemrd/wv"))
         for k in sorted(S["SQ_WAVE_CYCLES"]):
             if not k.startswith("k_"):
                 continue
             wc = avg(S["SQ_WAVE_CYCLES"][k]) or 1.0
             nw = avg(V["SQ_WAVES"].get(k, [1.0])) or 1.0
-            lines.append("%-22s %9.3f %9.3f %9.3f %9.3f %11.1f %9.1f" % (
-                k[:22], avg(S["SQ_WAIT_ANY"][k]) / wc, avg(S["SQ_WAIT_INST_ANY"][k]) / wc,
+            lines.append("%-28s %9.3f %9.3f %9.3f %9.3f %11.1f %9.1f" % (
+                k[:28], avg(S["SQ_WAIT_ANY"][k]) / wc, avg(S["SQ_WAIT_INST_ANY"][k]) / wc,
                 avg(S["SQ_ACTIVE_INST_ANY"][k]) / wc, avg(S["SQ_ACTIVE_INST_VMEM"][k]) / wc,
                 avg(S["SQ_INSTS_VALU_TRANS_F64"][k]) / nw, avg(S["SQ_INSTS_VMEM_RD"][k]) / nw))
     open(os.path.join(PROFILES, "%s_counters.txt" % tag), "w").write("\n".join(lines) + "\n")
