@@ -201,6 +201,16 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
 int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
              geno_stats* stats, void* stream);
 
+/* Conserved totals (diagnostic): totals[f] = |cell| * sum over the interior
+ * cells of W[f] for every field f (3 in 1-D, 4 in 2-D), |cell| = dx (1-D) or
+ * dx dy (2-D). The update is in conservation form (Eq. (1)): on periodic
+ * grids these totals stay constant up to rounding. Compensated summation
+ * (Neumaier) in a fixed order, so the result is deterministic and within a
+ * few units in the last place of the exactly rounded sum.
+ * W: device, the state layout of gks_step; totals: device, nfields doubles.
+ * Asynchronous on stream; no workspace. */
+int geno_conserved_totals(const geno_grid* g, const void* W, double* totals, void* stream);
+
 /* ---- batched form --------------------------------------------------------
  * Many independent 2-D grids advanced together: each kernel kind runs as one
  * launch over the work of every grid (work-group ranges concatenated; each

@@ -208,6 +208,20 @@ def step(prm, W, dW, nsteps, dx=None, dy=None, fixed_dt=0.0):
     return W, dW, dts[:nsteps], g.value
 
 
+def conserved_totals(W, dx=None, dy=None):
+    """Sum over the cells of each conserved field times the cell size (dx in
+    1-D, dx dy in 2-D): the quantities the conservation form of the update
+    (Eq. (1)) keeps fixed on periodic grids. Each sum is the exactly rounded
+    one (math.fsum), then multiplied by the cell size."""
+    import math
+    W = _c(W)
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    area = dx * dy if ndim == 2 else dx
+    return np.array([math.fsum(W[f].ravel().tolist()) * area for f in range(nv)])
+
+
 def cfl_dt(prm, W, dx=None, dy=None):
     W = _c(W)
     ndim, nv, ny, nx = _dims(W)

@@ -738,6 +738,54 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
   }
 }
 
+// Conserved totals: one work-group of 1024 lanes per field. Each lane sums
+// its cells (strided, in index order) with Neumaier's compensation; the
+// (sum, correction) pairs are then combined in a fixed tree, first across
+// the wave, then across the waves in order.
+__device__ __forceinline__ void two_sum_acc(double& s, double& c, double x) {
+  const double t = s + x;
+  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+__global__ void __launch_bounds__(1024) k_totals(Geo g, const double* __restrict__ W,
+                                                 double area, double* __restrict__ totals) {
+  __shared__ double rs[16], rc[16];
+  const int f = (int)blockIdx.x;
+  const int n = g.nx * g.ny;
+  double s = 0.0, c = 0.0;
+  for (int t = (int)threadIdx.x; t < n; t += (int)blockDim.x) {
+    const int j = t / g.nx, i = t - j * g.nx;
+    two_sum_acc(s, c, W[at(g, f, j, i)]);
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double s2 = __shfl_xor(s, off, 64), c2 = __shfl_xor(c, off, 64);
+    // lanes l and l ^ off combine in the order (lower lane, higher lane)
+    const bool lo = ((int)threadIdx.x & off) == 0;
+    double a = lo ? s : s2, b = lo ? s2 : s;
+    double cc = lo ? c + c2 : c2 + c;
+    two_sum_acc(a, cc, b);
+    s = a;
+    c = cc;
+  }
+  const int w = (int)threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rs[w] = s;
+    rc[w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (int)blockDim.x >> 6;
+    double a = rs[0], cc = rc[0];
+    for (int q = 1; q < nw; ++q) {
+      cc += rc[q];
+      two_sum_acc(a, cc, rs[q]);
+    }
+    totals[f] = (a + cc) * area;
+  }
+}
+
 // 1-D: reduce the CFL partials of the previous kernel (single block).
 __global__ void __launch_bounds__(BLOCK) k_dt1d(const double* __restrict__ part, int npart,
                                                 Ctrl* ctrl, double cfl, double dt_fixed,
@@ -2092,6 +2140,17 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
       return fail(GENO_ENONPHYS, "%llu non-physical cells (non-finite, rho <= 0 or p <= 0)",
                   h.nonfinite);
   }
+  return GENO_OK;
+}
+
+int geno_conserved_totals(const geno_grid* g, const void* W, double* totals, void* stream) {
+  const int rc = check_grid(g);
+  if (rc) return rc;
+  if (!W || !totals) return fail(GENO_EINVAL, "null pointer");
+  const int nv = g->ndim == 2 ? 4 : 3;
+  const double area = g->ndim == 2 ? g->dx * g->dy : g->dx;
+  HIP_TRY(launch_bs(-1, k_totals, (unsigned)nv, 1024u, (hipStream_t)stream, geo_of(g),
+                    (const double*)W, area, totals));
   return GENO_OK;
 }
 

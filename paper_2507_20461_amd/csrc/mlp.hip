@@ -1,10 +1,12 @@
 // Training kernels of the learned GENO gate (float32): forward pass, loss,
 // back-propagation and Adam, written out per sample and per parameter.
-// Gradients are reduced over the samples by one thread per parameter with a
-// float64 accumulator, so they are deterministic (no atomics).
+// Gradients are reduced over the samples in two deterministic passes (no
+// atomics): per chunk of CH samples and parameter a float64 partial sum, then
+// per parameter the sum of its partials in chunk order.
 //
-// Minibatch layout: X[n][40], y[n]; scratch per sample: a1[64], a2[64],
-// da1[64], da2[64], dz, loss (see geno_mlp_train_workspace_bytes).
+// Minibatch layout: X[n][40], y[n]; scratch per sample: a1[64], h1[64],
+// a2[64], h2[64], da1[64], da2[64], dz, loss, then the partial sums
+// [ceil(n / CH)][6849] (see geno_mlp_train_workspace_bytes).
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -24,32 +26,37 @@ using namespace mlp;
 
 constexpr int TB = 128;   // threads per work-group of the per-sample kernels
 
+constexpr int CH = 256;   // samples per partial sum of the gradient reduction
+
 struct Scratch {
-  float *a1, *a2, *da1, *da2, *dz, *ls;
+  float *a1, *h1, *a2, *h2, *da1, *da2, *dz, *ls;
+  double* part;   // [nchunk][NPARAM]
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int nchunks(int n) { return (n + CH - 1) / CH; }
 
 Scratch scratch_of(void* ws, int n) {
   char* b = (char*)ws;
   Scratch s;
   size_t off = 0;
-  s.a1 = (float*)(b + off);
-  off = align256(off + sizeof(float) * NH * (size_t)n);
-  s.a2 = (float*)(b + off);
-  off = align256(off + sizeof(float) * NH * (size_t)n);
-  s.da1 = (float*)(b + off);
-  off = align256(off + sizeof(float) * NH * (size_t)n);
-  s.da2 = (float*)(b + off);
-  off = align256(off + sizeof(float) * NH * (size_t)n);
+  float** per_sample[6] = {&s.a1, &s.h1, &s.a2, &s.h2, &s.da1, &s.da2};
+  for (float** f : per_sample) {
+    *f = (float*)(b + off);
+    off = align256(off + sizeof(float) * NH * (size_t)n);
+  }
   s.dz = (float*)(b + off);
   off = align256(off + sizeof(float) * (size_t)n);
   s.ls = (float*)(b + off);
+  off = align256(off + sizeof(float) * (size_t)n);
+  s.part = (double*)(b + off);
   return s;
 }
 
 size_t scratch_bytes(int n) {
-  return 4 * align256(sizeof(float) * NH * (size_t)n) + 2 * align256(sizeof(float) * (size_t)n);
+  return 6 * align256(sizeof(float) * NH * (size_t)n) + 2 * align256(sizeof(float) * (size_t)n) +
+         align256(sizeof(double) * NPARAM * (size_t)nchunks(n));
 }
 
 // weights of both hidden layers in LDS (26.6 KB), the rest in registers
@@ -87,8 +94,11 @@ __global__ void __launch_bounds__(TB) k_mlp_sample(const float* __restrict__ P,
     float a = b1[o];
 #pragma unroll
     for (int k = 0; k < NIN; ++k) a += sW1[o * NIN + k] * x[k];
-    if (y) s.a1[(size_t)i * NH + o] = a;
     h1[o] = gelu(a);
+    if (y) {
+      s.a1[(size_t)i * NH + o] = a;
+      s.h1[(size_t)i * NH + o] = h1[o];
+    }
   }
   float z = b3;
   float a2[NH];
@@ -112,6 +122,7 @@ __global__ void __launch_bounds__(TB) k_mlp_sample(const float* __restrict__ P,
 #pragma unroll
   for (int o = 0; o < NH; ++o) {
     s.a2[(size_t)i * NH + o] = a2[o];
+    s.h2[(size_t)i * NH + o] = gelu(a2[o]);
     a2[o] = dzi * w3[o] * gelu_d(a2[o]);
     s.da2[(size_t)i * NH + o] = a2[o];
   }
@@ -125,31 +136,43 @@ __global__ void __launch_bounds__(TB) k_mlp_sample(const float* __restrict__ P,
   }
 }
 
-// One thread per parameter: the sum over the samples of its gradient terms.
-__global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ X, Scratch s, int n,
-                                                    float* __restrict__ grad) {
+// Partial sums of the gradient terms: thread (parameter p, chunk blockIdx.y)
+// over the chunk's samples, in sample order.
+__global__ void __launch_bounds__(256) k_mlp_partial(const float* __restrict__ X, Scratch s,
+                                                     int n) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NPARAM) return;
+  const int i0 = (int)blockIdx.y * CH, i1 = min(n, i0 + CH);
   double acc = 0.0;
   if (p < OB1) {
     const int o = p / NIN, k = p % NIN;
-    for (int i = 0; i < n; ++i) acc += (double)s.da1[(size_t)i * NH + o] * X[(size_t)i * NIN + k];
+    for (int i = i0; i < i1; ++i)
+      acc += (double)s.da1[(size_t)i * NH + o] * X[(size_t)i * NIN + k];
   } else if (p < OW2) {
     const int o = p - OB1;
-    for (int i = 0; i < n; ++i) acc += s.da1[(size_t)i * NH + o];
+    for (int i = i0; i < i1; ++i) acc += s.da1[(size_t)i * NH + o];
   } else if (p < OB2) {
     const int q = p - OW2, o = q / NH, k = q % NH;
-    for (int i = 0; i < n; ++i)
-      acc += (double)s.da2[(size_t)i * NH + o] * gelu(s.a1[(size_t)i * NH + k]);
+    for (int i = i0; i < i1; ++i)
+      acc += (double)s.da2[(size_t)i * NH + o] * s.h1[(size_t)i * NH + k];
   } else if (p < OW3) {
     const int o = p - OB2;
-    for (int i = 0; i < n; ++i) acc += s.da2[(size_t)i * NH + o];
+    for (int i = i0; i < i1; ++i) acc += s.da2[(size_t)i * NH + o];
   } else if (p < OB3) {
     const int k = p - OW3;
-    for (int i = 0; i < n; ++i) acc += (double)s.dz[i] * gelu(s.a2[(size_t)i * NH + k]);
+    for (int i = i0; i < i1; ++i) acc += (double)s.dz[i] * s.h2[(size_t)i * NH + k];
   } else {
-    for (int i = 0; i < n; ++i) acc += s.dz[i];
+    for (int i = i0; i < i1; ++i) acc += s.dz[i];
   }
+  s.part[(size_t)blockIdx.y * NPARAM + p] = acc;
+}
+
+// One thread per parameter: its partial sums in chunk order.
+__global__ void __launch_bounds__(256) k_mlp_sum(Scratch s, int nch, float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  double acc = 0.0;
+  for (int c = 0; c < nch; ++c) acc += s.part[(size_t)c * NPARAM + p];
   grad[p] = (float)acc;
 }
 
@@ -204,7 +227,9 @@ int geno_mlp_grad(const float* params, const float* X, const float* y, int n, fl
   const Scratch s = scratch_of(ws, n);
   hipLaunchKernelGGL(k_mlp_sample, dim3((n + TB - 1) / TB), dim3(TB), 0, st, params, X, y, n, s,
                      (float*)nullptr);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, st, X, s, n, grad);
+  const int nch = nchunks(n);
+  hipLaunchKernelGGL(k_mlp_partial, dim3((NPARAM + 255) / 256, nch), dim3(256), 0, st, X, s, n);
+  hipLaunchKernelGGL(k_mlp_sum, dim3((NPARAM + 255) / 256), dim3(256), 0, st, s, nch, grad);
   if (loss) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, st, s, n, loss);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? GENO_OK : fail(GENO_EHIP, "mlp gradient: %s", hipGetErrorString(e));

@@ -57,7 +57,8 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
            "geno_kernel_name", "geno_tuning_default", "gks_batched_workspace_bytes", "gks_step_batched",
            "geno_autotune_batched", "geno_harvest", "geno_mlp_train_workspace_bytes", "geno_mlp_grad",
-           "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob")
+           "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob",
+           "geno_conserved_totals")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d",
            "gate")
 WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard", "gated")
@@ -120,8 +121,9 @@ def lib():
         L.geno_mlp_load.argtypes = [vp, vp]
         L.geno_mlp_infer.argtypes = [vp, i, vp, vp]
         L.geno_gate_prob.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, vp, vp]
+        L.geno_conserved_totals.argtypes = [ctypes.POINTER(geno_grid), vp, vp, vp]
         for name in ("geno_harvest", "geno_mlp_grad", "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load",
-                     "geno_mlp_infer", "geno_gate_prob"):
+                     "geno_mlp_infer", "geno_gate_prob", "geno_conserved_totals"):
             getattr(L, name).restype = i
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
                      "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
@@ -276,6 +278,16 @@ def gks_step(grid, W, dW, ws, nsteps, dt_out=None, stats=False, stream=None):
                         ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc)
     return st
+
+
+def conserved_totals(grid, W, out=None, stream=None):
+    """|cell| * sum of the interior cells of every field (device float64 tensor of nv)."""
+    _need(W, torch.float64, grid.nv * grid.rows * grid.pitch, "W")
+    if out is None:
+        out = torch.empty(grid.nv, dtype=torch.float64, device=W.device)
+    _need(out, torch.float64, grid.nv, "totals")
+    _check(lib().geno_conserved_totals(ctypes.byref(grid.g), _ptr(W), _ptr(out), _stream(stream)))
+    return out
 
 
 def timing_enable(max_launches):

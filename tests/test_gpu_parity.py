@@ -333,3 +333,36 @@ def test_full_size_512_sampled_steps(G, oracle):
         assert st.guard == og
         assert max(e) < TOL, e
     assert np.isfinite(gW).all() and (gW[0] > 0).all()
+
+
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_conserved_totals_match_oracle(G, oracle, ndim):
+    # device compensated sums against the exactly rounded ones, on states
+    # with cancellation between cells
+    _say("conserved_totals %d-D" % ndim)
+    rng = np.random.default_rng(11 + ndim)
+    if ndim == 1:
+        W, _ = inputs.sine_1d(517)
+    else:
+        W, _, _ = inputs.quadrants_2d(131, 97, 3)
+    W = W * (1.0 + 1e3 * rng.standard_normal(W.shape))
+    grid = _grid(G, W, 0)
+    Wd = grid.to_device(W)
+    got = G.conserved_totals(grid, Wd).cpu().numpy()
+    want = oracle.conserved_totals(W, dx=grid.dx, dy=grid.dy if ndim == 2 else None)
+    ulp = np.spacing(np.abs(want))
+    assert (np.abs(got - want) <= 4 * ulp).all(), (got - want) / ulp
+
+
+def test_conserved_totals_constant_on_periodic_run(G):
+    # the update is in conservation form: on a periodic grid the device
+    # totals stay fixed up to rounding over a whole run
+    W, dW = _case_2d("quadrants", 64, 48, 7)
+    grid = _grid(G, W, 0)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    t0 = G.conserved_totals(grid, Wd).cpu().numpy()
+    st = G.gks_step(grid, Wd, dWd, grid.workspace(), 30, stats=True)
+    assert st.nonfinite == 0
+    t1 = G.conserved_totals(grid, Wd).cpu().numpy()
+    scale = np.abs(W).reshape(4, -1).max(axis=1) * grid.dx * grid.dy * W[0].size
+    assert (np.abs(t1 - t0) <= 1e-13 * scale).all(), (t1 - t0) / scale

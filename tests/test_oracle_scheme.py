@@ -174,3 +174,20 @@ def test_oracle_sensitivity_to_rounding(oracle, seed):
     b, _, _, _ = oracle.step(prm, Wp, dW, 200)
     scale = np.abs(a).reshape(3, -1).max(axis=1)[:, None, None]
     assert (np.abs(a - b) / np.maximum(np.abs(a), scale)).max() > 1e-9
+
+
+def test_conserved_totals_exact_sums(oracle):
+    # the oracle's totals are the exactly rounded cell sums times the cell
+    # size: pinned against rational arithmetic on values of mixed magnitude
+    # and sign (cancellation), 1-D and 2-D
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    for shape, dx, dy in (((3, 1, 37), 0.125, None), ((4, 9, 11), 0.25, 0.5)):
+        W = rng.standard_normal(shape) * 10.0 ** rng.integers(-8, 9, shape)
+        W[:, 0, 0] = 1e16
+        W[:, -1, -1] = -1e16
+        tot = oracle.conserved_totals(W, dx=dx, dy=dy)
+        area = dx * dy if dy is not None else dx
+        for f in range(shape[0]):
+            exact = sum((Fraction(float(x)) for x in W[f].ravel()), Fraction(0))
+            assert tot[f] == float(exact) * area
