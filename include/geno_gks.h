@@ -85,6 +85,11 @@ extern "C" {
  *   In a run, the float32 fluxes also leave rounding of about one unit in the
  *   last place per step in W (dt/dx times the rounding of F), which
  *   accumulates over the steps; the default is 64.
+ *   The same bound sets where the mixed flux takes tau = C1 dt: a Gauss point
+ *   whose |p_l - p_r| / (p_l + p_r) is at most eps_ulps * 2^-24 (rounding
+ *   noise of the two reconstructed states) is evaluated in that limit. The
+ *   terms this drops are of order that ratio times the relative difference
+ *   of the states or of h |grad W| / |W|, below the float32 unit roundoff.
  * gate_delta: learned gate (2-D gks_step only). If > 0, before the normal
  *   reconstruction of each direction and stage the loaded network
  *   (geno_mlp_load) predicts chi of every cell from its stencil, and where the

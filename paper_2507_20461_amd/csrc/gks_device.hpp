@@ -219,7 +219,16 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
   const double g = k.gamma, K = k.K;
   Prim<R> pl = prim<NV, R>(Wl, g), pr = prim<NV, R>(Wr, g);
   const R dt = R(dt_w);
-  const R tau = R(k.tc1) * dt + R(k.tc2) * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
+  R tau = R(k.tc1) * dt + R(k.tc2) * dt * fabs(pl.p - pr.p) / (pl.p + pr.p);
+  if constexpr (std::is_same<R, float>::value) {
+    // float32 states: a pressure difference within eps_ulps units of 2^-24
+    // of the pressures is rounding noise; the tau > 0 solution differs from
+    // the tau = C1 dt one by terms of order that ratio times the (equally
+    // small) relative state difference or h |grad W| / |W|, below the
+    // float32 resolution, so that limit is taken
+    if (fabs(pl.p - pr.p) <= R(k.eps_ulps * (1.0 / 16777216.0)) * (pl.p + pr.p))
+      tau = R(k.tc1) * dt;
+  }
   const bool slow = tau > R(0.0);
   if (!FULL && slow) return PT_SLOW;
   // interface equilibrium W_c = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0}.
