@@ -202,3 +202,49 @@ def test_fixed_dt_matches_oracle(G, oracle):
     e = rel_err(gW, oW)
     _say("fixed dt 6 steps: %.3e" % e)
     assert e < 1e-10
+
+
+def test_mixed_flux_tau_limit_within_float32(G, oracle):
+    # With the default noise bound, a Gauss point whose pressures differ only
+    # by float32 rounding takes the tau = C1 dt limit. Against the oracle's
+    # float64 tau > 0 solution on the same point states the flux stays within
+    # the mixed bounds: the dropped terms are below float32 resolution.
+    nx, ny = 40, 36
+    W, dW = _case("smooth", nx, ny, 4)
+    grid = G.Grid(2, nx, ny, bc=0, precision=G.MIXED)    # default eps_ulps
+    assert grid.params.eps_ulps > 0
+    Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
+    fs = torch.empty(grid.face_state_shape(0), dtype=torch.float32, device="cuda")
+    G.geno_reconstruct(grid, Wd, dWd, 0, fs, None, grid.workspace())
+    # right states := left states, with rhoE raised by 4 units of 2^-24 (a
+    # pressure ratio far below 64 units); slopes kept as reconstructed
+    fs[1, :, 0] = fs[0, :, 0]
+    fs[1, :, 0, 3] = fs[0, :, 0, 3] * (1.0 + 4.0 * 2.0 ** -24)
+    shp = grid.flux_shape(0)
+    F, Ft, Wi = (torch.empty(shp, dtype=torch.float32, device="cuda") for _ in range(3))
+    dt = 0.4 * grid.dx
+    G.gks_flux(grid, fs, dt, 0, F, Ft, Wi)
+    torch.cuda.synchronize()
+    st = fs.cpu().numpy().astype(np.float64)
+    prm = oracle.params(ndim=2, bc=0)
+    acc = [np.zeros(shp) for _ in range(3)]
+    ptau = []
+    for q in range(2):
+        def pts(s, k, h):
+            return (st[s, q, k].reshape(4, -1).T / h).copy()
+        Wl, Wr = pts(0, 0, 1.0), pts(1, 0, 1.0)
+        pl = 0.4 * (Wl[:, 3] - 0.5 * (Wl[:, 1] ** 2 + Wl[:, 2] ** 2) / Wl[:, 0])
+        pr = 0.4 * (Wr[:, 3] - 0.5 * (Wr[:, 1] ** 2 + Wr[:, 2] ** 2) / Wr[:, 0])
+        ptau.append(np.abs(pl - pr) / (pl + pr))
+        res = oracle.gks_points(prm, 2, Wl, Wr, pts(0, 1, grid.dx), pts(1, 1, grid.dx),
+                                pts(0, 2, grid.dy), pts(1, 2, grid.dy), dt=dt)
+        for a, r in zip(acc, res):
+            a += 0.5 * r.T.reshape(4, *shp[1:])
+    ratio = np.concatenate(ptau)
+    assert ratio.min() > 0 and ratio.max() <= 64 * 2.0 ** -24
+    fsc = field_scale(acc[0])
+    e = (rel_err(F.cpu().numpy(), acc[0], fsc),
+         rel_err(Ft.cpu().numpy(), acc[1], np.maximum(field_scale(acc[1]), fsc / dt)),
+         rel_err(Wi.cpu().numpy(), acc[2]))
+    _say("mixed flux at noise-level pressure differences vs float64 tau > 0: F %.2e Ft %.2e Wi %.2e" % e)
+    assert e[0] < MIX_W and e[1] < MIX_DW and e[2] < MIX_W, e
