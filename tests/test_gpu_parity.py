@@ -366,3 +366,40 @@ def test_conserved_totals_constant_on_periodic_run(G):
     t1 = G.conserved_totals(grid, Wd).cpu().numpy()
     scale = np.abs(W).reshape(4, -1).max(axis=1) * grid.dx * grid.dy * W[0].size
     assert (np.abs(t1 - t0) <= 1e-13 * scale).all(), (t1 - t0) / scale
+
+
+# ------------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("nx,ny,bc", [(1, 1, 1), (2, 2, 0), (1, 6, 1), (7, 1, 1), (3, 2, 0), (2, 9, 0),
+                                      (5, 3, 1)])
+def test_step_tiny_grids(G, oracle, nx, ny, bc):
+    # degenerate and ragged 2-D grids (single cells, single rows or columns,
+    # the smallest periodic axes): three steps against the oracle
+    _say("tiny grid", nx, ny, bc)
+    W, dW = _case_2d("quadrants", nx, ny, 2)
+    grid = _grid(G, W, bc)
+    gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 3)
+    oW, odW, odt, og = oracle.step(_oprm(oracle, 2, bc), W, dW, 3, dx=grid.dx, dy=grid.dy)
+    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
+    _say("  errors W %.2e dW %.2e dt %.2e" % e)
+    assert gg.guard == og and max(e) < TOL, e
+
+
+@pytest.mark.parametrize("nx,bc", [(1, 1), (2, 0), (3, 1)])
+def test_step_tiny_1d(G, oracle, nx, bc):
+    _say("tiny 1-D", nx, bc)
+    W, dW, _ = inputs.jump_1d(nx, 1)
+    grid = _grid(G, W, bc)
+    gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 3)
+    oW, odW, odt, og = oracle.step(_oprm(oracle, 1, bc), W, dW, 3, dx=grid.dx)
+    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(gdt, odt))
+    assert gg.guard == og and max(e) < TOL, e
+
+
+def test_zero_steps_leave_the_state(G):
+    # nsteps = 0 is a valid call: the interior state is untouched
+    W, dW = _case_2d("vortex", 24, 20, 1)
+    grid = _grid(G, W, 1)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    st = G.gks_step(grid, Wd, dWd, grid.workspace(), 0, stats=True)
+    assert st.nonfinite == 0 and st.guard == 0
+    assert np.array_equal(grid.interior(Wd), W) and np.array_equal(grid.interior(dWd), dW)
