@@ -973,7 +973,7 @@ __device__ __forceinline__ void mlp_tile(const MlpRegs& R, const __bf16* xs, __b
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, R.w[nt], acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, R.w[4 + nt], acc, 0, 0, 0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) hs[(4 * g + e) * 64 + nt * 16 + r] = (__bf16)mlp::gelu(acc[e] + R.b1[nt]);
+    for (int e = 0; e < 4; ++e) hs[(4 * g + e) * 64 + nt * 16 + r] = (__bf16)mlp::gelu_fast(acc[e] + R.b1[nt]);
   }
   __syncthreads();
   a0 = *reinterpret_cast<const bf16x8*>(hs + r * 64 + 8 * g);
@@ -985,7 +985,7 @@ __device__ __forceinline__ void mlp_tile(const MlpRegs& R, const __bf16* xs, __b
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, R.w[8 + nt], acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, R.w[12 + nt], acc, 0, 0, 0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) zs[e] += mlp::gelu(acc[e] + R.b2[nt]) * R.w3[nt];
+    for (int e = 0; e < 4; ++e) zs[e] += mlp::gelu_fast(acc[e] + R.b2[nt]) * R.w3[nt];
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {

@@ -38,6 +38,15 @@ __device__ __forceinline__ float gelu_d(float u) {
 
 __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
 
+// The same function for inference, where the result is rounded to bfloat16
+// or summed in float32: u (1 + tanh z) / 2 = u / (1 + exp(-2 z)), with the
+// hardware exponential and reciprocal (a few units in the last place of
+// float32, far below bfloat16 resolution). Large |z| give u or 0 exactly.
+__device__ __forceinline__ float gelu_fast(float u) {
+  const float z = GC * (u + 0.044715f * u * u * u);
+  return u * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * z));
+}
+
 // stable softplus(z) - y z
 __device__ __forceinline__ float bce(float z, float y) {
   return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))) - y * z;
