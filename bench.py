@@ -72,6 +72,31 @@ def traffic(kind, n):
         "source": os.path.relpath(COUNTERS, ROOT)}
 
 
+def algo_bytes(kind, work, launches, nx, ny):
+    """Algorithmic HBM bytes of all launches of one kernel kind (2-D FP64):
+    what the kernel must read and write once, from its work counts.
+    normal: W and h d/dn of one cell in (16 B), value and h d/dn per side out
+    (32 B) per face-row entry. faces: the 16 face-row values of every face in
+    (128 B); F (stage 1 only), dF/dt and W_int out for each face it evaluates
+    (96 B / 64 B, 80 B on average over the two stages). slow: as faces for
+    the queued faces, plus the queue index. update_1: W in, two faces' 12
+    planes in amortised to 192 B, W*, grad W*, R out: 352 B per cell;
+    update_2: R in, 8 face planes, W and grad W out: 256 B per cell."""
+    u = work.get(kind, {}).get("units", 0)
+    if kind in ("normal_x", "normal_y"):
+        return 48.0 * u
+    if kind in ("faces_x", "faces_y"):
+        nfaces = ny * (nx + 1) if kind == "faces_x" else (ny + 1) * nx
+        return 128.0 * nfaces * launches + 80.0 * u
+    if kind == "slow":
+        return (128.0 + 80.0 + 4.0) * u
+    if kind == "update_1":
+        return 352.0 * u
+    if kind == "update_2":
+        return 256.0 * u
+    return None
+
+
 def cpu_baseline(W, dW, n, min_seconds=10.0):
     """The oracle timed on the host: whole S2O4 steps (2 stages each) of the
     same workload state, continued until at least min_seconds have passed."""
@@ -353,23 +378,36 @@ def main():
         if not nl:
             continue
         flops = sum(work[k][c] * costs[k][c] for c in costs[k])
+        ab = algo_bytes(k, work, nl, n, n)
         kernels[k] = {"ms_total": round(kms, 4), "launches": nl, "us_avg": round(1e3 * kms / nl, 3),
                       "gflop_per_launch": round(flops / nl / 1e9, 6),
                       "tflops": round(flops / (kms / 1e3) / 1e12, 4) if kms > 0 else None,
+                      "mb_per_launch": round(ab / nl / 1e6, 3) if ab else None,
+                      "gbs": round(ab / (kms / 1e3) / 1e9, 1) if ab and kms > 0 else None,
                       "work": {c: work[k][c] for c in work[k] if work[k][c]}}
     dominant = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
     roofline = None
     if dominant:
+        # classic roofline: the kernel's arithmetic intensity (counted flops
+        # per algorithmic byte) against the ridge point peak flops / peak bytes
         d = kernels[dominant]
-        achieved = d["tflops"]
         tbytes, tdetail = traffic(dominant, n)
-        roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved,
-                    "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 5) if achieved else None,
-                    "traffic": round(tbytes) if tbytes else None, "traffic_detail": tdetail,
-                    "hbm_gbs_at_traffic": round(tbytes / (d["us_avg"] * 1e-6) / 1e9, 1) if tbytes else None,
-                    "flop_convention": "add/sub/mul/div/sqrt and each exp/expm1/erfc/tanh call = 1 FP64 op",
-                    "gflop_per_launch": d["gflop_per_launch"], "us_per_launch": d["us_avg"]}
+        ridge = PEAK_FP64_VECTOR_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+        ai = d["gflop_per_launch"] * 1e9 / (d["mb_per_launch"] * 1e6) if d["mb_per_launch"] else None
+        alu_frac = round(d["tflops"] / PEAK_FP64_VECTOR_TFLOPS, 5) if d["tflops"] else None
+        if ai is not None and ai < ridge:
+            roofline = {"bound": "hbm", "kernel": dominant, "achieved": d["gbs"], "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(d["gbs"] / PEAK_HBM_GBS, 5)}
+        else:
+            roofline = {"bound": "alu", "kernel": dominant, "achieved": d["tflops"],
+                        "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac}
+        roofline.update({
+            "traffic": round(tbytes) if tbytes else None, "traffic_detail": tdetail,
+            "algorithmic_mb_per_launch": d["mb_per_launch"], "us_per_launch": d["us_avg"],
+            "arithmetic_intensity": round(ai, 3) if ai else None, "ridge_flop_per_byte": round(ridge, 3),
+            "alu_achieved_tflops": d["tflops"], "alu_peak_tflops": PEAK_FP64_VECTOR_TFLOPS, "alu_frac": alu_frac,
+            "flop_convention": "add/sub/mul/div/sqrt and each exp/expm1/erfc/tanh call = 1 FP64 op",
+            "gflop_per_launch": d["gflop_per_launch"]})
     out = {
         "metric": "Mcell-updates/s per stage (2-D Euler, compact GKS + GENO, FP64)",
         "value": round(value, 3),
