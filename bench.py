@@ -34,7 +34,10 @@ PEAK_HBM_GBS = 8000.0
 ROCPROF_NAMES = {"init": "k_init<2, double>", "normal_x": "k_normal2d<0, double>",
                  "normal_y": "k_normal2d<1, double>", "faces_x": "k_faces2d<0, 1, double>",
                  "faces_y": "k_faces2d<1, 1, double>", "slow": "k_slow2d<double>",
-                 "update_1": "k_update<2, 1, double>", "update_2": "k_update<2, 2, double>"}
+                 "update_1": "k_update<2, 1, double>", "update_2": "k_update<2, 2, double>",
+                 "normal_xy": "k_normal2d_xy<double>"}
+# a launch that does the work counted under several kinds
+COMBINED = {"normal_xy": ("normal_x", "normal_y")}
 COUNTERS = os.path.join(ROOT, "profiles", "faces_fp64_512_counters.json")
 
 
@@ -377,14 +380,16 @@ def main():
     for k, (kms, nl) in kt.items():
         if not nl:
             continue
-        flops = sum(work[k][c] * costs[k][c] for c in costs[k])
-        ab = algo_bytes(k, work, nl, n, n)
+        parts = COMBINED.get(k, (k,))
+        flops = sum(work[p][c] * costs[p][c] for p in parts for c in costs[p])
+        ab = sum(algo_bytes(p, work, nl, n, n) or 0.0 for p in parts) or None
         kernels[k] = {"ms_total": round(kms, 4), "launches": nl, "us_avg": round(1e3 * kms / nl, 3),
                       "gflop_per_launch": round(flops / nl / 1e9, 6),
                       "tflops": round(flops / (kms / 1e3) / 1e12, 4) if kms > 0 else None,
                       "mb_per_launch": round(ab / nl / 1e6, 3) if ab else None,
                       "gbs": round(ab / (kms / 1e3) / 1e9, 1) if ab and kms > 0 else None,
-                      "work": {c: work[k][c] for c in work[k] if work[k][c]}}
+                      "work": {c: sum(work[p][c] for p in parts) for c in work[parts[0]]
+                               if sum(work[p][c] for p in parts)}}
     dominant = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
     roofline = None
     if dominant:

@@ -350,6 +350,9 @@ enum {
   GENO_K_UPDATE_2,     /* stage-2 update, gradients, ghost cells, CFL partial minima */
   GENO_K_FACES_1D,     /* 1-D: GENO + flux per face */
   GENO_K_GATE,         /* learned gate of both directions (network inference) */
+  GENO_K_NORMAL_XY,    /* 2-D gks_step: normal GENO of both directions in one
+                          launch (its work is counted under NORMAL_X and
+                          NORMAL_Y) */
   GENO_NKERNELS
 };
 

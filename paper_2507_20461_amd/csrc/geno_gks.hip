@@ -74,7 +74,7 @@ int g_tim_suspend = 0;   // set while a launch sequence is captured into a graph
 
 const char* const KNAMES[GENO_NKERNELS] = {"init",     "normal_x", "normal_y", "faces_x",
                                            "faces_y",  "slow",     "update_1", "update_2",
-                                           "faces_1d", "gate"};
+                                           "faces_1d", "gate",     "normal_xy"};
 
 // Every launch goes through here: a kernel of kind >= 0 is timed while
 // timing is enabled (events bound to the dispatch itself).
@@ -608,6 +608,31 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
                                                    unsigned int* __restrict__ queue) {
   faces_body<DIR, MODE, T>(g, k, W, fr, out, ctrl, want_F, cnt, queue, xcd_block());
 }
+
+// The normal step of both directions in one launch: work-groups [0, nbx)
+// take the x-direction entries, the rest the y-direction ones (a uniform
+// branch per work-group; with the XCD remapping, XCDs 0-3 take x and 4-7
+// y). Twice the waves of one direction per launch, and one launch ramp
+// less per stage. (The face step stays one launch per direction: over both,
+// each XCD's L2 would hold twice the face-row rows it reuses.)
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_normal2d_xy(Geo g, geno::KParams k,
+                                                       const double* __restrict__ W,
+                                                       const T* __restrict__ dW,
+                                                       T* __restrict__ frx, T* __restrict__ fry,
+                                                       Ctrl* ctrl,
+                                                       const double* __restrict__ part, int npart,
+                                                       double* dt_out, int step, Cnt cnt,
+                                                       const unsigned char* __restrict__ gx,
+                                                       const unsigned char* __restrict__ gy,
+                                                       int nbx) {
+  const int b = xcd_block();
+  if (b < nbx)
+    normal_body<0, T>(g, k, W, dW, frx, nullptr, ctrl, part, npart, dt_out, step, cnt, b, gx);
+  else
+    normal_body<1, T>(g, k, W, dW, fry, nullptr, ctrl, nullptr, 0, nullptr, 0, cnt, b - nbx, gy);
+}
+
 
 // The faces of both directions queued by k_faces2d<DIR, 1> (tau > 0 at one
 // of their Gauss points), with the full solution: lane pairs as there,
@@ -1445,6 +1470,8 @@ int count_cap(const geno_grid* g) {
       m = std::max<size_t>(m, nblocks(4 * face_rows(g, d)));
       m = std::max<size_t>(m, nblocks(2 * faces_of(g, d)));
     }
+    // the normal-step launch over both directions
+    m = std::max<size_t>(m, nblocks(4 * face_rows(g, 0)) + nblocks(4 * face_rows(g, 1)));
     m = std::max<size_t>(m, slow_blocks(g));
   } else {
     m = std::max<size_t>(m, nblocks((size_t)g->nx + 1));
@@ -1478,14 +1505,11 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
       gx = B.gate;
       gy = B.gate + nc;
     }
-    HIP_TRY(launch(GENO_K_NORMAL_X, k_normal2d<0, T>, nblocks(4 * face_rows(g, 0)), s, geo, k,
-                   Win, dWin, B.fr[0], (double*)nullptr, B.ctrl, part, npart, dt_out, step, cnt,
-                   gx));
+    const unsigned nnx = nblocks(4 * face_rows(g, 0)), nny = nblocks(4 * face_rows(g, 1));
+    HIP_TRY(launch(GENO_K_NORMAL_XY, k_normal2d_xy<T>, nnx + nny, s, geo, k, Win, dWin, B.fr[0],
+                   B.fr[1], B.ctrl, part, npart, dt_out, step, cnt, gx, gy, (int)nnx));
     HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
                    B.fr[0], B.fl[0], B.ctrl, want_F, cnt, B.queue[0]));
-    HIP_TRY(launch(GENO_K_NORMAL_Y, k_normal2d<1, T>, nblocks(4 * face_rows(g, 1)), s, geo, k,
-                   Win, dWin, B.fr[1], (double*)nullptr, B.ctrl, (const double*)nullptr, 0,
-                   (double*)nullptr, 0, cnt, gy));
     HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
                    B.fr[1], B.fl[1], B.ctrl, want_F, cnt, B.queue[1]));
     HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T>, slow_blocks(g), s, geo, k, Win, B.fr[0], B.fr[1],

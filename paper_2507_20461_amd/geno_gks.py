@@ -60,7 +60,7 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob",
            "geno_conserved_totals")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d",
-           "gate")
+           "gate", "normal_xy")
 WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard", "gated")
 MLP_NIN, MLP_NPARAM = 40, 6849
 
