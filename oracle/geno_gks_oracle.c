@@ -1057,6 +1057,117 @@ int oracle_normal_faces(const double *params, int ndim, int nx, int ny, double d
   return OR_OK;
 }
 
+/* ---------------------------------------------------------------------- */
+/* The paper's comparison of the nonlinear weights (Sec. 5): WENO-Z and     */
+/* TENO weights on the same three sub-stencils, and the share of the linear */
+/* reconstruction each keeps, chi = min_k w_k / d_k (for GENO: its path     */
+/* function). d_k are the linear weights normalised to sum 1.               */
+/* ---------------------------------------------------------------------- */
+/* IS_k of the three sub-stencil quadratics of one side (as in geno_side). */
+static void side_is(const double dat[10], int si, double IS[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double c[3];
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+      for (int m = 0; m < 10; ++m) s += SUB[si][k][q][m] * dat[m];
+      c[q] = s;
+    }
+    IS[k] = is_quadratic(c);
+  }
+}
+
+/* WENO-Z: w~_k = d_k (1 + tau_Z / (IS_k + eps)), w = w~ / sum w~. tau_Z is
+ * the difference of the two outer sub-stencils' indicators, |IS_1 - IS_3|
+ * (reading: the paper leaves tau_Z to the stencil). Returns chi. */
+static double wenoz_weights(const ocfg *P, const double IS[3], double w[3]) {
+  double dsum = P->d[0] + P->d[1] + P->d[2], tz = fabs(IS[0] - IS[2]), ws = 0.0;
+  for (int k = 0; k < 3; ++k) { w[k] = (P->d[k] / dsum) * (1.0 + tz / (IS[k] + P->eps)); ws += w[k]; }
+  double chi = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    w[k] /= ws;
+    double r = w[k] / (P->d[k] / dsum);
+    if (r < chi) chi = r;
+  }
+  return chi;
+}
+
+/* TENO: scale separation gamma_k = (1/(IS_k + eps))^7 normalised; a
+ * sub-stencil with gamma_k <= C_T is cut; w_k = delta_k d_k / sum delta d.
+ * Returns chi (1 when no sub-stencil is cut, else 0). */
+static double teno_weights(const ocfg *P, const double IS[3], double ct, double w[3]) {
+  double g[3], gs = 0.0, ws = 0.0;
+  for (int k = 0; k < 3; ++k) { g[k] = pow(1.0 / (IS[k] + P->eps), 7.0); gs += g[k]; }
+  for (int k = 0; k < 3; ++k) { w[k] = (g[k] / gs > ct) ? P->d[k] : 0.0; ws += w[k]; }
+  double chi = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    w[k] /= ws;
+    double r = w[k] / (P->d[k] / (P->d[0] + P->d[1] + P->d[2]));
+    if (r < chi) chi = r;
+  }
+  return chi;
+}
+
+/* Weights of all three methods from given indicators IS[3]:
+ * out = w_Z[3], chi_Z, w_T[3], chi_T, chi_GENO (IS^tau of the compact scheme). */
+int oracle_weights(const double *params, const double *IS, double ct, double *out) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, 1, 1, 1, 1.0, 1.0, params);
+  out[3] = wenoz_weights(&P, IS, out);
+  out[7] = teno_weights(&P, IS, ct, out + 4);
+  double ISH = IS[0], ISL = IS[0];
+  for (int k = 1; k < 3; ++k) { if (IS[k] > ISH) ISH = IS[k]; if (IS[k] < ISL) ISL = IS[k]; }
+  out[8] = path_function(&P, fabs((IS[1] + IS[2]) / 2.0 - IS[0]), ISH, ISL);
+  return OR_OK;
+}
+
+/* chi of GENO, WENO-Z and TENO on every face-side of a direction (layout of
+ * oracle_normal_faces' chi): out[method][side][var][...]. */
+int oracle_linearity_faces(const double *params, int ndim, int nx, int ny, double dx, double dy,
+                           const double *W, const double *dW, int dir, double ct, double *out) {
+  if (oracle_init()) return OR_EINVAL;
+  ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
+  gstate g;
+  if (gstate_alloc(&P, &g)) return OR_ENOMEM;
+  gstate_load(&P, &g, W, dW);
+  fill_ghosts(&P, &g);
+  int nv = P.nv;
+  int n0, n1;
+  if (ndim == 1) { n0 = 1; n1 = nx + 1; }
+  else if (dir == 0) { n0 = ny + 2; n1 = nx + 1; }
+  else { n0 = ny + 1; n1 = nx + 2; }
+  int d = ndim == 1 ? 0 : dir;
+  size_t plane = (size_t)n0 * n1, mplane = 2 * (size_t)nv * plane;
+  double h = (d == 0) ? P.dx : P.dy;
+  for (int a = 0; a < n0; ++a)
+    for (int b = 0; b < n1; ++b) {
+      int i = NG + b - 1, j = ndim == 1 ? 0 : NG + a - 1;
+      for (int v = 0; v < nv; ++v) {
+        double q[4], gg[4];
+        for (int m = -1; m <= 2; ++m) {
+          int ii = (d == 0) ? i + m : i, jj = (d == 0) ? j : j + m;
+          q[m + 1] = g.W[gidx(&g, v, jj, ii)];
+          gg[m + 1] = h * g.dW[gidx(&g, d * nv + v, jj, ii)];
+        }
+        double dl[10] = {0}, dr[10] = {0};
+        for (int m = 0; m < 4; ++m) {
+          dl[2 * (m + 1)] = q[m]; dl[2 * (m + 1) + 1] = gg[m];
+          dr[2 * m] = q[m]; dr[2 * m + 1] = gg[m];
+        }
+        for (int s = 0; s < 2; ++s) {
+          double IS[3], w[9];
+          side_is(s == 0 ? dl : dr, s, IS);
+          oracle_weights(params, IS, ct, w);
+          size_t o = ((size_t)s * nv + v) * plane + (size_t)a * n1 + b;
+          out[0 * mplane + o] = w[8];
+          out[1 * mplane + o] = w[3];
+          out[2 * mplane + o] = w[7];
+        }
+      }
+    }
+  gstate_free(&g);
+  return OR_OK;
+}
+
 /* Face states at the Gauss points after the tangential step and the
  * positivity guard (2-D), or at the face (1-D).
  * out: [side][gauss][quant][var][nfy][nfx], quant = value, h*d_n, h*d_t (2-D)

@@ -56,11 +56,13 @@ def lib():
         L.oracle_face_states.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, llp]
         L.oracle_step.argtypes = [dp, i, i, i, d, d, dp, dp, i, d, dp, llp]
         L.oracle_stage_faces.argtypes = [dp, i, i, i, d, d, dp, dp, d, i, dp, dp, dp]
+        L.oracle_weights.argtypes = [dp, dp, d, dp]
+        L.oracle_linearity_faces.argtypes = [dp, i, i, i, d, d, dp, dp, i, d, dp]
         L.oracle_cfl_dt.argtypes = [dp, i, i, i, d, d, dp]
         L.oracle_cfl_dt.restype = d
         for name in ("oracle_linear_weights", "oracle_geno_face", "oracle_geno_side_detail", "oracle_moments",
                      "oracle_gks_points", "oracle_normal_faces", "oracle_face_states",
-                     "oracle_step", "oracle_stage_faces"):
+                     "oracle_step", "oracle_stage_faces", "oracle_weights", "oracle_linearity_faces"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -115,6 +117,37 @@ def geno_side_detail(prm, dat, side, qH, hqH):
                                          _p(out)), "oracle_geno_side_detail")
     return dict(IS=out[0:3], p=out[3:6], hp=out[6:9], omega=out[9:12], chi=out[12],
                 qL=out[13], hqL=out[14], R=out[15], hR=out[16])
+
+
+TENO_CT = 1e-6   # the paper's cut-off of the TENO scale separation
+
+
+def weights(prm, IS, ct=TENO_CT):
+    """WENO-Z and TENO weights and the linearity measures of the paper's
+    comparison from three sub-stencil indicators IS (IS_1, IS_2, IS_3).
+    Returns dict(wz, chi_z, wt, chi_t, chi_geno)."""
+    out = np.zeros(9)
+    _check(lib().oracle_weights(_p(_c(prm)), _p(_c(IS)), float(ct), _p(out)), "oracle_weights")
+    return dict(wz=out[0:3], chi_z=out[3], wt=out[4:7], chi_t=out[7], chi_geno=out[8])
+
+
+def linearity_faces(prm, W, dW, direction=0, ct=TENO_CT, dx=None, dy=None):
+    """chi of GENO, WENO-Z and TENO on every face-side of a direction:
+    [method][side][var][a][b] (layout of normal_faces' chi)."""
+    W, dW = _c(W), _c(dW)
+    ndim, nv, ny, nx = _dims(W)
+    dx = 1.0 / nx if dx is None else dx
+    dy = 1.0 / ny if dy is None else dy
+    if ndim == 1:
+        n0, n1 = 1, nx + 1
+    elif direction == 0:
+        n0, n1 = ny + 2, nx + 1
+    else:
+        n0, n1 = ny + 1, nx + 2
+    out = np.zeros((3, 2, nv, n0, n1))
+    _check(lib().oracle_linearity_faces(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), direction,
+                                        float(ct), _p(out)), "oracle_linearity_faces")
+    return out
 
 
 def moments(U, V, lam, K, half, has_v=True):
