@@ -100,6 +100,33 @@ def algo_bytes(kind, work, launches, nx, ny):
     return None
 
 
+def linearity_shares(G, torch, grid, Wd, dWd, ws, reps=5):
+    """The paper's comparison of nonlinear weights on a state: per method
+    (GENO, WENO-Z, TENO) the share of face-sides (both directions, all
+    variables) that keep the linear reconstruction (chi >= 0.999) and the mean
+    chi; and the time of one geno_linearity call (ghost fill + one direction)."""
+    import numpy as np
+    shares, means, total = np.zeros(3), np.zeros(3), 0
+    for d in (0, 1):
+        chi = G.linearity(grid, Wd, dWd, d, ws).cpu().numpy().reshape(3, -1)
+        shares += (chi >= 0.999).sum(axis=1)
+        means += chi.sum(axis=1)
+        total += chi.shape[1]
+    out = G.linearity(grid, Wd, dWd, 0, ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        G.linearity(grid, Wd, dWd, 0, ws, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    res = {m: {"linear_share": round(float(shares[i] / total), 4), "mean_chi": round(float(means[i] / total), 4)}
+           for i, m in enumerate(G.LINEARITY_METHODS)}
+    res["face_sides"] = total
+    res["us_per_call"] = round(1e3 * e0.elapsed_time(e1) / reps, 2)
+    res["teno_ct"] = 1e-6
+    return res
+
+
 def cpu_baseline(W, dW, n, min_seconds=10.0):
     """The oracle timed on the host: whole S2O4 steps (2 stages each) of the
     same workload state, continued until at least min_seconds have passed."""
@@ -211,6 +238,8 @@ def forms_comparison(G, inputs, np, torch, seed, n=2048, steps=200, acc_steps=10
                      "gated_share": round((wk["normal_x"]["gated"] + wk["normal_y"]["gated"]) / sides, 4),
                      "queued_face_share": round(wk["slow"]["units"] / max(1, wk["slow"]["units"] + wk["faces_x"]["units"]
                                                                        + wk["faces_y"]["units"]), 4)}
+        if name == "fp64":
+            res[name]["linearity_after_run"] = linearity_shares(G, torch, grid, Wd, dWd, ws)
         if prec == G.MIXED:
             res[name]["eps_ulps"] = grid.params.eps_ulps
         if delta > 0:
@@ -432,6 +461,9 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "ms_per_step_with_kernel_events": round(ms_events / args.steps, 5) if ms_events else None,
+        # the paper's comparison of GENO with WENO-Z and TENO weights on the
+        # final state of the timed run (diagnostic, outside the timed region)
+        "linearity_after_run": linearity_shares(G, torch, grid, Wd, dWd, ws),
     }
     if not args.no_forms:
         del ws, Wd, dWd

@@ -206,6 +206,23 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
 int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
              geno_stats* stats, void* stream);
 
+/* The paper's comparison of nonlinear reconstructions (Sec. 5), on every
+ * face-side of direction dir, from the stencils of the normal step: the
+ * share of the high-order linear reconstruction each method keeps.
+ *   method 0: GENO, its path function chi (Eq. (4));
+ *   method 1: WENO-Z weights w~_k = d_k (1 + tau_Z / (IS_k + eps)) on the
+ *             three sub-stencils, tau_Z = |IS_1 - IS_3| (the outer two);
+ *   method 2: TENO weights: scale separation (1/(IS_k + eps))^7 normalised,
+ *             sub-stencils with a share <= teno_ct cut (the paper uses 1e-6,
+ *             1e-3 for its Titarev-Toro run);
+ * with chi = min_k w_k / d_k for WENO-Z and TENO (d_k the linear weights of
+ * geno_params normalised to sum 1; TENO's chi is 1 or 0).
+ * chi3 (device): [3][2][nvar][n0][n1] doubles, [method][side][var] planes in
+ * the face-row layout of geno_reconstruct's chi. Fills the ghost layers of
+ * W, dW like geno_reconstruct; ws: workspace of gks_workspace_bytes(g). */
+int geno_linearity(const geno_grid* g, void* W, void* dW, int dir, double* chi3, double teno_ct,
+                   void* ws, void* stream);
+
 /* Conserved totals (diagnostic): totals[f] = |cell| * sum over the interior
  * cells of W[f] for every field f (3 in 1-D, 4 in 2-D), |cell| = dx (1-D) or
  * dx dy (2-D). The update is in conservation form (Eq. (1)): on periodic

@@ -102,16 +102,35 @@ GENO_HD void linear_p7(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2, R& qH, R&
 // d_k/(IS_k + eps)^2 normalised (Eq. (8)), evaluated over a common
 // denominator. When chi == 1 exactly the low-order part carries weight 0 and
 // is not formed. Returns true on the low-order branch (chi < 1).
+// Coefficients B_k, C_k of the three sub-stencil quadratics of one side and
+// their indicators IS_k (Jiang-Shu form of Eq. (6) on cell j).
+template <typename D>
+struct SideQuads {
+  D B1, C1, B2, C2, B3, C3, IS1, IS2, IS3;
+};
+
+template <typename D>
+GENO_HD SideQuads<D> side_quads(D Qm, D Q0, D Q1, D Q2, D Gm) {
+  SideQuads<D> s;
+  s.B1 = D(2.0) * (Q0 - Qm) - Gm;
+  s.C1 = (Q0 - Qm) - Gm;
+  s.B2 = D(0.5) * (Q1 - Qm);
+  s.C2 = D(0.5) * (Q1 - D(2.0) * Q0 + Qm);
+  s.B3 = D(0.5) * (D(4.0) * Q1 - D(3.0) * Q0 - Q2);
+  s.C3 = D(0.5) * (Q0 - D(2.0) * Q1 + Q2);
+  const D c13 = D(13.0 / 3.0);
+  s.IS1 = s.B1 * s.B1 + c13 * (s.C1 * s.C1);
+  s.IS2 = s.B2 * s.B2 + c13 * (s.C2 * s.C2);
+  s.IS3 = s.B3 * s.B3 + c13 * (s.C3 * s.C3);
+  return s;
+}
+
 template <typename R, typename D>
 GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, const KParams& k, R& val,
                        R& hder, D& chi) {
-  const D Bd1 = D(2.0) * (Q0 - Qm) - Gm, Cd1 = (Q0 - Qm) - Gm;
-  const D Bd2 = D(0.5) * (Q1 - Qm), Cd2 = D(0.5) * (Q1 - D(2.0) * Q0 + Qm);
-  const D Bd3 = D(0.5) * (D(4.0) * Q1 - D(3.0) * Q0 - Q2), Cd3 = D(0.5) * (Q0 - D(2.0) * Q1 + Q2);
-  const D c13 = D(13.0 / 3.0);
-  const D IS1 = Bd1 * Bd1 + c13 * (Cd1 * Cd1);
-  const D IS2 = Bd2 * Bd2 + c13 * (Cd2 * Cd2);
-  const D IS3 = Bd3 * Bd3 + c13 * (Cd3 * Cd3);
+  const SideQuads<D> sq = side_quads<D>(Qm, Q0, Q1, Q2, Gm);
+  const D Bd1 = sq.B1, Cd1 = sq.C1, Bd2 = sq.B2, Cd2 = sq.C2, Bd3 = sq.B3, Cd3 = sq.C3;
+  const D IS1 = sq.IS1, IS2 = sq.IS2, IS3 = sq.IS3;
   const D ISH = fmax(IS1, fmax(IS2, IS3));
   const D ISL = fmin(IS1, fmin(IS2, IS3));
   const D IStau = fabs(0.5 * (IS2 + IS3) - IS1);
@@ -173,6 +192,45 @@ GENO_HD int geno_face(D Qm, D Q0, D Q1, D Q2, D Gm, D G0, D G1, D G2, const KPar
     dr = -dm;
   }
   return n;
+}
+
+// The paper's comparison (Sec. 5): the share of the linear reconstruction
+// that WENO-Z and TENO weights on the same three sub-stencils keep,
+// chi = min_k w_k / d_k, d_k the linear weights normalised to sum 1.
+// WENO-Z: w~_k = d_k (1 + tau_Z / (IS_k + eps)), tau_Z = |IS_1 - IS_3| (the
+// two outer sub-stencils).
+template <typename D>
+GENO_HD D wenoz_chi(D IS1, D IS2, D IS3, const KParams& k) {
+  const D dsum = D(k.d1) + D(k.d2) + D(k.d3);
+  const D d[3] = {D(k.d1) / dsum, D(k.d2) / dsum, D(k.d3) / dsum};
+  const D IS[3] = {IS1, IS2, IS3};
+  const D tz = fabs(IS1 - IS3);
+  D w[3], ws = D(0.0);
+  for (int q = 0; q < 3; ++q) {
+    w[q] = d[q] * (D(1.0) + tz / (IS[q] + D(k.eps)));
+    ws = ws + w[q];
+  }
+  D chi = (w[0] / ws) / d[0];
+  for (int q = 1; q < 3; ++q) chi = fmin(chi, (w[q] / ws) / d[q]);
+  return chi;
+}
+
+// TENO: scale separation gamma_k = (1/(IS_k + eps))^7 normalised; a
+// sub-stencil with gamma_k <= ct is cut (weight 0), the others keep their
+// linear weights renormalised. chi is 1 when none is cut, else 0.
+template <typename D>
+GENO_HD D teno_chi(D IS1, D IS2, D IS3, D ct, const KParams& k) {
+  const D IS[3] = {IS1, IS2, IS3};
+  D g[3], gs = D(0.0);
+  for (int q = 0; q < 3; ++q) {
+    const D x = D(1.0) / (IS[q] + D(k.eps));
+    const D x2 = x * x;
+    g[q] = x2 * x2 * x2 * x;
+    gs = gs + g[q];
+  }
+  for (int q = 0; q < 3; ++q)
+    if (!(g[q] / gs > ct)) return D(0.0);
+  return D(1.0);
 }
 
 // Gauss points of a face: +-1/(2 sqrt 3) of its length about its centre.

@@ -396,6 +396,52 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                       gate);
 }
 
+// The paper's comparison of the nonlinear weights at every face-side of a
+// direction, from the same stencils as the normal step: chi of GENO (its
+// path function), of WENO-Z and of TENO (geno_device.hpp). One thread per
+// (variable, face-row entry) as in normal_body; 1-D uses the x-direction
+// indexing on its single row. out: [method][side][var][a][b], method 0 GENO,
+// 1 WENO-Z, 2 TENO.
+template <int DIR, typename T>
+__global__ void __launch_bounds__(BLOCK) k_linearity(Geo g, geno::KParams k, int ndim,
+                                                     const double* __restrict__ W,
+                                                     const T* __restrict__ dW,
+                                                     double* __restrict__ out, double ct) {
+  const int nv = ndim == 2 ? 4 : 3;
+  const int n1 = DIR == 0 ? g.nx + 1 : g.nx + 2;
+  const int n0 = ndim == 1 ? 1 : (DIR == 0 ? g.ny + 2 : g.ny + 1);
+  const int plane = n0 * n1;
+  const int t = xcd_block() * (int)blockDim.x + (int)threadIdx.x;
+  if (t >= nv * plane) return;
+  const int v = t / plane, o = t - v * plane;
+  const int a = o / n1, b = o - a * n1;
+  const double h = DIR == 0 ? g.dx : g.dy;
+  double Q[4], G[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    size_t id;
+    if (DIR == 0) id = at(g, v, ndim == 1 ? 0 : a - 1, b - 2 + m);
+    else id = at(g, v, a - 2 + m, b - 1);
+    Q[m] = W[id];
+    G[m] = h * (double)dW[id + (size_t)(DIR * nv) * g.rows * g.pitch];
+  }
+  const size_t mplane = (size_t)2 * nv * plane;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    // the right state is the left-state formula on the data mirrored about the face
+    const geno::SideQuads<double> sq =
+        side == 0 ? geno::side_quads<double>(Q[0], Q[1], Q[2], Q[3], G[0])
+                  : geno::side_quads<double>(Q[3], Q[2], Q[1], Q[0], -G[3]);
+    const double ISH = fmax(sq.IS1, fmax(sq.IS2, sq.IS3));
+    const double ISL = fmin(sq.IS1, fmin(sq.IS2, sq.IS3));
+    const double IStau = fabs(0.5 * (sq.IS2 + sq.IS3) - sq.IS1);
+    const size_t e = ((size_t)side * nv + v) * plane + o;
+    out[0 * mplane + e] = geno::path_chi<double>(IStau, ISH, ISL, k.eps, k);
+    out[1 * mplane + e] = geno::wenoz_chi<double>(sq.IS1, sq.IS2, sq.IS3, k);
+    out[2 * mplane + e] = geno::teno_chi<double>(sq.IS1, sq.IS2, sq.IS3, ct, k);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Faces (2-D), two lanes per face: lane q owns Gauss point q and computes the
 // tangential step of side q for both points; the halves are exchanged with
@@ -2163,6 +2209,45 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
     if (h.nonfinite)
       return fail(GENO_ENONPHYS, "%llu non-physical cells (non-finite, rho <= 0 or p <= 0)",
                   h.nonfinite);
+  }
+  return GENO_OK;
+}
+
+int geno_linearity(const geno_grid* g, void* W, void* dW, int dir, double* chi3, double teno_ct,
+                   void* ws, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!W || !dW || !chi3 || !ws) return fail(GENO_EINVAL, "null pointer");
+  if (dir != 0 && !(g->ndim == 2 && dir == 1)) return fail(GENO_EINVAL, "bad direction %d", dir);
+  if (!(teno_ct > 0.0 && teno_ct < 1.0)) return fail(GENO_EINVAL, "teno_ct must be in (0, 1)");
+  hipStream_t s = (hipStream_t)stream;
+  const Geo geo = geo_of(g);
+  const geno::KParams k = kparams(g);
+  const Layout L = layout_of(g);
+  const int nv = g->ndim == 2 ? 4 : 3;
+  const size_t n1 = dir == 0 ? g->nx + 1 : g->nx + 2;
+  const size_t n0 = g->ndim == 1 ? 1 : (dir == 0 ? g->ny + 2 : g->ny + 1);
+  const unsigned nb = nblocks((size_t)nv * n0 * n1);
+  if (g->params.precision == GENO_MIXED) {
+    const Bufs<float> B = bufs_of<float>((char*)ws, L, g->ndim);
+    rc = launch_init<float>(g, geo, k.gamma, (double*)W, (float*)dW, B, s);
+    if (rc) return rc;
+    if (dir == 0)
+      HIP_TRY(launch(-1, k_linearity<0, float>, nb, s, geo, k, g->ndim, (const double*)W,
+                     (const float*)dW, chi3, teno_ct));
+    else
+      HIP_TRY(launch(-1, k_linearity<1, float>, nb, s, geo, k, g->ndim, (const double*)W,
+                     (const float*)dW, chi3, teno_ct));
+  } else {
+    const Bufs<double> B = bufs_of<double>((char*)ws, L, g->ndim);
+    rc = launch_init<double>(g, geo, k.gamma, (double*)W, (double*)dW, B, s);
+    if (rc) return rc;
+    if (dir == 0)
+      HIP_TRY(launch(-1, k_linearity<0, double>, nb, s, geo, k, g->ndim, (const double*)W,
+                     (const double*)dW, chi3, teno_ct));
+    else
+      HIP_TRY(launch(-1, k_linearity<1, double>, nb, s, geo, k, g->ndim, (const double*)W,
+                     (const double*)dW, chi3, teno_ct));
   }
   return GENO_OK;
 }

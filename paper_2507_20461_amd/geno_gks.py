@@ -58,7 +58,7 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_kernel_name", "geno_tuning_default", "gks_batched_workspace_bytes", "gks_step_batched",
            "geno_autotune_batched", "geno_harvest", "geno_mlp_train_workspace_bytes", "geno_mlp_grad",
            "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob",
-           "geno_conserved_totals")
+           "geno_conserved_totals", "geno_linearity")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d",
            "gate", "normal_xy")
 WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard", "gated")
@@ -122,8 +122,9 @@ def lib():
         L.geno_mlp_infer.argtypes = [vp, i, vp, vp]
         L.geno_gate_prob.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, vp, vp]
         L.geno_conserved_totals.argtypes = [ctypes.POINTER(geno_grid), vp, vp, vp]
+        L.geno_linearity.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, d, vp, vp]
         for name in ("geno_harvest", "geno_mlp_grad", "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load",
-                     "geno_mlp_infer", "geno_gate_prob", "geno_conserved_totals"):
+                     "geno_mlp_infer", "geno_gate_prob", "geno_conserved_totals", "geno_linearity"):
             getattr(L, name).restype = i
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
                      "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
@@ -278,6 +279,22 @@ def gks_step(grid, W, dW, ws, nsteps, dt_out=None, stats=False, stream=None):
                         ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc)
     return st
+
+
+LINEARITY_METHODS = ("geno", "weno_z", "teno")
+
+
+def linearity(grid, W, dW, direction, ws, teno_ct=1e-6, out=None, stream=None):
+    """chi of GENO, WENO-Z and TENO at every face-side of a direction:
+    device float64 tensor [3][2][nvar][n0][n1] (layout of geno_reconstruct's chi)."""
+    _check_state(grid, W, dW, ws)
+    shape = (3,) + tuple(grid.chi_shape(direction))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=W.device)
+    _need(out, torch.float64, _prod(shape), "chi3")
+    _check(lib().geno_linearity(ctypes.byref(grid.g), _ptr(W), _ptr(dW), int(direction), _ptr(out),
+                                float(teno_ct), _ptr(ws), _stream(stream)))
+    return out
 
 
 def conserved_totals(grid, W, out=None, stream=None):

@@ -403,3 +403,36 @@ def test_zero_steps_leave_the_state(G):
     st = G.gks_step(grid, Wd, dWd, grid.workspace(), 0, stats=True)
     assert st.nonfinite == 0 and st.guard == 0
     assert np.array_equal(grid.interior(Wd), W) and np.array_equal(grid.interior(dWd), dW)
+
+
+# ------------------------------------------------------------------ weight comparison
+@pytest.mark.parametrize("ct", [1e-6, 1e-3])
+@pytest.mark.parametrize("kind,bc,direction", [("quadrants", 1, 0), ("quadrants", 1, 1), ("vortex", 1, 0),
+                                               ("smooth", 0, 1)])
+def test_linearity_2d_matches_oracle(G, oracle, kind, bc, direction, ct):
+    # chi of GENO, WENO-Z and TENO per face-side against the oracle. The two
+    # continuous measures depend on differences of indicators (IS^tau, and
+    # tau_Z = |IS_1 - IS_3|) relative to IS_k + eps; their rounding, ~1e-16
+    # IS^H, can reach 1e-10 of IS^L + eps where IS^H / IS^L is large (the same
+    # bound as chi in test_reconstruct_2d): 1e-8. TENO's cut decisions exactly.
+    _say("linearity", kind, bc, direction, ct)
+    W, dW = _case_2d(kind, 40, 36, 4)
+    grid = _grid(G, W, bc)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    got = G.linearity(grid, Wd, dWd, direction, grid.workspace(), teno_ct=ct).cpu().numpy()
+    ref = oracle.linearity_faces(_oprm(oracle, 2, bc), W, dW, direction, ct=ct, dx=grid.dx, dy=grid.dy)
+    e = (np.abs(got[0] - ref[0]).max(), np.abs(got[1] - ref[1]).max(), int((got[2] != ref[2]).sum()))
+    share = [float((ref[m] >= 0.999).mean()) for m in range(3)]
+    _say("  GENO %.2e WENO-Z %.2e TENO mismatches %d; linear shares GENO %.3f WENO-Z %.3f TENO %.3f" % (*e, *share))
+    assert e[0] < 1e-8 and e[1] < 1e-8 and e[2] == 0, e
+
+
+@pytest.mark.parametrize("name,seed", [("sine", None), ("jump", 2)])
+def test_linearity_1d_matches_oracle(G, oracle, name, seed):
+    W, dW, bc = _case_1d(name, seed)
+    grid = _grid(G, W, bc)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    got = G.linearity(grid, Wd, dWd, 0, grid.workspace()).cpu().numpy()
+    ref = oracle.linearity_faces(_oprm(oracle, 1, bc), W, dW, 0, dx=grid.dx)
+    assert np.abs(got[0] - ref[0]).max() < 1e-8 and np.abs(got[1] - ref[1]).max() < 1e-8
+    assert (got[2] == ref[2]).all()
