@@ -48,7 +48,7 @@ enum {
 
 typedef struct {
   double gamma, Cpath, eps, r, rL, d[3], tc1, tc2, cfl;
-  int bc[4];           /* 0 periodic, 1 transmissive: x-lo, x-hi, y-lo, y-hi */
+  int bc[4];           /* 0 periodic, 1 transmissive, 2 reflecting: x-lo, x-hi, y-lo, y-hi */
   int ndim, nx, ny;
   double dx, dy;
   double K;            /* internal degrees of freedom of the BGK model */
@@ -354,6 +354,12 @@ static void gstate_load(const ocfg *P, gstate *g, const double *W, const double 
  * that boundary = 0, tangential gradient = nearest interior cell.
  * 2-D: x-ghosts of the interior rows first, then y-ghosts of every column,
  * which fills the corners. */
+/* Boundary codes: 0 periodic, 1 transmissive (nearest interior cell, zero
+ * normal derivative), 2 reflecting wall (mirror image: the normal momentum
+ * changes sign; a derivative normal to the wall changes sign unless its
+ * field does, a tangential one changes sign with its field). */
+static double wall_sign_w(int f, int m) { return f == m ? -1.0 : 1.0; }
+
 static void fill_ghosts(const ocfg *P, gstate *g) {
   int nv = P->nv, nx = P->nx, ny = P->ny;
   int oy = (P->ndim == 1) ? 0 : NG;
@@ -362,18 +368,20 @@ static void fill_ghosts(const ocfg *P, gstate *g) {
     for (int gl = 1; gl <= NG; ++gl) {
       int il = NG - gl, ih = NG + nx - 1 + gl;          /* ghost columns */
       int sl, sh;
-      if (P->bc[0] == 0) sl = NG + nx - gl; else sl = NG;
-      if (P->bc[1] == 0) sh = NG + gl - 1; else sh = NG + nx - 1;
+      if (P->bc[0] == 0) sl = NG + nx - gl; else if (P->bc[0] == 2) sl = NG + gl - 1; else sl = NG;
+      if (P->bc[1] == 0) sh = NG + gl - 1; else if (P->bc[1] == 2) sh = NG + nx - gl; else sh = NG + nx - 1;
       for (int f = 0; f < nv; ++f) {
-        g->W[gidx(g, f, j, il)] = g->W[gidx(g, f, j, sl)];
-        g->W[gidx(g, f, j, ih)] = g->W[gidx(g, f, j, sh)];
+        g->W[gidx(g, f, j, il)] = (P->bc[0] == 2 ? wall_sign_w(f, 1) : 1.0) * g->W[gidx(g, f, j, sl)];
+        g->W[gidx(g, f, j, ih)] = (P->bc[1] == 2 ? wall_sign_w(f, 1) : 1.0) * g->W[gidx(g, f, j, sh)];
       }
       for (int d = 0; d < P->ndim; ++d)
         for (int f = 0; f < nv; ++f) {
           int ff = d * nv + f;
           double vl = g->dW[gidx(g, ff, j, sl)], vh = g->dW[gidx(g, ff, j, sh)];
-          if (d == 0 && P->bc[0] != 0) vl = 0.0;
-          if (d == 0 && P->bc[1] != 0) vh = 0.0;
+          if (d == 0 && P->bc[0] == 1) vl = 0.0;
+          if (d == 0 && P->bc[1] == 1) vh = 0.0;
+          if (P->bc[0] == 2) vl *= wall_sign_w(f, 1) * (d == 0 ? -1.0 : 1.0);
+          if (P->bc[1] == 2) vh *= wall_sign_w(f, 1) * (d == 0 ? -1.0 : 1.0);
           g->dW[gidx(g, ff, j, il)] = vl;
           g->dW[gidx(g, ff, j, ih)] = vh;
         }
@@ -384,18 +392,20 @@ static void fill_ghosts(const ocfg *P, gstate *g) {
     for (int gl = 1; gl <= NG; ++gl) {
       int jl = NG - gl, jh = NG + ny - 1 + gl;
       int sl, sh;
-      if (P->bc[2] == 0) sl = NG + ny - gl; else sl = NG;
-      if (P->bc[3] == 0) sh = NG + gl - 1; else sh = NG + ny - 1;
+      if (P->bc[2] == 0) sl = NG + ny - gl; else if (P->bc[2] == 2) sl = NG + gl - 1; else sl = NG;
+      if (P->bc[3] == 0) sh = NG + gl - 1; else if (P->bc[3] == 2) sh = NG + ny - gl; else sh = NG + ny - 1;
       for (int f = 0; f < nv; ++f) {
-        g->W[gidx(g, f, jl, i)] = g->W[gidx(g, f, sl, i)];
-        g->W[gidx(g, f, jh, i)] = g->W[gidx(g, f, sh, i)];
+        g->W[gidx(g, f, jl, i)] = (P->bc[2] == 2 ? wall_sign_w(f, 2) : 1.0) * g->W[gidx(g, f, sl, i)];
+        g->W[gidx(g, f, jh, i)] = (P->bc[3] == 2 ? wall_sign_w(f, 2) : 1.0) * g->W[gidx(g, f, sh, i)];
       }
       for (int d = 0; d < 2; ++d)
         for (int f = 0; f < nv; ++f) {
           int ff = d * nv + f;
           double vl = g->dW[gidx(g, ff, sl, i)], vh = g->dW[gidx(g, ff, sh, i)];
-          if (d == 1 && P->bc[2] != 0) vl = 0.0;
-          if (d == 1 && P->bc[3] != 0) vh = 0.0;
+          if (d == 1 && P->bc[2] == 1) vl = 0.0;
+          if (d == 1 && P->bc[3] == 1) vh = 0.0;
+          if (P->bc[2] == 2) vl *= wall_sign_w(f, 2) * (d == 1 ? -1.0 : 1.0);
+          if (P->bc[3] == 2) vh *= wall_sign_w(f, 2) * (d == 1 ? -1.0 : 1.0);
           g->dW[gidx(g, ff, jl, i)] = vl;
           g->dW[gidx(g, ff, jh, i)] = vh;
         }

@@ -24,7 +24,7 @@ _lib = None
 P_GAMMA, P_CPATH, P_EPS, P_R, P_RL, P_D1, P_D2, P_D3, P_TAUC1, P_TAUC2, P_CFL = range(11)
 P_BC = 11  # four boundary codes follow: x-lo, x-hi, y-lo, y-hi (0 periodic, 1 transmissive)
 N_PARAMS = 15
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
