@@ -53,6 +53,7 @@ extern "C" {
 /* boundary conditions (per side) */
 #define GENO_BC_PERIODIC 0
 #define GENO_BC_TRANSMISSIVE 1
+#define GENO_BC_REFLECTING 2   /* wall: mirror image, normal momentum negated */
 
 /* arithmetic of the reconstruction and the flux */
 #define GENO_F64 0     /* everything in float64 */

@@ -168,13 +168,48 @@ __device__ __forceinline__ double dt_of(const Ctrl* c) { return c->dt; }
 // ---------------------------------------------------------------------------
 // Ghost cells. Periodic: copy of the periodic image (values and gradients).
 // Transmissive: nearest interior cell, gradient normal to that boundary = 0.
-// A corner takes both rules (the same as filling x-ghosts of the interior rows
-// and then y-ghosts of every column). Every interior cell writes the ghost
-// cells whose source it is.
+// Reflecting wall: mirror image (ghost -1 of cell 0, -2 of cell 1): the
+// normal momentum changes sign; a derivative normal to the wall changes sign
+// unless its field is the normal momentum, a tangential one changes sign with
+// its field. A corner takes both rules (the same as filling x-ghosts of the
+// interior rows and then y-ghosts of every column). Every interior cell
+// writes the ghost cells whose source it is.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int ghost_src(int gi, int n, bool per) {
-  if (gi < 0) return per ? gi + n : 0;
-  return per ? gi - n : n - 1;
+__device__ __forceinline__ int ghost_src(int gi, int n, int bc_lo, int bc_hi) {
+  if (gi < 0) {
+    if (bc_lo == GENO_BC_PERIODIC) return gi + n;
+    return bc_lo == GENO_BC_REFLECTING ? -gi - 1 : 0;
+  }
+  if (bc_hi == GENO_BC_PERIODIC) return gi - n;
+  return bc_hi == GENO_BC_REFLECTING ? 2 * n - 1 - gi : n - 1;
+}
+
+// The boundary rule of one side applied to a copied state: axis 0 (x) or 1
+// (y); w, dx, dy: values and the x and y derivatives (dy unused in 1-D).
+template <int NV, typename T>
+__device__ __forceinline__ void ghost_rule(int bc, int axis, double* w, T* dx, T* dy) {
+  if (bc == GENO_BC_TRANSMISSIVE) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (axis == 0) dx[v] = T(0);
+      else dy[v] = T(0);
+    }
+  } else if (bc == GENO_BC_REFLECTING) {
+    const int m = 1 + axis;   // normal momentum
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const bool odd = v == m;
+      if (odd) w[v] = -w[v];
+      // normal derivative: sign of the field times -1; tangential: the field's sign
+      if (axis == 0) {
+        if (!odd) dx[v] = -dx[v];
+        if constexpr (NV == 4) if (odd) dy[v] = -dy[v];
+      } else {
+        if (!odd) dy[v] = -dy[v];
+        if (odd) dx[v] = -dx[v];
+      }
+    }
+  }
 }
 
 template <int NDIM, typename T>
@@ -182,16 +217,14 @@ __device__ __forceinline__ void scatter_ghosts(const Geo& g, double* __restrict_
                                                T* __restrict__ dW, int j, int i, const double* w,
                                                const T* dw) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
-  const bool px = g.bc[0] == GENO_BC_PERIODIC;
-  const bool py = NDIM == 2 && g.bc[2] == GENO_BC_PERIODIC;
   // ghost columns / rows whose source is this cell, as bit masks
   const int cx[4] = {-2, -1, g.nx, g.nx + 1};
   const int cy[4] = {-2, -1, g.ny, g.ny + 1};
   unsigned mx = 0, my = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (ghost_src(cx[q], g.nx, px) == i) mx |= 1u << q;
-    if (NDIM == 2 && ghost_src(cy[q], g.ny, py) == j) my |= 1u << q;
+    if (ghost_src(cx[q], g.nx, g.bc[0], g.bc[1]) == i) mx |= 1u << q;
+    if (NDIM == 2 && ghost_src(cy[q], g.ny, g.bc[2], g.bc[3]) == j) my |= 1u << q;
   }
   if (!mx && !my) return;
   // index 4 stands for the cell's own row / column
@@ -203,13 +236,21 @@ __device__ __forceinline__ void scatter_ghosts(const Geo& g, double* __restrict_
     for (int b = 0; b < 5; ++b) {
       if ((b < 4 && !((mx >> b) & 1u)) || (a == 4 && b == 4)) continue;
       const int ii = b == 4 ? i : cx[b];
-      const bool zx = b < 4 && !px;   // zero d/dx at transmissive x-ghosts
-      const bool zy = a < 4 && !py;   // zero d/dy at transmissive y-ghosts
+      double wg[NV];
+      T gx[NV], gy[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        W[at(g, v, jj, ii)] = w[v];
-        dW[at(g, v, jj, ii)] = zx ? T(0) : dw[v];
-        if constexpr (NDIM == 2) dW[at(g, NV + v, jj, ii)] = zy ? T(0) : dw[NV + v];
+        wg[v] = w[v];
+        gx[v] = dw[v];
+        gy[v] = NDIM == 2 ? dw[NV + v] : T(0);
+      }
+      if (b < 4) ghost_rule<NV, T>(g.bc[b < 2 ? 0 : 1], 0, wg, gx, gy);
+      if (a < 4) ghost_rule<NV, T>(g.bc[a < 2 ? 2 : 3], 1, wg, gx, gy);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        W[at(g, v, jj, ii)] = wg[v];
+        dW[at(g, v, jj, ii)] = gx[v];
+        if constexpr (NDIM == 2) dW[at(g, NV + v, jj, ii)] = gy[v];
       }
     }
   }
@@ -1394,7 +1435,8 @@ int check_params(const geno_params* p) {
   if (!(p->tau_c1 >= 0.0) || !(p->tau_c2 >= 0.0))
     return fail(GENO_EINVAL, "tau coefficients must be >= 0");
   for (int i = 0; i < 4; ++i)
-    if (p->bc[i] != GENO_BC_PERIODIC && p->bc[i] != GENO_BC_TRANSMISSIVE)
+    if (p->bc[i] != GENO_BC_PERIODIC && p->bc[i] != GENO_BC_TRANSMISSIVE &&
+        p->bc[i] != GENO_BC_REFLECTING)
       return fail(GENO_EINVAL, "bad boundary code %d", p->bc[i]);
   if ((p->bc[0] == GENO_BC_PERIODIC) != (p->bc[1] == GENO_BC_PERIODIC) ||
       (p->bc[2] == GENO_BC_PERIODIC) != (p->bc[3] == GENO_BC_PERIODIC))
@@ -1411,10 +1453,13 @@ int check_grid(const geno_grid* g) {
     return fail(GENO_EINVAL, "bad grid size");
   if (g->pitch < g->nx + 2 * NG || g->rows != (g->ndim == 2 ? g->ny + 2 * NG : 1))
     return fail(GENO_EINVAL, "grid pitch/rows inconsistent (use geno_grid_init)");
-  // periodic images must exist: 2 ghost layers need at least 2 cells
-  if ((g->params.bc[0] == GENO_BC_PERIODIC && g->nx < NG) ||
-      (g->ndim == 2 && g->params.bc[2] == GENO_BC_PERIODIC && g->ny < NG))
-    return fail(GENO_EINVAL, "periodic axis needs at least %d cells", NG);
+  // periodic and mirror images must exist: 2 ghost layers need 2 cells
+  const auto imaged = [&](int side) {
+    return g->params.bc[side] == GENO_BC_PERIODIC || g->params.bc[side] == GENO_BC_REFLECTING;
+  };
+  if (((imaged(0) || imaged(1)) && g->nx < NG) ||
+      (g->ndim == 2 && (imaged(2) || imaged(3)) && g->ny < NG))
+    return fail(GENO_EINVAL, "periodic or reflecting axis needs at least %d cells", NG);
   // 32-bit thread indexing: two lanes per face and 16 face-row planes
   if ((size_t)(g->nx + 4) * (g->ny + 4) * 16 > (size_t)0x7fffffff)
     return fail(GENO_EINVAL, "grid too large for 32-bit thread indexing");

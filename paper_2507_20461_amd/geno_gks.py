@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
-BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING = 0, 1, 2
 F64, MIXED = 0, 1
 ABI_VERSION = 1
 NG = 2

@@ -436,3 +436,28 @@ def test_linearity_1d_matches_oracle(G, oracle, name, seed):
     ref = oracle.linearity_faces(_oprm(oracle, 1, bc), W, dW, 0, dx=grid.dx)
     assert np.abs(got[0] - ref[0]).max() < 1e-8 and np.abs(got[1] - ref[1]).max() < 1e-8
     assert (got[2] == ref[2]).all()
+
+
+# ------------------------------------------------------------------ reflecting walls
+def test_step_reflecting_1d(G, oracle):
+    W, dW, _ = inputs.jump_1d(200, 3)
+    Ws, dWs = inputs.sine_1d(200)
+    W, dW = W + 0.1 * Ws, dW + 0.1 * dWs
+    # every GPU step against the oracle's step from the same state (a long
+    # trajectory across the jumps amplifies rounding beyond the bound)
+    bc = [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2
+    grid = G.Grid(1, 200, 1, bc=bc)
+    worst, _, _ = _shadow(G, oracle, grid, W, dW, 40, bc)
+    assert max(worst) < TOL, worst
+
+
+@pytest.mark.parametrize("bcs", [(2, 2, 1, 1), (2, 2, 2, 2), (1, 2, 2, 1)])
+def test_step_reflecting_2d(G, oracle, bcs):
+    _say("reflecting 2-D", bcs)
+    W, dW = _case_2d("quadrants", 40, 36, 6)
+    grid = G.Grid(2, 40, 36, bc=list(bcs))
+    gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 8)
+    oW, odW, odt, og = oracle.step(oracle.params(ndim=2, bc=list(bcs)), W, dW, 8, dx=grid.dx, dy=grid.dy)
+    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
+    _say("  W %.2e dW %.2e dt %.2e" % e)
+    assert gg.guard == og and max(e) < TOL, e
