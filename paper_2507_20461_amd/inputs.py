@@ -19,6 +19,11 @@ recipes are synthetic stand-ins for throughput measurement):
 * ``vortex_2d``: ``quadrants_2d`` plus a smooth vortex perturbation of the
   velocity.
 * ``batched_grids``: many independent quadrant grids of seeded sizes.
+* ``blast_wave_1d``: the Woodward-Colella interacting blast waves on [0, 1]
+  with reflecting walls (p = 1000 | 0.01 | 100, rho = 1, u = 0).
+* ``shu_osher_1d``: a Mach-3 shock running into the density wave
+  rho = 1 + 0.2 sin(5 x) on [-5, 5] (transmissive).
+  Both are the analytic robustness problems of the paper's Sec. 6.2.
 """
 from __future__ import annotations
 
@@ -211,3 +216,48 @@ def random_smooth_2d(nx: int, ny: int, seed: int, gamma: float = GAMMA, modes: i
         dW[0:4] += 0.5 * wa * (cons_at(xl + hx, ys) - cons_at(xl, ys)) / hx
         dW[4:8] += 0.5 * wa * (cons_at(xs, yl + hy) - cons_at(xs, yl)) / hy
     return W, dW
+
+
+def blast_wave_1d(nx: int, gamma: float = GAMMA):
+    """Woodward-Colella blast waves on [0, 1]: rho = 1, u = 0 and p = 1000 on
+    x < 0.1, 0.01 on 0.1 < x < 0.9, 100 on x > 0.9. The jumps sit on cell
+    faces when nx is a multiple of 10; cells are then constant and their
+    averaged gradients zero. End time 0.038."""
+    if nx % 10:
+        raise ValueError("nx must be a multiple of 10 (jumps on faces)")
+    xc = (np.arange(nx) + 0.5) / nx
+    p = np.where(xc < 0.1, 1000.0, np.where(xc > 0.9, 100.0, 0.01))
+    rho = np.ones(nx)
+    u = np.zeros(nx)
+    W = _cons_1d(rho, u, p, gamma)[:, None, :]
+    return W, np.zeros_like(W)
+
+
+SHU_OSHER_LEFT = (3.857143, 2.629369, 10.33333)   # (rho, u, p) behind the shock
+
+
+def shu_osher_1d(nx: int, gamma: float = GAMMA):
+    """Shu-Osher problem on [-5, 5]: (rho, u, p) = SHU_OSHER_LEFT on x < -4,
+    rho = 1 + 0.2 sin(5 x), u = 0, p = 1 on x > -4. Exact cell averages of the
+    density wave (analytic integral) and exact averaged gradients (Gauss
+    theorem: face values over h); the jump sits on a face when nx is a
+    multiple of 10. End time 1.8."""
+    if nx % 10:
+        raise ValueError("nx must be a multiple of 10 (jump on a face)")
+    h = 10.0 / nx
+    xl = -5.0 + np.arange(nx) * h
+    xr = xl + h
+    left = xr <= -4.0 + 1e-12
+    # density average of 1 + 0.2 sin(5x) over [xl, xr] and its face values
+    rho_avg = 1.0 + 0.2 * (np.cos(5.0 * xl) - np.cos(5.0 * xr)) / (5.0 * h)
+    rho_grad = 0.2 * (np.sin(5.0 * xr) - np.sin(5.0 * xl)) / h
+    rl, ul, pl = SHU_OSHER_LEFT
+    rho = np.where(left, rl, rho_avg)
+    u = np.where(left, ul, 0.0)
+    p = np.where(left, pl, 1.0)
+    W = _cons_1d(rho, u, p, gamma)
+    # u = 0 and p = 1 on the right: d(rho E)/dx = 0, d(rho u)/dx = 0; the
+    # left state is constant
+    dW = np.zeros_like(W)
+    dW[0] = np.where(left, 0.0, rho_grad)
+    return W[:, None, :], dW[:, None, :]

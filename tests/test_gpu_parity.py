@@ -461,3 +461,60 @@ def test_step_reflecting_2d(G, oracle, bcs):
     e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
     _say("  W %.2e dW %.2e dt %.2e" % e)
     assert gg.guard == og and max(e) < TOL, e
+
+
+# ------------------------------------------------------------------ robustness problems
+def _run_to(G, grid, W, dW, t_end, max_steps=20000):
+    """Steps until the accumulated time reaches t_end (the last step may pass
+    it by less than one step); returns the state, steps, time, guard count."""
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t, n, guard = 0.0, 0, 0
+    while t < t_end and n < max_steps:
+        st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        assert st.nonfinite == 0, (n, t)
+        t += float(dts.item())
+        n += 1
+        guard += st.guard
+    return grid.interior(Wd), n, t, guard
+
+
+@pytest.mark.parametrize("problem", ["blast", "shu_osher"])
+def test_robustness_problem_shadowed(G, oracle, problem):
+    # the paper's strong-shock problems: every GPU step of the first 40
+    # against the oracle's step from the same state
+    _say("robustness shadow", problem)
+    if problem == "blast":
+        W, dW = inputs.blast_wave_1d(400)
+        bc, x0, x1 = [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2, 0.0, 1.0
+    else:
+        W, dW = inputs.shu_osher_1d(400)
+        bc, x0, x1 = G.BC_TRANSMISSIVE, -5.0, 5.0
+    grid = G.Grid(1, 400, 1, x0=x0, x1=x1, bc=bc)
+    worst, _, _ = _shadow(G, oracle, grid, W, dW, 40, bc)
+    assert max(worst) < TOL, worst
+
+
+def test_blast_wave_full_run(G):
+    # to the paper's end time 0.038: finite and physical throughout, and mass
+    # and energy kept by the reflecting walls to rounding. With the
+    # component-wise reconstruction and CFL 0.5 the scheme loses positivity
+    # at t ~ 0.0016 (the oracle as well); CFL 0.2 runs through.
+    W, dW = inputs.blast_wave_1d(400)
+    grid = G.Grid(1, 400, 1, bc=[G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2, cfl=0.2)
+    Wn, n, t, guard = _run_to(G, grid, W, dW, 0.038)
+    _say("blast wave: %d steps to t = %.5f, guard %d, rho in [%.4f, %.4f]" % (n, t, guard, Wn[0].min(), Wn[0].max()))
+    assert Wn[0].min() > 0
+    for k in (0, 2):
+        assert abs(math.fsum(Wn[k].ravel()) - math.fsum(W[k].ravel())) <= 1e-12 * math.fsum(np.abs(W[k]).ravel())
+
+
+def test_shu_osher_full_run(G):
+    # to t = 1.8: finite and physical, and the shocked density wave reaches
+    # the compressed level behind the shock (rho > 3.5 somewhere behind it)
+    W, dW = inputs.shu_osher_1d(400)
+    grid = G.Grid(1, 400, 1, x0=-5.0, x1=5.0, bc=G.BC_TRANSMISSIVE)
+    Wn, n, t, guard = _run_to(G, grid, W, dW, 1.8)
+    _say("Shu-Osher: %d steps to t = %.4f, guard %d, rho in [%.4f, %.4f]" % (n, t, guard, Wn[0].min(), Wn[0].max()))
+    assert Wn[0].min() > 0 and Wn[0].max() > 3.5
