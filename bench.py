@@ -127,6 +127,46 @@ def linearity_shares(G, torch, grid, Wd, dWd, ws, reps=5):
     return res
 
 
+def robustness_runs(G, inputs, np, torch):
+    """The paper's strong-shock problems from analytic data, 400 cells, run
+    step by step to their end times: steps, guard events, density range,
+    mass / energy drift (reflecting walls keep both), wall time; a run that
+    loses positivity reports where."""
+    cases = [("blast_wave", inputs.blast_wave_1d, 0.038, (0.0, 1.0), [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2,
+              [(0.5, 0.0), (0.5, 0.001), (0.2, 0.0)]),
+             ("shu_osher", inputs.shu_osher_1d, 1.8, (-5.0, 5.0), G.BC_TRANSMISSIVE, [(0.5, 0.0)])]
+    out = {}
+    for name, make, t_end, (x0, x1), bc, settings in cases:
+        W, dW = make(400)
+        for cfl, c1 in settings:
+            grid = G.Grid(1, 400, 1, x0=x0, x1=x1, bc=bc, cfl=cfl, tau_c1=c1)
+            Wd, dWd = grid.to_device(W), grid.to_device(dW)
+            ws = grid.workspace()
+            dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+            t, n, guard, failed = 0.0, 0, 0, None
+            t0 = time.perf_counter()
+            while t < t_end and n < 20000:
+                try:
+                    st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+                except G.GenoError as e:
+                    failed = "step %d, t = %.5f: %s" % (n + 1, t, e)
+                    break
+                t += float(dts.item())
+                n += 1
+                guard += st.guard
+            wall = time.perf_counter() - t0
+            Wn = grid.interior(Wd)
+            rec = {"cfl": cfl, "tau_c1": c1, "steps": n, "t": round(t, 6), "guard": guard,
+                   "wall_s": round(wall, 3), "failed": failed}
+            if not failed:
+                rec["rho_range"] = [float(Wn[0].min()), float(Wn[0].max())]
+                if name == "blast_wave":   # walls: nothing enters or leaves
+                    rec["mass_energy_drift"] = [float(abs(Wn[k].sum() - W[k].sum()) / np.abs(W[k]).sum())
+                                                for k in (0, 2)]
+            out.setdefault(name, []).append(rec)
+    return out
+
+
 def cpu_baseline(W, dW, n, min_seconds=10.0):
     """The oracle timed on the host: whole S2O4 steps (2 stages each) of the
     same workload state, continued until at least min_seconds have passed."""
@@ -471,6 +511,8 @@ def main():
         out["forms"] = _finite(forms_comparison(G, inputs, np, torch, args.seed, gate=gate))
     if not args.no_batched:
         out["batched"] = _finite(batched_workload(G, inputs, np, torch, args.seed))
+    if not args.no_forms:
+        out["robustness"] = _finite(robustness_runs(G, inputs, np, torch))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)
     print(json.dumps(out), flush=True)
