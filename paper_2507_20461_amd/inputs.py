@@ -261,3 +261,69 @@ def shu_osher_1d(nx: int, gamma: float = GAMMA):
     dW = np.zeros_like(W)
     dW[0] = np.where(left, 0.0, rho_grad)
     return W[:, None, :], dW[:, None, :]
+
+
+# ---------------------------------------------------------------------------
+# Inputs of the sixth-order non-compact scheme: U[field, n] (no y axis).
+# ---------------------------------------------------------------------------
+
+def density_wave_noncompact(n: int, t: float = 0.0, gamma: float = GAMMA):
+    """The 1-D accuracy test of Sec. 6.1 as stated: rho = 1 + 0.2 sin(pi (x - t)),
+    U = p = 1 on [0, 2], periodic. Exact cell averages (rho U and rho E are
+    affine in rho) at time t of the advected wave."""
+    h = 2.0 / n
+    xl = np.arange(n) * h - t
+    xr = xl + h
+    rho = 1.0 + 0.2 * (np.cos(math.pi * xl) - np.cos(math.pi * xr)) / (math.pi * h)
+    return np.stack([rho, rho, 1.0 / (gamma - 1.0) + 0.5 * rho])
+
+
+def entropy_wave_noncompact(n: int = 1800, gamma: float = GAMMA, b: float = 1.5):
+    """The entropy-wave advection of Sec. 6.1: rho = 1 + 0.5 exp(-ln2 x^2 / b^2),
+    U = p = 1 on [-800, 1000], periodic; 1800 cells in the paper. Exact cell
+    averages through the error function."""
+    h = 1800.0 / n
+    xl = -800.0 + np.arange(n) * h
+    xr = xl + h
+    s = math.sqrt(math.log(2.0)) / b
+    erf = np.vectorize(math.erf)
+    rho = 1.0 + 0.5 * (math.sqrt(math.pi) / (2.0 * s)) * (erf(s * xr) - erf(s * xl)) / h
+    return np.stack([rho, rho, 1.0 / (gamma - 1.0) + 0.5 * rho])
+
+
+def smooth_noncompact(n: int, seed: int, gamma: float = GAMMA, modes: int = 3):
+    """Seeded smooth periodic state on [0, 1]: rho, u, p each a constant plus
+    `modes` Fourier modes with seeded amplitudes (rho, p in [0.5, 1.5],
+    |u| <= 0.6), sampled at the cell centres."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    fields = []
+    for base, amp in ((1.0, 0.4), (0.0, 0.5), (1.0, 0.4)):
+        f = np.full(n, base)
+        for m in range(1, modes + 1):
+            a, ph = rng.uniform(-1.0, 1.0) * amp / modes, rng.uniform(0.0, 2.0 * math.pi)
+            f += a * np.sin(2.0 * math.pi * m * x + ph)
+        fields.append(f)
+    return _cons_1d(fields[0], fields[1], fields[2], gamma)
+
+
+def shocks_noncompact(n: int, seed: int, gamma: float = GAMMA, cells_per_segment: int = 1000):
+    """Seeded piecewise-smooth stand-in for the paper's 1-D shock problems at
+    any size: segments of about `cells_per_segment` cells (the paper's runs
+    use 200 to 1800 cells with one to three discontinuities), each a seeded
+    constant (rho, p in [0.1, 10], |u| <= 1; jumps of up to two decades, as
+    in the Shu-Osher and Titarev-Toro data) plus a density wave
+    rho (1 + a sin(k x)) with a in [0, 0.2] and 8 to 64 cells per period;
+    sampled at the cell centres."""
+    rng = np.random.default_rng(seed)
+    nseg = max(1, n // cells_per_segment)
+    edges = np.sort(rng.choice(np.arange(1, n), size=nseg - 1, replace=False)) if nseg > 1 else np.array([], int)
+    seg = np.searchsorted(edges, np.arange(n), side="right")
+    rho0 = 10.0 ** rng.uniform(-1.0, 1.0, nseg)
+    u0 = rng.uniform(-1.0, 1.0, nseg)
+    p0 = 10.0 ** rng.uniform(-1.0, 1.0, nseg)
+    amp = rng.uniform(0.0, 0.2, nseg)
+    period = rng.uniform(8.0, 64.0, nseg)
+    i = np.arange(n)
+    rho = rho0[seg] * (1.0 + amp[seg] * np.sin(2.0 * math.pi * i / period[seg]))
+    return _cons_1d(rho, u0[seg], p0[seg], gamma)

@@ -1,0 +1,285 @@
+"""Pins of the sixth-order non-compact oracle (Sec. 4.1 GENO, HLLC, classical
+Runge-Kutta) against facts fixed outside it: textbook reconstruction
+coefficients, hand-integrated smoothness indicators, exactness on
+polynomials, the closed-form amplification of the linear scheme on a Fourier
+mode, the order of accuracy, the exact Euler flux and contact, mirror
+symmetry, conservation and the mirror-doubled domain."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geno6 as o6
+from paper_2507_20461_amd import inputs
+
+GAMMA = 1.4
+
+
+def face_weights(lo, n, xi):
+    """Weights mapping the averages of cells lo..lo+n-1 to the value at xi."""
+    w = []
+    for m in range(n):
+        e = np.zeros(n)
+        e[m] = 1.0
+        a = o6.poly(e, lo)
+        w.append(sum(a[k] * xi ** k for k in range(n)))
+    return np.array(w)
+
+
+def test_candidate_face_weights_are_the_textbook_ones():
+    # sixth-order interface formula of the symmetric six-cell stencil
+    assert np.allclose(face_weights(-2, 6, 0.5) * 60.0, [1, -8, 37, 37, -8, 1], atol=1e-12)
+    # third-order (ENO) and fourth-order stencils of the reconstruction tables
+    assert np.allclose(face_weights(-2, 3, 0.5), [1 / 3, -7 / 6, 11 / 6], atol=1e-13)
+    assert np.allclose(face_weights(-1, 3, 0.5), [-1 / 6, 5 / 6, 1 / 3], atol=1e-13)
+    assert np.allclose(face_weights(-1, 4, 0.5), [-1 / 12, 7 / 12, 7 / 12, -1 / 12], atol=1e-13)
+    assert np.allclose(face_weights(0, 4, 0.5), [1 / 4, 13 / 12, -5 / 12, 1 / 12], atol=1e-13)
+
+
+def test_smoothness_by_hand():
+    # p = xi: 1; xi^2: int (2 xi)^2 + int 2^2 = 1/3 + 4; xi^3: 9/80 + 3 + 36
+    assert o6.smoothness([0, 1], 1) == pytest.approx(1.0, abs=1e-15)
+    assert o6.smoothness([0, 0, 1], 2) == pytest.approx(13 / 3, abs=1e-14)
+    assert o6.smoothness([0, 0, 0, 1], 3) == pytest.approx(9 / 80 + 3 + 36, abs=1e-13)
+    # cross term of xi and xi^3: int 1 * 3 xi^2 * 2 = 1/2
+    assert o6.smoothness([0, 1, 0, 1], 3) == pytest.approx(1 + 0.5 + 9 / 80 + 3 + 36, abs=1e-13)
+
+
+def test_quadratic_indicators_are_jiang_shu():
+    rng = np.random.default_rng(4)
+    prm = o6.params()
+    for _ in range(20):
+        u = rng.normal(size=6)
+        a, b, c, d = u[0], u[1], u[2], u[3]
+        is1 = 13 / 12 * (a - 2 * b + c) ** 2 + 0.25 * (a - 4 * b + 3 * c) ** 2
+        is2 = 13 / 12 * (b - 2 * c + d) ** 2 + 0.25 * (b - d) ** 2
+        s = o6.side(prm, u, 0)
+        assert s["IS1"] == pytest.approx(is1, rel=1e-12, abs=1e-14)
+        assert s["IS2"] == pytest.approx(is2, rel=1e-12, abs=1e-14)
+
+
+def avg_of_poly(coef, n, lo=-2):
+    """Averages of sum coef[k] x^k over cells lo..lo+n-1 (unit cells, cell 0 = [-1/2, 1/2])."""
+    out = []
+    for m in range(lo, lo + n):
+        xl, xr = m - 0.5, m + 0.5
+        out.append(sum(c * (xr ** (k + 1) - xl ** (k + 1)) / (k + 1) for k, c in enumerate(coef)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3, 4, 5])
+def test_polynomial_exactness(deg):
+    rng = np.random.default_rng(deg)
+    coef = rng.normal(size=deg + 1)
+    u6 = avg_of_poly(coef, 6)
+    prm = o6.params()
+    for side, xf in ((0, 0.5), (1, 0.5)):
+        s = o6.side(prm, u6, side)
+        exact = sum(c * xf ** k for k, c in enumerate(coef))
+        # p^5 is exact up to degree 5, S_1, S_2 up to 2 and S_3, S_4 up to 3
+        assert s["p5"] == pytest.approx(exact, abs=1e-11)
+        for k, dmax in ((1, 2), (2, 2), (3, 3), (4, 3)):
+            if deg <= dmax:
+                assert s["p%d" % k] == pytest.approx(exact, abs=1e-11)
+
+
+def test_linear_data_keeps_the_linear_reconstruction():
+    # every candidate has IS = slope^2, so IS^tau = 0, alpha = 1, chi = 1 and
+    # the low-order weights are the linear ones d_k / sum d
+    prm = o6.params()
+    u6 = 0.3 + 0.7 * np.arange(6)
+    s = o6.side(prm, u6, 0)
+    assert s["chi"] == 1.0 and s["alpha"] == 1.0
+    assert np.allclose([s["w1"], s["w2"], s["w3"], s["w4"]], np.array([1, 8, 1, 1]) / 11, rtol=1e-12)
+    assert s["value"] == pytest.approx(0.3 + 0.7 * 2.5, abs=1e-13)
+
+
+def test_step_picks_the_smooth_side():
+    # a jump between cells j and j+1: the left state is the left constant and
+    # the right state the right one (only S_1 is smooth for the left side)
+    prm = o6.params()
+    u6 = np.array([1.0, 1.0, 1.0, 5.0, 5.0, 5.0])
+    left, right = o6.side(prm, u6, 0), o6.side(prm, u6, 1)
+    assert left["chi"] < 1e-20 and right["chi"] < 1e-20
+    assert left["value"] == pytest.approx(1.0, abs=1e-12)
+    assert right["value"] == pytest.approx(5.0, abs=1e-12)
+    # a jump between j-1 and j: S_4 is the only smooth stencil on the left side
+    u6 = np.array([1.0, 1.0, 5.0, 5.0, 5.0, 5.0])
+    assert o6.side(prm, u6, 0)["value"] == pytest.approx(5.0, abs=1e-12)
+
+
+def test_worked_examples_of_the_stencil_indicator():
+    prm = o6.params()
+    eps = 1e-15
+    # (a) a jump inside cell j+3 only: S_1..S_3 are flat, so IS^tau = 0 and
+    # the linear six-cell value is kept (chi = 1): 1/60 of the jump
+    s = o6.side(prm, [0, 0, 0, 0, 0, 1.0], 0)
+    assert s["chi"] == 1.0 and s["value"] == pytest.approx(1 / 60, abs=1e-15)
+    # (b) a jump inside cell j-2 only: IS_1 = 13/12 + 1/4 = 4/3, the others 0;
+    # IS^tau = IS_1 / 2 = 2/3, IS^H = 4/3, IS^L = 0
+    s = o6.side(prm, [1.0, 0, 0, 0, 0, 0], 0)
+    assert s["IS1"] == pytest.approx(4 / 3, rel=1e-13)
+    aH, aL = 1 + ((2 / 3) / (4 / 3 + eps)) ** 2, 1 + ((2 / 3) / eps) ** 2
+    assert s["alpha"] == pytest.approx(2 * aH / (aH + aL), rel=1e-12)
+    assert s["value"] == pytest.approx(0.0, abs=1e-25)
+    # (c) a jump inside cell j+2: S_3 and S_4 see it, S_1 and S_2 do not;
+    # IS^tau = IS_3 / 2 with IS_3, IS_4 from the pinned candidate helpers
+    s = o6.side(prm, [0, 0, 0, 0, 1.0, 0], 0)
+    is3 = o6.smoothness(o6.poly([0, 0, 0, 1.0], -1), 3)
+    is4 = o6.smoothness(o6.poly([0, 0, 1.0, 0], 0), 3)
+    assert s["IS3"] == pytest.approx(is3, rel=1e-12) and s["IS4"] == pytest.approx(is4, rel=1e-12)
+    aH, aL = 1 + ((is3 / 2) / (max(is3, is4) + eps)) ** 2, 1 + ((is3 / 2) / eps) ** 2
+    assert s["alpha"] == pytest.approx(2 * aH / (aH + aL), rel=1e-12)
+
+
+def test_mirror_symmetry_of_the_two_sides():
+    rng = np.random.default_rng(11)
+    prm = o6.params()
+    for _ in range(30):
+        u6 = rng.normal(size=6) * rng.choice([1e-3, 1.0, 10.0]) + (rng.random(6) < 0.3) * 3.0
+        a = o6.side(prm, u6, 0)
+        b = o6.side(prm, u6[::-1].copy(), 1)
+        for key in o6.SIDE_FIELDS:
+            assert a[key] == pytest.approx(b[key], rel=1e-12, abs=1e-13), key
+
+
+def test_path_function_bounds_and_limits():
+    prm = o6.params()
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        u6 = rng.normal(size=6)
+        s = o6.side(prm, u6, int(rng.integers(2)))
+        assert 0.0 < s["alpha"] <= 1.0
+        assert 0.0 <= s["chi"] <= 1.0 + 1e-15
+        assert sum(s["w%d" % k] for k in range(1, 5)) == pytest.approx(1.0, abs=1e-14)
+        lo, hi = min(s["p5"], s["p1"], s["p2"], s["p3"], s["p4"]), max(s["p5"], s["p1"], s["p2"], s["p3"], s["p4"])
+        assert lo - 1e-12 <= s["value"] <= hi + 1e-12
+
+
+def cons(rho, u, p):
+    return np.array([rho, rho * u, p / (GAMMA - 1) + 0.5 * rho * u * u])
+
+
+def euler_flux(rho, u, p):
+    E = p / (GAMMA - 1) + 0.5 * rho * u * u
+    return np.array([rho * u, rho * u * u + p, (E + p) * u])
+
+
+def test_hllc_consistency_upwinding_and_contacts():
+    prm = o6.params()
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        rho, u, p = rng.uniform(0.2, 2), rng.uniform(-2, 2), rng.uniform(0.2, 2)
+        assert np.allclose(o6.hllc(prm, cons(rho, u, p), cons(rho, u, p)), euler_flux(rho, u, p), rtol=1e-13)
+    # supersonic to the right / left: the upwind Euler flux
+    L, R = (1.0, 3.0, 1.0), (0.5, 3.5, 0.8)
+    assert np.allclose(o6.hllc(prm, cons(*L), cons(*R)), euler_flux(*L), rtol=1e-13)
+    L, R = (1.0, -3.0, 1.0), (0.5, -3.5, 0.8)
+    assert np.allclose(o6.hllc(prm, cons(*L), cons(*R)), euler_flux(*R), rtol=1e-13)
+    # isolated contacts are resolved exactly: stationary and moving
+    assert np.allclose(o6.hllc(prm, cons(1.0, 0.0, 0.7), cons(0.2, 0.0, 0.7)), [0.0, 0.7, 0.0], atol=1e-14)
+    for u in (0.4, -0.4):
+        F = o6.hllc(prm, cons(1.0, u, 0.7), cons(0.2, u, 0.7))
+        up = (1.0, u, 0.7) if u > 0 else (0.2, u, 0.7)
+        assert np.allclose(F, euler_flux(*up), rtol=1e-13)
+
+
+def test_hllc_mirror_symmetry():
+    prm = o6.params()
+    rng = np.random.default_rng(6)
+    for _ in range(30):
+        L = (rng.uniform(0.1, 3), rng.uniform(-2, 2), rng.uniform(0.1, 3))
+        R = (rng.uniform(0.1, 3), rng.uniform(-2, 2), rng.uniform(0.1, 3))
+        F = o6.hllc(prm, cons(*L), cons(*R))
+        G = o6.hllc(prm, cons(R[0], -R[1], R[2]), cons(L[0], -L[1], L[2]))
+        assert np.allclose(F, [-G[0], G[1], -G[2]], rtol=1e-12, atol=1e-13)
+
+
+def test_one_step_matches_the_fourier_amplification():
+    # On the density wave (U = p = 1) the reconstruction stays linear (chi = 1
+    # to rounding), both sides equal the sixth-order central value and HLLC is
+    # the exact contact flux: the scheme is linear advection of rho with the
+    # Fourier symbol of the six-cell formula and classical Runge-Kutta, whose
+    # one-step amplification is the degree-4 Taylor polynomial of exp(z).
+    n, dt = 16, 0.05
+    U = inputs.density_wave_noncompact(n)
+    h = 2.0 / n
+    U1, _, g = o6.step(o6.params(dt_fixed=dt), U, h, 1)
+    assert g == 0
+    k = math.pi
+    c = np.array([1, -8, 37, 37, -8, 1]) / 60.0
+    S = sum(c[m + 2] * np.exp(1j * k * m * h) for m in range(-2, 4))
+    z = -(S / h) * (1 - np.exp(-1j * k * h)) * dt
+    G = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    xc = (np.arange(n) + 0.5) * h
+    amp = 0.2 * math.sin(k * h / 2) / (k * h / 2)
+    rho = 1.0 + amp * np.imag(G * np.exp(1j * k * xc))
+    assert np.abs(U1[0] - rho).max() < 1e-13
+    assert np.abs(U1[1] - rho).max() < 1e-13
+    assert np.abs(U1[2] - (2.5 + 0.5 * rho)).max() < 1e-13
+
+
+def test_sixth_order_convergence_on_the_density_wave():
+    # t = 2 (one period); dt ~ h^1.5 so that the fourth-order time error
+    # stays below the sixth-order space error
+    errs = []
+    for n in (12, 24, 48):
+        h = 2.0 / n
+        steps = int(math.ceil(2.0 / (0.25 * h ** 1.5)))
+        dt = 2.0 / steps
+        U, _, _ = o6.step(o6.params(dt_fixed=dt), inputs.density_wave_noncompact(n), h, steps)
+        errs.append(np.abs(U[0] - inputs.density_wave_noncompact(n, t=2.0)[0]).mean())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] > 5.6, (errs, orders)
+
+
+def test_periodic_run_conserves_totals():
+    n = 64
+    U = inputs.shocks_noncompact(n, seed=2, cells_per_segment=16)
+    U1, dts, g = o6.step(o6.params(cfl=0.4), U, 1.0 / n, 20)
+    assert np.all(np.isfinite(U1))
+    for v in range(3):
+        assert abs(U1[v].sum() - U[v].sum()) <= 1e-12 * np.abs(U[v]).sum()
+
+
+def test_reflecting_walls_equal_the_mirror_doubled_periodic_run():
+    n = 40
+    U = inputs.smooth_noncompact(n, seed=9)
+    U[:, 10:14] *= 1.7   # a bump with jumps
+    prm_w = o6.params(bc=o6.REFLECTING, dt_fixed=2e-3)
+    Uw, _, _ = o6.step(prm_w, U, 1.0 / n, 15)
+    # mirror-doubled domain: cells reversed, momentum negated, periodic
+    M = U[:, ::-1].copy()
+    M[1] *= -1
+    D = np.concatenate([U, M], axis=1)
+    Dp, _, _ = o6.step(o6.params(bc=o6.PERIODIC, dt_fixed=2e-3), D, 1.0 / n, 15)
+    assert np.allclose(Uw, Dp[:, :n], rtol=1e-11, atol=1e-12)
+    for v in (0, 2):
+        assert abs(Uw[v].sum() - U[v].sum()) <= 1e-12 * np.abs(U[v]).sum()
+
+
+def test_transmissive_constant_state_is_steady():
+    U = np.repeat(cons(0.8, 0.3, 1.1)[:, None], 20, axis=1)
+    U1, _, g = o6.step(o6.params(bc=o6.TRANSMISSIVE), U, 0.05, 5)
+    assert g == 0 and np.allclose(U1, U, rtol=1e-14, atol=1e-14)
+
+
+def test_guard_replaces_a_non_physical_state():
+    # a cold, fast flow (p = 1e-9, |u| up to 2): reconstructing rho, rho U and
+    # rho E separately leaves the face pressure as the difference of nearly
+    # equal numbers, negative at many faces; guarded sides take the target
+    # cell's average, which is admissible
+    n = 12
+    x = np.arange(n) / n
+    u = 2.0 * np.sin(2 * np.pi * x)
+    rho = 1.0 + 0.5 * np.cos(2 * np.pi * x)
+    U = np.stack([rho, rho * u, 1e-9 / (GAMMA - 1) + 0.5 * rho * u * u])
+    UL, UR, F, chi, g = o6.faces(o6.params(bc=o6.PERIODIC), U)
+    assert g >= 1
+    assert np.all(np.isfinite(F))
+    replaced = 0
+    for s in range(n + 1):
+        for W, cell in ((UL[:, s], (s - 1) % n), (UR[:, s], s % n)):
+            assert W[0] > 0 and (GAMMA - 1) * (W[2] - 0.5 * W[1] ** 2 / W[0]) > 0
+            replaced += bool(np.array_equal(W, U[:, cell]))
+    assert replaced >= g
