@@ -1,0 +1,202 @@
+// Device functions of the sixth-order non-compact scheme (Sec. 4.1): GENO
+// side states on the six-cell stencil, the positivity guard and the HLLC
+// flux. Templated on the scalar type D so that the same code runs on the
+// device (double) and on the host with a counting type (operation counts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace geno6 {
+
+struct KP6 {
+  double gamma;
+  double C;          // path-function steepness (Eq. (4))
+  double inv_tanhC;  // 1 / tanh(C)
+  double eps;        // indicator floor (Eq. (5), (8))
+  double d[4];       // linear weights of S_1..S_4 (Eq. (8))
+  double cfl;
+  double dt_fixed;
+};
+
+// Candidate values at the face and indicators for the state LEFT of
+// x_{j+1/2}; u[0..5] are the averages of cells j-2..j+3 (the right state is
+// this function on the reversed stencil). The coefficients follow from the
+// cell-average conditions of each candidate in xi = (x - x_j)/h:
+//   S_1 {j-2, j-1, j}   value (2 u0 - 7 u1 + 11 u2) / 6
+//   S_2 {j-1, j, j+1}   value (-u1 + 5 u2 + 2 u3) / 6
+//   S_3 {j-1..j+2}      value (-u1 + 7 u2 + 7 u3 - u4) / 12
+//   S_4 {j..j+3}        value (3 u2 + 13 u3 - 5 u4 + u5) / 12
+// and Eq. (6) on the target cell, with p = sum a_k xi^k:
+//   quadratic: IS = a1^2 + 13/3 a2^2
+//   cubic:     IS = (a1 + a3/4)^2 + 13/3 a2^2 + 781/20 a3^2
+// (the integrals of p'^2, p''^2, p'''^2 over [-1/2, 1/2], completed to
+// squares). For S_3 and S_4 the linear combinations a1 + a3/4, a2, a3 of the
+// averages are (-2 u1 - 3 u2 + 6 u3 - u4)/6, (u1 - 2 u2 + u3)/2,
+// (-u1 + 3 u2 - 3 u3 + u4)/6 and (-11 u2 + 18 u3 - 9 u4 + 2 u5)/6,
+// (2 u2 - 5 u3 + 4 u4 - u5)/2, (-u2 + 3 u3 - 3 u4 + u5)/6.
+template <typename D>
+struct Cand {
+  D v1, v2, v4;        // face values of p_1, p_2, p_4 (p_3 is shared by both sides)
+  D IS[4];
+};
+
+template <typename D>
+__host__ __device__ __forceinline__ Cand<D> candidates(D u0, D u1, D u2, D u3, D u4, D u5) {
+  Cand<D> c;
+  const D sixth = D(1.0 / 6.0), twelfth = D(1.0 / 12.0);
+  c.v1 = (D(2.0) * u0 - D(7.0) * u1 + D(11.0) * u2) * sixth;
+  c.v2 = (D(5.0) * u2 + D(2.0) * u3 - u1) * sixth;
+  c.v4 = (D(3.0) * u2 + D(13.0) * u3 - D(5.0) * u4 + u5) * twelfth;
+  const D q1a = u0 - D(2.0) * u1 + u2, q1b = u0 - D(4.0) * u1 + D(3.0) * u2;
+  const D q2a = u1 - D(2.0) * u2 + u3, q2b = u1 - u3;
+  const D c3a = D(6.0) * u3 - D(2.0) * u1 - D(3.0) * u2 - u4;
+  const D c3c = D(3.0) * (u2 - u3) + u4 - u1;
+  const D c4a = D(18.0) * u3 - D(11.0) * u2 - D(9.0) * u4 + D(2.0) * u5;
+  const D c4b = D(2.0) * u2 - D(5.0) * u3 + D(4.0) * u4 - u5;
+  const D c4c = D(3.0) * (u3 - u4) + u5 - u2;
+  const D k13 = D(13.0 / 12.0), k36 = D(1.0 / 36.0), k781 = D(781.0 / 720.0);
+  const D m2 = k13 * q2a * q2a;   // 13/3 a2^2 of S_2, also of S_3
+  c.IS[0] = k13 * q1a * q1a + D(0.25) * q1b * q1b;
+  c.IS[1] = m2 + D(0.25) * q2b * q2b;
+  c.IS[2] = k36 * c3a * c3a + m2 + k781 * c3c * c3c;
+  c.IS[3] = k36 * c4a * c4a + k13 * c4b * c4b + k781 * c4c * c4c;
+  return c;
+}
+
+// Path function (Eq. (4), (5) with r = 2, Eq. (7), (9) and the Sec. 4.1
+// IS^tau). alpha = 2 aH / (aH + aL), aH = 1 + t^2/x^2, aL = 1 + t^2/y^2
+// (x = IS^H + eps, y = IS^L + eps) is formed with one division as
+// 2 y^2 (x^2 + t^2) / (2 x^2 y^2 + t^2 (x^2 + y^2)). tanh(z) for z >= 0 is
+// (1 - e)/(1 + e), e = exp(-2z); for z >= 19.8, e < 2^-54 and both
+// tanh(z) and tanh(C) (C >= z) round to 1, so chi is 1 exactly.
+template <typename D>
+__host__ __device__ __forceinline__ D path_chi6(const D (&IS)[4], const KP6& k) {
+  using std::fabs;
+  using std::fmax;
+  using std::fmin;
+  const D ISH = fmax(fmax(IS[0], IS[1]), fmax(IS[2], IS[3]));
+  const D ISL = fmin(fmin(IS[0], IS[1]), fmin(IS[2], IS[3]));
+  const D t = fabs(D(0.5) * (IS[0] + IS[2]) - IS[1]);
+  const D x = ISH + D(k.eps), y = ISL + D(k.eps);
+  const D x2 = x * x, y2 = y * y, t2 = t * t;
+  const D alpha = D(2.0) * y2 * (x2 + t2) / (D(2.0) * x2 * y2 + t2 * (x2 + y2));
+  const D z = D(k.C) * alpha;
+  if (!(z < D(19.8))) return D(1.0);
+  using std::exp;
+  const D e = exp(D(-2.0) * z);
+  return (D(1.0) - e) / (D(1.0) + e) * D(k.inv_tanhC);
+}
+
+// Eq. (8) with r^L = 2: q^L = sum_k d_k v_k / a_k / sum_k d_k / a_k,
+// a_k = (IS_k + eps)^2, formed with one division by multiplying through by
+// a_1 a_2 a_3 a_4.
+template <typename D>
+__host__ __device__ __forceinline__ D low_order6(const D (&IS)[4], D v1, D v2, D v3, D v4,
+                                                 const KP6& k) {
+  const D e = D(k.eps);
+  const D a1 = (IS[0] + e) * (IS[0] + e), a2 = (IS[1] + e) * (IS[1] + e);
+  const D a3 = (IS[2] + e) * (IS[2] + e), a4 = (IS[3] + e) * (IS[3] + e);
+  const D a12 = a1 * a2, a34 = a3 * a4;
+  const D w1 = D(k.d[0]) * (a2 * a34), w2 = D(k.d[1]) * (a1 * a34);
+  const D w3 = D(k.d[2]) * (a12 * a4), w4 = D(k.d[3]) * (a12 * a3);
+  return (w1 * v1 + w2 * v2 + w3 * v3 + w4 * v4) / (w1 + w2 + w3 + w4);
+}
+
+// GENO state of one side: c from candidates() on the side's stencil, p5 and
+// p3 the face values of the quintic and of the S_3 cubic (the same
+// polynomials for both sides). chi_out receives the path function.
+template <typename D>
+__host__ __device__ __forceinline__ D side6(const Cand<D>& c, D p5, D p3, const KP6& k,
+                                           D& chi_out) {
+  const D chi = path_chi6(c.IS, k);
+  chi_out = chi;
+  if (chi == D(1.0)) return p5;
+  const D qL = low_order6(c.IS, c.v1, c.v2, p3, c.v4, k);
+  return chi * p5 + (D(1.0) - chi) * qL;
+}
+
+// rho > 0 and p > 0 (as rho E - m^2/2 > 0, rho > 0) with finite entries.
+template <typename D>
+__host__ __device__ __forceinline__ bool admissible6(const D* W) {
+  using std::isfinite;
+  return isfinite(W[0]) && isfinite(W[1]) && isfinite(W[2]) && W[0] > D(0.0) &&
+         W[0] * W[2] - D(0.5) * W[1] * W[1] > D(0.0);
+}
+
+// HLLC flux (Toro's solver) with S_L = min(u_L - a_L, u_R - a_R),
+// S_R = max(u_L + a_L, u_R + a_R), contact speed
+// S* = (p_R - p_L + m_L (S_L - u_L) - m_R (S_R - u_R)) /
+//      (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
+// star state of side K: rho_K (S_K - u_K)/(S_K - S*) *
+//   (1, S*, E_K/rho_K + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K)))),
+// F = F_K + S_K (U*_K - U_K) with K = L for S* >= 0, else R; F_L for
+// S_L >= 0, F_R for S_R <= 0. The star side is chosen by selects, so a
+// wave takes no branch.
+template <typename D>
+__host__ __device__ __forceinline__ void hllc6(const D* UL, const D* UR, D gamma, D* F) {
+  using std::fmax;
+  using std::fmin;
+  using std::sqrt;
+  const D irl = D(1.0) / UL[0], irr = D(1.0) / UR[0];
+  const D ul = UL[1] * irl, ur = UR[1] * irr;
+  const D gm1 = gamma - D(1.0);
+  const D pl = gm1 * (UL[2] - D(0.5) * UL[1] * ul), pr = gm1 * (UR[2] - D(0.5) * UR[1] * ur);
+  const D al = sqrt(gamma * pl * irl), ar = sqrt(gamma * pr * irr);
+  const D SL = fmin(ul - al, ur - ar), SR = fmax(ul + al, ur + ar);
+  const D dl = SL - ul, dr = SR - ur;
+  const D Ss = (pr - pl + UL[1] * dl - UR[1] * dr) / (UL[0] * dl - UR[0] * dr);
+  const bool left = Ss >= D(0.0);
+  const D rK = left ? UL[0] : UR[0], mK = left ? UL[1] : UR[1], EK = left ? UL[2] : UR[2];
+  const D uK = left ? ul : ur, pK = left ? pl : pr, irK = left ? irl : irr;
+  const D SK = left ? SL : SR, dK = left ? dl : dr;
+  const D f = rK * dK / (SK - Ss);
+  const D Es = f * (EK * irK + (Ss - uK) * (Ss + pK * irK / dK));
+  const D FK0 = mK, FK1 = mK * uK + pK, FK2 = (EK + pK) * uK;
+  const D Fs0 = FK0 + SK * (f - rK), Fs1 = FK1 + SK * (f * Ss - mK), Fs2 = FK2 + SK * (Es - EK);
+  const bool sup_l = SL >= D(0.0), sup_r = SR <= D(0.0);
+  const D FL0 = UL[1], FL1 = UL[1] * ul + pl, FL2 = (UL[2] + pl) * ul;
+  const D FR0 = UR[1], FR1 = UR[1] * ur + pr, FR2 = (UR[2] + pr) * ur;
+  F[0] = sup_l ? FL0 : (sup_r ? FR0 : Fs0);
+  F[1] = sup_l ? FL1 : (sup_r ? FR1 : Fs1);
+  F[2] = sup_l ? FL2 : (sup_r ? FR2 : Fs2);
+}
+
+// One face: u[v][0..5] the averages of cells j-2..j+3 of variable v. Writes
+// the guarded states WL, WR, the flux F and (chi != nullptr) the six path
+// functions [side * 3 + v]; returns the number of guarded sides.
+template <typename D>
+__host__ __device__ __forceinline__ int face6(const D (&u)[3][6], const KP6& k, D* WL, D* WR,
+                                              D* F, D* chi) {
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const D* s = u[v];
+    const D p5 = (s[0] + s[5] - D(8.0) * (s[1] + s[4]) + D(37.0) * (s[2] + s[3])) * D(1.0 / 60.0);
+    const D p3 = (D(7.0) * (s[2] + s[3]) - s[1] - s[4]) * D(1.0 / 12.0);
+    const Cand<D> cl = candidates(s[0], s[1], s[2], s[3], s[4], s[5]);
+    const Cand<D> cr = candidates(s[5], s[4], s[3], s[2], s[1], s[0]);
+    D xl, xr;
+    WL[v] = side6(cl, p5, p3, k, xl);
+    WR[v] = side6(cr, p5, p3, k, xr);
+    if (chi) {
+      chi[v] = xl;
+      chi[3 + v] = xr;
+    }
+  }
+  int guard = 0;
+  if (!admissible6(WL)) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) WL[v] = u[v][2];
+    ++guard;
+  }
+  if (!admissible6(WR)) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) WR[v] = u[v][3];
+    ++guard;
+  }
+  hllc6(WL, WR, D(k.gamma), F);
+  return guard;
+}
+
+}  // namespace geno6

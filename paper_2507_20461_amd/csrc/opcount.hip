@@ -10,6 +10,8 @@
 
 #include <cmath>
 
+#include "geno6.h"
+#include "geno6_device.hpp"
 #include "geno_device.hpp"
 #include "geno_gks.h"
 #include "gks_device.hpp"
@@ -33,6 +35,8 @@ inline C operator/(C a, C b) { ++g_ops; return C(a.v / b.v); }
 inline C operator-(C a) { return C(-a.v); }
 inline bool operator>(C a, C b) { return a.v > b.v; }
 inline bool operator<(C a, C b) { return a.v < b.v; }
+inline bool operator>=(C a, C b) { return a.v >= b.v; }
+inline bool operator<=(C a, C b) { return a.v <= b.v; }
 inline bool operator==(C a, C b) { return a.v == b.v; }
 inline C sqrt(C a) { ++g_ops; return C(std::sqrt(a.v)); }
 inline C exp(C a) { ++g_ops; return C(std::exp(a.v)); }
@@ -185,4 +189,51 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     set(GENO_K_INIT, GENO_W_UNITS, 11.0);
   }
   return 0;
+}
+
+// Sixth-order non-compact scheme: a face with linear data (every side keeps
+// chi = 1 without the exponential or the low-order part), the extra work of
+// one side whose chi < 1, and the per-cell flux difference and stage update
+// (2 per variable for L, on average 5 per variable for the four stage
+// combinations, and the wave speed of the last stage, 9 operations, once in
+// four stages: 3 * 7 + 2 = 23).
+extern "C" int geno6_op_costs(double* costs) {
+  using opcount::C;
+  using opcount::count;
+  if (!costs) return GENO_EINVAL;
+  geno6::KP6 k;
+  k.gamma = 1.4;
+  k.C = 20.0;
+  k.inv_tanhC = 1.0 / std::tanh(20.0);
+  k.eps = 1e-15;
+  k.d[0] = 1.0;
+  k.d[1] = 8.0;
+  k.d[2] = 1.0;
+  k.d[3] = 1.0;
+  k.cfl = 0.5;
+  k.dt_fixed = 0.0;
+  // linear data of an admissible subsonic state (rho, rho u, rho E)
+  const long long face_lin = count([&] {
+    C u[3][6], WL[3], WR[3], F[3];
+    for (int m = 0; m < 6; ++m) {
+      u[0][m] = 1.0 + 0.01 * m;
+      u[1][m] = 0.1 + 0.01 * m;
+      u[2][m] = 2.5 + 0.01 * m;
+    }
+    (void)geno6::face6<C>(u, k, WL, WR, F, nullptr);
+  });
+  const long long side_lin = count([&] {
+    const geno6::Cand<C> c = geno6::candidates<C>(1.0, 1.1, 1.2, 1.3, 1.4, 1.5);
+    C x;
+    (void)geno6::side6<C>(c, C(1.25), C(1.25), k, x);
+  });
+  const long long side_low = count([&] {
+    const geno6::Cand<C> c = geno6::candidates<C>(1.0, 1.0, 1.0, 5.0, 5.0, 5.0);
+    C x;
+    (void)geno6::side6<C>(c, C(3.0), C(3.0), k, x);
+  });
+  costs[0] = (double)face_lin;
+  costs[1] = (double)(side_low - side_lin);
+  costs[2] = 23.0;
+  return GENO_OK;
 }

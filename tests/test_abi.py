@@ -1,5 +1,5 @@
 """The C-ABI library builds for gfx950, loads without a GPU and exports every
-function that include/geno_gks.h declares (no compute calls)."""
+function that include/*.h declares (no compute calls)."""
 import ctypes
 import os
 import re
@@ -41,8 +41,9 @@ def test_library_exports_every_declared_symbol(so):
 
 
 def test_binding_names_match_header():
-    from paper_2507_20461_amd import geno_gks
-    assert set(geno_gks.EXPORTS) == set(_declared())
+    from paper_2507_20461_amd import geno6, geno_gks
+    assert set(geno_gks.EXPORTS) | set(geno6.EXPORTS) == set(_declared())
+    assert not set(geno_gks.EXPORTS) & set(geno6.EXPORTS)
 
 
 def test_host_side_validation(so):
@@ -90,3 +91,37 @@ def test_batched_host_side_validation(so):
     vp = (ctypes.c_void_p * 2)(1, 1)
     assert G.lib().gks_step_batched(2, B.garr, vp, vp, ctypes.c_void_p(1), 1, ctypes.byref(bad_t), 0, None, None,
                                     None) == G.GENO_EINVAL
+
+
+def test_noncompact_host_side_validation(so):
+    from paper_2507_20461_amd import geno6 as S
+    from paper_2507_20461_amd import geno_gks as G
+    p = S.default_params()
+    assert (p.C, p.eps, list(p.d), p.cfl, list(p.bc)) == (20.0, 1e-15, [1.0, 8.0, 1.0, 1.0], 0.5, [0, 0])
+    g = S.Grid6(1000, 0.0, 2.0)
+    assert g.pitch == 1024 and g.dx == pytest.approx(0.002)
+    # control block, 4 tile maxima (255 cells each) and three stage arrays
+    assert S.lib().geno6_workspace_bytes(ctypes.byref(g.g)) >= 3 * 3 * 1024 * 8 + 4 * 8
+    for kw in ({"n": 2}, {"n": 8, "x0": 1.0, "x1": 1.0}):
+        with pytest.raises(G.GenoError):
+            S.Grid6(**kw)
+    for bad in ({"bc": (0, 1)}, {"d": (1, 8, 0, 1)}, {"cfl": 0.0}, {"bc": (3, 3)}, {"dt_fixed": -1.0}):
+        with pytest.raises(G.GenoError):
+            S.Grid6(16, params=S.default_params(**bad))
+    v = S.default_params()
+    v.version = 7
+    with pytest.raises(G.GenoError) as e:
+        S.Grid6(16, params=v)
+    assert e.value.code == G.GENO_EVERSION
+    # null pointers are rejected before any launch
+    assert S.lib().geno6_step(ctypes.byref(g.g), None, None, 1, None, None, None) == G.GENO_EINVAL
+    assert S.lib().geno6_rhs(ctypes.byref(g.g), None, None, None) == G.GENO_EINVAL
+    assert S.lib().geno6_faces(ctypes.byref(g.g), None, None, None, None, None, None) == G.GENO_EINVAL
+
+
+def test_noncompact_op_costs(so):
+    from paper_2507_20461_amd import geno6 as S
+    c = S.op_costs()
+    # a face: two sides of three variables plus HLLC; a low-order side adds
+    # the exponential of chi, the weights and the blend
+    assert 300 < c["face"] < 1500 and 10 < c["low_side"] < 100 and c["cell"] == 23.0
