@@ -10,6 +10,10 @@ update, device-side dt). Inputs are resident in HBM before timing.
 Metric: million cell-updates per second per stage (interior cells x 2 stages
 x steps / time).
 
+Beside it (its own object in the same JSON line): the sixth-order non-compact
+scheme of the paper's Sec. 4.1 (GENO + HLLC + classical RK4) on 2^24 cells of
+a 1-D piecewise-smooth state, with its own roofline and oracle baseline.
+
 Prints one JSON line (rank 0). `--gpus N` with N > 1 is rejected: this build
 runs on one GPU.
 """
@@ -52,6 +56,8 @@ def parse():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP64 vs mixed comparison at 2048^2")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched workload")
+    ap.add_argument("--noncompact-steps", type=int, default=40,
+                    help="timed Runge-Kutta steps of the 1-D sixth-order non-compact workload (0 = skip)")
     return ap.parse_args()
 
 
@@ -165,6 +171,140 @@ def robustness_runs(G, inputs, np, torch):
                                                 for k in (0, 2)]
             out.setdefault(name, []).append(rec)
     return out
+
+
+NONCOMPACT_N = 1 << 24
+NONCOMPACT_STAGE_BYTES = (72.0, 120.0, 120.0, 72.0)   # algorithmic HBM bytes per cell of stages 1..4
+
+
+def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_seconds=10.0, cpu=True):
+    """The sixth-order non-compact scheme (GENO on the six-cell stencil, HLLC,
+    classical Runge-Kutta) on 2^24 cells of the seeded piecewise-smooth 1-D
+    state (segments of ~1000 cells, transmissive ends, CFL 0.5), FP64.
+    Throughput in cell-updates per stage over `steps` steps (whole steps:
+    device dt + four stage launches), then the same steps again with events
+    bound to every launch (per-kernel durations; the replay must reproduce
+    the timed run bit for bit). Roofline of the stage kernel: algorithmic
+    bytes per cell (stage 1: Y in, acc and Y out = 72 B; stages 2, 3: Y, U,
+    acc in, acc and Y out = 120 B; stage 4: Y, acc in, U out = 72 B) and
+    counted flops (per face, per low-order side from the path functions of
+    the initial state, per cell)."""
+    from paper_2507_20461_amd import geno6 as S
+    U = inputs.shocks_noncompact(n, seed)
+    grid = S.Grid6(n, 0.0, 1.0, bc=1, cfl=0.5)
+    Ud = grid.to_device(U)
+    U0 = Ud.clone()
+    ws = grid.workspace()
+    # path functions of the initial state: share of sides with chi < 1
+    chi = torch.empty(2, 3, n + 1, dtype=torch.float64, device="cuda")
+    S.faces(grid, Ud, None, None, None, chi)
+    low = int((chi < 1.0).sum().item())
+    del chi
+    S.step(grid, Ud, ws, 2)                     # warm-up
+    Ud.copy_(U0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.step(grid, Ud, ws, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    Uend = Ud.clone()
+    Ud.copy_(U0)
+    torch.cuda.synchronize()
+    S.timing_enable(5 * steps + 4)
+    st = S.step(grid, Ud, ws, steps, stats=True)
+    kt = S.timing_read()
+    S.timing_enable(0)
+    assert torch.equal(Ud, Uend), "replay differs from the timed run"
+    costs = S.op_costs()
+    stage_ms, nl = kt["stage"]
+    us = 1e3 * stage_ms / nl
+    flops = (n + 1) * costs["face"] + low * costs["low_side"] + n * costs["cell"]
+    bytes_ = n * sum(NONCOMPACT_STAGE_BYTES) / 4.0
+    ridge = PEAK_FP64_VECTOR_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    ai = flops / bytes_
+    gbs = bytes_ / (us / 1e6) / 1e9
+    tf = flops / (us / 1e6) / 1e12
+    if ai < ridge:
+        roof = {"bound": "hbm", "kernel": "k6_stage", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 5)}
+    else:
+        roof = {"bound": "alu", "kernel": "k6_stage", "achieved": round(tf, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_VECTOR_TFLOPS, 5)}
+    tb, tdetail = noncompact_traffic()
+    roof.update({"traffic": round(tb) if tb else None, "traffic_detail": tdetail,
+                 "algorithmic_mb_per_launch": round(bytes_ / 1e6, 3), "us_per_launch": round(us, 3),
+                 "arithmetic_intensity": round(ai, 3), "ridge_flop_per_byte": round(ridge, 3),
+                 "alu_achieved_tflops": round(tf, 3), "alu_frac": round(tf / PEAK_FP64_VECTOR_TFLOPS, 5),
+                 "hbm_achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 5),
+                 "gflop_per_launch": round(flops / 1e9, 4), "low_order_sides_initial": low,
+                 "op_costs": costs})
+    V = Uend[:, :n]
+    out = {"workload": "1d-euler-%d-cells-piecewise-smooth-fp64" % n,
+           "scheme": "6th-order non-compact GENO + HLLC + classical RK4",
+           "value": round(4.0 * n * steps / (ms / 1e3) / 1e6, 3), "unit": "Mcell-updates/s per stage",
+           "steps": steps, "ms_per_step": round(ms / steps, 5), "cfl": 0.5, "bc": "transmissive", "seed": seed,
+           "guard": st.guard, "physical_after_run": bool(torch.isfinite(V).all().item() and (V[0] > 0).all().item()),
+           "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
+                           "us_avg": round(1e3 * v[0] / v[1], 3) if v[1] else None} for k, v in kt.items()},
+           "roofline": roof}
+    del ws, Ud, U0, Uend
+    # the paper's 1-D sizes are far below what fills the GPU: a run of the
+    # entropy-wave test (1800 cells, 100 steps) shows the launch-bound rate
+    U1 = inputs.entropy_wave_noncompact(1800)
+    g1 = S.Grid6(1800, -800.0, 1000.0)
+    u1, w1 = g1.to_device(U1), g1.workspace()
+    S.step(g1, u1, w1, 5)
+    torch.cuda.synchronize()
+    e0.record()
+    S.step(g1, u1, w1, 100)
+    e1.record()
+    torch.cuda.synchronize()
+    out["entropy_wave_1800"] = {"us_per_step": round(1e3 * e0.elapsed_time(e1) / 100, 2),
+                                "launches_per_step": 5}
+    if cpu:
+        out["cpu_baseline"] = noncompact_cpu_baseline(np, inputs, seed, min_cpu_seconds)
+    return out
+
+
+def noncompact_traffic():
+    """Mean HBM bytes per stage launch (the four stage kernels) from the
+    committed counter passes of the non-compact workload, or None."""
+    from paper_2507_20461_amd import profiling
+    if not os.path.exists(COUNTERS):
+        return None, None
+    meta = json.load(open(COUNTERS))
+    if meta.get("source_hash") != profiling.source_hash():
+        return None, "counters taken on other kernel sources"
+    rows = [meta["kernels"].get("k6_stage<%d>" % m) for m in range(4)]
+    if not all(rows) or any(r.get("fetch_bytes_cal") is None or r.get("write_bytes_cal") is None for r in rows):
+        return None, None
+    f = sum(r["fetch_bytes_cal"] for r in rows) / 4
+    w = sum(r["write_bytes_cal"] for r in rows) / 4
+    return f + w, {"fetch_bytes": round(f), "write_bytes": round(w), "calibration": meta["calibration"],
+                   "source": os.path.relpath(COUNTERS, ROOT)}
+
+
+def noncompact_cpu_baseline(np, inputs, seed, min_seconds=10.0, n=1 << 16):
+    """The non-compact oracle on the host: Runge-Kutta steps of the first
+    65536 cells of the same kind of state until min_seconds have passed."""
+    from oracle import geno6 as O6
+    O6.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    U = inputs.shocks_noncompact(n, seed)
+    prm = O6.params(bc=(1, 1), cfl=0.5)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        U, _, _ = O6.step(prm, U, 1.0 / n, 1)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    return {"value": round(4.0 * n * steps / dt / 1e6, 4), "unit": "Mcell-updates/s per stage", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d classical RK4 steps (4 stages each) of a %d-cell piecewise-smooth state, %.1f s wall"
+                      % (steps, n, dt)}
 
 
 def cpu_baseline(W, dW, n, min_seconds=10.0):
@@ -513,6 +653,9 @@ def main():
         out["batched"] = _finite(batched_workload(G, inputs, np, torch, args.seed))
     if not args.no_forms:
         out["robustness"] = _finite(robustness_runs(G, inputs, np, torch))
+    if args.noncompact_steps > 0:
+        out["noncompact"] = _finite(noncompact_workload(np, torch, inputs, args.seed, args.noncompact_steps,
+                                                        cpu=not args.no_cpu_baseline))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)
     print(json.dumps(out), flush=True)

@@ -85,7 +85,7 @@ int geno6_params_default(geno6_params* p);
  * GENO_EVERSION for a params version other than GENO6_ABI_VERSION. */
 int geno6_grid_init(geno6_grid* g, int n, double x0, double x1, const geno6_params* p);
 
-/* Bytes of the device workspace of geno6_step (control block, per-work-group
+/* Bytes of the device workspace of geno6_step (control block, 1024 slots of
  * wave-speed maxima and three stage arrays of 3 * pitch doubles). */
 size_t geno6_workspace_bytes(const geno6_grid* g);
 
@@ -117,7 +117,7 @@ int geno6_step(const geno6_grid* g, double* U, void* ws, int nsteps, double* dt_
 
 /* Kernel kinds of geno6_step for the timing hooks below. */
 enum {
-  GENO6_K_INIT = 0,   /* wave-speed maxima of the initial state, counters cleared */
+  GENO6_K_INIT = 0,   /* wave-speed maxima of the initial state */
   GENO6_K_DT,         /* time step of a step from the maxima (one work-group) */
   GENO6_K_STAGE,      /* one Runge-Kutta stage: GENO on both sides of every
                          face, HLLC, flux difference and the stage combination
@@ -130,11 +130,13 @@ enum {
 int geno6_timing_enable(int max_launches);
 int geno6_timing_read(int nkinds, double* ms_total, long long* launches);
 
-/* Floating-point operations of one face of a stage (both sides of the three
- * variables, guard tests and HLLC; add, sub, mul, div, sqrt and each exp
- * count 1), of the flux difference and stage combination of one cell, and
- * of the HLLC branch taken in the subsonic case, as the device functions
- * execute them: costs[0] per face, costs[1] per cell. */
+/* Floating-point operations (add, sub, mul, div, sqrt and each exp count 1)
+ * as the device functions execute them, host array of 3: costs[0] one face
+ * of a stage whose six sides keep chi = 1 (both sides of the three
+ * variables with their indicators, guard tests, HLLC); costs[1] the extra
+ * work of one side with chi < 1 (exponential, low-order weights, blend);
+ * costs[2] one cell (flux difference and stage combination, averaged over
+ * the four stages). */
 int geno6_op_costs(double* costs);
 
 #ifdef __cplusplus

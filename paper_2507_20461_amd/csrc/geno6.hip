@@ -8,9 +8,9 @@
 // the six-cell stencil for the three variables), guards them and evaluates
 // HLLC, the fluxes go back to LDS, and each lane finishes one cell: the flux
 // difference and the stage combination of the classical Runge-Kutta method.
-// The last stage also writes per-work-group maxima of |u| + a of the new
-// state, from which a one-work-group launch forms the next step's dt on the
-// device.
+// The last stage also folds the work-group maxima of |u| + a of the new
+// state into 1024 slots (atomic max), from which a one-work-group launch
+// forms the next step's dt on the device.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -36,6 +36,8 @@ constexpr int TB = 256;        // lanes per work-group
 constexpr int TC = TB - 1;     // cells per work-group (TB faces)
 constexpr int HALO = 3;        // cells needed on each side of a face stencil
 constexpr int TL = TC + 2 * HALO;   // staged cells per variable
+constexpr int NSLOT = 1024;         // slots of the wave-speed maxima (atomic max, bits of
+                                    // non-negative doubles order as unsigned integers)
 
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
@@ -132,30 +134,48 @@ __device__ __forceinline__ unsigned block_sum(unsigned v, unsigned* red) {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-// Start of geno6_step: counters cleared, per-work-group maxima of |u| + a of
-// the initial state (same tiling as the stage kernel).
-__global__ void __launch_bounds__(TB) k6_init(Geo6 g, double gamma, const double* __restrict__ U,
-                                               double* __restrict__ part, Ctrl6* ctrl) {
-  __shared__ double red[TB / 64];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+// Start of geno6_step: counters and maxima slots cleared (one work-group).
+__global__ void __launch_bounds__(TB) k6_clear(unsigned long long* __restrict__ slots, Ctrl6* ctrl) {
+  for (int q = threadIdx.x; q < NSLOT; q += TB) slots[q] = 0ull;
+  if (threadIdx.x == 0) {
     ctrl->guard = 0;
     ctrl->nonfinite = 0;
   }
+}
+
+// Work-group maximum s >= 0 into its slot (work-groups share a slot round
+// robin).
+__device__ __forceinline__ void slot_max(unsigned long long* slots, double s) {
+  if (threadIdx.x == 0)
+    atomicMax(&slots[blockIdx.x & (NSLOT - 1)], (unsigned long long)__double_as_longlong(s));
+}
+
+// Maxima of |u| + a of the initial state (same tiling as the stage kernel).
+__global__ void __launch_bounds__(TB) k6_init(Geo6 g, double gamma, const double* __restrict__ U,
+                                               unsigned long long* __restrict__ slots) {
+  __shared__ double red[TB / 64];
   const int c = (int)blockIdx.x * TC + (int)threadIdx.x;
   double s = 0.0;
   if (threadIdx.x < TC && c < g.n)
     s = wave_speed(gamma, U[c], U[(size_t)g.pitch + c], U[2 * (size_t)g.pitch + c]);
   s = block_max(s, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  slot_max(slots, s);
 }
 
-// dt of a step: cfl dx / max of the partial maxima (or dt_fixed).
-__global__ void __launch_bounds__(TB) k6_dt(const double* __restrict__ part, int npart, double dx,
+// dt of a step: cfl dx / max of the slots (or dt_fixed); the slots are
+// cleared for the maxima of the step's last stage. One work-group of TB
+// lanes, NSLOT / TB slots each.
+__global__ void __launch_bounds__(TB) k6_dt(unsigned long long* __restrict__ slots, double dx,
                                              double cfl, double dt_fixed, Ctrl6* ctrl,
                                              double* dt_out, int step) {
   __shared__ double red[TB / 64];
   double m = 0.0;
-  for (int q = threadIdx.x; q < npart; q += TB) m = fmax(m, part[q]);
+#pragma unroll
+  for (int q = 0; q < NSLOT / TB; ++q) {
+    unsigned long long& sl = slots[q * TB + threadIdx.x];
+    m = fmax(m, __longlong_as_double((long long)sl));
+    sl = 0ull;
+  }
   m = block_max(m, red);
   if (threadIdx.x == 0) {
     const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * dx / m;
@@ -174,7 +194,7 @@ template <int MODE>
 __global__ void __launch_bounds__(TB) k6_stage(Geo6 g, KP6 k, const double* __restrict__ Y,
                                                 const double* __restrict__ U0,
                                                 double* __restrict__ acc, double* __restrict__ Yout,
-                                                Ctrl6* ctrl, double* __restrict__ part) {
+                                                Ctrl6* ctrl, unsigned long long* __restrict__ slots) {
   __shared__ double su[3][TL];
   __shared__ double sf[3][TB];
   __shared__ double redd[TB / 64];
@@ -251,10 +271,8 @@ __global__ void __launch_bounds__(TB) k6_stage(Geo6 g, KP6 k, const double* __re
     }
     s = block_max(s, redd);
     const unsigned nbad = block_sum(bad, redu);
-    if (t == 0) {
-      part[blockIdx.x] = s;
-      if (nbad) atomicAdd(&ctrl->nonfinite, (unsigned long long)nbad);
-    }
+    slot_max(slots, s);
+    if (t == 0 && nbad) atomicAdd(&ctrl->nonfinite, (unsigned long long)nbad);
   }
 }
 
@@ -343,14 +361,14 @@ unsigned tiles(const geno6_grid* g) { return (unsigned)((g->n + TC - 1) / TC); }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WS6 {
-  size_t part, ya, yb, acc, total;
+  size_t slots, ya, yb, acc, total;
 };
 
 WS6 ws_layout(const geno6_grid* g) {
   WS6 w;
   size_t off = align256(sizeof(Ctrl6));
-  w.part = off;
-  off = align256(off + sizeof(double) * tiles(g));
+  w.slots = off;
+  off = align256(off + sizeof(unsigned long long) * NSLOT);
   const size_t arr = align256(sizeof(double) * 3 * (size_t)g->pitch);
   w.ya = off;
   off += arr;
@@ -418,7 +436,8 @@ int geno6_rhs(const geno6_grid* g, const double* U, double* L, void* stream) {
   if (rc) return rc;
   if (!U || !L) return fail(GENO_EINVAL, "null state");
   HIP_TRY(launch6(-1, k6_stage<4>, tiles(g), (hipStream_t)stream, geo6(g), kp6(g->params), U,
-                  (const double*)nullptr, (double*)nullptr, L, (Ctrl6*)nullptr, (double*)nullptr));
+                  (const double*)nullptr, (double*)nullptr, L, (Ctrl6*)nullptr,
+                  (unsigned long long*)nullptr));
   return GENO_OK;
 }
 
@@ -432,25 +451,25 @@ int geno6_step(const geno6_grid* g, double* U, void* ws, int nsteps, double* dt_
   const WS6 L = ws_layout(g);
   char* base = (char*)ws;
   Ctrl6* ctrl = (Ctrl6*)base;
-  double* part = (double*)(base + L.part);
+  unsigned long long* slots = (unsigned long long*)(base + L.slots);
   double* ya = (double*)(base + L.ya);
   double* yb = (double*)(base + L.yb);
   double* acc = (double*)(base + L.acc);
   const Geo6 geo = geo6(g);
   const KP6 k = kp6(g->params);
   const unsigned nb = tiles(g);
-  HIP_TRY(launch6(GENO6_K_INIT, k6_init, nb, s, geo, k.gamma, (const double*)U, part, ctrl));
+  HIP_TRY(launch6(-1, k6_clear, 1, s, slots, ctrl));
+  HIP_TRY(launch6(GENO6_K_INIT, k6_init, nb, s, geo, k.gamma, (const double*)U, slots));
   for (int st = 0; st < nsteps; ++st) {
-    HIP_TRY(launch6(GENO6_K_DT, k6_dt, 1, s, (const double*)part, (int)nb, g->dx, k.cfl, k.dt_fixed,
-                    ctrl, dt_out, st));
+    HIP_TRY(launch6(GENO6_K_DT, k6_dt, 1, s, slots, g->dx, k.cfl, k.dt_fixed, ctrl, dt_out, st));
     HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<0>, nb, s, geo, k, (const double*)U, (const double*)U,
-                    acc, ya, ctrl, part));
+                    acc, ya, ctrl, slots));
     HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<1>, nb, s, geo, k, (const double*)ya, (const double*)U,
-                    acc, yb, ctrl, part));
+                    acc, yb, ctrl, slots));
     HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<2>, nb, s, geo, k, (const double*)yb, (const double*)U,
-                    acc, ya, ctrl, part));
+                    acc, ya, ctrl, slots));
     HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<3>, nb, s, geo, k, (const double*)ya, (const double*)U,
-                    acc, U, ctrl, part));
+                    acc, U, ctrl, slots));
   }
   if (stats) {
     Ctrl6 h;

@@ -67,10 +67,12 @@ __host__ __device__ __forceinline__ Cand<D> candidates(D u0, D u1, D u2, D u3, D
 
 // Path function (Eq. (4), (5) with r = 2, Eq. (7), (9) and the Sec. 4.1
 // IS^tau). alpha = 2 aH / (aH + aL), aH = 1 + t^2/x^2, aL = 1 + t^2/y^2
-// (x = IS^H + eps, y = IS^L + eps) is formed with one division as
-// 2 y^2 (x^2 + t^2) / (2 x^2 y^2 + t^2 (x^2 + y^2)). tanh(z) for z >= 0 is
-// (1 - e)/(1 + e), e = exp(-2z); for z >= 19.8, e < 2^-54 and both
-// tanh(z) and tanh(C) (C >= z) round to 1, so chi is 1 exactly.
+// (x = IS^H + eps, y = IS^L + eps) is the fraction num / den with
+// num = 2 y^2 (x^2 + t^2), den = 2 x^2 y^2 + t^2 (x^2 + y^2). tanh(z) for
+// z >= 0 is (1 - e)/(1 + e), e = exp(-2z); for z = C alpha >= 19.8,
+// e < 2^-54 and both tanh(z) and tanh(C) (C >= z) round to 1, so chi is 1
+// exactly: that case is recognised without the division, as
+// C num >= 19.8 den (near the threshold both branches give 1).
 template <typename D>
 __host__ __device__ __forceinline__ D path_chi6(const D (&IS)[4], const KP6& k) {
   using std::fabs;
@@ -81,10 +83,11 @@ __host__ __device__ __forceinline__ D path_chi6(const D (&IS)[4], const KP6& k) 
   const D t = fabs(D(0.5) * (IS[0] + IS[2]) - IS[1]);
   const D x = ISH + D(k.eps), y = ISL + D(k.eps);
   const D x2 = x * x, y2 = y * y, t2 = t * t;
-  const D alpha = D(2.0) * y2 * (x2 + t2) / (D(2.0) * x2 * y2 + t2 * (x2 + y2));
-  const D z = D(k.C) * alpha;
-  if (!(z < D(19.8))) return D(1.0);
+  const D num = D(2.0) * y2 * (x2 + t2);
+  const D den = D(2.0) * x2 * y2 + t2 * (x2 + y2);
+  if (!(D(k.C) * num < D(19.8) * den)) return D(1.0);
   using std::exp;
+  const D z = D(k.C) * (num / den);
   const D e = exp(D(-2.0) * z);
   return (D(1.0) - e) / (D(1.0) + e) * D(k.inv_tanhC);
 }
@@ -129,17 +132,21 @@ __host__ __device__ __forceinline__ bool admissible6(const D* W) {
 // S_R = max(u_L + a_L, u_R + a_R), contact speed
 // S* = (p_R - p_L + m_L (S_L - u_L) - m_R (S_R - u_R)) /
 //      (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
-// star state of side K: rho_K (S_K - u_K)/(S_K - S*) *
-//   (1, S*, E_K/rho_K + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K)))),
+// star state of side K: f (1, S*, E_K/rho_K + (S* - u_K)(S* + p_K /
+// (rho_K (S_K - u_K)))), f = rho_K (S_K - u_K)/(S_K - S*),
 // F = F_K + S_K (U*_K - U_K) with K = L for S* >= 0, else R; F_L for
 // S_L >= 0, F_R for S_R <= 0. The star side is chosen by selects, so a
-// wave takes no branch.
+// wave takes no branch. Three divisions: 1/(rho_L rho_R) gives both
+// reciprocal densities, one for S*, and q = 1/((S_K - u_K)(S_K - S*))
+// gives f = rho_K (S_K - u_K)^2 q and p_K/(rho_K (S_K - u_K)) =
+// p_K (S_K - S*) q / rho_K.
 template <typename D>
 __host__ __device__ __forceinline__ void hllc6(const D* UL, const D* UR, D gamma, D* F) {
   using std::fmax;
   using std::fmin;
   using std::sqrt;
-  const D irl = D(1.0) / UL[0], irr = D(1.0) / UR[0];
+  const D irr_l = D(1.0) / (UL[0] * UR[0]);
+  const D irl = UR[0] * irr_l, irr = UL[0] * irr_l;
   const D ul = UL[1] * irl, ur = UR[1] * irr;
   const D gm1 = gamma - D(1.0);
   const D pl = gm1 * (UL[2] - D(0.5) * UL[1] * ul), pr = gm1 * (UR[2] - D(0.5) * UR[1] * ur);
@@ -151,8 +158,10 @@ __host__ __device__ __forceinline__ void hllc6(const D* UL, const D* UR, D gamma
   const D rK = left ? UL[0] : UR[0], mK = left ? UL[1] : UR[1], EK = left ? UL[2] : UR[2];
   const D uK = left ? ul : ur, pK = left ? pl : pr, irK = left ? irl : irr;
   const D SK = left ? SL : SR, dK = left ? dl : dr;
-  const D f = rK * dK / (SK - Ss);
-  const D Es = f * (EK * irK + (Ss - uK) * (Ss + pK * irK / dK));
+  const D gap = SK - Ss;
+  const D q = D(1.0) / (dK * gap);
+  const D f = rK * dK * dK * q;
+  const D Es = f * (EK * irK + (Ss - uK) * (Ss + pK * gap * q * irK));
   const D FK0 = mK, FK1 = mK * uK + pK, FK2 = (EK + pK) * uK;
   const D Fs0 = FK0 + SK * (f - rK), Fs1 = FK1 + SK * (f * Ss - mK), Fs2 = FK2 + SK * (Es - EK);
   const bool sup_l = SL >= D(0.0), sup_r = SR <= D(0.0);

@@ -309,19 +309,25 @@ def smooth_noncompact(n: int, seed: int, gamma: float = GAMMA, modes: int = 3):
 
 def shocks_noncompact(n: int, seed: int, gamma: float = GAMMA, cells_per_segment: int = 1000):
     """Seeded piecewise-smooth stand-in for the paper's 1-D shock problems at
-    any size: segments of about `cells_per_segment` cells (the paper's runs
-    use 200 to 1800 cells with one to three discontinuities), each a seeded
-    constant (rho, p in [0.1, 10], |u| <= 1; jumps of up to two decades, as
-    in the Shu-Osher and Titarev-Toro data) plus a density wave
-    rho (1 + a sin(k x)) with a in [0, 0.2] and 8 to 64 cells per period;
-    sampled at the cell centres."""
+    any size: segments of seeded lengths in [cells_per_segment / 2,
+    3 cells_per_segment / 2] (the paper's runs use 200 to 1800 cells with one
+    to three discontinuities between wide constant or smooth regions), each a
+    seeded constant state (rho, p in [10^-0.5, 10^0.5], |u| <= 0.5: jumps of
+    up to a factor 10, as the density and pressure jumps of the Shu-Osher and
+    Titarev-Toro data, and velocity jumps below the sound speeds, so that no
+    Riemann problem opens a near-vacuum) times a density wave
+    1 + a sin(2 pi i / P) with a in [0, 0.2] and P in [8, 64] cells; sampled
+    at the cell centres."""
     rng = np.random.default_rng(seed)
-    nseg = max(1, n // cells_per_segment)
-    edges = np.sort(rng.choice(np.arange(1, n), size=nseg - 1, replace=False)) if nseg > 1 else np.array([], int)
+    half = max(1, cells_per_segment // 2)
+    lens = rng.integers(half, 3 * half + 1, n // half + 2)
+    edges = np.cumsum(lens)
+    edges = edges[edges < n]
+    nseg = len(edges) + 1
     seg = np.searchsorted(edges, np.arange(n), side="right")
-    rho0 = 10.0 ** rng.uniform(-1.0, 1.0, nseg)
-    u0 = rng.uniform(-1.0, 1.0, nseg)
-    p0 = 10.0 ** rng.uniform(-1.0, 1.0, nseg)
+    rho0 = 10.0 ** rng.uniform(-0.5, 0.5, nseg)
+    u0 = rng.uniform(-0.5, 0.5, nseg)
+    p0 = 10.0 ** rng.uniform(-0.5, 0.5, nseg)
     amp = rng.uniform(0.0, 0.2, nseg)
     period = rng.uniform(8.0, 64.0, nseg)
     i = np.arange(n)

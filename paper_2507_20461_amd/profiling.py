@@ -35,7 +35,8 @@ CAL_ELEMS = CAL_BYTES // 8
 
 BENCH_FULL = ["python3", os.path.join(ROOT, "bench.py")]
 BENCH_SHORT = ["python3", os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
-               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms", "--no-batched"]
+               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms", "--no-batched", "--noncompact-steps", "2"]
+OWN = ("k_", "kb_", "k6_")   # prefixes of the library's kernels
 PASSES = {
     "ktrace": (["--kernel-trace", "--stats"], BENCH_FULL),
     "fetch": (["--pmc", "FETCH_SIZE"], BENCH_SHORT),
@@ -96,7 +97,7 @@ def _counters(path, counter):
 def _cal_scale(path, counter):
     best = 0.0
     for r in csv.DictReader(open(path)):
-        if r["Counter_Name"] == counter and not _short(r["Kernel_Name"]).startswith("k_"):
+        if r["Counter_Name"] == counter and not _short(r["Kernel_Name"]).startswith(OWN):
             best = max(best, float(r["Counter_Value"]) * 1024)
     if abs(best - CAL_BYTES) > 0.75 * CAL_BYTES:
         return None
@@ -119,9 +120,12 @@ def summarize(tag="faces_fp64_512"):
         if k.startswith("k_init<2"):
             n = int(round(cells ** 0.5))
             label = "%s %dx%d" % ("mixed" if "float" in k else "fp64", n, n)
+        if k.startswith("k6_init"):
+            # one geno6_step call: 255 cells per work-group of 256 lanes
+            label = "noncompact fp64 %d tiles of 255 cells" % (cells // 256)
         if k.startswith("kb_"):
             lab = "batched (mixed)"
-        elif label is None or not k.startswith("k_"):
+        elif label is None or not k.startswith(("k_", "k6_")):
             continue
         else:
             lab = label
@@ -131,7 +135,8 @@ def summarize(tag="faces_fp64_512"):
     lines.append("# command: " + " ".join(command("ktrace")).replace(ROOT + "/", ""))
     lines.append("# kernel sources sha256[:16]: " + sh)
     lines.append("# workload labels: element type and grid of the gks_step call (k_init grid size = cells,")
-    lines.append("# rounded to the next work-group); the bench's 512x512 workload is 'fp64 512x512'")
+    lines.append("# rounded to the next work-group); the bench's 512x512 workload is 'fp64 512x512', its")
+    lines.append("# 2^24-cell non-compact workload 'noncompact fp64 65794 tiles of 255 cells'")
     ktrace = {}
     for lab, ks in per.items():
         lines.append("")
@@ -139,7 +144,7 @@ def summarize(tag="faces_fp64_512"):
         lines.append("%-28s %7s %10s %10s" % ("kernel", "calls", "avg_us", "total_ms"))
         for k, v in sorted(ks.items(), key=lambda kv: -sum(kv[1])):
             lines.append("%-28s %7d %10.2f %10.3f" % (k[:28], len(v), sum(v) / len(v), sum(v) / 1e3))
-            if lab.startswith("fp64 512x512"):
+            if lab.startswith("fp64 512x512") or lab.startswith("noncompact fp64 65794 "):
                 ktrace.setdefault(k, []).extend(v)
     ktrace = {k: sum(v) / len(v) for k, v in ktrace.items()}
     open(os.path.join(PROFILES, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
@@ -154,7 +159,7 @@ def summarize(tag="faces_fp64_512"):
     avg = lambda v: sum(v) / len(v)
     rows = {}
     for k in sorted(F):
-        if not k.startswith("k_"):
+        if not k.startswith(("k_", "k6_")):
             continue
         f, w = avg(F[k]) * 1024, avg(Wr.get(k, [0.0])) * 1024
         insts = avg(V["SQ_INSTS_VALU"].get(k, [0.0]))
@@ -165,7 +170,8 @@ def summarize(tag="faces_fp64_512"):
                    "fetch_bytes_cal": f / fcal if fcal else None, "write_bytes_cal": w / wcal if wcal else None,
                    "valu_insts_per_wave": insts / waves if waves else None,
                    "valu_busy": 4.0 * active / SIMDS / gui if gui else None}
-    lines = ["# rocprofv3 counters per dispatch (3 separate --pmc passes), 2-D Euler 512x512 FP64",
+    lines = ["# rocprofv3 counters per dispatch (3 separate --pmc passes), 2-D Euler 512x512 FP64 (k_*) and",
+             "# the 1-D non-compact workload of 2^24 cells (k6_*)",
              "# commands:"]
     for name in ("fetch", "write", "valu"):
         lines.append("#   " + " ".join(command(name)).replace(ROOT + "/", ""))
@@ -192,7 +198,7 @@ def summarize(tag="faces_fp64_512"):
         lines.append("%-28s %9s %9s %9s %9s %11s %9s" % ("kernel", "wait_any", "wait_inst", "active", "vmem_act",
                                                        "trans64/wv", "vmemrd/wv"))
         for k in sorted(S["SQ_WAVE_CYCLES"]):
-            if not k.startswith("k_"):
+            if not k.startswith(("k_", "k6_")):
                 continue
             wc = avg(S["SQ_WAVE_CYCLES"][k]) or 1.0
             nw = avg(V["SQ_WAVES"].get(k, [1.0])) or 1.0

@@ -100,8 +100,8 @@ def test_noncompact_host_side_validation(so):
     assert (p.C, p.eps, list(p.d), p.cfl, list(p.bc)) == (20.0, 1e-15, [1.0, 8.0, 1.0, 1.0], 0.5, [0, 0])
     g = S.Grid6(1000, 0.0, 2.0)
     assert g.pitch == 1024 and g.dx == pytest.approx(0.002)
-    # control block, 4 tile maxima (255 cells each) and three stage arrays
-    assert S.lib().geno6_workspace_bytes(ctypes.byref(g.g)) >= 3 * 3 * 1024 * 8 + 4 * 8
+    # control block, 1024 maxima slots and three stage arrays
+    assert S.lib().geno6_workspace_bytes(ctypes.byref(g.g)) >= 3 * 3 * 1024 * 8 + 1024 * 8
     for kw in ({"n": 2}, {"n": 8, "x0": 1.0, "x1": 1.0}):
         with pytest.raises(G.GenoError):
             S.Grid6(**kw)
