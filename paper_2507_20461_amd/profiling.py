@@ -87,21 +87,33 @@ def _short(name):
 
 
 def _counters(path, counter):
+    """Per kernel name, the counter values of its dispatches on the largest
+    grid it ran on (the benchmark's workload; a kernel also launched on
+    smaller grids, as the non-compact stage on the paper's 1800-cell test,
+    is summarised at the large size only)."""
     d = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            d[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-    return d
+            d[_short(r["Kernel_Name"])].append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+    out = {}
+    for k, v in d.items():
+        g = max(x[0] for x in v)
+        out[k] = [x[1] for x in v if x[0] == g]
+    return out
 
 
 def _cal_scale(path, counter):
-    best = 0.0
-    for r in csv.DictReader(open(path)):
-        if r["Counter_Name"] == counter and not _short(r["Kernel_Name"]).startswith(OWN):
-            best = max(best, float(r["Counter_Value"]) * 1024)
-    if abs(best - CAL_BYTES) > 0.75 * CAL_BYTES:
-        return None
-    return best / CAL_BYTES
+    """The calibration copy is the first dispatch of the run (a device copy
+    of CAL_BYTES made before any of the method's kernels)."""
+    rows = sorted((r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter),
+                  key=lambda r: int(r["Dispatch_Id"]))
+    for r in rows:
+        if _short(r["Kernel_Name"]).startswith(OWN):
+            break
+        v = float(r["Counter_Value"]) * 1024
+        if abs(v - CAL_BYTES) <= 0.75 * CAL_BYTES:
+            return v / CAL_BYTES
+    return None
 
 
 def summarize(tag="faces_fp64_512"):
