@@ -213,13 +213,9 @@ __global__ void __launch_bounds__(TB) k6_stage(Geo6 g, KP6 k, const double* __re
   // face s = c0 + t between cells s-1 and s: stencil cells s-3..s+2 = LDS t..t+5
   unsigned guard = 0;
   if (c0 + t <= g.n) {
-    double u[3][6];
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-      for (int m = 0; m < 6; ++m) u[f][m] = su[f][t + m];
+    const auto get = [&](int f, int m) { return su[f][t + m]; };
     double WL[3], WR[3], F[3];
-    guard = (unsigned)geno6::face6<double>(u, k, WL, WR, F, nullptr);
+    guard = (unsigned)geno6::face6<double>(get, k, WL, WR, F, nullptr);
 #pragma unroll
     for (int f = 0; f < 3; ++f) sf[f][t] = F[f];
   }
@@ -287,8 +283,9 @@ __global__ void __launch_bounds__(TB) k6_faces(Geo6 g, KP6 k, const double* __re
   for (int f = 0; f < 3; ++f)
 #pragma unroll
     for (int m = 0; m < 6; ++m) u[f][m] = cell_at(g, U, f, s - HALO + m);
+  const auto get = [&](int f, int m) { return u[f][m]; };
   double WL[3], WR[3], FF[3], X[6];
-  geno6::face6<double>(u, k, WL, WR, FF, X);
+  geno6::face6<double>(get, k, WL, WR, FF, X);
   const size_t nf = (size_t)g.n + 1;
 #pragma unroll
   for (int f = 0; f < 3; ++f) {

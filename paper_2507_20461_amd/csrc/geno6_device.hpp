@@ -20,22 +20,37 @@ struct KP6 {
   double dt_fixed;
 };
 
-// Candidate values at the face and indicators for the state LEFT of
-// x_{j+1/2}; u[0..5] are the averages of cells j-2..j+3 (the right state is
-// this function on the reversed stencil). The coefficients follow from the
-// cell-average conditions of each candidate in xi = (x - x_j)/h:
-//   S_1 {j-2, j-1, j}   value (2 u0 - 7 u1 + 11 u2) / 6
-//   S_2 {j-1, j, j+1}   value (-u1 + 5 u2 + 2 u3) / 6
-//   S_3 {j-1..j+2}      value (-u1 + 7 u2 + 7 u3 - u4) / 12
-//   S_4 {j..j+3}        value (3 u2 + 13 u3 - 5 u4 + u5) / 12
+// Candidate values at the face and indicators of both states at the face
+// x_{j+1/2}; u[0..5] are the averages of cells j-2..j+3. The coefficients
+// follow from the cell-average conditions of each candidate in
+// xi = (x - x_t)/h about its target cell t (j for the left state, j+1 for
+// the right one, whose stencils are the mirror images about the face):
+//   S_1 {j-2, j-1, j}   face value (2 u0 - 7 u1 + 11 u2) / 6
+//   S_2 {j-1, j, j+1}   face value (-u1 + 5 u2 + 2 u3) / 6
+//   S_3 {j-1..j+2}      face value (-u1 + 7 u2 + 7 u3 - u4) / 12
+//   S_4 {j..j+3}        face value (3 u2 + 13 u3 - 5 u4 + u5) / 12
 // and Eq. (6) on the target cell, with p = sum a_k xi^k:
 //   quadratic: IS = a1^2 + 13/3 a2^2
 //   cubic:     IS = (a1 + a3/4)^2 + 13/3 a2^2 + 781/20 a3^2
-// (the integrals of p'^2, p''^2, p'''^2 over [-1/2, 1/2], completed to
-// squares). For S_3 and S_4 the linear combinations a1 + a3/4, a2, a3 of the
-// averages are (-2 u1 - 3 u2 + 6 u3 - u4)/6, (u1 - 2 u2 + u3)/2,
-// (-u1 + 3 u2 - 3 u3 + u4)/6 and (-11 u2 + 18 u3 - 9 u4 + 2 u5)/6,
-// (2 u2 - 5 u3 + 4 u4 - u5)/2, (-u2 + 3 u3 - 3 u4 + u5)/6.
+// (the integrals over [-1/2, 1/2] of the squared first, second and third
+// derivatives, completed to squares). Everything is written in the first
+// differences d_i = u_i - u_{i-1} (i = 1..5) and the second differences
+// D_a = d_2 - d_1, D_b = d_3 - d_2, D_c = d_4 - d_3, D_d = d_5 - d_4, which
+// the two states share. Left state (2 a1 and 2 a2 of S_1, S_2; 6 (a1 +
+// a3/4), 2 a2, 6 a3 of S_3, S_4):
+//   S_1: D_a + 2 d_2, D_a;   S_2: -(d_2 + d_3), D_b
+//   S_3: 2 d_2 + 5 d_3 - d_4, D_b, D_c - D_b
+//   S_4: 11 d_3 - 7 d_4 + 2 d_5, 2 D_c - D_d, D_d - D_c
+// face values u2 + (5 d_2 - 2 d_1)/6, u2 + (d_2 + 2 d_3)/6,
+// p_3 = (7 (u2 + u3) - u1 - u4)/12, u3 + (d_5 - 3 d_3 - 4 d_4)/12.
+// The right state is the same with d_i -> -d_{6-i} and D_a <-> D_d,
+// D_b <-> D_c (signs inside squares dropped):
+//   S_1: D_d - 2 d_4, D_d;   S_2: d_3 + d_4, D_c
+//   S_3: 2 d_4 + 5 d_3 - d_2, D_c, D_b - D_c (the square of S_3's a3 is
+//        the left state's)
+//   S_4: 11 d_3 - 7 d_2 + 2 d_1, 2 D_b - D_a, D_a - D_b
+// face values u3 + (2 d_5 - 5 d_4)/6, u3 - (d_4 + 2 d_3)/6, p_3,
+// u2 + (3 d_3 + 4 d_2 - d_1)/12.
 template <typename D>
 struct Cand {
   D v1, v2, v4;        // face values of p_1, p_2, p_4 (p_3 is shared by both sides)
@@ -43,26 +58,40 @@ struct Cand {
 };
 
 template <typename D>
-__host__ __device__ __forceinline__ Cand<D> candidates(D u0, D u1, D u2, D u3, D u4, D u5) {
-  Cand<D> c;
+__host__ __device__ __forceinline__ void candidates(const D (&u)[6], Cand<D>& L, Cand<D>& R, D& p5,
+                                                   D& p3) {
   const D sixth = D(1.0 / 6.0), twelfth = D(1.0 / 12.0);
-  c.v1 = (D(2.0) * u0 - D(7.0) * u1 + D(11.0) * u2) * sixth;
-  c.v2 = (D(5.0) * u2 + D(2.0) * u3 - u1) * sixth;
-  c.v4 = (D(3.0) * u2 + D(13.0) * u3 - D(5.0) * u4 + u5) * twelfth;
-  const D q1a = u0 - D(2.0) * u1 + u2, q1b = u0 - D(4.0) * u1 + D(3.0) * u2;
-  const D q2a = u1 - D(2.0) * u2 + u3, q2b = u1 - u3;
-  const D c3a = D(6.0) * u3 - D(2.0) * u1 - D(3.0) * u2 - u4;
-  const D c3c = D(3.0) * (u2 - u3) + u4 - u1;
-  const D c4a = D(18.0) * u3 - D(11.0) * u2 - D(9.0) * u4 + D(2.0) * u5;
-  const D c4b = D(2.0) * u2 - D(5.0) * u3 + D(4.0) * u4 - u5;
-  const D c4c = D(3.0) * (u3 - u4) + u5 - u2;
-  const D k13 = D(13.0 / 12.0), k36 = D(1.0 / 36.0), k781 = D(781.0 / 720.0);
-  const D m2 = k13 * q2a * q2a;   // 13/3 a2^2 of S_2, also of S_3
-  c.IS[0] = k13 * q1a * q1a + D(0.25) * q1b * q1b;
-  c.IS[1] = m2 + D(0.25) * q2b * q2b;
-  c.IS[2] = k36 * c3a * c3a + m2 + k781 * c3c * c3c;
-  c.IS[3] = k36 * c4a * c4a + k13 * c4b * c4b + k781 * c4c * c4c;
-  return c;
+  const D k13 = D(13.0 / 12.0), k36 = D(1.0 / 36.0), k781 = D(781.0 / 720.0), q = D(0.25);
+  const D d1 = u[1] - u[0], d2 = u[2] - u[1], d3 = u[3] - u[2], d4 = u[4] - u[3], d5 = u[5] - u[4];
+  const D Da = d2 - d1, Db = d3 - d2, Dc = d4 - d3, Dd = d5 - d4;
+  p5 = (u[0] + u[5] - D(8.0) * (u[1] + u[4]) + D(37.0) * (u[2] + u[3])) * D(1.0 / 60.0);
+  p3 = (D(7.0) * (u[2] + u[3]) - u[1] - u[4]) * twelfth;
+  // 13/3 a2^2 terms of the four second differences and the shared a3 term of S_3
+  const D Ka = k13 * Da * Da, Kb = k13 * Db * Db, Kc = k13 * Dc * Dc, Kd = k13 * Dd * Dd;
+  const D c3 = Dc - Db;
+  const D P3 = k781 * c3 * c3;
+  // left state
+  L.v1 = u[2] + (D(5.0) * d2 - D(2.0) * d1) * sixth;
+  L.v2 = u[2] + (d2 + D(2.0) * d3) * sixth;
+  L.v4 = u[3] + (d5 - D(3.0) * d3 - D(4.0) * d4) * twelfth;
+  const D l1 = Da + D(2.0) * d2, l2 = d2 + d3;
+  const D l3 = D(2.0) * d2 + D(5.0) * d3 - d4;
+  const D l4a = D(11.0) * d3 - D(7.0) * d4 + D(2.0) * d5, l4b = D(2.0) * Dc - Dd, l4c = Dd - Dc;
+  L.IS[0] = Ka + q * l1 * l1;
+  L.IS[1] = Kb + q * l2 * l2;
+  L.IS[2] = Kb + P3 + k36 * l3 * l3;
+  L.IS[3] = k36 * l4a * l4a + k13 * l4b * l4b + k781 * l4c * l4c;
+  // right state
+  R.v1 = u[3] + (D(2.0) * d5 - D(5.0) * d4) * sixth;
+  R.v2 = u[3] - (d4 + D(2.0) * d3) * sixth;
+  R.v4 = u[2] + (D(3.0) * d3 + D(4.0) * d2 - d1) * twelfth;
+  const D r1 = Dd - D(2.0) * d4, r2 = d3 + d4;
+  const D r3 = D(2.0) * d4 + D(5.0) * d3 - d2;
+  const D r4a = D(11.0) * d3 - D(7.0) * d2 + D(2.0) * d1, r4b = D(2.0) * Db - Da, r4c = Da - Db;
+  R.IS[0] = Kd + q * r1 * r1;
+  R.IS[1] = Kc + q * r2 * r2;
+  R.IS[2] = Kc + P3 + k36 * r3 * r3;
+  R.IS[3] = k36 * r4a * r4a + k13 * r4b * r4b + k781 * r4c * r4c;
 }
 
 // Path function (Eq. (4), (5) with r = 2, Eq. (7), (9) and the Sec. 4.1
@@ -172,19 +201,21 @@ __host__ __device__ __forceinline__ void hllc6(const D* UL, const D* UR, D gamma
   F[2] = sup_l ? FL2 : (sup_r ? FR2 : Fs2);
 }
 
-// One face: u[v][0..5] the averages of cells j-2..j+3 of variable v. Writes
-// the guarded states WL, WR, the flux F and (chi != nullptr) the six path
-// functions [side * 3 + v]; returns the number of guarded sides.
-template <typename D>
-__host__ __device__ __forceinline__ int face6(const D (&u)[3][6], const KP6& k, D* WL, D* WR,
-                                              D* F, D* chi) {
+// One face: get(v, m) returns the average of cell j-2+m (m = 0..5) of
+// variable v around the face x_{j+1/2} (a functor, so that a caller can
+// read each variable's stencil from LDS when it is needed and hold only
+// one in registers). Writes the guarded states WL, WR, the flux F and
+// (chi != nullptr) the six path functions [side * 3 + v]; returns the
+// number of guarded sides.
+template <typename D, typename Get>
+__host__ __device__ __forceinline__ int face6(const Get& get, const KP6& k, D* WL, D* WR, D* F,
+                                              D* chi) {
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    const D* s = u[v];
-    const D p5 = (s[0] + s[5] - D(8.0) * (s[1] + s[4]) + D(37.0) * (s[2] + s[3])) * D(1.0 / 60.0);
-    const D p3 = (D(7.0) * (s[2] + s[3]) - s[1] - s[4]) * D(1.0 / 12.0);
-    const Cand<D> cl = candidates(s[0], s[1], s[2], s[3], s[4], s[5]);
-    const Cand<D> cr = candidates(s[5], s[4], s[3], s[2], s[1], s[0]);
+    const D u[6] = {get(v, 0), get(v, 1), get(v, 2), get(v, 3), get(v, 4), get(v, 5)};
+    Cand<D> cl, cr;
+    D p5, p3;
+    candidates(u, cl, cr, p5, p3);
     D xl, xr;
     WL[v] = side6(cl, p5, p3, k, xl);
     WR[v] = side6(cr, p5, p3, k, xr);
@@ -196,12 +227,12 @@ __host__ __device__ __forceinline__ int face6(const D (&u)[3][6], const KP6& k, 
   int guard = 0;
   if (!admissible6(WL)) {
 #pragma unroll
-    for (int v = 0; v < 3; ++v) WL[v] = u[v][2];
+    for (int v = 0; v < 3; ++v) WL[v] = get(v, 2);
     ++guard;
   }
   if (!admissible6(WR)) {
 #pragma unroll
-    for (int v = 0; v < 3; ++v) WR[v] = u[v][3];
+    for (int v = 0; v < 3; ++v) WR[v] = get(v, 3);
     ++guard;
   }
   hllc6(WL, WR, D(k.gamma), F);

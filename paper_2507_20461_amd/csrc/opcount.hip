@@ -220,17 +220,21 @@ extern "C" int geno6_op_costs(double* costs) {
       u[1][m] = 0.1 + 0.01 * m;
       u[2][m] = 2.5 + 0.01 * m;
     }
-    (void)geno6::face6<C>(u, k, WL, WR, F, nullptr);
+    const auto get = [&](int v, int m) { return u[v][m]; };
+    (void)geno6::face6<C>(get, k, WL, WR, F, nullptr);
   });
+  geno6::Cand<C> cl, cr, sl, sr;
+  C p5, p3;
+  const C lin[6] = {1.0, 1.1, 1.2, 1.3, 1.4, 1.5}, step[6] = {1.0, 1.0, 1.0, 5.0, 5.0, 5.0};
+  geno6::candidates<C>(lin, cl, cr, p5, p3);
+  geno6::candidates<C>(step, sl, sr, p5, p3);
   const long long side_lin = count([&] {
-    const geno6::Cand<C> c = geno6::candidates<C>(1.0, 1.1, 1.2, 1.3, 1.4, 1.5);
     C x;
-    (void)geno6::side6<C>(c, C(1.25), C(1.25), k, x);
+    (void)geno6::side6<C>(cl, C(1.25), C(1.25), k, x);
   });
   const long long side_low = count([&] {
-    const geno6::Cand<C> c = geno6::candidates<C>(1.0, 1.0, 1.0, 5.0, 5.0, 5.0);
     C x;
-    (void)geno6::side6<C>(c, C(3.0), C(3.0), k, x);
+    (void)geno6::side6<C>(sl, C(3.0), C(3.0), k, x);
   });
   costs[0] = (double)face_lin;
   costs[1] = (double)(side_low - side_lin);
