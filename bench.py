@@ -271,8 +271,83 @@ def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_
     torch.cuda.synchronize()
     out["entropy_wave_1800"] = {"us_per_step": round(1e3 * e0.elapsed_time(e1) / 100, 2),
                                 "launches_per_step": 5}
+    out["paper_problems"] = noncompact_paper_runs(np, torch, inputs)
     if cpu:
         out["cpu_baseline"] = noncompact_cpu_baseline(np, inputs, seed, min_cpu_seconds)
+    return out
+
+
+def noncompact_paper_runs(np, torch, inputs):
+    """The paper's 1-D problems with the non-compact scheme (CFL 0.5): the
+    density-wave accuracy test (rho = 1 + 0.2 sin(pi x) on [0, 2], t = 2 on 6
+    to 192 cells, and t = 20 on 6 cells; a fixed dt = T / ceil(T / dt_CFL) of
+    the initial state so that every run ends at T), the entropy wave (1800
+    cells on [-800, 1000], t = 400, against the exact advected profile), the
+    Shu-Osher problem (200 cells, t = 1.8) and the Woodward-Colella blast
+    waves (400 cells, reflecting walls, t = 0.038, at CFL 0.5 and 0.2), the
+    last two run step by step with the device dt."""
+    from paper_2507_20461_amd import geno6 as S
+    from paper_2507_20461_amd import geno_gks as G
+    gam = 1.4
+
+    def fixed_dt(U, h, T, cfl=0.5):
+        rho, u = U[0], U[1] / U[0]
+        c = np.sqrt(gam * (gam - 1.0) * (U[2] - 0.5 * U[1] * u) / rho)
+        dt = cfl * h / float((np.abs(u) + c).max())
+        k = int(math.ceil(T / dt - 1e-12))
+        return T / k, k
+
+    def run_fixed(U, n, x0, x1, T, bc=0):
+        dt, k = fixed_dt(U, (x1 - x0) / n, T)
+        grid = S.Grid6(n, x0, x1, bc=bc, dt_fixed=dt)
+        Ud = grid.to_device(U)
+        st = S.step(grid, Ud, grid.workspace(), k, stats=True)
+        return grid.interior(Ud), k, st
+
+    out = {"density_wave": {"t": 2.0, "cfl": 0.5, "meshes": []}}
+    prev = None
+    for n in (6, 12, 24, 48, 96, 192):
+        V, k, _ = run_fixed(inputs.density_wave_noncompact(n), n, 0.0, 2.0, 2.0)
+        e = np.abs(V[0] - inputs.density_wave_noncompact(n, t=2.0)[0])
+        rec = {"n": n, "steps": k, "l1": float(e.mean()), "linf": float(e.max())}
+        if prev:
+            rec["order_l1"] = round(math.log2(prev / rec["l1"]), 3)
+        prev = rec["l1"]
+        out["density_wave"]["meshes"].append(rec)
+    V, k, _ = run_fixed(inputs.density_wave_noncompact(6), 6, 0.0, 2.0, 20.0)
+    out["density_wave"]["t20_on_6_cells"] = {
+        "steps": k, "l1": float(np.abs(V[0] - inputs.density_wave_noncompact(6, t=20.0)[0]).mean()),
+        "amplitude_kept": float(np.ptp(V[0]) / np.ptp(inputs.density_wave_noncompact(6)[0]))}
+    U = inputs.entropy_wave_noncompact(1800)
+    V, k, _ = run_fixed(U, 1800, -800.0, 1000.0, 400.0)
+    exact = np.roll(U[0], 400)   # one cell per unit length: t = 400 is a shift of 400 cells
+    out["entropy_wave"] = {"n": 1800, "t": 400.0, "steps": k, "l1": float(np.abs(V[0] - exact).mean()),
+                           "peak": float(V[0].max()), "exact_peak": float(exact.max())}
+    cases = [("shu_osher", inputs.shu_osher_1d, 200, (-5.0, 5.0), 1.8, 1, 0.5),
+             ("blast_wave", inputs.blast_wave_1d, 400, (0.0, 1.0), 0.038, 2, 0.5),
+             ("blast_wave", inputs.blast_wave_1d, 400, (0.0, 1.0), 0.038, 2, 0.2)]
+    for name, make, n, (x0, x1), T, bc, cfl in cases:
+        U = make(n)[0][:, 0, :]
+        grid = S.Grid6(n, x0, x1, bc=bc, cfl=cfl)
+        Ud, ws = grid.to_device(U), grid.workspace()
+        dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+        t, k, guard, failed = 0.0, 0, 0, None
+        while t < T and k < 20000:
+            try:
+                st = S.step(grid, Ud, ws, 1, dt_out=dts, stats=True)
+            except G.GenoError as e:
+                failed = "step %d, t = %.5f: %s" % (k + 1, t, e)
+                break
+            t += float(dts.item())
+            k += 1
+            guard += st.guard
+        V = grid.interior(Ud)
+        rec = {"n": n, "cfl": cfl, "steps": k, "t": round(t, 6), "guard": guard, "failed": failed}
+        if not failed:
+            rec["rho_range"] = [float(V[0].min()), float(V[0].max())]
+            if bc == 2:
+                rec["mass_energy_drift"] = [float(abs(V[f].sum() - U[f].sum()) / np.abs(U[f]).sum()) for f in (0, 2)]
+        out.setdefault(name, []).append(rec)
     return out
 
 
