@@ -23,8 +23,8 @@ _SO = os.path.join(_HERE, "libgeno6_oracle.so")
 _lib = None
 
 PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
-# parameter vector: gamma, C, eps, d1..d4, cfl, bc_lo, bc_hi, dt_fixed
-N_PARAMS = 11
+# parameter vector: gamma, C, eps, d1..d4, cfl, bc_lo, bc_hi, dt_fixed, characteristic
+N_PARAMS = 12
 
 
 def build(force: bool = True) -> str:
@@ -52,6 +52,8 @@ def lib():
         L.o6_smoothness.restype = d
         L.o6_side.argtypes = [dp, dp, i, dp]
         L.o6_side.restype = i
+        L.o6_eigen.argtypes = [dp, dp, dp, dp, dp, dp]
+        L.o6_eigen.restype = i
         L.o6_hllc.argtypes = [dp, dp, dp, dp]
         L.o6_hllc.restype = i
         L.o6_faces.argtypes = [dp, i, dp, dp, dp, dp, dp]
@@ -76,11 +78,23 @@ def _c(a):
 
 
 def params(bc=PERIODIC, gamma=1.4, C=20.0, eps=1e-15, d=(1.0, 8.0, 1.0, 1.0), cfl=0.5,
-           dt_fixed=0.0) -> np.ndarray:
+           dt_fixed=0.0, characteristic=False) -> np.ndarray:
     """Method constants of Sec. 3 and 4.1 (C = 20, eps = 1e-15, C_0 = 8 on the
-    central sub-stencil S_2). bc: one code or a (low, high) pair."""
+    central sub-stencil S_2). bc: one code or a (low, high) pair;
+    characteristic: reconstruct characteristic instead of conservative
+    variables."""
     lo, hi = (bc, bc) if np.isscalar(bc) else bc
-    return np.array([gamma, C, eps, *d, cfl, lo, hi, dt_fixed], dtype=np.float64)
+    return np.array([gamma, C, eps, *d, cfl, lo, hi, dt_fixed, 1.0 if characteristic else 0.0],
+                    dtype=np.float64)
+
+
+def eigen(prm, Ua, Ub):
+    """Roe-averaged right eigenvectors R, their inverse L (3x3) and the
+    speeds (u - c, u, u + c) of the face between states Ua and Ub."""
+    R, L, lam = np.zeros(9), np.zeros(9), np.zeros(3)
+    if lib().o6_eigen(_p(_c(prm)), _p(_c(Ua)), _p(_c(Ub)), _p(R), _p(L), _p(lam)):
+        raise ValueError("no eigen-structure (non-physical average)")
+    return R.reshape(3, 3), L.reshape(3, 3), lam
 
 
 def poly(avg, lo: int) -> np.ndarray:

@@ -33,7 +33,12 @@
  *   - The right-side state mirrors every stencil about x_{j+1/2}.
  *   - The central sub-stencil boosted by C_0 = 8 in Eq. (8) is S_2 (the one
  *     centred on the target cell): d = (1, 8, 1, 1).
- *   - Variables are reconstructed component by component (conservative).
+ *   - Variables are reconstructed component by component, either the
+ *     conservative ones or (option) the characteristic ones: the stencil's
+ *     states are projected on the left eigenvectors of the flux Jacobian at
+ *     the Roe average of the two cells at the face, reconstructed, and
+ *     mapped back with the right eigenvectors (a face whose Roe average has
+ *     no real sound speed keeps the conservative variables).
  *   - A reconstructed state with rho <= 0, p <= 0 or a non-finite entry is
  *     replaced by the target cell's average (guard).
  *   - HLLC (Toro): wave speeds S_L = min(u_L - a_L, u_R - a_R),
@@ -55,11 +60,12 @@
 #define O6_EINVAL -1
 #define O6_ENOMEM -2
 
-enum { Q_GAMMA = 0, Q_C, Q_EPS, Q_D1, Q_D2, Q_D3, Q_D4, Q_CFL, Q_BCL, Q_BCH, Q_DTFIX, Q_COUNT };
+enum { Q_GAMMA = 0, Q_C, Q_EPS, Q_D1, Q_D2, Q_D3, Q_D4, Q_CFL, Q_BCL, Q_BCH, Q_DTFIX, Q_CHAR, Q_COUNT };
 
 typedef struct {
   double gamma, C, eps, d[4], cfl, dt_fixed;
   int bc[2];   /* 0 periodic, 1 transmissive, 2 reflecting */
+  int characteristic;   /* 0: conservative variables, 1: characteristic variables */
 } cfg6;
 
 static void cfg_load(cfg6 *c, const double *p) {
@@ -67,6 +73,7 @@ static void cfg_load(cfg6 *c, const double *p) {
   for (int k = 0; k < 4; ++k) c->d[k] = p[Q_D1 + k];
   c->cfl = p[Q_CFL]; c->bc[0] = (int)p[Q_BCL]; c->bc[1] = (int)p[Q_BCH];
   c->dt_fixed = p[Q_DTFIX];
+  c->characteristic = (int)p[Q_CHAR];
 }
 
 /* ---------------------------------------------------------------------- */
@@ -232,6 +239,37 @@ static int admissible(const cfg6 *P, const double *U) {
 }
 
 /* ---------------------------------------------------------------------- */
+/* Characteristic variables (reading: Roe average of the two cells at the  */
+/* face, right eigenvectors of the Euler flux Jacobian there; the left     */
+/* ones are their inverse, obtained here by Gaussian elimination)          */
+/* ---------------------------------------------------------------------- */
+/* Roe average of Ua, Ub: (u, H, c); right eigenvectors R (columns for the
+ * speeds u - c, u, u + c, row-major R[row * 3 + col]) and L = R^-1. */
+static int eigen(const cfg6 *P, const double *Ua, const double *Ub, double *R, double *L,
+                 double *lam) {
+  const double sa = sqrt(Ua[0]), sb = sqrt(Ub[0]);
+  const double ua = Ua[1] / Ua[0], ub = Ub[1] / Ub[0];
+  const double Ha = (Ua[2] + pressure(P, Ua)) / Ua[0], Hb = (Ub[2] + pressure(P, Ub)) / Ub[0];
+  const double u = (sa * ua + sb * ub) / (sa + sb), H = (sa * Ha + sb * Hb) / (sa + sb);
+  const double c2 = (P->gamma - 1.0) * (H - 0.5 * u * u);
+  if (!(c2 > 0.0)) return O6_EINVAL;
+  const double c = sqrt(c2);
+  const double Rm[9] = {1.0, 1.0, 1.0,
+                        u - c, u, u + c,
+                        H - u * c, 0.5 * u * u, H + u * c};
+  for (int i = 0; i < 9; ++i) R[i] = Rm[i];
+  for (int col = 0; col < 3; ++col) {     /* L = R^-1, column by column */
+    double A[9], b[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 9; ++i) A[i] = Rm[i];
+    b[col] = 1.0;
+    if (gauss_solve(3, A, b)) return O6_EINVAL;
+    for (int r = 0; r < 3; ++r) L[r * 3 + col] = b[r];
+  }
+  if (lam) { lam[0] = u - c; lam[1] = u; lam[2] = u + c; }
+  return O6_OK;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Ghost cells and face states                                             */
 /* ---------------------------------------------------------------------- */
 /* Value of field f at cell index i in [-3, n+3) from the interior array. */
@@ -250,13 +288,32 @@ static double cell(const cfg6 *P, const double *U, int n, int f, int i) {
 static int face(const cfg6 *P, const double *U, int n, int s, double UL[3], double UR[3],
                 double F[3], double chi[6]) {
   int guard = 0;
+  double st[6][3];   /* the stencil's conservative states, cells s-3..s+2 */
+  for (int m = 0; m < 6; ++m)
+    for (int v = 0; v < 3; ++v) st[m][v] = cell(P, U, n, v, s - 3 + m);
+  double R[9], L[9];
+  /* a face whose Roe average has no real sound speed (non-physical cells)
+     falls back to the conservative variables */
+  const int ch = P->characteristic && eigen(P, st[2], st[3], R, L, NULL) == O6_OK;
+  double wl[3], wr[3];
   for (int v = 0; v < 3; ++v) {
     double u6[6], det[16];
-    for (int m = 0; m < 6; ++m) u6[m] = cell(P, U, n, v, s - 3 + m);
+    for (int m = 0; m < 6; ++m)
+      u6[m] = ch ? L[v * 3 + 0] * st[m][0] + L[v * 3 + 1] * st[m][1] + L[v * 3 + 2] * st[m][2]
+                 : st[m][v];
     if (geno_side(P, u6, 0, det)) return O6_EINVAL;
-    UL[v] = det[0]; if (chi) chi[v] = det[1];
+    wl[v] = det[0]; if (chi) chi[v] = det[1];
     if (geno_side(P, u6, 1, det)) return O6_EINVAL;
-    UR[v] = det[0]; if (chi) chi[3 + v] = det[1];
+    wr[v] = det[0]; if (chi) chi[3 + v] = det[1];
+  }
+  for (int v = 0; v < 3; ++v) {
+    if (ch) {
+      UL[v] = R[v * 3 + 0] * wl[0] + R[v * 3 + 1] * wl[1] + R[v * 3 + 2] * wl[2];
+      UR[v] = R[v * 3 + 0] * wr[0] + R[v * 3 + 1] * wr[1] + R[v * 3 + 2] * wr[2];
+    } else {
+      UL[v] = wl[v];
+      UR[v] = wr[v];
+    }
   }
   if (!admissible(P, UL)) { for (int v = 0; v < 3; ++v) UL[v] = cell(P, U, n, v, s - 1); ++guard; }
   if (!admissible(P, UR)) { for (int v = 0; v < 3; ++v) UR[v] = cell(P, U, n, v, s); ++guard; }
@@ -308,6 +365,13 @@ double o6_smoothness(const double *a, int n, int lmax) { return smoothness(a, n,
 int o6_side(const double *params, const double *u6, int side, double *detail) {
   cfg6 P; cfg_load(&P, params);
   return geno_side(&P, u6, side, detail);
+}
+
+/* Roe-averaged eigen-structure of the face between states Ua and Ub. */
+int o6_eigen(const double *params, const double *Ua, const double *Ub, double *R, double *L,
+             double *lam) {
+  cfg6 P; cfg_load(&P, params);
+  return eigen(&P, Ua, Ub, R, L, lam);
 }
 
 int o6_hllc(const double *params, const double *UL, const double *UR, double *F) {

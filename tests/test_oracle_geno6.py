@@ -283,3 +283,69 @@ def test_guard_replaces_a_non_physical_state():
             assert W[0] > 0 and (GAMMA - 1) * (W[2] - 0.5 * W[1] ** 2 / W[0]) > 0
             replaced += bool(np.array_equal(W, U[:, cell]))
     assert replaced >= g
+
+
+def test_roe_eigenstructure_satisfies_the_roe_property():
+    # A(U~) = R diag(lambda) L is the Roe matrix: A (U_R - U_L) = F(U_R) - F(U_L)
+    # exactly, and L R = I; the speeds are u~ -+ c~ and u~
+    prm = o6.params()
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        a = (rng.uniform(0.2, 3), rng.uniform(-2, 2), rng.uniform(0.2, 3))
+        b = (rng.uniform(0.2, 3), rng.uniform(-2, 2), rng.uniform(0.2, 3))
+        R, L, lam = o6.eigen(prm, cons(*a), cons(*b))
+        assert np.allclose(L @ R, np.eye(3), atol=1e-12)
+        A = R @ np.diag(lam) @ L
+        dF = euler_flux(*b) - euler_flux(*a)
+        assert np.allclose(A @ (cons(*b) - cons(*a)), dF, rtol=1e-11, atol=1e-11)
+        # each column of R is an eigenvector of the flux Jacobian at the Roe state
+        sa, sb = math.sqrt(a[0]), math.sqrt(b[0])
+        u = (sa * a[1] + sb * b[1]) / (sa + sb)
+        assert lam[1] == pytest.approx(u, rel=1e-12, abs=1e-13)
+        assert lam[0] < lam[1] < lam[2]
+
+
+def test_characteristic_reconstruction_equals_the_conservative_one_on_smooth_data():
+    # where every path function is 1 the reconstruction is the linear p^5,
+    # which commutes with the (face-wise constant) projection
+    # (compared on the faces where all twelve path functions are 1)
+    n = 64
+    U = inputs.smooth_noncompact(n, seed=4)
+    a = o6.faces(o6.params(), U)
+    b = o6.faces(o6.params(characteristic=True), U)
+    lin = np.all(a[3] == 1.0, axis=(0, 1)) & np.all(b[3] == 1.0, axis=(0, 1))
+    assert lin.sum() > n // 2
+    for x, y in zip(a[:3], b[:3]):
+        assert np.allclose(x[:, lin], y[:, lin], rtol=1e-12, atol=1e-12)
+
+
+def test_characteristic_reconstruction_of_an_isolated_contact():
+    # a contact (u, p equal, rho jumps) moves only the entropy field: the
+    # characteristic states keep u and p exactly constant, and the flux is
+    # the exact contact flux
+    n = 24
+    rho = np.where(np.arange(n) < 12, 1.0, 0.3)
+    U = np.stack([rho, 0.5 * rho, 1.0 / (GAMMA - 1) + 0.125 * rho])
+    UL, UR, F, chi, g = o6.faces(o6.params(bc=o6.TRANSMISSIVE, characteristic=True), U)
+    for W in (UL, UR):
+        u = W[1] / W[0]
+        p = (GAMMA - 1) * (W[2] - 0.5 * W[1] * u)
+        assert np.allclose(u, 0.5, atol=1e-12) and np.allclose(p, 1.0, atol=1e-12)
+    # u > 0: the contact flux carries the left state's density
+    assert np.allclose(F[0], 0.5 * UL[0], rtol=1e-12)
+    assert np.allclose(F[1], 0.25 * UL[0] + 1.0, rtol=1e-12)
+
+
+def test_characteristic_step_conserves_and_mirrors():
+    n = 40
+    U = inputs.smooth_noncompact(n, seed=9)
+    U[:, 10:14] *= 1.7
+    prm = o6.params(bc=o6.REFLECTING, dt_fixed=2e-3, characteristic=True)
+    Uw, _, _ = o6.step(prm, U, 1.0 / n, 10)
+    M = U[:, ::-1].copy()
+    M[1] *= -1
+    Dp, _, _ = o6.step(o6.params(bc=o6.PERIODIC, dt_fixed=2e-3, characteristic=True),
+                       np.concatenate([U, M], axis=1), 1.0 / n, 10)
+    assert np.allclose(Uw, Dp[:, :n], rtol=1e-11, atol=1e-12)
+    for v in (0, 2):
+        assert abs(Uw[v].sum() - U[v].sum()) <= 1e-12 * np.abs(U[v]).sum()
