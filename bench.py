@@ -360,7 +360,7 @@ def noncompact_traffic():
     meta = json.load(open(COUNTERS))
     if meta.get("source_hash") != profiling.source_hash():
         return None, "counters taken on other kernel sources"
-    rows = [meta["kernels"].get("k6_stage<%d>" % m) for m in range(4)]
+    rows = [meta["kernels"].get("k6_stage<%d, false>" % m) for m in range(4)]
     if not all(rows) or any(r.get("fetch_bytes_cal") is None or r.get("write_bytes_cal") is None for r in rows):
         return None, None
     f = sum(r["fetch_bytes_cal"] for r in rows) / 4
@@ -379,7 +379,7 @@ def noncompact_valu_busy():
     meta = json.load(open(COUNTERS))
     if meta.get("source_hash") != profiling.source_hash():
         return None
-    rows = [meta["kernels"].get("k6_stage<%d>" % m) for m in range(4)]
+    rows = [meta["kernels"].get("k6_stage<%d, false>" % m) for m in range(4)]
     if not all(rows) or any(r.get("valu_busy") is None for r in rows):
         return None
     return {"valu_busy": round(sum(r["valu_busy"] for r in rows) / 4, 4),

@@ -43,7 +43,11 @@
 extern "C" {
 #endif
 
-#define GENO6_ABI_VERSION 1
+#define GENO6_ABI_VERSION 2
+
+/* variables the reconstruction works on */
+#define GENO6_VARS_CONSERVATIVE 0
+#define GENO6_VARS_CHARACTERISTIC 1
 
 /* Method parameters.
  * gamma: ratio of specific heats (> 1).
@@ -57,7 +61,15 @@ extern "C" {
  * bc: low and high end (GENO_BC_PERIODIC on both or neither;
  *   GENO_BC_TRANSMISSIVE copies the end cell; GENO_BC_REFLECTING mirrors
  *   the cells with the momentum negated).
- * dt_fixed: if > 0, every step uses this dt instead of the CFL condition. */
+ * dt_fixed: if > 0, every step uses this dt instead of the CFL condition.
+ * variables: GENO6_VARS_CONSERVATIVE (default) reconstructs rho, rho U,
+ *   rho E component by component; GENO6_VARS_CHARACTERISTIC projects the
+ *   stencil's states on the left eigenvectors of the Euler flux Jacobian at
+ *   the Roe average of the two cells at the face, reconstructs the three
+ *   characteristic fields and maps both face states back with the right
+ *   eigenvectors (a face whose Roe average has no real sound speed keeps
+ *   the conservative variables). The paper does not say which variables it
+ *   reconstructs. */
 typedef struct geno6_params {
   int version;
   double gamma;
@@ -67,6 +79,7 @@ typedef struct geno6_params {
   double cfl;
   int bc[2];
   double dt_fixed;
+  int variables;
 } geno6_params;
 
 typedef struct geno6_grid {
@@ -77,7 +90,7 @@ typedef struct geno6_grid {
 } geno6_grid;
 
 /* Defaults: gamma 1.4, C 20, eps 1e-15, d (1, 8, 1, 1), cfl 0.5, periodic,
- * dt_fixed 0. */
+ * dt_fixed 0, conservative variables. */
 int geno6_params_default(geno6_params* p);
 
 /* Fills *g for n uniform cells on [x0, x1] and copies *p. GENO_EINVAL for
@@ -92,8 +105,8 @@ size_t geno6_workspace_bytes(const geno6_grid* g);
 /* Reconstruction and flux at every face s = 0..n (Sec. 4.1 and the HLLC
  * flux): UL, UR the guarded left and right states, F the HLLC flux, each
  * [3][n + 1]; chi (may be NULL) the path function of every side and
- * variable before the guard, [side(2)][3][n + 1]. Any of UL, UR, F may be
- * NULL. */
+ * variable (characteristic field with GENO6_VARS_CHARACTERISTIC) before the
+ * guard, [side(2)][3][n + 1]. Any of UL, UR, F may be NULL. */
 int geno6_faces(const geno6_grid* g, const double* U, double* UL, double* UR, double* F,
                 double* chi, void* stream);
 

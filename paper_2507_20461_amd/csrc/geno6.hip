@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(TB) k6_dt(unsigned long long* __restrict__ slo
 //   2: acc += dt/3 L,    Yout = U0 + dt L
 //   3: Yout = acc + dt/6 L (= the new U), maxima of |u| + a, non-physical
 //      cells counted
-template <int MODE>
+template <int MODE, bool CHAR>
 __global__ void __launch_bounds__(TB) k6_stage(Geo6 g, KP6 k, const double* __restrict__ Y,
                                                 const double* __restrict__ U0,
                                                 double* __restrict__ acc, double* __restrict__ Yout,
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(TB) k6_stage(Geo6 g, KP6 k, const double* __re
   if (c0 + t <= g.n) {
     const auto get = [&](int f, int m) { return su[f][t + m]; };
     double WL[3], WR[3], F[3];
-    guard = (unsigned)geno6::face6<double>(get, k, WL, WR, F, nullptr);
+    guard = (unsigned)geno6::face6<double, CHAR>(get, k, WL, WR, F, nullptr);
 #pragma unroll
     for (int f = 0; f < 3; ++f) sf[f][t] = F[f];
   }
@@ -273,6 +273,7 @@ __global__ void __launch_bounds__(TB) k6_stage(Geo6 g, KP6 k, const double* __re
 }
 
 // Reconstruction and flux of every face (output form of geno6_faces).
+template <bool CHAR>
 __global__ void __launch_bounds__(TB) k6_faces(Geo6 g, KP6 k, const double* __restrict__ U,
                                                 double* __restrict__ UL, double* __restrict__ UR,
                                                 double* __restrict__ F, double* __restrict__ chi) {
@@ -285,7 +286,7 @@ __global__ void __launch_bounds__(TB) k6_faces(Geo6 g, KP6 k, const double* __re
     for (int m = 0; m < 6; ++m) u[f][m] = cell_at(g, U, f, s - HALO + m);
   const auto get = [&](int f, int m) { return u[f][m]; };
   double WL[3], WR[3], FF[3], X[6];
-  geno6::face6<double>(get, k, WL, WR, FF, X);
+  geno6::face6<double, CHAR>(get, k, WL, WR, FF, X);
   const size_t nf = (size_t)g.n + 1;
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
@@ -311,6 +312,8 @@ int check_params6(const geno6_params* p) {
   for (int i = 0; i < 4; ++i)
     if (!(p->d[i] > 0.0)) return fail(GENO_EINVAL, "linear weights d must be positive");
   if (!(p->dt_fixed >= 0.0)) return fail(GENO_EINVAL, "dt_fixed must be >= 0");
+  if (p->variables != GENO6_VARS_CONSERVATIVE && p->variables != GENO6_VARS_CHARACTERISTIC)
+    return fail(GENO_EINVAL, "bad variables code %d", p->variables);
   for (int i = 0; i < 2; ++i)
     if (p->bc[i] != GENO_BC_PERIODIC && p->bc[i] != GENO_BC_TRANSMISSIVE &&
         p->bc[i] != GENO_BC_REFLECTING)
@@ -350,6 +353,7 @@ KP6 kp6(const geno6_params& p) {
   for (int i = 0; i < 4; ++i) k.d[i] = p.d[i];
   k.cfl = p.cfl;
   k.dt_fixed = p.dt_fixed;
+  k.characteristic = p.variables == GENO6_VARS_CHARACTERISTIC;
   return k;
 }
 
@@ -394,6 +398,7 @@ int geno6_params_default(geno6_params* p) {
   p->cfl = 0.5;
   p->bc[0] = p->bc[1] = GENO_BC_PERIODIC;
   p->dt_fixed = 0.0;
+  p->variables = GENO6_VARS_CONSERVATIVE;
   return GENO_OK;
 }
 
@@ -424,7 +429,11 @@ int geno6_faces(const geno6_grid* g, const double* U, double* UL, double* UR, do
   if (rc) return rc;
   if (!U) return fail(GENO_EINVAL, "null state");
   const unsigned nb = (unsigned)((g->n + 1 + TB - 1) / TB);
-  HIP_TRY(launch6(-1, k6_faces, nb, (hipStream_t)stream, geo6(g), kp6(g->params), U, UL, UR, F, chi));
+  const KP6 k = kp6(g->params);
+  if (k.characteristic)
+    HIP_TRY(launch6(-1, k6_faces<true>, nb, (hipStream_t)stream, geo6(g), k, U, UL, UR, F, chi));
+  else
+    HIP_TRY(launch6(-1, k6_faces<false>, nb, (hipStream_t)stream, geo6(g), k, U, UL, UR, F, chi));
   return GENO_OK;
 }
 
@@ -432,9 +441,10 @@ int geno6_rhs(const geno6_grid* g, const double* U, double* L, void* stream) {
   const int rc = check_grid6(g);
   if (rc) return rc;
   if (!U || !L) return fail(GENO_EINVAL, "null state");
-  HIP_TRY(launch6(-1, k6_stage<4>, tiles(g), (hipStream_t)stream, geo6(g), kp6(g->params), U,
-                  (const double*)nullptr, (double*)nullptr, L, (Ctrl6*)nullptr,
-                  (unsigned long long*)nullptr));
+  const KP6 k = kp6(g->params);
+  auto kern = k.characteristic ? k6_stage<4, true> : k6_stage<4, false>;
+  HIP_TRY(launch6(-1, kern, tiles(g), (hipStream_t)stream, geo6(g), k, U, (const double*)nullptr,
+                  (double*)nullptr, L, (Ctrl6*)nullptr, (unsigned long long*)nullptr));
   return GENO_OK;
 }
 
@@ -457,16 +467,21 @@ int geno6_step(const geno6_grid* g, double* U, void* ws, int nsteps, double* dt_
   const unsigned nb = tiles(g);
   HIP_TRY(launch6(-1, k6_clear, 1, s, slots, ctrl));
   HIP_TRY(launch6(GENO6_K_INIT, k6_init, nb, s, geo, k.gamma, (const double*)U, slots));
+  const bool ch = k.characteristic;
+  auto s0 = ch ? k6_stage<0, true> : k6_stage<0, false>;
+  auto s1 = ch ? k6_stage<1, true> : k6_stage<1, false>;
+  auto s2 = ch ? k6_stage<2, true> : k6_stage<2, false>;
+  auto s3 = ch ? k6_stage<3, true> : k6_stage<3, false>;
   for (int st = 0; st < nsteps; ++st) {
     HIP_TRY(launch6(GENO6_K_DT, k6_dt, 1, s, slots, g->dx, k.cfl, k.dt_fixed, ctrl, dt_out, st));
-    HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<0>, nb, s, geo, k, (const double*)U, (const double*)U,
-                    acc, ya, ctrl, slots));
-    HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<1>, nb, s, geo, k, (const double*)ya, (const double*)U,
-                    acc, yb, ctrl, slots));
-    HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<2>, nb, s, geo, k, (const double*)yb, (const double*)U,
-                    acc, ya, ctrl, slots));
-    HIP_TRY(launch6(GENO6_K_STAGE, k6_stage<3>, nb, s, geo, k, (const double*)ya, (const double*)U,
-                    acc, U, ctrl, slots));
+    HIP_TRY(launch6(GENO6_K_STAGE, s0, nb, s, geo, k, (const double*)U, (const double*)U, acc, ya,
+                    ctrl, slots));
+    HIP_TRY(launch6(GENO6_K_STAGE, s1, nb, s, geo, k, (const double*)ya, (const double*)U, acc, yb,
+                    ctrl, slots));
+    HIP_TRY(launch6(GENO6_K_STAGE, s2, nb, s, geo, k, (const double*)yb, (const double*)U, acc, ya,
+                    ctrl, slots));
+    HIP_TRY(launch6(GENO6_K_STAGE, s3, nb, s, geo, k, (const double*)ya, (const double*)U, acc, U,
+                    ctrl, slots));
   }
   if (stats) {
     Ctrl6 h;

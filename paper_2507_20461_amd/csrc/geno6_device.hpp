@@ -18,6 +18,7 @@ struct KP6 {
   double d[4];       // linear weights of S_1..S_4 (Eq. (8))
   double cfl;
   double dt_fixed;
+  int characteristic;   // reconstruct characteristic fields (0 or 1)
 };
 
 // Candidate values at the face and indicators of both states at the face
@@ -201,15 +202,61 @@ __host__ __device__ __forceinline__ void hllc6(const D* UL, const D* UR, D gamma
   F[2] = sup_l ? FL2 : (sup_r ? FR2 : Fs2);
 }
 
-// One face: get(v, m) returns the average of cell j-2+m (m = 0..5) of
-// variable v around the face x_{j+1/2} (a functor, so that a caller can
-// read each variable's stencil from LDS when it is needed and hold only
-// one in registers). Writes the guarded states WL, WR, the flux F and
-// (chi != nullptr) the six path functions [side * 3 + v]; returns the
-// number of guarded sides.
+// Roe average of the two cells at a face and the eigenvectors of the Euler
+// flux Jacobian there, for the speeds u - c, u, u + c: right eigenvectors
+// (columns) (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c); left
+// ones (rows of the inverse), with b1 = (gamma - 1)/c^2, b2 = b1 u^2 / 2:
+// ((b2 + u/c)/2, -(b1 u + 1/c)/2, b1/2), (1 - b2, b1 u, -b1),
+// ((b2 - u/c)/2, -(b1 u - 1/c)/2, b1/2). Returns false when the average has
+// no real sound speed (the face then keeps the conservative variables).
+template <typename D>
+struct Eig {
+  D u, c, H;
+  D L[3][3];
+};
+
+template <typename D>
+__host__ __device__ __forceinline__ bool roe_eigen(const D* Wa, const D* Wb, D gamma, Eig<D>& e) {
+  using std::sqrt;
+  const D sa = sqrt(Wa[0]), sb = sqrt(Wb[0]);
+  const D isa = D(1.0) / sa, isb = D(1.0) / sb, iss = D(1.0) / (sa + sb);
+  const D gm1 = gamma - D(1.0);
+  // sqrt(rho) u = m / sqrt(rho); sqrt(rho) H = (E + p) / sqrt(rho)
+  const D pa = gm1 * (Wa[2] - D(0.5) * Wa[1] * Wa[1] * isa * isa);
+  const D pb = gm1 * (Wb[2] - D(0.5) * Wb[1] * Wb[1] * isb * isb);
+  e.u = (Wa[1] * isa + Wb[1] * isb) * iss;
+  e.H = ((Wa[2] + pa) * isa + (Wb[2] + pb) * isb) * iss;
+  const D c2 = gm1 * (e.H - D(0.5) * e.u * e.u);
+  if (!(c2 > D(0.0))) return false;
+  e.c = sqrt(c2);
+  const D ic = D(1.0) / e.c;
+  const D b1 = gm1 * ic * ic, b2 = D(0.5) * b1 * e.u * e.u, uc = e.u * ic;
+  e.L[0][0] = D(0.5) * (b2 + uc);
+  e.L[0][1] = D(-0.5) * (b1 * e.u + ic);
+  e.L[0][2] = D(0.5) * b1;
+  e.L[1][0] = D(1.0) - b2;
+  e.L[1][1] = b1 * e.u;
+  e.L[1][2] = -b1;
+  e.L[2][0] = D(0.5) * (b2 - uc);
+  e.L[2][1] = D(-0.5) * (b1 * e.u - ic);
+  e.L[2][2] = D(0.5) * b1;
+  return true;
+}
+
+// W = R w with the right eigenvectors of e.
+template <typename D>
+__host__ __device__ __forceinline__ void from_characteristic(const Eig<D>& e, const D* w, D* W) {
+  const D uc = e.u * e.c;
+  W[0] = w[0] + w[1] + w[2];
+  W[1] = (e.u - e.c) * w[0] + e.u * w[1] + (e.u + e.c) * w[2];
+  W[2] = (e.H - uc) * w[0] + D(0.5) * e.u * e.u * w[1] + (e.H + uc) * w[2];
+}
+
+// GENO states of the three fields of one face: get(v, m) returns field v of
+// cell j-2+m (m = 0..5) around the face x_{j+1/2}.
 template <typename D, typename Get>
-__host__ __device__ __forceinline__ int face6(const Get& get, const KP6& k, D* WL, D* WR, D* F,
-                                              D* chi) {
+__host__ __device__ __forceinline__ void reconstruct6(const Get& get, const KP6& k, D* WL, D* WR,
+                                                      D* chi) {
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     const D u[6] = {get(v, 0), get(v, 1), get(v, 2), get(v, 3), get(v, 4), get(v, 5)};
@@ -224,6 +271,34 @@ __host__ __device__ __forceinline__ int face6(const Get& get, const KP6& k, D* W
       chi[3 + v] = xr;
     }
   }
+}
+
+// One face: get(v, m) returns the average of cell j-2+m (m = 0..5) of
+// conservative variable v around the face x_{j+1/2} (a functor, so that a
+// caller can read each variable's stencil from LDS when it is needed and
+// hold only one in registers). CHAR: reconstruct characteristic fields
+// (with the conservative fallback of roe_eigen). Writes the guarded states
+// WL, WR, the flux F and (chi != nullptr) the six path functions
+// [side * 3 + v]; returns the number of guarded sides.
+template <typename D, bool CHAR, typename Get>
+__host__ __device__ __forceinline__ int face6(const Get& get, const KP6& k, D* WL, D* WR, D* F,
+                                              D* chi) {
+  bool done = false;
+  if constexpr (CHAR) {
+    const D Wa[3] = {get(0, 2), get(1, 2), get(2, 2)}, Wb[3] = {get(0, 3), get(1, 3), get(2, 3)};
+    Eig<D> e;
+    if (roe_eigen(Wa, Wb, D(k.gamma), e)) {
+      const auto getw = [&](int v, int m) {
+        return e.L[v][0] * get(0, m) + e.L[v][1] * get(1, m) + e.L[v][2] * get(2, m);
+      };
+      D wl[3], wr[3];
+      reconstruct6<D>(getw, k, wl, wr, chi);
+      from_characteristic(e, wl, WL);
+      from_characteristic(e, wr, WR);
+      done = true;
+    }
+  }
+  if (!done) reconstruct6<D>(get, k, WL, WR, chi);
   int guard = 0;
   if (!admissible6(WL)) {
 #pragma unroll

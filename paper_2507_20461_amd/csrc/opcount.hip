@@ -212,6 +212,7 @@ extern "C" int geno6_op_costs(double* costs) {
   k.d[3] = 1.0;
   k.cfl = 0.5;
   k.dt_fixed = 0.0;
+  k.characteristic = 0;
   // linear data of an admissible subsonic state (rho, rho u, rho E)
   const long long face_lin = count([&] {
     C u[3][6], WL[3], WR[3], F[3];
@@ -221,7 +222,7 @@ extern "C" int geno6_op_costs(double* costs) {
       u[2][m] = 2.5 + 0.01 * m;
     }
     const auto get = [&](int v, int m) { return u[v][m]; };
-    (void)geno6::face6<C>(get, k, WL, WR, F, nullptr);
+    (void)geno6::face6<C, false>(get, k, WL, WR, F, nullptr);
   });
   geno6::Cand<C> cl, cr, sl, sr;
   C p5, p3;

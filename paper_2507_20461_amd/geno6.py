@@ -13,7 +13,8 @@ import torch
 
 from . import geno_gks as G
 
-ABI_VERSION = 1
+ABI_VERSION = 2
+VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
 KERNELS = ("init", "dt", "stage")
 EXPORTS = ("geno6_params_default", "geno6_grid_init", "geno6_workspace_bytes", "geno6_faces", "geno6_rhs",
            "geno6_step", "geno6_timing_enable", "geno6_timing_read", "geno6_op_costs")
@@ -22,7 +23,7 @@ EXPORTS = ("geno6_params_default", "geno6_grid_init", "geno6_workspace_bytes", "
 class geno6_params(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int), ("gamma", ctypes.c_double), ("C", ctypes.c_double),
                 ("eps", ctypes.c_double), ("d", ctypes.c_double * 4), ("cfl", ctypes.c_double),
-                ("bc", ctypes.c_int * 2), ("dt_fixed", ctypes.c_double)]
+                ("bc", ctypes.c_int * 2), ("dt_fixed", ctypes.c_double), ("variables", ctypes.c_int)]
 
 
 class geno6_grid(ctypes.Structure):

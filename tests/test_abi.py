@@ -97,7 +97,8 @@ def test_noncompact_host_side_validation(so):
     from paper_2507_20461_amd import geno6 as S
     from paper_2507_20461_amd import geno_gks as G
     p = S.default_params()
-    assert (p.C, p.eps, list(p.d), p.cfl, list(p.bc)) == (20.0, 1e-15, [1.0, 8.0, 1.0, 1.0], 0.5, [0, 0])
+    assert (p.C, p.eps, list(p.d), p.cfl, list(p.bc), p.variables) == (20.0, 1e-15, [1.0, 8.0, 1.0, 1.0], 0.5,
+                                                                      [0, 0], S.VARS_CONSERVATIVE)
     g = S.Grid6(1000, 0.0, 2.0)
     assert g.pitch == 1024 and g.dx == pytest.approx(0.002)
     # control block, 1024 maxima slots and three stage arrays
@@ -105,7 +106,8 @@ def test_noncompact_host_side_validation(so):
     for kw in ({"n": 2}, {"n": 8, "x0": 1.0, "x1": 1.0}):
         with pytest.raises(G.GenoError):
             S.Grid6(**kw)
-    for bad in ({"bc": (0, 1)}, {"d": (1, 8, 0, 1)}, {"cfl": 0.0}, {"bc": (3, 3)}, {"dt_fixed": -1.0}):
+    for bad in ({"bc": (0, 1)}, {"d": (1, 8, 0, 1)}, {"cfl": 0.0}, {"bc": (3, 3)}, {"dt_fixed": -1.0},
+                {"variables": 2}):
         with pytest.raises(G.GenoError):
             S.Grid6(16, params=S.default_params(**bad))
     v = S.default_params()
