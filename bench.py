@@ -257,6 +257,27 @@ def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_
            "kernels": {k: {"ms_total": round(v[0], 4), "launches": v[1],
                            "us_avg": round(1e3 * v[0] / v[1], 3) if v[1] else None} for k, v in kt.items()},
            "roofline": roof}
+    # the same steps with characteristic-variable reconstruction
+    gc = S.Grid6(n, 0.0, 1.0, bc=1, cfl=0.5, variables=S.VARS_CHARACTERISTIC)
+    Ud.copy_(U0)
+    S.step(gc, Ud, ws, 2)
+    Ud.copy_(U0)
+    torch.cuda.synchronize()
+    S.timing_enable(5 * steps + 4)
+    e0.record()
+    S.step(gc, Ud, ws, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    kc = S.timing_read()
+    S.timing_enable(0)
+    msc = e0.elapsed_time(e1)
+    Vc = Ud[:, :n]
+    pc = 0.4 * (Vc[2] - 0.5 * Vc[1] * Vc[1] / Vc[0])
+    bad = int((~torch.isfinite(Vc).all(dim=0) | (Vc[0] <= 0) | (pc <= 0)).sum().item())
+    out["characteristic"] = {"value": round(4.0 * n * steps / (msc / 1e3) / 1e6, 3),
+                             "ms_per_step": round(msc / steps, 5), "nonphysical_cells_after_run": bad,
+                             "stage_us_avg": round(1e3 * kc["stage"][0] / kc["stage"][1], 3),
+                             "note": "timed with events bound to every launch"}
     del ws, Ud, U0, Uend
     # the paper's 1-D sizes are far below what fills the GPU: a run of the
     # entropy-wave test (1800 cells, 100 steps) shows the launch-bound rate
@@ -284,8 +305,9 @@ def noncompact_paper_runs(np, torch, inputs):
     the initial state so that every run ends at T), the entropy wave (1800
     cells on [-800, 1000], t = 400, against the exact advected profile), the
     Shu-Osher problem (200 cells, t = 1.8) and the Woodward-Colella blast
-    waves (400 cells, reflecting walls, t = 0.038, at CFL 0.5 and 0.2), the
-    last two run step by step with the device dt."""
+    waves (400 cells, reflecting walls, t = 0.038, at CFL 0.5 and 0.05), the
+    last two with conservative and characteristic variables, run step by
+    step with the device dt."""
     from paper_2507_20461_amd import geno6 as S
     from paper_2507_20461_amd import geno_gks as G
     gam = 1.4
@@ -323,12 +345,12 @@ def noncompact_paper_runs(np, torch, inputs):
     exact = np.roll(U[0], 400)   # one cell per unit length: t = 400 is a shift of 400 cells
     out["entropy_wave"] = {"n": 1800, "t": 400.0, "steps": k, "l1": float(np.abs(V[0] - exact).mean()),
                            "peak": float(V[0].max()), "exact_peak": float(exact.max())}
-    cases = [("shu_osher", inputs.shu_osher_1d, 200, (-5.0, 5.0), 1.8, 1, 0.5),
-             ("blast_wave", inputs.blast_wave_1d, 400, (0.0, 1.0), 0.038, 2, 0.5),
-             ("blast_wave", inputs.blast_wave_1d, 400, (0.0, 1.0), 0.038, 2, 0.2)]
-    for name, make, n, (x0, x1), T, bc, cfl in cases:
+    cases = [("shu_osher", inputs.shu_osher_1d, 200, (-5.0, 5.0), 1.8, 1, 0.5, v) for v in (0, 1)]
+    cases += [("blast_wave", inputs.blast_wave_1d, 400, (0.0, 1.0), 0.038, 2, cfl, v)
+              for cfl in (0.5, 0.05) for v in (0, 1)]
+    for name, make, n, (x0, x1), T, bc, cfl, var in cases:
         U = make(n)[0][:, 0, :]
-        grid = S.Grid6(n, x0, x1, bc=bc, cfl=cfl)
+        grid = S.Grid6(n, x0, x1, bc=bc, cfl=cfl, variables=var)
         Ud, ws = grid.to_device(U), grid.workspace()
         dts = torch.zeros(1, dtype=torch.float64, device="cuda")
         t, k, guard, failed = 0.0, 0, 0, None
@@ -342,7 +364,8 @@ def noncompact_paper_runs(np, torch, inputs):
             k += 1
             guard += st.guard
         V = grid.interior(Ud)
-        rec = {"n": n, "cfl": cfl, "steps": k, "t": round(t, 6), "guard": guard, "failed": failed}
+        rec = {"n": n, "cfl": cfl, "variables": ("conservative", "characteristic")[var], "steps": k,
+               "t": round(t, 6), "guard": guard, "failed": failed}
         if not failed:
             rec["rho_range"] = [float(V[0].min()), float(V[0].max())]
             if bc == 2:
