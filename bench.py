@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched workload")
     ap.add_argument("--noncompact-steps", type=int, default=40,
                     help="timed Runge-Kutta steps of the 1-D sixth-order non-compact workload (0 = skip)")
+    ap.add_argument("--no-paper-problems", action="store_true",
+                    help="skip the paper's 1-D problems with the non-compact scheme")
     return ap.parse_args()
 
 
@@ -177,7 +179,8 @@ NONCOMPACT_N = 1 << 24
 NONCOMPACT_STAGE_BYTES = (72.0, 120.0, 120.0, 72.0)   # algorithmic HBM bytes per cell of stages 1..4
 
 
-def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_seconds=10.0, cpu=True):
+def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_seconds=10.0, cpu=True,
+                        paper=True):
     """The sixth-order non-compact scheme (GENO on the six-cell stencil, HLLC,
     classical Runge-Kutta) on 2^24 cells of the seeded piecewise-smooth 1-D
     state (segments of ~1000 cells, transmissive ends, CFL 0.5), FP64.
@@ -292,7 +295,8 @@ def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_
     torch.cuda.synchronize()
     out["entropy_wave_1800"] = {"us_per_step": round(1e3 * e0.elapsed_time(e1) / 100, 2),
                                 "launches_per_step": 5}
-    out["paper_problems"] = noncompact_paper_runs(np, torch, inputs)
+    if paper:
+        out["paper_problems"] = noncompact_paper_runs(np, torch, inputs)
     if cpu:
         out["cpu_baseline"] = noncompact_cpu_baseline(np, inputs, seed, min_cpu_seconds)
     return out
@@ -779,7 +783,8 @@ def main():
         out["robustness"] = _finite(robustness_runs(G, inputs, np, torch))
     if args.noncompact_steps > 0:
         out["noncompact"] = _finite(noncompact_workload(np, torch, inputs, args.seed, args.noncompact_steps,
-                                                        cpu=not args.no_cpu_baseline))
+                                                        cpu=not args.no_cpu_baseline,
+                                                        paper=not args.no_paper_problems))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)
     print(json.dumps(out), flush=True)

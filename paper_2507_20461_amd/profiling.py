@@ -2,8 +2,9 @@
 
 Usage on a GPU machine (from the repository root)::
 
-    python -m paper_2507_20461_amd.profiling run       # kernel trace + counter passes
-    python -m paper_2507_20461_amd.profiling summarize # write profiles/*.txt
+    python -m paper_2507_20461_amd.profiling run       # kernel trace + counter passes,
+                                                       # summaries into gpurun_out/profiles
+    python -m paper_2507_20461_amd.profiling summarize # summaries into profiles/
 
 Each counter pass is its own rocprofv3 run (FETCH_SIZE, WRITE_SIZE, VALU
 activity). Summaries record the commands, the per-kernel averages and a hash of
@@ -35,7 +36,8 @@ CAL_ELEMS = CAL_BYTES // 8
 
 BENCH_FULL = ["python3", os.path.join(ROOT, "bench.py")]
 BENCH_SHORT = ["python3", os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
-               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms", "--no-batched", "--noncompact-steps", "2"]
+               "--no-cpu-baseline", "--no-kernel-timing", "--no-forms", "--no-batched", "--noncompact-steps", "2",
+               "--no-paper-problems"]
 OWN = ("k_", "kb_", "k6_")   # prefixes of the library's kernels
 PASSES = {
     "ktrace": (["--kernel-trace", "--stats"], BENCH_FULL),
@@ -79,6 +81,10 @@ def run(extra=()):
         print("   exit %d, results %s" % (rc, "present" if os.path.exists(res) else "missing"), flush=True)
         if rc != 0 and not (rc in (139, -11) and os.path.exists(res)):
             sys.exit(rc if rc > 0 else 1)
+    # summaries next to the raw output; the per-dispatch kernel trace (tens
+    # of MB for the default benchmark) is dropped once summarised
+    summarize(dest=os.path.join(OUT, "profiles"))
+    os.remove(os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv"))
 
 
 def _short(name):
@@ -116,8 +122,8 @@ def _cal_scale(path, counter):
     return None
 
 
-def summarize(tag="faces_fp64_512"):
-    os.makedirs(PROFILES, exist_ok=True)
+def summarize(tag="faces_fp64_512", dest=PROFILES):
+    os.makedirs(dest, exist_ok=True)
     sh = source_hash()
     lines = []
     # kernel trace, per workload: every gks_step call starts with k_init, so
@@ -159,7 +165,7 @@ def summarize(tag="faces_fp64_512"):
             if lab.startswith("fp64 512x512") or lab.startswith("noncompact fp64 65794 "):
                 ktrace.setdefault(k, []).extend(v)
     ktrace = {k: sum(v) / len(v) for k, v in ktrace.items()}
-    open(os.path.join(PROFILES, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(dest, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
     # counters
     F = _counters(os.path.join(OUT, "prof_fetch", "run_counter_collection.csv"), "FETCH_SIZE")
     Wr = _counters(os.path.join(OUT, "prof_write", "run_counter_collection.csv"), "WRITE_SIZE")
@@ -218,10 +224,10 @@ def summarize(tag="faces_fp64_512"):
                 k[:28], avg(S["SQ_WAIT_ANY"][k]) / wc, avg(S["SQ_WAIT_INST_ANY"][k]) / wc,
                 avg(S["SQ_ACTIVE_INST_ANY"][k]) / wc, avg(S["SQ_ACTIVE_INST_VMEM"][k]) / wc,
                 avg(S["SQ_INSTS_VALU_TRANS_F64"][k]) / nw, avg(S["SQ_INSTS_VMEM_RD"][k]) / nw))
-    open(os.path.join(PROFILES, "%s_counters.txt" % tag), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(dest, "%s_counters.txt" % tag), "w").write("\n".join(lines) + "\n")
     meta = {"source_hash": sh, "calibration": {"fetch": fcal, "write": wcal}, "kernels": rows,
             "ktrace_avg_us": ktrace}
-    open(os.path.join(PROFILES, "%s_counters.json" % tag), "w").write(json.dumps(meta, indent=1) + "\n")
+    open(os.path.join(dest, "%s_counters.json" % tag), "w").write(json.dumps(meta, indent=1) + "\n")
     print("\n".join(lines))
 
 
