@@ -22,9 +22,10 @@ _SRC = os.path.join(_HERE, "geno6_oracle.c")
 _SO = os.path.join(_HERE, "libgeno6_oracle.so")
 _lib = None
 
-PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
-# parameter vector: gamma, C, eps, d1..d4, cfl, bc_lo, bc_hi, dt_fixed, characteristic
-N_PARAMS = 12
+PERIODIC, TRANSMISSIVE, REFLECTING, FIXED = 0, 1, 2, 3
+# parameter vector: gamma, C, eps, d1..d4, cfl, bc_lo, bc_hi, dt_fixed, characteristic,
+# then 18 ghost values [end][cell k][field] of fixed ends
+N_PARAMS = 30
 
 
 def build(force: bool = True) -> str:
@@ -78,13 +79,15 @@ def _c(a):
 
 
 def params(bc=PERIODIC, gamma=1.4, C=20.0, eps=1e-15, d=(1.0, 8.0, 1.0, 1.0), cfl=0.5,
-           dt_fixed=0.0, characteristic=False) -> np.ndarray:
+           dt_fixed=0.0, characteristic=False, ghost=None) -> np.ndarray:
     """Method constants of Sec. 3 and 4.1 (C = 20, eps = 1e-15, C_0 = 8 on the
     central sub-stencil S_2). bc: one code or a (low, high) pair;
     characteristic: reconstruct characteristic instead of conservative
-    variables."""
+    variables; ghost: [2, 3, 3] states of the ghost cells of FIXED ends
+    ([end][cell k][field], cell -1-k or n+k)."""
     lo, hi = (bc, bc) if np.isscalar(bc) else bc
-    return np.array([gamma, C, eps, *d, cfl, lo, hi, dt_fixed, 1.0 if characteristic else 0.0],
+    g = np.zeros(18) if ghost is None else np.asarray(ghost, dtype=np.float64).reshape(18)
+    return np.array([gamma, C, eps, *d, cfl, lo, hi, dt_fixed, 1.0 if characteristic else 0.0, *g],
                     dtype=np.float64)
 
 

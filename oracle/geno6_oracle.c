@@ -47,7 +47,8 @@
  *   - dt = cfl dx / max over cells of (|u| + a), taken at the start of the
  *     step; classical Runge-Kutta stages with weights 1/6, 1/3, 1/3, 1/6.
  *   - Ghost cells: periodic images; transmissive = copy of the nearest
- *     interior cell; reflecting = mirror image with the momentum negated.
+ *     interior cell; reflecting = mirror image with the momentum negated;
+ *     fixed = given states (inflow or a fixed profile).
  *
  * Layout of every state array handed in: SoA [field][n], fields
  * (rho, rho U, rho E), interior cells only.
@@ -60,12 +61,15 @@
 #define O6_EINVAL -1
 #define O6_ENOMEM -2
 
-enum { Q_GAMMA = 0, Q_C, Q_EPS, Q_D1, Q_D2, Q_D3, Q_D4, Q_CFL, Q_BCL, Q_BCH, Q_DTFIX, Q_CHAR, Q_COUNT };
+enum { Q_GAMMA = 0, Q_C, Q_EPS, Q_D1, Q_D2, Q_D3, Q_D4, Q_CFL, Q_BCL, Q_BCH, Q_DTFIX, Q_CHAR,
+       Q_GHOST,                /* 18 values: [end][ghost cell k][field] for fixed ends */
+       Q_COUNT = Q_GHOST + 18 };
 
 typedef struct {
   double gamma, C, eps, d[4], cfl, dt_fixed;
-  int bc[2];   /* 0 periodic, 1 transmissive, 2 reflecting */
+  int bc[2];   /* 0 periodic, 1 transmissive, 2 reflecting, 3 fixed states */
   int characteristic;   /* 0: conservative variables, 1: characteristic variables */
+  double ghost[2][3][3];  /* fixed ends: [end][k][field], cell -1-k or n+k */
 } cfg6;
 
 static void cfg_load(cfg6 *c, const double *p) {
@@ -74,6 +78,9 @@ static void cfg_load(cfg6 *c, const double *p) {
   c->cfl = p[Q_CFL]; c->bc[0] = (int)p[Q_BCL]; c->bc[1] = (int)p[Q_BCH];
   c->dt_fixed = p[Q_DTFIX];
   c->characteristic = (int)p[Q_CHAR];
+  for (int e = 0; e < 2; ++e)
+    for (int k = 0; k < 3; ++k)
+      for (int f = 0; f < 3; ++f) c->ghost[e][k][f] = p[Q_GHOST + (e * 3 + k) * 3 + f];
 }
 
 /* ---------------------------------------------------------------------- */
@@ -276,6 +283,7 @@ static int eigen(const cfg6 *P, const double *Ua, const double *Ub, double *R, d
 static double cell(const cfg6 *P, const double *U, int n, int f, int i) {
   if (i >= 0 && i < n) return U[(size_t)f * n + i];
   const int lo = i < 0, bc = P->bc[lo ? 0 : 1];
+  if (bc == 3) return P->ghost[lo ? 0 : 1][lo ? -i - 1 : i - n][f];
   if (bc == 0) return U[(size_t)f * n + (lo ? i + n : i - n)];
   if (bc == 1) return U[(size_t)f * n + (lo ? 0 : n - 1)];
   const int src = lo ? -i - 1 : 2 * n - 1 - i;

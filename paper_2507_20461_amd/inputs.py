@@ -333,3 +333,34 @@ def shocks_noncompact(n: int, seed: int, gamma: float = GAMMA, cells_per_segment
     i = np.arange(n)
     rho = rho0[seg] * (1.0 + amp[seg] * np.sin(2.0 * math.pi * i / period[seg]))
     return _cons_1d(rho, u0[seg], p0[seg], gamma)
+
+
+TITAREV_TORO_LEFT = (1.515695, 0.523346, 1.805)   # (rho, u, p) behind the shock
+
+
+def titarev_toro_noncompact(n: int = 1000, gamma: float = GAMMA):
+    """The Titarev-Toro problem of Sec. 6.2 on [-5, 5]: (rho, u, p) =
+    TITAREV_TORO_LEFT on x <= -4, rho = 1 + 0.1 sin(20 pi x), u = 0, p = 1 on
+    x > -4 (exact cell averages; the jump sits on a face when n is a
+    multiple of 10); end time 5. Returns U and the ghost states [2, 3, 3] of
+    the paper's boundaries: the inflow state on the left and the fixed wave
+    profile (the cell averages of the three cells beyond x = 5) on the
+    right."""
+    if n % 10:
+        raise ValueError("n must be a multiple of 10 (jump on a face)")
+    h = 10.0 / n
+
+    def averages(xl):
+        xr = xl + h
+        return 1.0 + 0.1 * (np.cos(20.0 * math.pi * xl) - np.cos(20.0 * math.pi * xr)) / (20.0 * math.pi * h)
+
+    xl = -5.0 + np.arange(n) * h
+    left = xl + h <= -4.0 + 1e-12
+    rl, ul, pl = TITAREV_TORO_LEFT
+    rho = np.where(left, rl, averages(xl))
+    U = _cons_1d(rho, np.where(left, ul, 0.0), np.where(left, pl, 1.0), gamma)
+    ghost = np.zeros((2, 3, 3))
+    ghost[0] = np.asarray(_cons_1d(np.full(3, rl), np.full(3, ul), np.full(3, pl), gamma)).T
+    xg = 5.0 + np.arange(3) * h
+    ghost[1] = np.asarray(_cons_1d(averages(xg), np.zeros(3), np.ones(3), gamma)).T
+    return U, ghost

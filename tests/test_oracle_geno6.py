@@ -349,3 +349,32 @@ def test_characteristic_step_conserves_and_mirrors():
     assert np.allclose(Uw, Dp[:, :n], rtol=1e-11, atol=1e-12)
     for v in (0, 2):
         assert abs(Uw[v].sum() - U[v].sum()) <= 1e-12 * np.abs(U[v]).sum()
+
+
+def test_fixed_ends_reproduce_the_other_kinds():
+    # fixed ghost states equal to the copies of the end cells give the
+    # transmissive right-hand side, equal to the periodic images the
+    # periodic one (a run differs afterwards: fixed ghosts do not follow
+    # the end cells)
+    n = 30
+    U = inputs.smooth_noncompact(n, seed=6)
+    g = np.zeros((2, 3, 3))
+    g[0] = np.repeat(U[:, :1].T, 3, axis=0)
+    g[1] = np.repeat(U[:, -1:].T, 3, axis=0)
+    a, _ = o6.rhs(o6.params(bc=o6.FIXED, ghost=g), U, 1.0 / n)
+    b, _ = o6.rhs(o6.params(bc=o6.TRANSMISSIVE), U, 1.0 / n)
+    assert np.array_equal(a, b)
+    g[0] = U[:, [-1, -2, -3]].T      # cells -1, -2, -3 are n-1, n-2, n-3
+    g[1] = U[:, [0, 1, 2]].T         # cells n, n+1, n+2 are 0, 1, 2
+    La, _ = o6.rhs(o6.params(bc=o6.FIXED, ghost=g), U, 1.0 / n)
+    Lb, _ = o6.rhs(o6.params(bc=o6.PERIODIC), U, 1.0 / n)
+    assert np.array_equal(La, Lb)
+
+
+def test_titarev_toro_data():
+    U, g = inputs.titarev_toro_noncompact(1000)
+    rho = U[0]
+    assert np.allclose(rho[:100], 1.515695) and abs(rho[100:].mean() - 1.0) < 1e-3
+    # exact averages of 1 + 0.1 sin(20 pi x) over the 10 cells of a period sum to 10
+    assert abs(rho[100:110].sum() - 10.0) < 1e-12
+    assert np.allclose(g[0, :, 0], 1.515695) and np.allclose(g[1, :, 1], 0.0)
