@@ -308,10 +308,11 @@ def noncompact_paper_runs(np, torch, inputs):
     to 192 cells, and t = 20 on 6 cells; a fixed dt = T / ceil(T / dt_CFL) of
     the initial state so that every run ends at T), the entropy wave (1800
     cells on [-800, 1000], t = 400, against the exact advected profile), the
-    Shu-Osher problem (200 cells, t = 1.8) and the Woodward-Colella blast
-    waves (400 cells, reflecting walls, t = 0.038, at CFL 0.5 and 0.05), the
-    last two with conservative and characteristic variables, run step by
-    step with the device dt."""
+    Shu-Osher problem (200 cells, t = 1.8), the Woodward-Colella blast waves
+    (400 cells, reflecting walls, t = 0.038, at CFL 0.5 and 0.05) and the
+    Titarev-Toro problem (1000 cells, inflow and fixed-profile ends, t = 5),
+    the last three with conservative and characteristic variables, run step
+    by step with the device dt."""
     from paper_2507_20461_amd import geno6 as S
     from paper_2507_20461_amd import geno_gks as G
     gam = 1.4
@@ -352,9 +353,14 @@ def noncompact_paper_runs(np, torch, inputs):
     cases = [("shu_osher", inputs.shu_osher_1d, 200, (-5.0, 5.0), 1.8, 1, 0.5, v) for v in (0, 1)]
     cases += [("blast_wave", inputs.blast_wave_1d, 400, (0.0, 1.0), 0.038, 2, cfl, v)
               for cfl in (0.5, 0.05) for v in (0, 1)]
+    cases += [("titarev_toro", None, 1000, (-5.0, 5.0), 5.0, S.BC_FIXED, 0.5, v) for v in (0, 1)]
     for name, make, n, (x0, x1), T, bc, cfl, var in cases:
-        U = make(n)[0][:, 0, :]
-        grid = S.Grid6(n, x0, x1, bc=bc, cfl=cfl, variables=var)
+        if make is None:
+            U, ghost = inputs.titarev_toro_noncompact(n)
+            grid = S.Grid6(n, x0, x1, bc=bc, cfl=cfl, variables=var, ghost=ghost)
+        else:
+            U = make(n)[0][:, 0, :]
+            grid = S.Grid6(n, x0, x1, bc=bc, cfl=cfl, variables=var)
         Ud, ws = grid.to_device(U), grid.workspace()
         dts = torch.zeros(1, dtype=torch.float64, device="cuda")
         t, k, guard, failed = 0.0, 0, 0, None
@@ -743,7 +749,14 @@ def main():
         else:
             roofline = {"bound": "alu", "kernel": dominant, "achieved": d["tflops"],
                         "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac}
+        vb = None
+        if tdetail and isinstance(tdetail, dict):
+            meta = json.load(open(COUNTERS))
+            row = meta["kernels"].get(ROCPROF_NAMES.get(dominant, ""), {})
+            vb = {"valu_busy": round(row["valu_busy"], 4), "valu_insts_per_wave": round(row["valu_insts_per_wave"], 1)} \
+                if row.get("valu_busy") is not None else None
         roofline.update({
+            "counters": vb,
             "traffic": round(tbytes) if tbytes else None, "traffic_detail": tdetail,
             "algorithmic_mb_per_launch": d["mb_per_launch"], "us_per_launch": d["us_avg"],
             "arithmetic_intensity": round(ai, 3) if ai else None, "ridge_flop_per_byte": round(ridge, 3),

@@ -43,7 +43,12 @@
 extern "C" {
 #endif
 
-#define GENO6_ABI_VERSION 2
+#define GENO6_ABI_VERSION 3
+
+/* boundary kind of this path beside GENO_BC_PERIODIC, _TRANSMISSIVE and
+ * _REFLECTING: the three ghost cells hold given states (inflow, or a fixed
+ * profile) */
+#define GENO6_BC_FIXED 3
 
 /* variables the reconstruction works on */
 #define GENO6_VARS_CONSERVATIVE 0
@@ -60,7 +65,11 @@ extern "C" {
  *   the start of each step (the paper runs with CFL >= 0.5; default 0.5).
  * bc: low and high end (GENO_BC_PERIODIC on both or neither;
  *   GENO_BC_TRANSMISSIVE copies the end cell; GENO_BC_REFLECTING mirrors
- *   the cells with the momentum negated).
+ *   the cells with the momentum negated; GENO6_BC_FIXED takes the states of
+ *   `ghost`).
+ * ghost: conserved states (rho, rho U, rho E) of the three ghost cells of
+ *   each end for GENO6_BC_FIXED: ghost[0][k] is cell -1-k, ghost[1][k] is
+ *   cell n+k (k = 0 next to the grid). Unused for the other kinds.
  * dt_fixed: if > 0, every step uses this dt instead of the CFL condition.
  * variables: GENO6_VARS_CONSERVATIVE (default) reconstructs rho, rho U,
  *   rho E component by component; GENO6_VARS_CHARACTERISTIC projects the
@@ -80,6 +89,7 @@ typedef struct geno6_params {
   int bc[2];
   double dt_fixed;
   int variables;
+  double ghost[2][3][3];
 } geno6_params;
 
 typedef struct geno6_grid {

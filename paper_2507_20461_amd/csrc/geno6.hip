@@ -54,6 +54,7 @@ struct Ctrl6 {
 struct Geo6 {
   int n, pitch, bc_lo, bc_hi;
   double dx, inv_dx;
+  double ghost[2][3][3];   // GENO6_BC_FIXED states: [end][cell k][field]
 };
 
 // ---------------------------------------------------------------------------
@@ -86,6 +87,8 @@ hipError_t launch6(int kind, void (*kern)(KArgs...), unsigned grid, hipStream_t 
 __device__ __forceinline__ double cell_at(const Geo6& g, const double* __restrict__ U, int f, int i) {
   int src = i;
   double sign = 1.0;
+  if (i < 0 && g.bc_lo == GENO6_BC_FIXED) return g.ghost[0][-i - 1][f];
+  if (i >= g.n && g.bc_hi == GENO6_BC_FIXED) return g.ghost[1][i - g.n][f];
   if (i < 0) {
     src = g.bc_lo == GENO_BC_PERIODIC ? i + g.n : (g.bc_lo == GENO_BC_REFLECTING ? -i - 1 : 0);
     if (g.bc_lo == GENO_BC_REFLECTING && f == 1) sign = -1.0;
@@ -316,7 +319,7 @@ int check_params6(const geno6_params* p) {
     return fail(GENO_EINVAL, "bad variables code %d", p->variables);
   for (int i = 0; i < 2; ++i)
     if (p->bc[i] != GENO_BC_PERIODIC && p->bc[i] != GENO_BC_TRANSMISSIVE &&
-        p->bc[i] != GENO_BC_REFLECTING)
+        p->bc[i] != GENO_BC_REFLECTING && p->bc[i] != GENO6_BC_FIXED)
       return fail(GENO_EINVAL, "bad boundary code %d", p->bc[i]);
   if ((p->bc[0] == GENO_BC_PERIODIC) != (p->bc[1] == GENO_BC_PERIODIC))
     return fail(GENO_EINVAL, "periodic boundaries must be set on both ends");
@@ -341,6 +344,9 @@ Geo6 geo6(const geno6_grid* g) {
   o.bc_hi = g->params.bc[1];
   o.dx = g->dx;
   o.inv_dx = 1.0 / g->dx;
+  for (int e = 0; e < 2; ++e)
+    for (int c = 0; c < 3; ++c)
+      for (int f = 0; f < 3; ++f) o.ghost[e][c][f] = g->params.ghost[e][c][f];
   return o;
 }
 
@@ -399,6 +405,9 @@ int geno6_params_default(geno6_params* p) {
   p->bc[0] = p->bc[1] = GENO_BC_PERIODIC;
   p->dt_fixed = 0.0;
   p->variables = GENO6_VARS_CONSERVATIVE;
+  for (int e = 0; e < 2; ++e)
+    for (int c = 0; c < 3; ++c)
+      for (int f = 0; f < 3; ++f) p->ghost[e][c][f] = 0.0;
   return GENO_OK;
 }
 

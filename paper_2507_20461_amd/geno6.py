@@ -13,8 +13,9 @@ import torch
 
 from . import geno_gks as G
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
+BC_FIXED = 3
 KERNELS = ("init", "dt", "stage")
 EXPORTS = ("geno6_params_default", "geno6_grid_init", "geno6_workspace_bytes", "geno6_faces", "geno6_rhs",
            "geno6_step", "geno6_timing_enable", "geno6_timing_read", "geno6_op_costs")
@@ -23,7 +24,8 @@ EXPORTS = ("geno6_params_default", "geno6_grid_init", "geno6_workspace_bytes", "
 class geno6_params(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int), ("gamma", ctypes.c_double), ("C", ctypes.c_double),
                 ("eps", ctypes.c_double), ("d", ctypes.c_double * 4), ("cfl", ctypes.c_double),
-                ("bc", ctypes.c_int * 2), ("dt_fixed", ctypes.c_double), ("variables", ctypes.c_int)]
+                ("bc", ctypes.c_int * 2), ("dt_fixed", ctypes.c_double), ("variables", ctypes.c_int),
+                ("ghost", ctypes.c_double * 18)]
 
 
 class geno6_grid(ctypes.Structure):
@@ -67,6 +69,9 @@ def default_params(**kw) -> geno6_params:
         elif k == "d":
             for j in range(4):
                 p.d[j] = float(v[j])
+        elif k == "ghost":   # [end][cell k][field], see geno6.h
+            for j, x in enumerate(np.asarray(v, dtype=np.float64).reshape(18)):
+                p.ghost[j] = float(x)
         else:
             setattr(p, k, v)
     return p

@@ -106,7 +106,8 @@ def test_noncompact_host_side_validation(so):
     for kw in ({"n": 2}, {"n": 8, "x0": 1.0, "x1": 1.0}):
         with pytest.raises(G.GenoError):
             S.Grid6(**kw)
-    for bad in ({"bc": (0, 1)}, {"d": (1, 8, 0, 1)}, {"cfl": 0.0}, {"bc": (3, 3)}, {"dt_fixed": -1.0},
+    S.Grid6(16, bc=(S.BC_FIXED, 1))   # fixed-state ends are a boundary kind of this path
+    for bad in ({"bc": (0, 1)}, {"d": (1, 8, 0, 1)}, {"cfl": 0.0}, {"bc": (4, 4)}, {"dt_fixed": -1.0},
                 {"variables": 2}):
         with pytest.raises(G.GenoError):
             S.Grid6(16, params=S.default_params(**bad))

@@ -162,6 +162,29 @@ def test_step_shadow(S, bc, kind, n, char):
         assert e <= TOL, (k, e)
 
 
+@pytest.mark.parametrize("char", [False, True], ids=["cons", "char"])
+def test_titarev_toro_fixed_ends(S, char):
+    # the paper's inflow / fixed-profile ends: faces at the start and eight
+    # shadowed steps
+    _say("geno6 titarev-toro char=%d" % char)
+    U, ghost = inputs.titarev_toro_noncompact(1000)
+    grid = S.Grid6(1000, -5.0, 5.0, bc=S.BC_FIXED, ghost=ghost, variables=int(char))
+    prm = dict(bc=O6.FIXED, ghost=ghost, characteristic=char)
+    g = gpu_faces(S, grid, U)
+    o = O6.faces(O6.params(**prm), U)
+    for a, b in zip(g[:3], o[:3]):
+        assert rel_err(a, b) <= TOL
+    Ud = grid.to_device(U)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(8):
+        start = grid.interior(Ud)
+        S.step(grid, Ud, ws, 1, dt_out=dts)
+        torch.cuda.synchronize()
+        Uo, _, _ = O6.step(O6.params(dt_fixed=float(dts.item()), **prm), start, grid.dx, 1)
+        assert rel_err(grid.interior(Ud), Uo) <= TOL, k
+
+
 def test_guard_counts(S):
     n = 40
     U = state("cold", n)
