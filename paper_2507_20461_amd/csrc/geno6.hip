@@ -355,6 +355,7 @@ KP6 kp6(const geno6_params& p) {
   k.gamma = p.gamma;
   k.C = p.C;
   k.inv_tanhC = 1.0 / std::tanh(p.C);
+  k.t2_cut = 2.0 * (1.0 - 19.8 / p.C) / (19.8 / p.C);
   k.eps = p.eps;
   for (int i = 0; i < 4; ++i) k.d[i] = p.d[i];
   k.cfl = p.cfl;

@@ -14,6 +14,7 @@ struct KP6 {
   double gamma;
   double C;          // path-function steepness (Eq. (4))
   double inv_tanhC;  // 1 / tanh(C)
+  double t2_cut;     // 2 (1 - A) / A, A = 19.8 / C: alpha >= A when (IS^tau / y)^2 is below it
   double eps;        // indicator floor (Eq. (5), (8))
   double d[4];       // linear weights of S_1..S_4 (Eq. (8))
   double cfl;
@@ -113,6 +114,10 @@ __host__ __device__ __forceinline__ D path_chi6(const D (&IS)[4], const KP6& k) 
   const D t = fabs(D(0.5) * (IS[0] + IS[2]) - IS[1]);
   const D x = ISH + D(k.eps), y = ISL + D(k.eps);
   const D x2 = x * x, y2 = y * y, t2 = t * t;
+  // alpha >= A = 19.8 / C already holds when t^2 / y^2 <= 2 (1 - A) / A
+  // (then 2 (1 + t^2/x^2) >= A (2 + t^2/x^2 + t^2/y^2) for any x >= y): a
+  // cheaper sufficient test with the same outcome, chi = 1
+  if (t2 <= D(k.t2_cut) * y2) return D(1.0);
   const D num = D(2.0) * y2 * (x2 + t2);
   const D den = D(2.0) * x2 * y2 + t2 * (x2 + y2);
   if (!(D(k.C) * num < D(19.8) * den)) return D(1.0);
@@ -299,19 +304,16 @@ __host__ __device__ __forceinline__ int face6(const Get& get, const KP6& k, D* W
     }
   }
   if (!done) reconstruct6<D>(get, k, WL, WR, chi);
-  int guard = 0;
-  if (!admissible6(WL)) {
+  // guard by selects (no branch: a wave rarely has a guarded lane, and the
+  // branch would cost register copies on every path)
+  const bool okl = admissible6(WL), okr = admissible6(WR);
 #pragma unroll
-    for (int v = 0; v < 3; ++v) WL[v] = get(v, 2);
-    ++guard;
-  }
-  if (!admissible6(WR)) {
-#pragma unroll
-    for (int v = 0; v < 3; ++v) WR[v] = get(v, 3);
-    ++guard;
+  for (int v = 0; v < 3; ++v) {
+    WL[v] = okl ? WL[v] : get(v, 2);
+    WR[v] = okr ? WR[v] : get(v, 3);
   }
   hllc6(WL, WR, D(k.gamma), F);
-  return guard;
+  return (okl ? 0 : 1) + (okr ? 0 : 1);
 }
 
 }  // namespace geno6

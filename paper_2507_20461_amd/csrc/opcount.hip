@@ -205,6 +205,7 @@ extern "C" int geno6_op_costs(double* costs) {
   k.gamma = 1.4;
   k.C = 20.0;
   k.inv_tanhC = 1.0 / std::tanh(20.0);
+  k.t2_cut = 2.0 * (1.0 - 19.8 / 20.0) / (19.8 / 20.0);
   k.eps = 1e-15;
   k.d[0] = 1.0;
   k.d[1] = 8.0;
