@@ -43,12 +43,16 @@
 /* ---------------------------------------------------------------------- */
 enum {
   PI_GAMMA = 0, PI_CPATH, PI_EPS, PI_R, PI_RL, PI_D1, PI_D2, PI_D3,
-  PI_TAUC1, PI_TAUC2, PI_CFL, PI_BCXL, PI_BCXH, PI_BCYL, PI_BCYH, PI_COUNT
+  PI_TAUC1, PI_TAUC2, PI_CFL, PI_BCXL, PI_BCXH, PI_BCYL, PI_BCYH,
+  PI_GHOST,     /* 24 values, 1-D fixed ends: [end][layer][W (3), dW (3)] */
+  PI_COUNT = PI_GHOST + 24
 };
 
 typedef struct {
   double gamma, Cpath, eps, r, rL, d[3], tc1, tc2, cfl;
-  int bc[4];           /* 0 periodic, 1 transmissive, 2 reflecting: x-lo, x-hi, y-lo, y-hi */
+  int bc[4];           /* 0 periodic, 1 transmissive, 2 reflecting, 3 fixed (1-D only):
+                          x-lo, x-hi, y-lo, y-hi */
+  double ghost[2][2][6];  /* fixed ends: [end][layer 0 = next to the grid][W, dW] */
   int ndim, nx, ny;
   double dx, dy;
   double K;            /* internal degrees of freedom of the BGK model */
@@ -62,6 +66,9 @@ static void cfg_from(ocfg *c, int ndim, int nx, int ny, double dx, double dy,
   c->d[0] = p[PI_D1]; c->d[1] = p[PI_D2]; c->d[2] = p[PI_D3];
   c->tc1 = p[PI_TAUC1]; c->tc2 = p[PI_TAUC2]; c->cfl = p[PI_CFL];
   for (int i = 0; i < 4; ++i) c->bc[i] = (int)p[PI_BCXL + i];
+  for (int e = 0; e < 2; ++e)
+    for (int l = 0; l < 2; ++l)
+      for (int q = 0; q < 6; ++q) c->ghost[e][l][q] = p[PI_GHOST + (e * 2 + l) * 6 + q];
   c->ndim = ndim; c->nx = nx; c->ny = (ndim == 1) ? 1 : ny;
   c->dx = dx; c->dy = dy;
   /* Internal degrees of freedom so that gamma = (K + D + 2)/(K + D) with
@@ -357,7 +364,9 @@ static void gstate_load(const ocfg *P, gstate *g, const double *W, const double 
 /* Boundary codes: 0 periodic, 1 transmissive (nearest interior cell, zero
  * normal derivative), 2 reflecting wall (mirror image: the normal momentum
  * changes sign; a derivative normal to the wall changes sign unless its
- * field does, a tangential one changes sign with its field). */
+ * field does, a tangential one changes sign with its field), 3 fixed states
+ * (1-D: given averages and gradients of the ghost cells, as an inflow state
+ * or a fixed wave profile). */
 static double wall_sign_w(int f, int m) { return f == m ? -1.0 : 1.0; }
 
 static void fill_ghosts(const ocfg *P, gstate *g) {
@@ -384,6 +393,17 @@ static void fill_ghosts(const ocfg *P, gstate *g) {
           if (P->bc[1] == 2) vh *= wall_sign_w(f, 1) * (d == 0 ? -1.0 : 1.0);
           g->dW[gidx(g, ff, j, il)] = vl;
           g->dW[gidx(g, ff, j, ih)] = vh;
+        }
+      if (P->ndim == 1)   /* fixed ends overwrite the images */
+        for (int f = 0; f < nv; ++f) {
+          if (P->bc[0] == 3) {
+            g->W[gidx(g, f, j, il)] = P->ghost[0][gl - 1][f];
+            g->dW[gidx(g, f, j, il)] = P->ghost[0][gl - 1][3 + f];
+          }
+          if (P->bc[1] == 3) {
+            g->W[gidx(g, f, j, ih)] = P->ghost[1][gl - 1][f];
+            g->dW[gidx(g, f, j, ih)] = P->ghost[1][gl - 1][3 + f];
+          }
         }
     }
   }

@@ -364,3 +364,41 @@ def titarev_toro_noncompact(n: int = 1000, gamma: float = GAMMA):
     xg = 5.0 + np.arange(3) * h
     ghost[1] = np.asarray(_cons_1d(averages(xg), np.zeros(3), np.ones(3), gamma)).T
     return U, ghost
+
+
+def titarev_toro_1d(nx: int = 800, gamma: float = GAMMA):
+    """The Titarev-Toro problem for the compact scheme (800 cells in the
+    paper) on [-5, 5]: cell averages and averaged gradients (Gauss theorem:
+    face-value differences over h) of TITAREV_TORO_LEFT on x <= -4 and
+    rho = 1 + 0.1 sin(20 pi x), u = 0, p = 1 beyond; end time 5. Also
+    returns the ghost states [end][layer 0 = next to the grid][W (3), dW (3)]
+    of the paper's boundaries: the constant inflow state on the left and the
+    fixed wave profile (averages and averaged gradients of the two cells
+    beyond x = 5) on the right."""
+    if nx % 10:
+        raise ValueError("nx must be a multiple of 10 (jump on a face)")
+    h = 10.0 / nx
+    k = 20.0 * math.pi
+
+    def avg_grad(xl):
+        xr = xl + h
+        rho = 1.0 + 0.1 * (np.cos(k * xl) - np.cos(k * xr)) / (k * h)
+        drho = 0.1 * (np.sin(k * xr) - np.sin(k * xl)) / h
+        return rho, drho
+
+    xl = -5.0 + np.arange(nx) * h
+    left = xl + h <= -4.0 + 1e-12
+    rho_w, drho_w = avg_grad(xl)
+    rl, ul, pl = TITAREV_TORO_LEFT
+    rho = np.where(left, rl, rho_w)
+    W = _cons_1d(rho, np.where(left, ul, 0.0), np.where(left, pl, 1.0), gamma)
+    dW = np.zeros_like(W)
+    # u = 0, p = 1 on the right: rho U and rho E are constant there, and rho E
+    # carries no kinetic part, so only d rho / dx is non-zero
+    dW[0] = np.where(left, 0.0, drho_w)
+    ghost = np.zeros((2, 2, 6))
+    ghost[0, :, :3] = np.asarray(_cons_1d(np.full(2, rl), np.full(2, ul), np.full(2, pl), gamma)).T
+    rg, dg = avg_grad(5.0 + np.arange(2) * h)
+    ghost[1, :, :3] = np.asarray(_cons_1d(rg, np.zeros(2), np.ones(2), gamma)).T
+    ghost[1, :, 3] = dg
+    return W[:, None, :], dW[:, None, :], ghost

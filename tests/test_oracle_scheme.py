@@ -242,3 +242,40 @@ def test_reflecting_walls_conserve_mass_and_energy(oracle):
     W1, _, _, _ = oracle.step(prm, W, dW, 30)
     for k in (0, 2):
         assert abs(_fsum(W1[k]) - _fsum(W[k])) <= 1e-13 * 64 * np.abs(W[k]).max()
+
+
+def test_fixed_ends_reproduce_transmissive_and_periodic_faces(oracle):
+    # 1-D fixed ends: ghost states equal to the transmissive images (end
+    # cell, zero gradient) give the transmissive face fluxes, equal to the
+    # periodic images the periodic ones
+    from paper_2507_20461_amd import inputs
+    n = 40
+    W, dW = inputs.sine_1d(n)
+    W = W.copy()
+    W[:, :, 10:14] *= 1.3   # a bump with jumps
+    g = np.zeros((2, 2, 6))
+    for layer in range(2):
+        g[0, layer, :3] = W[:, 0, 0]
+        g[1, layer, :3] = W[:, 0, -1]
+    a = oracle.stage_faces(oracle.params(ndim=1, bc=(oracle.FIXED, oracle.FIXED, 0, 0), ghost=g), W, dW, 1e-3)
+    b = oracle.stage_faces(oracle.params(ndim=1, bc=oracle.TRANSMISSIVE), W, dW, 1e-3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    for layer in range(2):
+        g[0, layer, :3], g[0, layer, 3:] = W[:, 0, n - 1 - layer], dW[:, 0, n - 1 - layer]
+        g[1, layer, :3], g[1, layer, 3:] = W[:, 0, layer], dW[:, 0, layer]
+    a = oracle.stage_faces(oracle.params(ndim=1, bc=(oracle.FIXED, oracle.FIXED, 0, 0), ghost=g), W, dW, 1e-3)
+    b = oracle.stage_faces(oracle.params(ndim=1, bc=oracle.PERIODIC), W, dW, 1e-3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_titarev_toro_compact_data():
+    from paper_2507_20461_amd import inputs
+    W, dW, g = inputs.titarev_toro_1d(800)
+    rho = W[0, 0]
+    assert np.allclose(rho[:80], 1.515695) and abs(rho[80:].mean() - 1.0) < 1e-3
+    # averaged gradients integrate back to the face jumps: the sum over the
+    # 8 cells of one period of h * d rho / dx is 0 (a full sine period)
+    assert abs(dW[0, 0, 80:88].sum()) < 1e-10
+    assert np.allclose(g[0, :, 0], 1.515695) and np.all(g[0, :, 3:] == 0.0)
