@@ -136,19 +136,25 @@ def linearity_shares(G, torch, grid, Wd, dWd, ws, reps=5):
 
 
 def robustness_runs(G, inputs, np, torch):
-    """The paper's strong-shock problems from analytic data, 400 cells, run
-    step by step to their end times: steps, guard events, density range,
-    mass / energy drift (reflecting walls keep both), wall time; a run that
-    loses positivity reports where."""
-    cases = [("blast_wave", inputs.blast_wave_1d, 0.038, (0.0, 1.0), [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2,
-              [(0.5, 0.0), (0.5, 0.001), (0.2, 0.0)]),
-             ("shu_osher", inputs.shu_osher_1d, 1.8, (-5.0, 5.0), G.BC_TRANSMISSIVE, [(0.5, 0.0)])]
+    """The paper's strong-shock problems from analytic data (blast waves and
+    Shu-Osher on 400 cells, Titarev-Toro on 800 with its inflow and
+    fixed-profile ends), run step by step to their end times: steps, guard
+    events, density range, mass / energy drift (reflecting walls keep both),
+    wall time; a run that loses positivity reports where."""
+    cases = [("blast_wave", inputs.blast_wave_1d, 400, 0.038, (0.0, 1.0),
+              [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2, [(0.5, 0.0), (0.5, 0.001), (0.2, 0.0)]),
+             ("shu_osher", inputs.shu_osher_1d, 400, 1.8, (-5.0, 5.0), G.BC_TRANSMISSIVE, [(0.5, 0.0)]),
+             ("titarev_toro", inputs.titarev_toro_1d, 800, 5.0, (-5.0, 5.0),
+              [G.BC_FIXED] * 2 + [G.BC_PERIODIC] * 2, [(0.5, 0.0)])]
     out = {}
-    for name, make, t_end, (x0, x1), bc, settings in cases:
-        W, dW = make(400)
+    for name, make, ncell, t_end, (x0, x1), bc, settings in cases:
+        made = make(ncell)
+        W, dW = made[0], made[1]
         for cfl, c1 in settings:
-            grid = G.Grid(1, 400, 1, x0=x0, x1=x1, bc=bc, cfl=cfl, tau_c1=c1)
+            grid = G.Grid(1, ncell, 1, x0=x0, x1=x1, bc=bc, cfl=cfl, tau_c1=c1)
             Wd, dWd = grid.to_device(W), grid.to_device(dW)
+            if len(made) == 3:   # fixed ends: inflow state and fixed profile
+                grid.set_fixed_ghosts(Wd, dWd, made[2])
             ws = grid.workspace()
             dts = torch.zeros(1, dtype=torch.float64, device="cuda")
             t, n, guard, failed = 0.0, 0, 0, None

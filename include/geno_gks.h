@@ -28,8 +28,9 @@
  *   Element types: W is float64 in every precision mode. dW, face_state,
  *   F, Ft and Wint are float64 with GENO_F64 and float32 with GENO_MIXED;
  *   chi is float64 in both.
- *   Ghost cells belong to the library: calls overwrite them; interior cells
- *   are written only by gks_step.
+ *   Ghost cells belong to the library: calls overwrite them (except those
+ *   of GENO_BC_FIXED ends, which the caller fills); interior cells are
+ *   written only by gks_step.
  */
 #ifndef GENO_GKS_H
 #define GENO_GKS_H
@@ -54,6 +55,12 @@ extern "C" {
 #define GENO_BC_PERIODIC 0
 #define GENO_BC_TRANSMISSIVE 1
 #define GENO_BC_REFLECTING 2   /* wall: mirror image, normal momentum negated */
+#define GENO_BC_FIXED 3        /* 1-D only: the caller's ghost cells of W and dW
+                                  (two per end, averages and physical
+                                  gradients) are kept as given: an inflow
+                                  state or a fixed profile; the library never
+                                  writes them and carries them into its
+                                  stage arrays */
 
 /* arithmetic of the reconstruction and the flux */
 #define GENO_F64 0     /* everything in float64 */

@@ -176,6 +176,8 @@ __device__ __forceinline__ double dt_of(const Ctrl* c) { return c->dt; }
 // writes the ghost cells whose source it is.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int ghost_src(int gi, int n, int bc_lo, int bc_hi) {
+  // fixed ends: no interior cell is the source (the caller owns those ghosts)
+  if ((gi < 0 && bc_lo == GENO_BC_FIXED) || (gi >= n && bc_hi == GENO_BC_FIXED)) return -1;
   if (gi < 0) {
     if (bc_lo == GENO_BC_PERIODIC) return gi + n;
     return bc_lo == GENO_BC_REFLECTING ? -gi - 1 : 0;
@@ -1436,7 +1438,7 @@ int check_params(const geno_params* p) {
     return fail(GENO_EINVAL, "tau coefficients must be >= 0");
   for (int i = 0; i < 4; ++i)
     if (p->bc[i] != GENO_BC_PERIODIC && p->bc[i] != GENO_BC_TRANSMISSIVE &&
-        p->bc[i] != GENO_BC_REFLECTING)
+        p->bc[i] != GENO_BC_REFLECTING && p->bc[i] != GENO_BC_FIXED)
       return fail(GENO_EINVAL, "bad boundary code %d", p->bc[i]);
   if ((p->bc[0] == GENO_BC_PERIODIC) != (p->bc[1] == GENO_BC_PERIODIC) ||
       (p->bc[2] == GENO_BC_PERIODIC) != (p->bc[3] == GENO_BC_PERIODIC))
@@ -1449,6 +1451,9 @@ int check_grid(const geno_grid* g) {
   int rc = check_params(&g->params);
   if (rc) return rc;
   if (g->ndim != 1 && g->ndim != 2) return fail(GENO_EINVAL, "ndim must be 1 or 2");
+  for (int i = 0; i < 4; ++i)
+    if (g->ndim == 2 && g->params.bc[i] == GENO_BC_FIXED)
+      return fail(GENO_EINVAL, "fixed-state ends are available in 1-D only");
   if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1))
     return fail(GENO_EINVAL, "bad grid size");
   if (g->pitch < g->nx + 2 * NG || g->rows != (g->ndim == 2 ? g->ny + 2 * NG : 1))
@@ -1540,6 +1545,17 @@ int launch_init(const geno_grid* g, const Geo& geo, double gamma, double* W, T* 
     HIP_TRY(launch(GENO_K_INIT, k_init<2, T>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
   else
     HIP_TRY(launch(GENO_K_INIT, k_init<1, T>, nblocks(n), s, geo, gamma, W, dW, B.part, B.ctrl));
+  // 1-D fixed ends: the caller's ghost cells also serve the stage state
+  // (NG cells of each of the three field rows)
+  for (int side = 0; side < 2 && g->ndim == 1; ++side) {
+    if (g->params.bc[side] != GENO_BC_FIXED) continue;
+    const size_t col = side == 0 ? 0 : (size_t)g->nx + NG;
+    HIP_TRY(hipMemcpy2DAsync(B.wst + col, g->pitch * sizeof(double), W + col,
+                             g->pitch * sizeof(double), NG * sizeof(double), 3,
+                             hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpy2DAsync(B.dwst + col, g->pitch * sizeof(T), dW + col, g->pitch * sizeof(T),
+                             NG * sizeof(T), 3, hipMemcpyDeviceToDevice, s));
+  }
   return GENO_OK;
 }
 

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING = 0, 1, 2
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING, BC_FIXED = 0, 1, 2, 3
 F64, MIXED = 0, 1
 ABI_VERSION = 1
 NG = 2
@@ -219,6 +219,20 @@ class Grid:
     def grad_to_device(self, A, device="cuda"):
         """Interior gradients [ndim * nv, ny, nx] -> padded device tensor of the grid's dW type."""
         return self.to_device(A, device, self.fdtype)
+
+    def set_fixed_ghosts(self, W, dW, ghost):
+        """1-D fixed ends: write the ghost states [end][layer 0 = next to the
+        grid][W (3), dW (3)] into the padded device tensors W and dW."""
+        if self.ndim != 1:
+            raise ValueError("fixed-state ends are 1-D only")
+        ghost = np.asarray(ghost, dtype=np.float64).reshape(2, NG, 6)
+        for end in range(2):
+            if self.params.bc[end] != BC_FIXED:
+                continue
+            for layer in range(NG):
+                col = NG - 1 - layer if end == 0 else NG + self.nx + layer
+                W[:, 0, col] = torch.as_tensor(ghost[end, layer, :3], dtype=W.dtype, device=W.device)
+                dW[:, 0, col] = torch.as_tensor(ghost[end, layer, 3:], dtype=dW.dtype, device=dW.device)
 
     def interior(self, T):
         """Padded tensor -> interior numpy array [f, ny, nx]."""

@@ -66,6 +66,10 @@ def test_host_side_validation(so):
     assert e.value.code == G.GENO_EVERSION
     with pytest.raises(G.GenoError):
         G.Grid(2, 8, 8, params=G.default_params(bc=(0, 1, 1, 1)))
+    # fixed-state ends: 1-D only
+    G.Grid(1, 16, params=G.default_params(bc=(3, 3, 0, 0)))
+    with pytest.raises(G.GenoError):
+        G.Grid(2, 8, 8, params=G.default_params(bc=(3, 3, 1, 1)))
     # null pointers are rejected before any launch
     assert G.lib().gks_step(ctypes.byref(g.g), None, None, None, 1, None, None, None) == G.GENO_EINVAL
     assert G.lib().geno_reconstruct(ctypes.byref(g.g), None, None, 0, None, None, None, None) == G.GENO_EINVAL

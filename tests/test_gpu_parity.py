@@ -496,6 +496,35 @@ def test_robustness_problem_shadowed(G, oracle, problem):
     assert max(worst) < TOL, worst
 
 
+def test_titarev_toro_fixed_ends_shadowed(G, oracle):
+    # the paper's Titarev-Toro problem (800 cells) with its inflow and
+    # fixed-profile ends (caller-owned ghost cells): every GPU step of the
+    # first 40 against the oracle's step from the same state, then the full
+    # run to t = 5 stays physical
+    _say("titarev-toro fixed ends")
+    W, dW, ghost = inputs.titarev_toro_1d(800)
+    bc = (G.BC_FIXED, G.BC_FIXED, G.BC_PERIODIC, G.BC_PERIODIC)
+    grid = G.Grid(1, 800, 1, x0=-5.0, x1=5.0, bc=bc)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    grid.set_fixed_ghosts(Wd, dWd, ghost)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prm = oracle.params(ndim=1, bc=bc, ghost=ghost)
+    worst = [0.0, 0.0]
+    for n in range(40):
+        W0, dW0 = grid.interior(Wd), grid.interior(dWd)
+        st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        oW, odW, _, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, fixed_dt=float(dts.item()))
+        gW, gdW = grid.interior(Wd), grid.interior(dWd)
+        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        assert st.guard == og and st.nonfinite == 0
+    assert max(worst) < TOL, worst
+    # the caller's ghost cells are kept as given
+    Wg = Wd.cpu().numpy()
+    assert np.array_equal(Wg[:, 0, 1], ghost[0, 0, :3]) and np.array_equal(Wg[:, 0, 0], ghost[0, 1, :3])
+    assert np.array_equal(Wg[:, 0, 802], ghost[1, 0, :3]) and np.array_equal(Wg[:, 0, 803], ghost[1, 1, :3])
+
+
 def test_blast_wave_full_run(G):
     # to the paper's end time 0.038: finite and physical throughout, and mass
     # and energy kept by the reflecting walls to rounding. With the
