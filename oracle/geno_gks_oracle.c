@@ -45,7 +45,8 @@ enum {
   PI_GAMMA = 0, PI_CPATH, PI_EPS, PI_R, PI_RL, PI_D1, PI_D2, PI_D3,
   PI_TAUC1, PI_TAUC2, PI_CFL, PI_BCXL, PI_BCXH, PI_BCYL, PI_BCYH,
   PI_GHOST,     /* 24 values, 1-D fixed ends: [end][layer][W (3), dW (3)] */
-  PI_COUNT = PI_GHOST + 24
+  PI_CHAR = PI_GHOST + 24,   /* 1-D: 1 = characteristic-variable reconstruction */
+  PI_COUNT
 };
 
 typedef struct {
@@ -53,6 +54,7 @@ typedef struct {
   int bc[4];           /* 0 periodic, 1 transmissive, 2 reflecting, 3 fixed (1-D only):
                           x-lo, x-hi, y-lo, y-hi */
   double ghost[2][2][6];  /* fixed ends: [end][layer 0 = next to the grid][W, dW] */
+  int characteristic;     /* 1-D: reconstruct characteristic variables */
   int ndim, nx, ny;
   double dx, dy;
   double K;            /* internal degrees of freedom of the BGK model */
@@ -69,6 +71,7 @@ static void cfg_from(ocfg *c, int ndim, int nx, int ny, double dx, double dy,
   for (int e = 0; e < 2; ++e)
     for (int l = 0; l < 2; ++l)
       for (int q = 0; q < 6; ++q) c->ghost[e][l][q] = p[PI_GHOST + (e * 2 + l) * 6 + q];
+  c->characteristic = (int)p[PI_CHAR];
   c->ndim = ndim; c->nx = nx; c->ny = (ndim == 1) ? 1 : ny;
   c->dx = dx; c->dy = dy;
   /* Internal degrees of freedom so that gamma = (K + D + 2)/(K + D) with
@@ -747,9 +750,65 @@ static int admissible(const ocfg *P, const double *W) {
 /* Normal GENO for the face between cells (i, j) and (i+1, j) along x (dir 0)
  * or between (i, j) and (i, j+1) along y (dir 1) in ghosted coordinates.
  * out[side][quant][var]: quant 0 value, 1 h * normal derivative; chi[side][var]. */
+/* Characteristic variables (reading, 1-D option): right eigenvectors of the
+ * Euler flux Jacobian at the Roe average of the two cells at the face,
+ * columns for the speeds u - c, u, u + c; the left ones are their inverse,
+ * by Gaussian elimination. Returns nonzero when the average has no real
+ * sound speed (the face then keeps the conservative variables). */
+static int roe_eigen(const ocfg *P, const double *Wa, const double *Wb, double R[3][3],
+                     double L[3][3]) {
+  const double g = P->gamma;
+  const double pa = (g - 1.0) * (Wa[2] - 0.5 * Wa[1] * Wa[1] / Wa[0]);
+  const double pb = (g - 1.0) * (Wb[2] - 0.5 * Wb[1] * Wb[1] / Wb[0]);
+  const double sa = sqrt(Wa[0]), sb = sqrt(Wb[0]);
+  const double u = (sa * Wa[1] / Wa[0] + sb * Wb[1] / Wb[0]) / (sa + sb);
+  const double H = (sa * (Wa[2] + pa) / Wa[0] + sb * (Wb[2] + pb) / Wb[0]) / (sa + sb);
+  const double c2 = (g - 1.0) * (H - 0.5 * u * u);
+  if (!(c2 > 0.0)) return 1;
+  const double c = sqrt(c2);
+  const double Rm[3][3] = {{1.0, 1.0, 1.0}, {u - c, u, u + c}, {H - u * c, 0.5 * u * u, H + u * c}};
+  for (int col = 0; col < 3; ++col) {
+    double A[9], b[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) A[r * 3 + k] = Rm[r][k];
+    b[col] = 1.0;
+    if (solve_d(3, A, b)) return 1;
+    for (int r = 0; r < 3; ++r) L[r][col] = b[r];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) R[r][k] = Rm[r][k];
+  return 0;
+}
+
 static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
                         double out[2][2][4], double chi[2][4]) {
   int nv = P->nv;
+  double R[3][3], L[3][3];
+  if (P->ndim == 1 && P->characteristic) {
+    double Wa[3], Wb[3];
+    for (int v = 0; v < 3; ++v) { Wa[v] = g->W[gidx(g, v, j, i)]; Wb[v] = g->W[gidx(g, v, j, i + 1)]; }
+    if (!roe_eigen(P, Wa, Wb, R, L)) {
+      double val[2][3], der[2][3];
+      for (int c = 0; c < 3; ++c) {
+        double q[4] = {0, 0, 0, 0}, gg[4] = {0, 0, 0, 0};
+        for (int m = -1; m <= 2; ++m)
+          for (int v = 0; v < 3; ++v) {
+            q[m + 1] += L[c][v] * g->W[gidx(g, v, j, i + m)];
+            gg[m + 1] += L[c][v] * P->dx * g->dW[gidx(g, v, j, i + m)];
+          }
+        double l[3], r[3];
+        geno_face(P, q, gg, l, r);
+        val[0][c] = l[0]; der[0][c] = l[1]; chi[0][c] = l[2];
+        val[1][c] = r[0]; der[1][c] = r[1]; chi[1][c] = r[2];
+      }
+      for (int s = 0; s < 2; ++s)
+        for (int v = 0; v < 3; ++v) {
+          out[s][0][v] = R[v][0] * val[s][0] + R[v][1] * val[s][1] + R[v][2] * val[s][2];
+          out[s][1][v] = R[v][0] * der[s][0] + R[v][1] * der[s][1] + R[v][2] * der[s][2];
+        }
+      return;
+    }
+  }
   for (int v = 0; v < nv; ++v) {
     double q[4], gg[4];
     double h = (dir == 0) ? P->dx : P->dy;

@@ -24,7 +24,8 @@ _lib = None
 P_GAMMA, P_CPATH, P_EPS, P_R, P_RL, P_D1, P_D2, P_D3, P_TAUC1, P_TAUC2, P_CFL = range(11)
 P_BC = 11  # four boundary codes follow: x-lo, x-hi, y-lo, y-hi (0 periodic, 1 transmissive)
 P_GHOST = 15  # 24 values: 1-D fixed ends [end][layer][W (3), dW (3)]
-N_PARAMS = 39
+P_CHAR = 39   # 1-D: 1 = characteristic-variable reconstruction
+N_PARAMS = 40
 PERIODIC, TRANSMISSIVE, REFLECTING, FIXED = 0, 1, 2, 3
 
 
@@ -78,12 +79,15 @@ def _c(a):
 
 
 def params(ndim: int = 2, bc=TRANSMISSIVE, gamma=1.4, C=20.0, eps=1e-15, r=2.0, rL=2.0,
-           d=(1.0, 8.0, 1.0), tau_c1=0.0, tau_c2=1.0, cfl=0.5, ghost=None) -> np.ndarray:
+           d=(1.0, 8.0, 1.0), tau_c1=0.0, tau_c2=1.0, cfl=0.5, ghost=None,
+           characteristic=False) -> np.ndarray:
     """Oracle parameter vector. Paper constants (Sec. 3): C = 20, eps = 1e-15,
     r = 2 (structured), r^L = 2, central weight C_0 = 8. ghost: [2, 2, 6]
     states of the ghost cells of 1-D FIXED ends ([end][layer 0 = next to the
-    grid][W (3), dW (3)])."""
+    grid][W (3), dW (3)]); characteristic: 1-D reconstruction of the
+    characteristic variables of the Roe-averaged flux Jacobian at each face."""
     p = np.zeros(N_PARAMS)
+    p[P_CHAR] = 1.0 if characteristic else 0.0
     if ghost is not None:
         p[P_GHOST:P_GHOST + 24] = np.asarray(ghost, dtype=np.float64).reshape(24)
     p[P_GAMMA], p[P_CPATH], p[P_EPS], p[P_R], p[P_RL] = gamma, C, eps, r, rL

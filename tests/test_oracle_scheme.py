@@ -279,3 +279,27 @@ def test_titarev_toro_compact_data():
     # 8 cells of one period of h * d rho / dx is 0 (a full sine period)
     assert abs(dW[0, 0, 80:88].sum()) < 1e-10
     assert np.allclose(g[0, :, 0], 1.515695) and np.all(g[0, :, 3:] == 0.0)
+
+
+def test_characteristic_reconstruction_compact_1d(oracle):
+    from paper_2507_20461_amd import inputs
+    # where every path function is 1 the reconstruction of values and
+    # h-derivatives is linear and commutes with the face-wise projection
+    n = 64
+    W, dW = inputs.sine_1d(n)
+    a, ca = oracle.normal_faces(oracle.params(ndim=1, bc=oracle.PERIODIC), W, dW)
+    b, cb = oracle.normal_faces(oracle.params(ndim=1, bc=oracle.PERIODIC, characteristic=True), W, dW)
+    lin = np.all(ca == 1.0, axis=(0, 1, 2)) & np.all(cb == 1.0, axis=(0, 1, 2))
+    assert lin.sum() > n // 2
+    assert np.allclose(a[..., lin], b[..., lin], rtol=1e-12, atol=1e-12)
+    # an isolated contact (u = 0.5, p = 1, rho jumps, zero gradients): the
+    # characteristic face states keep u and p exactly
+    rho = np.where(np.arange(n) < n // 2, 1.0, 0.3)
+    Wc = np.stack([rho, 0.5 * rho, 1.0 / 0.4 + 0.125 * rho])[:, None, :]
+    o, _ = oracle.normal_faces(oracle.params(ndim=1, bc=oracle.TRANSMISSIVE, characteristic=True),
+                               Wc, np.zeros_like(Wc))
+    for side in range(2):
+        S = o[side, 0, :, 0, :]
+        u = S[1] / S[0]
+        assert np.allclose(u, 0.5, atol=1e-12)
+        assert np.allclose(0.4 * (S[2] - 0.5 * S[1] * u), 1.0, atol=1e-12)
