@@ -141,17 +141,20 @@ def robustness_runs(G, inputs, np, torch):
     fixed-profile ends), run step by step to their end times: steps, guard
     events, density range, mass / energy drift (reflecting walls keep both),
     wall time; a run that loses positivity reports where."""
+    cons, char = G.VARS_CONSERVATIVE, G.VARS_CHARACTERISTIC
     cases = [("blast_wave", inputs.blast_wave_1d, 400, 0.038, (0.0, 1.0),
-              [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2, [(0.5, 0.0), (0.5, 0.001), (0.2, 0.0)]),
-             ("shu_osher", inputs.shu_osher_1d, 400, 1.8, (-5.0, 5.0), G.BC_TRANSMISSIVE, [(0.5, 0.0)]),
+              [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2,
+              [(0.5, 0.0, cons), (0.5, 0.001, cons), (0.2, 0.0, cons), (0.5, 0.0, char)]),
+             ("shu_osher", inputs.shu_osher_1d, 400, 1.8, (-5.0, 5.0), G.BC_TRANSMISSIVE,
+              [(0.5, 0.0, cons), (0.5, 0.0, char)]),
              ("titarev_toro", inputs.titarev_toro_1d, 800, 5.0, (-5.0, 5.0),
-              [G.BC_FIXED] * 2 + [G.BC_PERIODIC] * 2, [(0.5, 0.0)])]
+              [G.BC_FIXED] * 2 + [G.BC_PERIODIC] * 2, [(0.5, 0.0, cons), (0.5, 0.0, char)])]
     out = {}
     for name, make, ncell, t_end, (x0, x1), bc, settings in cases:
         made = make(ncell)
         W, dW = made[0], made[1]
-        for cfl, c1 in settings:
-            grid = G.Grid(1, ncell, 1, x0=x0, x1=x1, bc=bc, cfl=cfl, tau_c1=c1)
+        for cfl, c1, var in settings:
+            grid = G.Grid(1, ncell, 1, x0=x0, x1=x1, bc=bc, cfl=cfl, tau_c1=c1, variables=var)
             Wd, dWd = grid.to_device(W), grid.to_device(dW)
             if len(made) == 3:   # fixed ends: inflow state and fixed profile
                 grid.set_fixed_ghosts(Wd, dWd, made[2])
@@ -170,8 +173,8 @@ def robustness_runs(G, inputs, np, torch):
                 guard += st.guard
             wall = time.perf_counter() - t0
             Wn = grid.interior(Wd)
-            rec = {"cfl": cfl, "tau_c1": c1, "steps": n, "t": round(t, 6), "guard": guard,
-                   "wall_s": round(wall, 3), "failed": failed}
+            rec = {"cfl": cfl, "tau_c1": c1, "variables": ("conservative", "characteristic")[var], "steps": n,
+                   "t": round(t, 6), "guard": guard, "wall_s": round(wall, 3), "failed": failed}
             if not failed:
                 rec["rho_range"] = [float(Wn[0].min()), float(Wn[0].max())]
                 if name == "blast_wave":   # walls: nothing enters or leaves

@@ -45,14 +45,14 @@ extern "C" {
 
 #define GENO6_ABI_VERSION 3
 
-/* boundary kind of this path beside GENO_BC_PERIODIC, _TRANSMISSIVE and
- * _REFLECTING: the three ghost cells hold given states (inflow, or a fixed
- * profile) */
-#define GENO6_BC_FIXED 3
+/* fixed-state ends of this path (the GENO_BC_FIXED code of geno_gks.h):
+ * the three ghost cells of an end hold the states of geno6_params.ghost
+ * (inflow, or a fixed profile) */
+#define GENO6_BC_FIXED GENO_BC_FIXED
 
-/* variables the reconstruction works on */
-#define GENO6_VARS_CONSERVATIVE 0
-#define GENO6_VARS_CHARACTERISTIC 1
+/* variables the reconstruction works on (the GENO_VARS_* codes) */
+#define GENO6_VARS_CONSERVATIVE GENO_VARS_CONSERVATIVE
+#define GENO6_VARS_CHARACTERISTIC GENO_VARS_CHARACTERISTIC
 
 /* Method parameters.
  * gamma: ratio of specific heats (> 1).

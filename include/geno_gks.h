@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GENO_ABI_VERSION 1
+#define GENO_ABI_VERSION 2
 
 /* error codes */
 #define GENO_OK 0
@@ -61,6 +61,10 @@ extern "C" {
                                   state or a fixed profile; the library never
                                   writes them and carries them into its
                                   stage arrays */
+
+/* variables of the reconstruction (1-D) */
+#define GENO_VARS_CONSERVATIVE 0
+#define GENO_VARS_CHARACTERISTIC 1
 
 /* arithmetic of the reconstruction and the flux */
 #define GENO_F64 0     /* everything in float64 */
@@ -98,6 +102,15 @@ extern "C" {
  *   noise of the two reconstructed states) is evaluated in that limit. The
  *   terms this drops are of order that ratio times the relative difference
  *   of the states or of h |grad W| / |W|, below the float32 unit roundoff.
+ * variables: 1-D only: GENO_VARS_CONSERVATIVE (default) reconstructs rho,
+ *   rho U, rho E component by component; GENO_VARS_CHARACTERISTIC projects
+ *   the averages and h-scaled gradients of the four stencil cells on the
+ *   left eigenvectors of the Euler flux Jacobian at the Roe average of the
+ *   two cells at the face, reconstructs the three characteristic fields
+ *   (values and derivatives) and maps both face states back with the right
+ *   eigenvectors (a face whose Roe average has no real sound speed keeps the
+ *   conservative variables). The paper does not say which variables it
+ *   reconstructs.
  * gate_delta: learned gate (2-D gks_step only). If > 0, before the normal
  *   reconstruction of each direction and stage the loaded network
  *   (geno_mlp_load) predicts chi of every cell from its stencil, and where the
@@ -120,6 +133,7 @@ typedef struct geno_params {
   double dt_fixed;
   double eps_ulps;
   double gate_delta;
+  int variables;   /* GENO_VARS_* (1-D) */
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */

@@ -35,6 +35,7 @@ struct KParams {
   double eps_ulps;    // float32 data: eps floor in units of 2^-24 of the stencil magnitude
   double gate_thr;    // learned gate: a prediction >= gate_thr sets chi = 1
   int gate;           // learned gate enabled
+  int charvars;       // 1-D: reconstruct characteristic variables
 };
 
 // Path function chi = tanh(C alpha)/tanh(C) (Eq. (4)) of the ultimate

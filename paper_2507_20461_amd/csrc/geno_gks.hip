@@ -27,6 +27,7 @@
 #include <utility>
 #include <vector>
 
+#include "geno6_device.hpp"
 #include "geno_device.hpp"
 #include "geno_gks.h"
 #include "gks_device.hpp"
@@ -783,21 +784,80 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
   int pk = -1;
   if (f < nfc) {
     T S[2][3], Dn[2][3];
+    // characteristic variables: the left eigenvectors at the Roe average of
+    // cells f-1 and f (both stencil quantities projected), back with the
+    // right ones; a face without a real sound speed stays conservative
+    geno6::Eig<double> e;
+    bool ch = false;
+    if (k.charvars) {
+      double Wa[3], Wb[3];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      double Q[4], G[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const size_t id = at(g, v, 0, f - 2 + m);
-        Q[m] = W[id];
-        G[m] = g.dx * (double)dW[id];
+      for (int v = 0; v < 3; ++v) {
+        Wa[v] = W[at(g, v, 0, f - 1)];
+        Wb[v] = W[at(g, v, 0, f)];
       }
-      double xl, xr;
-      nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
-                                         S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr);
-      if (chi) {
-        chi[(size_t)(0 * 3 + v) * nfc + f] = xl;
-        chi[(size_t)(1 * 3 + v) * nfc + f] = xr;
+      ch = geno6::roe_eigen<double>(Wa, Wb, k.gamma, e);
+    }
+    if (ch) {
+      double Qv[3][4], Gv[3][4];
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const size_t id = at(g, v, 0, f - 2 + m);
+          Qv[v][m] = W[id];
+          Gv[v][m] = g.dx * (double)dW[id];
+        }
+      double wv[2][3], wd[2][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double Q[4], G[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          Q[m] = e.L[c][0] * Qv[0][m] + e.L[c][1] * Qv[1][m] + e.L[c][2] * Qv[2][m];
+          G[m] = e.L[c][0] * Gv[0][m] + e.L[c][1] * Gv[1][m] + e.L[c][2] * Gv[2][m];
+        }
+        T s0, d0, s1, d1;
+        double xl, xr;
+        nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
+                                           s0, d0, xl, s1, d1, xr);
+        wv[0][c] = (double)s0;
+        wd[0][c] = (double)d0;
+        wv[1][c] = (double)s1;
+        wd[1][c] = (double)d1;
+        if (chi) {
+          chi[(size_t)(0 * 3 + c) * nfc + f] = xl;
+          chi[(size_t)(1 * 3 + c) * nfc + f] = xr;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        double Sv[3], Dv[3];
+        geno6::from_characteristic(e, wv[s], Sv);
+        geno6::from_characteristic(e, wd[s], Dv);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          S[s][v] = T(Sv[v]);
+          Dn[s][v] = T(Dv[v]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        double Q[4], G[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const size_t id = at(g, v, 0, f - 2 + m);
+          Q[m] = W[id];
+          G[m] = g.dx * (double)dW[id];
+        }
+        double xl, xr;
+        nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
+                                           S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr);
+        if (chi) {
+          chi[(size_t)(0 * 3 + v) * nfc + f] = xl;
+          chi[(size_t)(1 * 3 + v) * nfc + f] = xr;
+        }
       }
     }
 #pragma unroll
@@ -1454,6 +1514,10 @@ int check_grid(const geno_grid* g) {
   for (int i = 0; i < 4; ++i)
     if (g->ndim == 2 && g->params.bc[i] == GENO_BC_FIXED)
       return fail(GENO_EINVAL, "fixed-state ends are available in 1-D only");
+  if (g->params.variables != GENO_VARS_CONSERVATIVE &&
+      !(g->params.variables == GENO_VARS_CHARACTERISTIC && g->ndim == 1))
+    return fail(GENO_EINVAL, "characteristic variables are available in 1-D only (code %d)",
+                g->params.variables);
   if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1))
     return fail(GENO_EINVAL, "bad grid size");
   if (g->pitch < g->nx + 2 * NG || g->rows != (g->ndim == 2 ? g->ny + 2 * NG : 1))
@@ -1490,6 +1554,7 @@ geno::KParams kparams(const geno_grid* g) {
   k.eps_ulps = p.eps_ulps;
   k.gate = (p.gate_delta > 0.0 && g->ndim == 2) ? 1 : 0;
   k.gate_thr = 1.0 - p.gate_delta;
+  k.charvars = (g->ndim == 1 && p.variables == GENO_VARS_CHARACTERISTIC) ? 1 : 0;
   return k;
 }
 
@@ -2142,6 +2207,7 @@ int geno_params_default(geno_params* p) {
   if (!p) return fail(GENO_EINVAL, "null params");
   memset(p, 0, sizeof *p);
   p->version = GENO_ABI_VERSION;
+  p->variables = GENO_VARS_CONSERVATIVE;
   p->precision = GENO_F64;
   p->gamma = 1.4;
   p->C = 20.0;

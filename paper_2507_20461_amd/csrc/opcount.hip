@@ -72,6 +72,7 @@ geno::KParams params(int ndim, double gamma) {
   k.eps_ulps = 0.0;
   k.gate_thr = 1.0;
   k.gate = 0;
+  k.charvars = 0;
   return k;
 }
 

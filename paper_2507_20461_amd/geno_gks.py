@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING, BC_FIXED = 0, 1, 2, 3
 F64, MIXED = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 NG = 2
+VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
 
 
 class geno_params(ctypes.Structure):
@@ -28,7 +29,8 @@ class geno_params(ctypes.Structure):
                 ("C", ctypes.c_double), ("eps", ctypes.c_double), ("r", ctypes.c_double),
                 ("rL", ctypes.c_double), ("d", ctypes.c_double * 3), ("tau_c1", ctypes.c_double),
                 ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4),
-                ("dt_fixed", ctypes.c_double), ("eps_ulps", ctypes.c_double), ("gate_delta", ctypes.c_double)]
+                ("dt_fixed", ctypes.c_double), ("eps_ulps", ctypes.c_double), ("gate_delta", ctypes.c_double),
+                ("variables", ctypes.c_int)]
 
 
 class geno_grid(ctypes.Structure):

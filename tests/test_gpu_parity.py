@@ -83,16 +83,17 @@ def _case_1d(name, seed, n=200):
 
 
 @pytest.mark.parametrize("name,seed", CASES_1D)
-def test_reconstruct_1d(G, oracle, name, seed):
-    _say("reconstruct_1d", name, seed)
+@pytest.mark.parametrize("char", [False, True], ids=["cons", "char"])
+def test_reconstruct_1d(G, oracle, name, seed, char):
+    _say("reconstruct_1d", name, seed, "char" if char else "cons")
     W, dW, bc = _case_1d(name, seed)
-    grid = _grid(G, W, bc)
+    grid = _grid(G, W, bc, variables=int(char))
     Wd, dWd = grid.to_device(W), grid.to_device(dW)
     fs = torch.empty(grid.face_state_shape(), dtype=torch.float64, device="cuda")
     chi = torch.empty(grid.chi_shape(), dtype=torch.float64, device="cuda")
     G.geno_reconstruct(grid, Wd, dWd, 0, fs, chi, grid.workspace())
     torch.cuda.synchronize()
-    prm = _oprm(oracle, 1, bc)
+    prm = _oprm(oracle, 1, bc, characteristic=char)
     ref, _ = oracle.face_states(prm, W, dW)
     _, ref_chi = oracle.normal_faces(prm, W, dW)
     got = fs.cpu().numpy()
@@ -523,6 +524,46 @@ def test_titarev_toro_fixed_ends_shadowed(G, oracle):
     Wg = Wd.cpu().numpy()
     assert np.array_equal(Wg[:, 0, 1], ghost[0, 0, :3]) and np.array_equal(Wg[:, 0, 0], ghost[0, 1, :3])
     assert np.array_equal(Wg[:, 0, 802], ghost[1, 0, :3]) and np.array_equal(Wg[:, 0, 803], ghost[1, 1, :3])
+
+
+@pytest.mark.parametrize("problem", ["blast", "shu_osher"])
+def test_characteristic_1d_shadowed(G, oracle, problem):
+    # characteristic variables (1-D): every GPU step of the first 40 against
+    # the oracle's step from the same state; the blast waves run at CFL 0.5
+    _say("characteristic shadow", problem)
+    if problem == "blast":
+        W, dW = inputs.blast_wave_1d(400)
+        bc, x0, x1 = [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2, 0.0, 1.0
+    else:
+        W, dW = inputs.shu_osher_1d(400)
+        bc, x0, x1 = [G.BC_TRANSMISSIVE] * 4, -5.0, 5.0
+    grid = G.Grid(1, 400, 1, x0=x0, x1=x1, bc=bc, variables=G.VARS_CHARACTERISTIC)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prm = oracle.params(ndim=1, bc=bc, characteristic=True)
+    worst = [0.0, 0.0]
+    for n in range(40):
+        W0, dW0 = grid.interior(Wd), grid.interior(dWd)
+        st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx)
+        gW, gdW = grid.interior(Wd), grid.interior(dWd)
+        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        assert st.guard == og and st.nonfinite == 0
+        assert float(dts.item()) == pytest.approx(float(odt[0]), rel=1e-13)
+    assert max(worst) < TOL, worst
+
+
+def test_characteristic_blast_wave_full_run_at_cfl_half(G):
+    # component-wise reconstruction loses positivity at step 71 at CFL 0.5;
+    # with characteristic variables the run reaches the paper's end time
+    W, dW = inputs.blast_wave_1d(400)
+    bc = [G.BC_REFLECTING] * 2 + [G.BC_PERIODIC] * 2
+    grid = G.Grid(1, 400, 1, bc=bc, cfl=0.5, variables=G.VARS_CHARACTERISTIC)
+    Wn, n, t, guard = _run_to(G, grid, W, dW, 0.038)
+    assert t >= 0.038 and np.all(np.isfinite(Wn)) and np.all(Wn[0] > 0)
+    for k in (0, 2):
+        assert abs(Wn[k].sum() - W[k].sum()) <= 1e-13 * np.abs(W[k]).sum()
 
 
 def test_blast_wave_full_run(G):
