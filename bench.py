@@ -304,6 +304,7 @@ def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_
     torch.cuda.synchronize()
     out["entropy_wave_1800"] = {"us_per_step": round(1e3 * e0.elapsed_time(e1) / 100, 2),
                                 "launches_per_step": 5}
+    out["small_grids"] = noncompact_small_grids(np, torch, inputs, S)
     if paper:
         out["paper_problems"] = noncompact_paper_runs(np, torch, inputs)
     if cpu:
@@ -391,6 +392,64 @@ def noncompact_paper_runs(np, torch, inputs):
                 rec["mass_energy_drift"] = [float(abs(V[f].sum() - U[f].sum()) / np.abs(U[f]).sum()) for f in (0, 2)]
         out.setdefault(name, []).append(rec)
     return out
+
+
+def noncompact_small_grids(np, torch, inputs, S, n=1800, ngrids=2048, steps=100):
+    """The paper's problem size (1800 cells) in geno6_step_batch: one launch
+    for all steps of all grids, one work-group per grid. Per-step time of one
+    grid against geno6_step's five launches per step, and the throughput of
+    2048 such grids (seeded piecewise-smooth states, transmissive ends,
+    CFL 0.5) against 64 of them run one after another with geno6_step."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    grid = S.Grid6(n, 0.0, 1.0, bc=1, cfl=0.5)
+    states = [grid.to_device(inputs.shocks_noncompact(n, 1000 + i, cells_per_segment=600)) for i in range(ngrids)]
+    U0 = torch.stack(states)
+    del states
+    res = {"n": n, "steps": steps}
+    # one grid
+    U1 = U0[:1].clone()
+    ws1 = S.batch_workspace(grid, 1)
+    S.step_batch(grid, U1, ws1, 5)
+    U1.copy_(U0[:1])
+    torch.cuda.synchronize()
+    e0.record()
+    S.step_batch(grid, U1, ws1, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    res["one_grid_us_per_step"] = round(1e3 * e0.elapsed_time(e1) / steps, 2)
+    # all grids
+    U = U0.clone()
+    ws = S.batch_workspace(grid, ngrids)
+    S.step_batch(grid, U, ws, 2)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    e0.record()
+    st = S.step_batch(grid, U, ws, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    V = U[:, :, :n]
+    res["batch"] = {"grids": ngrids, "ms": round(ms, 3),
+                    "value": round(4.0 * n * ngrids * steps / (ms / 1e3) / 1e6, 3),
+                    "unit": "Mcell-updates/s per stage",
+                    "physical_after_run": bool(torch.isfinite(V).all().item() and (V[:, 0] > 0).all().item())}
+    # 64 grids one after another with the per-stage launches
+    wsg = grid.workspace()
+    Us = U0[:64].clone()
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(64):
+        S.step(grid, Us[i], wsg, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    seq = e0.elapsed_time(e1) * ngrids / 64.0
+    res["sequential_geno6_step"] = {"value": round(4.0 * n * ngrids * steps / (seq / 1e3) / 1e6, 3),
+                                    "us_per_grid_step": round(1e3 * seq / ngrids / steps, 2),
+                                    "sample": "64 grids timed, scaled to %d" % ngrids}
+    res["batch_speedup_vs_sequential"] = round(seq / ms, 2)
+    assert torch.equal(Us[:64], U[:64]), "batched and single-grid steps differ"
+    del U, U0, Us, ws
+    return res
 
 
 def noncompact_traffic():

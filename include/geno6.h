@@ -138,13 +138,35 @@ int geno6_rhs(const geno6_grid* g, const double* U, double* L, void* stream);
 int geno6_step(const geno6_grid* g, double* U, void* ws, int nsteps, double* dt_out,
                geno_stats* stats, void* stream);
 
-/* Kernel kinds of geno6_step for the timing hooks below. */
+/* ---- many small grids ----------------------------------------------------
+ * The paper's 1-D problems have 200 to 1800 cells, far too few to fill the
+ * GPU: one launch per stage is then latency-bound. geno6_step_batch advances
+ * ngrids grids of the same geometry and parameters (different states) by
+ * nsteps steps in ONE launch: one work-group per grid (1024 lanes; 512 with
+ * characteristic variables) runs all steps and stages (each grid keeps its
+ * own CFL time step), with the stage arithmetic of geno6_step in the same
+ * order, so each grid's result equals geno6_step on that grid alone, bit for
+ * bit. Intended for small grids (the work-group sweeps its grid in passes of
+ * 1023, resp. 511, cells).
+ * U (device): ngrids states one after the other, each in the layout above
+ *   (3 * pitch doubles), advanced in place.
+ * ws: geno6_batch_workspace_bytes(g, ngrids) bytes (control block and three
+ *   stage arrays per grid).
+ * dt_out (device, may be NULL): [ngrids][nsteps] step sizes.
+ * stats: as geno6_step (counts summed over the grids; last_dt of grid 0). */
+#define GENO6_BATCH_MAX 65535
+size_t geno6_batch_workspace_bytes(const geno6_grid* g, int ngrids);
+int geno6_step_batch(const geno6_grid* g, int ngrids, double* U, void* ws, int nsteps,
+                     double* dt_out, geno_stats* stats, void* stream);
+
+/* Kernel kinds of geno6_step and geno6_step_batch for the timing hooks. */
 enum {
   GENO6_K_INIT = 0,   /* wave-speed maxima of the initial state */
   GENO6_K_DT,         /* time step of a step from the maxima (one work-group) */
   GENO6_K_STAGE,      /* one Runge-Kutta stage: GENO on both sides of every
                          face, HLLC, flux difference and the stage combination
                          (the last stage also forms the next maxima) */
+  GENO6_K_SMALL,      /* geno6_step_batch: all steps of all grids */
   GENO6_NKERNELS
 };
 

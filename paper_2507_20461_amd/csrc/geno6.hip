@@ -68,17 +68,23 @@ struct Timing6 {
 Timing6 g_tim6;
 
 template <typename... KArgs, typename... Args>
-hipError_t launch6(int kind, void (*kern)(KArgs...), unsigned grid, hipStream_t s, Args&&... args) {
+hipError_t launch6_bs(int kind, void (*kern)(KArgs...), unsigned grid, unsigned bs, hipStream_t s,
+                      Args&&... args) {
   std::tuple<KArgs...> tup = validateArgsCountType(kern, std::tuple<Args...>{args...});
   void* argv[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
   pArgs<0>(tup, argv);
   if (kind >= 0 && g_tim6.used < g_tim6.cap) {
     const int u = g_tim6.used++;
     g_tim6.kind[u] = kind;
-    return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(TB), argv, 0, s,
+    return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(bs), argv, 0, s,
                               g_tim6.ev[2 * u], g_tim6.ev[2 * u + 1], 0);
   }
-  return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(TB), argv, 0, s);
+  return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(bs), argv, 0, s);
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch6(int kind, void (*kern)(KArgs...), unsigned grid, hipStream_t s, Args&&... args) {
+  return launch6_bs(kind, kern, grid, TB, s, std::forward<Args>(args)...);
 }
 
 // ---------------------------------------------------------------------------
@@ -139,7 +145,8 @@ __device__ __forceinline__ unsigned block_sum(unsigned v, unsigned* red) {
 // ---------------------------------------------------------------------------
 // Start of geno6_step: counters and maxima slots cleared (one work-group).
 __global__ void __launch_bounds__(TB) k6_clear(unsigned long long* __restrict__ slots, Ctrl6* ctrl) {
-  for (int q = threadIdx.x; q < NSLOT; q += TB) slots[q] = 0ull;
+  if (slots)
+    for (int q = threadIdx.x; q < NSLOT; q += TB) slots[q] = 0ull;
   if (threadIdx.x == 0) {
     ctrl->guard = 0;
     ctrl->nonfinite = 0;
@@ -300,6 +307,144 @@ __global__ void __launch_bounds__(TB) k6_faces(Geo6 g, KP6 k, const double* __re
       chi[f * nf + s] = X[f];
       chi[(3 + f) * nf + s] = X[3 + f];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small grids (the paper's 1-D problems have 200 to 1800 cells): one
+// work-group of SB lanes per grid runs all steps and stages of the call in
+// one launch. Each stage sweeps the grid in passes of SB - 1 cells (stage
+// the pass's cells and halo in LDS, reconstruct and flux its SB faces, flux
+// difference and stage combination of its cells); a barrier between stages
+// makes the stage's writes visible to the work-group (its waves share one
+// CU's caches). The arithmetic is the stage kernel's, in the same order, so
+// each grid's result is the one geno6_step gives.
+// ---------------------------------------------------------------------------
+// Lanes per work-group (one grid): 1024 with conservative variables; 512
+// with characteristic ones, whose face code needs more than the 128 VGPRs a
+// 1024-lane work-group leaves each lane.
+template <bool CHAR>
+struct SmallShape {
+  static constexpr int SB = CHAR ? 512 : 1024;
+  static constexpr int SC = SB - 1;               // cells per pass
+  static constexpr int SL = SC + 2 * HALO;        // staged cells per variable
+};
+
+template <int SB>
+__device__ __forceinline__ double block_max_s(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int w = 1; w < SB / 64; ++w) m = fmax(m, red[w]);
+  return m;
+}
+
+template <int SB>
+__device__ __forceinline__ unsigned block_sum_s(unsigned v, unsigned* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned s = 0;
+#pragma unroll
+  for (int w = 0; w < SB / 64; ++w) s += red[w];
+  return s;
+}
+
+template <bool CHAR>
+__global__ void __launch_bounds__(SmallShape<CHAR>::SB) k6_small(Geo6 g, KP6 k,
+                                                                  double* __restrict__ Ubase,
+                                                                  double* __restrict__ wsbase,
+                                                                  size_t stride, int nsteps,
+                                                                  double* __restrict__ dt_out,
+                                                                  Ctrl6* ctrl) {
+  constexpr int SB = SmallShape<CHAR>::SB, SC = SmallShape<CHAR>::SC, SL = SmallShape<CHAR>::SL;
+  __shared__ double su[3][SL];
+  __shared__ double sf[3][SB];
+  __shared__ double redd[SB / 64];
+  __shared__ unsigned redu[SB / 64];
+  const int t = (int)threadIdx.x;
+  const size_t gi = blockIdx.x;
+  double* U = Ubase + gi * stride;
+  double* acc = wsbase + gi * 3 * stride;
+  double* ya = acc + stride;
+  double* yb = ya + stride;
+  // wave-speed maximum of the initial state
+  double smax = 0.0;
+  for (int c = t; c < g.n; c += SB)
+    smax = fmax(smax, wave_speed(k.gamma, U[c], U[(size_t)g.pitch + c], U[2 * (size_t)g.pitch + c]));
+  smax = block_max_s<SB>(smax, redd);
+  unsigned guard = 0, bad = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    const double dt = k.dt_fixed > 0.0 ? k.dt_fixed : k.cfl * g.dx / smax;
+    if (t == 0 && dt_out) dt_out[gi * nsteps + step] = dt;
+    double snew = 0.0;
+#pragma unroll 1
+    for (int stage = 0; stage < 4; ++stage) {
+      const double* Y = stage == 0 ? U : (stage == 2 ? yb : ya);
+      double* Yout = stage == 0 ? ya : (stage == 1 ? yb : (stage == 2 ? ya : U));
+      for (int c0 = 0; c0 < g.n; c0 += SC) {
+        for (int q = t; q < SL; q += SB) {
+          const int i = c0 - HALO + q;
+          if (i <= g.n + 2) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) su[f][q] = cell_at(g, Y, f, i);
+          }
+        }
+        __syncthreads();
+        if (c0 + t <= g.n) {
+          const auto get = [&](int f, int m) { return su[f][t + m]; };
+          double WL[3], WR[3], F[3];
+          guard += (unsigned)geno6::face6<double, CHAR>(get, k, WL, WR, F, nullptr);
+#pragma unroll
+          for (int f = 0; f < 3; ++f) sf[f][t] = F[f];
+        }
+        __syncthreads();
+        const int c = c0 + t;
+        if (t < SC && c < g.n) {
+          double wnew[3];
+#pragma unroll
+          for (int f = 0; f < 3; ++f) {
+            const double L = -(sf[f][t + 1] - sf[f][t]) * g.inv_dx;
+            const size_t o = (size_t)f * g.pitch + c;
+            if (stage == 0) {
+              const double y = su[f][t + HALO];
+              acc[o] = y + (dt * (1.0 / 6.0)) * L;
+              Yout[o] = y + (0.5 * dt) * L;
+            } else if (stage == 1) {
+              acc[o] = acc[o] + (dt * (1.0 / 3.0)) * L;
+              Yout[o] = U[o] + (0.5 * dt) * L;
+            } else if (stage == 2) {
+              acc[o] = acc[o] + (dt * (1.0 / 3.0)) * L;
+              Yout[o] = U[o] + dt * L;
+            } else {
+              wnew[f] = acc[o] + (dt * (1.0 / 6.0)) * L;
+              Yout[o] = wnew[f];
+            }
+          }
+          if (stage == 3) {
+            if (physical(wnew[0], wnew[1], wnew[2]))
+              snew = fmax(snew, wave_speed(k.gamma, wnew[0], wnew[1], wnew[2]));
+            else
+              ++bad;
+          }
+        }
+        __syncthreads();   // the pass's LDS is reused; its global writes are read next stage
+      }
+    }
+    smax = block_max_s<SB>(snew, redd);
+  }
+  const unsigned gsum = block_sum_s<SB>(guard, redu);
+  const unsigned nbad = block_sum_s<SB>(bad, redu);
+  if (t == 0) {
+    if (gsum) atomicAdd(&ctrl->guard, (unsigned long long)gsum);
+    if (nbad) atomicAdd(&ctrl->nonfinite, (unsigned long long)nbad);
+    if (gi == 0 && nsteps > 0) ctrl->dt = k.dt_fixed > 0.0 ? k.dt_fixed : k.cfl * g.dx / smax;
   }
 }
 
@@ -493,6 +638,44 @@ int geno6_step(const geno6_grid* g, double* U, void* ws, int nsteps, double* dt_
     HIP_TRY(launch6(GENO6_K_STAGE, s3, nb, s, geo, k, (const double*)ya, (const double*)U, acc, U,
                     ctrl, slots));
   }
+  if (stats) {
+    Ctrl6 h;
+    HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stats->guard = (long long)h.guard;
+    stats->nonfinite = (long long)h.nonfinite;
+    stats->last_dt = nsteps > 0 ? h.dt : 0.0;
+    if (h.nonfinite) return fail(GENO_ENONPHYS, "%llu non-physical cells", h.nonfinite);
+  }
+  return GENO_OK;
+}
+
+size_t geno6_batch_workspace_bytes(const geno6_grid* g, int ngrids) {
+  if (check_grid6(g) || ngrids < 1) return 0;
+  return align256(sizeof(Ctrl6)) + (size_t)ngrids * 3 * 3 * (size_t)g->pitch * sizeof(double);
+}
+
+int geno6_step_batch(const geno6_grid* g, int ngrids, double* U, void* ws, int nsteps,
+                     double* dt_out, geno_stats* stats, void* stream) {
+  int rc = check_grid6(g);
+  if (rc) return rc;
+  if (ngrids < 1 || ngrids > GENO6_BATCH_MAX) return fail(GENO_EINVAL, "ngrids must be in [1, %d]", GENO6_BATCH_MAX);
+  if (!U || !ws) return fail(GENO_EINVAL, "null state or workspace");
+  if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  Ctrl6* ctrl = (Ctrl6*)base;
+  double* arrays = (double*)(base + align256(sizeof(Ctrl6)));
+  const Geo6 geo = geo6(g);
+  const KP6 k = kp6(g->params);
+  const size_t stride = 3 * (size_t)g->pitch;
+  HIP_TRY(launch6(-1, k6_clear, 1, s, (unsigned long long*)nullptr, ctrl));
+  if (k.characteristic)
+    HIP_TRY(launch6_bs(GENO6_K_SMALL, k6_small<true>, (unsigned)ngrids, SmallShape<true>::SB, s, geo,
+                       k, U, arrays, stride, nsteps, dt_out, ctrl));
+  else
+    HIP_TRY(launch6_bs(GENO6_K_SMALL, k6_small<false>, (unsigned)ngrids, SmallShape<false>::SB, s,
+                       geo, k, U, arrays, stride, nsteps, dt_out, ctrl));
   if (stats) {
     Ctrl6 h;
     HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, s));

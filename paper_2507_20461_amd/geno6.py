@@ -16,9 +16,10 @@ from . import geno_gks as G
 ABI_VERSION = 3
 VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
 BC_FIXED = 3
-KERNELS = ("init", "dt", "stage")
+KERNELS = ("init", "dt", "stage", "small")
 EXPORTS = ("geno6_params_default", "geno6_grid_init", "geno6_workspace_bytes", "geno6_faces", "geno6_rhs",
-           "geno6_step", "geno6_timing_enable", "geno6_timing_read", "geno6_op_costs")
+           "geno6_step", "geno6_timing_enable", "geno6_timing_read", "geno6_op_costs",
+           "geno6_batch_workspace_bytes", "geno6_step_batch")
 
 
 class geno6_params(ctypes.Structure):
@@ -52,8 +53,11 @@ def lib():
         L.geno6_timing_enable.argtypes = [i]
         L.geno6_timing_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
         L.geno6_op_costs.argtypes = [ctypes.POINTER(ctypes.c_double)]
+        L.geno6_batch_workspace_bytes.argtypes = [gp, i]
+        L.geno6_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.geno6_step_batch.argtypes = [gp, i, vp, vp, i, vp, ctypes.POINTER(G.geno_stats), vp]
         for name in EXPORTS:
-            if name != "geno6_workspace_bytes":
+            if name not in ("geno6_workspace_bytes", "geno6_batch_workspace_bytes"):
                 getattr(L, name).restype = i
         _ready = True
     return L
@@ -151,3 +155,21 @@ def op_costs():
     c = (ctypes.c_double * 3)()
     G._check(lib().geno6_op_costs(c))
     return {"face": c[0], "low_side": c[1], "cell": c[2]}
+
+
+def batch_workspace(grid, ngrids, device="cuda"):
+    return torch.empty(lib().geno6_batch_workspace_bytes(ctypes.byref(grid.g), int(ngrids)), dtype=torch.uint8,
+                       device=device)
+
+
+def step_batch(grid, U, ws, nsteps, dt_out=None, stats=False, stream=None):
+    """nsteps steps of every grid of U [ngrids, 3, pitch] in place, one launch."""
+    ngrids = U.shape[0]
+    G._need(U, torch.float64, ngrids * 3 * grid.pitch, "U")
+    G._need(ws, torch.uint8, lib().geno6_batch_workspace_bytes(ctypes.byref(grid.g), int(ngrids)), "ws")
+    G._need(dt_out, torch.float64, ngrids * nsteps, "dt_out", optional=True)
+    st = G.geno_stats() if stats else None
+    G._check(lib().geno6_step_batch(ctypes.byref(grid.g), int(ngrids), G._ptr(U), G._ptr(ws), int(nsteps),
+                                    G._ptr(dt_out), ctypes.byref(st) if st is not None else None,
+                                    G._stream(stream)))
+    return st

@@ -124,6 +124,10 @@ def test_noncompact_host_side_validation(so):
     assert S.lib().geno6_step(ctypes.byref(g.g), None, None, 1, None, None, None) == G.GENO_EINVAL
     assert S.lib().geno6_rhs(ctypes.byref(g.g), None, None, None) == G.GENO_EINVAL
     assert S.lib().geno6_faces(ctypes.byref(g.g), None, None, None, None, None, None) == G.GENO_EINVAL
+    assert S.lib().geno6_batch_workspace_bytes(ctypes.byref(g.g), 4) >= 4 * 3 * 3 * 1024 * 8
+    assert S.lib().geno6_batch_workspace_bytes(ctypes.byref(g.g), 0) == 0
+    assert S.lib().geno6_step_batch(ctypes.byref(g.g), 0, None, None, 1, None, None, None) == G.GENO_EINVAL
+    assert S.lib().geno6_step_batch(ctypes.byref(g.g), 2, None, None, 1, None, None, None) == G.GENO_EINVAL
 
 
 def test_noncompact_op_costs(so):

@@ -293,3 +293,40 @@ def test_full_size_sampled(S, n):
         assert np.all(np.abs(got[:, q] - Wo[:, 20]) <= TOL * sc), c
     # the CFL dt of the whole state
     assert dt == pytest.approx(O6.cfl_dt(O6.params(), U, grid.dx), rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [3, 200, 511, 1023, 1024, 1800, 2047])
+@pytest.mark.parametrize("char", [False, True], ids=["cons", "char"])
+def test_batch_equals_single_grid_steps(S, n, char):
+    # one launch for several grids: each grid bit for bit as geno6_step on it
+    _say("geno6 batch n=%d char=%d" % (n, char))
+    ngr, steps = 5, 7
+    bcs = [(1, 1), (0, 0), (2, 2), (1, 2), (0, 0)]
+    for bc in bcs[:2] if n < 6 else bcs:
+        grid = S.Grid6(n, 0.0, 1.0, bc=bc, variables=int(char))
+        states = [inputs.shocks_noncompact(n, seed, cells_per_segment=max(4, n // 3)) for seed in range(ngr)]
+        Ub = torch.stack([grid.to_device(U) for U in states])
+        dtb = torch.zeros(ngr, steps, dtype=torch.float64, device="cuda")
+        st = S.step_batch(grid, Ub, S.batch_workspace(grid, ngr), steps, dt_out=dtb, stats=True)
+        assert st.nonfinite == 0
+        ws = grid.workspace()
+        guard = 0
+        for gi, U in enumerate(states):
+            Ud = grid.to_device(U)
+            dts = torch.zeros(steps, dtype=torch.float64, device="cuda")
+            guard += S.step(grid, Ud, ws, steps, dt_out=dts, stats=True).guard
+            assert torch.equal(Ub[gi], Ud), (bc, gi)
+            assert torch.equal(dtb[gi], dts), (bc, gi)
+        assert st.guard == guard
+
+
+def test_batch_reports_nonphysical_states(S):
+    n = 64
+    U = inputs.smooth_noncompact(n, seed=1)
+    U[2, 10] = -1.0
+    grid = S.Grid6(n, dt_fixed=1e-6)
+    Ub = torch.stack([grid.to_device(U), grid.to_device(inputs.smooth_noncompact(n, seed=2))])
+    from paper_2507_20461_amd import geno_gks as G
+    with pytest.raises(G.GenoError) as e:
+        S.step_batch(grid, Ub, S.batch_workspace(grid, 2), 1, stats=True)
+    assert e.value.code == G.GENO_ENONPHYS
