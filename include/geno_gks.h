@@ -196,7 +196,9 @@ size_t gks_workspace_bytes(const geno_grid* g);
  *   [side][var][row][face] over the rows the tangential step reads:
  *   1-D 1 x (nx+1); x-faces (ny+2) x (nx+1) (rows -1..ny); y-faces
  *   (ny+1) x (nx+2) (columns -1..nx) - the same face-row layout with rows and
- *   faces swapped, i.e. [side][var][face a][column b].
+ *   faces swapped, i.e. [side][var][face a][column b]. With characteristic
+ *   variables (1-D) var indexes the characteristic fields (speeds u - c,
+ *   u, u + c) of each face.
  * ws: workspace of gks_workspace_bytes(g) bytes. */
 int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_state,
                      void* chi, void* ws, void* stream);
@@ -241,7 +243,9 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
  * geno_params normalised to sum 1; TENO's chi is 1 or 0).
  * chi3 (device): [3][2][nvar][n0][n1] doubles, [method][side][var] planes in
  * the face-row layout of geno_reconstruct's chi. Fills the ghost layers of
- * W, dW like geno_reconstruct; ws: workspace of gks_workspace_bytes(g). */
+ * W, dW like geno_reconstruct; ws: workspace of gks_workspace_bytes(g).
+ * The comparison works on the conservative variables whatever
+ * geno_params.variables says. */
 int geno_linearity(const geno_grid* g, void* W, void* dW, int dir, double* chi3, double teno_ct,
                    void* ws, void* stream);
 
