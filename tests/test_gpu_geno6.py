@@ -330,3 +330,22 @@ def test_batch_reports_nonphysical_states(S):
     with pytest.raises(G.GenoError) as e:
         S.step_batch(grid, Ub, S.batch_workspace(grid, 2), 1, stats=True)
     assert e.value.code == G.GENO_ENONPHYS
+
+
+def test_batch_fixed_ends_and_zero_steps(S):
+    # Titarev-Toro states with fixed ends in a batch of 3 (the ghost states
+    # are part of the shared grid description), and a call of zero steps
+    U, ghost = inputs.titarev_toro_noncompact(1000)
+    grid = S.Grid6(1000, -5.0, 5.0, bc=S.BC_FIXED, ghost=ghost)
+    states = [U, U * np.array([[1.01], [1.0], [1.02]]), U]
+    Ub = torch.stack([grid.to_device(x) for x in states])
+    ws = S.batch_workspace(grid, 3)
+    before = Ub.clone()
+    S.step_batch(grid, Ub, ws, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(Ub, before)
+    S.step_batch(grid, Ub, ws, 6)
+    for gi, x in enumerate(states):
+        Ud = grid.to_device(x)
+        S.step(grid, Ud, grid.workspace(), 6)
+        assert torch.equal(Ub[gi], Ud), gi
