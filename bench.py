@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--noncompact-steps", type=int, default=40,
                     help="timed Runge-Kutta steps of the 1-D sixth-order non-compact workload (0 = skip)")
     ap.add_argument("--no-paper-problems", action="store_true",
-                    help="skip the paper's 1-D problems with the non-compact scheme")
+                    help="skip the paper's 1-D problems and the small-grid batch with the non-compact scheme")
     return ap.parse_args()
 
 
@@ -304,7 +304,8 @@ def noncompact_workload(np, torch, inputs, seed, steps, n=NONCOMPACT_N, min_cpu_
     torch.cuda.synchronize()
     out["entropy_wave_1800"] = {"us_per_step": round(1e3 * e0.elapsed_time(e1) / 100, 2),
                                 "launches_per_step": 5}
-    out["small_grids"] = noncompact_small_grids(np, torch, inputs, S)
+    if paper:
+        out["small_grids"] = noncompact_small_grids(np, torch, inputs, S)
     if paper:
         out["paper_problems"] = noncompact_paper_runs(np, torch, inputs)
     if cpu:

@@ -71,6 +71,7 @@ def run(extra=()):
     and the result file is complete."""
     os.makedirs(OUT, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp")
+    dest = os.path.join(OUT, "profiles")
     for name in PASSES:
         cmd = command(name, extra)
         print("==", " ".join(cmd), flush=True)
@@ -79,12 +80,14 @@ def run(extra=()):
         res = os.path.join(OUT, "prof_" + name, "run_kernel_stats.csv" if name == "ktrace"
                            else "run_counter_collection.csv")
         print("   exit %d, results %s" % (rc, "present" if os.path.exists(res) else "missing"), flush=True)
+        if name == "ktrace" and os.path.exists(os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv")):
+            # summarised next to the raw output at once; the per-dispatch
+            # trace (tens of MB for the default benchmark) is then dropped
+            summarize_ktrace(dest=dest)
+            os.remove(os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv"))
         if rc != 0 and not (rc in (139, -11) and os.path.exists(res)):
             sys.exit(rc if rc > 0 else 1)
-    # summaries next to the raw output; the per-dispatch kernel trace (tens
-    # of MB for the default benchmark) is dropped once summarised
-    summarize(dest=os.path.join(OUT, "profiles"))
-    os.remove(os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv"))
+    summarize(dest=dest)
 
 
 def _short(name):
@@ -122,7 +125,10 @@ def _cal_scale(path, counter):
     return None
 
 
-def summarize(tag="faces_fp64_512", dest=PROFILES):
+def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
+    """Per-workload kernel averages from the kernel trace into
+    <tag>_kernel_stats.txt, and the averages of the benchmark's two
+    workloads into <tag>_ktrace_avg.json (read by the counter summary)."""
     os.makedirs(dest, exist_ok=True)
     sh = source_hash()
     lines = []
@@ -166,6 +172,16 @@ def summarize(tag="faces_fp64_512", dest=PROFILES):
                 ktrace.setdefault(k, []).extend(v)
     ktrace = {k: sum(v) / len(v) for k, v in ktrace.items()}
     open(os.path.join(dest, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(dest, "%s_ktrace_avg.json" % tag), "w").write(json.dumps(ktrace, indent=1) + "\n")
+
+
+def summarize(tag="faces_fp64_512", dest=PROFILES):
+    os.makedirs(dest, exist_ok=True)
+    sh = source_hash()
+    trace_csv = os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv")
+    if os.path.exists(trace_csv):
+        summarize_ktrace(tag, dest)
+    ktrace = json.load(open(os.path.join(dest, "%s_ktrace_avg.json" % tag)))
     # counters
     F = _counters(os.path.join(OUT, "prof_fetch", "run_counter_collection.csv"), "FETCH_SIZE")
     Wr = _counters(os.path.join(OUT, "prof_write", "run_counter_collection.csv"), "WRITE_SIZE")
