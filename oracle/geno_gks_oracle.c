@@ -45,7 +45,7 @@ enum {
   PI_GAMMA = 0, PI_CPATH, PI_EPS, PI_R, PI_RL, PI_D1, PI_D2, PI_D3,
   PI_TAUC1, PI_TAUC2, PI_CFL, PI_BCXL, PI_BCXH, PI_BCYL, PI_BCYH,
   PI_GHOST,     /* 24 values, 1-D fixed ends: [end][layer][W (3), dW (3)] */
-  PI_CHAR = PI_GHOST + 24,   /* 1-D: 1 = characteristic-variable reconstruction */
+  PI_CHAR = PI_GHOST + 24,   /* 1 = characteristic-variable reconstruction (normal step) */
   PI_COUNT
 };
 
@@ -54,7 +54,7 @@ typedef struct {
   int bc[4];           /* 0 periodic, 1 transmissive, 2 reflecting, 3 fixed (1-D only):
                           x-lo, x-hi, y-lo, y-hi */
   double ghost[2][2][6];  /* fixed ends: [end][layer 0 = next to the grid][W, dW] */
-  int characteristic;     /* 1-D: reconstruct characteristic variables */
+  int characteristic;     /* reconstruct characteristic variables in the normal step */
   int ndim, nx, ny;
   double dx, dy;
   double K;            /* internal degrees of freedom of the BGK model */
@@ -750,68 +750,107 @@ static int admissible(const ocfg *P, const double *W) {
 /* Normal GENO for the face between cells (i, j) and (i+1, j) along x (dir 0)
  * or between (i, j) and (i, j+1) along y (dir 1) in ghosted coordinates.
  * out[side][quant][var]: quant 0 value, 1 h * normal derivative; chi[side][var]. */
-/* Characteristic variables (reading, 1-D option): right eigenvectors of the
- * Euler flux Jacobian at the Roe average of the two cells at the face,
- * columns for the speeds u - c, u, u + c; the left ones are their inverse,
- * by Gaussian elimination. Returns nonzero when the average has no real
- * sound speed (the face then keeps the conservative variables). */
-static int roe_eigen(const ocfg *P, const double *Wa, const double *Wb, double R[3][3],
-                     double L[3][3]) {
+/* Characteristic variables (reading; the paper does not name the variables
+ * it reconstructs): right eigenvectors of the Euler flux Jacobian in the
+ * normal direction `dir` at the Roe average of the two cells at the face.
+ * In the normal frame (normal velocity un, tangential ut) the columns belong
+ * to the speeds un - c, un, un (shear, 2-D only), un + c; the left vectors are
+ * the inverse matrix, by Gaussian elimination. Components are stored in the
+ * state order (rho, rho U, [rho V,] rho E), so along y the two momentum rows
+ * trade places. Returns nonzero when the average has no real sound speed
+ * (the face then keeps the conservative variables). */
+static int roe_eigen(const ocfg *P, int dir, const double *Wa, const double *Wb,
+                     double R[4][4], double L[4][4]) {
+  const int nv = P->nv, e = nv - 1;
+  const int in = 1 + dir, it = 2 - dir;   /* normal and (2-D) tangential momentum */
   const double g = P->gamma;
-  const double pa = (g - 1.0) * (Wa[2] - 0.5 * Wa[1] * Wa[1] / Wa[0]);
-  const double pb = (g - 1.0) * (Wb[2] - 0.5 * Wb[1] * Wb[1] / Wb[0]);
-  const double sa = sqrt(Wa[0]), sb = sqrt(Wb[0]);
-  const double u = (sa * Wa[1] / Wa[0] + sb * Wb[1] / Wb[0]) / (sa + sb);
-  const double H = (sa * (Wa[2] + pa) / Wa[0] + sb * (Wb[2] + pb) / Wb[0]) / (sa + sb);
-  const double c2 = (g - 1.0) * (H - 0.5 * u * u);
-  if (!(c2 > 0.0)) return 1;
-  const double c = sqrt(c2);
-  const double Rm[3][3] = {{1.0, 1.0, 1.0}, {u - c, u, u + c}, {H - u * c, 0.5 * u * u, H + u * c}};
-  for (int col = 0; col < 3; ++col) {
-    double A[9], b[3] = {0.0, 0.0, 0.0};
-    for (int r = 0; r < 3; ++r)
-      for (int k = 0; k < 3; ++k) A[r * 3 + k] = Rm[r][k];
-    b[col] = 1.0;
-    if (solve_d(3, A, b)) return 1;
-    for (int r = 0; r < 3; ++r) L[r][col] = b[r];
+  double sa = sqrt(Wa[0]), sb = sqrt(Wb[0]);
+  double vel[2][3], H[2];
+  const double *Ws[2] = {Wa, Wb};
+  for (int s = 0; s < 2; ++s) {
+    const double *W = Ws[s];
+    double ke = 0.0;
+    for (int k = 1; k < e; ++k) { vel[s][k] = W[k] / W[0]; ke += W[k] * vel[s][k]; }
+    double p = (g - 1.0) * (W[e] - 0.5 * ke);
+    H[s] = (W[e] + p) / W[0];
   }
-  for (int r = 0; r < 3; ++r)
-    for (int k = 0; k < 3; ++k) R[r][k] = Rm[r][k];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int k = 1; k < e; ++k) v[k] = (sa * vel[0][k] + sb * vel[1][k]) / (sa + sb);
+  const double Hr = (sa * H[0] + sb * H[1]) / (sa + sb);
+  double q2 = 0.0;
+  for (int k = 1; k < e; ++k) q2 += v[k] * v[k];
+  const double c2 = (g - 1.0) * (Hr - 0.5 * q2);
+  if (!(c2 > 0.0)) return 1;
+  const double c = sqrt(c2), un = v[in];
+  double Rm[4][4];
+  memset(Rm, 0, sizeof Rm);
+  /* acoustic and entropy columns: 0 (un - c), 1 (un), nv - 1 (un + c) */
+  const int cols[3] = {0, 1, nv - 1};
+  const double shift[3] = {-c, 0.0, c};
+  for (int q = 0; q < 3; ++q) {
+    int col = cols[q];
+    Rm[0][col] = 1.0;
+    for (int k = 1; k < e; ++k) Rm[k][col] = v[k];
+    Rm[in][col] += shift[q];
+    Rm[e][col] = (q == 1) ? 0.5 * q2 : Hr + shift[q] * un;
+  }
+  if (nv == 4) {   /* shear column: tangential momentum */
+    Rm[it][2] = 1.0;
+    Rm[e][2] = v[it];
+  }
+  for (int col = 0; col < nv; ++col) {
+    double A[16], b[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < nv; ++r)
+      for (int k = 0; k < nv; ++k) A[r * nv + k] = Rm[r][k];
+    b[col] = 1.0;
+    if (solve_d(nv, A, b)) return 1;
+    for (int r = 0; r < nv; ++r) L[r][col] = b[r];
+  }
+  for (int r = 0; r < nv; ++r)
+    for (int k = 0; k < nv; ++k) R[r][k] = Rm[r][k];
   return 0;
 }
 
 static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
                         double out[2][2][4], double chi[2][4]) {
   int nv = P->nv;
-  double R[3][3], L[3][3];
-  if (P->ndim == 1 && P->characteristic) {
-    double Wa[3], Wb[3];
-    for (int v = 0; v < 3; ++v) { Wa[v] = g->W[gidx(g, v, j, i)]; Wb[v] = g->W[gidx(g, v, j, i + 1)]; }
-    if (!roe_eigen(P, Wa, Wb, R, L)) {
-      double val[2][3], der[2][3];
-      for (int c = 0; c < 3; ++c) {
+  double h = (dir == 0) ? P->dx : P->dy;
+  double R[4][4], L[4][4];
+  if (P->characteristic) {
+    /* the two cells at the face are m = 0 and m = 1 of the normal stencil */
+    double Wa[4], Wb[4];
+    for (int v = 0; v < nv; ++v) {
+      Wa[v] = g->W[gidx(g, v, j, i)];
+      Wb[v] = g->W[gidx(g, v, dir == 0 ? j : j + 1, dir == 0 ? i + 1 : i)];
+    }
+    if (!roe_eigen(P, dir, Wa, Wb, R, L)) {
+      double val[2][4], der[2][4];
+      for (int c = 0; c < nv; ++c) {
         double q[4] = {0, 0, 0, 0}, gg[4] = {0, 0, 0, 0};
-        for (int m = -1; m <= 2; ++m)
-          for (int v = 0; v < 3; ++v) {
-            q[m + 1] += L[c][v] * g->W[gidx(g, v, j, i + m)];
-            gg[m + 1] += L[c][v] * P->dx * g->dW[gidx(g, v, j, i + m)];
+        for (int m = -1; m <= 2; ++m) {
+          int ii = (dir == 0) ? i + m : i, jj = (dir == 0) ? j : j + m;
+          for (int v = 0; v < nv; ++v) {
+            q[m + 1] += L[c][v] * g->W[gidx(g, v, jj, ii)];
+            gg[m + 1] += L[c][v] * h * g->dW[gidx(g, dir * nv + v, jj, ii)];
           }
+        }
         double l[3], r[3];
         geno_face(P, q, gg, l, r);
         val[0][c] = l[0]; der[0][c] = l[1]; chi[0][c] = l[2];
         val[1][c] = r[0]; der[1][c] = r[1]; chi[1][c] = r[2];
       }
       for (int s = 0; s < 2; ++s)
-        for (int v = 0; v < 3; ++v) {
-          out[s][0][v] = R[v][0] * val[s][0] + R[v][1] * val[s][1] + R[v][2] * val[s][2];
-          out[s][1][v] = R[v][0] * der[s][0] + R[v][1] * der[s][1] + R[v][2] * der[s][2];
+        for (int v = 0; v < nv; ++v) {
+          double a0 = 0.0, a1 = 0.0;
+          for (int c = 0; c < nv; ++c) { a0 += R[v][c] * val[s][c]; a1 += R[v][c] * der[s][c]; }
+          out[s][0][v] = a0;
+          out[s][1][v] = a1;
         }
       return;
     }
   }
   for (int v = 0; v < nv; ++v) {
     double q[4], gg[4];
-    double h = (dir == 0) ? P->dx : P->dy;
     for (int m = -1; m <= 2; ++m) {
       int ii = (dir == 0) ? i + m : i, jj = (dir == 0) ? j : j + m;
       q[m + 1] = g->W[gidx(g, v, jj, ii)];
@@ -1194,6 +1233,29 @@ static double teno_weights(const ocfg *P, const double IS[3], double ct, double 
     if (r < chi) chi = r;
   }
   return chi;
+}
+
+
+/* Characteristic decomposition of the normal-direction flux Jacobian at the
+ * Roe average of Wa and Wb (nv = 3 in 1-D, 4 in 2-D; dir 0 = x, 1 = y):
+ * R (nv x nv, row-major, columns are right eigenvectors), L = R^-1 and the
+ * speeds un - c, un, [un,] un + c. OR_EINVAL without a real sound speed. */
+int oracle_roe_eigen(const double *params, int ndim, int dir, const double *Wa, const double *Wb,
+                     double *R, double *L, double *lam) {
+  ocfg P;
+  cfg_from(&P, ndim, 1, 1, 1.0, 1.0, params);
+  if (ndim == 1 && dir != 0) return OR_EINVAL;
+  double Rm[4][4], Lm[4][4];
+  if (roe_eigen(&P, dir, Wa, Wb, Rm, Lm)) return OR_EINVAL;
+  const int nv = P.nv;
+  for (int r = 0; r < nv; ++r)
+    for (int k = 0; k < nv; ++k) { R[r * nv + k] = Rm[r][k]; L[r * nv + k] = Lm[r][k]; }
+  /* speeds: each non-shear column has density entry 1, so its normal
+   * momentum entry is its speed; the shear column moves with the entropy
+   * column's speed un */
+  const int in = 1 + dir;
+  for (int k = 0; k < nv; ++k) lam[k] = Rm[in][(nv == 4 && k == 2) ? 1 : k];
+  return OR_OK;
 }
 
 /* Weights of all three methods from given indicators IS[3]:

@@ -24,7 +24,7 @@ _lib = None
 P_GAMMA, P_CPATH, P_EPS, P_R, P_RL, P_D1, P_D2, P_D3, P_TAUC1, P_TAUC2, P_CFL = range(11)
 P_BC = 11  # four boundary codes follow: x-lo, x-hi, y-lo, y-hi (0 periodic, 1 transmissive)
 P_GHOST = 15  # 24 values: 1-D fixed ends [end][layer][W (3), dW (3)]
-P_CHAR = 39   # 1-D: 1 = characteristic-variable reconstruction
+P_CHAR = 39   # 1 = characteristic-variable reconstruction in the normal step
 N_PARAMS = 40
 PERIODIC, TRANSMISSIVE, REFLECTING, FIXED = 0, 1, 2, 3
 
@@ -55,6 +55,7 @@ def lib():
         L.oracle_geno_side_detail.argtypes = [dp, dp, i, d, d, dp]
         L.oracle_gks_points.argtypes = [dp, i, i, dp, dp, dp, dp, dp, dp, d, dp, dp, dp]
         L.oracle_normal_faces.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, dp]
+        L.oracle_roe_eigen.argtypes = [dp, i, i, dp, dp, dp, dp, dp]
         L.oracle_face_states.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, llp]
         L.oracle_step.argtypes = [dp, i, i, i, d, d, dp, dp, i, d, dp, llp]
         L.oracle_stage_faces.argtypes = [dp, i, i, i, d, d, dp, dp, d, i, dp, dp, dp]
@@ -64,7 +65,8 @@ def lib():
         L.oracle_cfl_dt.restype = d
         for name in ("oracle_linear_weights", "oracle_geno_face", "oracle_geno_side_detail", "oracle_moments",
                      "oracle_gks_points", "oracle_normal_faces", "oracle_face_states",
-                     "oracle_step", "oracle_stage_faces", "oracle_weights", "oracle_linearity_faces"):
+                     "oracle_step", "oracle_stage_faces", "oracle_weights", "oracle_linearity_faces",
+                     "oracle_roe_eigen"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -84,8 +86,10 @@ def params(ndim: int = 2, bc=TRANSMISSIVE, gamma=1.4, C=20.0, eps=1e-15, r=2.0, 
     """Oracle parameter vector. Paper constants (Sec. 3): C = 20, eps = 1e-15,
     r = 2 (structured), r^L = 2, central weight C_0 = 8. ghost: [2, 2, 6]
     states of the ghost cells of 1-D FIXED ends ([end][layer 0 = next to the
-    grid][W (3), dW (3)]); characteristic: 1-D reconstruction of the
-    characteristic variables of the Roe-averaged flux Jacobian at each face."""
+    grid][W (3), dW (3)]); characteristic: the normal step reconstructs the
+    characteristic variables of the normal flux Jacobian at the Roe average
+    of the two cells at each face (values and h-derivatives projected alike);
+    the tangential step of 2-D faces works on the conservative face values."""
     p = np.zeros(N_PARAMS)
     p[P_CHAR] = 1.0 if characteristic else 0.0
     if ghost is not None:
@@ -201,6 +205,16 @@ def normal_faces(prm, W, dW, direction=0, dx=None, dy=None):
     _check(lib().oracle_normal_faces(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), direction,
                                      _p(out), _p(chi)), "oracle_normal_faces")
     return out, chi
+
+
+def roe_eigen(prm, ndim, direction, Wa, Wb):
+    """Right eigenvectors R (columns), L = R^-1 and speeds of the normal flux
+    Jacobian at the Roe average of the states Wa, Wb."""
+    nv = 3 if ndim == 1 else 4
+    R, Lm, lam = np.zeros(nv * nv), np.zeros(nv * nv), np.zeros(nv)
+    _check(lib().oracle_roe_eigen(_p(_c(prm)), ndim, direction, _p(_c(Wa)), _p(_c(Wb)), _p(R), _p(Lm),
+                                  _p(lam)), "oracle_roe_eigen")
+    return R.reshape(nv, nv), Lm.reshape(nv, nv), lam
 
 
 def face_states(prm, W, dW, direction=0, dx=None, dy=None):
