@@ -184,6 +184,37 @@ def robustness_runs(G, inputs, np, torch):
     return out
 
 
+def characteristic_2d(G, np, torch, W, dW, n, steps):
+    """The headline workload with the characteristic normal step (Roe-averaged
+    eigenvectors along each face normal): the same initial state and steps,
+    timed the same way (outside the headline number), then replayed with
+    statistics for the guard count."""
+    grid = G.Grid(2, n, n, bc=G.BC_TRANSMISSIVE, variables=G.VARS_CHARACTERISTIC)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    stream = torch.cuda.current_stream()
+    G.gks_step(grid, Wd, dWd, ws, 2)
+
+    def restart():
+        Wd.copy_(grid.to_device(W))
+        dWd.copy_(grid.to_device(dW))
+        torch.cuda.synchronize()
+
+    restart()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    G.gks_step(grid, Wd, dWd, ws, steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    restart()
+    st = G.gks_step(grid, Wd, dWd, ws, steps, stats=True)
+    Wn = grid.interior(Wd)
+    return {"value": round(2.0 * n * n * steps / (ms / 1e3) / 1e6, 3), "unit": "Mcell-updates/s per stage",
+            "ms_per_step": round(ms / steps, 5), "steps": steps, "guard": int(st.guard),
+            "nonfinite": int(st.nonfinite), "rho_range": [float(Wn[0].min()), float(Wn[0].max())]}
+
+
 NONCOMPACT_N = 1 << 24
 NONCOMPACT_STAGE_BYTES = (72.0, 120.0, 120.0, 72.0)   # algorithmic HBM bytes per cell of stages 1..4
 
@@ -855,8 +886,9 @@ def main():
         # final state of the timed run (diagnostic, outside the timed region)
         "linearity_after_run": linearity_shares(G, torch, grid, Wd, dWd, ws),
     }
+    del ws, Wd, dWd
+    out["characteristic_2d"] = _finite(characteristic_2d(G, np, torch, W, dW, n, args.steps))
     if not args.no_forms:
-        del ws, Wd, dWd
         gate = train_gate(G, torch, args.seed)
         out["forms"] = _finite(forms_comparison(G, inputs, np, torch, args.seed, gate=gate))
     if not args.no_batched:

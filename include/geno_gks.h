@@ -62,7 +62,7 @@ extern "C" {
                                   writes them and carries them into its
                                   stage arrays */
 
-/* variables of the reconstruction (1-D) */
+/* variables of the normal reconstruction */
 #define GENO_VARS_CONSERVATIVE 0
 #define GENO_VARS_CHARACTERISTIC 1
 
@@ -102,15 +102,18 @@ extern "C" {
  *   noise of the two reconstructed states) is evaluated in that limit. The
  *   terms this drops are of order that ratio times the relative difference
  *   of the states or of h |grad W| / |W|, below the float32 unit roundoff.
- * variables: 1-D only: GENO_VARS_CONSERVATIVE (default) reconstructs rho,
- *   rho U, rho E component by component; GENO_VARS_CHARACTERISTIC projects
- *   the averages and h-scaled gradients of the four stencil cells on the
- *   left eigenvectors of the Euler flux Jacobian at the Roe average of the
- *   two cells at the face, reconstructs the three characteristic fields
- *   (values and derivatives) and maps both face states back with the right
- *   eigenvectors (a face whose Roe average has no real sound speed keeps the
- *   conservative variables). The paper does not say which variables it
- *   reconstructs.
+ * variables: GENO_VARS_CONSERVATIVE (default) reconstructs the conserved
+ *   variables component by component; GENO_VARS_CHARACTERISTIC projects the
+ *   averages and h-scaled normal gradients of the four stencil cells of the
+ *   normal step on the left eigenvectors of the Euler flux Jacobian along
+ *   the face normal at the Roe average of the two cells at the face,
+ *   reconstructs the characteristic fields (values and derivatives: three in
+ *   1-D; four in 2-D, the speeds un - c, un, un (shear), un + c) and maps both
+ *   face states back with the right eigenvectors (a face whose Roe average
+ *   has no real sound speed keeps the conservative variables). The 2-D
+ *   tangential step then works on the conservative face values. The paper
+ *   does not say which variables it reconstructs. Not combined with the
+ *   learned gate (GENO_EINVAL), whose network predicts conservative chi.
  * gate_delta: learned gate (2-D gks_step only). If > 0, before the normal
  *   reconstruction of each direction and stage the loaded network
  *   (geno_mlp_load) predicts chi of every cell from its stencil, and where the
@@ -133,7 +136,7 @@ typedef struct geno_params {
   double dt_fixed;
   double eps_ulps;
   double gate_delta;
-  int variables;   /* GENO_VARS_* (1-D) */
+  int variables;   /* GENO_VARS_* */
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */
@@ -197,8 +200,8 @@ size_t gks_workspace_bytes(const geno_grid* g);
  *   1-D 1 x (nx+1); x-faces (ny+2) x (nx+1) (rows -1..ny); y-faces
  *   (ny+1) x (nx+2) (columns -1..nx) - the same face-row layout with rows and
  *   faces swapped, i.e. [side][var][face a][column b]. With characteristic
- *   variables (1-D) var indexes the characteristic fields (speeds u - c,
- *   u, u + c) of each face.
+ *   variables var indexes the characteristic fields of each face (speeds
+ *   u - c, u, u + c in 1-D; un - c, un, un (shear), un + c in 2-D).
  * ws: workspace of gks_workspace_bytes(g) bytes. */
 int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_state,
                      void* chi, void* ws, void* stream);

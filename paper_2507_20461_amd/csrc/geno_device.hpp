@@ -35,7 +35,7 @@ struct KParams {
   double eps_ulps;    // float32 data: eps floor in units of 2^-24 of the stencil magnitude
   double gate_thr;    // learned gate: a prediction >= gate_thr sets chi = 1
   int gate;           // learned gate enabled
-  int charvars;       // 1-D: reconstruct characteristic variables
+  int charvars;       // reconstruct characteristic variables in the normal step
 };
 
 // Path function chi = tanh(C alpha)/tanh(C) (Eq. (4)) of the ultimate
@@ -293,6 +293,67 @@ GENO_HD bool admissible(const R* W, double gamma) {
   // p = (gamma - 1)(rhoE - |m|^2 / (2 rho)) > 0  <=>  rho rhoE - |m|^2 / 2 > 0 (rho > 0)
   (void)gamma;
   return W[0] * W[NV - 1] - R(0.5) * ke > R(0.0);
+}
+
+// Characteristic fields of the 2-D Euler flux Jacobian along a face normal,
+// at the Roe average of the two cells at the face, in the normal frame
+// (rho, rho un, rho ut, rho E). Right eigenvectors (columns) for the speeds
+// un - c, un, un (shear) and un + c:
+//   (1, un - c, ut, H - un c), (1, un, ut, q^2/2), (0, 0, 1, ut),
+//   (1, un + c, ut, H + un c),  q^2 = un^2 + ut^2,
+// and their inverse in closed form, with b1 = (gamma - 1)/c^2, b2 = b1 q^2/2:
+//   ((b2 + un/c)/2, -(b1 un + 1/c)/2, -b1 ut/2, b1/2),
+//   (1 - b2, b1 un, b1 ut, -b1), (-ut, 0, 1, 0),
+//   ((b2 - un/c)/2, -(b1 un - 1/c)/2, -b1 ut/2, b1/2).
+struct Eig2 {
+  double un, ut, c, H, q2;
+  double L[4][4];
+};
+
+// false when the average has no real sound speed (the face then keeps the
+// conservative variables)
+GENO_HD bool roe_eigen2(const double* Wa, const double* Wb, double gamma, Eig2& e) {
+  const double sa = sqrt(Wa[0]), sb = sqrt(Wb[0]);
+  const double isa = 1.0 / sa, isb = 1.0 / sb, iss = 1.0 / (sa + sb);
+  const double gm1 = gamma - 1.0;
+  const double pa = gm1 * (Wa[3] - 0.5 * (Wa[1] * Wa[1] + Wa[2] * Wa[2]) * isa * isa);
+  const double pb = gm1 * (Wb[3] - 0.5 * (Wb[1] * Wb[1] + Wb[2] * Wb[2]) * isb * isb);
+  // sqrt(rho) u = m / sqrt(rho); sqrt(rho) H = (E + p) / sqrt(rho)
+  e.un = (Wa[1] * isa + Wb[1] * isb) * iss;
+  e.ut = (Wa[2] * isa + Wb[2] * isb) * iss;
+  e.H = ((Wa[3] + pa) * isa + (Wb[3] + pb) * isb) * iss;
+  e.q2 = e.un * e.un + e.ut * e.ut;
+  const double c2 = gm1 * (e.H - 0.5 * e.q2);
+  if (!(c2 > 0.0)) return false;
+  e.c = sqrt(c2);
+  const double ic = 1.0 / e.c;
+  const double b1 = gm1 * ic * ic, b2 = 0.5 * b1 * e.q2, uc = e.un * ic;
+  e.L[0][0] = 0.5 * (b2 + uc);
+  e.L[0][1] = -0.5 * (b1 * e.un + ic);
+  e.L[0][2] = -0.5 * b1 * e.ut;
+  e.L[0][3] = 0.5 * b1;
+  e.L[1][0] = 1.0 - b2;
+  e.L[1][1] = b1 * e.un;
+  e.L[1][2] = b1 * e.ut;
+  e.L[1][3] = -b1;
+  e.L[2][0] = -e.ut;
+  e.L[2][1] = 0.0;
+  e.L[2][2] = 1.0;
+  e.L[2][3] = 0.0;
+  e.L[3][0] = 0.5 * (b2 - uc);
+  e.L[3][1] = -0.5 * (b1 * e.un - ic);
+  e.L[3][2] = e.L[0][2];
+  e.L[3][3] = e.L[0][3];
+  return true;
+}
+
+// W = R w (normal frame) with the right eigenvectors of e.
+GENO_HD void from_characteristic2(const Eig2& e, const double* w, double* W) {
+  const double uc = e.un * e.c, s = w[0] + w[1] + w[3];
+  W[0] = s;
+  W[1] = (e.un - e.c) * w[0] + e.un * w[1] + (e.un + e.c) * w[3];
+  W[2] = e.ut * s + w[2];
+  W[3] = (e.H - uc) * w[0] + 0.5 * e.q2 * w[1] + e.ut * w[2] + (e.H + uc) * w[3];
 }
 
 }  // namespace geno

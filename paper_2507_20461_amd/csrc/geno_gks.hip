@@ -356,6 +356,93 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
   init_body<NDIM, T>(g, gamma, W, dW, part, ctrl, (int)blockIdx.x);
 }
 
+// Normal GENO of one face-row entry o = a * n1 + b (indexing as normal_body)
+// on characteristic variables: the stencil's four cells, values and
+// h-scaled normal derivatives, in the normal frame (rho, rho un, rho ut,
+// rho E), projected on the left eigenvectors at the Roe average of the two
+// cells at the face (m = 1, 2), reconstructed field by field and mapped back
+// with the right ones. A face whose average has no real sound speed keeps
+// the conservative variables. Returns the sides on the low-order branch.
+template <int DIR, typename T>
+__device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KParams& k,
+                                                    const double* __restrict__ W,
+                                                    const T* __restrict__ dW,
+                                                    T* __restrict__ fr,
+                                                    double* __restrict__ chi, int o, int n1,
+                                                    int plane) {
+  const int a = o / n1, b = o - a * n1;
+  const double h = DIR == 0 ? g.dx : g.dy;
+  // state variable of each normal-frame slot
+  constexpr int VM[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
+  double Qv[4][4], Gv[4][4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      size_t id;
+      if (DIR == 0) id = at(g, VM[f], a - 1, b - 2 + m);
+      else id = at(g, VM[f], a - 2 + m, b - 1);
+      Qv[f][m] = W[id];
+      Gv[f][m] = h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+    }
+  const double Wa[4] = {Qv[0][1], Qv[1][1], Qv[2][1], Qv[3][1]};
+  const double Wb[4] = {Qv[0][2], Qv[1][2], Qv[2][2], Qv[3][2]};
+  geno::Eig2 e;
+  const bool ch = geno::roe_eigen2(Wa, Wb, k.gamma, e);
+  unsigned int nlow = 0;
+  double wv[2][4], wd[2][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double Q[4], G[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (ch) {
+        Q[m] = e.L[c][0] * Qv[0][m] + e.L[c][1] * Qv[1][m] + e.L[c][2] * Qv[2][m] +
+               e.L[c][3] * Qv[3][m];
+        G[m] = e.L[c][0] * Gv[0][m] + e.L[c][1] * Gv[1][m] + e.L[c][2] * Gv[2][m] +
+               e.L[c][3] * Gv[3][m];
+      } else {
+        Q[m] = Qv[c][m];
+        G[m] = Gv[c][m];
+      }
+    }
+    T vl, dl, vr, dr;
+    double xl, xr;
+    nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl,
+                                       xl, vr, dr, xr);
+    wv[0][c] = (double)vl;
+    wd[0][c] = (double)dl;
+    wv[1][c] = (double)vr;
+    wd[1][c] = (double)dr;
+    if (chi) {
+      // characteristic field c, or the state variable of slot c
+      const int cv = ch ? c : VM[c];
+      chi[(size_t)(0 * 4 + cv) * plane + o] = xl;
+      chi[(size_t)(1 * 4 + cv) * plane + o] = xr;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    double Sv[4], Dv[4];
+    if (ch) {
+      geno::from_characteristic2(e, wv[s], Sv);
+      geno::from_characteristic2(e, wd[s], Dv);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        Sv[f] = wv[s][f];
+        Dv[f] = wd[s][f];
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      fr[(size_t)((2 * s + 0) * 4 + VM[f]) * plane + o] = T(Sv[f]);
+      fr[(size_t)((2 * s + 1) * 4 + VM[f]) * plane + o] = T(Dv[f]);
+    }
+  }
+  return nlow;
+}
+
 // ---------------------------------------------------------------------------
 // Normal GENO on face-rows (2-D), one thread per (variable, face-row entry).
 // DIR 0: rows a = 0..ny+1 (j = a-1), faces b = 0..nx (between cells b-1 and
@@ -368,7 +455,10 @@ __global__ void __launch_bounds__(BLOCK) k_init(Geo g, double gamma, double* __r
 // ---------------------------------------------------------------------------
 // gate: the learned gate's flags of the interior cells for this direction
 // ([ny][nx], 1 = chi of the cell's sides is 1), or nullptr.
-template <int DIR, typename T>
+// CHAR: characteristic variables, one thread per face-row entry (all four
+// variables of its stencil are needed for the projection); chi then holds
+// the characteristic fields (un - c, un, shear, un + c).
+template <int DIR, typename T, bool CHAR = false>
 __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k,
                                             const double* __restrict__ W,
                                             const T* __restrict__ dW, T* __restrict__ fr,
@@ -383,7 +473,10 @@ __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k
   const int plane = n0 * n1;
   const int t = lb * (int)blockDim.x + (int)threadIdx.x;
   unsigned int nlow = 0, ngated = 0;
-  if (t < 4 * plane) {
+  const int nent = CHAR ? plane : 4 * plane;
+  if constexpr (CHAR) {
+    if (t < plane) nlow = normal_char<DIR, T>(g, k, W, dW, fr, chi, t, n1, plane);
+  } else if (t < nent) {
     const int v = t / plane, o = t - v * plane;
     const int a = o / n1, b = o - a * n1;
     const double h = DIR == 0 ? g.dx : g.dy;
@@ -420,14 +513,14 @@ __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k
   }
   if (cnt.p) {
     unsigned int wc[GENO_NCLASS] = {};
-    wc[GENO_W_UNITS] = t < 4 * plane ? 1u : 0u;
+    wc[GENO_W_UNITS] = t < nent ? (CHAR ? 4u : 1u) : 0u;
     wc[GENO_W_LOW] = nlow;
     wc[GENO_W_GATED] = ngated;
     block_count(cnt, DIR == 0 ? GENO_K_NORMAL_X : GENO_K_NORMAL_Y, wc);
   }
 }
 
-template <int DIR, typename T>
+template <int DIR, typename T, bool CHAR>
 __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                                                     const double* __restrict__ W,
                                                     const T* __restrict__ dW,
@@ -436,8 +529,8 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d(Geo g, geno::KParams k,
                                                     const double* __restrict__ part, int npart,
                                                     double* dt_out, int step, Cnt cnt,
                                                     const unsigned char* __restrict__ gate) {
-  normal_body<DIR, T>(g, k, W, dW, fr, chi, ctrl, part, npart, dt_out, step, cnt, xcd_block(),
-                      gate);
+  normal_body<DIR, T, CHAR>(g, k, W, dW, fr, chi, ctrl, part, npart, dt_out, step, cnt,
+                            xcd_block(), gate);
 }
 
 // The paper's comparison of the nonlinear weights at every face-side of a
@@ -705,7 +798,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
 // y). Twice the waves of one direction per launch, and one launch ramp
 // less per stage. (The face step stays one launch per direction: over both,
 // each XCD's L2 would hold twice the face-row rows it reuses.)
-template <typename T>
+template <typename T, bool CHAR>
 __global__ void __launch_bounds__(BLOCK) k_normal2d_xy(Geo g, geno::KParams k,
                                                        const double* __restrict__ W,
                                                        const T* __restrict__ dW,
@@ -718,9 +811,11 @@ __global__ void __launch_bounds__(BLOCK) k_normal2d_xy(Geo g, geno::KParams k,
                                                        int nbx) {
   const int b = xcd_block();
   if (b < nbx)
-    normal_body<0, T>(g, k, W, dW, frx, nullptr, ctrl, part, npart, dt_out, step, cnt, b, gx);
+    normal_body<0, T, CHAR>(g, k, W, dW, frx, nullptr, ctrl, part, npart, dt_out, step, cnt, b,
+                            gx);
   else
-    normal_body<1, T>(g, k, W, dW, fry, nullptr, ctrl, nullptr, 0, nullptr, 0, cnt, b - nbx, gy);
+    normal_body<1, T, CHAR>(g, k, W, dW, fry, nullptr, ctrl, nullptr, 0, nullptr, 0, cnt,
+                            b - nbx, gy);
 }
 
 
@@ -1362,7 +1457,7 @@ __global__ void __launch_bounds__(BS) kb_init(const BEntry* __restrict__ tab,
   init_body<2, T>(e.geo, gamma, e.W, (T*)e.dW, e.part, e.ctrl, gb - st[gi]);
 }
 
-template <int DIR, typename T, int BS>
+template <int DIR, typename T, int BS, bool CHAR>
 __global__ void __launch_bounds__(BS) kb_normal(const BEntry* __restrict__ tab,
                                                 const int* __restrict__ offs, int ngrids,
                                                 geno::KParams k, int stage, Cnt cnt) {
@@ -1373,8 +1468,8 @@ __global__ void __launch_bounds__(BS) kb_normal(const BEntry* __restrict__ tab,
   const double* W = stage == 1 ? e.W : e.wst;
   const T* dW = (const T*)(stage == 1 ? e.dW : e.dwst);
   const double* part = (DIR == 0 && stage == 1) ? e.part : nullptr;
-  normal_body<DIR, T>(e.geo, k, W, dW, (T*)e.fr[DIR], nullptr, e.ctrl, part, e.npart, nullptr, 0,
-                      cnt, gb - st[gi]);
+  normal_body<DIR, T, CHAR>(e.geo, k, W, dW, (T*)e.fr[DIR], nullptr, e.ctrl, part, e.npart,
+                            nullptr, 0, cnt, gb - st[gi]);
 }
 
 template <int DIR, typename T, int BS>
@@ -1503,6 +1598,8 @@ int check_params(const geno_params* p) {
   if ((p->bc[0] == GENO_BC_PERIODIC) != (p->bc[1] == GENO_BC_PERIODIC) ||
       (p->bc[2] == GENO_BC_PERIODIC) != (p->bc[3] == GENO_BC_PERIODIC))
     return fail(GENO_EINVAL, "periodic boundaries must be set on both sides of an axis");
+  if (p->variables != GENO_VARS_CONSERVATIVE && p->variables != GENO_VARS_CHARACTERISTIC)
+    return fail(GENO_EINVAL, "bad variables code %d", p->variables);
   return GENO_OK;
 }
 
@@ -1514,10 +1611,9 @@ int check_grid(const geno_grid* g) {
   for (int i = 0; i < 4; ++i)
     if (g->ndim == 2 && g->params.bc[i] == GENO_BC_FIXED)
       return fail(GENO_EINVAL, "fixed-state ends are available in 1-D only");
-  if (g->params.variables != GENO_VARS_CONSERVATIVE &&
-      !(g->params.variables == GENO_VARS_CHARACTERISTIC && g->ndim == 1))
-    return fail(GENO_EINVAL, "characteristic variables are available in 1-D only (code %d)",
-                g->params.variables);
+  if (g->params.variables == GENO_VARS_CHARACTERISTIC && g->ndim == 2 &&
+      g->params.gate_delta > 0.0)
+    return fail(GENO_EINVAL, "the learned gate works on conservative variables only");
   if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1))
     return fail(GENO_EINVAL, "bad grid size");
   if (g->pitch < g->nx + 2 * NG || g->rows != (g->ndim == 2 ? g->ny + 2 * NG : 1))
@@ -1554,7 +1650,7 @@ geno::KParams kparams(const geno_grid* g) {
   k.eps_ulps = p.eps_ulps;
   k.gate = (p.gate_delta > 0.0 && g->ndim == 2) ? 1 : 0;
   k.gate_thr = 1.0 - p.gate_delta;
-  k.charvars = (g->ndim == 1 && p.variables == GENO_VARS_CHARACTERISTIC) ? 1 : 0;
+  k.charvars = p.variables == GENO_VARS_CHARACTERISTIC ? 1 : 0;
   return k;
 }
 
@@ -1628,6 +1724,14 @@ int launch_init(const geno_grid* g, const Geo& geo, double gamma, double* W, T* 
 size_t face_rows(const geno_grid* g, int dir) {
   return dir == 0 ? (size_t)(g->ny + 2) * (g->nx + 1) : (size_t)(g->ny + 1) * (g->nx + 2);
 }
+// threads of the normal step: one per (variable, face-row entry), or one
+// per entry with characteristic variables
+bool char2d(const geno_grid* g) {
+  return g->ndim == 2 && g->params.variables == GENO_VARS_CHARACTERISTIC;
+}
+size_t normal_threads(const geno_grid* g, int dir) {
+  return (char2d(g) ? 1 : 4) * face_rows(g, dir);
+}
 size_t faces_of(const geno_grid* g, int dir) {
   return dir == 0 ? (size_t)g->ny * (g->nx + 1) : (size_t)(g->ny + 1) * g->nx;
 }
@@ -1677,9 +1781,13 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
       gx = B.gate;
       gy = B.gate + nc;
     }
-    const unsigned nnx = nblocks(4 * face_rows(g, 0)), nny = nblocks(4 * face_rows(g, 1));
-    HIP_TRY(launch(GENO_K_NORMAL_XY, k_normal2d_xy<T>, nnx + nny, s, geo, k, Win, dWin, B.fr[0],
-                   B.fr[1], B.ctrl, part, npart, dt_out, step, cnt, gx, gy, (int)nnx));
+    const unsigned nnx = nblocks(normal_threads(g, 0)), nny = nblocks(normal_threads(g, 1));
+    if (k.charvars)
+      HIP_TRY(launch(GENO_K_NORMAL_XY, k_normal2d_xy<T, true>, nnx + nny, s, geo, k, Win, dWin,
+                     B.fr[0], B.fr[1], B.ctrl, part, npart, dt_out, step, cnt, gx, gy, (int)nnx));
+    else
+      HIP_TRY(launch(GENO_K_NORMAL_XY, k_normal2d_xy<T, false>, nnx + nny, s, geo, k, Win, dWin,
+                     B.fr[0], B.fr[1], B.ctrl, part, npart, dt_out, step, cnt, gx, gy, (int)nnx));
     HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
                    B.fr[0], B.fl[0], B.ctrl, want_F, cnt, B.queue[0]));
     HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
@@ -1727,16 +1835,18 @@ int reconstruct_t(const geno_grid* g, double* W, T* dW, int dir, T* face_state, 
     HIP_TRY(launch(-1, k_faces1d<0, T>, nblocks((size_t)g->nx + 1), s, geo, k, (const double*)W,
                    (const T*)dW, face_state, chi, (Ctrl*)nullptr, 0, none));
   } else if (dir == 0) {
-    HIP_TRY(launch(-1, k_normal2d<0, T>, nblocks(4 * face_rows(g, 0)), s, geo, k, (const double*)W,
-                   (const T*)dW, B.fr[0], chi, (Ctrl*)nullptr, (const double*)nullptr, 0,
-                   (double*)nullptr, 0, none, (const unsigned char*)nullptr));
+    HIP_TRY(launch(-1, k.charvars ? k_normal2d<0, T, true> : k_normal2d<0, T, false>,
+                   nblocks(normal_threads(g, 0)), s, geo, k, (const double*)W, (const T*)dW,
+                   B.fr[0], chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
+                   none, (const unsigned char*)nullptr));
     HIP_TRY(launch(-1, k_faces2d<0, 0, T>, nblocks(2 * faces_of(g, 0)), s, geo, k,
                    (const double*)W, (const T*)B.fr[0], face_state, (Ctrl*)nullptr, 0, none,
                    (unsigned int*)nullptr));
   } else {
-    HIP_TRY(launch(-1, k_normal2d<1, T>, nblocks(4 * face_rows(g, 1)), s, geo, k, (const double*)W,
-                   (const T*)dW, B.fr[1], chi, (Ctrl*)nullptr, (const double*)nullptr, 0,
-                   (double*)nullptr, 0, none, (const unsigned char*)nullptr));
+    HIP_TRY(launch(-1, k.charvars ? k_normal2d<1, T, true> : k_normal2d<1, T, false>,
+                   nblocks(normal_threads(g, 1)), s, geo, k, (const double*)W, (const T*)dW,
+                   B.fr[1], chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
+                   none, (const unsigned char*)nullptr));
     HIP_TRY(launch(-1, k_faces2d<1, 0, T>, nblocks(2 * faces_of(g, 1)), s, geo, k,
                    (const double*)W, (const T*)B.fr[1], face_state, (Ctrl*)nullptr, 0, none,
                    (unsigned int*)nullptr));
@@ -1821,7 +1931,7 @@ bool same_method(const geno_params& a, const geno_params& b) {
          a.C == b.C && a.eps == b.eps && a.r == b.r && a.rL == b.rL && a.d[0] == b.d[0] &&
          a.d[1] == b.d[1] && a.d[2] == b.d[2] && a.tau_c1 == b.tau_c1 &&
          a.tau_c2 == b.tau_c2 && a.cfl == b.cfl && a.dt_fixed == b.dt_fixed &&
-         a.eps_ulps == b.eps_ulps;
+         a.eps_ulps == b.eps_ulps && a.variables == b.variables;
 }
 
 // devices on which a network has been loaded (geno_mlp_load)
@@ -1884,9 +1994,9 @@ int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPl
     const size_t f = faces_of(g, 0) + faces_of(g, 1);
     const long long nbk[BK_N] = {
         nblocks_bs(ncell, t.block_update),
-        nblocks_bs(4 * face_rows(g, 0), t.block_normal),
+        nblocks_bs(normal_threads(g, 0), t.block_normal),
         nblocks_bs(2 * faces_of(g, 0), t.block_faces),
-        nblocks_bs(4 * face_rows(g, 1), t.block_normal),
+        nblocks_bs(normal_threads(g, 1), t.block_normal),
         nblocks_bs(2 * faces_of(g, 1), t.block_faces),
         std::min<long long>(1024, std::max<long long>(1, (long long)((f + t.slow_faces_per_block - 1) /
                                                                   t.slow_faces_per_block))),
@@ -1941,11 +2051,11 @@ void bind_batch(BatchPlan* P, char* ws, void* const* W, void* const* dW, const g
     default: return launch_bs(KIND, KERN<256>, NB, 256, s, __VA_ARGS__);                 \
   }
 
-template <typename T>
+template <typename T, bool CHAR = false>
 struct BatchK {
   template <int BS> static constexpr auto init = kb_init<T, BS>;
-  template <int BS> static constexpr auto nx = kb_normal<0, T, BS>;
-  template <int BS> static constexpr auto ny = kb_normal<1, T, BS>;
+  template <int BS> static constexpr auto nx = kb_normal<0, T, BS, CHAR>;
+  template <int BS> static constexpr auto ny = kb_normal<1, T, BS, CHAR>;
   template <int BS> static constexpr auto fx = kb_faces<0, T, BS>;
   template <int BS> static constexpr auto fy = kb_faces<1, T, BS>;
   template <int BS> static constexpr auto slow = kb_slow<T, BS>;
@@ -1964,14 +2074,21 @@ template <typename T>
 hipError_t go_phase(int phase, const BatchPlan& P, const BEntry* tab, const int* offs,
                     const geno::KParams& k, int stage, const Cnt& cnt, hipStream_t s) {
   const int ng = P.ngrids;
+  using BC = BatchK<T, true>;   // normal step on characteristic variables
   switch (phase) {
     case BK_NORMAL_X:
+      if (k.charvars)
+        GO_BS(P.bs[phase], GENO_K_NORMAL_X, BC::template nx, P.nb[phase], tab,
+              offs, ng, k, stage, cnt)
       GO_BS(P.bs[phase], GENO_K_NORMAL_X, BatchK<T>::template nx, P.nb[phase], tab, offs, ng, k,
             stage, cnt)
     case BK_FACES_X:
       GO_BS(P.bs[phase], GENO_K_FACES_X, BatchK<T>::template fx, P.nb[phase], tab, offs, ng, k,
             stage, cnt)
     case BK_NORMAL_Y:
+      if (k.charvars)
+        GO_BS(P.bs[phase], GENO_K_NORMAL_Y, BC::template ny, P.nb[phase], tab,
+              offs, ng, k, stage, cnt)
       GO_BS(P.bs[phase], GENO_K_NORMAL_Y, BatchK<T>::template ny, P.nb[phase], tab, offs, ng, k,
             stage, cnt)
     case BK_FACES_Y:

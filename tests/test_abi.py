@@ -70,6 +70,12 @@ def test_host_side_validation(so):
     G.Grid(1, 16, params=G.default_params(bc=(3, 3, 0, 0)))
     with pytest.raises(G.GenoError):
         G.Grid(2, 8, 8, params=G.default_params(bc=(3, 3, 1, 1)))
+    # characteristic variables in both dimensions, not with the learned gate
+    G.Grid(2, 8, 8, params=G.default_params(variables=G.VARS_CHARACTERISTIC))
+    with pytest.raises(G.GenoError):
+        G.Grid(2, 8, 8, params=G.default_params(variables=G.VARS_CHARACTERISTIC, gate_delta=0.1))
+    with pytest.raises(G.GenoError):
+        G.Grid(1, 16, params=G.default_params(variables=7))
     # null pointers are rejected before any launch
     assert G.lib().gks_step(ctypes.byref(g.g), None, None, None, 1, None, None, None) == G.GENO_EINVAL
     assert G.lib().geno_reconstruct(ctypes.byref(g.g), None, None, 0, None, None, None, None) == G.GENO_EINVAL

@@ -37,14 +37,14 @@ def _say(*a):
 SHAPES = [(32, 32, 1, 0), (48, 40, 1, 1), (64, 24, 0, 2), (20, 56, 1, 3), (72, 72, 1, 4)]
 
 
-def _make(G, prec):
+def _make(G, prec, variables=0):
     grids, data = [], []
     for nx, ny, bc, seed in SHAPES:
         W, dW, _ = inputs.quadrants_2d(nx, ny, seed)
         Ws, dWs = inputs.random_smooth_2d(nx, ny, seed + 5)
         W = W + 0.05 * (Ws - Ws.mean(axis=(1, 2), keepdims=True))
         dW = dW + 0.05 * dWs
-        grids.append(G.Grid(2, nx, ny, bc=bc, precision=prec))
+        grids.append(G.Grid(2, nx, ny, bc=bc, precision=prec, variables=variables))
         data.append((W, dW))
     return grids, data
 
@@ -71,10 +71,11 @@ def _same(grids, Ws, dWs, ref):
     return True
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_batched_equals_single_grid(G, mixed):
+@pytest.mark.parametrize("mixed,char", [(False, False), (True, False), (False, True), (True, True)],
+                         ids=["fp64", "mixed", "fp64-char", "mixed-char"])
+def test_batched_equals_single_grid(G, mixed, char):
     prec = G.MIXED if mixed else G.F64
-    grids, data = _make(G, prec)
+    grids, data = _make(G, prec, G.VARS_CHARACTERISTIC if char else G.VARS_CONSERVATIVE)
     ref = _single(G, grids, data, 4)
     B = G.Batch(grids)
     ws = B.workspace()

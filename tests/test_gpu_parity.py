@@ -124,16 +124,17 @@ def _case_2d(kind, nx, ny, seed):
 
 @pytest.mark.parametrize("direction", [0, 1])
 @pytest.mark.parametrize("kind,bc", [("quadrants", 1), ("smooth", 0), ("vortex", 1)])
-def test_reconstruct_2d(G, oracle, direction, kind, bc):
-    _say("reconstruct_2d", kind, bc, direction)
+@pytest.mark.parametrize("char", [False, True], ids=["cons", "char"])
+def test_reconstruct_2d(G, oracle, direction, kind, bc, char):
+    _say("reconstruct_2d", kind, bc, direction, "char" if char else "cons")
     W, dW = _case_2d(kind, 40, 36, 3)
-    grid = _grid(G, W, bc)
+    grid = _grid(G, W, bc, variables=int(char))
     Wd, dWd = grid.to_device(W), grid.to_device(dW)
     fs = torch.empty(grid.face_state_shape(direction), dtype=torch.float64, device="cuda")
     chi = torch.empty(grid.chi_shape(direction), dtype=torch.float64, device="cuda")
     G.geno_reconstruct(grid, Wd, dWd, direction, fs, chi, grid.workspace())
     torch.cuda.synchronize()
-    prm = _oprm(oracle, 2, bc)
+    prm = _oprm(oracle, 2, bc, characteristic=char)
     ref, _ = oracle.face_states(prm, W, dW, direction)
     _, ref_chi = oracle.normal_faces(prm, W, dW, direction)
     got = fs.cpu().numpy()
@@ -552,6 +553,53 @@ def test_characteristic_1d_shadowed(G, oracle, problem):
         assert st.guard == og and st.nonfinite == 0
         assert float(dts.item()) == pytest.approx(float(odt[0]), rel=1e-13)
     assert max(worst) < TOL, worst
+
+
+@pytest.mark.parametrize("kind,bc,nx,ny,steps", [("quadrants", 1, 48, 40, 12), ("quadrants", 2, 36, 44, 8),
+                                                 ("quadrants", 0, 32, 36, 8), ("vortex", 1, 64, 64, 6)])
+def test_characteristic_2d_shadowed(G, oracle, kind, bc, nx, ny, steps):
+    # characteristic variables in 2-D (normal step on the Roe-averaged
+    # eigenvectors of each face's normal direction): every GPU step against
+    # the oracle's step from the same state
+    _say("characteristic 2-D shadow", kind, bc, nx, ny, steps)
+    W, dW = _case_2d(kind, nx, ny, 7)
+    grid = _grid(G, W, bc, variables=G.VARS_CHARACTERISTIC)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prm = _oprm(oracle, 2, bc, characteristic=True)
+    worst = [0.0, 0.0]
+    for n in range(steps):
+        W0, dW0 = grid.interior(Wd), grid.interior(dWd)
+        st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        assert st.nonfinite == 0
+        oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, dy=grid.dy)
+        gW, gdW = grid.interior(Wd), grid.interior(dWd)
+        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        assert st.guard == og, (n, st.guard, og)
+        assert float(dts.item()) == pytest.approx(float(odt[0]), rel=1e-13)
+    _say("worst W %.3e dW %.3e" % tuple(worst))
+    assert max(worst) < TOL, worst
+
+
+def test_characteristic_2d_y_invariant_equals_1d(G):
+    # y-invariant data with V = 0: every row of the 2-D characteristic run
+    # is the 1-D characteristic run (K of the BGK model is set so that both
+    # have gamma = 1.4)
+    n, ny = 96, 4
+    W1, dW1, _ = inputs.jump_1d(n, 3)
+    g1 = G.Grid(1, n, 1, bc=1, variables=G.VARS_CHARACTERISTIC)
+    a, da, _, _ = _run_gpu(G, g1, W1, dW1, 6)
+    W2 = np.zeros((4, ny, n))
+    dW2 = np.zeros((8, ny, n))
+    for v2, v1 in ((0, 0), (1, 1), (3, 2)):
+        W2[v2] = W1[v1, 0]
+        dW2[v2] = dW1[v1, 0]
+    g2 = G.Grid(2, n, ny, x1=1.0, y1=ny / n, bc=1, variables=G.VARS_CHARACTERISTIC)
+    b, db, _, _ = _run_gpu(G, g2, W2, dW2, 6)
+    for r in range(ny):
+        assert rel_err(b[[0, 1, 3], r], a[:, 0]) < TOL
+        assert np.abs(b[2, r]).max() < 1e-13
 
 
 def test_characteristic_blast_wave_full_run_at_cfl_half(G):
