@@ -402,3 +402,154 @@ def titarev_toro_1d(nx: int = 800, gamma: float = GAMMA):
     ghost[1, :, :3] = np.asarray(_cons_1d(rg, np.zeros(2), np.ones(2), gamma)).T
     ghost[1, :, 3] = dg
     return W[:, None, :], dW[:, None, :], ghost
+
+
+# ---------------------------------------------------------------------------
+# Triangular meshes (the unstructured reconstruction of Sec. 4.3)
+# ---------------------------------------------------------------------------
+def tri_mesh(nx: int, ny: int, seed: int, jitter: float = 0.2):
+    """Periodic triangulation of the unit square: an nx x ny lattice whose
+    vertices are moved by up to jitter/2 of the spacing (seeded), each
+    quadrilateral split into two counter-clockwise triangles, 2 nx ny cells.
+
+    Returns a dict with
+      xv    [ncell, 3, 2]  vertex coordinates, each triangle unwrapped about
+                           its own lattice square;
+      nbr   [ncell, 3]     the cell across edge e (from vertex e to e+1);
+      shift [ncell, 3, 2]  translation that places that neighbour, as stored,
+                           next to the cell (a period across the boundary).
+    Cell 2 (j nx + i) is the lower triangle of square (i, j), cell + 1 the
+    upper one."""
+    if nx < 2 or ny < 2:
+        raise ValueError("the periodic mesh needs at least 2 x 2 squares")
+    rng = np.random.default_rng(seed)
+    hx, hy = 1.0 / nx, 1.0 / ny
+    jit = rng.uniform(-0.5, 0.5, size=(ny, nx, 2)) * jitter * np.array([hx, hy])
+    base = np.stack(np.meshgrid(np.arange(nx) * hx, np.arange(ny) * hy), axis=-1) + jit
+
+    def vert(i, j):
+        return base[j % ny, i % nx] + np.array([(i // nx) * 1.0, (j // ny) * 1.0])
+
+    n = 2 * nx * ny
+    xv = np.zeros((n, 3, 2))
+    nbr = np.zeros((n, 3), dtype=np.int64)
+    shift = np.zeros((n, 3, 2))
+
+    def lower(i, j):
+        return 2 * ((j % ny) * nx + (i % nx))
+
+    def wrap(i, j):
+        # translation of the canonical square of (i, j) to position (i, j)
+        return np.array([(i // nx) * 1.0, (j // ny) * 1.0])
+
+    for j in range(ny):
+        for i in range(nx):
+            c = lower(i, j)
+            v00, v10, v11, v01 = vert(i, j), vert(i + 1, j), vert(i + 1, j + 1), vert(i, j + 1)
+            xv[c] = (v00, v10, v11)
+            xv[c + 1] = (v00, v11, v01)
+            # lower: bottom edge, right edge, diagonal
+            nbr[c] = (lower(i, j - 1) + 1, lower(i + 1, j) + 1, c + 1)
+            shift[c] = (wrap(i, j - 1), wrap(i + 1, j), (0.0, 0.0))
+            # upper: diagonal, top edge, left edge
+            nbr[c + 1] = (c, lower(i, j + 1), lower(i - 1, j))
+            shift[c + 1] = ((0.0, 0.0), wrap(i, j + 1), wrap(i - 1, j))
+    return {"xv": xv, "nbr": nbr, "shift": shift, "nx": nx, "ny": ny}
+
+
+# Gauss-Legendre nodes and weights on [0, 1] (8 points) for the collapsed
+# (Duffy) rule that builds exact-enough averages of the initial data
+_GL8 = np.polynomial.legendre.leggauss(8)
+_GL8_X, _GL8_W = 0.5 * (_GL8[0] + 1.0), 0.5 * _GL8[1]
+
+
+def _tri_points(xv):
+    """Points and weights (summing to 1) of the collapsed 8 x 8 Gauss rule on
+    each triangle of xv [n, 3, 2] (exact for polynomials of degree <= 14)."""
+    s, t = np.meshgrid(_GL8_X, _GL8_X, indexing="ij")
+    ws = np.outer(_GL8_W, _GL8_W) * 2.0 * (1.0 - s)   # Jacobian of (s, t) -> (b1, b2)
+    b1 = s.ravel()
+    b2 = ((1.0 - s) * t).ravel()
+    w = ws.ravel()
+    b0 = 1.0 - b1 - b2
+    pts = (b0[None, :, None] * xv[:, None, 0] + b1[None, :, None] * xv[:, None, 1]
+           + b2[None, :, None] * xv[:, None, 2])
+    return pts, w
+
+
+def tri_cell_data(mesh, f, grad):
+    """Cell averages of f(x, y) and of its gradient grad(x, y) -> (gx, gy)
+    over every triangle; f may return several fields stacked on axis 0.
+    Returns W [nf, ncell] and dW [2, nf, ncell] (x then y derivatives)."""
+    pts, w = _tri_points(mesh["xv"])
+    x, y = pts[..., 0], pts[..., 1]
+    fv = np.asarray(f(x, y))
+    single = fv.ndim == 2
+    fv = fv[None] if single else fv
+    gx, gy = grad(x, y)
+    gx, gy = np.asarray(gx), np.asarray(gy)
+    if single:
+        gx, gy = gx[None], gy[None]
+    W = (fv * w).sum(axis=-1)
+    dW = np.stack([(gx * w).sum(axis=-1), (gy * w).sum(axis=-1)])
+    return W, dW
+
+
+def tri_euler_smooth(mesh, seed: int, gamma: float = GAMMA):
+    """Smooth periodic Euler state (a few seeded Fourier modes per primitive)
+    as conservative cell averages and averaged gradients on a triangle mesh."""
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, size=(4, 2, 2, 2))
+    base = np.array([1.0, 0.3, -0.2, 1.0])
+
+    def prim(x, y):
+        out, dx, dy = [], [], []
+        for fidx in range(4):
+            s = base[fidx] + 0.0 * x
+            sx = 0.0 * x
+            sy = 0.0 * x
+            for a in range(2):
+                for b in range(2):
+                    kx, ky = 2 * math.pi * (a + 1), 2 * math.pi * b
+                    ph = kx * x + ky * y
+                    c0, c1 = 0.1 * coef[fidx, a, b, 0] / (1 + a + b), 0.1 * coef[fidx, a, b, 1] / (1 + a + b)
+                    s = s + c0 * np.sin(ph) + c1 * np.cos(ph)
+                    d = c0 * np.cos(ph) - c1 * np.sin(ph)
+                    sx = sx + kx * d
+                    sy = sy + ky * d
+            out.append(s)
+            dx.append(sx)
+            dy.append(sy)
+        return out, dx, dy
+
+    def cons(x, y):
+        (rho, u, v, p), _, _ = prim(x, y)
+        return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+    def cons_grad(x, y):
+        (rho, u, v, p), dx, dy = prim(x, y)
+        out = []
+        for d in (dx, dy):
+            dr, du, dv, dp = d
+            out.append(np.stack([dr, dr * u + rho * du, dr * v + rho * dv,
+                                 dp / (gamma - 1.0) + 0.5 * dr * (u * u + v * v) + rho * (u * du + v * dv)]))
+        return out[0], out[1]
+
+    return tri_cell_data(mesh, cons, cons_grad)
+
+
+def tri_euler_jumps(mesh, seed: int, gamma: float = GAMMA):
+    """Piecewise-constant Euler state on a triangle mesh: the four quadrant
+    states of the structured Riemann data, drawn the same way, on the cells
+    whose centroid lies in each quadrant (jumps along cell edges, zero
+    gradients), plus a small smooth part so that no stencil is flat."""
+    rng = np.random.default_rng(seed)
+    states = quadrant_states(rng)
+    cen = mesh["xv"].mean(axis=1)
+    right, top = cen[:, 0] > 0.5, cen[:, 1] > 0.5
+    q = np.where(right & top, 0, np.where(top, 1, np.where(right, 3, 2)))
+    prim = np.asarray(states)[q].T   # rho, u, v, p per cell
+    W = _cons_2d(prim[0], prim[1], prim[2], prim[3], gamma)
+    Ws, dWs = tri_euler_smooth(mesh, seed + 1, gamma)
+    W = W + 0.02 * (Ws - Ws.mean(axis=1, keepdims=True))
+    return W, 0.02 * dWs
