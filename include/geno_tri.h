@@ -1,0 +1,83 @@
+/*
+ * geno_tri.h - C ABI of the fourth-order compact GENO reconstruction on 2-D
+ * triangular meshes (Zhao & Xu, "A generalized ENO reconstruction in compact
+ * GKS for compressible flow simulations", Sec. 4.3, with the GENO blend,
+ * Eq. (3)-(4), the ultimate smoothness indicator, Eq. (5), the indicators of
+ * Eq. IS-highorder-1 and IS-tau, and the ENO weights of Eq. (8) from Sec. 3),
+ * for gfx950.
+ *
+ * Method, per cell Omega_j (target) and per variable, data being the cell
+ * averages and averaged gradients of the compact scheme:
+ *   q^H = p^3: the cubic whose average on Omega_j is exact and which fits in
+ *     least squares the averages of the nine other cells of S_0 (the three
+ *     edge neighbours Omega_{j_k} and their six other neighbours) and the
+ *     h-scaled averaged gradients of Omega_j and of the three edge
+ *     neighbours (the compact stencil of Sec. 4.3; the paper defers the
+ *     least-squares details to its references);
+ *   p_k, k = 1..3: the linear polynomial on S_k = {Omega_j, Omega_{j_k}}
+ *     whose average on Omega_j is exact and which fits in least squares the
+ *     average and h-scaled gradient of Omega_{j_k};
+ *   IS^H = sum over multi-indices 1 <= |l| <= 3 of h^{2|l|-2} int (D^l q^H)^2,
+ *   IS~^H the same over |l| <= 2, IS^tau = |IS^H - IS~^H| (Eq. IS-tau);
+ *   IS_k = int |grad p_k|^2; IS^L = (sum IS_k - min - max)/(k_0 - 2), k_0 = 3;
+ *   alpha^{H,L} = 1 + (IS^tau/(IS^{H,L} + eps))^r with r = 3,
+ *   alpha = 2 alpha^H/(alpha^H + alpha^L), chi = tanh(C alpha)/tanh(C);
+ *   w_k ~ d_k/(IS_k + eps)^2 with d_k = 1;
+ *   R = chi p^3 + (1 - chi) sum_k w_k p_k.
+ * h = sqrt(|Omega_j|). Component-wise on the given variables.
+ *
+ * Mesh (host arrays, periodic or not - translations carry the periods):
+ *   xv    [ncell][3][2] vertex coordinates of each triangle, counter-clockwise;
+ *   nbr   [ncell][3]    the cell across edge e (vertex e to vertex e+1);
+ *   shift [ncell][3][2] translation that places nbr[c][e], as given by its
+ *                       own xv, next to cell c (zero inside the domain).
+ * Every cell must have three neighbours (closed or periodic mesh).
+ *
+ * Conventions as geno_gks.h (error codes GENO_*, geno_last_error).
+ */
+#ifndef GENO_TRI_H
+#define GENO_TRI_H
+
+#include <stddef.h>
+
+#include "geno_gks.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Doubles per cell of the operator table (least-squares operators of the
+ * candidates, indicator matrix, scaled geometry, stencil indices). */
+size_t geno_tri_table_doubles(void);
+
+/* Mesh layer, host only (no device access; call once per mesh): fills the
+ * operator table ops (HOST array of ncell * geno_tri_table_doubles()
+ * doubles, cell-fastest layout, owned by the caller) from the mesh arrays
+ * above. The caller copies it to device memory for geno_tri_reconstruct.
+ * GENO_EINVAL for ncell < 1, null pointers, a neighbour index out of range,
+ * a degenerate (non counter-clockwise) triangle or a rank-deficient
+ * least-squares system. */
+int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* shift, double* ops);
+
+/* GENO reconstruction of every cell at the two Gauss points of each of its
+ * edges (points t = 1/2 -+ 1/(2 sqrt 3) along edge e from vertex e to e+1).
+ * ops: DEVICE copy of the table from geno_tri_build.
+ * W (device): cell averages [nv][ncell]; dW (device): averaged gradients
+ *   [2][nv][ncell] (d/dx rows, then d/dy rows). nv in 1..GENO_TRI_MAXV.
+ * out (device): [point(6) = 2 e + g][quant(3)][nv][ncell], quant 0 the value,
+ *   1 and 2 h d/dx and h d/dy of R (h of the cell).
+ * chi (device, may be NULL): [nv][ncell] path function of each cell.
+ * Asynchronous on stream; allocates nothing. */
+#define GENO_TRI_MAXV 4
+int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, const double* dW,
+                         double* out, double* chi, void* stream);
+
+/* Floating-point operations per cell and variable of geno_tri_reconstruct
+ * (as the kernel executes them; add, sub, mul, div, sqrt, tanh count 1). */
+double geno_tri_op_cost(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENO_TRI_H */

@@ -180,11 +180,14 @@ def edge_points(tri):
     return out
 
 
-def reconstruct(mesh, W, dW, prm=None):
-    """GENO states of every cell at the Gauss points of its edges.
-    W [nv, ncell] cell averages, dW [2, nv, ncell] averaged gradients.
-    Returns out [ncell, 3 edges, 2 points, nv, 3 (value, h d/dx, h d/dy)],
-    chi [ncell, nv] and the indicators {ISH, IStau, ISL} [ncell, nv]."""
+def reconstruct(mesh, W, dW, prm=None, cells=None, chi_given=None):
+    """GENO states of every cell (or of the listed cells) at the Gauss points
+    of its edges. W [nv, ncell] cell averages, dW [2, nv, ncell] averaged
+    gradients. Returns out [ncell, 3 edges, 2 points, nv, 3 (value, h d/dx,
+    h d/dy)], chi [ncell, nv] and the indicators {ISH, IStau, ISL} [ncell, nv]
+    (rows of cells not listed stay zero). chi_given [ncell, nv], if set,
+    replaces the path function in the blend (to compare the blended states
+    of another implementation whose chi differs by rounding)."""
     prm = params() if prm is None else prm
     W = np.asarray(W, dtype=np.float64)
     dW = np.asarray(dW, dtype=np.float64)
@@ -192,12 +195,14 @@ def reconstruct(mesh, W, dW, prm=None):
     out = np.zeros((n, 3, 2, nv, 3))
     chi = np.zeros((n, nv))
     info = {"ISH": np.zeros((n, nv)), "IStau": np.zeros((n, nv)), "ISL": np.zeros((n, nv))}
-    for c in range(n):
+    for c in (range(n) if cells is None else cells):
         fit = cell_fit(mesh, W, dW, c)
         ISH, _, IStau, ISk = indicators(fit)
         k0 = ISk.shape[0]
         ISL = (ISk.sum(axis=0) - ISk.min(axis=0) - ISk.max(axis=0)) / (k0 - 2)
         x, _ = path(prm, IStau, ISH, ISL)
+        if chi_given is not None:
+            x = np.asarray(chi_given[c], dtype=np.float64)
         wt = prm["d"][:, None] / (ISk + prm["eps"]) ** prm["rL"]
         wt = wt / wt.sum(axis=0)
         chi[c] = x

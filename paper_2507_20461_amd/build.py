@@ -9,10 +9,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "geno_gks.hip")
 SRCS = [SRC, os.path.join(PKG, "csrc", "opcount.hip"), os.path.join(PKG, "csrc", "mlp.hip"),
-        os.path.join(PKG, "csrc", "geno6.hip")]
+        os.path.join(PKG, "csrc", "geno6.hip"), os.path.join(PKG, "csrc", "geno_tri.hip")]
 HEADERS = [os.path.join(PKG, "csrc", h) for h in ("geno_device.hpp", "gks_device.hpp", "mlp_device.hpp",
                                                   "geno6_device.hpp")] + [
-    os.path.join(ROOT, "include", h) for h in ("geno_gks.h", "geno6.h")]
+    os.path.join(ROOT, "include", h) for h in ("geno_gks.h", "geno6.h", "geno_tri.h")]
 LIB = os.path.join(PKG, "libgeno_gks.so")
 ARCH = "gfx950"
 

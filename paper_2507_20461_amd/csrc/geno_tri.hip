@@ -1,0 +1,435 @@
+// Fourth-order compact GENO reconstruction on triangular meshes (Sec. 4.3
+// with Sec. 3): the mesh layer that turns the geometry into per-cell
+// operator tables (host, once per mesh), and the reconstruction kernel.
+//
+// Everything about the polynomials is expressed in the scaled coordinates
+// xi = (x - x_j)/h, eta = (y - y_j)/h of the target cell (h^2 = |Omega_j|),
+// with the cubic candidate written as
+//   p^3 = Q_j + sum_alpha a_alpha (phi_alpha - m_alpha),
+// phi_alpha the nine monomials xi^a eta^b of degree 1..3 in the order
+// (1,0) (0,1) (2,0) (1,1) (0,2) (3,0) (2,1) (1,2) (0,3), m_alpha their
+// averages on Omega_j (so the cell average is exact). In these coordinates
+// h^{2|l|-2} int (D^l p)^2 dx = mean over Omega_j of (d^l p / d xi^l)^2, so
+//   IS~^H = a^T G a,  G_ab = mean of sum_{|l| = 1, 2} d^l phi_a d^l phi_b,
+//   IS^tau = 36 a_30^2 + 4 a_21^2 + 4 a_12^2 + 36 a_03^2 (third derivatives
+//            of a cubic are constants),  IS^H = IS~^H + IS^tau,
+// and for p_k = Q_j + b_k . (xi, eta): IS_k = |b_k|^2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "geno_tri.h"
+
+namespace geno_err {
+int fail(int code, const char* fmt, ...);
+}
+
+namespace {
+
+using geno_err::fail;
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(GENO_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int NA = 9;        // coefficients of the cubic candidate
+constexpr int ND = 17;       // entries of its data vector
+// table offsets (doubles per cell, cell-fastest: entry q of cell c at q * n + c)
+constexpr int T_IDX = 0;                  // 9 stencil cells (3 edge neighbours, 6 second level)
+constexpr int T_M = T_IDX + 9;            // least-squares operator [NA][ND]
+constexpr int T_L = T_M + NA * ND;        // linear candidates [3][2][3]
+constexpr int T_G = T_L + 18;             // indicator matrix, upper triangle (off-diagonal doubled)
+constexpr int T_V = T_G + NA * (NA + 1) / 2;   // scaled vertices (xi, eta) x 3
+constexpr int T_MEAN = T_V + 6;           // m_alpha
+constexpr int T_H = T_MEAN + NA;          // h
+constexpr int T_N = T_H + 1;
+
+constexpr int EX[NA][2] = {{1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}, {3, 0}, {2, 1}, {1, 2}, {0, 3}};
+
+// d^(da+db) / dxi^da deta^db of xi^a eta^b
+double mono(int a, int b, int da, int db, double x, double y) {
+  if (da > a || db > b) return 0.0;
+  double c = 1.0;
+  for (int q = 0; q < da; ++q) c *= (double)(a - q);
+  for (int q = 0; q < db; ++q) c *= (double)(b - q);
+  for (int q = 0; q < a - da; ++q) c *= x;
+  for (int q = 0; q < b - db; ++q) c *= y;
+  return c;
+}
+
+// averages over a triangle of the nine monomials and of
+// their xi- and eta-derivatives, all at once, by the rule exact for degree
+// <= 3 (vertices 1/20, edge midpoints 2/15, centroid 9/20)
+void tri_avgs(const double (&t)[3][2], double (&m)[NA], double (&mx)[NA], double (&my)[NA]) {
+  double P[7][2], Wq[7];
+  for (int v = 0; v < 3; ++v) {
+    const int w = (v + 1) % 3;
+    P[v][0] = t[v][0];
+    P[v][1] = t[v][1];
+    Wq[v] = 1.0 / 20.0;
+    P[3 + v][0] = 0.5 * (t[v][0] + t[w][0]);
+    P[3 + v][1] = 0.5 * (t[v][1] + t[w][1]);
+    Wq[3 + v] = 2.0 / 15.0;
+  }
+  P[6][0] = (t[0][0] + t[1][0] + t[2][0]) / 3.0;
+  P[6][1] = (t[0][1] + t[1][1] + t[2][1]) / 3.0;
+  Wq[6] = 9.0 / 20.0;
+  for (int q = 0; q < NA; ++q) m[q] = mx[q] = my[q] = 0.0;
+  for (int g = 0; g < 7; ++g) {
+    const double x = P[g][0], y = P[g][1], xx = x * x, xy = x * y, yy = y * y;
+    const double ph[NA] = {x, y, xx, xy, yy, xx * x, xx * y, x * yy, yy * y};
+    const double px[NA] = {1.0, 0.0, 2.0 * x, y, 0.0, 3.0 * xx, 2.0 * xy, yy, 0.0};
+    const double py[NA] = {0.0, 1.0, 0.0, x, 2.0 * y, 0.0, xx, 2.0 * xy, 3.0 * yy};
+    for (int q = 0; q < NA; ++q) {
+      m[q] += Wq[g] * ph[q];
+      mx[q] += Wq[g] * px[q];
+      my[q] += Wq[g] * py[q];
+    }
+  }
+}
+
+// degree-4 averages over a triangle (Dunavant's symmetric 6-point rule)
+template <typename F>
+double avg4(const double (&t)[3][2], F f) {
+  const double A[2] = {0.445948490915965, 0.091576213509771};
+  const double Wt[2] = {0.223381589678011, 0.109951743655322};
+  double s = 0.0;
+  for (int g = 0; g < 2; ++g)
+    for (int r = 0; r < 3; ++r) {
+      double bc[3] = {A[g], A[g], A[g]};
+      bc[r] = 1.0 - 2.0 * A[g];
+      const double x = bc[0] * t[0][0] + bc[1] * t[1][0] + bc[2] * t[2][0];
+      const double y = bc[0] * t[0][1] + bc[1] * t[1][1] + bc[2] * t[2][1];
+      s += Wt[g] * f(x, y);
+    }
+  return s;
+}
+
+// Least-squares operator P = A^+ (NA x ND) of the ND x NA matrix A (full
+// column rank) by Householder QR: A = Q R, P = R^-1 Q^T. Returns false if a
+// diagonal of R is below 1e-12 of the largest.
+bool pinv(const double (&A)[ND][NA], double (&P)[NA][ND]) {
+  double R[ND][NA], Qt[ND][ND];
+  std::memcpy(R, A, sizeof R);
+  for (int i = 0; i < ND; ++i)
+    for (int j = 0; j < ND; ++j) Qt[i][j] = i == j ? 1.0 : 0.0;
+  for (int k = 0; k < NA; ++k) {
+    double nrm = 0.0;
+    for (int i = k; i < ND; ++i) nrm += R[i][k] * R[i][k];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) return false;
+    const double alpha = R[k][k] > 0.0 ? -nrm : nrm;
+    double v[ND] = {};
+    for (int i = k; i < ND; ++i) v[i] = R[i][k];
+    v[k] -= alpha;
+    double vv = 0.0;
+    for (int i = k; i < ND; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    for (int j = 0; j < NA; ++j) {
+      double s = 0.0;
+      for (int i = k; i < ND; ++i) s += v[i] * R[i][j];
+      s = 2.0 * s / vv;
+      for (int i = k; i < ND; ++i) R[i][j] -= s * v[i];
+    }
+    for (int j = 0; j < ND; ++j) {
+      double s = 0.0;
+      for (int i = k; i < ND; ++i) s += v[i] * Qt[i][j];
+      s = 2.0 * s / vv;
+      for (int i = k; i < ND; ++i) Qt[i][j] -= s * v[i];
+    }
+  }
+  double rmax = 0.0;
+  for (int k = 0; k < NA; ++k) rmax = std::fmax(rmax, std::fabs(R[k][k]));
+  for (int k = 0; k < NA; ++k)
+    if (!(std::fabs(R[k][k]) > 1e-12 * rmax)) return false;
+  // back substitution R[0:NA, :] X = Qt[0:NA, :]
+  for (int j = 0; j < ND; ++j)
+    for (int k = NA - 1; k >= 0; --k) {
+      double s = Qt[k][j];
+      for (int q = k + 1; q < NA; ++q) s -= R[k][q] * P[q][j];
+      P[k][j] = s / R[k][k];
+    }
+  return true;
+}
+
+struct TriK {
+  double C, inv_tanhC, eps, d[3];
+};
+
+// NV lanes per cell, one per variable (the lanes of a cell sit in one wave
+// and load the same table entries, which the wave merges): the cubic's
+// coefficients from the 17 data entries, the indicators, the path function,
+// the ENO weights and the blended states at the six edge Gauss points.
+template <int NV>
+__global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ ops,
+                                             const double* __restrict__ W,
+                                             const double* __restrict__ dW,
+                                             double* __restrict__ out, double* __restrict__ chi,
+                                             TriK k) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = t / NV, v = t - c * NV;
+  if (c >= n) return;
+  const double* op = ops + c;
+  const size_t sn = (size_t)n;
+  int idx[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) idx[i] = (int)op[(T_IDX + i) * sn];
+  const double h = op[T_H * sn];
+  const double wc = W[v * sn + c];
+  // entry i of the data vector
+  auto data = [&](int i) -> double {
+    if (i < 9) return W[v * sn + idx[i]] - wc;
+    if (i < 11) return h * dW[((i - 9) * NV + v) * sn + c];
+    const int kk = (i - 11) >> 1, dir = (i - 11) & 1;
+    return h * dW[(dir * NV + v) * sn + idx[kk]];
+  };
+  double av[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) av[q] = 0.0;
+  // (not unrolled: one operator column and one data entry live at a time)
+#pragma unroll 1
+  for (int i = 0; i < ND; ++i) {
+    const double d = data(i);
+#pragma unroll
+    for (int q = 0; q < NA; ++q) av[q] = fma(op[(T_M + q * ND + i) * sn], d, av[q]);
+  }
+  const double IStau = 36.0 * av[5] * av[5] + 4.0 * av[6] * av[6] + 4.0 * av[7] * av[7] +
+                       36.0 * av[8] * av[8];
+  double Q = 0.0;
+  {
+    int g = 0;
+#pragma unroll
+    for (int p = 0; p < NA; ++p)
+#pragma unroll
+      for (int q = p; q < NA; ++q, ++g) Q = fma(op[(T_G + g) * sn] * av[p], av[q], Q);
+  }
+  const double ISH = Q + IStau;
+  double b[3][2], IS[3];
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    const double e0 = data(kk), e1 = data(11 + 2 * kk), e2 = data(12 + 2 * kk);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int o = T_L + (kk * 2 + r) * 3;
+      b[kk][r] = op[o * sn] * e0 + op[(o + 1) * sn] * e1 + op[(o + 2) * sn] * e2;
+    }
+    IS[kk] = b[kk][0] * b[kk][0] + b[kk][1] * b[kk][1];
+  }
+  const double ISL = IS[0] + IS[1] + IS[2] - fmin(IS[0], fmin(IS[1], IS[2])) -
+                     fmax(IS[0], fmax(IS[1], IS[2]));
+  const double xH = IStau / (ISH + k.eps), xL = IStau / (ISL + k.eps);
+  const double aH = 1.0 + xH * xH * xH, aL = 1.0 + xL * xL * xL;
+  const double alpha = 2.0 * aH / (aH + aL);
+  const double x = tanh(k.C * alpha) * k.inv_tanhC;
+  double w[3], ws = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    const double e = IS[kk] + k.eps;
+    w[kk] = k.d[kk] / (e * e);
+    ws += w[kk];
+  }
+  const double iw = 1.0 / ws;
+  double gLx = 0.0, gLy = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    w[kk] *= iw;
+    gLx = fma(w[kk], b[kk][0], gLx);
+    gLy = fma(w[kk], b[kk][1], gLy);
+  }
+  if (chi) chi[v * sn + c] = x;
+  const double xm = 1.0 - x;
+  double vx[3], vy[3], mean[NA];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    vx[r] = op[(T_V + 2 * r) * sn];
+    vy[r] = op[(T_V + 2 * r + 1) * sn];
+  }
+#pragma unroll
+  for (int q = 0; q < NA; ++q) mean[q] = op[(T_MEAN + q) * sn];
+  const double t0 = 0.5 - 0.5 / 1.7320508075688772935, t1 = 0.5 + 0.5 / 1.7320508075688772935;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int e1 = (e + 1) % 3;
+#pragma unroll
+    for (int gp = 0; gp < 2; ++gp) {
+      const double tt = gp == 0 ? t0 : t1;
+      const double X = vx[e] + tt * (vx[e1] - vx[e]), Y = vy[e] + tt * (vy[e1] - vy[e]);
+      const double XX = X * X, XY = X * Y, YY = Y * Y;
+      const double ph[NA] = {X, Y, XX, XY, YY, XX * X, XX * Y, X * YY, YY * Y};
+      const double px[NA] = {1.0, 0.0, 2.0 * X, Y, 0.0, 3.0 * XX, 2.0 * XY, YY, 0.0};
+      const double py[NA] = {0.0, 1.0, 0.0, X, 2.0 * Y, 0.0, XX, 2.0 * XY, 3.0 * YY};
+      double p3 = wc, p3x = 0.0, p3y = 0.0;
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        p3 = fma(av[q], ph[q] - mean[q], p3);
+        p3x = fma(av[q], px[q], p3x);
+        p3y = fma(av[q], py[q], p3y);
+      }
+      double pL = wc;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) pL = fma(w[kk], b[kk][0] * X + b[kk][1] * Y, pL);
+      const int pt = 2 * e + gp;
+      out[((pt * 3 + 0) * NV + v) * sn + c] = x * p3 + xm * pL;
+      out[((pt * 3 + 1) * NV + v) * sn + c] = x * p3x + xm * gLx;
+      out[((pt * 3 + 2) * NV + v) * sn + c] = x * p3y + xm * gLy;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t geno_tri_table_doubles(void) { return (size_t)T_N; }
+
+int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* shift, double* ops) {
+  if (ncell < 1 || !xv || !nbr || !shift || !ops) return fail(GENO_EINVAL, "bad mesh arguments");
+  const size_t n = (size_t)ncell;
+  for (size_t c = 0; c < n; ++c)
+    for (int e = 0; e < 3; ++e)
+      if (nbr[3 * c + e] < 0 || nbr[3 * c + e] >= ncell)
+        return fail(GENO_EINVAL, "cell %zu: neighbour %d out of range", c, nbr[3 * c + e]);
+  auto vert = [&](size_t c, int v, int d) { return xv[(c * 3 + v) * 2 + d]; };
+  auto area_of = [&](size_t c) {
+    return 0.5 * ((vert(c, 1, 0) - vert(c, 0, 0)) * (vert(c, 2, 1) - vert(c, 0, 1)) -
+                  (vert(c, 2, 0) - vert(c, 0, 0)) * (vert(c, 1, 1) - vert(c, 0, 1)));
+  };
+  for (size_t c = 0; c < n; ++c) {
+    const double area = area_of(c);
+    if (!(area > 0.0)) return fail(GENO_EINVAL, "cell %zu is degenerate or clockwise", c);
+    const double h = std::sqrt(area);
+    const double xc = (vert(c, 0, 0) + vert(c, 1, 0) + vert(c, 2, 0)) / 3.0;
+    const double yc = (vert(c, 0, 1) + vert(c, 1, 1) + vert(c, 2, 1)) / 3.0;
+    // stencil: edge neighbours, then their neighbours other than c itself
+    int cell[9];
+    double tr[9][2];
+    int ns = 3;
+    for (int e = 0; e < 3; ++e) {
+      cell[e] = nbr[3 * c + e];
+      tr[e][0] = shift[(c * 3 + e) * 2];
+      tr[e][1] = shift[(c * 3 + e) * 2 + 1];
+    }
+    for (int e = 0; e < 3; ++e) {
+      const size_t d = (size_t)cell[e];
+      for (int f = 0; f < 3; ++f) {
+        const int q = nbr[3 * d + f];
+        const double sx = tr[e][0] + shift[(d * 3 + f) * 2], sy = tr[e][1] + shift[(d * 3 + f) * 2 + 1];
+        if ((size_t)q == c && sx == 0.0 && sy == 0.0) continue;
+        if (ns == 9) return fail(GENO_EINVAL, "cell %zu: more than six second-level cells", c);
+        cell[ns] = q;
+        tr[ns][0] = sx;
+        tr[ns][1] = sy;
+        ++ns;
+      }
+    }
+    if (ns != 9) return fail(GENO_EINVAL, "cell %zu: %d second-level cells, not six", c, ns - 3);
+    // scaled triangle of a stencil cell (translated), about x_c
+    auto scaled = [&](size_t d, double sx, double sy, double (&t)[3][2]) {
+      for (int v = 0; v < 3; ++v) {
+        t[v][0] = (vert(d, v, 0) + sx - xc) / h;
+        t[v][1] = (vert(d, v, 1) + sy - yc) / h;
+      }
+    };
+    double own[3][2];
+    scaled(c, 0.0, 0.0, own);
+    double mean[NA], mx[NA], my[NA];
+    tri_avgs(own, mean, mx, my);
+    double A[ND][NA];
+    // h-scaled gradient rows: own cell (entries 9, 10), edge neighbour k (11 + 2k, 12 + 2k)
+    for (int q = 0; q < NA; ++q) {
+      A[9][q] = mx[q];
+      A[10][q] = my[q];
+    }
+    for (int s = 0; s < 9; ++s) {
+      double t[3][2], ms[NA], sx[NA], sy[NA];
+      scaled((size_t)cell[s], tr[s][0], tr[s][1], t);
+      tri_avgs(t, ms, sx, sy);
+      for (int q = 0; q < NA; ++q) {
+        A[s][q] = ms[q] - mean[q];
+        if (s < 3) {
+          A[11 + 2 * s][q] = sx[q];
+          A[12 + 2 * s][q] = sy[q];
+        }
+      }
+    }
+    double P[NA][ND];
+    if (!pinv(A, P)) return fail(GENO_EINVAL, "cell %zu: rank-deficient least-squares stencil", c);
+    double* o = ops + c;
+    for (int s = 0; s < 9; ++s) o[(T_IDX + s) * n] = (double)cell[s];
+    for (int q = 0; q < NA; ++q)
+      for (int i = 0; i < ND; ++i) o[(T_M + q * ND + i) * n] = P[q][i];
+    // linear candidate k: rows (centroid offset), (1, 0), (0, 1) of the
+    // edge neighbour; its least-squares inverse in closed form
+    for (int kk = 0; kk < 3; ++kk) {
+      double t[3][2];
+      scaled((size_t)cell[kk], tr[kk][0], tr[kk][1], t);
+      const double cx = (t[0][0] + t[1][0] + t[2][0]) / 3.0, cy = (t[0][1] + t[1][1] + t[2][1]) / 3.0;
+      const double det = 1.0 + cx * cx + cy * cy;
+      const double inv[2][2] = {{(cy * cy + 1.0) / det, -cx * cy / det}, {-cx * cy / det, (cx * cx + 1.0) / det}};
+      const double At[2][3] = {{cx, 1.0, 0.0}, {cy, 0.0, 1.0}};
+      for (int r = 0; r < 2; ++r)
+        for (int col = 0; col < 3; ++col)
+          o[(T_L + (kk * 2 + r) * 3 + col) * n] = inv[r][0] * At[0][col] + inv[r][1] * At[1][col];
+    }
+    // indicator matrix of the first and second derivatives over the cell
+    static const int L12[5][2] = {{1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}};
+    int g = 0;
+    for (int p = 0; p < NA; ++p)
+      for (int q = p; q < NA; ++q, ++g) {
+        const double val = avg4(own, [&](double x, double y) {
+          double s = 0.0;
+          for (const auto& l : L12)
+            s += mono(EX[p][0], EX[p][1], l[0], l[1], x, y) * mono(EX[q][0], EX[q][1], l[0], l[1], x, y);
+          return s;
+        });
+        o[(T_G + g) * n] = p == q ? val : 2.0 * val;
+      }
+    for (int v = 0; v < 3; ++v) {
+      o[(T_V + 2 * v) * n] = own[v][0];
+      o[(T_V + 2 * v + 1) * n] = own[v][1];
+    }
+    for (int q = 0; q < NA; ++q) o[(T_MEAN + q) * n] = mean[q];
+    o[T_H * n] = h;
+  }
+  return GENO_OK;
+}
+
+int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, const double* dW,
+                         double* out, double* chi, void* stream) {
+  if (ncell < 1 || nv < 1 || nv > GENO_TRI_MAXV) return fail(GENO_EINVAL, "bad ncell or nv");
+  if (!ops || !W || !dW || !out) return fail(GENO_EINVAL, "null pointer");
+  TriK k;
+  k.C = 20.0;
+  k.inv_tanhC = 1.0 / std::tanh(20.0);
+  k.eps = 1e-15;
+  k.d[0] = k.d[1] = k.d[2] = 1.0;
+  const dim3 grid((unsigned)(((size_t)ncell * nv + 255) / 256)), block(256);
+  hipStream_t s = (hipStream_t)stream;
+  const double* T = (const double*)ops;
+  switch (nv) {
+    case 1: hipLaunchKernelGGL(k_tri<1>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
+    case 2: hipLaunchKernelGGL(k_tri<2>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
+    case 3: hipLaunchKernelGGL(k_tri<3>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
+    default: hipLaunchKernelGGL(k_tri<4>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return GENO_OK;
+}
+
+// per cell and variable, as k_tri executes them: data entries 17, the
+// operator product 2 * 153, IS^tau 11, a^T G a 3 * 45, IS^H 1, linear
+// candidates 3 * (2 * 5 + 3), IS^L 4, alpha 13, chi 2 (tanh counted 1),
+// weights 3 * 4 + 2 + 1, blended gradient 3 * 4, and per Gauss point
+// (6): point 6, monomials 7, derivatives 9, cubic 9 * 2 + 2 * 2 * 9, linear
+// blend 3 * 4, output 3 * 3
+double geno_tri_op_cost(void) {
+  const double per_point = 6 + 7 + 9 + (9 * 2 + 2 * 2 * 9) + 3 * 4 + 3 * 3;
+  return 17 + 2 * 153 + 11 + 3 * 45 + 1 + 3 * (2 * 5 + 3) + 4 + 13 + 2 + (3 * 4 + 2 + 1) + 3 * 4 +
+         6 * per_point;
+}
+
+}  // extern "C"

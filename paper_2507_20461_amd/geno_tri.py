@@ -1,0 +1,79 @@
+"""Python binding of the fourth-order compact GENO reconstruction on
+triangular meshes (C ABI in ``include/geno_tri.h``; the entry points live in
+``libgeno_gks.so``).
+
+Argument marshalling only: the operator table is built by the library's
+host mesh layer, the reconstruction runs in its kernel. torch provides
+device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import geno_gks as G
+
+EXPORTS = ("geno_tri_table_doubles", "geno_tri_build", "geno_tri_reconstruct", "geno_tri_op_cost")
+MAXV = 4
+_ready = False
+
+
+def lib():
+    global _ready
+    L = G.lib()
+    if not _ready:
+        vp, i, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        L.geno_tri_table_doubles.restype = ctypes.c_size_t
+        L.geno_tri_table_doubles.argtypes = []
+        L.geno_tri_build.argtypes = [i, dp, ctypes.POINTER(ctypes.c_int), dp, dp]
+        L.geno_tri_build.restype = i
+        L.geno_tri_reconstruct.argtypes = [i, i, vp, vp, vp, vp, vp, vp]
+        L.geno_tri_reconstruct.restype = i
+        L.geno_tri_op_cost.restype = ctypes.c_double
+        L.geno_tri_op_cost.argtypes = []
+        _ready = True
+    return L
+
+
+def build_table(mesh) -> np.ndarray:
+    """Host operator table [table_doubles, ncell] of a mesh dict (xv, nbr, shift)."""
+    xv = np.ascontiguousarray(mesh["xv"], dtype=np.float64)
+    nbr = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
+    sh = np.ascontiguousarray(mesh["shift"], dtype=np.float64)
+    n = xv.shape[0]
+    nt = lib().geno_tri_table_doubles()
+    ops = np.zeros((nt, n))
+    dp = ctypes.POINTER(ctypes.c_double)
+    G._check(lib().geno_tri_build(n, xv.ctypes.data_as(dp), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  sh.ctypes.data_as(dp), ops.ctypes.data_as(dp)))
+    return ops
+
+
+class TriMesh:
+    """A triangle mesh with its operator table on the device."""
+
+    def __init__(self, mesh, device="cuda"):
+        self.ncell = int(np.asarray(mesh["xv"]).shape[0])
+        self.table_host = build_table(mesh)
+        self.table = torch.from_numpy(self.table_host).to(device)
+
+    def out_shape(self, nv):
+        return (6, 3, nv, self.ncell)
+
+
+def reconstruct(tm, W, dW, out, chi=None, stream=None):
+    """W [nv, ncell], dW [2, nv, ncell] float64 on the device; out [6, 3, nv,
+    ncell]; chi [nv, ncell] or None."""
+    nv = W.shape[0]
+    G._need(W, torch.float64, nv * tm.ncell, "W")
+    G._need(dW, torch.float64, 2 * nv * tm.ncell, "dW")
+    G._need(out, torch.float64, 18 * nv * tm.ncell, "out")
+    G._need(chi, torch.float64, nv * tm.ncell, "chi", optional=True)
+    G._check(lib().geno_tri_reconstruct(tm.ncell, nv, G._ptr(tm.table), G._ptr(W), G._ptr(dW), G._ptr(out),
+                                        G._ptr(chi), G._stream(stream)))
+
+
+def op_cost():
+    return lib().geno_tri_op_cost()

@@ -457,17 +457,14 @@ def tri_mesh(nx: int, ny: int, seed: int, jitter: float = 0.2):
     return {"xv": xv, "nbr": nbr, "shift": shift, "nx": nx, "ny": ny}
 
 
-# Gauss-Legendre nodes and weights on [0, 1] (8 points) for the collapsed
-# (Duffy) rule that builds exact-enough averages of the initial data
-_GL8 = np.polynomial.legendre.leggauss(8)
-_GL8_X, _GL8_W = 0.5 * (_GL8[0] + 1.0), 0.5 * _GL8[1]
-
-
-def _tri_points(xv):
-    """Points and weights (summing to 1) of the collapsed 8 x 8 Gauss rule on
-    each triangle of xv [n, 3, 2] (exact for polynomials of degree <= 14)."""
-    s, t = np.meshgrid(_GL8_X, _GL8_X, indexing="ij")
-    ws = np.outer(_GL8_W, _GL8_W) * 2.0 * (1.0 - s)   # Jacobian of (s, t) -> (b1, b2)
+def _tri_points(xv, npts=8):
+    """Points and weights (summing to 1) of the collapsed npts x npts Gauss
+    rule on each triangle of xv [n, 3, 2] (exact for polynomials of degree
+    <= 2 npts - 2)."""
+    gx, gw = np.polynomial.legendre.leggauss(npts)
+    gx, gw = 0.5 * (gx + 1.0), 0.5 * gw
+    s, t = np.meshgrid(gx, gx, indexing="ij")
+    ws = np.outer(gw, gw) * 2.0 * (1.0 - s)   # Jacobian of (s, t) -> (b1, b2)
     b1 = s.ravel()
     b2 = ((1.0 - s) * t).ravel()
     w = ws.ravel()
@@ -477,11 +474,12 @@ def _tri_points(xv):
     return pts, w
 
 
-def tri_cell_data(mesh, f, grad):
+def tri_cell_data(mesh, f, grad, npts=8):
     """Cell averages of f(x, y) and of its gradient grad(x, y) -> (gx, gy)
-    over every triangle; f may return several fields stacked on axis 0.
-    Returns W [nf, ncell] and dW [2, nf, ncell] (x then y derivatives)."""
-    pts, w = _tri_points(mesh["xv"])
+    over every triangle (collapsed npts x npts Gauss rule); f may return
+    several fields stacked on axis 0. Returns W [nf, ncell] and dW [2, nf,
+    ncell] (x then y derivatives)."""
+    pts, w = _tri_points(mesh["xv"], npts)
     x, y = pts[..., 0], pts[..., 1]
     fv = np.asarray(f(x, y))
     single = fv.ndim == 2
@@ -495,7 +493,7 @@ def tri_cell_data(mesh, f, grad):
     return W, dW
 
 
-def tri_euler_smooth(mesh, seed: int, gamma: float = GAMMA):
+def tri_euler_smooth(mesh, seed: int, gamma: float = GAMMA, npts: int = 8):
     """Smooth periodic Euler state (a few seeded Fourier modes per primitive)
     as conservative cell averages and averaged gradients on a triangle mesh."""
     rng = np.random.default_rng(seed)
@@ -535,14 +533,15 @@ def tri_euler_smooth(mesh, seed: int, gamma: float = GAMMA):
                                  dp / (gamma - 1.0) + 0.5 * dr * (u * u + v * v) + rho * (u * du + v * dv)]))
         return out[0], out[1]
 
-    return tri_cell_data(mesh, cons, cons_grad)
+    return tri_cell_data(mesh, cons, cons_grad, npts)
 
 
-def tri_euler_jumps(mesh, seed: int, gamma: float = GAMMA):
+def tri_euler_jumps(mesh, seed: int, gamma: float = GAMMA, npts: int = 8):
     """Piecewise-constant Euler state on a triangle mesh: the four quadrant
     states of the structured Riemann data, drawn the same way, on the cells
     whose centroid lies in each quadrant (jumps along cell edges, zero
-    gradients), plus a small smooth part so that no stencil is flat."""
+    gradients), plus a small smooth part so that no stencil is flat
+    (averaged with the collapsed npts x npts rule; large meshes take 2)."""
     rng = np.random.default_rng(seed)
     states = quadrant_states(rng)
     cen = mesh["xv"].mean(axis=1)
@@ -550,6 +549,6 @@ def tri_euler_jumps(mesh, seed: int, gamma: float = GAMMA):
     q = np.where(right & top, 0, np.where(top, 1, np.where(right, 3, 2)))
     prim = np.asarray(states)[q].T   # rho, u, v, p per cell
     W = _cons_2d(prim[0], prim[1], prim[2], prim[3], gamma)
-    Ws, dWs = tri_euler_smooth(mesh, seed + 1, gamma)
+    Ws, dWs = tri_euler_smooth(mesh, seed + 1, gamma, npts)
     W = W + 0.02 * (Ws - Ws.mean(axis=1, keepdims=True))
     return W, 0.02 * dWs
