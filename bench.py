@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched workload")
     ap.add_argument("--noncompact-steps", type=int, default=40,
                     help="timed Runge-Kutta steps of the 1-D sixth-order non-compact workload (0 = skip)")
+    ap.add_argument("--tri-reps", type=int, default=20,
+                    help="reconstructions timed on the 2 x 512^2 triangle mesh (0 skips it)")
     ap.add_argument("--no-paper-problems", action="store_true",
                     help="skip the paper's 1-D problems and the small-grid batch with the non-compact scheme")
     return ap.parse_args()
@@ -213,6 +215,62 @@ def characteristic_2d(G, np, torch, W, dW, n, steps):
     return {"value": round(2.0 * n * n * steps / (ms / 1e3) / 1e6, 3), "unit": "Mcell-updates/s per stage",
             "ms_per_step": round(ms / steps, 5), "steps": steps, "guard": int(st.guard),
             "nonfinite": int(st.nonfinite), "rho_range": [float(Wn[0].min()), float(Wn[0].max())]}
+
+
+TRI_N = 512    # lattice squares per side of the triangle mesh (2 TRI_N^2 cells)
+
+
+def triangles_workload(np, torch, inputs, seed, reps, cpu=True):
+    """GENO reconstruction on the periodic triangle mesh of 2 x 512^2 cells
+    (Sec. 4.3): reps launches over the four Euler variables of the quadrant
+    data, timed with events on the launch stream; the kernel's roofline from
+    its algorithmic bytes (operator table, data and outputs once per cell);
+    the oracle's rate on a bounded sample of cells."""
+    from paper_2507_20461_amd import geno_tri as T
+    mesh = inputs.tri_mesh(TRI_N, TRI_N, seed)
+    W, dW = inputs.tri_euler_jumps(mesh, seed, npts=2)
+    t0 = time.perf_counter()
+    tm = T.TriMesh(mesh)
+    build_s = time.perf_counter() - t0
+    nv, n = W.shape
+    Wd, dWd = torch.from_numpy(W).cuda(), torch.from_numpy(dW).cuda()
+    out = torch.empty(tm.out_shape(nv), dtype=torch.float64, device="cuda")
+    chi = torch.empty((nv, n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    T.reconstruct(tm, Wd, dWd, out, chi, stream=stream)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        T.reconstruct(tm, Wd, dWd, out, chi, stream=stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    us = 1e3 * start.elapsed_time(end) / reps
+    nt = T.lib().geno_tri_table_doubles()
+    # algorithmic bytes per cell: table, W and dW read once, states and chi written once
+    per_cell = 8.0 * (nt + 3 * nv + 18 * nv + nv)
+    gbs = per_cell * n / (us * 1e-6) / 1e9
+    flops = T.op_cost() * nv * n
+    res = {"workload": "tri-periodic-2x%dx%d-quadrants-fp64" % (TRI_N, TRI_N), "cells": n, "variables": nv,
+           "us_per_launch": round(us, 2), "mcells_per_s": round(n / us, 1),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_cell": per_cell,
+                        "traffic": None, "traffic_detail": None,
+                        "alu_tflops": round(flops / (us * 1e-6) / 1e12, 3),
+                        "alu_frac": round(flops / (us * 1e-6) / 1e12 / PEAK_FP64_VECTOR_TFLOPS, 4)},
+           "table_build_s": round(build_s, 2), "chi_below_half": float((chi.cpu().numpy() < 0.5).mean())}
+    tb, td = tri_counters()
+    res["roofline"]["traffic"] = round(tb) if tb else None
+    res["roofline"]["traffic_detail"] = td
+    if cpu:
+        from oracle import geno_tri as O
+        cells = list(range(0, n, max(1, n // 400)))[:400]
+        t0 = time.perf_counter()
+        O.reconstruct(mesh, W, dW, cells=cells)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(len(cells) / dt / 1e6, 6), "unit": "Mcells/s", "cores": 1,
+                               "kind": "oracle", "sample": "%d cells of the mesh, all four variables" % len(cells)}
+    return res
 
 
 NONCOMPACT_N = 1 << 24
@@ -500,6 +558,25 @@ def noncompact_traffic():
     w = sum(r["write_bytes_cal"] for r in rows) / 4
     return f + w, {"fetch_bytes": round(f), "write_bytes": round(w), "calibration": meta["calibration"],
                    "source": os.path.relpath(COUNTERS, ROOT)}
+
+
+def tri_counters():
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) and VALU
+    busy share of the triangle kernel from the committed counter passes, or
+    (None, reason) when they were taken on other kernel sources."""
+    from paper_2507_20461_amd import profiling
+    if not os.path.exists(COUNTERS):
+        return None, None
+    meta = json.load(open(COUNTERS))
+    if meta.get("source_hash") != profiling.source_hash():
+        return None, "counters taken on other kernel sources"
+    r = meta["kernels"].get("k_tri<4>")
+    if not r or r.get("fetch_bytes_cal") is None or r.get("write_bytes_cal") is None:
+        return None, None
+    return r["fetch_bytes_cal"] + r["write_bytes_cal"], {
+        "fetch_bytes": round(r["fetch_bytes_cal"]), "write_bytes": round(r["write_bytes_cal"]),
+        "valu_busy": r.get("valu_busy"), "calibration": meta["calibration"],
+        "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def noncompact_valu_busy():
@@ -895,6 +972,9 @@ def main():
         out["batched"] = _finite(batched_workload(G, inputs, np, torch, args.seed))
     if not args.no_forms:
         out["robustness"] = _finite(robustness_runs(G, inputs, np, torch))
+    if args.tri_reps > 0:
+        out["triangles"] = _finite(triangles_workload(np, torch, inputs, args.seed, args.tri_reps,
+                                                      cpu=not args.no_cpu_baseline))
     if args.noncompact_steps > 0:
         out["noncompact"] = _finite(noncompact_workload(np, torch, inputs, args.seed, args.noncompact_steps,
                                                         cpu=not args.no_cpu_baseline,

@@ -37,7 +37,7 @@ CAL_ELEMS = CAL_BYTES // 8
 BENCH_FULL = ["python3", os.path.join(ROOT, "bench.py")]
 BENCH_SHORT = ["python3", os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1",
                "--no-cpu-baseline", "--no-kernel-timing", "--no-forms", "--no-batched", "--noncompact-steps", "2",
-               "--no-paper-problems"]
+               "--no-paper-problems", "--tri-reps", "3"]
 OWN = ("k_", "kb_", "k6_")   # prefixes of the library's kernels
 PASSES = {
     "ktrace": (["--kernel-trace", "--stats"], BENCH_FULL),
@@ -147,6 +147,9 @@ def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
         if k.startswith("k6_init"):
             # one geno6_step call: 255 cells per work-group of 256 lanes
             label = "noncompact fp64 %d tiles of 255 cells" % (cells // 256)
+        if k.startswith("k_tri"):
+            # one lane per cell and variable (four variables)
+            label = "triangles fp64 %d cells" % (cells // 4)
         if k.startswith("kb_"):
             lab = "batched (mixed)"
         elif label is None or not k.startswith(("k_", "k6_")):
@@ -160,7 +163,8 @@ def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
     lines.append("# kernel sources sha256[:16]: " + sh)
     lines.append("# workload labels: element type and grid of the gks_step call (k_init grid size = cells,")
     lines.append("# rounded to the next work-group); the bench's 512x512 workload is 'fp64 512x512', its")
-    lines.append("# 2^24-cell non-compact workload 'noncompact fp64 65794 tiles of 255 cells'")
+    lines.append("# 2^24-cell non-compact workload 'noncompact fp64 65794 tiles of 255 cells', its")
+    lines.append("# triangle mesh of 2 x 512^2 cells 'triangles fp64 524288 cells'")
     ktrace = {}
     for lab, ks in per.items():
         lines.append("")
@@ -168,7 +172,7 @@ def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
         lines.append("%-28s %7s %10s %10s" % ("kernel", "calls", "avg_us", "total_ms"))
         for k, v in sorted(ks.items(), key=lambda kv: -sum(kv[1])):
             lines.append("%-28s %7d %10.2f %10.3f" % (k[:28], len(v), sum(v) / len(v), sum(v) / 1e3))
-            if lab.startswith("fp64 512x512") or lab.startswith("noncompact fp64 65794 "):
+            if lab.startswith(("fp64 512x512", "noncompact fp64 65794 ", "triangles fp64 524288 ")):
                 ktrace.setdefault(k, []).extend(v)
     ktrace = {k: sum(v) / len(v) for k, v in ktrace.items()}
     open(os.path.join(dest, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
@@ -204,8 +208,9 @@ def summarize(tag="faces_fp64_512", dest=PROFILES):
                    "fetch_bytes_cal": f / fcal if fcal else None, "write_bytes_cal": w / wcal if wcal else None,
                    "valu_insts_per_wave": insts / waves if waves else None,
                    "valu_busy": 4.0 * active / SIMDS / gui if gui else None}
-    lines = ["# rocprofv3 counters per dispatch (3 separate --pmc passes), 2-D Euler 512x512 FP64 (k_*) and",
-             "# the 1-D non-compact workload of 2^24 cells (k6_*)",
+    lines = ["# rocprofv3 counters per dispatch (3 separate --pmc passes), 2-D Euler 512x512 FP64 (k_*),",
+             "# the 1-D non-compact workload of 2^24 cells (k6_*) and the triangle mesh of 2 x 512^2 cells",
+             "# (k_tri)",
              "# commands:"]
     for name in ("fetch", "write", "valu"):
         lines.append("#   " + " ".join(command(name)).replace(ROOT + "/", ""))
