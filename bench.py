@@ -35,11 +35,11 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # rocprofv3 kernel names of the measured kernel kinds (2-D path)
-ROCPROF_NAMES = {"init": "k_init<2, double>", "normal_x": "k_normal2d<0, double>",
-                 "normal_y": "k_normal2d<1, double>", "faces_x": "k_faces2d<0, 1, double>",
+ROCPROF_NAMES = {"init": "k_init<2, double>", "normal_x": "k_normal2d<0, double, false>",
+                 "normal_y": "k_normal2d<1, double, false>", "faces_x": "k_faces2d<0, 1, double>",
                  "faces_y": "k_faces2d<1, 1, double>", "slow": "k_slow2d<double>",
                  "update_1": "k_update<2, 1, double>", "update_2": "k_update<2, 2, double>",
-                 "normal_xy": "k_normal2d_xy<double>"}
+                 "normal_xy": "k_normal2d_xy<double, false>"}
 # a launch that does the work counted under several kinds
 COMBINED = {"normal_xy": ("normal_x", "normal_y")}
 COUNTERS = os.path.join(ROOT, "profiles", "faces_fp64_512_counters.json")

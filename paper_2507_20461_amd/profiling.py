@@ -147,6 +147,9 @@ def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
         if k.startswith("k6_init"):
             # one geno6_step call: 255 cells per work-group of 256 lanes
             label = "noncompact fp64 %d tiles of 255 cells" % (cells // 256)
+        if k.startswith("k6_faces"):
+            # a geno6_faces call (no k6_init before it)
+            label = "noncompact faces fp64 %d lanes" % cells
         if k.startswith("k_tri"):
             # one lane per cell and variable (four variables)
             label = "triangles fp64 %d cells" % (cells // 4)
