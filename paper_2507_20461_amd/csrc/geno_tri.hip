@@ -160,18 +160,20 @@ struct TriK {
   double C, inv_tanhC, eps, d[3];
 };
 
-// NV lanes per cell, one per variable (the lanes of a cell sit in one wave
-// and load the same table entries, which the wave merges): the cubic's
-// coefficients from the 17 data entries, the indicators, the path function,
-// the ENO weights and the blended states at the six edge Gauss points.
+// One wave per variable over 64 consecutive cells: a work-group of NV waves
+// covers 64 cells, its waves read the same table lines (the repeats hit the
+// caches) and every load and store of a wave spans 64 consecutive cells.
+// Per lane: the cubic's coefficients from the 17 data entries, the
+// indicators, the path function, the ENO weights and the blended states at
+// the six edge Gauss points.
 template <int NV>
 __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ ops,
                                              const double* __restrict__ W,
                                              const double* __restrict__ dW,
                                              double* __restrict__ out, double* __restrict__ chi,
                                              TriK k) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = t / NV, v = t - c * NV;
+  const int v = (int)(threadIdx.x >> 6);
+  const int c = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
   if (c >= n) return;
   const double* op = ops + c;
   const size_t sn = (size_t)n;
@@ -190,8 +192,7 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
   double av[NA];
 #pragma unroll
   for (int q = 0; q < NA; ++q) av[q] = 0.0;
-  // (not unrolled: one operator column and one data entry live at a time)
-#pragma unroll 1
+#pragma unroll
   for (int i = 0; i < ND; ++i) {
     const double d = data(i);
 #pragma unroll
@@ -407,7 +408,7 @@ int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, co
   k.inv_tanhC = 1.0 / std::tanh(20.0);
   k.eps = 1e-15;
   k.d[0] = k.d[1] = k.d[2] = 1.0;
-  const dim3 grid((unsigned)(((size_t)ncell * nv + 255) / 256)), block(256);
+  const dim3 grid((unsigned)((ncell + 63) / 64)), block(64 * nv);
   hipStream_t s = (hipStream_t)stream;
   const double* T = (const double*)ops;
   switch (nv) {
