@@ -246,9 +246,12 @@ def triangles_workload(np, torch, inputs, seed, reps, cpu=True):
     end.record(stream)
     torch.cuda.synchronize()
     us = 1e3 * start.elapsed_time(end) / reps
-    nt = T.lib().geno_tri_table_doubles()
-    # algorithmic bytes per cell: table, W and dW read once, states and chi written once
-    per_cell = 8.0 * (nt + 3 * nv + 18 * nv + nv)
+    # algorithmic bytes per cell: the table's 241 entries (9 stencil indices,
+    # h, the 9 x 17 operator, 18 linear-candidate entries, 45 indicator
+    # entries, 6 vertex and 9 mean coordinates; its 19 padding entries are a
+    # layout choice and not counted), W and dW read once, states and chi
+    # written once
+    per_cell = 8.0 * (241 + 3 * nv + 18 * nv + nv)
     gbs = per_cell * n / (us * 1e-6) / 1e9
     flops = T.op_cost() * nv * n
     res = {"workload": "tri-periodic-2x%dx%d-quadrants-fp64" % (TRI_N, TRI_N), "cells": n, "variables": nv,

@@ -52,7 +52,8 @@ size_t geno_tri_table_doubles(void);
 
 /* Mesh layer, host only (no device access; call once per mesh): fills the
  * operator table ops (HOST array of ncell * geno_tri_table_doubles()
- * doubles, cell-fastest layout, owned by the caller) from the mesh arrays
+ * doubles, owned by the caller; entries stored in pairs, entry e of cell c
+ * at index ((e / 2) * ncell + c) * 2 + e % 2) from the mesh arrays
  * above. The caller copies it to device memory for geno_tri_reconstruct.
  * GENO_EINVAL for ncell < 1, null pointers, a neighbour index out of range,
  * a degenerate (non counter-clockwise) triangle or a rank-deficient
@@ -61,7 +62,7 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
 
 /* GENO reconstruction of every cell at the two Gauss points of each of its
  * edges (points t = 1/2 -+ 1/(2 sqrt 3) along edge e from vertex e to e+1).
- * ops: DEVICE copy of the table from geno_tri_build.
+ * ops: DEVICE copy of the table from geno_tri_build (16-byte aligned).
  * W (device): cell averages [nv][ncell]; dW (device): averaged gradients
  *   [2][nv][ncell] (d/dx rows, then d/dy rows). nv in 1..GENO_TRI_MAXV.
  * out (device): [point(6) = 2 e + g][quant(3)][nv][ncell], quant 0 the value,

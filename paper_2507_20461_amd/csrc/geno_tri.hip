@@ -38,15 +38,25 @@ using geno_err::fail;
 
 constexpr int NA = 9;        // coefficients of the cubic candidate
 constexpr int ND = 17;       // entries of its data vector
-// table offsets (doubles per cell, cell-fastest: entry q of cell c at q * n + c)
-constexpr int T_IDX = 0;                  // 9 stencil cells (3 edge neighbours, 6 second level)
-constexpr int T_M = T_IDX + 9;            // least-squares operator [NA][ND]
-constexpr int T_L = T_M + NA * ND;        // linear candidates [3][2][3]
-constexpr int T_G = T_L + 18;             // indicator matrix, upper triangle (off-diagonal doubled)
-constexpr int T_V = T_G + NA * (NA + 1) / 2;   // scaled vertices (xi, eta) x 3
-constexpr int T_MEAN = T_V + 6;           // m_alpha
-constexpr int T_H = T_MEAN + NA;          // h
-constexpr int T_N = T_H + 1;
+// Table entries per cell, stored in pairs: entries 2p and 2p+1 of cell c
+// are the two doubles of pair p at pair index p * n + c (16-byte aligned),
+// so that one 16-byte load per lane brings two entries and a wave's load
+// spans 64 consecutive cells. Every region starts on an even entry.
+constexpr int E_IDX = 0;                  // 9 stencil cells (3 edge neighbours, 6 second level)
+constexpr int E_H = 9;                    // h
+constexpr int NAP = NA + 1;               // operator column padded to pairs
+constexpr int E_M = 10;                   // least-squares operator [ND][NAP] (column i of P, padded)
+constexpr int E_L = E_M + ND * NAP;       // linear candidates [3][2][3]
+constexpr int E_G = E_L + 18;             // indicator matrix, upper triangle (off-diagonal doubled), padded
+constexpr int NG = NA * (NA + 1) / 2 + 1;
+constexpr int E_V = E_G + NG;             // scaled vertices (xi, eta) x 3
+constexpr int E_MEAN = E_V + 6;           // m_alpha, padded
+constexpr int E_N = E_MEAN + NA + 1;
+static_assert(E_M % 2 == 0 && E_L % 2 == 0 && E_G % 2 == 0 && E_V % 2 == 0 && E_MEAN % 2 == 0 &&
+                  E_N % 2 == 0, "table regions start on pairs");
+
+// host index of entry e of cell c in a table of n cells
+inline size_t tab_index(int e, size_t c, size_t n) { return ((size_t)(e >> 1) * n + c) * 2 + (e & 1); }
 
 constexpr int EX[NA][2] = {{1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}, {3, 0}, {2, 1}, {1, 2}, {0, 3}};
 
@@ -175,12 +185,23 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
   const int v = (int)(threadIdx.x >> 6);
   const int c = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
   if (c >= n) return;
-  const double* op = ops + c;
   const size_t sn = (size_t)n;
+  const double2* op2 = reinterpret_cast<const double2*>(ops) + c;
+  // entries [e0, e0 + 2 np) of this cell, np pair loads
+  auto region = [&](int e0, int np, double* r) {
+#pragma unroll
+    for (int p = 0; p < np; ++p) {
+      const double2 x = op2[(size_t)((e0 >> 1) + p) * sn];
+      r[2 * p] = x.x;
+      r[2 * p + 1] = x.y;
+    }
+  };
+  double ih[10];
+  region(E_IDX, 5, ih);
   int idx[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) idx[i] = (int)op[(T_IDX + i) * sn];
-  const double h = op[T_H * sn];
+  for (int i = 0; i < 9; ++i) idx[i] = (int)ih[i];
+  const double h = ih[E_H];
   const double wc = W[v * sn + c];
   // entry i of the data vector
   auto data = [&](int i) -> double {
@@ -195,19 +216,27 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
     const double d = data(i);
+    {
+      double m[NAP];
+      region(E_M + i * NAP, NAP / 2, m);
 #pragma unroll
-    for (int q = 0; q < NA; ++q) av[q] = fma(op[(T_M + q * ND + i) * sn], d, av[q]);
+      for (int q = 0; q < NA; ++q) av[q] = fma(m[q], d, av[q]);
+    }
   }
   const double IStau = 36.0 * av[5] * av[5] + 4.0 * av[6] * av[6] + 4.0 * av[7] * av[7] +
                        36.0 * av[8] * av[8];
   double Q = 0.0;
   {
+    double G[NG];
+    region(E_G, NG / 2, G);
     int g = 0;
 #pragma unroll
     for (int p = 0; p < NA; ++p)
 #pragma unroll
-      for (int q = p; q < NA; ++q, ++g) Q = fma(op[(T_G + g) * sn] * av[p], av[q], Q);
+      for (int q = p; q < NA; ++q, ++g) Q = fma(G[g] * av[p], av[q], Q);
   }
+  double Lk[18];
+  region(E_L, 9, Lk);
   const double ISH = Q + IStau;
   double b[3][2], IS[3];
 #pragma unroll
@@ -215,8 +244,8 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
     const double e0 = data(kk), e1 = data(11 + 2 * kk), e2 = data(12 + 2 * kk);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const int o = T_L + (kk * 2 + r) * 3;
-      b[kk][r] = op[o * sn] * e0 + op[(o + 1) * sn] * e1 + op[(o + 2) * sn] * e2;
+      const int o = (kk * 2 + r) * 3;
+      b[kk][r] = Lk[o] * e0 + Lk[o + 1] * e1 + Lk[o + 2] * e2;
     }
     IS[kk] = b[kk][0] * b[kk][0] + b[kk][1] * b[kk][1];
   }
@@ -243,14 +272,14 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
   }
   if (chi) chi[v * sn + c] = x;
   const double xm = 1.0 - x;
-  double vx[3], vy[3], mean[NA];
+  double vv[6], mean[NA + 1], vx[3], vy[3];
+  region(E_V, 3, vv);
+  region(E_MEAN, (NA + 1) / 2, mean);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    vx[r] = op[(T_V + 2 * r) * sn];
-    vy[r] = op[(T_V + 2 * r + 1) * sn];
+    vx[r] = vv[2 * r];
+    vy[r] = vv[2 * r + 1];
   }
-#pragma unroll
-  for (int q = 0; q < NA; ++q) mean[q] = op[(T_MEAN + q) * sn];
   const double t0 = 0.5 - 0.5 / 1.7320508075688772935, t1 = 0.5 + 0.5 / 1.7320508075688772935;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
@@ -285,7 +314,7 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
 
 extern "C" {
 
-size_t geno_tri_table_doubles(void) { return (size_t)T_N; }
+size_t geno_tri_table_doubles(void) { return (size_t)E_N; }
 
 int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* shift, double* ops) {
   if (ncell < 1 || !xv || !nbr || !shift || !ops) return fail(GENO_EINVAL, "bad mesh arguments");
@@ -359,10 +388,13 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
     }
     double P[NA][ND];
     if (!pinv(A, P)) return fail(GENO_EINVAL, "cell %zu: rank-deficient least-squares stencil", c);
-    double* o = ops + c;
-    for (int s = 0; s < 9; ++s) o[(T_IDX + s) * n] = (double)cell[s];
-    for (int q = 0; q < NA; ++q)
-      for (int i = 0; i < ND; ++i) o[(T_M + q * ND + i) * n] = P[q][i];
+    auto put = [&](int e, double x) { ops[tab_index(e, c, n)] = x; };
+    for (int s = 0; s < 9; ++s) put(E_IDX + s, (double)cell[s]);
+    put(E_H, h);
+    for (int i = 0; i < ND; ++i) {
+      for (int q = 0; q < NA; ++q) put(E_M + i * NAP + q, P[q][i]);
+      put(E_M + i * NAP + NA, 0.0);
+    }
     // linear candidate k: rows (centroid offset), (1, 0), (0, 1) of the
     // edge neighbour; its least-squares inverse in closed form
     for (int kk = 0; kk < 3; ++kk) {
@@ -374,7 +406,7 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
       const double At[2][3] = {{cx, 1.0, 0.0}, {cy, 0.0, 1.0}};
       for (int r = 0; r < 2; ++r)
         for (int col = 0; col < 3; ++col)
-          o[(T_L + (kk * 2 + r) * 3 + col) * n] = inv[r][0] * At[0][col] + inv[r][1] * At[1][col];
+          put(E_L + (kk * 2 + r) * 3 + col, inv[r][0] * At[0][col] + inv[r][1] * At[1][col]);
     }
     // indicator matrix of the first and second derivatives over the cell
     static const int L12[5][2] = {{1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}};
@@ -387,14 +419,15 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
             s += mono(EX[p][0], EX[p][1], l[0], l[1], x, y) * mono(EX[q][0], EX[q][1], l[0], l[1], x, y);
           return s;
         });
-        o[(T_G + g) * n] = p == q ? val : 2.0 * val;
+        put(E_G + g, p == q ? val : 2.0 * val);
       }
+    put(E_G + NG - 1, 0.0);
     for (int v = 0; v < 3; ++v) {
-      o[(T_V + 2 * v) * n] = own[v][0];
-      o[(T_V + 2 * v + 1) * n] = own[v][1];
+      put(E_V + 2 * v, own[v][0]);
+      put(E_V + 2 * v + 1, own[v][1]);
     }
-    for (int q = 0; q < NA; ++q) o[(T_MEAN + q) * n] = mean[q];
-    o[T_H * n] = h;
+    for (int q = 0; q < NA; ++q) put(E_MEAN + q, mean[q]);
+    put(E_MEAN + NA, 0.0);
   }
   return GENO_OK;
 }

@@ -38,13 +38,14 @@ def lib():
 
 
 def build_table(mesh) -> np.ndarray:
-    """Host operator table [table_doubles, ncell] of a mesh dict (xv, nbr, shift)."""
+    """Host operator table of a mesh dict (xv, nbr, shift): table_doubles *
+    ncell doubles, entry e of cell c at ((e // 2) * ncell + c) * 2 + e % 2."""
     xv = np.ascontiguousarray(mesh["xv"], dtype=np.float64)
     nbr = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
     sh = np.ascontiguousarray(mesh["shift"], dtype=np.float64)
     n = xv.shape[0]
     nt = lib().geno_tri_table_doubles()
-    ops = np.zeros((nt, n))
+    ops = np.zeros(nt * n)
     dp = ctypes.POINTER(ctypes.c_double)
     G._check(lib().geno_tri_build(n, xv.ctypes.data_as(dp), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                   sh.ctypes.data_as(dp), ops.ctypes.data_as(dp)))

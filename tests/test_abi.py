@@ -153,9 +153,12 @@ def test_triangle_table_host_side(so):
     from paper_2507_20461_amd import geno_tri as T
     from paper_2507_20461_amd import inputs
     nt = T.lib().geno_tri_table_doubles()
-    assert nt == 241
+    assert nt == 260
     mesh = inputs.tri_mesh(8, 8, 3)
-    ops = T.build_table(mesh)
+    n = 2 * 8 * 8
+    flat = T.build_table(mesh)
+    # entries are stored in pairs: entry e of cell c at ((e // 2) n + c) 2 + e % 2
+    ops = np.stack([flat[((e // 2) * n + np.arange(n)) * 2 + e % 2] for e in range(nt)])
     rng = np.random.default_rng(4)
     co = rng.normal(size=10)
     ex = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1), (1, 2), (0, 3)]
@@ -165,11 +168,11 @@ def test_triangle_table_host_side(so):
     W, dW = inputs.tri_cell_data(mesh, f, g)
     c = 2 * (4 * 8 + 4)            # a cell whose stencil stays inside the square
     idx = ops[0:9, c].astype(int)
-    h = ops[240, c]
+    h = ops[9, c]
     d = np.concatenate([W[0, idx] - W[0, c], h * dW[:, 0, c], (h * dW[:, 0, idx[:3]]).T.ravel()])
-    a = ops[9:9 + 153, c].reshape(9, 17) @ d
+    a = ops[10:10 + 170, c].reshape(17, 10)[:, :9].T @ d
     xc = mesh["xv"][c].mean(axis=0)
-    mean = ops[231:240, c]
+    mean = ops[250:259, c]
     for e in range(3):
         p, q = mesh["xv"][c][e], mesh["xv"][c][(e + 1) % 3]
         for t in (0.5 - 0.5 / math.sqrt(3), 0.5 + 0.5 / math.sqrt(3)):
