@@ -246,12 +246,11 @@ def triangles_workload(np, torch, inputs, seed, reps, cpu=True):
     end.record(stream)
     torch.cuda.synchronize()
     us = 1e3 * start.elapsed_time(end) / reps
-    # algorithmic bytes per cell: the table's 241 entries (9 stencil indices,
-    # h, the 9 x 17 operator, 18 linear-candidate entries, 45 indicator
-    # entries, 6 vertex and 9 mean coordinates; its 19 padding entries are a
-    # layout choice and not counted), W and dW read once, states and chi
-    # written once
-    per_cell = 8.0 * (241 + 3 * nv + 18 * nv + nv)
+    # algorithmic bytes per cell: the table's 187 entries (9 stencil indices,
+    # h, the 9 x 17 operator, 18 linear-candidate entries, 6 vertex
+    # coordinates; its 17 padding entries are a layout choice and not
+    # counted), W and dW read once, states and chi written once
+    per_cell = 8.0 * (187 + 3 * nv + 18 * nv + nv)
     gbs = per_cell * n / (us * 1e-6) / 1e9
     flops = T.op_cost() * nv * n
     res = {"workload": "tri-periodic-2x%dx%d-quadrants-fp64" % (TRI_N, TRI_N), "cells": n, "variables": nv,
@@ -967,23 +966,37 @@ def main():
         "linearity_after_run": linearity_shares(G, torch, grid, Wd, dWd, ws),
     }
     del ws, Wd, dWd
+    t_start = time.perf_counter()
+
+    def done(what):
+        # progress on stderr (the JSON line stays the only stdout line)
+        print("bench: %s done, %.0f s" % (what, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+
+    done("headline workload")
     out["characteristic_2d"] = _finite(characteristic_2d(G, np, torch, W, dW, n, args.steps))
+    done("characteristic variables")
     if not args.no_forms:
         gate = train_gate(G, torch, args.seed)
         out["forms"] = _finite(forms_comparison(G, inputs, np, torch, args.seed, gate=gate))
+        done("forms")
     if not args.no_batched:
         out["batched"] = _finite(batched_workload(G, inputs, np, torch, args.seed))
+        done("batched")
     if not args.no_forms:
         out["robustness"] = _finite(robustness_runs(G, inputs, np, torch))
+        done("robustness runs")
     if args.tri_reps > 0:
         out["triangles"] = _finite(triangles_workload(np, torch, inputs, args.seed, args.tri_reps,
                                                       cpu=not args.no_cpu_baseline))
+        done("triangles")
     if args.noncompact_steps > 0:
         out["noncompact"] = _finite(noncompact_workload(np, torch, inputs, args.seed, args.noncompact_steps,
                                                         cpu=not args.no_cpu_baseline,
                                                         paper=not args.no_paper_problems))
+        done("non-compact workload")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, dW, n)
+        done("CPU baseline")
     print(json.dumps(out), flush=True)
 
 

@@ -10,10 +10,13 @@
 // (1,0) (0,1) (2,0) (1,1) (0,2) (3,0) (2,1) (1,2) (0,3), m_alpha their
 // averages on Omega_j (so the cell average is exact). In these coordinates
 // h^{2|l|-2} int (D^l p)^2 dx = mean over Omega_j of (d^l p / d xi^l)^2, so
-//   IS~^H = a^T G a,  G_ab = mean of sum_{|l| = 1, 2} d^l phi_a d^l phi_b,
+//   IS~^H = mean over Omega_j of the squared first and second derivatives
+//           (Dunavant's degree-4 rule on the cell, exact for them),
 //   IS^tau = 36 a_30^2 + 4 a_21^2 + 4 a_12^2 + 36 a_03^2 (third derivatives
 //            of a cubic are constants),  IS^H = IS~^H + IS^tau,
-// and for p_k = Q_j + b_k . (xi, eta): IS_k = |b_k|^2.
+// and for p_k = Q_j + b_k . (xi, eta): IS_k = |b_k|^2. The kernel forms the
+// means m_alpha with the same rule; the table holds what depends on the
+// neighbours (stencil, least-squares operators) and the scaled vertices.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -47,29 +50,13 @@ constexpr int E_H = 9;                    // h
 constexpr int NAP = NA + 1;               // operator column padded to pairs
 constexpr int E_M = 10;                   // least-squares operator [ND][NAP] (column i of P, padded)
 constexpr int E_L = E_M + ND * NAP;       // linear candidates [3][2][3]
-constexpr int E_G = E_L + 18;             // indicator matrix, upper triangle (off-diagonal doubled), padded
-constexpr int NG = NA * (NA + 1) / 2 + 1;
-constexpr int E_V = E_G + NG;             // scaled vertices (xi, eta) x 3
-constexpr int E_MEAN = E_V + 6;           // m_alpha, padded
-constexpr int E_N = E_MEAN + NA + 1;
-static_assert(E_M % 2 == 0 && E_L % 2 == 0 && E_G % 2 == 0 && E_V % 2 == 0 && E_MEAN % 2 == 0 &&
-                  E_N % 2 == 0, "table regions start on pairs");
+constexpr int E_V = E_L + 18;             // scaled vertices (xi, eta) x 3
+constexpr int E_N = E_V + 6;
+static_assert(E_M % 2 == 0 && E_L % 2 == 0 && E_V % 2 == 0 && E_N % 2 == 0, "table regions start on pairs");
 
 // host index of entry e of cell c in a table of n cells
 inline size_t tab_index(int e, size_t c, size_t n) { return ((size_t)(e >> 1) * n + c) * 2 + (e & 1); }
 
-constexpr int EX[NA][2] = {{1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}, {3, 0}, {2, 1}, {1, 2}, {0, 3}};
-
-// d^(da+db) / dxi^da deta^db of xi^a eta^b
-double mono(int a, int b, int da, int db, double x, double y) {
-  if (da > a || db > b) return 0.0;
-  double c = 1.0;
-  for (int q = 0; q < da; ++q) c *= (double)(a - q);
-  for (int q = 0; q < db; ++q) c *= (double)(b - q);
-  for (int q = 0; q < a - da; ++q) c *= x;
-  for (int q = 0; q < b - db; ++q) c *= y;
-  return c;
-}
 
 // averages over a triangle of the nine monomials and of
 // their xi- and eta-derivatives, all at once, by the rule exact for degree
@@ -100,23 +87,6 @@ void tri_avgs(const double (&t)[3][2], double (&m)[NA], double (&mx)[NA], double
       my[q] += Wq[g] * py[q];
     }
   }
-}
-
-// degree-4 averages over a triangle (Dunavant's symmetric 6-point rule)
-template <typename F>
-double avg4(const double (&t)[3][2], F f) {
-  const double A[2] = {0.445948490915965, 0.091576213509771};
-  const double Wt[2] = {0.223381589678011, 0.109951743655322};
-  double s = 0.0;
-  for (int g = 0; g < 2; ++g)
-    for (int r = 0; r < 3; ++r) {
-      double bc[3] = {A[g], A[g], A[g]};
-      bc[r] = 1.0 - 2.0 * A[g];
-      const double x = bc[0] * t[0][0] + bc[1] * t[1][0] + bc[2] * t[2][0];
-      const double y = bc[0] * t[0][1] + bc[1] * t[1][1] + bc[2] * t[2][1];
-      s += Wt[g] * f(x, y);
-    }
-  return s;
 }
 
 // Least-squares operator P = A^+ (NA x ND) of the ND x NA matrix A (full
@@ -225,15 +195,39 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
   }
   const double IStau = 36.0 * av[5] * av[5] + 4.0 * av[6] * av[6] + 4.0 * av[7] * av[7] +
                        36.0 * av[8] * av[8];
+  double vv[6], vx[3], vy[3], mean[NA];
+  region(E_V, 3, vv);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    vx[r] = vv[2 * r];
+    vy[r] = vv[2 * r + 1];
+  }
+  // means of the monomials and IS~^H by Dunavant's degree-4 rule on the cell
   double Q = 0.0;
+#pragma unroll
+  for (int q = 0; q < NA; ++q) mean[q] = 0.0;
   {
-    double G[NG];
-    region(E_G, NG / 2, G);
-    int g = 0;
+    const double A2[2] = {0.445948490915965, 0.091576213509771};
+    const double W2[2] = {0.223381589678011, 0.109951743655322};
 #pragma unroll
-    for (int p = 0; p < NA; ++p)
+    for (int gq = 0; gq < 2; ++gq)
 #pragma unroll
-      for (int q = p; q < NA; ++q, ++g) Q = fma(G[g] * av[p], av[q], Q);
+      for (int r = 0; r < 3; ++r) {
+        const double b0 = r == 0 ? 1.0 - 2.0 * A2[gq] : A2[gq];
+        const double b1 = r == 1 ? 1.0 - 2.0 * A2[gq] : A2[gq];
+        const double b2 = r == 2 ? 1.0 - 2.0 * A2[gq] : A2[gq];
+        const double X = b0 * vx[0] + b1 * vx[1] + b2 * vx[2], Y = b0 * vy[0] + b1 * vy[1] + b2 * vy[2];
+        const double XX = X * X, XY = X * Y, YY = Y * Y, w = W2[gq];
+        const double ph[NA] = {X, Y, XX, XY, YY, XX * X, XX * Y, X * YY, YY * Y};
+#pragma unroll
+        for (int q = 0; q < NA; ++q) mean[q] = fma(w, ph[q], mean[q]);
+        const double dx = av[0] + 2.0 * av[2] * X + av[3] * Y + 3.0 * av[5] * XX + 2.0 * av[6] * XY + av[7] * YY;
+        const double dy = av[1] + av[3] * X + 2.0 * av[4] * Y + av[6] * XX + 2.0 * av[7] * XY + 3.0 * av[8] * YY;
+        const double dxx = 2.0 * av[2] + 6.0 * av[5] * X + 2.0 * av[6] * Y;
+        const double dxy = av[3] + 2.0 * av[6] * X + 2.0 * av[7] * Y;
+        const double dyy = 2.0 * av[4] + 2.0 * av[7] * X + 6.0 * av[8] * Y;
+        Q = fma(w, dx * dx + dy * dy + dxx * dxx + dxy * dxy + dyy * dyy, Q);
+      }
   }
   double Lk[18];
   region(E_L, 9, Lk);
@@ -272,14 +266,7 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
   }
   if (chi) chi[v * sn + c] = x;
   const double xm = 1.0 - x;
-  double vv[6], mean[NA + 1], vx[3], vy[3];
-  region(E_V, 3, vv);
-  region(E_MEAN, (NA + 1) / 2, mean);
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    vx[r] = vv[2 * r];
-    vy[r] = vv[2 * r + 1];
-  }
+
   const double t0 = 0.5 - 0.5 / 1.7320508075688772935, t1 = 0.5 + 0.5 / 1.7320508075688772935;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
@@ -408,26 +395,11 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
         for (int col = 0; col < 3; ++col)
           put(E_L + (kk * 2 + r) * 3 + col, inv[r][0] * At[0][col] + inv[r][1] * At[1][col]);
     }
-    // indicator matrix of the first and second derivatives over the cell
-    static const int L12[5][2] = {{1, 0}, {0, 1}, {2, 0}, {1, 1}, {0, 2}};
-    int g = 0;
-    for (int p = 0; p < NA; ++p)
-      for (int q = p; q < NA; ++q, ++g) {
-        const double val = avg4(own, [&](double x, double y) {
-          double s = 0.0;
-          for (const auto& l : L12)
-            s += mono(EX[p][0], EX[p][1], l[0], l[1], x, y) * mono(EX[q][0], EX[q][1], l[0], l[1], x, y);
-          return s;
-        });
-        put(E_G + g, p == q ? val : 2.0 * val);
-      }
-    put(E_G + NG - 1, 0.0);
     for (int v = 0; v < 3; ++v) {
       put(E_V + 2 * v, own[v][0]);
       put(E_V + 2 * v + 1, own[v][1]);
     }
-    for (int q = 0; q < NA; ++q) put(E_MEAN + q, mean[q]);
-    put(E_MEAN + NA, 0.0);
+
   }
   return GENO_OK;
 }
@@ -455,14 +427,16 @@ int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, co
 }
 
 // per cell and variable, as k_tri executes them: data entries 17, the
-// operator product 2 * 153, IS^tau 11, a^T G a 3 * 45, IS^H 1, linear
-// candidates 3 * (2 * 5 + 3), IS^L 4, alpha 13, chi 2 (tanh counted 1),
-// weights 3 * 4 + 2 + 1, blended gradient 3 * 4, and per Gauss point
+// operator product 2 * 153, IS^tau 11, the means and IS~^H over the six
+// quadrature points 6 * 92 (point 10, monomials 7, means 18, first
+// derivatives 26, second derivatives 20, squares and sum 11), IS^H 1,
+// linear candidates 3 * (2 * 5 + 3), IS^L 4, alpha 13, chi 2 (tanh counted
+// 1), weights 3 * 4 + 2 + 1, blended gradient 3 * 4, and per Gauss point
 // (6): point 6, monomials 7, derivatives 9, cubic 9 * 2 + 2 * 2 * 9, linear
 // blend 3 * 4, output 3 * 3
 double geno_tri_op_cost(void) {
   const double per_point = 6 + 7 + 9 + (9 * 2 + 2 * 2 * 9) + 3 * 4 + 3 * 3;
-  return 17 + 2 * 153 + 11 + 3 * 45 + 1 + 3 * (2 * 5 + 3) + 4 + 13 + 2 + (3 * 4 + 2 + 1) + 3 * 4 +
+  return 17 + 2 * 153 + 11 + 6 * 92 + 1 + 3 * (2 * 5 + 3) + 4 + 13 + 2 + (3 * 4 + 2 + 1) + 3 * 4 +
          6 * per_point;
 }
 

@@ -153,7 +153,7 @@ def test_triangle_table_host_side(so):
     from paper_2507_20461_amd import geno_tri as T
     from paper_2507_20461_amd import inputs
     nt = T.lib().geno_tri_table_doubles()
-    assert nt == 260
+    assert nt == 204
     mesh = inputs.tri_mesh(8, 8, 3)
     n = 2 * 8 * 8
     flat = T.build_table(mesh)
@@ -172,7 +172,14 @@ def test_triangle_table_host_side(so):
     d = np.concatenate([W[0, idx] - W[0, c], h * dW[:, 0, c], (h * dW[:, 0, idx[:3]]).T.ravel()])
     a = ops[10:10 + 170, c].reshape(17, 10)[:, :9].T @ d
     xc = mesh["xv"][c].mean(axis=0)
-    mean = ops[250:259, c]
+    # the cell's monomial means (the kernel forms them), by the rule with
+    # vertex, edge-midpoint and centroid weights 1/20, 2/15, 9/20 (exact for cubics)
+    tri = (mesh["xv"][c] - xc) / h
+    pts = [tri[0], tri[1], tri[2], (tri[0] + tri[1]) / 2, (tri[1] + tri[2]) / 2, (tri[2] + tri[0]) / 2,
+           tri.mean(axis=0)]
+    wts = [1 / 20] * 3 + [2 / 15] * 3 + [9 / 20]
+    mono = lambda X, Y: np.array([X, Y, X * X, X * Y, Y * Y, X ** 3, X * X * Y, X * Y * Y, Y ** 3])
+    mean = sum(w * mono(*p) for w, p in zip(wts, pts))
     for e in range(3):
         p, q = mesh["xv"][c][e], mesh["xv"][c][(e + 1) % 3]
         for t in (0.5 - 0.5 / math.sqrt(3), 0.5 + 0.5 / math.sqrt(3)):
