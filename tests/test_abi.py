@@ -198,3 +198,17 @@ def test_triangle_table_host_side(so):
     flip["xv"] = mesh["xv"][:, ::-1].copy()
     with pytest.raises(G.GenoError):
         T.build_table(flip)
+
+
+def test_triangle_reconstruct_rejects_bad_arguments(so):
+    # argument checks happen on the host, before any launch
+    from paper_2507_20461_amd import geno_gks as G
+    from paper_2507_20461_amd import geno_tri as T
+    L = T.lib()
+    fake = 256   # never dereferenced: every call below fails its checks first
+    assert L.geno_tri_reconstruct(10, 5, fake, fake, fake, fake, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 0, fake, fake, fake, fake, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(0, 4, fake, fake, fake, fake, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 4, None, fake, fake, fake, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 4, fake, fake, fake, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_build(0, None, None, None, None) == G.GENO_EINVAL
