@@ -183,6 +183,33 @@ def robustness_runs(G, inputs, np, torch):
                     rec["mass_energy_drift"] = [float(abs(Wn[k].sum() - W[k].sum()) / np.abs(W[k]).sum())
                                                 for k in (0, 2)]
             out.setdefault(name, []).append(rec)
+    # 2-D: strong seeded quadrant jumps on 256^2 (transmissive) to t = 0.2,
+    # both variable sets at the paper's CFL
+    for seed in (0, 1, 2):
+        W2, dW2, _ = inputs.quadrants_2d_strong(256, 256, seed)
+        for var in (cons, char):
+            grid = G.Grid(2, 256, 256, bc=G.BC_TRANSMISSIVE, cfl=0.5, variables=var)
+            Wd, dWd = grid.to_device(W2), grid.to_device(dW2)
+            ws = grid.workspace()
+            dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+            t, nst, guard, failed = 0.0, 0, 0, None
+            t0 = time.perf_counter()
+            while t < 0.2 and nst < 5000:
+                try:
+                    st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+                except G.GenoError as e:
+                    failed = "step %d, t = %.5f: %s" % (nst + 1, t, e)
+                    break
+                t += float(dts.item())
+                nst += 1
+                guard += st.guard
+            Wn = grid.interior(Wd)
+            rec = {"seed": seed, "cfl": 0.5, "variables": ("conservative", "characteristic")[var],
+                   "steps": nst, "t": round(t, 6), "guard": guard,
+                   "wall_s": round(time.perf_counter() - t0, 3), "failed": failed}
+            if not failed:
+                rec["rho_range"] = [float(Wn[0].min()), float(Wn[0].max())]
+            out.setdefault("quadrants_2d_strong_256", []).append(rec)
     return out
 
 

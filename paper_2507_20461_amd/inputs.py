@@ -123,6 +123,17 @@ def quadrants_2d(nx: int, ny: int, seed: int, gamma: float = GAMMA):
     return W, np.zeros((8, ny, nx)), states
 
 
+def quadrants_2d_strong(nx: int, ny: int, seed: int, gamma: float = GAMMA):
+    """Four seeded constant quadrants with strong jumps (robustness runs):
+    rho ~ U[0.1, 1.5], p ~ U[0.03, 1.5], u, v ~ U[-1.2, 1.2] per quadrant,
+    drawn in the order of quadrant_states."""
+    rng = np.random.default_rng(seed)
+    states = [(rng.uniform(0.1, 1.5), rng.uniform(-1.2, 1.2), rng.uniform(-1.2, 1.2), rng.uniform(0.03, 1.5))
+              for _ in range(4)]
+    (rho, u, v, p), _ = _quadrant_fields(nx, ny, states)
+    return _cons_2d(rho, u, v, p, gamma), np.zeros((8, ny, nx)), states
+
+
 _GL4_X = np.array([-0.8611363115940526, -0.3399810435848563, 0.3399810435848563, 0.8611363115940526])
 _GL4_W = np.array([0.3478548451374538, 0.6521451548625461, 0.6521451548625461, 0.3478548451374538])
 
