@@ -582,6 +582,46 @@ def test_characteristic_2d_shadowed(G, oracle, kind, bc, nx, ny, steps):
     assert max(worst) < TOL, worst
 
 
+@pytest.mark.parametrize("char", [False, True], ids=["cons", "char"])
+def test_strong_quadrants_2d_shadowed(G, oracle, char):
+    # strong seeded jumps (Mach up to about 5): every GPU step of the first 10
+    # against the oracle's step from the same state, both variable sets
+    _say("strong quadrants shadow", "char" if char else "cons")
+    W, dW, _ = inputs.quadrants_2d_strong(48, 40, 0)
+    grid = _grid(G, W, 1, variables=int(char))
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prm = _oprm(oracle, 2, 1, characteristic=char)
+    worst = [0.0, 0.0]
+    for n in range(10):
+        W0, dW0 = grid.interior(Wd), grid.interior(dWd)
+        st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, dy=grid.dy)
+        gW, gdW = grid.interior(Wd), grid.interior(dWd)
+        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        assert st.guard == og and st.nonfinite == 0, (n, st.guard, og)
+    _say("worst W %.3e dW %.3e" % tuple(worst))
+    assert max(worst) < TOL, worst
+
+
+def test_characteristic_2d_strong_quadrants_run(G):
+    # the seeded strong-quadrant state that loses positivity at step 57 with
+    # conservative variables reaches t = 0.2 with characteristic ones
+    W, dW, _ = inputs.quadrants_2d_strong(256, 256, 0)
+    grid = G.Grid(2, 256, 256, bc=G.BC_TRANSMISSIVE, cfl=0.5, variables=G.VARS_CHARACTERISTIC)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t, n = 0.0, 0
+    while t < 0.2 and n < 2000:
+        G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
+        t += float(dts.item())
+        n += 1
+    Wn = grid.interior(Wd)
+    assert t >= 0.2 and np.all(np.isfinite(Wn)) and Wn[0].min() > 0
+
+
 def test_characteristic_2d_y_invariant_equals_1d(G):
     # y-invariant data with V = 0: every row of the 2-D characteristic run
     # is the 1-D characteristic run (K of the BGK model is set so that both
