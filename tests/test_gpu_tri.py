@@ -1,7 +1,9 @@
 """The GENO reconstruction on triangles through the C ABI (geno_tri.h)
 against the oracle, element by element: every cell of small periodic meshes
 (ragged sizes, several work-groups and a partial last one), smooth and
-discontinuous Euler data and a scalar field, and sampled cells of the
+discontinuous Euler data and a scalar field, the smallest periodic meshes
+(2 x 2 lattice squares, whose stencils hold periodic images of the same
+cells), and sampled cells of the
 benchmark's 2 x 512^2 mesh in its launch configuration.
 
 Tolerances from the arithmetic. Both sides solve the same least-squares
@@ -75,14 +77,15 @@ def _compare(O, mesh, W, dW, got, gchi, cells=None):
 
 
 @pytest.mark.parametrize("nx,ny,kind,seed", [(6, 5, "smooth", 1), (9, 7, "jumps", 2), (16, 12, "smooth", 3),
-                                             (13, 11, "jumps", 4)])
+                                             (13, 11, "jumps", 4), (2, 2, "jumps", 5), (3, 2, "smooth", 6),
+                                             (2, 5, "jumps", 7)])
 def test_reconstruct_matches_oracle(T, O, nx, ny, kind, seed):
     _say("tri reconstruct", nx, ny, kind, seed)
     mesh = inputs.tri_mesh(nx, ny, seed)
     W, dW = (inputs.tri_euler_smooth if kind == "smooth" else inputs.tri_euler_jumps)(mesh, seed)
     got, gchi = _run(T, mesh, W, dW)
     rchi = _compare(O, mesh, W, dW, got, gchi)
-    if kind == "jumps":
+    if kind == "jumps" and nx > 2:
         assert (rchi < 0.5).mean() > 0.2       # the low-order branch is exercised
 
 
