@@ -149,3 +149,32 @@ def test_eno_at_a_jump(T):
             assert chi[c, 0] < 1e-6
             # the two candidates on the own side are flat and take the weight
             assert np.abs(out[c, ..., 0, 0] - W[0, c]).max() < 1e-9
+
+
+def test_quarter_turn_symmetry(T):
+    # turning mesh and data by 90 degrees, (x, y) -> (-y, x), turns every
+    # state: the momenta and gradients rotate, the rest is unchanged (the
+    # indicators sum each partial derivative once, which a quarter turn
+    # permutes up to sign)
+    mesh = inputs.tri_mesh(6, 5, 8)
+    W, dW = inputs.tri_euler_jumps(mesh, 8)
+    rot = lambda a: np.stack([-a[..., 1], a[..., 0]], axis=-1)
+    m2 = {"xv": rot(mesh["xv"]), "nbr": mesh["nbr"], "shift": rot(mesh["shift"]), "nx": 6, "ny": 5}
+    W2 = np.stack([W[0], -W[2], W[1], W[3]])
+    # gradient of the turned field at the turned point: (d/dx', d/dy') = (-d/dy, d/dx)
+    g = np.stack([-dW[1], dW[0]])
+    dW2 = np.stack([g[:, 0], -g[:, 2], g[:, 1], g[:, 3]], axis=1)
+    out, chi, _ = T.reconstruct(mesh, W, dW)
+    out2, chi2, _ = T.reconstruct(m2, W2, dW2)
+    assert np.allclose(chi2[:, [0, 3]], chi[:, [0, 3]], atol=1e-9)
+    assert np.allclose(chi2[:, 1], chi[:, 2], atol=1e-9) and np.allclose(chi2[:, 2], chi[:, 1], atol=1e-9)
+    # values: momenta turned
+    v, v2 = out[..., 0], out2[..., 0]
+    assert np.allclose(v2[..., [0, 3]], v[..., [0, 3]], atol=1e-12)
+    assert np.allclose(v2[..., 1], -v[..., 2], atol=1e-12) and np.allclose(v2[..., 2], v[..., 1], atol=1e-12)
+    # h-gradients: (d/dx', d/dy') = (-d/dy, d/dx), then the momenta turned
+    gx2, gy2 = out2[..., 1], out2[..., 2]
+    tx, ty = -out[..., 2], out[..., 1]
+    assert np.allclose(gx2[..., [0, 3]], tx[..., [0, 3]], atol=1e-11)
+    assert np.allclose(gy2[..., [0, 3]], ty[..., [0, 3]], atol=1e-11)
+    assert np.allclose(gx2[..., 1], -tx[..., 2], atol=1e-11) and np.allclose(gx2[..., 2], tx[..., 1], atol=1e-11)
