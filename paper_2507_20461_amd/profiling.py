@@ -3,7 +3,7 @@
 Usage on a GPU machine (from the repository root)::
 
     python -m paper_2507_20461_amd.profiling run       # kernel trace + counter passes,
-                                                       # summaries into gpurun_out/profiles
+                                                       # summaries into <OUT>/profiles
     python -m paper_2507_20461_amd.profiling summarize # summaries into profiles/
 
 Each counter pass is its own rocprofv3 run (FETCH_SIZE, WRITE_SIZE, VALU
@@ -29,7 +29,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-OUT = os.path.join(ROOT, "gpurun_out")
+OUT = os.path.join(ROOT, "gpurun_out")   # raw output folder of the runs (not committed)
 PROFILES = os.path.join(ROOT, "profiles")
 CAL_BYTES = 256 * 1024 * 1024
 CAL_ELEMS = CAL_BYTES // 8
