@@ -46,6 +46,9 @@ enum {
   PI_TAUC1, PI_TAUC2, PI_CFL, PI_BCXL, PI_BCXH, PI_BCYL, PI_BCYH,
   PI_GHOST,     /* 24 values, 1-D fixed ends: [end][layer][W (3), dW (3)] */
   PI_CHAR = PI_GHOST + 24,   /* 1 = characteristic-variable reconstruction (normal step) */
+  PI_GUPD,   /* time stepping of the gradients: 0 the two-stage fourth-order
+                structure on the interface values (default), 1 the BGK
+                interface state at dt/2 of each stage (earlier reading) */
   PI_COUNT
 };
 
@@ -55,6 +58,7 @@ typedef struct {
                           x-lo, x-hi, y-lo, y-hi */
   double ghost[2][2][6];  /* fixed ends: [end][layer 0 = next to the grid][W, dW] */
   int characteristic;     /* reconstruct characteristic variables in the normal step */
+  int gupd;               /* gradient update reading (PI_GUPD) */
   int ndim, nx, ny;
   double dx, dy;
   double K;            /* internal degrees of freedom of the BGK model */
@@ -72,6 +76,7 @@ static void cfg_from(ocfg *c, int ndim, int nx, int ny, double dx, double dy,
     for (int l = 0; l < 2; ++l)
       for (int q = 0; q < 6; ++q) c->ghost[e][l][q] = p[PI_GHOST + (e * 2 + l) * 6 + q];
   c->characteristic = (int)p[PI_CHAR];
+  c->gupd = (int)p[PI_GUPD];
   c->ndim = ndim; c->nx = nx; c->ny = (ndim == 1) ? 1 : ny;
   c->dx = dx; c->dy = dy;
   /* Internal degrees of freedom so that gamma = (K + D + 2)/(K + D) with
@@ -155,9 +160,10 @@ static long double avg_dmono(int k, long double a, long double b) {
  * the degree-7 polynomial whose averages and averaged h-scaled derivatives
  * match those of the four cells. Coordinate y = (x - x_{j+1/2})/h, cell j-1+m
  * occupies [m-2, m-1]. Data order: (Q_{-1}, G_{-1}, Q_0, G_0, Q_1, G_1, Q_2, G_2),
- * G = h * (cell-averaged derivative). H_val / H_der: weights of the face
- * value and of h times the face derivative. */
-static double H_val[8], H_der[8];
+ * G = h * (cell-averaged derivative). H_val / H_der / H_d2: weights of the
+ * face value, of h times the face derivative and of h^2 times the second
+ * derivative. */
+static double H_val[8], H_der[8], H_d2[8];
 
 /* Low-order sub-stencil quadratics p_k (Sec. 4.2, S_1 = {j-1, j} with the
  * gradient of cell j-1, S_2 = {j-1, j, j+1}, S_3 = {j, j+1, j+2}) for the
@@ -179,7 +185,7 @@ static int build_ops(void) {
   /* p^7 */
   {
     long double A[64], rhs[8];
-    double Hv[8], Hd[8];
+    double Hv[8], Hd[8], H2[8];
     for (int col = 0; col < 8; ++col) {
       /* column col of the inverse: solve with unit right-hand side */
       for (int m = 0; m < 4; ++m) {
@@ -193,9 +199,11 @@ static int build_ops(void) {
       if (solve_ld(8, A, rhs)) return -1;
       Hv[col] = (double)rhs[0];           /* p(0) */
       Hd[col] = (double)rhs[1];           /* h p'(0) */
+      H2[col] = (double)(2.0L * rhs[2]);  /* h^2 p''(0) */
     }
     memcpy(H_val, Hv, sizeof Hv);
     memcpy(H_der, Hd, sizeof Hd);
+    memcpy(H_d2, H2, sizeof H2);
   }
   /* quadratics */
   for (int si = 0; si < 2; ++si) {
@@ -269,12 +277,15 @@ static double path_function(const ocfg *P, double IStau, double ISH, double ISL)
 
 /* dat: Q_{c-2}, G_{c-2}, ..., Q_{c+2}, G_{c+2} about the reconstructing cell
  * c; si = 0 for the left state (face at xi = +1/2), 1 for the right state
- * (face at xi = -1/2). qH, hqH: shared linear value and h * derivative.
- * Output: value, h * derivative and chi at the face. */
+ * (face at xi = -1/2). qH, hqH, h2qH: shared linear value, h * derivative and
+ * h^2 * second derivative. Output: value, h * derivative, h^2 * second
+ * derivative and chi at the face. The second derivative follows the blend of
+ * Eq. (3) with the same weights (the quadratics' second derivatives 2 c_2 in
+ * the low-order part); the time stepping of the gradients uses it. */
 static void geno_side(const ocfg *P, const double dat[10], int si, double qH, double hqH,
-                      double *val, double *hder, double *chi_out) {
+                      double h2qH, double *val, double *hder, double *h2der, double *chi_out) {
   double xf = (si == 0) ? 0.5 : -0.5;
-  double c[3][3], IS[3], pv[3], pd[3];
+  double c[3][3], IS[3], pv[3], pd[3], p2[3];
   for (int k = 0; k < 3; ++k) {
     for (int q = 0; q < 3; ++q) {
       double s = 0.0;
@@ -284,6 +295,7 @@ static void geno_side(const ocfg *P, const double dat[10], int si, double qH, do
     IS[k] = is_quadratic(c[k]);
     pv[k] = c[k][0] + c[k][1] * xf + c[k][2] * xf * xf;
     pd[k] = c[k][1] + 2.0 * c[k][2] * xf;
+    p2[k] = 2.0 * c[k][2];
   }
   /* Eq. (7) and Eq. (9): structured-mesh IS^H and IS^L */
   double ISH = IS[0], ISL = IS[0];
@@ -294,23 +306,28 @@ static void geno_side(const ocfg *P, const double dat[10], int si, double qH, do
   /* Eq. (8): ENO combination of the sub-stencil polynomials */
   double wt[3], wsum = 0.0;
   for (int k = 0; k < 3; ++k) { wt[k] = P->d[k] / pow(IS[k] + P->eps, P->rL); wsum += wt[k]; }
-  double qL = 0.0, hqL = 0.0;
-  for (int k = 0; k < 3; ++k) { qL += (wt[k] / wsum) * pv[k]; hqL += (wt[k] / wsum) * pd[k]; }
-  /* Eq. (3) and Eq. (13), same weights for the derivative */
+  double qL = 0.0, hqL = 0.0, h2qL = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    qL += (wt[k] / wsum) * pv[k]; hqL += (wt[k] / wsum) * pd[k]; h2qL += (wt[k] / wsum) * p2[k];
+  }
+  /* Eq. (3) and Eq. (13), same weights for the derivatives */
   *val = chi * qH + (1.0 - chi) * qL;
   *hder = chi * hqH + (1.0 - chi) * hqL;
+  *h2der = chi * h2qH + (1.0 - chi) * h2qL;
   *chi_out = chi;
 }
 
 /* Full GENO at face j+1/2 for one component. q[0..3] = averages of cells
- * j-1..j+2 (stencil S_0), g[0..3] = their h-scaled averaged derivatives. */
+ * j-1..j+2 (stencil S_0), g[0..3] = their h-scaled averaged derivatives.
+ * out_l / out_r: value, h * derivative, chi, h^2 * second derivative. */
 static void geno_face(const ocfg *P, const double q[4], const double g[4],
-                      double out_l[3], double out_r[3]) {
+                      double out_l[4], double out_r[4]) {
   /* linear part: one polynomial per face, shared by both sides (Sec. 4.2) */
-  double qH = 0.0, hqH = 0.0;
+  double qH = 0.0, hqH = 0.0, h2qH = 0.0;
   for (int m = 0; m < 4; ++m) {
     qH += H_val[2 * m] * q[m] + H_val[2 * m + 1] * g[m];
     hqH += H_der[2 * m] * q[m] + H_der[2 * m + 1] * g[m];
+    h2qH += H_d2[2 * m] * q[m] + H_d2[2 * m + 1] * g[m];
   }
   /* data about the reconstructing cell: left state uses cells j-2..j+2
    * (j-2 carries zero weight), right state cells j-1..j+3 (j+3 zero weight) */
@@ -319,8 +336,8 @@ static void geno_face(const ocfg *P, const double q[4], const double g[4],
     dl[2 * (m + 1)] = q[m]; dl[2 * (m + 1) + 1] = g[m];
     dr[2 * m] = q[m]; dr[2 * m + 1] = g[m];
   }
-  geno_side(P, dl, 0, qH, hqH, &out_l[0], &out_l[1], &out_l[2]);
-  geno_side(P, dr, 1, qH, hqH, &out_r[0], &out_r[1], &out_r[2]);
+  geno_side(P, dl, 0, qH, hqH, h2qH, &out_l[0], &out_l[1], &out_l[3], &out_l[2]);
+  geno_side(P, dr, 1, qH, hqH, h2qH, &out_r[0], &out_r[1], &out_r[3], &out_r[2]);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -441,10 +458,11 @@ static void fill_ghosts(const ocfg *P, gstate *g) {
 /* ---------------------------------------------------------------------- */
 /* Polynomials in (u, v, z) with z = xi^2 (sum of squared internal
  * velocities), stored as a list of terms c * u^i v^j z^k.
- * Degree bounds: u <= 7, v <= 5, z <= 2. */
+ * Degree bounds: u <= 7, v <= 7, z <= 3 (the second time derivative of the
+ * interface state needs moments of psi times degree-5 polynomials). */
 #define DU 8
-#define DV 6
-#define DZ 3
+#define DV 8
+#define DZ 4
 #define MAXT 128
 typedef struct { int n; unsigned char e[MAXT][3]; double c[MAXT]; } poly;
 
@@ -495,9 +513,9 @@ static void moments(double U, double V, double lam, double K, int half, int has_
     for (int n = 0; n + 2 < DV; ++n)
       m->mv[n + 2] = V * m->mv[n + 1] + (n + 1) / (2.0 * lam) * m->mv[n];
   }
+  /* <z^n> over the K internal degrees of freedom: prod_{i<n} (K + 2i) / (2 lam)^n */
   m->mz[0] = 1.0;
-  m->mz[1] = K / (2.0 * lam);
-  m->mz[2] = K * (K + 2.0) / (4.0 * lam * lam);
+  for (int n = 1; n < DZ; ++n) m->mz[n] = m->mz[n - 1] * (K + 2.0 * (n - 1)) / (2.0 * lam);
 }
 
 static double poly_moment(const poly *p, const mtab *m) {
@@ -591,17 +609,111 @@ static void time_slope(const ocfg *P, const prim *pr, const double *a, const dou
   micro_slope(P, pr, rhs, At);
 }
 
+/* (a.psi)(b.psi) and u (a.psi) / v (a.psi) as polynomials */
+static void prod_poly(const poly *a, const poly *b, poly *out) { poly_mul(a, b, out); }
+static void u_times(const poly *a, poly *out) {
+  poly u1; poly_zero(&u1); poly_add_term(&u1, 1, 0, 0, 1.0); poly_mul(a, &u1, out);
+}
+static void v_times(const poly *a, poly *out) {
+  poly v1; poly_zero(&v1); poly_add_term(&v1, 0, 1, 0, 1.0); poly_mul(a, &v1, out);
+}
+
+/* Second time derivative of the equilibrium state at the interface (Euler
+ * level; the time stepping of the gradients applies the two-stage
+ * fourth-order structure to the interface values and needs it). The
+ * equilibrium g = rho_c g~ of W_c varies in space and time with micro-slopes:
+ * d_x g = g a, d_y g = g b, d_t g = g A, and
+ *   d_x (g a) = g (a a + a_x),  d_y (g a) = g (b a + a_y),  a_y = b_x, ...
+ * Taking moments, with M x = <x psi> over g~:
+ *   M a_x = W_xx / rho - <a a psi>, M a_y = W_xy / rho - <a b psi>,
+ *   M b_y = W_yy / rho - <b b psi>;
+ *   M A = -<(u a + v b) psi> (compatibility);
+ *   M A_x = -<(u (a a + a_x) + v (a b + b_x)) psi> - <a A psi>,
+ *   M A_y = -<(u (a b + a_y) + v (b b + b_y)) psi> - <b A psi>
+ * (the x and y derivatives of the compatibility condition), and
+ *   W_tt = -d_x <u psi g A> - d_y <v psi g A>
+ *        = -rho <(u (a A + A_x) + v (b A + A_y)) psi>.
+ * ac, bc, Ac: the equilibrium micro-slopes; sxx, sxy, syy: physical second
+ * derivatives (face frame, x normal). 1-D drops every v and y term. */
+static void equilibrium_wtt(const ocfg *P, const prim *pc, const double *ac, const double *bc,
+                            const double *Ac, const double *sxx, const double *sxy,
+                            const double *syy, double *Wtt) {
+  int nv = P->nv, has_v = (nv == 4);
+  mtab mc; moments(pc->U, pc->V, pc->lam, P->K, 0, has_v, &mc);
+  poly pa, pb, pA, aa, ab, bb, aA, bA, tmp, t2, sum;
+  slope_poly(nv, ac, &pa);
+  slope_poly(nv, Ac, &pA);
+  prod_poly(&pa, &pa, &aa);
+  prod_poly(&pa, &pA, &aA);
+  double rhs[4] = {0, 0, 0, 0}, ax[4], ay[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0}, Ax[4];
+  double Ay[4] = {0, 0, 0, 0};
+  double m1[4], m2[4];
+  /* a_x */
+  moment_vec(nv, &aa, &mc, m1);
+  for (int k = 0; k < nv; ++k) rhs[k] = sxx[k] / pc->rho - m1[k];
+  micro_slope(P, pc, rhs, ax);
+  if (has_v) {
+    slope_poly(nv, bc, &pb);
+    prod_poly(&pa, &pb, &ab);
+    prod_poly(&pb, &pb, &bb);
+    prod_poly(&pb, &pA, &bA);
+    moment_vec(nv, &ab, &mc, m1);
+    for (int k = 0; k < nv; ++k) rhs[k] = sxy[k] / pc->rho - m1[k];
+    micro_slope(P, pc, rhs, ay);                 /* = b_x */
+    moment_vec(nv, &bb, &mc, m1);
+    for (int k = 0; k < nv; ++k) rhs[k] = syy[k] / pc->rho - m1[k];
+    micro_slope(P, pc, rhs, by);
+  }
+  poly pax, pay, pby;
+  slope_poly(nv, ax, &pax);
+  /* A_x */
+  sum = aa; poly_add(&sum, &pax, 1.0); u_times(&sum, &tmp);
+  if (has_v) {
+    slope_poly(nv, ay, &pay);
+    slope_poly(nv, by, &pby);
+    t2 = ab; poly_add(&t2, &pay, 1.0); v_times(&t2, &sum); poly_add(&tmp, &sum, 1.0);
+  }
+  poly_add(&tmp, &aA, 1.0);
+  moment_vec(nv, &tmp, &mc, m1);
+  for (int k = 0; k < nv; ++k) rhs[k] = -m1[k];
+  micro_slope(P, pc, rhs, Ax);
+  if (has_v) {
+    /* A_y */
+    sum = ab; poly_add(&sum, &pay, 1.0); u_times(&sum, &tmp);
+    t2 = bb; poly_add(&t2, &pby, 1.0); v_times(&t2, &sum); poly_add(&tmp, &sum, 1.0);
+    poly_add(&tmp, &bA, 1.0);
+    moment_vec(nv, &tmp, &mc, m1);
+    for (int k = 0; k < nv; ++k) rhs[k] = -m1[k];
+    micro_slope(P, pc, rhs, Ay);
+  }
+  /* W_tt */
+  poly pAx, pAy;
+  slope_poly(nv, Ax, &pAx);
+  sum = aA; poly_add(&sum, &pAx, 1.0); u_times(&sum, &tmp);
+  if (has_v) {
+    slope_poly(nv, Ay, &pAy);
+    t2 = bA; poly_add(&t2, &pAy, 1.0); v_times(&t2, &sum); poly_add(&tmp, &sum, 1.0);
+  }
+  moment_vec(nv, &tmp, &mc, m2);
+  for (int k = 0; k < nv; ++k) Wtt[k] = -pc->rho * m2[k];
+}
+
 /* Integrated flux over [0, delta] and the interface state at t = delta of
  * the BGK solution
  *   f = (1 - e) g0 + ((t+tau) e - tau)(abar u + bbar v) g0 + (t - tau(1 - e)) Abar g0
  *     + e sum_s H_s g_s [1 - (t + tau)(a_s u + b_s v) - tau A_s],  e = exp(-t/tau)
  * at one point of a face. Inputs are in the face frame (normal velocity
  * first). dn*, dt*: physical normal / tangential derivatives of the left and
- * right conserved states. Outputs the fitted F, dF/dt (from delta = dt/2
- * and dt) and W(dt/2). */
+ * right conserved states; snn, snt, stt: physical second derivatives of the
+ * point (normal-normal, normal-tangential, tangential-tangential; 1-D: snn
+ * only), averaged over the sides. Outputs the fitted F, dF/dt (from delta =
+ * dt/2 and dt), the interface state W(dt/2) and W(dt) of the solution, and
+ * the equilibrium second time derivative W_tt. */
 static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
                       const double *dnl, const double *dnr, const double *dtl,
-                      const double *dtr, double dt, double *F, double *Ft, double *Wi) {
+                      const double *dtr, const double *snn, const double *snt,
+                      const double *stt, double dt, double *F, double *Ft, double *Wh,
+                      double *Wf, double *Wtt) {
   int nv = P->nv, has_v = (nv == 4);
   double K = P->K;
   prim pl = to_prim(P, Wl), pr = to_prim(P, Wr);
@@ -639,6 +751,7 @@ static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
   time_slope(P, &pl, al, bl, Al);
   time_slope(P, &pr, ar, br, Ar);
   time_slope(P, &pc, ac, bc, Ac);
+  equilibrium_wtt(P, &pc, ac, bc, Ac, snn, snt, stt, Wtt);
 
   /* moment vectors */
   poly u1, v1, pa, pb, t1, t2, uone;
@@ -715,9 +828,9 @@ static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
     F[k] = (4.0 * Fd[0][k] - Fd[1][k]) / dt;
     Ft[k] = 4.0 * (Fd[1][k] - 2.0 * Fd[0][k]) / (dt * dt);
   }
-  /* interface state at t = dt/2 */
-  {
-    double del = 0.5 * dt, e, em, k1, k2, k3, k4, k5;
+  /* interface state at t = dt/2 and t = dt */
+  for (int q = 0; q < 2; ++q) {
+    double del = (q == 0) ? 0.5 * dt : dt, e, em, k1, k2, k3, k4, k5;
     if (tau > 0.0) {
       e = exp(-del / tau); em = -expm1(-del / tau);
       k1 = em; k2 = (del + tau) * e - tau; k3 = del - tau * em;
@@ -725,8 +838,9 @@ static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
     } else {
       e = 0.0; em = 1.0; k1 = 1.0; k2 = 0.0; k3 = del; k4 = 0.0; k5 = 0.0;
     }
+    double *Wo = (q == 0) ? Wh : Wf;
     for (int k = 0; k < nv; ++k) {
-      Wi[k] = pc.rho * (k1 * c_1[k] + k2 * c_s[k] + k3 * c_A[k])
+      Wo[k] = pc.rho * (k1 * c_1[k] + k2 * c_s[k] + k3 * c_A[k])
             + e * (pl.rho * (l_1[k] - k4 * l_s[k] - k5 * l_A[k])
                  + pr.rho * (r_1[k] - k4 * r_s[k] - k5 * r_A[k]));
     }
@@ -749,7 +863,8 @@ static int admissible(const ocfg *P, const double *W) {
 
 /* Normal GENO for the face between cells (i, j) and (i+1, j) along x (dir 0)
  * or between (i, j) and (i, j+1) along y (dir 1) in ghosted coordinates.
- * out[side][quant][var]: quant 0 value, 1 h * normal derivative; chi[side][var]. */
+ * out[side][quant][var]: quant 0 value, 1 h * normal derivative, 2 h^2 * second
+ * normal derivative; chi[side][var]. */
 /* Characteristic variables (reading; the paper does not name the variables
  * it reconstructs): right eigenvectors of the Euler flux Jacobian in the
  * normal direction `dir` at the Roe average of the two cells at the face.
@@ -812,7 +927,7 @@ static int roe_eigen(const ocfg *P, int dir, const double *Wa, const double *Wb,
 }
 
 static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
-                        double out[2][2][4], double chi[2][4]) {
+                        double out[2][3][4], double chi[2][4]) {
   int nv = P->nv;
   double h = (dir == 0) ? P->dx : P->dy;
   double R[4][4], L[4][4];
@@ -824,7 +939,7 @@ static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
       Wb[v] = g->W[gidx(g, v, dir == 0 ? j : j + 1, dir == 0 ? i + 1 : i)];
     }
     if (!roe_eigen(P, dir, Wa, Wb, R, L)) {
-      double val[2][4], der[2][4];
+      double val[2][4], der[2][4], d2[2][4];
       for (int c = 0; c < nv; ++c) {
         double q[4] = {0, 0, 0, 0}, gg[4] = {0, 0, 0, 0};
         for (int m = -1; m <= 2; ++m) {
@@ -834,17 +949,20 @@ static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
             gg[m + 1] += L[c][v] * h * g->dW[gidx(g, dir * nv + v, jj, ii)];
           }
         }
-        double l[3], r[3];
+        double l[4], r[4];
         geno_face(P, q, gg, l, r);
-        val[0][c] = l[0]; der[0][c] = l[1]; chi[0][c] = l[2];
-        val[1][c] = r[0]; der[1][c] = r[1]; chi[1][c] = r[2];
+        val[0][c] = l[0]; der[0][c] = l[1]; chi[0][c] = l[2]; d2[0][c] = l[3];
+        val[1][c] = r[0]; der[1][c] = r[1]; chi[1][c] = r[2]; d2[1][c] = r[3];
       }
       for (int s = 0; s < 2; ++s)
         for (int v = 0; v < nv; ++v) {
-          double a0 = 0.0, a1 = 0.0;
-          for (int c = 0; c < nv; ++c) { a0 += R[v][c] * val[s][c]; a1 += R[v][c] * der[s][c]; }
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+          for (int c = 0; c < nv; ++c) {
+            a0 += R[v][c] * val[s][c]; a1 += R[v][c] * der[s][c]; a2 += R[v][c] * d2[s][c];
+          }
           out[s][0][v] = a0;
           out[s][1][v] = a1;
+          out[s][2][v] = a2;
         }
       return;
     }
@@ -856,10 +974,10 @@ static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
       q[m + 1] = g->W[gidx(g, v, jj, ii)];
       gg[m + 1] = h * g->dW[gidx(g, dir * nv + v, jj, ii)];
     }
-    double l[3], r[3];
+    double l[4], r[4];
     geno_face(P, q, gg, l, r);
-    out[0][0][v] = l[0]; out[0][1][v] = l[1]; chi[0][v] = l[2];
-    out[1][0][v] = r[0]; out[1][1][v] = r[1]; chi[1][v] = r[2];
+    out[0][0][v] = l[0]; out[0][1][v] = l[1]; out[0][2][v] = l[3]; chi[0][v] = l[2];
+    out[1][0][v] = r[0]; out[1][1][v] = r[1]; out[1][2][v] = r[3]; chi[1][v] = r[2];
   }
 }
 
@@ -870,8 +988,10 @@ static void normal_face(const ocfg *P, const gstate *g, int dir, int i, int j,
  * low-order one is the ENO combination (d = 1) of the two one-sided linear
  * polynomials; they are blended with the path function of Eq. (4)-(5) using
  * IS = h * int (p')^2 of each linear polynomial, IS^H = max, IS^L = min,
- * IS^tau = |IS_+ - IS_-|. Returns the value; *hder = h * tangential derivative. */
-static double tangential(const ocfg *P, const double phi[3], double eta, double *hder) {
+ * IS^tau = |IS_+ - IS_-|. Returns the value; *hder = h * tangential
+ * derivative, *chi_t = the blend weight. */
+static double tangential(const ocfg *P, const double phi[3], double eta, double *hder,
+                         double *chi_t) {
   double c[3];
   for (int q = 0; q < 3; ++q) c[q] = TQ[q][0] * phi[0] + TQ[q][1] * phi[1] + TQ[q][2] * phi[2];
   double vH = c[0] + c[1] * eta + c[2] * eta * eta;
@@ -884,7 +1004,23 @@ static double tangential(const ocfg *P, const double phi[3], double eta, double 
   double sL = (wm / (wm + wp)) * sm + (wp / (wm + wp)) * sp;
   double vL = phi[1] + eta * sL;
   *hder = chi * dH + (1.0 - chi) * sL;
+  if (chi_t) *chi_t = chi;
   return chi * vH + (1.0 - chi) * vL;
+}
+
+/* Second derivatives at the points of a face for the time stepping of the
+ * gradients (reading, 2-D; the paper gives no structured 2-D scheme): per
+ * side, h_t^2 d_tt = chi_t (phi_{j+1} - 2 phi_j + phi_{j-1}) (the second
+ * derivative of the tangential quadratic, weighted like its value; the
+ * low-order candidate is linear), and h_n h_t d_nt = chi_t (psi_{j+1} -
+ * psi_{j-1}) / 2 from the h-scaled normal derivatives psi of the three rows;
+ * h_n^2 d_nn is the normal step's value of the centre row. The point takes
+ * the mean of the two sides (the averaged slopes of the equilibrium part of
+ * the flux are taken the same way). */
+static void side_second(const double phi[3], const double psi[3], double chi_t, double *stt,
+                        double *snt) {
+  *stt = chi_t * (phi[2] - 2.0 * phi[1] + phi[0]);
+  *snt = chi_t * 0.5 * (psi[2] - psi[0]);
 }
 
 /* Gauss points of a face (reading of the 2-point rule on a face):
@@ -894,9 +1030,46 @@ static const double GAUSS_ETA[2] = {-0.28867513459481288225, 0.28867513459481288
 /* ---------------------------------------------------------------------- */
 /* One stage: fluxes, Lagrangian, interface states                         */
 /* ---------------------------------------------------------------------- */
-/* Per-face results for the stage: F, dF/dt and W_int (Gauss-averaged). */
+/* Point data of Gauss point gp on the 2-D face with normal-step results
+ * o[row t-1, t, t+1][side][quant][var] (x/y frame): per side the state, the
+ * h-scaled normal and tangential derivatives after the tangential step and
+ * the positivity guard, and the h-scaled second derivatives of the point
+ * (h_n^2 d_nn, h_n h_t d_nt, h_t^2 d_tt; zero when a side is guarded).
+ * (ci, cj)[side]: the own cells of the two sides. Returns the guard count. */
+static int face_point(const ocfg *P, const gstate *g, double o[3][2][3][4], int gp,
+                      const int ci[2], const int cj[2], double S[2][4], double Dn[2][4],
+                      double Dt[2][4], double Sec[3][4]) {
+  int nv = P->nv, guard = 0, ok[2];
+  double ss[2][3][4];
+  for (int side = 0; side < 2; ++side) {
+    for (int v = 0; v < nv; ++v) {
+      double phi[3] = {o[0][side][0][v], o[1][side][0][v], o[2][side][0][v]};
+      double psi[3] = {o[0][side][1][v], o[1][side][1][v], o[2][side][1][v]};
+      double chi_t;
+      S[side][v] = tangential(P, phi, GAUSS_ETA[gp], &Dt[side][v], &chi_t);
+      Dn[side][v] = o[1][side][1][v];
+      ss[side][0][v] = o[1][side][2][v];
+      side_second(phi, psi, chi_t, &ss[side][2][v], &ss[side][1][v]);
+    }
+    ok[side] = admissible(P, S[side]);
+    if (!ok[side]) {
+      ++guard;
+      for (int v = 0; v < nv; ++v) {
+        S[side][v] = g->W[gidx(g, v, cj[side], ci[side])]; Dn[side][v] = 0.0; Dt[side][v] = 0.0;
+      }
+    }
+  }
+  for (int q = 0; q < 3; ++q)
+    for (int v = 0; v < nv; ++v)
+      Sec[q][v] = (ok[0] && ok[1]) ? 0.5 * (ss[0][q][v] + ss[1][q][v]) : 0.0;
+  return guard;
+}
+
+/* Per-face results for the stage (Gauss-averaged): F, dF/dt, the interface
+ * state W(dt/2) and W(dt) of the BGK solution and the equilibrium second
+ * time derivative W_tt. */
 typedef struct {
-  double *F[2], *Ft[2], *Wi[2];   /* dir x / y: [nv][nfy][nfx] */
+  double *F[2], *Ft[2], *Wh[2], *Wf[2], *W2[2];   /* dir x / y: [nv][nfy][nfx] */
   int nfx[2], nfy[2];
   long long guard;
 } faceres;
@@ -908,21 +1081,24 @@ static void stage_faces(const ocfg *P, const gstate *g, double dt, faceres *fr) 
   if (P->ndim == 1) {
     for (int f = 0; f <= nx; ++f) {
       int i = NG + f - 1;                 /* left cell of face f */
-      double out[2][2][4], chi[2][4];
+      double out[2][3][4], chi[2][4];
       normal_face(P, g, 0, i, 0, out, chi);
-      double Wl[4], Wr[4], dl[4], dr[4];
+      double Wl[4], Wr[4], dl[4], dr[4], sxx[4];
       for (int v = 0; v < nv; ++v) {
         Wl[v] = out[0][0][v]; dl[v] = out[0][1][v] / P->dx;
         Wr[v] = out[1][0][v]; dr[v] = out[1][1][v] / P->dx;
+        sxx[v] = 0.5 * (out[0][2][v] + out[1][2][v]) / (P->dx * P->dx);
       }
-      if (!admissible(P, Wl)) { ++guard; for (int v = 0; v < nv; ++v) { Wl[v] = g->W[gidx(g, v, 0, i)]; dl[v] = 0.0; } }
-      if (!admissible(P, Wr)) { ++guard; for (int v = 0; v < nv; ++v) { Wr[v] = g->W[gidx(g, v, 0, i + 1)]; dr[v] = 0.0; } }
-      double F[4], Ft[4], Wi[4];
-      gks_point(P, Wl, Wr, dl, dr, NULL, NULL, dt, F, Ft, Wi);
+      int okl = admissible(P, Wl), okr = admissible(P, Wr);
+      if (!okl) { ++guard; for (int v = 0; v < nv; ++v) { Wl[v] = g->W[gidx(g, v, 0, i)]; dl[v] = 0.0; } }
+      if (!okr) { ++guard; for (int v = 0; v < nv; ++v) { Wr[v] = g->W[gidx(g, v, 0, i + 1)]; dr[v] = 0.0; } }
+      if (!okl || !okr) for (int v = 0; v < nv; ++v) sxx[v] = 0.0;
+      double F[4], Ft[4], Wh[4], Wf[4], W2[4];
+      gks_point(P, Wl, Wr, dl, dr, NULL, NULL, sxx, NULL, NULL, dt, F, Ft, Wh, Wf, W2);
       for (int v = 0; v < nv; ++v) {
-        fr->F[0][(size_t)v * (nx + 1) + f] = F[v];
-        fr->Ft[0][(size_t)v * (nx + 1) + f] = Ft[v];
-        fr->Wi[0][(size_t)v * (nx + 1) + f] = Wi[v];
+        size_t o = (size_t)v * (nx + 1) + f;
+        fr->F[0][o] = F[v]; fr->Ft[0][o] = Ft[v];
+        fr->Wh[0][o] = Wh[v]; fr->Wf[0][o] = Wf[v]; fr->W2[0][o] = W2[v];
       }
     }
     fr->guard += guard;
@@ -939,7 +1115,7 @@ static void stage_faces(const ocfg *P, const gstate *g, double dt, faceres *fr) 
     for (int t = 0; t < nt; ++t) {
       for (int f = 0; f < nfn; ++f) {
         /* normal reconstruction for rows t-1, t, t+1 */
-        double out[3][2][2][4], chi[2][4];
+        double out[3][2][3][4], chi[2][4];
         for (int dt_ = -1; dt_ <= 1; ++dt_) {
           int i, j;
           if (dir == 0) { i = NG + f - 1; j = NG + t + dt_; }
@@ -947,43 +1123,34 @@ static void stage_faces(const ocfg *P, const gstate *g, double dt, faceres *fr) 
           normal_face(P, g, dir, i, j, out[dt_ + 1], chi);
         }
         /* own cells of the two sides in the centre row */
-        int il, jl, ir, jr;
-        if (dir == 0) { il = NG + f - 1; ir = NG + f; jl = jr = NG + t; }
-        else { jl = NG + f - 1; jr = NG + f; il = ir = NG + t; }
-        double Fs[4] = {0, 0, 0, 0}, Fts[4] = {0, 0, 0, 0}, Wis[4] = {0, 0, 0, 0};
+        int ci[2], cj[2];
+        if (dir == 0) { ci[0] = NG + f - 1; ci[1] = NG + f; cj[0] = cj[1] = NG + t; }
+        else { cj[0] = NG + f - 1; cj[1] = NG + f; ci[0] = ci[1] = NG + t; }
+        double Fs[4] = {0, 0, 0, 0}, Fts[4] = {0, 0, 0, 0}, Whs[4] = {0, 0, 0, 0};
+        double Wfs[4] = {0, 0, 0, 0}, W2s[4] = {0, 0, 0, 0};
         for (int gp = 0; gp < 2; ++gp) {
-          double S[2][4], Dn[2][4], Dt[2][4];
-          for (int side = 0; side < 2; ++side) {
-            for (int v = 0; v < nv; ++v) {
-              double phi[3] = {out[0][side][0][v], out[1][side][0][v], out[2][side][0][v]};
-              double hdt;
-              S[side][v] = tangential(P, phi, GAUSS_ETA[gp], &hdt);
-              Dt[side][v] = hdt / ht;
-              Dn[side][v] = out[1][side][1][v] / hn;
-            }
-            if (!admissible(P, S[side])) {
-              ++gsum;
-              int ci = side ? ir : il, cj = side ? jr : jl;
-              for (int v = 0; v < nv; ++v) {
-                S[side][v] = g->W[gidx(g, v, cj, ci)]; Dn[side][v] = 0.0; Dt[side][v] = 0.0;
-              }
-            }
-          }
-          /* rotate into the face frame: normal momentum first */
-          double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
+          double S[2][4], Dn[2][4], Dt[2][4], Sec[3][4];
+          gsum += face_point(P, g, out, gp, ci, cj, S, Dn, Dt, Sec);
+          /* rotate into the face frame: normal momentum first; physical units */
+          double Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4], snn[4], snt[4], stt[4];
           int perm[4] = {0, 1, 2, 3};
           if (dir == 1) { perm[1] = 2; perm[2] = 1; }
           for (int v = 0; v < 4; ++v) {
             Wl[v] = S[0][perm[v]]; Wr[v] = S[1][perm[v]];
-            nl[v] = Dn[0][perm[v]]; nr[v] = Dn[1][perm[v]];
-            tl[v] = Dt[0][perm[v]]; tr[v] = Dt[1][perm[v]];
+            nl[v] = Dn[0][perm[v]] / hn; nr[v] = Dn[1][perm[v]] / hn;
+            tl[v] = Dt[0][perm[v]] / ht; tr[v] = Dt[1][perm[v]] / ht;
+            snn[v] = Sec[0][perm[v]] / (hn * hn);
+            snt[v] = Sec[1][perm[v]] / (hn * ht);
+            stt[v] = Sec[2][perm[v]] / (ht * ht);
           }
-          double F[4], Ft[4], Wi[4];
-          gks_point(P, Wl, Wr, nl, nr, tl, tr, dt, F, Ft, Wi);
+          double F[4], Ft[4], Wh[4], Wf[4], W2[4];
+          gks_point(P, Wl, Wr, nl, nr, tl, tr, snn, snt, stt, dt, F, Ft, Wh, Wf, W2);
           for (int v = 0; v < 4; ++v) {
             Fs[perm[v]] += 0.5 * F[v];
             Fts[perm[v]] += 0.5 * Ft[v];
-            Wis[perm[v]] += 0.5 * Wi[v];
+            Whs[perm[v]] += 0.5 * Wh[v];
+            Wfs[perm[v]] += 0.5 * Wf[v];
+            W2s[perm[v]] += 0.5 * W2[v];
           }
         }
         int nfx = fr->nfx[dir];
@@ -992,7 +1159,9 @@ static void stage_faces(const ocfg *P, const gstate *g, double dt, faceres *fr) 
         for (int v = 0; v < 4; ++v) {
           fr->F[dir][v * plane + base] = Fs[v];
           fr->Ft[dir][v * plane + base] = Fts[v];
-          fr->Wi[dir][v * plane + base] = Wis[v];
+          fr->Wh[dir][v * plane + base] = Whs[v];
+          fr->Wf[dir][v * plane + base] = Wfs[v];
+          fr->W2[dir][v * plane + base] = W2s[v];
         }
       }
     }
@@ -1010,18 +1179,21 @@ static int faceres_alloc(const ocfg *P, faceres *fr) {
     size_t n = (size_t)fr->nfx[d] * fr->nfy[d] * P->nv;
     fr->F[d] = (double *)calloc(n, sizeof(double));
     fr->Ft[d] = (double *)calloc(n, sizeof(double));
-    fr->Wi[d] = (double *)calloc(n, sizeof(double));
-    if (!fr->F[d] || !fr->Ft[d] || !fr->Wi[d]) return -1;
+    fr->Wh[d] = (double *)calloc(n, sizeof(double));
+    fr->Wf[d] = (double *)calloc(n, sizeof(double));
+    fr->W2[d] = (double *)calloc(n, sizeof(double));
+    if (!fr->F[d] || !fr->Ft[d] || !fr->Wh[d] || !fr->Wf[d] || !fr->W2[d]) return -1;
   }
   return 0;
 }
 static void faceres_free(faceres *fr) {
-  for (int d = 0; d < 2; ++d) { free(fr->F[d]); free(fr->Ft[d]); free(fr->Wi[d]); }
+  for (int d = 0; d < 2; ++d) {
+    free(fr->F[d]); free(fr->Ft[d]); free(fr->Wh[d]); free(fr->Wf[d]); free(fr->W2[d]);
+  }
 }
 
-/* L = -(1/|Omega|) sum faces F.n |Gamma| (Eq. (1)) and its time derivative;
- * gradients by the Gauss theorem (Eq. (2)) from W_int. */
-static void cell_terms(const ocfg *P, const faceres *fr, double *L, double *Lt, double *G) {
+/* L = -(1/|Omega|) sum faces F.n |Gamma| (Eq. (1)) and its time derivative. */
+static void cell_terms(const ocfg *P, const faceres *fr, double *L, double *Lt) {
   int nv = P->nv, nx = P->nx, ny = P->ny;
   size_t ncell = (size_t)nx * ny;
   for (int v = 0; v < nv; ++v)
@@ -1032,15 +1204,33 @@ static void cell_terms(const ocfg *P, const faceres *fr, double *L, double *Lt, 
         size_t fxl = v * px + (size_t)j * fr->nfx[0] + i, fxh = fxl + 1;
         double l = -(fr->F[0][fxh] - fr->F[0][fxl]) / P->dx;
         double lt = -(fr->Ft[0][fxh] - fr->Ft[0][fxl]) / P->dx;
-        G[c] = (fr->Wi[0][fxh] - fr->Wi[0][fxl]) / P->dx;
         if (P->ndim == 2) {
           size_t py = (size_t)fr->nfx[1] * fr->nfy[1];
           size_t fyl = v * py + (size_t)j * fr->nfx[1] + i, fyh = fyl + fr->nfx[1];
           l += -(fr->F[1][fyh] - fr->F[1][fyl]) / P->dy;
           lt += -(fr->Ft[1][fyh] - fr->Ft[1][fyl]) / P->dy;
-          G[(size_t)nv * ncell + c] = (fr->Wi[1][fyh] - fr->Wi[1][fyl]) / P->dy;
         }
         L[c] = l; Lt[c] = lt;
+      }
+}
+
+/* Cell-averaged gradients by the Gauss theorem, Eq. (2), from interface
+ * values Wx (x-faces) and Wy (y-faces, 2-D), laid out like faceres. */
+static void gauss_gradient(const ocfg *P, const faceres *fr, double *const Wface[2], double *G) {
+  int nv = P->nv, nx = P->nx, ny = P->ny;
+  size_t ncell = (size_t)nx * ny;
+  for (int v = 0; v < nv; ++v)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        size_t c = (size_t)v * ncell + (size_t)j * nx + i;
+        size_t px = (size_t)fr->nfx[0] * fr->nfy[0];
+        size_t fxl = v * px + (size_t)j * fr->nfx[0] + i, fxh = fxl + 1;
+        G[c] = (Wface[0][fxh] - Wface[0][fxl]) / P->dx;
+        if (P->ndim == 2) {
+          size_t py = (size_t)fr->nfx[1] * fr->nfy[1];
+          size_t fyl = v * py + (size_t)j * fr->nfx[1] + i, fyh = fyl + fr->nfx[1];
+          G[(size_t)nv * ncell + c] = (Wface[1][fyh] - Wface[1][fyl]) / P->dy;
+        }
       }
 }
 
@@ -1078,13 +1268,14 @@ int oracle_linear_weights(double *hval, double *hder) {
 
 /* GENO at one face for one component: q, g = averages and h-scaled averaged
  * derivatives of cells j-1..j+2. out = (value_l, hder_l, chi_l, value_r,
- * hder_r, chi_r). */
+ * hder_r, chi_r, h2der_l, h2der_r): h2der = h^2 * second derivative. */
 int oracle_geno_face(const double *params, const double *q, const double *g, double *out) {
   if (oracle_init()) return OR_EINVAL;
   ocfg P; cfg_from(&P, 1, 1, 1, 1.0, 1.0, params);
-  double l[3], r[3];
+  double l[4], r[4];
   geno_face(&P, q, g, l, r);
   for (int k = 0; k < 3; ++k) { out[k] = l[k]; out[3 + k] = r[k]; }
+  out[6] = l[3]; out[7] = r[3];
   return OR_OK;
 }
 
@@ -1111,8 +1302,8 @@ int oracle_geno_side_detail(const double *params, const double *dat, int si, dou
     wsum += wt[k];
   }
   for (int k = 0; k < 3; ++k) out[9 + k] = wt[k] / wsum;
-  double v, hd, chi;
-  geno_side(&P, dat, si, qH, hqH, &v, &hd, &chi);
+  double v, hd, h2, chi;
+  geno_side(&P, dat, si, qH, hqH, 0.0, &v, &hd, &h2, &chi);
   out[12] = chi;
   out[13] = 0.0; out[14] = 0.0;
   for (int k = 0; k < 3; ++k) { out[13] += out[9 + k] * out[3 + k]; out[14] += out[9 + k] * out[6 + k]; }
@@ -1120,7 +1311,7 @@ int oracle_geno_side_detail(const double *params, const double *dat, int si, dou
   return OR_OK;
 }
 
-/* Maxwellian moment table: out = mu[0..7], mv[0..5], mz[0..2]. */
+/* Maxwellian moment table: out = mu[0..DU-1], mv[0..DV-1], mz[0..DZ-1]. */
 int oracle_moments(double U, double V, double lam, double K, int half, int has_v, double *out) {
   mtab m; moments(U, V, lam, K, half, has_v, &m);
   memcpy(out, m.mu, sizeof m.mu);
@@ -1130,19 +1321,25 @@ int oracle_moments(double U, double V, double lam, double K, int half, int has_v
 }
 
 /* GKS flux at npts points (face frame). ndim selects 1-D (3 vars, no
- * tangential data) or 2-D (4 vars). Arrays are [npts][nv]. */
+ * tangential data) or 2-D (4 vars). Arrays are [npts][nv]; sec is
+ * [npts][3][nv]: physical second derivatives d_nn, d_nt, d_tt of the point
+ * (1-D: d_nn only, the others ignored), or NULL for zero. Outputs F, dF/dt,
+ * W(dt/2), W(dt) and the equilibrium W_tt. */
 int oracle_gks_points(const double *params, int ndim, int npts, const double *Wl,
                       const double *Wr, const double *dnl, const double *dnr,
-                      const double *dtl, const double *dtr, double dt,
-                      double *F, double *Ft, double *Wi) {
+                      const double *dtl, const double *dtr, const double *sec, double dt,
+                      double *F, double *Ft, double *Wh, double *Wf, double *Wtt) {
   if (ndim != 1 && ndim != 2) return OR_EINVAL;
   if (oracle_init()) return OR_EINVAL;
   ocfg P; cfg_from(&P, ndim, 1, 1, 1.0, 1.0, params);
   int nv = P.nv;
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < npts; ++p) {
+    const double *s0 = sec ? sec + (size_t)p * 3 * nv : zero;
+    const double *s1 = sec ? s0 + nv : zero, *s2 = sec ? s0 + 2 * nv : zero;
     gks_point(&P, Wl + p * nv, Wr + p * nv, dnl + p * nv, dnr + p * nv,
-              ndim == 2 ? dtl + p * nv : NULL, ndim == 2 ? dtr + p * nv : NULL, dt,
-              F + p * nv, Ft + p * nv, Wi + p * nv);
+              ndim == 2 ? dtl + p * nv : NULL, ndim == 2 ? dtr + p * nv : NULL, s0, s1, s2, dt,
+              F + p * nv, Ft + p * nv, Wh + p * nv, Wf + p * nv, Wtt + p * nv);
   }
   return OR_OK;
 }
@@ -1150,7 +1347,8 @@ int oracle_gks_points(const double *params, int ndim, int npts, const double *Wl
 /* Normal GENO over all faces of direction dir (after filling ghost cells).
  * 1-D: faces f = 0..nx; 2-D x-faces: rows j = -1..ny (ny+2) x faces 0..nx;
  * y-faces: faces 0..ny x columns i = -1..nx (nx+2).
- * out: [side][quant(2)][var][rows][faces] (x) or [side][quant][var][faces][cols] (y),
+ * out: [side][quant(3)][var][rows][faces] (x) or [side][quant][var][faces][cols] (y),
+ * quant = value, h d_n, h^2 d_nn;
  * chi: [side][var][...]. */
 int oracle_normal_faces(const double *params, int ndim, int nx, int ny, double dx, double dy,
                         const double *W, const double *dW, int dir, double *out, double *chi) {
@@ -1172,12 +1370,12 @@ int oracle_normal_faces(const double *params, int ndim, int nx, int ny, double d
       if (ndim == 1) { i = NG + b - 1; j = 0; }
       else if (dir == 0) { i = NG + b - 1; j = NG + a - 1; }
       else { i = NG + b - 1; j = NG + a - 1; }
-      double o[2][2][4], c[2][4];
+      double o[2][3][4], c[2][4];
       normal_face(&P, &g, ndim == 1 ? 0 : dir, i, j, o, c);
       for (int s = 0; s < 2; ++s)
         for (int v = 0; v < nv; ++v) {
-          for (int q = 0; q < 2; ++q)
-            out[(((size_t)s * 2 + q) * nv + v) * plane + (size_t)a * n1 + b] = o[s][q][v];
+          for (int q = 0; q < 3; ++q)
+            out[(((size_t)s * 3 + q) * nv + v) * plane + (size_t)a * n1 + b] = o[s][q][v];
           chi[((size_t)s * nv + v) * plane + (size_t)a * n1 + b] = c[s][v];
         }
     }
@@ -1321,8 +1519,11 @@ int oracle_linearity_faces(const double *params, int ndim, int nx, int ny, doubl
 
 /* Face states at the Gauss points after the tangential step and the
  * positivity guard (2-D), or at the face (1-D).
- * out: [side][gauss][quant][var][nfy][nfx], quant = value, h*d_n, h*d_t (2-D)
- * or value, h*d_n (1-D); variables in the (x, y) frame. */
+ * out (2-D): [side][gauss][quant][var][nfy][nfx], quant = value, h*d_n,
+ * h*d_t, followed by the second derivatives of the points
+ * [gauss][h_n^2 d_nn, h_n h_t d_nt, h_t^2 d_tt][var][nfy][nfx];
+ * (1-D): [side][value, h*d_n][var][nf] followed by h^2 d_nn [var][nf].
+ * Variables in the (x, y) frame. */
 int oracle_face_states(const double *params, int ndim, int nx, int ny, double dx, double dy,
                        const double *W, const double *dW, int dir, double *out, long long *guard) {
   if (oracle_init()) return OR_EINVAL;
@@ -1337,20 +1538,24 @@ int oracle_face_states(const double *params, int ndim, int nx, int ny, double dx
     size_t plane = (size_t)(nx + 1);
     for (int f = 0; f <= nx; ++f) {
       int i = NG + f - 1;
-      double o[2][2][4], c[2][4];
+      double o[2][3][4], c[2][4];
       normal_face(&P, &g, 0, i, 0, o, c);
+      int ok[2];
       for (int s = 0; s < 2; ++s) {
         double S[4];
         for (int v = 0; v < nv; ++v) S[v] = o[s][0][v];
-        int ok = admissible(&P, S);
-        if (!ok) ++gcount;
+        ok[s] = admissible(&P, S);
+        if (!ok[s]) ++gcount;
         for (int v = 0; v < nv; ++v) {
-          double val = ok ? o[s][0][v] : g.W[gidx(&g, v, 0, i + s)];
-          double dn = ok ? o[s][1][v] : 0.0;
+          double val = ok[s] ? o[s][0][v] : g.W[gidx(&g, v, 0, i + s)];
+          double dn = ok[s] ? o[s][1][v] : 0.0;
           out[(((size_t)s * 2 + 0) * nv + v) * plane + f] = val;
           out[(((size_t)s * 2 + 1) * nv + v) * plane + f] = dn;
         }
       }
+      for (int v = 0; v < nv; ++v)
+        out[((size_t)4 * nv + v) * plane + f] =
+            (ok[0] && ok[1]) ? 0.5 * (o[0][2][v] + o[1][2][v]) : 0.0;
     }
   } else {
     int nfx = (dir == 0) ? nx + 1 : nx, nfy = (dir == 0) ? ny : ny + 1;
@@ -1358,35 +1563,32 @@ int oracle_face_states(const double *params, int ndim, int nx, int ny, double dx
     for (int a = 0; a < nfy; ++a)
       for (int b = 0; b < nfx; ++b) {
         int f = (dir == 0) ? b : a, t = (dir == 0) ? a : b;
-        double o[3][2][2][4], c[2][4];
+        double o[3][2][3][4], c[2][4];
         for (int dt_ = -1; dt_ <= 1; ++dt_) {
           int i, j;
           if (dir == 0) { i = NG + f - 1; j = NG + t + dt_; }
           else { i = NG + t + dt_; j = NG + f - 1; }
           normal_face(&P, &g, dir, i, j, o[dt_ + 1], c);
         }
-        for (int gp = 0; gp < 2; ++gp)
-          for (int s = 0; s < 2; ++s) {
-            double S[4], Dn[4], Dt[4];
-            for (int v = 0; v < nv; ++v) {
-              double phi[3] = {o[0][s][0][v], o[1][s][0][v], o[2][s][0][v]};
-              S[v] = tangential(&P, phi, GAUSS_ETA[gp], &Dt[v]);
-              Dn[v] = o[1][s][1][v];
-            }
-            if (!admissible(&P, S)) {
-              ++gcount;
-              int ci, cj;
-              if (dir == 0) { ci = NG + f - 1 + s; cj = NG + t; }
-              else { ci = NG + t; cj = NG + f - 1 + s; }
-              for (int v = 0; v < nv; ++v) { S[v] = g.W[gidx(&g, v, cj, ci)]; Dn[v] = 0.0; Dt[v] = 0.0; }
-            }
+        int ci[2], cj[2];
+        if (dir == 0) { ci[0] = NG + f - 1; ci[1] = NG + f; cj[0] = cj[1] = NG + t; }
+        else { cj[0] = NG + f - 1; cj[1] = NG + f; ci[0] = ci[1] = NG + t; }
+        for (int gp = 0; gp < 2; ++gp) {
+          double S[2][4], Dn[2][4], Dt[2][4], Sec[3][4];
+          gcount += face_point(&P, &g, o, gp, ci, cj, S, Dn, Dt, Sec);
+          for (int s = 0; s < 2; ++s)
             for (int v = 0; v < nv; ++v) {
               size_t base = (((size_t)s * 2 + gp) * 3) * nv;
-              out[(base + 0 * nv + v) * plane + (size_t)a * nfx + b] = S[v];
-              out[(base + 1 * nv + v) * plane + (size_t)a * nfx + b] = Dn[v];
-              out[(base + 2 * nv + v) * plane + (size_t)a * nfx + b] = Dt[v];
+              out[(base + 0 * nv + v) * plane + (size_t)a * nfx + b] = S[s][v];
+              out[(base + 1 * nv + v) * plane + (size_t)a * nfx + b] = Dn[s][v];
+              out[(base + 2 * nv + v) * plane + (size_t)a * nfx + b] = Dt[s][v];
             }
-          }
+          for (int q = 0; q < 3; ++q)
+            for (int v = 0; v < nv; ++v) {
+              size_t base = (size_t)12 * nv + ((size_t)gp * 3 + q) * nv;
+              out[(base + v) * plane + (size_t)a * nfx + b] = Sec[q][v];
+            }
+        }
       }
   }
   if (guard) *guard = gcount;
@@ -1394,10 +1596,19 @@ int oracle_face_states(const double *params, int ndim, int nx, int ny, double dx
   return OR_OK;
 }
 
-/* nsteps full S2O4 steps in place (reading of the two-stage fourth-order
- * method: stage 1 W* = W + dt/2 L + dt^2/8 L_t, stage 2
- * W^{n+1} = W + dt L + dt^2/6 L_t + dt^2/3 L_t*; gradients at the stage
- * times from W_int(dt/2) of each stage, Eq. (2)).
+/* nsteps full steps of the two-stage fourth-order method (S2O4) in place.
+ * Cell averages (Eq. (1)), with L and its time derivative L_t from the
+ * time-fitted interface fluxes:
+ *   stage 1: W* = W + dt/2 L + dt^2/8 L_t,
+ *   stage 2: W^{n+1} = W + dt L + dt^2/6 (L_t + 2 L_t*).
+ * Cell-averaged gradients by the Gauss theorem (Eq. (2)) from the interface
+ * values at the stage times. Reading (default): the same two-stage structure
+ * applied to the interface values, whose time derivatives are those of the
+ * BGK interface solution (through its states at dt/2 and dt, linear in t for
+ * tau = 0) and the equilibrium second time derivative W_tt of each stage:
+ *   W_face(t*) = W_int(dt/2) + dt^2/8 W_tt,
+ *   W_face(t^{n+1}) = W_int(dt) + dt^2/6 (W_tt + 2 W_tt*).
+ * Earlier reading (gupd = 1): the BGK interface state at dt/2 of each stage.
  * dt_hist: nsteps doubles (may be NULL). guard: positivity fall-backs.
  * fixed_dt > 0 overrides the CFL step. */
 int oracle_step(const double *params, int ndim, int nx, int ny, double dx, double dy,
@@ -1414,6 +1625,14 @@ int oracle_step(const double *params, int ndim, int nx, int ny, double dx, doubl
   double *R = malloc(nW * sizeof(double));
   gstate g; faceres fr;
   if (!L || !Lt || !Ws || !Gs || !R || gstate_alloc(&P, &g) || faceres_alloc(&P, &fr)) return OR_ENOMEM;
+  /* interface values at the stage times, per direction */
+  double *Wst[2] = {NULL, NULL}, *Wnx[2] = {NULL, NULL};
+  for (int d = 0; d < ndim; ++d) {
+    size_t n = (size_t)fr.nfx[d] * fr.nfy[d] * nv;
+    Wst[d] = malloc(n * sizeof(double));
+    Wnx[d] = malloc(n * sizeof(double));
+    if (!Wst[d] || !Wnx[d]) return OR_ENOMEM;
+  }
   for (int n = 0; n < nsteps; ++n) {
     double dt = fixed_dt > 0.0 ? fixed_dt : cfl_dt(&P, W);
     if (dt_hist) dt_hist[n] = dt;
@@ -1421,29 +1640,47 @@ int oracle_step(const double *params, int ndim, int nx, int ny, double dx, doubl
     gstate_load(&P, &g, W, dW);
     fill_ghosts(&P, &g);
     stage_faces(&P, &g, dt, &fr);
-    cell_terms(&P, &fr, L, Lt, Gs);
+    cell_terms(&P, &fr, L, Lt);
     for (size_t k = 0; k < nW; ++k) {
       Ws[k] = W[k] + 0.5 * dt * L[k] + dt * dt / 8.0 * Lt[k];
       R[k] = W[k] + dt * L[k] + dt * dt / 6.0 * Lt[k];
     }
+    for (int d = 0; d < ndim; ++d) {
+      size_t nf = (size_t)fr.nfx[d] * fr.nfy[d] * nv;
+      for (size_t k = 0; k < nf; ++k) {
+        if (P.gupd == 1) { Wst[d][k] = fr.Wh[d][k]; continue; }
+        Wst[d][k] = fr.Wh[d][k] + dt * dt / 8.0 * fr.W2[d][k];
+        Wnx[d][k] = fr.Wf[d][k] + dt * dt / 6.0 * fr.W2[d][k];
+      }
+    }
+    gauss_gradient(&P, &fr, Wst, Gs);
     /* stage 2 */
     gstate_load(&P, &g, Ws, Gs);
     fill_ghosts(&P, &g);
     stage_faces(&P, &g, dt, &fr);
-    cell_terms(&P, &fr, L, Lt, dW);
+    cell_terms(&P, &fr, L, Lt);
     for (size_t k = 0; k < nW; ++k) W[k] = R[k] + dt * dt / 3.0 * Lt[k];
+    for (int d = 0; d < ndim; ++d) {
+      size_t nf = (size_t)fr.nfx[d] * fr.nfy[d] * nv;
+      for (size_t k = 0; k < nf; ++k) {
+        if (P.gupd == 1) Wnx[d][k] = fr.Wh[d][k];
+        else Wnx[d][k] += dt * dt / 3.0 * fr.W2[d][k];
+      }
+    }
+    gauss_gradient(&P, &fr, Wnx, dW);
   }
   if (guard) *guard = fr.guard;
   free(L); free(Lt); free(Ws); free(Gs); free(R);
+  for (int d = 0; d < 2; ++d) { free(Wst[d]); free(Wnx[d]); }
   gstate_free(&g); faceres_free(&fr);
   return OR_OK;
 }
 
-/* One stage's face results (for unit parity of the flux over a grid):
- * F, Ft, Wi for direction dir: [nv][nfy][nfx]. */
+/* One stage's face results (for unit parity of the flux over a grid) for
+ * direction dir, each [nv][nfy][nfx]: F, dF/dt, W(dt/2), W(dt) and W_tt. */
 int oracle_stage_faces(const double *params, int ndim, int nx, int ny, double dx, double dy,
                        const double *W, const double *dW, double dt, int dir,
-                       double *F, double *Ft, double *Wi) {
+                       double *F, double *Ft, double *Wh, double *Wf, double *Wtt) {
   if (oracle_init()) return OR_EINVAL;
   ocfg P; cfg_from(&P, ndim, nx, ny, dx, dy, params);
   gstate g; faceres fr;
@@ -1455,7 +1692,9 @@ int oracle_stage_faces(const double *params, int ndim, int nx, int ny, double dx
   size_t n = (size_t)fr.nfx[d] * fr.nfy[d] * P.nv;
   memcpy(F, fr.F[d], n * sizeof(double));
   memcpy(Ft, fr.Ft[d], n * sizeof(double));
-  memcpy(Wi, fr.Wi[d], n * sizeof(double));
+  memcpy(Wh, fr.Wh[d], n * sizeof(double));
+  memcpy(Wf, fr.Wf[d], n * sizeof(double));
+  memcpy(Wtt, fr.W2[d], n * sizeof(double));
   gstate_free(&g); faceres_free(&fr);
   return OR_OK;
 }

@@ -25,7 +25,9 @@ P_GAMMA, P_CPATH, P_EPS, P_R, P_RL, P_D1, P_D2, P_D3, P_TAUC1, P_TAUC2, P_CFL = 
 P_BC = 11  # four boundary codes follow: x-lo, x-hi, y-lo, y-hi (0 periodic, 1 transmissive)
 P_GHOST = 15  # 24 values: 1-D fixed ends [end][layer][W (3), dW (3)]
 P_CHAR = 39   # 1 = characteristic-variable reconstruction in the normal step
-N_PARAMS = 40
+P_GUPD = 40   # time stepping of the gradients: 0 two-stage structure on the interface values, 1 earlier reading
+N_PARAMS = 41
+GUPD_S2O4, GUPD_STAGE_HALF = 0, 1
 PERIODIC, TRANSMISSIVE, REFLECTING, FIXED = 0, 1, 2, 3
 
 
@@ -53,12 +55,12 @@ def lib():
         L.oracle_geno_face.argtypes = [dp, dp, dp, dp]
         L.oracle_moments.argtypes = [d, d, d, d, i, i, dp]
         L.oracle_geno_side_detail.argtypes = [dp, dp, i, d, d, dp]
-        L.oracle_gks_points.argtypes = [dp, i, i, dp, dp, dp, dp, dp, dp, d, dp, dp, dp]
+        L.oracle_gks_points.argtypes = [dp, i, i, dp, dp, dp, dp, dp, dp, dp, d, dp, dp, dp, dp, dp]
         L.oracle_normal_faces.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, dp]
         L.oracle_roe_eigen.argtypes = [dp, i, i, dp, dp, dp, dp, dp]
         L.oracle_face_states.argtypes = [dp, i, i, i, d, d, dp, dp, i, dp, llp]
         L.oracle_step.argtypes = [dp, i, i, i, d, d, dp, dp, i, d, dp, llp]
-        L.oracle_stage_faces.argtypes = [dp, i, i, i, d, d, dp, dp, d, i, dp, dp, dp]
+        L.oracle_stage_faces.argtypes = [dp, i, i, i, d, d, dp, dp, d, i, dp, dp, dp, dp, dp]
         L.oracle_weights.argtypes = [dp, dp, d, dp]
         L.oracle_linearity_faces.argtypes = [dp, i, i, i, d, d, dp, dp, i, d, dp]
         L.oracle_cfl_dt.argtypes = [dp, i, i, i, d, d, dp]
@@ -82,16 +84,20 @@ def _c(a):
 
 def params(ndim: int = 2, bc=TRANSMISSIVE, gamma=1.4, C=20.0, eps=1e-15, r=2.0, rL=2.0,
            d=(1.0, 8.0, 1.0), tau_c1=0.0, tau_c2=1.0, cfl=0.5, ghost=None,
-           characteristic=False) -> np.ndarray:
+           characteristic=False, gradient_update=GUPD_S2O4) -> np.ndarray:
     """Oracle parameter vector. Paper constants (Sec. 3): C = 20, eps = 1e-15,
     r = 2 (structured), r^L = 2, central weight C_0 = 8. ghost: [2, 2, 6]
     states of the ghost cells of 1-D FIXED ends ([end][layer 0 = next to the
     grid][W (3), dW (3)]); characteristic: the normal step reconstructs the
     characteristic variables of the normal flux Jacobian at the Roe average
     of the two cells at each face (values and h-derivatives projected alike);
-    the tangential step of 2-D faces works on the conservative face values."""
+    the tangential step of 2-D faces works on the conservative face values.
+    gradient_update: GUPD_S2O4 applies the two-stage fourth-order structure to
+    the interface values that update the gradients (Eq. (2)); GUPD_STAGE_HALF
+    takes the BGK interface state at dt/2 of each stage (earlier reading)."""
     p = np.zeros(N_PARAMS)
     p[P_CHAR] = 1.0 if characteristic else 0.0
+    p[P_GUPD] = float(gradient_update)
     if ghost is not None:
         p[P_GHOST:P_GHOST + 24] = np.asarray(ghost, dtype=np.float64).reshape(24)
     p[P_GAMMA], p[P_CPATH], p[P_EPS], p[P_R], p[P_RL] = gamma, C, eps, r, rL
@@ -115,8 +121,9 @@ def linear_weights():
 
 def geno_face(prm, q, g):
     """GENO at one face for one component; q, g: averages and h-scaled averaged
-    derivatives of cells j-1..j+2. Returns (val_l, hder_l, chi_l, val_r, hder_r, chi_r)."""
-    q, g, out = _c(q), _c(g), np.zeros(6)
+    derivatives of cells j-1..j+2. Returns (val_l, hder_l, chi_l, val_r, hder_r, chi_r,
+    h2der_l, h2der_r) with h2der = h^2 times the second derivative."""
+    q, g, out = _c(q), _c(g), np.zeros(8)
     _check(lib().oracle_geno_face(_p(_c(prm)), _p(q), _p(g), _p(out)), "oracle_geno_face")
     return out
 
@@ -164,21 +171,26 @@ def linearity_faces(prm, W, dW, direction=0, ct=TENO_CT, dx=None, dy=None):
 
 
 def moments(U, V, lam, K, half, has_v=True):
-    out = np.zeros(8 + 6 + 3)
+    """Normalised Maxwellian moments <u^n> (n < 8), <v^n> (n < 8), <xi^(2n)> (n < 4)."""
+    out = np.zeros(8 + 8 + 4)
     lib().oracle_moments(U, V, lam, K, int(half), int(has_v), _p(out))
-    return out[:8], out[8:14], out[14:]
+    return out[:8], out[8:16], out[16:]
 
 
-def gks_points(prm, ndim, Wl, Wr, dnl, dnr, dtl=None, dtr=None, dt=1e-3):
-    """GKS flux at points in the face frame; arrays [npts, nv]. Returns F, Ft, Wint."""
+def gks_points(prm, ndim, Wl, Wr, dnl, dnr, dtl=None, dtr=None, dt=1e-3, sec=None, full=False):
+    """GKS flux at points in the face frame; arrays [npts, nv]. sec: [npts, 3, nv]
+    physical second derivatives (d_nn, d_nt, d_tt) of the points, or None.
+    Returns F, Ft, W(dt/2) (and with full=True also W(dt) and W_tt)."""
     Wl, Wr, dnl, dnr = map(_c, (Wl, Wr, dnl, dnr))
     npts, nv = Wl.shape
     dtl = _c(dtl) if dtl is not None else np.zeros_like(Wl)
     dtr = _c(dtr) if dtr is not None else np.zeros_like(Wl)
-    F, Ft, Wi = np.zeros_like(Wl), np.zeros_like(Wl), np.zeros_like(Wl)
+    sec = _c(sec) if sec is not None else np.zeros((npts, 3, nv))
+    F, Ft, Wh, Wf, W2 = (np.zeros_like(Wl) for _ in range(5))
     _check(lib().oracle_gks_points(_p(_c(prm)), ndim, npts, _p(Wl), _p(Wr), _p(dnl), _p(dnr),
-                                   _p(dtl), _p(dtr), dt, _p(F), _p(Ft), _p(Wi)), "oracle_gks_points")
-    return F, Ft, Wi
+                                   _p(dtl), _p(dtr), _p(sec), dt, _p(F), _p(Ft), _p(Wh), _p(Wf),
+                                   _p(W2)), "oracle_gks_points")
+    return (F, Ft, Wh, Wf, W2) if full else (F, Ft, Wh)
 
 
 def _dims(W):
@@ -189,7 +201,8 @@ def _dims(W):
 
 def normal_faces(prm, W, dW, direction=0, dx=None, dy=None):
     """Normal GENO on every face of a direction (rows -1..ny for x-faces,
-    columns -1..nx for y-faces). Returns out[side, quant, var, a, b], chi[side, var, a, b]."""
+    columns -1..nx for y-faces). Returns out[side, quant, var, a, b] (quant = value,
+    h d_n, h^2 d_nn), chi[side, var, a, b]."""
     W, dW = _c(W), _c(dW)
     ndim, nv, ny, nx = _dims(W)
     dx = 1.0 / nx if dx is None else dx
@@ -200,7 +213,7 @@ def normal_faces(prm, W, dW, direction=0, dx=None, dy=None):
         n0, n1 = ny + 2, nx + 1
     else:
         n0, n1 = ny + 1, nx + 2
-    out = np.zeros((2, 2, nv, n0, n1))
+    out = np.zeros((2, 3, nv, n0, n1))
     chi = np.zeros((2, nv, n0, n1))
     _check(lib().oracle_normal_faces(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), direction,
                                      _p(out), _p(chi)), "oracle_normal_faces")
@@ -217,26 +230,35 @@ def roe_eigen(prm, ndim, direction, Wa, Wb):
     return R.reshape(nv, nv), Lm.reshape(nv, nv), lam
 
 
-def face_states(prm, W, dW, direction=0, dx=None, dy=None):
+def face_states(prm, W, dW, direction=0, dx=None, dy=None, second=False):
     """Point states on faces after the tangential step and positivity guard.
-    Returns (out[side, gauss, quant, var, nfy, nfx], guard_count)."""
+    Returns (out[side, gauss, quant, var, nfy, nfx], guard_count); with
+    second=True also the points' h-scaled second derivatives
+    sec[gauss, (h_n^2 d_nn, h_n h_t d_nt, h_t^2 d_tt), var, nfy, nfx] (1-D: one
+    point and d_nn only): (out, sec, guard_count)."""
     W, dW = _c(W), _c(dW)
     ndim, nv, ny, nx = _dims(W)
     dx = 1.0 / nx if dx is None else dx
     dy = 1.0 / ny if dy is None else dy
     if ndim == 1:
-        out = np.zeros((2, 1, 2, nv, 1, nx + 1))
+        nfy, nfx, npl, nsec = 1, nx + 1, 4, 1
+        shape, sshape = (2, 1, 2, nv, 1, nx + 1), (1, 1, nv, 1, nx + 1)
     else:
         nfx, nfy = (nx + 1, ny) if direction == 0 else (nx, ny + 1)
-        out = np.zeros((2, 2, 3, nv, nfy, nfx))
+        npl, nsec = 12, 6
+        shape, sshape = (2, 2, 3, nv, nfy, nfx), (2, 3, nv, nfy, nfx)
+    buf = np.zeros((npl + nsec) * nv * nfy * nfx)
     g = ctypes.c_longlong(0)
     _check(lib().oracle_face_states(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), direction,
-                                    _p(out), ctypes.byref(g)), "oracle_face_states")
-    return out, g.value
+                                    _p(buf), ctypes.byref(g)), "oracle_face_states")
+    n = npl * nv * nfy * nfx
+    out, sec = buf[:n].reshape(shape), buf[n:].reshape(sshape)
+    return (out, sec, g.value) if second else (out, g.value)
 
 
-def stage_faces(prm, W, dW, dt, direction=0, dx=None, dy=None):
-    """Gauss-averaged F, dF/dt and W_int(dt/2) on every face of a direction: [nv, nfy, nfx]."""
+def stage_faces(prm, W, dW, dt, direction=0, dx=None, dy=None, full=False):
+    """Gauss-averaged F, dF/dt and W_int(dt/2) on every face of a direction:
+    [nv, nfy, nfx]; with full=True also W_int(dt) and the equilibrium W_tt."""
     W, dW = _c(W), _c(dW)
     ndim, nv, ny, nx = _dims(W)
     dx = 1.0 / nx if dx is None else dx
@@ -245,10 +267,10 @@ def stage_faces(prm, W, dW, dt, direction=0, dx=None, dy=None):
         shape = (nv, ny, nx + 1)
     else:
         shape = (nv, ny + 1, nx)
-    F, Ft, Wi = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    F, Ft, Wh, Wf, W2 = (np.zeros(shape) for _ in range(5))
     _check(lib().oracle_stage_faces(_p(_c(prm)), ndim, nx, ny, dx, dy, _p(W), _p(dW), dt, direction,
-                                    _p(F), _p(Ft), _p(Wi)), "oracle_stage_faces")
-    return F, Ft, Wi
+                                    _p(F), _p(Ft), _p(Wh), _p(Wf), _p(W2)), "oracle_stage_faces")
+    return (F, Ft, Wh, Wf, W2) if full else (F, Ft, Wh)
 
 
 def step(prm, W, dW, nsteps, dx=None, dy=None, fixed_dt=0.0):

@@ -289,6 +289,49 @@ def density_wave_noncompact(n: int, t: float = 0.0, gamma: float = GAMMA):
     return np.stack([rho, rho, 1.0 / (gamma - 1.0) + 0.5 * rho])
 
 
+def density_wave_compact(n: int, t: float = 0.0, gamma: float = GAMMA):
+    """The 1-D accuracy test of Sec. 6.1 for the compact scheme: rho = 1 +
+    0.2 sin(pi (x - t)), U = p = 1 on [0, 2], periodic, at time t of the
+    advected wave. Exact cell averages and exact averaged gradients (the
+    difference of the point values at the cell faces over h); rho U and rho E
+    are affine in rho. Returns (W[3, 1, n], dW[3, 1, n])."""
+    h = 2.0 / n
+    xl = np.arange(n) * h - t
+    xr = xl + h
+    rho = 1.0 + 0.2 * (np.cos(math.pi * xl) - np.cos(math.pi * xr)) / (math.pi * h)
+    W = np.stack([rho, rho, 1.0 / (gamma - 1.0) + 0.5 * rho])
+    drho = 0.2 * (np.sin(math.pi * xr) - np.sin(math.pi * xl)) / h
+    dW = np.stack([drho, drho, 0.5 * drho])
+    return W.reshape(3, 1, n), dW.reshape(3, 1, n)
+
+
+def diagonal_wave_2d(n: int, t: float = 0.0, amp: float = 0.2, gamma: float = GAMMA):
+    """An oblique density wave on the periodic unit square: rho = 1 + amp
+    sin(2 pi (x + y - 2t)), U = V = p = 1, at time t. Exact cell averages and
+    exact cell-averaged gradients (face averages of the point values by the
+    Gauss theorem). Returns (W[4, n, n], dW[8, n, n])."""
+    h = 1.0 / n
+    k = 2.0 * math.pi
+    ph = -2.0 * k * t
+    x0 = np.arange(n) * h
+    X, Y = np.meshgrid(x0, x0, indexing="xy")
+
+    def cell(xa, ya):
+        s = np.sin
+        return -(s(k * (xa + h + ya + h) + ph) - s(k * (xa + h + ya) + ph)
+                 - s(k * (xa + ya + h) + ph) + s(k * (xa + ya) + ph)) / (k * h) ** 2
+
+    def face(xf, ya):   # average over [ya, ya + h] of sin(k (xf + y) + ph)
+        return -(np.cos(k * (xf + ya + h) + ph) - np.cos(k * (xf + ya) + ph)) / (k * h)
+
+    rho = 1.0 + amp * cell(X, Y)
+    drx = amp * (face(X + h, Y) - face(X, Y)) / h
+    dry = amp * (face(Y + h, X) - face(Y, X)) / h
+    W = np.stack([rho, rho, rho, 1.0 / (gamma - 1.0) + rho])
+    dW = np.stack([drx, drx, drx, drx, dry, dry, dry, dry])
+    return W, dW
+
+
 def entropy_wave_noncompact(n: int = 1800, gamma: float = GAMMA, b: float = 1.5):
     """The entropy-wave advection of Sec. 6.1: rho = 1 + 0.5 exp(-ln2 x^2 / b^2),
     U = p = 1 on [-800, 1000], periodic; 1800 cells in the paper. Exact cell

@@ -75,3 +75,16 @@ def test_discontinuity_scenario(oracle, prm):
             assert w["chi_geno"] > 0.999 and w["chi_z"] > 0.999 and w["chi_t"] == 1.0
         else:
             assert w["chi_geno"] < 1e-3 and w["chi_z"] < 1e-3 and w["chi_t"] == 0.0
+
+
+def test_path_function_hand_worked_value(oracle):
+    # Eq. (5) with r = 2 and Eq. (4), C = 20, for the compact scheme's IS^tau
+    # (Eq. (14)) from indicators worked by hand: IS = (IS_1, IS_2, IS_3) =
+    # (1, 13, 11) gives IS^H = 13, IS^L = 1, IS^tau = |(13 + 11)/2 - 1| = 11;
+    # alpha^H = 1 + (11/13)^2 = 290/169, alpha^L = 1 + 11^2 = 122 (eps
+    # negligible), alpha = 2 alpha^H / (alpha^H + alpha^L) = 580/20908 =
+    # 145/5227 = 0.0277405...; tanh(20) rounds to 1, so chi = tanh(2900/5227) =
+    # (e^1.10962 - 1) / (e^1.10962 + 1) = 2.03321 / 4.03321 = 0.504118...
+    w = oracle.weights(oracle.params(), np.array([1.0, 13.0, 11.0]))
+    assert abs(w["chi_geno"] - 0.5041176819) < 2e-10, w["chi_geno"]
+    assert abs(w["chi_geno"] - math.tanh(20.0 * 145.0 / 5227.0) / math.tanh(20.0)) < 1e-14
