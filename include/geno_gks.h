@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GENO_ABI_VERSION 2
+#define GENO_ABI_VERSION 3
 
 /* error codes */
 #define GENO_OK 0
@@ -114,12 +114,13 @@ extern "C" {
  *   tangential step then works on the conservative face values. The paper
  *   does not say which variables it reconstructs. Not combined with the
  *   learned gate (GENO_EINVAL), whose network predicts conservative chi.
- * gate_delta: learned gate (2-D gks_step only). If > 0, before the normal
- *   reconstruction of each direction and stage the loaded network
- *   (geno_mlp_load) predicts chi of every cell from its stencil, and where the
- *   prediction is >= 1 - gate_delta the cell's two face-sides of that
- *   direction take chi = 1 (the linear reconstruction) without forming the
- *   smoothness indicators; elsewhere plain GENO decides. 0 (default) = off. */
+ * gate_delta: learned gate (2-D gks_step only). If > 0, once per step, on
+ *   the state at its start, the loaded network (geno_mlp_load) predicts chi
+ *   of every cell and direction from its stencil; where the prediction is
+ *   >= 1 - gate_delta the cell's two face-sides of that direction take
+ *   chi = 1 (the linear reconstruction) without forming the smoothness
+ *   indicators, in both stages of the step; elsewhere plain GENO decides.
+ *   0 (default) = off. */
 typedef struct geno_params {
   int version;
   int precision;   /* GENO_F64 or GENO_MIXED */
@@ -195,6 +196,16 @@ size_t gks_workspace_bytes(const geno_grid* g);
  *        of y between (b, a-1) and (b, a). Side 0 = the lower-index cell.
  *   h is the cell size along the normal (d/dn) or the tangent (d/dt).
  *   Variables stay in the (x, y) frame.
+ *   Followed by the second derivatives of the points that the time stepping
+ *   of the gradients uses (the mean over the two sides; zero at a point with
+ *   a guarded side): [gauss(G)][quant2(Q2)][var][nfy][nfx] with
+ *   1-D: Q2 = 1 (h^2 d2/dn2, the GENO blend of Eq. (3) applied to the
+ *        second derivatives of p^7 and of the sub-stencil quadratics);
+ *   2-D: Q2 = 3 (h_n^2 d2/dn2 of the face-row; h_n h_t d2/dndt = chi_t
+ *        (psi_{t+1} - psi_{t-1})/2 from the h-scaled normal derivatives psi
+ *        of the rows t-1, t+1; h_t^2 d2/dt2 = chi_t (phi_{t+1} - 2 phi_t +
+ *        phi_{t-1}) from the face-row values phi, chi_t the weight of the
+ *        tangential step). In all (2 G Q + G Q2) nv planes.
  * chi (device, may be NULL): path function of the normal reconstruction per
  *   [side][var][row][face] over the rows the tangential step reads:
  *   1-D 1 x (nx+1); x-faces (ny+2) x (nx+1) (rows -1..ny); y-faces
@@ -214,17 +225,24 @@ int geno_reconstruct(const geno_grid* g, void* W, void* dW, int dir, void* face_
  *   F    = flux at the start of the step, from fitting F + t dF/dt to the
  *          time integrals of the flux over dt/2 and dt;
  *   Ft   = dF/dt of that fit;
- *   Wint = conserved state of the interface solution at t = dt/2.
+ *   Wint = three blocks [3][var][nfy][nfx]: the conserved state of the
+ *          interface solution at t = dt/2 and at t = dt, and the second time
+ *          derivative W_tt of the interface equilibrium (the Euler equations'
+ *          -d_x(A W_t) - d_y(B W_t) from the points' first and second
+ *          derivatives).
  * Any of F, Ft, Wint may be NULL. dir as in geno_reconstruct. */
 int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, void* F,
              void* Ft, void* Wint, void* stream);
 
 /* nsteps steps of the two-stage fourth-order GKS update of W and dW in place
  * (Eq. (1): face fluxes; Eq. (2): cell-averaged gradients from the interface
- * states by the Gauss theorem). Each step: dt from the CFL condition on the
- * current state; stage 1 W* = W + dt/2 L + dt^2/8 dL/dt and gradients from
- * the interface states at dt/2; stage 2 W = W + dt L + dt^2/6 dL/dt +
- * dt^2/3 dL/dt(W*) with gradients from the stage-2 interface states at dt/2.
+ * values by the Gauss theorem). Each step: dt from the CFL condition on the
+ * current state; stage 1 W* = W + dt/2 L + dt^2/8 dL/dt, with gradients from
+ * the interface values W(dt/2) + dt^2/8 W_tt at the stage time; stage 2
+ * W = W + dt L + dt^2/6 dL/dt + dt^2/3 dL/dt(W*), with gradients from the
+ * interface values at the end of the step, W(dt) + dt^2/6 (W_tt + 2 W_tt*)
+ * (the same two-stage structure applied to the interface values: W(t) of
+ * the interface solution and W_tt of its equilibrium, W_tt* from stage 2).
  * ws: workspace of gks_workspace_bytes(g) bytes.
  * dt_out (device, may be NULL): nsteps doubles, the step sizes.
  * stats (host, may be NULL): if given, the call waits for the stream and

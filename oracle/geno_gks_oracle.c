@@ -698,6 +698,32 @@ static void equilibrium_wtt(const ocfg *P, const prim *pc, const double *ac, con
   for (int k = 0; k < nv; ++k) Wtt[k] = -pc->rho * m2[k];
 }
 
+/* Weight of the second-order term of the interface value at a point with
+ * side states pl, pr (see gks_point). */
+#define SECOND_ORDER_R0 1e-1
+#define SECOND_ORDER_R1 1e-2
+static double second_order_weight(const ocfg *P, const prim *pl, const prim *pr,
+                                  const double *Wl, const double *Wr,
+                                  const double *dnl, const double *dnr, double dt) {
+  double prl = pl->rho / (2.0 * pl->lam), prr = pr->rho / (2.0 * pr->lam);
+  double cl = sqrt(P->gamma * prl / pl->rho), cr = sqrt(P->gamma * prr / pr->rho);
+  double r = fabs(prl - prr) / (prl + prr);
+  double rr = fabs(pl->rho - pr->rho) / (pl->rho + pr->rho);
+  double ru = fabs(pl->U - pr->U) / (cl + cr), rv = fabs(pl->V - pr->V) / (cl + cr);
+  if (rr > r) r = rr;
+  if (ru > r) r = ru;
+  if (rv > r) r = rv;
+  double cb = 0.5 * (cl + cr), rs = pl->rho + pr->rho;
+  for (int k = 0; k < P->nv; ++k) {
+    double sc = (k == 0) ? rs : (k == P->nv - 1) ? fabs(Wl[k]) + fabs(Wr[k]) : rs * cb;
+    double rd = dt * cb * fabs(dnl[k] - dnr[k]) / sc;
+    if (rd > r) r = rd;
+  }
+  if (r <= SECOND_ORDER_R1) return 1.0;
+  double x = (r - SECOND_ORDER_R1) / (SECOND_ORDER_R0 - SECOND_ORDER_R1);
+  return x < 1.0 ? 1.0 - x * x : 0.0;
+}
+
 /* Integrated flux over [0, delta] and the interface state at t = delta of
  * the BGK solution
  *   f = (1 - e) g0 + ((t+tau) e - tau)(abar u + bbar v) g0 + (t - tau(1 - e)) Abar g0
@@ -708,7 +734,7 @@ static void equilibrium_wtt(const ocfg *P, const prim *pc, const double *ac, con
  * point (normal-normal, normal-tangential, tangential-tangential; 1-D: snn
  * only), averaged over the sides. Outputs the fitted F, dF/dt (from delta =
  * dt/2 and dt), the interface state W(dt/2) and W(dt) of the solution, and
- * the equilibrium second time derivative W_tt. */
+ * the weighted equilibrium second time derivative phi W_tt. */
 static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
                       const double *dnl, const double *dnr, const double *dtl,
                       const double *dtr, const double *snn, const double *snt,
@@ -751,7 +777,27 @@ static void gks_point(const ocfg *P, const double *Wl, const double *Wr,
   time_slope(P, &pl, al, bl, Al);
   time_slope(P, &pr, ar, br, Ar);
   time_slope(P, &pc, ac, bc, Ac);
-  equilibrium_wtt(P, &pc, ac, bc, Ac, snn, snt, stt, Wtt);
+  /* The second-order term of the interface value (reading): phi W_tt, the
+   * equilibrium's W_tt weighted by phi(r), r the largest jump between the
+   * two sides relative to its scale: of the states (pressure and density:
+   * |a_l - a_r| / (a_l + a_r); velocity components: over the sum of the
+   * sound speeds) and of the normal derivatives over the distance a sound
+   * wave covers in dt (dt c |d_l - d_r| over the variable's scale: the
+   * density sum, that sum times c for the momenta, the energy sum; c the
+   * mean sound speed). phi = 1 for r <= r1 = 1e-2, 1 - x^2 with
+   * x = (r - r1) / (r0 - r1) up to r0 = 1e-1, and 0 beyond: 1 for smooth
+   * data, whose two sides agree in state and slope up to the truncation
+   * error, and 0 at a discontinuity of the state or of its slope (a shock,
+   * a contact, the foot of a shock), where the interface value keeps the
+   * BGK solution's own time dependence. phi is continuous, and exactly 1
+   * over the range of smooth data. */
+  double phi = second_order_weight(P, &pl, &pr, Wl, Wr, dnl, dnr, dt);
+  if (phi > 0.0) {
+    equilibrium_wtt(P, &pc, ac, bc, Ac, snn, snt, stt, Wtt);
+    for (int k = 0; k < nv; ++k) Wtt[k] *= phi;
+  } else {
+    for (int k = 0; k < nv; ++k) Wtt[k] = 0.0;
+  }
 
   /* moment vectors */
   poly u1, v1, pa, pb, t1, t2, uone;

@@ -180,29 +180,27 @@ def edge_points(tri):
     return out
 
 
-def reconstruct(mesh, W, dW, prm=None, cells=None, chi_given=None):
+def reconstruct(mesh, W, dW, prm=None, cells=None):
     """GENO states of every cell (or of the listed cells) at the Gauss points
     of its edges. W [nv, ncell] cell averages, dW [2, nv, ncell] averaged
     gradients. Returns out [ncell, 3 edges, 2 points, nv, 3 (value, h d/dx,
-    h d/dy)], chi [ncell, nv] and the indicators {ISH, IStau, ISL} [ncell, nv]
-    (rows of cells not listed stay zero). chi_given [ncell, nv], if set,
-    replaces the path function in the blend (to compare the blended states
-    of another implementation whose chi differs by rounding)."""
+    h d/dy)], chi [ncell, nv] and info: the indicators {ISH, IStau, ISL}
+    [ncell, nv] and the two candidates of the blend, high (the cubic q^H) and
+    low (q^L), in the layout of out (rows of cells not listed stay zero)."""
     prm = params() if prm is None else prm
     W = np.asarray(W, dtype=np.float64)
     dW = np.asarray(dW, dtype=np.float64)
     nv, n = W.shape
     out = np.zeros((n, 3, 2, nv, 3))
     chi = np.zeros((n, nv))
-    info = {"ISH": np.zeros((n, nv)), "IStau": np.zeros((n, nv)), "ISL": np.zeros((n, nv))}
+    info = {"ISH": np.zeros((n, nv)), "IStau": np.zeros((n, nv)), "ISL": np.zeros((n, nv)),
+            "high": np.zeros((n, 3, 2, nv, 3)), "low": np.zeros((n, 3, 2, nv, 3))}
     for c in (range(n) if cells is None else cells):
         fit = cell_fit(mesh, W, dW, c)
         ISH, _, IStau, ISk = indicators(fit)
         k0 = ISk.shape[0]
         ISL = (ISk.sum(axis=0) - ISk.min(axis=0) - ISk.max(axis=0)) / (k0 - 2)
         x, _ = path(prm, IStau, ISH, ISL)
-        if chi_given is not None:
-            x = np.asarray(chi_given[c], dtype=np.float64)
         wt = prm["d"][:, None] / (ISk + prm["eps"]) ** prm["rL"]
         wt = wt / wt.sum(axis=0)
         chi[c] = x
@@ -219,4 +217,9 @@ def reconstruct(mesh, W, dW, prm=None, cells=None, chi_given=None):
         hgy = x[:, None] * h * gy3 + (1.0 - x[:, None]) * gL[:, 1, None]
         o = np.stack([val, hgx, hgy], axis=-1)      # [nv, 6, 3]
         out[c] = o.transpose(1, 0, 2).reshape(3, 2, nv, 3)
+        hi = np.stack([v3, h * gx3, h * gy3], axis=-1)
+        lo = np.stack([vL, np.broadcast_to(gL[:, 0, None], vL.shape), np.broadcast_to(gL[:, 1, None], vL.shape)],
+                      axis=-1)
+        info["high"][c] = hi.transpose(1, 0, 2).reshape(3, 2, nv, 3)
+        info["low"][c] = lo.transpose(1, 0, 2).reshape(3, 2, nv, 3)
     return out, chi, info

@@ -82,15 +82,21 @@ GENO_HD D eps_of(D qmax, const KParams& k) {
 }
 
 // Linear high-order reconstruction p^7 on S_0 = {j-1, j, j+1, j+2} (Sec. 4.2)
-// at x_{j+1/2}: value and h * derivative of the degree-7 polynomial whose cell
-// averages and averaged h-scaled derivatives match those of the four cells.
-// Written in symmetric pairs so that the mirrored evaluation is exact.
+// at x_{j+1/2}: value and h * derivative (linear_p7) and h^2 * second
+// derivative (linear_p7_d2) of the degree-7 polynomial whose cell averages
+// and averaged h-scaled derivatives match those of the four cells. Written
+// in symmetric pairs so that the mirrored evaluation is exact (the second
+// derivative is even under the mirror).
 template <typename R>
 GENO_HD void linear_p7(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2, R& qH, R& hqH) {
   qH = (R(5.0) * (Qm + Q2) + R(37.0) * (Q0 + Q1)) * R(1.0 / 84.0) +
        ((Gm - G2) + R(17.0) * (G0 - G1)) * R(1.0 / 70.0);
   hqH = R(7.0) * (Q2 - Qm) * R(1.0 / 54.0) + R(2.5) * (Q1 - Q0) -
         ((Gm + G2) * R(1.0 / 36.0) + R(11.0) * (G0 + G1) * R(1.0 / 12.0));
+}
+template <typename R>
+GENO_HD R linear_p7_d2(R Qm, R Q0, R Q1, R Q2, R Gm, R G0, R G1, R G2) {
+  return ((Q0 + Q1) - (Qm + Q2)) + (R(9.0) * (G1 - G0) + (G2 - Gm)) * R(0.25);
 }
 
 // GENO value and h * derivative at the face on the right of cell j (the
@@ -127,8 +133,8 @@ GENO_HD SideQuads<D> side_quads(D Qm, D Q0, D Q1, D Q2, D Gm) {
 }
 
 template <typename R, typename D>
-GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, const KParams& k, R& val,
-                       R& hder, D& chi) {
+GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, R h2qH, const KParams& k,
+                       R& val, R& hder, R& h2der, D& chi) {
   const SideQuads<D> sq = side_quads<D>(Qm, Q0, Q1, Q2, Gm);
   const D Bd1 = sq.B1, Cd1 = sq.C1, Bd2 = sq.B2, Cd2 = sq.C2, Bd3 = sq.B3, Cd3 = sq.C3;
   const D IS1 = sq.IS1, IS2 = sq.IS2, IS3 = sq.IS3;
@@ -140,6 +146,7 @@ GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, const KParams&
   if (chi == 1.0) {
     val = qH;
     hder = hqH;
+    h2der = h2qH;
     return false;
   }
   D e1 = IS1 + eps, e2 = IS2 + eps, e3 = IS3 + eps;
@@ -156,42 +163,51 @@ GENO_HD bool geno_side(D Qm, D Q0, D Q1, D Q2, D Gm, R qH, R hqH, const KParams&
   const R p3 = q0 + R(0.5) * B3 + s6 * C3;
   const R qL = o1 * p1 + o2 * p2 + o3 * p3;
   const R hqL = o1 * (B1 + C1) + o2 * (B2 + C2) + o3 * (B3 + C3);
+  // second derivatives of the quadratics: h^2 p_k'' = 2 C_k
+  const R h2qL = R(2.0) * (o1 * C1 + o2 * C2 + o3 * C3);
   const R x = R(chi), xm = R(1.0 - chi);
   val = x * qH + xm * qL;
   hder = x * hqH + xm * hqL;
+  h2der = x * h2qH + xm * h2qL;
   return true;
 }
 
 // Both states at face j+1/2 for one component from cells j-1..j+2 (data in
 // the indicator type D, the linear part evaluated in R). The right state
 // (cell j+1) is the left-state formula applied to the data reflected about
-// the face: Q~_m = Q_{1-m}, G~_m = -G_{1-m}; its derivative changes sign.
-// A side marked skip (by the learned gate) takes chi = 1, the linear
-// reconstruction, without its indicators. Returns the number of sides on the
-// low-order branch.
+// the face: Q~_m = Q_{1-m}, G~_m = -G_{1-m}; its derivative changes sign, its
+// second derivative does not. A side marked skip (by the learned gate) takes
+// chi = 1, the linear reconstruction, without its indicators. h2: the mean of
+// the two sides' h^2 * second derivatives (the time stepping of the gradients
+// uses the mean). Returns the number of sides on the low-order branch.
 template <typename R, typename D>
 GENO_HD int geno_face(D Qm, D Q0, D Q1, D Q2, D Gm, D G0, D G1, D G2, const KParams& k, R& vl,
-                      R& dl, D& xl, R& vr, R& dr, D& xr, bool skipL = false,
+                      R& dl, D& xl, R& vr, R& dr, D& xr, R& h2, bool skipL = false,
                       bool skipR = false) {
   R qH, hqH;
   linear_p7<R>(R(Qm), R(Q0), R(Q1), R(Q2), R(Gm), R(G0), R(G1), R(G2), qH, hqH);
+  const R h2qH = linear_p7_d2<R>(R(Qm), R(Q0), R(Q1), R(Q2), R(Gm), R(G0), R(G1), R(G2));
   int n = 0;
+  R sl, sr;
   if (skipL) {
     vl = qH;
     dl = hqH;
+    sl = h2qH;
     xl = D(1.0);
   } else {
-    n += geno_side<R, D>(Qm, Q0, Q1, Q2, Gm, qH, hqH, k, vl, dl, xl);
+    n += geno_side<R, D>(Qm, Q0, Q1, Q2, Gm, qH, hqH, h2qH, k, vl, dl, sl, xl);
   }
   if (skipR) {
     vr = qH;
     dr = hqH;
+    sr = h2qH;
     xr = D(1.0);
   } else {
     R dm;
-    n += geno_side<R, D>(Q2, Q1, Q0, Qm, -G2, qH, -hqH, k, vr, dm, xr);
+    n += geno_side<R, D>(Q2, Q1, Q0, Qm, -G2, qH, -hqH, h2qH, k, vr, dm, sr, xr);
     dr = -dm;
   }
+  h2 = R(0.5) * (sl + sr);
   return n;
 }
 
@@ -245,9 +261,12 @@ GENO_HD D teno_chi(D IS1, D IS2, D IS3, D ct, const KParams& k) {
 // one the ENO combination (d = 1, r^L = 2) of the slopes s_- and s_+; the two
 // are blended by the path function with IS_+- = s_+-^2, IS^H = max,
 // IS^L = min, IS^tau = |IS_+ - IS_-|. Point 0 is at -eta, point 1 at +eta.
+// chi_t: the blend weight; h^2 * the second tangential derivative of the
+// blend is chi_t D2 (d2_out = D2; the low-order candidate is linear).
 // Returns true on the low-order branch.
 template <typename R, typename D>
-GENO_HD bool tangential(R phm, R ph0, R php, const KParams& k, R& v0, R& v1, R& t0, R& t1) {
+GENO_HD bool tangential(R phm, R ph0, R php, const KParams& k, R& v0, R& v1, R& t0, R& t1,
+                        R& chi_t, R& d2_out) {
   const R sm = ph0 - phm, sp = php - ph0;
   const R sc = R(0.5) * (sm + sp), d2 = sp - sm;
   const D ISm = D(sm * sm), ISp = D(sp * sp);
@@ -278,6 +297,8 @@ GENO_HD bool tangential(R phm, R ph0, R php, const KParams& k, R& v0, R& v1, R& 
   v1 = ph0 + eta * s;
   t0 = th0;
   t1 = th1;
+  chi_t = R(chi);
+  d2_out = d2;
   return low;
 }
 

@@ -390,7 +390,7 @@ __device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KP
   geno::Eig2 e;
   const bool ch = geno::roe_eigen2(Wa, Wb, k.gamma, e);
   unsigned int nlow = 0;
-  double wv[2][4], wd[2][4];
+  double wv[2][4], wd[2][4], w2[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     double Q[4], G[4];
@@ -406,14 +406,15 @@ __device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KP
         G[m] = Gv[c][m];
       }
     }
-    T vl, dl, vr, dr;
+    T vl, dl, vr, dr, h2;
     double xl, xr;
     nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl,
-                                       xl, vr, dr, xr);
+                                       xl, vr, dr, xr, h2);
     wv[0][c] = (double)vl;
     wd[0][c] = (double)dl;
     wv[1][c] = (double)vr;
     wd[1][c] = (double)dr;
+    w2[c] = (double)h2;
     if (chi) {
       // characteristic field c, or the state variable of slot c
       const int cv = ch ? c : VM[c];
@@ -440,6 +441,17 @@ __device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KP
       fr[(size_t)((2 * s + 1) * 4 + VM[f]) * plane + o] = T(Dv[f]);
     }
   }
+  // the mean of the two sides' h^2 * second derivatives, mapped back like
+  // the states (the map is linear and common to both sides)
+  double S2[4];
+  if (ch) {
+    geno::from_characteristic2(e, w2, S2);
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) S2[f] = w2[f];
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) fr[(size_t)(16 + VM[f]) * plane + o] = T(S2[f]);
   return nlow;
 }
 
@@ -449,7 +461,9 @@ __device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KP
 // b). DIR 1: faces a = 0..ny (between rows a-1 and a), columns b = 0..nx+1
 // (i = b-1). Thread index (v, a, b) with b fastest, so that a wave reads and
 // writes 64 consecutive entries of one plane.
-// fr: [side][quant(value, h d/dn)][var][a][b]; chi: [side][var][a][b].
+// fr: [side][quant(value, h d/dn)][var][a][b] (16 planes), then the mean
+// over the two sides of h^2 d^2/dn^2, [var][a][b] (4 planes); chi:
+// [side][var][a][b].
 // With part (first kernel of a step), block 0 also reduces the CFL partial
 // minima of the previous kernel into ctrl->tmin and records dt.
 // ---------------------------------------------------------------------------
@@ -498,14 +512,15 @@ __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k
       Q[m] = W[id];
       G[m] = h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
     }
-    T vl, dl, vr, dr;
+    T vl, dl, vr, dr, h2;
     double xl, xr;
     nlow = geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl,
-                                      xl, vr, dr, xr, skipL, skipR);
+                                      xl, vr, dr, xr, h2, skipL, skipR);
     fr[(size_t)(0 * 4 + v) * plane + o] = vl;
     fr[(size_t)(1 * 4 + v) * plane + o] = dl;
     fr[(size_t)(2 * 4 + v) * plane + o] = vr;
     fr[(size_t)(3 * 4 + v) * plane + o] = dr;
+    fr[(size_t)(16 + v) * plane + o] = h2;
     if (chi) {
       chi[(size_t)(0 * 4 + v) * plane + o] = xl;
       chi[(size_t)(1 * 4 + v) * plane + o] = xr;
@@ -587,6 +602,16 @@ __global__ void __launch_bounds__(BLOCK) k_linearity(Geo g, geno::KParams k, int
 // MODE 0: write the point states (geno_reconstruct).
 // MODE 1: flux for tau = 0; faces with tau > 0 at either point are queued.
 // MODE 2: flux of the queued faces with the full solution (grid-stride).
+// Second derivatives of a point (time stepping of the gradients): h_n^2 d_nn
+// is the normal step's mean of row t; per side h_t^2 d_tt = chi_t D2 and
+// h_n h_t d_nt = chi_t (psi_{t+1} - psi_{t-1})/2 from the tangential step of
+// the value (chi_t, D2) and the h-scaled normal derivatives psi of the three
+// rows; the point takes the mean of the two sides, and zero if a side is
+// guarded.
+// Flux outputs, Gauss-averaged, [kind][var][face]: stage 1 (want_F) F, dF/dt,
+// W(dt/2) + dt^2/8 W_tt and W(dt) + dt^2/6 W_tt (the interface values at the
+// stage time and the first part of those at the end of the step); stage 2
+// dF/dt in kind 1 and W_tt in kind 2.
 // ---------------------------------------------------------------------------
 // Value of the partner lane (lane ^ 1) by a DPP quad permutation [1, 0, 3, 2]
 // (a VALU move, no trip through LDS). Both lanes of a pair are always active
@@ -630,19 +655,23 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   const size_t rm = (size_t)a * fg.r1 + b;
   const size_t rc = DIR == 0 ? rm + fg.r1 : rm + 1;
   const size_t rp = DIR == 0 ? rc + fg.r1 : rc + 1;
-  // tangential step of side q for both points
-  T own_v[4], own_t[4], snd_v[4], snd_t[4], dn[4];
+  // tangential step of side q for both points, and the side's second
+  // tangential and cross derivatives
+  T own_v[4], own_t[4], snd_v[4], snd_t[4], dn[4], s_tt[4], s_nt[4];
   unsigned int nlow = 0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const T* p = fr + (size_t)((2 * q + 0) * 4 + v) * rplane;
-    T v0, v1, t0, t1;
-    nlow += geno::tangential<T, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1);
+    const T* pd = fr + (size_t)((2 * q + 1) * 4 + v) * rplane;
+    T v0, v1, t0, t1, cht, d2;
+    nlow += geno::tangential<T, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1, cht, d2);
     own_v[v] = q ? v1 : v0;
     own_t[v] = q ? t1 : t0;
     snd_v[v] = q ? v0 : v1;
     snd_t[v] = q ? t0 : t1;
-    dn[v] = fr[(size_t)((2 * q + 1) * 4 + v) * rplane + rc];
+    dn[v] = pd[rc];
+    s_tt[v] = cht * d2;
+    s_nt[v] = cht * (T(0.5) * (pd[rp] - pd[rm]));
   }
   // states of both sides at this lane's point
   T S[2][4], Dn[2][4], Dt[2][4];
@@ -657,6 +686,9 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
     Dt[1][v] = q ? own_t[v] : rt;
     Dn[0][v] = q ? rd : dn[v];
     Dn[1][v] = q ? dn[v] : rd;
+    // the mean of the two sides (the same sum in both lanes)
+    s_tt[v] = T(0.5) * (s_tt[v] + pair_swap(s_tt[v]));
+    s_nt[v] = T(0.5) * (s_nt[v] + pair_swap(s_nt[v]));
   }
   // positivity guard per side: fall back to the own cell average
   unsigned int nguard = 0;
@@ -674,6 +706,12 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       }
     }
   }
+  T s_nn[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    s_nn[v] = nguard ? T(0) : fr[(size_t)(16 + v) * rplane + rc];
+    if (nguard) s_tt[v] = s_nt[v] = T(0);
+  }
   if (!valid) nguard = nlow = 0;
   const size_t plane = (size_t)nfaces;
   const size_t o = (size_t)fc;
@@ -688,14 +726,23 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
           out[(base + 1 * 4 + v) * plane + o] = Dn[s][v];
           out[(base + 2 * 4 + v) * plane + o] = Dt[s][v];
         }
+      // second derivatives of this lane's point, after the 48 state planes
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t base = (size_t)48 + (size_t)(q * 3) * 4;
+        out[(base + 0 * 4 + v) * plane + o] = s_nn[v];
+        out[(base + 1 * 4 + v) * plane + o] = s_nt[v];
+        out[(base + 2 * 4 + v) * plane + o] = s_tt[v];
+      }
     }
   } else {
     const double dt = dt_of(ctrl);
     const double hn = DIR == 0 ? g.dx : g.dy, ht = DIR == 0 ? g.dy : g.dx;
     const T ihn = T(1.0 / hn), iht = T(1.0 / ht);
+    const T inn = T(1.0 / (hn * hn)), int_ = T(1.0 / (hn * ht)), itt = T(1.0 / (ht * ht));
     constexpr int p1 = DIR == 0 ? 1 : 2, p2 = DIR == 0 ? 2 : 1;
     constexpr int perm[4] = {0, p1, p2, 3};
-    T Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4];
+    T Wl[4], Wr[4], nl[4], nr[4], tl[4], tr[4], xnn[4], xnt[4], xtt[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       Wl[v] = S[0][perm[v]];
@@ -704,15 +751,18 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       nr[v] = Dn[1][perm[v]] * ihn;
       tl[v] = Dt[0][perm[v]] * iht;
       tr[v] = Dt[1][perm[v]] * iht;
+      xnn[v] = s_nn[perm[v]] * inn;
+      xnt[v] = s_nt[perm[v]] * int_;
+      xtt[v] = s_tt[perm[v]] * itt;
     }
-    T F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wi[4] = {0, 0, 0, 0};
+    gks::PointOut<4, T> po;
     int pk;   // point kind; MODE 1: PT_SLOW not evaluated; MODE 2: evaluated
     if constexpr (MODE == 1)
-      pk = gks::point_flux<4, false, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F, Ft,
-                                        Wi);
+      pk = gks::point_flux<4, false, T>(Wl, Wr, nl, nr, tl, tr, xnn, xnt, xtt, dt, k, want_F != 0,
+                                        po);
     else
-      pk = gks::point_flux<4, true, T>(Wl, Wr, nl, nr, tl, tr, dt, k, T(0.5), want_F != 0, F, Ft,
-                                       Wi);
+      pk = gks::point_flux<4, true, T>(Wl, Wr, nl, nr, tl, tr, xnn, xnt, xtt, dt, k, want_F != 0,
+                                       po);
     const bool slow = pk == gks::PT_SLOW;
     bool pair_slow = false;
     if constexpr (MODE == 1) {
@@ -734,16 +784,32 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       }
     }
     if (nguard && (MODE == 2 || !pair_slow)) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
-    // Gauss average: add the partner's half
-    T So[12];
+    // this point's share of the Gauss average (weights 1/2) of the stage's
+    // four outputs: stage 1 F, dF/dt, W(dt/2) + dt^2/8 W_tt, W(dt) + dt^2/6
+    // W_tt; stage 2 -, dF/dt, W_tt, -. Results of a PT_SLOW point in MODE 1
+    // are not formed (the face is written by MODE 2).
+    T So[16];
+    const T c8 = T(dt * dt / 8.0), c6 = T(dt * dt / 6.0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      So[v] = F[v] + pair_swap(F[v]);
-      So[4 + v] = Ft[v] + pair_swap(Ft[v]);
-      So[8 + v] = Wi[v] + pair_swap(Wi[v]);
+      if (slow && MODE == 1) {
+        So[v] = So[4 + v] = So[8 + v] = So[12 + v] = T(0);
+      } else if (want_F) {
+        So[v] = T(0.5) * po.F[v];
+        So[4 + v] = T(0.5) * po.Ft[v];
+        So[8 + v] = T(0.5) * (po.Wh[v] + c8 * po.Wtt[v]);
+        So[12 + v] = T(0.5) * (po.Wf[v] + c6 * po.Wtt[v]);
+      } else {
+        So[v] = So[12 + v] = T(0);
+        So[4 + v] = T(0.5) * po.Ft[v];
+        So[8 + v] = T(0.5) * po.Wtt[v];
+      }
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) So[e] = So[e] + pair_swap(So[e]);
     if (valid && !pair_slow) {
-      // back to the (x, y) frame; lane 0 writes F and Ft, lane 1 writes W_int
+      // back to the (x, y) frame; lane 0 writes kinds 0, 1 and lane 1 kinds
+      // 2, 3 (stage 2: lane 0 dF/dt, lane 1 W_tt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int pv = perm[v];
@@ -752,6 +818,7 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
           out[(size_t)(1 * 4 + pv) * plane + o] = So[4 + v];
         } else {
           out[(size_t)(2 * 4 + pv) * plane + o] = So[8 + v];
+          if (want_F) out[(size_t)(3 * 4 + pv) * plane + o] = So[12 + v];
         }
       }
     }
@@ -863,8 +930,10 @@ __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
 // ---------------------------------------------------------------------------
 // 1-D faces: normal GENO of the three variables at face f (cells f-2..f+1),
 // guard, then states (MODE 0) or flux (MODE 1). out as the 2-D layouts with
-// one Gauss point: states [side][quant(2)][var][f], flux [kind][var][f].
-// The 1-D step is reduced before this kernel (k_dt1d).
+// one Gauss point: states [side][quant(2)][var][f] followed by the mean
+// h^2 d^2/dx^2 [var][f] (zero if a side is guarded), flux [kind][var][f]
+// with the kinds of the 2-D face step. The 1-D step is reduced before this
+// kernel (k_dt1d).
 // ---------------------------------------------------------------------------
 template <int MODE, typename T>
 __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
@@ -878,7 +947,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
   unsigned int nlow = 0, nguard = 0;
   int pk = -1;
   if (f < nfc) {
-    T S[2][3], Dn[2][3];
+    T S[2][3], Dn[2][3], D2[3];
     // characteristic variables: the left eigenvectors at the Roe average of
     // cells f-1 and f (both stencil quantities projected), back with the
     // right ones; a face without a real sound speed stays conservative
@@ -903,7 +972,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
           Qv[v][m] = W[id];
           Gv[v][m] = g.dx * (double)dW[id];
         }
-      double wv[2][3], wd[2][3];
+      double wv[2][3], wd[2][3], w2[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double Q[4], G[4];
@@ -912,14 +981,15 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
           Q[m] = e.L[c][0] * Qv[0][m] + e.L[c][1] * Qv[1][m] + e.L[c][2] * Qv[2][m];
           G[m] = e.L[c][0] * Gv[0][m] + e.L[c][1] * Gv[1][m] + e.L[c][2] * Gv[2][m];
         }
-        T s0, d0, s1, d1;
+        T s0, d0, s1, d1, h2;
         double xl, xr;
         nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
-                                           s0, d0, xl, s1, d1, xr);
+                                           s0, d0, xl, s1, d1, xr, h2);
         wv[0][c] = (double)s0;
         wd[0][c] = (double)d0;
         wv[1][c] = (double)s1;
         wd[1][c] = (double)d1;
+        w2[c] = (double)h2;
         if (chi) {
           chi[(size_t)(0 * 3 + c) * nfc + f] = xl;
           chi[(size_t)(1 * 3 + c) * nfc + f] = xr;
@@ -936,6 +1006,10 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
           Dn[s][v] = T(Dv[v]);
         }
       }
+      double S2[3];
+      geno6::from_characteristic(e, w2, S2);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) D2[v] = T(S2[v]);
     } else {
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
@@ -948,7 +1022,7 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
         }
         double xl, xr;
         nlow += geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k,
-                                           S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr);
+                                           S[0][v], Dn[0][v], xl, S[1][v], Dn[1][v], xr, D2[v]);
         if (chi) {
           chi[(size_t)(0 * 3 + v) * nfc + f] = xl;
           chi[(size_t)(1 * 3 + v) * nfc + f] = xr;
@@ -967,6 +1041,9 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
       }
     }
     if (nguard && ctrl) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
+    if (nguard)
+#pragma unroll
+      for (int v = 0; v < 3; ++v) D2[v] = T(0);
     if constexpr (MODE == 0) {
 #pragma unroll
       for (int s = 0; s < 2; ++s)
@@ -975,23 +1052,32 @@ __global__ void __launch_bounds__(BLOCK) k_faces1d(Geo g, geno::KParams k,
           out[(size_t)((s * 2 + 0) * 3 + v) * nfc + f] = S[s][v];
           out[(size_t)((s * 2 + 1) * 3 + v) * nfc + f] = Dn[s][v];
         }
+#pragma unroll
+      for (int v = 0; v < 3; ++v) out[(size_t)(12 + v) * nfc + f] = D2[v];
     } else {
       const double dt = dt_of(ctrl);
-      const T ih = T(1.0 / g.dx);
-      T nl[3], nr[3];
+      const T ih = T(1.0 / g.dx), ih2 = T(1.0 / (g.dx * g.dx));
+      T nl[3], nr[3], xx[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         nl[v] = Dn[0][v] * ih;
         nr[v] = Dn[1][v] * ih;
+        xx[v] = D2[v] * ih2;
       }
-      T F[3] = {0, 0, 0}, Ft[3] = {0, 0, 0}, Wi[3] = {0, 0, 0};
-      pk = gks::point_flux<3, true, T>(S[0], S[1], nl, nr, nullptr, nullptr, dt, k, T(1.0),
-                                       want_F != 0, F, Ft, Wi);
+      gks::PointOut<3, T> po;
+      pk = gks::point_flux<3, true, T>(S[0], S[1], nl, nr, nullptr, nullptr, xx, nullptr, nullptr,
+                                       dt, k, want_F != 0, po);
+      const T c8 = T(dt * dt / 8.0), c6 = T(dt * dt / 6.0);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        if (want_F) out[(size_t)(0 * 3 + v) * nfc + f] = F[v];
-        out[(size_t)(1 * 3 + v) * nfc + f] = Ft[v];
-        out[(size_t)(2 * 3 + v) * nfc + f] = Wi[v];
+        out[(size_t)(1 * 3 + v) * nfc + f] = po.Ft[v];
+        if (want_F) {
+          out[(size_t)(0 * 3 + v) * nfc + f] = po.F[v];
+          out[(size_t)(2 * 3 + v) * nfc + f] = po.Wh[v] + c8 * po.Wtt[v];
+          out[(size_t)(3 * 3 + v) * nfc + f] = po.Wf[v] + c6 * po.Wtt[v];
+        } else {
+          out[(size_t)(2 * 3 + v) * nfc + f] = po.Wtt[v];
+        }
       }
     }
   }
@@ -1062,7 +1148,10 @@ __global__ void __launch_bounds__(BLOCK) k_dt1d(const double* __restrict__ part,
   reduce_dt(part, npart, ctrl, cfl, dt_fixed, dt_out, step);
 }
 
-// gks_flux on caller-given point states (layout of geno_reconstruct).
+// gks_flux on caller-given point states (layout of geno_reconstruct: the
+// point states, then the points' h-scaled second derivatives). Outputs the
+// Gauss averages of F, dF/dt, and in Wi three blocks [W(dt/2), W(dt),
+// W_tt][var][face].
 template <int NV, typename T>
 __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, int dir,
                                                        geno::KParams k, double hn, double ht,
@@ -1072,47 +1161,72 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= nfaces) return;
   constexpr int Q = NV == 4 ? 3 : 2;
+  constexpr int NQ2 = NV == 4 ? 3 : 1;   // second-derivative quantities per point
   const T w = T(1.0 / ngauss);
   const T ihn = T(1.0 / hn), iht = T(1.0 / ht);
+  const T inn = T(1.0 / (hn * hn)), int_ = T(1.0 / (hn * ht)), itt = T(1.0 / (ht * ht));
   const int perm[4] = {0, dir == 0 ? 1 : 2, dir == 0 ? 2 : 1, 3};
-  T Fa[NV], Fta[NV], Wia[NV];
+  const size_t sec0 = (size_t)2 * ngauss * Q * NV;
+  T A[5][NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Fa[v] = Fta[v] = Wia[v] = T(0);
+  for (int e = 0; e < 5; ++e)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[e][v] = T(0);
   for (int q = 0; q < ngauss; ++q) {
-    T Ws[2][NV], ns[2][NV], ts[2][NV];
+    T Ws[2][NV], ns[2][NV], ts[2][NV], xnn[NV], xnt[NV], xtt[NV];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int v = 0; v < NV; ++v) {
+      const int pv = NV == 4 ? perm[v] : v;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int pv = NV == 4 ? perm[v] : v;
+      for (int s = 0; s < 2; ++s) {
         const size_t base = (size_t)((s * ngauss + q) * Q) * NV;
         Ws[s][v] = st[(base + 0 * NV + pv) * nfaces + o];
         ns[s][v] = st[(base + 1 * NV + pv) * nfaces + o] * ihn;
         ts[s][v] = NV == 4 ? st[(base + 2 * NV + pv) * nfaces + o] * iht : T(0);
       }
-    gks::point_flux<NV, true, T>(Ws[0], Ws[1], ns[0], ns[1], ts[0], ts[1], dt, k, w, true, Fa,
-                                 Fta, Wia);
+      const size_t sb = sec0 + (size_t)(q * NQ2) * NV;
+      xnn[v] = st[(sb + pv) * nfaces + o] * inn;
+      xnt[v] = NV == 4 ? st[(sb + NV + pv) * nfaces + o] * int_ : T(0);
+      xtt[v] = NV == 4 ? st[(sb + 2 * NV + pv) * nfaces + o] * itt : T(0);
+    }
+    gks::PointOut<NV, T> po;
+    gks::point_flux<NV, true, T>(Ws[0], Ws[1], ns[0], ns[1], ts[0], ts[1], xnn, xnt, xtt, dt, k,
+                                 true, po);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      A[0][v] = A[0][v] + w * po.F[v];
+      A[1][v] = A[1][v] + w * po.Ft[v];
+      A[2][v] = A[2][v] + w * po.Wh[v];
+      A[3][v] = A[3][v] + w * po.Wf[v];
+      A[4][v] = A[4][v] + w * po.Wtt[v];
+    }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int pv = NV == 4 ? perm[v] : v;
-    if (F) F[(size_t)pv * nfaces + o] = Fa[v];
-    if (Ft) Ft[(size_t)pv * nfaces + o] = Fta[v];
-    if (Wi) Wi[(size_t)pv * nfaces + o] = Wia[v];
+    if (F) F[(size_t)pv * nfaces + o] = A[0][v];
+    if (Ft) Ft[(size_t)pv * nfaces + o] = A[1][v];
+    if (Wi)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) Wi[(size_t)(e * NV + pv) * nfaces + o] = A[2 + e][v];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Cell update. STAGE 1: W* = W + dt/2 L + dt^2/8 Lt, R = W + dt L + dt^2/6 Lt,
-// grad* from W_int (Eq. (2)). STAGE 2: W = R + dt^2/3 Lt*, grad from the
-// stage-2 W_int, and the CFL minima of the new state per block. Both write
-// the ghost cells of the state they produce.
+// Cell update (two-stage fourth-order method). STAGE 1: W* = W + dt/2 L +
+// dt^2/8 Lt, R = W + dt L + dt^2/6 Lt; grad* by the Gauss theorem (Eq. (2))
+// from the interface values at the stage time, W(dt/2) + dt^2/8 W_tt, and
+// RG from W(dt) + dt^2/6 W_tt. STAGE 2: W = R + dt^2/3 Lt*, grad = RG +
+// dt^2/3 (Gauss theorem on W_tt*), and the CFL minima of the new state per
+// block. Both write the ghost cells of the state they produce. RG has the
+// layout of the gradients (interior cells only).
 // ---------------------------------------------------------------------------
 template <int NDIM, int STAGE, typename T>
 __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k,
                                             const double* __restrict__ Win,
                                             double* __restrict__ Wout, T* __restrict__ dWout,
-                                            double* __restrict__ R, const T* __restrict__ fx,
+                                            double* __restrict__ R, T* __restrict__ RG,
+                                            const T* __restrict__ fx,
                                             const T* __restrict__ fy, Ctrl* ctrl,
                                             double* __restrict__ part, const Cnt& cnt, int lb) {
   constexpr int NV = NDIM == 2 ? 4 : 3;
@@ -1130,18 +1244,20 @@ __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k
     const auto X = [&](int plane, size_t o) { return (double)fx[plane * px + o]; };
     const auto Y = [&](int plane, size_t o) { return (double)fy[plane * py + o]; };
     const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+    const double c3 = dt * dt / 3.0;
     double w[NV];
     T dw[NV * NDIM];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      double l, lt;
-      dw[v] = T((X(2 * NV + v, ox + 1) - X(2 * NV + v, ox)) * idx);
+      double l, lt, gx, gy = 0.0;
+      // Gauss theorem on kind 2: W(dt/2) + dt^2/8 W_tt (stage 1), W_tt* (stage 2)
+      gx = (X(2 * NV + v, ox + 1) - X(2 * NV + v, ox)) * idx;
       if constexpr (NDIM == 2) {
         l = -dot2(X(0 * NV + v, ox + 1) - X(0 * NV + v, ox), idx,
                   Y(0 * NV + v, oy + g.nx) - Y(0 * NV + v, oy), idy);
         lt = -dot2(X(1 * NV + v, ox + 1) - X(1 * NV + v, ox), idx,
                    Y(1 * NV + v, oy + g.nx) - Y(1 * NV + v, oy), idy);
-        dw[NV + v] = T((Y(2 * NV + v, oy + g.nx) - Y(2 * NV + v, oy)) * idy);
+        gy = (Y(2 * NV + v, oy + g.nx) - Y(2 * NV + v, oy)) * idy;
       } else {
         l = -(X(0 * NV + v, ox + 1) - X(0 * NV + v, ox)) * idx;
         lt = -(X(1 * NV + v, ox + 1) - X(1 * NV + v, ox)) * idx;
@@ -1151,9 +1267,18 @@ __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k
         const double w0 = Win[c];
         w[v] = w0 + 0.5 * dt * l + dt * dt / 8.0 * lt;
         R[c] = w0 + dt * l + dt * dt / 6.0 * lt;
+        dw[v] = T(gx);
+        // kind 3: W(dt) + dt^2/6 W_tt
+        RG[at(g, v, j, i)] = T((X(3 * NV + v, ox + 1) - X(3 * NV + v, ox)) * idx);
+        if constexpr (NDIM == 2) {
+          dw[NV + v] = T(gy);
+          RG[at(g, NV + v, j, i)] = T((Y(3 * NV + v, oy + g.nx) - Y(3 * NV + v, oy)) * idy);
+        }
       } else {
         (void)l;
-        w[v] = R[c] + dt * dt / 3.0 * lt;
+        w[v] = R[c] + c3 * lt;
+        dw[v] = T((double)RG[at(g, v, j, i)] + c3 * gx);
+        if constexpr (NDIM == 2) dw[NV + v] = T((double)RG[at(g, NV + v, j, i)] + c3 * gy);
       }
       Wout[c] = w[v];
     }
@@ -1185,11 +1310,12 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
                                                   const double* __restrict__ Win,
                                                   double* __restrict__ Wout,
                                                   T* __restrict__ dWout,
-                                                  double* __restrict__ R,
+                                                  double* __restrict__ R, T* __restrict__ RG,
                                                   const T* __restrict__ fx,
                                                   const T* __restrict__ fy, Ctrl* ctrl,
                                                   double* __restrict__ part, Cnt cnt) {
-  update_body<NDIM, STAGE, T>(g, k, Win, Wout, dWout, R, fx, fy, ctrl, part, cnt, xcd_block());
+  update_body<NDIM, STAGE, T>(g, k, Win, Wout, dWout, R, RG, fx, fy, ctrl, part, cnt,
+                              xcd_block());
 }
 
 // ---------------------------------------------------------------------------
@@ -1401,8 +1527,11 @@ __global__ void __launch_bounds__(BLOCK) k_harvest(Geo g, geno::KParams k,
       double val, der, xl, xr;
       // left state of face j+1/2 (cells j-1..j+2) and right state of face j-1/2
       // (cells j-2..j+1 reflected about that face)
-      geno::geno_side<double, double>(q[1], q[2], q[3], q[4], d[1], 0.0, 0.0, k, val, der, xl);
-      geno::geno_side<double, double>(q[3], q[2], q[1], q[0], -d[3], 0.0, 0.0, k, val, der, xr);
+      double d2;
+      geno::geno_side<double, double>(q[1], q[2], q[3], q[4], d[1], 0.0, 0.0, 0.0, k, val, der, d2,
+                                      xl);
+      geno::geno_side<double, double>(q[3], q[2], q[1], q[0], -d[3], 0.0, 0.0, 0.0, k, val, der, d2,
+                                      xr);
       tmin = fmin(tmin, fmin(xl, xr));
     }
   }
@@ -1429,6 +1558,7 @@ struct BEntry {
   double* wst;
   double* r;
   void* dwst;
+  void* rg;
   void* fr[2];
   void* fl[2];
   int npart;     // update work-groups of this grid (CFL partials)
@@ -1507,10 +1637,10 @@ __global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
   const int gi = find_grid(st, ngrids, gb);
   const BEntry& e = tab[gi];
   if (STAGE == 1)
-    update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (const T*)e.fl[0],
+    update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (T*)e.rg, (const T*)e.fl[0],
                          (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
   else
-    update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (const T*)e.fl[0],
+    update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (T*)e.rg, (const T*)e.fl[0],
                          (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
 }
 
@@ -1518,7 +1648,7 @@ __global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
 // host helpers
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t ctrl, part, queue[2], gate, wst, dwst, r, fr[2], fl[2], total;
+  size_t ctrl, part, queue[2], gate, wst, dwst, r, rg, fr[2], fl[2], total;
   size_t nstate;   // elements per field plane
   int npart;
 };
@@ -1557,18 +1687,20 @@ Layout layout_of(const geno_grid* g) {
   off = align256(off + L.nstate * nv * g->ndim * es);
   L.r = off;
   off = align256(off + L.nstate * nv * sizeof(double));
+  L.rg = off;   // the gradients' share of the end-of-step interface values
+  off = align256(off + L.nstate * nv * g->ndim * es);
   if (g->ndim == 2) {
     L.fr[0] = off;
-    off = align256(off + (size_t)16 * (g->ny + 2) * (g->nx + 1) * es);
+    off = align256(off + (size_t)20 * (g->ny + 2) * (g->nx + 1) * es);
     L.fr[1] = off;
-    off = align256(off + (size_t)16 * (g->ny + 1) * (g->nx + 2) * es);
+    off = align256(off + (size_t)20 * (g->ny + 1) * (g->nx + 2) * es);
     L.fl[0] = off;
-    off = align256(off + (size_t)12 * g->ny * (g->nx + 1) * es);
+    off = align256(off + (size_t)16 * g->ny * (g->nx + 1) * es);
     L.fl[1] = off;
-    off = align256(off + (size_t)12 * (g->ny + 1) * g->nx * es);
+    off = align256(off + (size_t)16 * (g->ny + 1) * g->nx * es);
   } else {
     L.fl[0] = off;
-    off = align256(off + (size_t)9 * (g->nx + 1) * es);
+    off = align256(off + (size_t)15 * (g->nx + 1) * es);
   }
   L.total = off;
   return L;
@@ -1625,8 +1757,8 @@ int check_grid(const geno_grid* g) {
   if (((imaged(0) || imaged(1)) && g->nx < NG) ||
       (g->ndim == 2 && (imaged(2) || imaged(3)) && g->ny < NG))
     return fail(GENO_EINVAL, "periodic or reflecting axis needs at least %d cells", NG);
-  // 32-bit thread indexing: two lanes per face and 16 face-row planes
-  if ((size_t)(g->nx + 4) * (g->ny + 4) * 16 > (size_t)0x7fffffff)
+  // 32-bit thread indexing: two lanes per face and 20 face-row planes
+  if ((size_t)(g->nx + 4) * (g->ny + 4) * 20 > (size_t)0x7fffffff)
     return fail(GENO_EINVAL, "grid too large for 32-bit thread indexing");
   if (!(g->dx > 0.0) || !(g->dy > 0.0)) return fail(GENO_EINVAL, "bad cell size");
   return GENO_OK;
@@ -1675,7 +1807,7 @@ struct Bufs {
   unsigned int* queue[2];
   unsigned char* gate;
   double *wst, *r;
-  T *dwst, *fr[2], *fl[2];
+  T *dwst, *rg, *fr[2], *fl[2];
 };
 
 template <typename T>
@@ -1686,6 +1818,7 @@ Bufs<T> bufs_of(char* ws, const Layout& L, int ndim) {
   b.wst = reinterpret_cast<double*>(ws + L.wst);
   b.dwst = reinterpret_cast<T*>(ws + L.dwst);
   b.r = reinterpret_cast<double*>(ws + L.r);
+  b.rg = reinterpret_cast<T*>(ws + L.rg);
   b.fl[0] = reinterpret_cast<T*>(ws + L.fl[0]);
   if (ndim == 2) {
     b.queue[0] = reinterpret_cast<unsigned int*>(ws + L.queue[0]);
@@ -1772,12 +1905,16 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
     const unsigned char* gx = nullptr;
     const unsigned char* gy = nullptr;
     if (k.gate) {
+      // the gate is evaluated once per step, on the state at its start; the
+      // second stage reuses those flags
       const size_t nc = (size_t)g->nx * g->ny;
       const unsigned nbg = gate_blocks(nc);
-      HIP_TRY(launch(GENO_K_GATE, k_gate<0, T, 0>, nbg, s, geo, Win, dWin, (float)k.gate_thr,
-                     B.gate, (float*)nullptr));
-      HIP_TRY(launch(GENO_K_GATE, k_gate<1, T, 0>, nbg, s, geo, Win, dWin, (float)k.gate_thr,
-                     B.gate + nc, (float*)nullptr));
+      if (stage == 1) {
+        HIP_TRY(launch(GENO_K_GATE, k_gate<0, T, 0>, nbg, s, geo, Win, dWin, (float)k.gate_thr,
+                       B.gate, (float*)nullptr));
+        HIP_TRY(launch(GENO_K_GATE, k_gate<1, T, 0>, nbg, s, geo, Win, dWin, (float)k.gate_thr,
+                       B.gate + nc, (float*)nullptr));
+      }
       gx = B.gate;
       gy = B.gate + nc;
     }
@@ -1805,17 +1942,17 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
   const T* fy = g->ndim == 2 ? B.fl[1] : nullptr;
   if (g->ndim == 2) {
     if (stage == 1)
-      HIP_TRY(launch(kind, k_update<2, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
+      HIP_TRY(launch(kind, k_update<2, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.rg, B.fl[0], fy,
                      B.ctrl, B.part, cnt));
     else
-      HIP_TRY(launch(kind, k_update<2, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0],
+      HIP_TRY(launch(kind, k_update<2, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.rg, B.fl[0],
                      fy, B.ctrl, B.part, cnt));
   } else {
     if (stage == 1)
-      HIP_TRY(launch(kind, k_update<1, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
+      HIP_TRY(launch(kind, k_update<1, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.rg, B.fl[0], fy,
                      B.ctrl, B.part, cnt));
     else
-      HIP_TRY(launch(kind, k_update<1, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0],
+      HIP_TRY(launch(kind, k_update<1, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.rg, B.fl[0],
                      fy, B.ctrl, B.part, cnt));
   }
   return GENO_OK;
@@ -2037,6 +2174,7 @@ void bind_batch(BatchPlan* P, char* ws, void* const* W, void* const* dW, const g
     e.wst = reinterpret_cast<double*>(b + L.wst);
     e.r = reinterpret_cast<double*>(b + L.r);
     e.dwst = b + L.dwst;
+    e.rg = b + L.rg;
     e.fr[0] = b + L.fr[0];
     e.fr[1] = b + L.fr[1];
     e.fl[0] = b + L.fl[0];

@@ -19,6 +19,15 @@
 // rho_c <(abar u + bbar v) psi>_c = -W_t and rho_c <Abar psi>_c = W_t.
 // With tau = 0 the solution reduces exactly to F = F_Euler(W_c),
 // dF/dt = J_x(W_c) W_t and W(t) = W_c + t W_t.
+// The time stepping of the gradients also needs the equilibrium's second
+// time derivative at the point, W_tt = -d_x (J_x W_t) - d_y (J_y W_t) of the
+// Euler equations (the moments of the BGK equilibrium), weighted by
+// second_order_weight (1 for smooth data, 0 at a jump of the state or slope),
+// formed here from the Hessians of the Euler fluxes:
+//   (W_t)_x = -(F''[W_x, W_x] + J_x W_xx + G''[W_x, W_y] + J_y W_xy),
+//   (W_t)_y = -(F''[W_x, W_y] + J_x W_xy + G''[W_y, W_y] + J_y W_yy),
+//   W_tt = -(F''[W_x, W_t] + J_x (W_t)_x + G''[W_y, W_t] + J_y (W_t)_y),
+// with the averaged first and second derivatives of the point.
 //
 // Templated on the arithmetic type R (double; float in the mixed form) and
 // host+device so that an operation-counting type can be substituted.
@@ -107,6 +116,100 @@ GENO_HD void jac_y(const R* W, const Prim<R>& q, const R* d, double gamma, R* ou
   out[1] = d[1] * q.V + W[1] * dV;
   out[2] = d[2] * q.V + W[2] * dV + dp;
   out[3] = dV * (W[3] + q.p) + q.V * (d[3] + dp);
+}
+
+// F''[b, d]: the Hessian of the Euler flux along x (face frame) applied to
+// two changes b, d of the state (symmetric in b and d). With the velocity
+// and pressure changes bU = (b_1 - U b_0)/rho, bp = (gamma - 1)(b_E - U b_1 -
+// V b_2 + |U|^2/2 b_0) (same for d) and H = (rho E + p)/rho:
+//   (0, rho ((3 - gamma) bU dU - (gamma - 1) bV dV), rho (bU dV + dU bV),
+//    bU (d_E + dp - H d_0) + dU (b_E + bp - H b_0) - U (gamma - 1) rho (bU dU + bV dV)).
+template <int NV, typename R>
+GENO_HD void hess_x(const R* W, const Prim<R>& q, const R* b, const R* d, double gamma, R* out) {
+  const R gm = R(gamma - 1.0);
+  const R H = (W[NV - 1] + q.p) * q.ir;
+  const R bU = (b[1] - q.U * b[0]) * q.ir, dU = (d[1] - q.U * d[0]) * q.ir;
+  R bp, dp, s;
+  if constexpr (NV == 4) {
+    const R bV = (b[2] - q.V * b[0]) * q.ir, dV = (d[2] - q.V * d[0]) * q.ir;
+    const R k2 = R(0.5) * (q.U * q.U + q.V * q.V);
+    bp = gm * (b[3] - q.U * b[1] - q.V * b[2] + k2 * b[0]);
+    dp = gm * (d[3] - q.U * d[1] - q.V * d[2] + k2 * d[0]);
+    s = bU * dU + bV * dV;
+    out[1] = q.rho * (R(3.0 - gamma) * (bU * dU) - gm * (bV * dV));
+    out[2] = q.rho * (bU * dV + dU * bV);
+  } else {
+    const R k2 = R(0.5) * q.U * q.U;
+    bp = gm * (b[2] - q.U * b[1] + k2 * b[0]);
+    dp = gm * (d[2] - q.U * d[1] + k2 * d[0]);
+    s = bU * dU;
+    out[1] = q.rho * (R(3.0 - gamma) * s);
+  }
+  out[0] = R(0.0);
+  out[NV - 1] = bU * (d[NV - 1] + dp - H * d[0]) + dU * (b[NV - 1] + bp - H * b[0]) -
+                q.U * (gm * q.rho * s);
+}
+
+// G''[b, d]: the same for the flux along y (2-D).
+template <typename R>
+GENO_HD void hess_y(const R* W, const Prim<R>& q, const R* b, const R* d, double gamma, R* out) {
+  const R gm = R(gamma - 1.0);
+  const R H = (W[3] + q.p) * q.ir;
+  const R bU = (b[1] - q.U * b[0]) * q.ir, dU = (d[1] - q.U * d[0]) * q.ir;
+  const R bV = (b[2] - q.V * b[0]) * q.ir, dV = (d[2] - q.V * d[0]) * q.ir;
+  const R k2 = R(0.5) * (q.U * q.U + q.V * q.V);
+  const R bp = gm * (b[3] - q.U * b[1] - q.V * b[2] + k2 * b[0]);
+  const R dp = gm * (d[3] - q.U * d[1] - q.V * d[2] + k2 * d[0]);
+  const R s = bU * dU + bV * dV;
+  out[0] = R(0.0);
+  out[1] = q.rho * (bV * dU + dV * bU);
+  out[2] = q.rho * (R(3.0 - gamma) * (bV * dV) - gm * (bU * dU));
+  out[3] = bV * (d[3] + dp - H * d[0]) + dV * (b[3] + bp - H * b[0]) - q.V * (gm * q.rho * s);
+}
+
+// Equilibrium second time derivative W_tt at state W (face frame) from the
+// first derivatives dx, dy, the time derivative Wt and the second
+// derivatives sxx, sxy, syy (2-D; 1-D uses dx, Wt and sxx only).
+template <int NV, typename R>
+GENO_HD void second_time(const R* W, const Prim<R>& q, const R* dx, const R* dy, const R* Wt,
+                         const R* sxx, const R* sxy, const R* syy, double gamma, R* Wtt) {
+  R a[NV], b[NV], tx[NV];
+  hess_x<NV, R>(W, q, dx, dx, gamma, a);
+  jac_x<NV, R>(W, q, sxx, gamma, b);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) tx[v] = -(a[v] + b[v]);
+  if constexpr (NV == 4) {
+    R ty[NV];
+    hess_y<R>(W, q, dx, dy, gamma, a);
+    jac_y<R>(W, q, sxy, gamma, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) tx[v] = tx[v] - (a[v] + b[v]);
+    hess_x<NV, R>(W, q, dx, dy, gamma, a);
+    jac_x<NV, R>(W, q, sxy, gamma, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ty[v] = -(a[v] + b[v]);
+    hess_y<R>(W, q, dy, dy, gamma, a);
+    jac_y<R>(W, q, syy, gamma, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ty[v] = ty[v] - (a[v] + b[v]);
+    // W_tt = -(F''[W_x, W_t] + J_x (W_t)_x + G''[W_y, W_t] + J_y (W_t)_y)
+    hess_x<NV, R>(W, q, dx, Wt, gamma, a);
+    jac_x<NV, R>(W, q, tx, gamma, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wtt[v] = -(a[v] + b[v]);
+    hess_y<R>(W, q, dy, Wt, gamma, a);
+    jac_y<R>(W, q, ty, gamma, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wtt[v] = Wtt[v] - (a[v] + b[v]);
+  } else {
+    (void)dy;
+    (void)sxy;
+    (void)syy;
+    hess_x<NV, R>(W, q, dx, Wt, gamma, a);
+    jac_x<NV, R>(W, q, tx, gamma, b);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Wtt[v] = -(a[v] + b[v]);
+  }
 }
 
 // Micro-slope a with <a psi> = w over the Maxwellian (U, V, lam), closed form
@@ -201,20 +304,64 @@ GENO_HD void mom_a(const Mom<R>& m, const R* a, int i, int j, R* out) {
   }
 }
 
+// Weight phi of the second-order term of the interface value at a point
+// with side states Wl, Wr (primitives pl, pr) and physical normal
+// derivatives nl, nr: r is the largest of the jumps between the sides
+// relative to their scale (pressure and density |a_l - a_r| / (a_l + a_r);
+// the velocity components over the sum of the sound speeds) and of the
+// jumps of the normal derivatives over the distance a sound wave covers in
+// dt (dt c |d_l - d_r| over the variable's scale: the density sum, that sum
+// times c for the momenta, the energy sum; c the mean sound speed);
+// phi = 1 for r <= r1 = 1e-2, 1 - x^2 with x = (r - r1) / (r0 - r1) up to
+// r0 = 1e-1, 0 beyond. A shock or contact (and the foot of a shock, where
+// the states agree but the slopes do not) gives r of order one, resolved
+// data r far below r1; phi is continuous, and flat (exactly 1) over the
+// whole range of smooth data, where the scheme's rounding sensitivity is
+// that of the unweighted term.
+template <int NV, typename R>
+GENO_HD R second_order_weight(const Prim<R>& pl, const Prim<R>& pr, const R* Wl, const R* Wr,
+                              const R* nl, const R* nr, R dt, const KParams& k) {
+  const R cl = sqrt(R(k.gamma) * pl.p * pl.ir), cr = sqrt(R(k.gamma) * pr.p * pr.ir);
+  const R ic = R(1.0) / (cl + cr);
+  R r = fabs(pl.p - pr.p) / (pl.p + pr.p);
+  r = fmax(r, fabs(pl.rho - pr.rho) / (pl.rho + pr.rho));
+  r = fmax(r, fabs(pl.U - pr.U) * ic);
+  if constexpr (NV == 4) r = fmax(r, fabs(pl.V - pr.V) * ic);
+  const R rs = pl.rho + pr.rho, dc = dt * R(0.5) * (cl + cr);
+  r = fmax(r, dc * fabs(nl[0] - nr[0]) / rs);
+#pragma unroll
+  for (int v = 1; v < NV - 1; ++v) r = fmax(r, dt * fabs(nl[v] - nr[v]) / rs);
+  r = fmax(r, dc * fabs(nl[NV - 1] - nr[NV - 1]) / (fabs(Wl[NV - 1]) + fabs(Wr[NV - 1])));
+  constexpr double r1 = 1e-2, r0 = 1e-1;
+  if (r <= R(r1)) return R(1.0);
+  const R x = (r - R(r1)) * R(1.0 / (r0 - r1));
+  return x < R(1.0) ? R(1.0) - x * x : R(0.0);
+}
+
 // Kinds of gas-kinetic point, returned by point_flux.
 enum { PT_EQUAL = 0, PT_FAST = 1, PT_SLOW = 2 };
 
+// Results at one point: F, dF/dt (time fit of the integrals over dt/2 and
+// dt), the interface state W(dt/2) and W(dt) of the solution, and the
+// equilibrium second time derivative W_tt.
+template <int NV, typename R>
+struct PointOut {
+  R F[NV], Ft[NV], Wh[NV], Wf[NV], Wtt[NV];
+};
+
 // Point flux. Wl, Wr: states (face frame, normal momentum first); nl, nr,
-// tl, tr: physical normal / tangential derivatives (tl, tr unused in 1-D).
-// Accumulates w * F, w * dF/dt and w * W(dt/2) into F, Ft, Wi (F skipped
-// unless want_F). Returns PT_SLOW if the collision time is positive, else
-// PT_EQUAL for equal states and PT_FAST otherwise. With FULL = false a
-// PT_SLOW point is not evaluated and nothing is accumulated (the caller hands
-// the face to the full path).
+// tl, tr: physical normal / tangential derivatives (tl, tr unused in 1-D);
+// snn, snt, stt: physical second derivatives of the point (normal-normal,
+// normal-tangential, tangential-tangential; snt, stt unused in 1-D). Writes
+// the point's results into o (F only if want_F). Returns PT_SLOW if the
+// collision time is positive, else PT_EQUAL for equal states and PT_FAST
+// otherwise. With FULL = false a PT_SLOW point is not evaluated and o is not
+// written (the caller hands the face to the full path).
 template <int NV, bool FULL, typename R>
 GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const R* tl,
-                        const R* tr, typename Wide<R>::type dt_w, const KParams& k, R w,
-                        bool want_F, R* F, R* Ft, R* Wi) {
+                        const R* tr, const R* snn, const R* snt, const R* stt,
+                        typename Wide<R>::type dt_w, const KParams& k, bool want_F,
+                        PointOut<NV, R>& o) {
   using D = typename Wide<R>::type;
   const double g = k.gamma, K = k.K;
   Prim<R> pl = prim<NV, R>(Wl, g), pr = prim<NV, R>(Wr, g);
@@ -292,14 +439,28 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
   R Fe[NV], JW[NV];
   euler_flux<NV, R>(Wc, pc, Fe);
   jac_x<NV, R>(Wc, pc, Wt, g, JW);
+  // the second-order term of the interface value: phi W_tt of the
+  // equilibrium, phi = 1 where the two sides reconstruct the same state and
+  // slope (smooth data) and 0 at a discontinuity (second_order_weight)
+  const R phi = second_order_weight<NV, R>(pl, pr, Wl, Wr, nl, nr, dt, k);
+  if (phi > R(0.0)) {
+    second_time<NV, R>(Wc, pc, dn, dtn, Wt, snn, snt, stt, g, o.Wtt);
+    if (phi < R(1.0))
+#pragma unroll
+      for (int v = 0; v < NV; ++v) o.Wtt[v] = phi * o.Wtt[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o.Wtt[v] = R(0.0);
+  }
   const R h = R(0.5) * dt;
   if (!slow) {
     // tau = 0: exact limits of the time integrals
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      if (want_F) F[v] = F[v] + w * Fe[v];
-      Ft[v] = Ft[v] + w * JW[v];
-      Wi[v] = Wi[v] + w * (Wc[v] + h * Wt[v]);
+      if (want_F) o.F[v] = Fe[v];
+      o.Ft[v] = JW[v];
+      o.Wh[v] = Wc[v] + h * Wt[v];
+      o.Wf[v] = Wc[v] + dt * Wt[v];
     }
     return same ? PT_EQUAL : PT_FAST;
   }
@@ -327,9 +488,11 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
     const R f4 = R((D(4.0) * c4h - c4f) * idt), g4 = R((c4f - D(2.0) * c4h) * idt2);
     const R f5 = R((D(4.0) * c5h - c5f) * idt), g5 = R((c5f - D(2.0) * c5h) * idt2);
     const R f6 = R((D(4.0) * c6h - c6f) * idt), g6 = R((c6f - D(2.0) * c6h) * idt2);
-    // interface state at dt/2
-    const R k1 = R(emh), k2 = R((hh + td) * eh - td), k3 = R(hh - td * emh), k4 = R(hh + td);
-    const R ehr = R(eh);
+    // interface state at d = dt/2 and dt: weights em, (d + tau) e - tau and
+    // d - tau em of the equilibrium part; e (1, -(d + tau), -tau) of each side
+    const R k1h = R(emh), k2h = R((hh + td) * eh - td), k3h = R(hh - td * emh), k4h = R(hh + td);
+    const R k1f = R(emf), k2f = R((dd + td) * ef - td), k3f = R(dd - td * emf), k4f = R(dd + td);
+    const R ehr = R(eh), efr = R(ef);
 
     // equilibrium part: <u (abar u + bbar v) psi>_c needs the moments of g_c
     {
@@ -355,9 +518,10 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const R x2 = pc.rho * X2[v];
-        if (want_F) F[v] = F[v] + w * (f1 * Fe[v] + f2 * x2 + f3 * JW[v]);
-        Ft[v] = Ft[v] + w * (g1 * Fe[v] + g2 * x2 + g3 * JW[v]);
-        Wi[v] = Wi[v] + w * (k1 * Wc[v] + (k3 - k2) * Wt[v]);
+        if (want_F) o.F[v] = f1 * Fe[v] + f2 * x2 + f3 * JW[v];
+        o.Ft[v] = g1 * Fe[v] + g2 * x2 + g3 * JW[v];
+        o.Wh[v] = k1h * Wc[v] + (k3h - k2h) * Wt[v];
+        o.Wf[v] = k1f * Wc[v] + (k3f - k2f) * Wt[v];
       }
     }
     // non-equilibrium part, one side at a time
@@ -407,9 +571,10 @@ GENO_HD int point_flux(const R* Wl, const R* Wr, const R* nl, const R* nr, const
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const R r = ps.rho;
-        if (want_F) F[v] = F[v] + w * r * (f4 * U1[v] - f5 * Xs[v] - f6 * Ys[v]);
-        Ft[v] = Ft[v] + w * r * (g4 * U1[v] - g5 * Xs[v] - g6 * Ys[v]);
-        Wi[v] = Wi[v] + w * ehr * r * (P0[v] - k4 * Zs[v] - tau * A0[v]);
+        if (want_F) o.F[v] = o.F[v] + r * (f4 * U1[v] - f5 * Xs[v] - f6 * Ys[v]);
+        o.Ft[v] = o.Ft[v] + r * (g4 * U1[v] - g5 * Xs[v] - g6 * Ys[v]);
+        o.Wh[v] = o.Wh[v] + ehr * r * (P0[v] - k4h * Zs[v] - tau * A0[v]);
+        o.Wf[v] = o.Wf[v] + efr * r * (P0[v] - k4f * Zs[v] - tau * A0[v]);
       }
     }
   }

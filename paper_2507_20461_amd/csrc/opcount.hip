@@ -90,22 +90,28 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
   const long long lin = count([&] {
     C qH, hqH;
     geno::linear_p7<C>(1.0, 1.1, 1.2, 1.3, 0.1, 0.1, 0.1, 0.1, qH, hqH);
+    (void)geno::linear_p7_d2<C>(1.0, 1.1, 1.2, 1.3, 0.1, 0.1, 0.1, 0.1);
   });
-  const long long side_hi = count([&] {   // linear data: IS_tau = 0, chi = 1 without tanh
-    C v, d, x;
-    geno::geno_side<C, C>(1.0, 1.1, 1.2, 1.3, 0.1, 1.15, 0.1, k, v, d, x);
+  // one side, plus its half of the mean second derivative (1 add, 1 mul
+  // per face: counted as one per side)
+  const long long side_hi = 1 + count([&] {   // linear data: IS_tau = 0, chi = 1 without tanh
+    C v, d, d2, x;
+    geno::geno_side<C, C>(1.0, 1.1, 1.2, 1.3, 0.1, 1.15, 0.1, 0.0, k, v, d, d2, x);
   });
-  const long long side_lo = count([&] {   // a step: chi < 1, low-order part formed
-    C v, d, x;
-    geno::geno_side<C, C>(0.0, 0.0, 1.0, 1.0, 0.0, 0.5, 0.0, k, v, d, x);
+  const long long side_lo = 1 + count([&] {   // a step: chi < 1, low-order part formed
+    C v, d, d2, x;
+    geno::geno_side<C, C>(0.0, 0.0, 1.0, 1.0, 0.0, 0.5, 0.0, 0.0, k, v, d, d2, x);
   });
-  const long long tan_hi = count([&] {
-    C v0, v1, t0, t1;
-    geno::tangential<C, C>(1.0, 1.1, 1.2, k, v0, v1, t0, t1);
+  // tangential step of one side and variable, with its second tangential
+  // and cross derivatives (2 mul, 1 sub, 1 mul) and their mean over the
+  // sides (1 add, 1 mul each, per side: 2)
+  const long long tan_hi = 6 + count([&] {
+    C v0, v1, t0, t1, ct, d2;
+    geno::tangential<C, C>(1.0, 1.1, 1.2, k, v0, v1, t0, t1, ct, d2);
   });
-  const long long tan_lo = count([&] {
-    C v0, v1, t0, t1;
-    geno::tangential<C, C>(0.0, 0.0, 1.0, k, v0, v1, t0, t1);
+  const long long tan_lo = 6 + count([&] {
+    C v0, v1, t0, t1, ct, d2;
+    geno::tangential<C, C>(0.0, 0.0, 1.0, k, v0, v1, t0, t1, ct, d2);
   });
   const int nv = ndim == 2 ? 4 : 3;
   const long long adm = count([&] {
@@ -121,35 +127,39 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     C Wl[4] = {1.0, 0.25, -0.125, 2.5390625}, Wr[4] = {0.5, 0.125, -0.0625, 2.51953125};
     C Wr2[4] = {0.8, 0.1, 0.1, 2.0};
     C n[4] = {0.1, 0.2, 0.3, 0.4}, t[4] = {0.2, 0.1, 0.0, -0.1};
-    pequal = count([&] {
-      C F[4], Ft[4], Wi[4];
-      gks::point_flux<4, true, C>(Wl, Wl, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
+    C s1[4] = {0.3, -0.2, 0.1, 0.4}, s2[4] = {0.1, 0.1, -0.3, 0.2}, s3[4] = {-0.2, 0.3, 0.1, 0.1};
+    // the point plus its share of the stage-1 outputs (Gauss weight and
+    // the two interface-value combinations: 4 per variable)
+    pequal = 16 + count([&] {
+      gks::PointOut<4, C> o;
+      gks::point_flux<4, true, C>(Wl, Wl, n, n, t, t, s1, s2, s3, C(1e-3), k, true, o);
     });
-    pfast = count([&] {
-      C F[4], Ft[4], Wi[4];
-      gks::point_flux<4, true, C>(Wl, Wr, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
+    pfast = 16 + count([&] {
+      gks::PointOut<4, C> o;
+      gks::point_flux<4, true, C>(Wl, Wr, n, n, t, t, s1, s2, s3, C(1e-3), k, true, o);
     });
-    pslow = count([&] {
-      C F[4], Ft[4], Wi[4];
-      gks::point_flux<4, true, C>(Wl, Wr2, n, n, t, t, C(1e-3), k, C(0.5), true, F, Ft, Wi);
+    pslow = 16 + count([&] {
+      gks::PointOut<4, C> o;
+      gks::point_flux<4, true, C>(Wl, Wr2, n, n, t, t, s1, s2, s3, C(1e-3), k, true, o);
     });
   } else {
     C Wl[3] = {1.0, 0.25, 2.53125}, Wr[3] = {0.5, 0.125, 2.515625}, Wr2[3] = {0.8, 0.1, 2.0};
-    C n[3] = {0.1, 0.2, 0.3};
-    pequal = count([&] {
-      C F[3], Ft[3], Wi[3];
-      gks::point_flux<3, true, C>(Wl, Wl, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
-                                  Ft, Wi);
+    C n[3] = {0.1, 0.2, 0.3}, s1[3] = {0.3, -0.2, 0.1};
+    // plus the two interface-value combinations (2 per variable)
+    pequal = 6 + count([&] {
+      gks::PointOut<3, C> o;
+      gks::point_flux<3, true, C>(Wl, Wl, n, n, nullptr, nullptr, s1, nullptr, nullptr, C(1e-3),
+                                  k, true, o);
     });
-    pfast = count([&] {
-      C F[3], Ft[3], Wi[3];
-      gks::point_flux<3, true, C>(Wl, Wr, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
-                                  Ft, Wi);
+    pfast = 6 + count([&] {
+      gks::PointOut<3, C> o;
+      gks::point_flux<3, true, C>(Wl, Wr, n, n, nullptr, nullptr, s1, nullptr, nullptr, C(1e-3),
+                                  k, true, o);
     });
-    pslow = count([&] {
-      C F[3], Ft[3], Wi[3];
-      gks::point_flux<3, true, C>(Wl, Wr2, n, n, nullptr, nullptr, C(1e-3), k, C(1.0), true, F,
-                                  Ft, Wi);
+    pslow = 6 + count([&] {
+      gks::PointOut<3, C> o;
+      gks::point_flux<3, true, C>(Wl, Wr2, n, n, nullptr, nullptr, s1, nullptr, nullptr, C(1e-3),
+                                  k, true, o);
     });
   }
   if (ndim == 2) {
@@ -162,10 +172,10 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
       // a gated side skips its indicators (work counted with the unit)
       set(kind, GENO_W_GATED, -(double)side_hi);
     }
-    // face: 8 tangential steps, 4 guard checks, derivative scaling (2 points x
-    // 3 arrays x 2 sides x 4 variables, of which the two h*d/dn arrays per
-    // point) and the Gauss average (12 additions)
-    const double face = 8.0 * tan_hi + 4.0 * adm + 2.0 * 16.0 + 12.0;
+    // face: 8 tangential steps, 4 guard checks, derivative scaling (per
+    // point: 16 first and 12 second derivatives) and the Gauss average of
+    // 16 outputs (a weight and an addition each)
+    const double face = 8.0 * tan_hi + 4.0 * adm + 2.0 * 28.0 + 32.0;
     for (int kind : {GENO_K_FACES_X, GENO_K_FACES_Y, GENO_K_SLOW}) {
       set(kind, GENO_W_UNITS, face);
       set(kind, GENO_W_LOW, (double)(tan_lo - tan_hi));
@@ -173,10 +183,12 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
       set(kind, GENO_W_FAST, (double)pfast);
       set(kind, GENO_W_SLOW, (double)pslow);
     }
-    // update per cell and variable: stage 1 L (5), L_t (5), gradients (4),
-    // W* (7), R (6); stage 2 L_t (5), gradients (4), W (4) and the CFL bound
-    set(GENO_K_UPDATE_1, GENO_W_UNITS, 4.0 * 27.0);
-    set(GENO_K_UPDATE_2, GENO_W_UNITS, 4.0 * 13.0 + 17.0);
+    // update per cell and variable: stage 1 L (5), L_t (5), gradients at the
+    // stage time and their end-of-step share (8), W* (7), R (6); stage 2
+    // L_t (5), gradients (8), W (2), and per cell dt^2/3 (2) and the CFL
+    // bound (17)
+    set(GENO_K_UPDATE_1, GENO_W_UNITS, 4.0 * 31.0);
+    set(GENO_K_UPDATE_2, GENO_W_UNITS, 4.0 * 15.0 + 19.0);
     set(GENO_K_INIT, GENO_W_UNITS, 17.0);
   } else {
     const double face = 3.0 * (4 + lin + 2 * side_hi) + 2.0 * adm + 6.0;
@@ -185,8 +197,8 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     set(GENO_K_FACES_1D, GENO_W_EQUAL, (double)pequal);
     set(GENO_K_FACES_1D, GENO_W_FAST, (double)pfast);
     set(GENO_K_FACES_1D, GENO_W_SLOW, (double)pslow);
-    set(GENO_K_UPDATE_1, GENO_W_UNITS, 3.0 * 19.0);
-    set(GENO_K_UPDATE_2, GENO_W_UNITS, 3.0 * 8.0 + 11.0);
+    set(GENO_K_UPDATE_1, GENO_W_UNITS, 3.0 * 21.0);
+    set(GENO_K_UPDATE_2, GENO_W_UNITS, 3.0 * 8.0 + 13.0);
     set(GENO_K_INIT, GENO_W_UNITS, 11.0);
   }
   return 0;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING, BC_FIXED = 0, 1, 2, 3
 F64, MIXED = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 NG = 2
 VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
 
@@ -242,10 +242,23 @@ class Grid:
         return A[:, self.yoff:self.yoff + self.ny, NG:NG + self.nx].copy()
 
     def face_state_shape(self, direction=0):
+        """Planes of geno_reconstruct's output: the point states
+        [side][gauss][quant][var] then the points' second derivatives
+        [gauss][quant2][var], over [nfy][nfx]."""
         if self.ndim == 1:
-            return (2, 1, 2, 3, 1, self.nx + 1)
+            return (2 * 1 * 2 * 3 + 1 * 1 * 3, 1, self.nx + 1)
         nfx, nfy = (self.nx + 1, self.ny) if direction == 0 else (self.nx, self.ny + 1)
-        return (2, 2, 3, 4, nfy, nfx)
+        return (2 * 2 * 3 * 4 + 2 * 3 * 4, nfy, nfx)
+
+    def face_state_parts(self, fs):
+        """Split a face_state array (numpy) into the point states
+        [side, gauss, quant, var, nfy, nfx] and the second derivatives
+        [gauss, quant2, var, nfy, nfx]."""
+        fs = np.asarray(fs)
+        if self.ndim == 1:
+            return fs[:12].reshape(2, 1, 2, 3, 1, self.nx + 1), fs[12:].reshape(1, 1, 3, 1, self.nx + 1)
+        _, nfy, nfx = fs.shape
+        return fs[:48].reshape(2, 2, 3, 4, nfy, nfx), fs[48:].reshape(2, 3, 4, nfy, nfx)
 
     def chi_shape(self, direction=0):
         if self.ndim == 1:
@@ -278,9 +291,10 @@ def geno_reconstruct(grid, W, dW, direction, face_state, chi, ws, stream=None):
 
 
 def gks_flux(grid, face_state, dt, direction, F, Ft, Wint, stream=None):
+    """F, Ft: flux_shape; Wint: 3 x flux_shape (W(dt/2), W(dt), W_tt)."""
     _need(face_state, grid.fdtype, _prod(grid.face_state_shape(direction)), "face_state")
-    for name, t in (("F", F), ("Ft", Ft), ("Wint", Wint)):
-        _need(t, grid.fdtype, _prod(grid.flux_shape(direction)), name, optional=True)
+    for name, t, m in (("F", F, 1), ("Ft", Ft, 1), ("Wint", Wint, 3)):
+        _need(t, grid.fdtype, m * _prod(grid.flux_shape(direction)), name, optional=True)
     _check(lib().gks_flux(ctypes.byref(grid.g), _ptr(face_state), float(dt), int(direction),
                           _ptr(F), _ptr(Ft), _ptr(Wint), _stream(stream)))
 

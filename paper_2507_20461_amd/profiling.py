@@ -125,7 +125,7 @@ def _cal_scale(path, counter):
     return None
 
 
-def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
+def summarize_ktrace(tag="stage_fp64_2048", dest=PROFILES):
     """Per-workload kernel averages from the kernel trace into
     <tag>_kernel_stats.txt, and the averages of the benchmark's two
     workloads into <tag>_ktrace_avg.json (read by the counter summary)."""
@@ -165,7 +165,7 @@ def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
     lines.append("# command: " + " ".join(command("ktrace")).replace(ROOT + "/", ""))
     lines.append("# kernel sources sha256[:16]: " + sh)
     lines.append("# workload labels: element type and grid of the gks_step call (k_init grid size = cells,")
-    lines.append("# rounded to the next work-group); the bench's 512x512 workload is 'fp64 512x512', its")
+    lines.append("# rounded to the next work-group); the bench's 2048x2048 workload is 'fp64 2048x2048', its")
     lines.append("# 2^24-cell non-compact workload 'noncompact fp64 65794 tiles of 255 cells', its")
     lines.append("# triangle mesh of 2 x 512^2 cells 'triangles fp64 524288 cells'")
     ktrace = {}
@@ -175,14 +175,14 @@ def summarize_ktrace(tag="faces_fp64_512", dest=PROFILES):
         lines.append("%-28s %7s %10s %10s" % ("kernel", "calls", "avg_us", "total_ms"))
         for k, v in sorted(ks.items(), key=lambda kv: -sum(kv[1])):
             lines.append("%-28s %7d %10.2f %10.3f" % (k[:28], len(v), sum(v) / len(v), sum(v) / 1e3))
-            if lab.startswith(("fp64 512x512", "noncompact fp64 65794 ", "triangles fp64 524288 ")):
+            if lab.startswith(("fp64 2048x2048", "noncompact fp64 65794 ", "triangles fp64 524288 ")):
                 ktrace.setdefault(k, []).extend(v)
     ktrace = {k: sum(v) / len(v) for k, v in ktrace.items()}
     open(os.path.join(dest, "%s_kernel_stats.txt" % tag), "w").write("\n".join(lines) + "\n")
     open(os.path.join(dest, "%s_ktrace_avg.json" % tag), "w").write(json.dumps(ktrace, indent=1) + "\n")
 
 
-def summarize(tag="faces_fp64_512", dest=PROFILES):
+def summarize(tag="stage_fp64_2048", dest=PROFILES):
     os.makedirs(dest, exist_ok=True)
     sh = source_hash()
     trace_csv = os.path.join(OUT, "prof_ktrace", "run_kernel_trace.csv")
@@ -211,7 +211,7 @@ def summarize(tag="faces_fp64_512", dest=PROFILES):
                    "fetch_bytes_cal": f / fcal if fcal else None, "write_bytes_cal": w / wcal if wcal else None,
                    "valu_insts_per_wave": insts / waves if waves else None,
                    "valu_busy": 4.0 * active / SIMDS / gui if gui else None}
-    lines = ["# rocprofv3 counters per dispatch (3 separate --pmc passes), 2-D Euler 512x512 FP64 (k_*),",
+    lines = ["# rocprofv3 counters per dispatch (separate --pmc passes), 2-D Euler 2048x2048 FP64 (k_*),",
              "# the 1-D non-compact workload of 2^24 cells (k6_*) and the triangle mesh of 2 x 512^2 cells",
              "# (k_tri)",
              "# commands:"]

@@ -146,3 +146,28 @@ def test_batched_rejects_mismatched_parameters(G):
     B = G.Batch([a, b])
     with pytest.raises(G.GenoError):
         B.workspace()
+
+
+def test_batched_grids_match_oracle(G):
+    # each grid of an FP64 batch against the CPU oracle run alone: two steps
+    # from the same state, per cell at 1e-12 of the value for density and
+    # energy, of the field's scale for the momenta, and of the field's scale
+    # over the cell size for the gradients (plus the path-function term of
+    # the second-order part of the gradients, 1e-8 CFL^2/3, at the jumps)
+    from oracle import oracle as O
+    grids, data = _make(G, G.F64)
+    B = G.Batch(grids)
+    Ws, dWs = _upload(grids, data)
+    _, st = B.step(Ws, dWs, B.workspace(), 2, graph=False, stats=True)
+    assert st.nonfinite == 0
+    for (nx, ny, bc, _), g, W, dW, (W0, dW0) in zip(SHAPES, grids, Ws, dWs, data):
+        _say("batched grid %dx%d bc %d vs oracle" % (nx, ny, bc))
+        oW, odW, _, _ = O.step(O.params(ndim=2, bc=bc), W0, dW0, 2, dx=g.dx, dy=g.dy)
+        gW, gdW = g.interior(W), g.interior(dW)
+        sc = np.abs(oW).reshape(4, -1).max(axis=1)
+        den = np.abs(oW).reshape(4, -1).copy()
+        den[1:3] = np.maximum(den[1:3], sc[1:3, None])
+        assert (np.abs(gW - oW).reshape(4, -1) / den).max() < 1e-12
+        gsc = np.concatenate([sc / g.dx, sc / g.dy])
+        eg = (np.abs(gdW - odW).reshape(8, -1) / np.maximum(np.abs(odW).reshape(8, -1), gsc[:, None])).max()
+        assert eg < 1e-12 + 1e-8 * 0.5 ** 2 / 3.0, eg

@@ -1,12 +1,13 @@
 """Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
 
-Tolerance (FP64): per cell and field, |gpu - oracle| <= 1e-12 * max(|oracle|,
-scale of the field) - a relative bound floored by the magnitude of the field,
-so that components crossing zero are compared on their own scale. The scale
-of a conserved field is its largest |value|; derivatives are compared on the
-scale of the field they differentiate (h-scaled derivatives: the field's
-scale; physical gradients: the field's scale over the cell size); dF/dt on
-max(|dF/dt|, |F| / dt), the resolution of its two-point time fit.
+Tolerance (FP64), per cell: the density and the total energy (positive
+fields) at 1e-12 of their own value, |gpu - oracle| <= 1e-12 |oracle|; the
+momenta, which cross zero, at 1e-12 * max(|oracle|, scale of the field).
+Elsewhere the same relative bound is floored by the magnitude of the field:
+derivatives are compared on the scale of the field they differentiate
+(h-scaled derivatives: the field's scale; physical gradients: the field's
+scale over the cell size); dF/dt on max(|dF/dt|, |F| / dt), the resolution
+of its two-point time fit.
 """
 import math
 import sys
@@ -21,6 +22,15 @@ from paper_2507_20461_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+# Second derivatives enter through a path-function weight (Eq. (3) applied to
+# h^2 q'' in the normal step, chi_t D2 and chi_t (psi_{t+1} - psi_{t-1})/2 in
+# the tangential one). chi agrees between the two implementations to 1e-8
+# only (see test_reconstruct_1d), while the high- and low-order second
+# derivatives it blends can differ by the jump itself; so they carry, beside
+# the rounding bound, 1e-8 of their field's magnitude, and the gradients
+# after a step with such jumps 1e-8 of the largest weight of the
+# second-order terms, dt^2/3 W_tt ~ CFL^2/3 of scale / h.
+CHI_TOL = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -46,6 +56,21 @@ def rel_err(g, o, scale=None):
     g2 = g.reshape(g.shape[0], -1)
     sc = field_scale(o) if scale is None else np.broadcast_to(np.asarray(scale, dtype=np.float64), (o.shape[0],))
     den = np.maximum(np.abs(o2), sc[:, None])
+    return float((np.abs(g2 - o2) / den).max())
+
+
+def state_err(g, o):
+    """Per-cell error of a conserved state [nv, ...]: density and total energy
+    relative to their own value, momenta relative to max(|value|, the
+    field's largest |value|)."""
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    nv = o.shape[0]
+    o2, g2 = o.reshape(nv, -1), g.reshape(nv, -1)
+    sc = field_scale(o)
+    sc[0] = sc[nv - 1] = 0.0
+    den = np.maximum(np.abs(o2), sc[:, None])
+    den = np.where(den > 0, den, 1.0)
     return float((np.abs(g2 - o2) / den).max())
 
 
@@ -94,14 +119,15 @@ def test_reconstruct_1d(G, oracle, name, seed, char):
     G.geno_reconstruct(grid, Wd, dWd, 0, fs, chi, grid.workspace())
     torch.cuda.synchronize()
     prm = _oprm(oracle, 1, bc, characteristic=char)
-    ref, _ = oracle.face_states(prm, W, dW)
+    ref, ref2, _ = oracle.face_states(prm, W, dW, second=True)
     _, ref_chi = oracle.normal_faces(prm, W, dW)
-    got = fs.cpu().numpy()
-    # value and h*d/dn per side, var
+    got, got2 = grid.face_state_parts(fs.cpu().numpy())
+    # value and h*d/dn per side, var; the mean h^2 d2/dn2
     sc = field_scale(W)
     for s in range(2):
         for q in range(2):
             assert rel_err(got[s, 0, q], ref[s, 0, q], sc) < TOL, (s, q)
+    assert rel_err(got2[0, 0], ref2[0, 0], sc) < TOL
     # chi = tanh(C alpha) (Eq. (4)-(5)): IS^tau is a difference of indicators,
     # so its rounding (~1e-16 IS^H) relative to IS^L + eps can reach 1e-10 where
     # IS^H/IS^L is large, and chi moves by up to C = 20 times that. The states
@@ -135,14 +161,21 @@ def test_reconstruct_2d(G, oracle, direction, kind, bc, char):
     G.geno_reconstruct(grid, Wd, dWd, direction, fs, chi, grid.workspace())
     torch.cuda.synchronize()
     prm = _oprm(oracle, 2, bc, characteristic=char)
-    ref, _ = oracle.face_states(prm, W, dW, direction)
+    ref, ref2, _ = oracle.face_states(prm, W, dW, direction, second=True)
     _, ref_chi = oracle.normal_faces(prm, W, dW, direction)
-    got = fs.cpu().numpy()
+    got, got2 = grid.face_state_parts(fs.cpu().numpy())
     sc = field_scale(W)
     for s in range(2):
         for q in range(2):
             for k in range(3):
                 assert rel_err(got[s, q, k], ref[s, q, k], sc) < TOL, (s, q, k)
+    # second derivatives of the points (h-scaled: the field's scale), plus
+    # the chi term (CHI_TOL)
+    for q in range(2):
+        for k in range(3):
+            d = np.abs(got2[q, k] - ref2[q, k]).reshape(4, -1)
+            bound = TOL * sc[:, None] + CHI_TOL * np.abs(ref2[q, k]).reshape(4, -1).max(axis=1)[:, None]
+            assert np.all(d <= bound), ("second", q, k, (d / sc[:, None]).max())
     # chi = tanh(C alpha) (Eq. (4)-(5)): IS^tau is a difference of indicators,
     # so its rounding (~1e-16 IS^H) relative to IS^L + eps can reach 1e-10 where
     # IS^H/IS^L is large, and chi moves by up to C = 20 times that. The states
@@ -161,29 +194,35 @@ def test_gks_flux_2d(G, oracle, direction, tau_c1):
     fs = torch.empty(grid.face_state_shape(direction), dtype=torch.float64, device="cuda")
     G.geno_reconstruct(grid, Wd, dWd, direction, fs, None, grid.workspace())
     shp = grid.flux_shape(direction)
-    F, Ft, Wi = (torch.empty(shp, dtype=torch.float64, device="cuda") for _ in range(3))
+    F, Ft = (torch.empty(shp, dtype=torch.float64, device="cuda") for _ in range(2))
+    Wi = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
     dt = 0.4 * grid.dx
     G.gks_flux(grid, fs, dt, direction, F, Ft, Wi)
     torch.cuda.synchronize()
-    # oracle flux on the GPU's point states (rotated into the face frame)
-    st = fs.cpu().numpy()
+    # oracle flux on the GPU's point states and second derivatives (rotated
+    # into the face frame)
+    st, sec = grid.face_state_parts(fs.cpu().numpy())
     perm = [0, 1, 2, 3] if direction == 0 else [0, 2, 1, 3]
     hn, ht = (grid.dx, grid.dy) if direction == 0 else (grid.dy, grid.dx)
     prm = _oprm(oracle, 2, 1, tau_c1=tau_c1)
-    acc = [np.zeros(shp) for _ in range(3)]
+    acc = [np.zeros(shp) for _ in range(5)]
     for q in range(2):
-        def pts(s, k, h):
-            a = st[s, q, k][perm]                      # [var, nfy, nfx]
-            return (a.reshape(4, -1).T / h).copy()
-        Wl, Wr = pts(0, 0, 1.0), pts(1, 0, 1.0)
-        nl, nr = pts(0, 1, hn), pts(1, 1, hn)
-        tl, tr = pts(0, 2, ht), pts(1, 2, ht)
-        res = oracle.gks_points(prm, 2, Wl, Wr, nl, nr, tl, tr, dt=dt)
+        def pts(a, h):
+            return (a[perm].reshape(4, -1).T / h).copy()      # a: [var, nfy, nfx]
+        Wl, Wr = pts(st[0, q, 0], 1.0), pts(st[1, q, 0], 1.0)
+        nl, nr = pts(st[0, q, 1], hn), pts(st[1, q, 1], hn)
+        tl, tr = pts(st[0, q, 2], ht), pts(st[1, q, 2], ht)
+        s2 = np.stack([pts(sec[q, 0], hn * hn), pts(sec[q, 1], hn * ht), pts(sec[q, 2], ht * ht)], axis=1)
+        res = oracle.gks_points(prm, 2, Wl, Wr, nl, nr, tl, tr, dt=dt, sec=s2, full=True)
         for a, r in zip(acc, res):
             a += 0.5 * r.T.reshape(4, *shp[1:])[np.argsort(perm)]
     fsc = field_scale(acc[0])
-    for got, ref, sc in zip((F, Ft, Wi), acc, (fsc, np.maximum(field_scale(acc[1]), fsc / dt), None)):
-        assert rel_err(got.cpu().numpy(), ref, sc) < TOL
+    gWi = Wi.cpu().numpy()
+    for got, ref, sc, name in ((F.cpu().numpy(), acc[0], fsc, "F"),
+                               (Ft.cpu().numpy(), acc[1], np.maximum(field_scale(acc[1]), fsc / dt), "Ft"),
+                               (gWi[0], acc[2], None, "W(dt/2)"), (gWi[1], acc[3], None, "W(dt)"),
+                               (gWi[2], acc[4], None, "W_tt")):
+        assert rel_err(got, ref, sc) < TOL, name
 
 
 def test_gks_flux_1d(G, oracle):
@@ -195,17 +234,25 @@ def test_gks_flux_1d(G, oracle):
     fs = torch.empty(grid.face_state_shape(), dtype=torch.float64, device="cuda")
     G.geno_reconstruct(grid, Wd, dWd, 0, fs, None, grid.workspace())
     shp = grid.flux_shape()
-    F, Ft, Wi = (torch.empty(shp, dtype=torch.float64, device="cuda") for _ in range(3))
+    F, Ft = (torch.empty(shp, dtype=torch.float64, device="cuda") for _ in range(2))
+    Wi = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
     dt = 0.3 * grid.dx
     G.gks_flux(grid, fs, dt, 0, F, Ft, Wi)
     torch.cuda.synchronize()
-    st = fs.cpu().numpy()
+    st, sec = grid.face_state_parts(fs.cpu().numpy())
     pts = lambda s, k, h: (st[s, 0, k].reshape(3, -1).T / h).copy()
+    s2 = np.zeros((st.shape[-1], 3, 3))
+    s2[:, 0, :] = sec[0, 0].reshape(3, -1).T / grid.dx ** 2
     res = oracle.gks_points(_oprm(oracle, 1, 1, tau_c1=0.02), 1, pts(0, 0, 1.0), pts(1, 0, 1.0),
-                            pts(0, 1, grid.dx), pts(1, 1, grid.dx), dt=dt)
+                            pts(0, 1, grid.dx), pts(1, 1, grid.dx), dt=dt, sec=s2, full=True)
     fsc = field_scale(res[0].T)
-    for got, ref, sc in zip((F, Ft, Wi), res, (fsc, np.maximum(field_scale(res[1].T), fsc / dt), None)):
-        assert rel_err(got.cpu().numpy().reshape(3, -1), ref.T, sc) < TOL
+    gWi = Wi.cpu().numpy().reshape(3, 3, -1)
+    for got, ref, sc, name in ((F.cpu().numpy().reshape(3, -1), res[0].T, fsc, "F"),
+                               (Ft.cpu().numpy().reshape(3, -1), res[1].T,
+                                np.maximum(field_scale(res[1].T), fsc / dt), "Ft"),
+                               (gWi[0], res[2].T, None, "W(dt/2)"), (gWi[1], res[3].T, None, "W(dt)"),
+                               (gWi[2], res[4].T, None, "W_tt")):
+        assert rel_err(got, ref, sc) < TOL, name
 
 
 # ------------------------------------------------------------------ full steps
@@ -235,7 +282,7 @@ def _shadow(G, oracle, grid, W, dW, nsteps, bc, check_every=1):
         if check:
             oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, dy=grid.dy)
             gW, gdW = grid.interior(Wd), grid.interior(dWd)
-            e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)),
+            e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)),
                  rel_err(dts.cpu().numpy(), odt))
             worst = [max(a, b) for a, b in zip(worst, e)]
             assert st.guard == og, (n, st.guard, og)
@@ -260,6 +307,21 @@ def test_step_1d_200_steps(G, oracle, name, seed):
             assert abs(math.fsum(gW[k].ravel()) - math.fsum(W[k].ravel())) < 1e-13 * W.shape[2] * np.abs(W[k]).max()
 
 
+def test_step_1d_sine_trajectory_200_steps(G, oracle):
+    # the smooth 1-D workload compared over its whole run: 200 cells, CFL
+    # 0.5, 200 steps from the same initial state, no shadowing (chi = 1 at
+    # every face, so rounding differences are not amplified)
+    _say("sine trajectory 200 steps")
+    W, dW, bc = _case_1d("sine", None)
+    grid = _grid(G, W, bc)
+    gW, gdW, gdt, st = _run_gpu(G, grid, W, dW, 200)
+    oW, odW, odt, og = oracle.step(_oprm(oracle, 1, bc), W, dW, 200)
+    e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(gdt, odt))
+    _say("errors W %.3e dW %.3e dt %.3e" % e)
+    assert st.nonfinite == 0 and st.guard == og == 0
+    assert max(e) < TOL, e
+
+
 @pytest.mark.parametrize("kind,bc,nx,ny,steps", [("quadrants", 1, 48, 40, 20), ("quadrants", 0, 32, 36, 12),
                                                  ("vortex", 1, 64, 64, 10)])
 def test_step_2d_shadow(G, oracle, kind, bc, nx, ny, steps):
@@ -279,7 +341,7 @@ def test_step_2d_trajectory(G, oracle, kind, bc, nx, ny, steps):
     grid = _grid(G, W, bc)
     gW, gdW, gdt, st = _run_gpu(G, grid, W, dW, steps)
     oW, odW, odt, og = oracle.step(_oprm(oracle, 2, bc), W, dW, steps)
-    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(gdt, odt))
+    e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(gdt, odt))
     _say("errors W %.3e dW %.3e dt %.3e guard %d/%d" % (*e, st.guard, og))
     assert st.nonfinite == 0 and st.guard == og
     assert max(e) < TOL, e
@@ -330,7 +392,7 @@ def test_full_size_512_sampled_steps(G, oracle):
         gW, gdW = grid.interior(Wd), grid.interior(dWd)
         _say("oracle step %d at 512^2" % target)
         oW, odW, odt, og = oracle.step(prm, W0, dW0, 1)
-        e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(dts.cpu().numpy(), odt))
+        e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(dts.cpu().numpy(), odt))
         _say("step %d errors W %.3e dW %.3e dt %.3e guard %d/%d" % (target, *e, st.guard, og))
         assert st.guard == og
         assert max(e) < TOL, e
@@ -381,7 +443,7 @@ def test_step_tiny_grids(G, oracle, nx, ny, bc):
     grid = _grid(G, W, bc)
     gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 3)
     oW, odW, odt, og = oracle.step(_oprm(oracle, 2, bc), W, dW, 3, dx=grid.dx, dy=grid.dy)
-    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
+    e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
     _say("  errors W %.2e dW %.2e dt %.2e" % e)
     assert gg.guard == og and max(e) < TOL, e
 
@@ -393,7 +455,7 @@ def test_step_tiny_1d(G, oracle, nx, bc):
     grid = _grid(G, W, bc)
     gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 3)
     oW, odW, odt, og = oracle.step(_oprm(oracle, 1, bc), W, dW, 3, dx=grid.dx)
-    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(gdt, odt))
+    e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)), rel_err(gdt, odt))
     assert gg.guard == og and max(e) < TOL, e
 
 
@@ -460,7 +522,7 @@ def test_step_reflecting_2d(G, oracle, bcs):
     grid = G.Grid(2, 40, 36, bc=list(bcs))
     gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 8)
     oW, odW, odt, og = oracle.step(oracle.params(ndim=2, bc=list(bcs)), W, dW, 8, dx=grid.dx, dy=grid.dy)
-    e = (rel_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
+    e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
     _say("  W %.2e dW %.2e dt %.2e" % e)
     assert gg.guard == og and max(e) < TOL, e
 
@@ -518,7 +580,7 @@ def test_titarev_toro_fixed_ends_shadowed(G, oracle):
         st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
         oW, odW, _, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, fixed_dt=float(dts.item()))
         gW, gdW = grid.interior(Wd), grid.interior(dWd)
-        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        worst = [max(worst[0], state_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
         assert st.guard == og and st.nonfinite == 0
     assert max(worst) < TOL, worst
     # the caller's ghost cells are kept as given
@@ -549,7 +611,7 @@ def test_characteristic_1d_shadowed(G, oracle, problem):
         st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
         oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx)
         gW, gdW = grid.interior(Wd), grid.interior(dWd)
-        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        worst = [max(worst[0], state_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
         assert st.guard == og and st.nonfinite == 0
         assert float(dts.item()) == pytest.approx(float(odt[0]), rel=1e-13)
     assert max(worst) < TOL, worst
@@ -575,7 +637,7 @@ def test_characteristic_2d_shadowed(G, oracle, kind, bc, nx, ny, steps):
         assert st.nonfinite == 0
         oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, dy=grid.dy)
         gW, gdW = grid.interior(Wd), grid.interior(dWd)
-        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        worst = [max(worst[0], state_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
         assert st.guard == og, (n, st.guard, og)
         assert float(dts.item()) == pytest.approx(float(odt[0]), rel=1e-13)
     _say("worst W %.3e dW %.3e" % tuple(worst))
@@ -599,10 +661,13 @@ def test_strong_quadrants_2d_shadowed(G, oracle, char):
         st = G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts, stats=True)
         oW, odW, odt, og = oracle.step(prm, W0, dW0, 1, dx=grid.dx, dy=grid.dy)
         gW, gdW = grid.interior(Wd), grid.interior(dWd)
-        worst = [max(worst[0], rel_err(gW, oW)), max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
+        worst = [max(worst[0], state_err(gW, oW)),
+                 max(worst[1], rel_err(gdW, odW, grad_scale(oW, odW, grid.dx)))]
         assert st.guard == og and st.nonfinite == 0, (n, st.guard, og)
     _say("worst W %.3e dW %.3e" % tuple(worst))
-    assert max(worst) < TOL, worst
+    # W at 1e-12 per cell; the gradients also carry the chi term of the
+    # second-order part at these strong jumps (see CHI_TOL)
+    assert worst[0] < TOL and worst[1] < TOL + CHI_TOL * 0.5 ** 2 / 3.0, worst
 
 
 def test_characteristic_2d_strong_quadrants_run(G):
@@ -676,3 +741,40 @@ def test_shu_osher_full_run(G):
     Wn, n, t, guard = _run_to(G, grid, W, dW, 1.8)
     _say("Shu-Osher: %d steps to t = %.4f, guard %d, rho in [%.4f, %.4f]" % (n, t, guard, Wn[0].min(), Wn[0].max()))
     assert Wn[0].min() > 0 and Wn[0].max() > 3.5
+
+
+# ------------------------------------------------------------------ failure injection
+@pytest.mark.parametrize("ndim,fault", [(1, "nan"), (1, "negative_p"), (2, "nan"), (2, "negative_p"),
+                                        (2, "negative_rho")])
+def test_nonphysical_state_is_reported(G, ndim, fault):
+    # a state corrupted on the host (a NaN, a negative pressure or density in
+    # one cell) makes gks_step return GENO_ENONPHYS once it synchronises;
+    # every kernel still runs to its end (fixed dt: the CFL bound of the bad
+    # cell is not needed)
+    _say("nonphysical", ndim, fault)
+    if ndim == 1:
+        W, dW = inputs.sine_1d(64)
+        grid = G.Grid(1, 64, bc=0, dt_fixed=1e-4)
+        cell = (slice(None), 0, 17)
+    else:
+        W, dW = inputs.random_smooth_2d(24, 20, 3)
+        grid = G.Grid(2, 24, 20, bc=0, dt_fixed=1e-4)
+        cell = (slice(None), 7, 11)
+    W = W.copy()
+    nv = W.shape[0]
+    if fault == "nan":
+        W[(0,) + cell[1:]] = np.nan
+    elif fault == "negative_p":
+        ke = 0.5 * sum(W[(k,) + cell[1:]] ** 2 for k in range(1, nv - 1)) / W[(0,) + cell[1:]]
+        W[(nv - 1,) + cell[1:]] = 0.5 * ke     # rho E below the kinetic energy: p < 0
+    else:
+        W[(0,) + cell[1:]] = -0.5
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    with pytest.raises(G.GenoError) as e:
+        G.gks_step(grid, Wd, dWd, grid.workspace(), 2, stats=True)
+    assert e.value.code == G.GENO_ENONPHYS, e.value
+    # the library stays usable: a clean state on the same grid runs
+    Wd, dWd = grid.to_device(inputs.sine_1d(64)[0] if ndim == 1 else inputs.random_smooth_2d(24, 20, 3)[0]), \
+        grid.to_device(dW)
+    st = G.gks_step(grid, Wd, dWd, grid.workspace(), 2, stats=True)
+    assert st.nonfinite == 0

@@ -65,14 +65,24 @@ def _run(T, mesh, W, dW):
 
 
 def _compare(O, mesh, W, dW, got, gchi, cells=None):
-    ref, rchi, _ = O.reconstruct(mesh, W, dW, cells=cells)
+    """GPU states against the oracle's own states (its own chi). chi of Eq. (4)
+    is compared at 1e-8: IS^tau = |IS^H - IS~^H| is a difference of
+    indicators whose rounding (~1e-16 IS^H) relative to IS^L + eps moves chi
+    by up to that much. The blended states then differ by the rounding of
+    their arithmetic (1e-12 of the variable's scale) plus |chi_gpu -
+    chi_oracle| times the distance of the oracle's two candidates,
+    |q^H - q^L| (Eq. (3))."""
+    ref, rchi, info = O.reconstruct(mesh, W, dW, cells=cells)
     sel = np.arange(W.shape[1]) if cells is None else np.asarray(cells)
-    assert np.abs(gchi[sel] - rchi[sel]).max() < 1e-8
-    ref2, _, _ = O.reconstruct(mesh, W, dW, cells=cells, chi_given=gchi)
+    dchi = np.abs(gchi - rchi)
+    assert dchi[sel].max() < 1e-8
     sc = np.maximum(np.abs(W).max(axis=1), 1e-300)      # per-variable scale
-    err = np.abs(got[sel] - ref2[sel]) / sc[None, None, None, :, None]
-    _say("max rel err %.3e, chi err %.3e" % (err.max(), np.abs(gchi[sel] - rchi[sel]).max()))
-    assert err.max() < TOL
+    spread = np.abs(info["high"] - info["low"])           # [n, 3, 2, nv, 3]
+    bound = TOL * sc[None, None, None, :, None] + dchi[:, None, None, :, None] * spread
+    diff = np.abs(got - ref)
+    err = diff[sel] / sc[None, None, None, :, None]
+    _say("max rel err %.3e, chi err %.3e" % (err.max(), dchi[sel].max()))
+    assert np.all(diff[sel] <= bound[sel]), (err.max(), dchi[sel].max())
     return rchi
 
 
