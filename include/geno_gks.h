@@ -251,6 +251,30 @@ int gks_flux(const geno_grid* g, const void* face_state, double dt, int dir, voi
 int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double* dt_out,
              geno_stats* stats, void* stream);
 
+/* Size of the device memory gks_step_noalloc works in: 64 MiB on every
+ * device the library runs on (enough for the workspace of a 2-D float64 grid
+ * of up to about 290 x 290 cells, mixed precision about 390 x 390; see
+ * gks_workspace_bytes). */
+#define GENO_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* gks_step without a workspace argument and without allocating: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). The same steps, kernels
+ * and results as gks_step (bitwise), with the workspace taken from a
+ * file-scope device array of GENO_NOALLOC_SCRATCH_BYTES that each device
+ * holds from the library's load until the process ends. The caller passes
+ * the state and the outputs as for gks_step.
+ * Calls on one device share that device's array and keep the last call's
+ * contents in it (every entry a step reads is written by that step first):
+ * calls that overlap on one device (other streams, other host threads)
+ * race; serialise them. No work counting (geno_count_enable) is done.
+ * Errors: GENO_EINVAL if the grid's workspace (gks_workspace_bytes) exceeds
+ * GENO_NOALLOC_SCRATCH_BYTES, for a bad grid, null W or dW, or nsteps < 0;
+ * otherwise as gks_step. Never calls hipMalloc, hipFree or an allocating
+ * library routine. */
+int gks_step_noalloc(const geno_grid* g, void* W, void* dW, int nsteps, double* dt_out,
+                     geno_stats* stats, void* stream);
+
 /* The paper's comparison of nonlinear reconstructions (Sec. 5), on every
  * face-side of direction dir, from the stencils of the normal step: the
  * share of the high-order linear reconstruction each method keeps.

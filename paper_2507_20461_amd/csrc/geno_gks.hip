@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -2368,6 +2369,38 @@ int batch_stats(const BatchPlan& P, char* ws, const geno_grid* grids, geno_stats
 // operation costs per work class (opcount.hip)
 int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* costs);
 
+// Device memory of gks_step_noalloc: its whole workspace, one copy of
+// GENO_NOALLOC_SCRATCH_BYTES on every device the library runs on, held until
+// the process ends. In host code this name is not a device address; the
+// address of each device's copy is taken once with hipGetSymbolAddress and
+// kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[GENO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+void* scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+std::mutex scratch_mu;
+
+// the device address of the current device's scratch (looked up on the
+// first call on that device, with that device current)
+int scratch_of_current(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(GENO_EINVAL, "device %d beyond the %d devices the scratch table holds", dev,
+                SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GENO_EHIP, "no device address for the scratch array");
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return GENO_OK;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -2575,6 +2608,47 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
                            s));
     cnt = Cnt{g_cnt.p, g_cnt.cap};
   }
+  Ctrl* ctrl = nullptr;
+  if (g->params.precision == GENO_MIXED)
+    rc = step_t<float>(g, (double*)W, (float*)dW, ws, nsteps, dt_out, cnt, s, &ctrl);
+  else
+    rc = step_t<double>(g, (double*)W, (double*)dW, ws, nsteps, dt_out, cnt, s, &ctrl);
+  if (rc) return rc;
+  if (stats) {
+    Ctrl h;
+    HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stats->guard = (long long)h.guard;
+    stats->nonfinite = (long long)h.nonfinite;
+    stats->last_dt = nsteps > 0 ? h.dt : 0.0;
+    if (h.nonfinite)
+      return fail(GENO_ENONPHYS, "%llu non-physical cells (non-finite, rho <= 0 or p <= 0)",
+                  h.nonfinite);
+  }
+  return GENO_OK;
+}
+
+int gks_step_noalloc(const geno_grid* g, void* W, void* dW, int nsteps, double* dt_out,
+                     geno_stats* stats, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!W || !dW) return fail(GENO_EINVAL, "null pointer");
+  if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
+  rc = check_gate(g);
+  if (rc) return rc;
+  const size_t need = layout_of(g).total;
+  if (need > (size_t)GENO_NOALLOC_SCRATCH_BYTES)
+    return fail(GENO_EINVAL,
+                "grid needs %zu bytes of workspace, above the %zu bytes of the allocation-free "
+                "scratch (use gks_step with a workspace)",
+                need, (size_t)GENO_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  rc = scratch_of_current(&ws);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // no work counting here (its per-block slots are allocated on first use);
+  // every workspace entry the step reads is written by it first
+  const Cnt cnt{nullptr, 0};
   Ctrl* ctrl = nullptr;
   if (g->params.precision == GENO_MIXED)
     rc = step_t<float>(g, (double*)W, (float*)dW, ws, nsteps, dt_out, cnt, s, &ctrl);

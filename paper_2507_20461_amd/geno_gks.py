@@ -56,7 +56,7 @@ class geno_stats(ctypes.Structure):
 
 EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_grid_init",
            "geno_state_elems", "gks_workspace_bytes", "geno_reconstruct", "gks_flux", "gks_step",
-           "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
+           "gks_step_noalloc", "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read", "geno_op_costs",
            "geno_kernel_name", "geno_tuning_default", "gks_batched_workspace_bytes", "gks_step_batched",
            "geno_autotune_batched", "geno_harvest", "geno_mlp_train_workspace_bytes", "geno_mlp_grad",
            "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob",
@@ -96,6 +96,8 @@ def lib():
         L.gks_flux.argtypes = [ctypes.POINTER(geno_grid), vp, d, i, vp, vp, vp, vp]
         L.gks_step.argtypes = [ctypes.POINTER(geno_grid), vp, vp, vp, i, vp,
                                ctypes.POINTER(geno_stats), vp]
+        L.gks_step_noalloc.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp,
+                                       ctypes.POINTER(geno_stats), vp]
         L.geno_timing_enable.argtypes = [i]
         L.geno_count_enable.argtypes = [i]
         L.geno_timing_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
@@ -129,7 +131,7 @@ def lib():
                      "geno_mlp_infer", "geno_gate_prob", "geno_conserved_totals", "geno_linearity"):
             getattr(L, name).restype = i
         for name in ("geno_params_default", "geno_grid_init", "geno_reconstruct", "gks_flux", "gks_step",
-                     "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
+                     "gks_step_noalloc", "geno_timing_enable", "geno_count_enable", "geno_timing_read", "geno_work_read",
                      "geno_op_costs"):
             getattr(L, name).restype = i
         if L.geno_abi_version() != ABI_VERSION:
@@ -307,6 +309,23 @@ def gks_step(grid, W, dW, ws, nsteps, dt_out=None, stats=False, stream=None):
     st = geno_stats() if stats else None
     rc = lib().gks_step(ctypes.byref(grid.g), _ptr(W), _ptr(dW), _ptr(ws), int(nsteps), _ptr(dt_out),
                         ctypes.byref(st) if st is not None else None, _stream(stream))
+    _check(rc)
+    return st
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # GENO_NOALLOC_SCRATCH_BYTES
+
+
+def gks_step_noalloc(grid, W, dW, nsteps, dt_out=None, stats=False, stream=None):
+    """gks_step with the library's own per-device scratch as workspace (no
+    allocation by the library; calls overlapping on one device race).
+    Returns a geno_stats if stats=True (synchronises)."""
+    _check_state(grid, W, dW)
+    if dt_out is not None:
+        _need(dt_out, torch.float64, int(nsteps), "dt_out")
+    st = geno_stats() if stats else None
+    rc = lib().gks_step_noalloc(ctypes.byref(grid.g), _ptr(W), _ptr(dW), int(nsteps), _ptr(dt_out),
+                                ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc)
     return st
 
