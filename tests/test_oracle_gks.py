@@ -370,3 +370,42 @@ def test_finite_tau_point_vs_quadrature(oracle, ratio):
     for got, want, name in ((F[0], ref[0], "F"), (Ft[0], ref[1], "Ft"), (Wh[0], ref[2], "W(dt/2)"),
                             (Wf[0], ref[3], "W(dt)")):
         assert np.abs(got - want).max() < 1e-9 * (1.0 + np.abs(want).max()), (name, got, want)
+
+
+def test_second_order_weight_of_the_interface_value(oracle):
+    # The weight phi(r) of the interface value's second-order term (reading):
+    # with equal side states and a jump of the density's normal slope only,
+    # the averaged derivatives, hence the unweighted W_tt, are the same for
+    # every jump size, and r = dt c |dn_l - dn_r|_rho / (rho_l + rho_r).
+    # r <= 1e-2 keeps phi = 1, r = 0.055 gives phi = 1 - (0.045 / 0.09)^2 =
+    # 0.75, r >= 0.1 gives 0; a state jump of r = 0.5 gives 0 as well;
+    # rounding-size state differences keep phi = 1
+    d = _euler_wtt_symbolic(2)
+    W = d["W"][None]
+    sec = np.stack([d["Wxx"], d["Wxy"], d["Wyy"]])[None]
+    dt = 1e-3
+    prm = oracle.params(ndim=2)
+    rho, U, V = d["W"][0], d["W"][1] / d["W"][0], d["W"][2] / d["W"][0]
+    p = (GAMMA - 1) * (d["W"][3] - 0.5 * rho * (U * U + V * V))
+    c = math.sqrt(GAMMA * p / rho)
+
+    def w2(r_slope, Wr=None):
+        delta = np.zeros(4)
+        delta[0] = r_slope * rho / (dt * c)       # |dn_l - dn_r|_rho = 2 delta
+        nl, nr = d["Wx"] + delta, d["Wx"] - delta
+        out = oracle.gks_points(prm, 2, W, W if Wr is None else Wr, nl[None], nr[None],
+                                d["Wy"][None], d["Wy"][None], dt=dt, sec=sec, full=True)
+        return out[4][0]
+    ref = w2(0.0)
+    scale = np.abs(ref).max()
+    assert np.abs(ref - d["Wtt"]).max() < 1e-12 * np.abs(d["Wtt"]).max()
+    for r, phi in ((0.005, 1.0), (0.01, 1.0), (0.055, 0.75), (0.1, 0.0), (0.3, 0.0)):
+        got = w2(r)
+        assert np.abs(got - phi * ref).max() <= 1e-12 * scale, (r, phi, got / ref)
+    # a jump of the states (pressure ratio giving r = 0.5): the term is off
+    Wj = d["W"].copy()
+    Wj[3] += (3.0 * p) / (GAMMA - 1)                 # p_r = 4 p_l: r = 3/5
+    assert np.all(w2(0.0, Wj[None]) == 0.0)
+    # rounding-size state differences: phi = 1
+    Wn = d["W"] * (1.0 + 4e-16 * np.array([1.0, -1.0, 1.0, -1.0]))
+    assert np.abs(w2(0.0, Wn[None]) - ref).max() < 1e-11 * scale

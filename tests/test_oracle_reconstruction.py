@@ -186,3 +186,90 @@ def test_path_function_limits(oracle):
     det = oracle.geno_side_detail(prm, _dat(Q, np.zeros(5)), 0, 0.5, 0.0)
     assert det["chi"] < 1e-20
     assert math.tanh(20.0) == 1.0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_second_derivative_reproduces_degree_7(oracle, seed):
+    # with eps huge (chi = 1) the point's h^2 d2/dx2 is that of p^7, exact
+    # for a polynomial of degree 7: 2 c_2 at the face x = 0 (h = 1)
+    rng = np.random.default_rng(10 + seed)
+    coefs = [Fr(int(c), 7) for c in rng.integers(-20, 21, size=8)]
+    q, g = _poly_avgs(coefs, [-2, -1, 0, 1])
+    out = oracle.geno_face(oracle.params(eps=1e30), [float(x) for x in q], [float(x) for x in g])
+    scale = max(abs(float(x)) for x in q)
+    assert abs(out[6] - 2.0 * float(coefs[2])) < 1e-11 * scale
+    assert abs(out[7] - 2.0 * float(coefs[2])) < 1e-11 * scale
+
+
+def test_second_derivative_takes_the_low_order_branch_at_a_jump(oracle):
+    # cells j-1..j+2 with averages 0, 0, 1, 2 and h-scaled gradients 0, 0, 1,
+    # 1 (a jump at the face): the left side's smoothest sub-stencil {j-1, j}
+    # is constant, so with chi ~ 0 its second derivative is ~0, while the
+    # linear p^7 (eps huge) has a large one
+    q, g = [0.0, 0.0, 1.0, 2.0], [0.0, 0.0, 1.0, 1.0]
+    lin = oracle.geno_face(oracle.params(eps=1e30), q, g)
+    out = oracle.geno_face(oracle.params(), q, g)
+    assert abs(lin[6]) > 1.0 and out[2] < 1e-6
+    assert abs(out[6]) < 1e-6 * abs(lin[6])
+
+
+def _poly2d_cells(nx, ny, kind):
+    """Exact cell averages and averaged gradients on [0,1]^2 of
+    f = y^2 (kind 'yy') or f = x y (kind 'xy'), and of the conserved state
+    W = W0 + A f (every component a polynomial in x, y)."""
+    h, k = 1.0 / nx, 1.0 / ny
+    x0 = np.arange(nx) * h
+    y0 = np.arange(ny) * k
+    X0, Y0 = np.meshgrid(x0, y0)
+    X1, Y1 = X0 + h, Y0 + k
+    xm, ym = 0.5 * (X0 + X1), 0.5 * (Y0 + Y1)
+    if kind == "yy":
+        f = (Y1 ** 3 - Y0 ** 3) / (3.0 * k)
+        fx, fy = np.zeros_like(f), 2.0 * ym
+    else:
+        f = xm * ym
+        fx, fy = ym, xm
+    W0 = np.array([1.0, 0.1, -0.05, 2.5])
+    A = np.array([0.05, 0.02, 0.03, 0.1])
+    W = W0[:, None, None] + A[:, None, None] * f[None]
+    dW = np.concatenate([A[:, None, None] * fx[None], A[:, None, None] * fy[None]])
+    return W, dW, A
+
+
+@pytest.mark.parametrize("kind", ["yy", "xy"])
+def test_point_second_derivatives_2d_closed_forms(oracle, kind):
+    # x-faces, chi = 1 (eps huge), interior faces whose stencils stay inside
+    # the grid. f = y^2: h_y^2 d_tt = 2 h_y^2 A, the normal and cross terms 0
+    # (the tangential quadratic through three face averages is exact).
+    # f = x y: h_x h_y d_nt = h_x h_y A (central difference of the face rows'
+    # h d_n, exact for a bilinear field), d_nn = d_tt = 0
+    nx = ny = 10
+    W, dW, A = _poly2d_cells(nx, ny, kind)
+    prm = oracle.params(ndim=2, bc=oracle.TRANSMISSIVE, eps=1e30)
+    _, sec, _ = oracle.face_states(prm, W, dW, 0, second=True)
+    h = 1.0 / nx
+    want = {"yy": (0.0, 0.0, 2.0 * h * h), "xy": (0.0, h * h, 0.0)}[kind]
+    for gp in range(2):
+        for m in range(3):
+            got = sec[gp, m][:, 2:ny - 2, 3:nx - 2]          # [var, rows, faces]
+            ref = want[m] * A[:, None, None]
+            assert np.abs(got - ref).max() < 1e-13, (kind, gp, m, np.abs(got - ref).max())
+
+
+def test_second_derivative_of_the_low_order_quadratic(oracle):
+    # a parabola c0 + c1 x + c2 x^2 on cells j-1, j and a jump to 1000 at the
+    # face: the left side's low-order branch is the sub-stencil {j-1, j},
+    # whose quadratic is the parabola itself (h^2 q'' = 2 c2); the side's
+    # value is chi p^7'' + (1 - chi) 2 c2, up to the ENO weights leaking to
+    # the sub-stencils across the jump (omega ~ d_k (IS_1 / IS_k)^2 ~ 1e-11,
+    # times their curvature ~ 1e3)
+    coefs = [Fr(1, 3), Fr(-2, 5), Fr(3, 7)]
+    q, g = _poly_avgs(coefs, [-2, -1])
+    q = [float(x) for x in q] + [1000.0, 1000.0]
+    g = [float(x) for x in g] + [0.0, 0.0]
+    lin = oracle.geno_face(oracle.params(eps=1e30), q, g)
+    out = oracle.geno_face(oracle.params(), q, g)
+    chi = out[2]
+    assert chi < 0.01
+    want = chi * lin[6] + (1.0 - chi) * 2.0 * float(coefs[2])
+    assert abs(out[6] - want) < 1e-6, (out[6], want)
