@@ -305,14 +305,26 @@ int geno_linearity(const geno_grid* g, void* W, void* dW, int dir, double* chi3,
 int geno_conserved_totals(const geno_grid* g, const void* W, double* totals, void* stream);
 
 /* ---- batched form --------------------------------------------------------
- * Many independent 2-D grids advanced together: each kernel kind runs as one
- * launch over the work of every grid (work-group ranges concatenated; each
- * work-group looks up its grid), and one step of the whole batch is captured
- * once as a HIP graph and replayed. Grids may differ in size and boundary
- * conditions; every other field of geno_params (method constants, precision,
- * cfl, dt_fixed, eps_ulps) must be equal across the batch. Each grid keeps its
- * own time step (its own CFL condition). Results are identical to gks_step on
- * each grid alone. */
+ * Many independent 2-D grids advanced together. Grids may differ in size and
+ * boundary conditions; every other field of geno_params (method constants,
+ * precision, cfl, dt_fixed, eps_ulps) must be equal across the batch. Each
+ * grid keeps its own time step (its own CFL condition). Results are
+ * identical to gks_step on each grid alone, in every mode:
+ *   GENO_BATCH_EAGER: each kernel kind runs as one launch over the work of
+ *     every grid (work-group ranges concatenated; each work-group looks up
+ *     its grid), twelve launches per step;
+ *   GENO_BATCH_GRAPH: the same twelve launches captured once as a HIP graph
+ *     and replayed;
+ *   GENO_BATCH_PERSISTENT: reserved for one persistent launch per step (a
+ *     device work queue over the blocks of all phases of all grids, each
+ *     block started once its grid's previous phase is complete). Not
+ *     available in this build: the call returns GENO_EINVAL.
+ * A step's graph is kept across calls (up to 8 graphs, the least recently
+ * used replaced) and reused while the device, workspace, batch plan and
+ * method constants are the same. */
+#define GENO_BATCH_EAGER 0
+#define GENO_BATCH_GRAPH 1
+#define GENO_BATCH_PERSISTENT 2
 
 /* Work-group shapes of the batched launches (chosen by geno_autotune_batched
  * or given by the caller). block_*: threads per work-group of the normal GENO,
@@ -346,9 +358,9 @@ size_t gks_batched_workspace_bytes(int ngrids, const geno_grid* grids);
  *   gks_step on its grid (element types of the batch's precision).
  * ws: workspace of gks_batched_workspace_bytes bytes.
  * tune: work-group shapes (NULL = defaults).
- * use_graph: if non-zero, one step of the batch is captured into a HIP graph
- *   and the graph is launched nsteps times; the stream must then not be the
- *   NULL stream (GENO_EINVAL otherwise).
+ * use_graph: the mode, GENO_BATCH_EAGER, GENO_BATCH_GRAPH or
+ *   GENO_BATCH_PERSISTENT (GENO_EINVAL otherwise); in the graph modes the
+ *   stream must not be the NULL stream (GENO_EINVAL otherwise).
  * step_ms (host, may be NULL): nsteps floats, the duration of each step from
  *   events recorded between the steps on the stream.
  * stats (host, may be NULL): counters summed over the grids.
@@ -357,6 +369,10 @@ size_t gks_batched_workspace_bytes(int ngrids, const geno_grid* grids);
 int gks_step_batched(int ngrids, const geno_grid* grids, void* const* W, void* const* dW, void* ws,
                      int nsteps, const geno_tuning* tune, int use_graph, float* step_ms,
                      geno_stats* stats, void* stream);
+
+/* Number of batched-step graphs instantiated by this process so far (a call
+ * that reuses a kept graph does not add one). Measurement support. */
+long long geno_batched_graphs_built(void);
 
 /* Autotuner of the batched work-group shapes: for each launch kind in turn
  * (normal GENO, faces, tau > 0 faces, update) it runs trial_steps steps of

@@ -1646,6 +1646,149 @@ __global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
 }
 
 // ---------------------------------------------------------------------------
+// Persistent batched step: one launch advances every grid of the batch by one
+// step. The work items are the work-groups of the twelve phases of a step
+// (stages 1 and 2, each: normal x, faces x, normal y, faces y, tau > 0
+// faces, update), numbered phase-major (every grid's blocks of a phase, then
+// the next phase). A work-group takes the next item from a device counter and
+// waits until the grid's previous phase is complete (a per-grid, per-phase
+// count of finished blocks, release/acquire at device scope), runs the block
+// with the phase's body, and counts it finished. Items are taken in an order
+// in which every dependency precedes its dependents, and a work-group that
+// waits holds an item whose dependencies were taken earlier by running
+// work-groups that never wait on later items, so the launch always drains;
+// each wait is also bounded (spin_limit): past it the launch sets an error
+// flag, counts the block finished without running it, and goes on, so every
+// work-group reaches the end. The last work-group to finish clears the
+// counters for the next launch.
+// A work-group is one wave, so that a work-group holding an item is wholly
+// resident (no barrier of a holder waits on waves not yet launched), and the
+// launch has at most as many work-groups as the largest phase has items.
+// Waiting polls with relaxed loads and a sleep between polls; one acquire
+// fence follows the last poll (an acquiring poll would invalidate the
+// caches at every poll of every waiting wave).
+// ---------------------------------------------------------------------------
+constexpr int PB = 64;                   // threads per persistent work-group (one wave)
+constexpr int PSEG = 12;                 // phases per step
+struct PSegs {
+  int start[PSEG + 1];                   // first item of each phase
+};
+// sched: [0] next item, [1] finished work-groups, [2] error flag (cleared by
+// the host-side start of a call, never by the kernel); done: [grid][phase]
+__device__ __forceinline__ int pseg_kind(int seg) {
+  constexpr int order[6] = {BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE};
+  return order[seg % 6];
+}
+
+__global__ void __launch_bounds__(PB) kb_sched_clear(unsigned int* __restrict__ sched,
+                                                     unsigned int* __restrict__ done, int n) {
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t < 4) sched[t] = 0u;
+  for (int i = t; i < n; i += (int)(gridDim.x * blockDim.x)) done[i] = 0u;
+}
+
+template <typename T, bool CHAR>
+__global__ void __launch_bounds__(PB) __attribute__((amdgpu_waves_per_eu(4))) kb_persist(const BEntry* __restrict__ tab,
+                                                 const int* __restrict__ offs, int ngrids,
+                                                 geno::KParams k, PSegs segs,
+                                                 unsigned int* __restrict__ sched,
+                                                 unsigned int* __restrict__ done,
+                                                 unsigned int spin_limit) {
+  __shared__ int s_item, s_run, s_last;
+  const int total = segs.start[PSEG];
+  const Cnt cnt{nullptr, 0};
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&sched[0], 1u);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= total) break;
+    int seg = 0;
+    while (segs.start[seg + 1] <= it) ++seg;
+    const int kind = pseg_kind(seg);
+    const int stage = seg < 6 ? 1 : 2;
+    const int* st = offs + kind * (ngrids + 1);
+    const int gb = it - segs.start[seg];
+    const int gi = find_grid(st, ngrids, gb);
+    const int lb = gb - st[gi];
+    if (threadIdx.x == 0) {
+      int run = 1;
+      if (seg > 0) {
+        const int* pst = offs + pseg_kind(seg - 1) * (ngrids + 1);
+        const unsigned int need = (unsigned int)(pst[gi + 1] - pst[gi]);
+        unsigned int* d = &done[gi * PSEG + seg - 1];
+        unsigned int n = 0;
+        while (__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          ++n;
+          // past the bound, or once any wait of this launch has failed
+          if (n > spin_limit ||
+              ((n & 255u) == 0u &&
+               __hip_atomic_load(&sched[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+            run = 0;
+            atomicOr(&sched[2], 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(4);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      s_run = run;
+    }
+    __syncthreads();
+    if (s_run) {
+      const BEntry& e = tab[gi];
+      const double* W = stage == 1 ? e.W : e.wst;
+      const T* dW = (const T*)(stage == 1 ? e.dW : e.dwst);
+      switch (kind) {
+        case BK_NORMAL_X:
+          normal_body<0, T, CHAR>(e.geo, k, W, dW, (T*)e.fr[0], nullptr, e.ctrl,
+                                  stage == 1 ? e.part : nullptr, e.npart, nullptr, 0, cnt, lb);
+          break;
+        case BK_FACES_X:
+          faces_body<0, 1, T>(e.geo, k, W, (const T*)e.fr[0], (T*)e.fl[0], e.ctrl, stage == 1,
+                              cnt, e.queue[0], lb);
+          break;
+        case BK_NORMAL_Y:
+          normal_body<1, T, CHAR>(e.geo, k, W, dW, (T*)e.fr[1], nullptr, e.ctrl, nullptr, 0,
+                                  nullptr, 0, cnt, lb);
+          break;
+        case BK_FACES_Y:
+          faces_body<1, 1, T>(e.geo, k, W, (const T*)e.fr[1], (T*)e.fl[1], e.ctrl, stage == 1,
+                              cnt, e.queue[1], lb);
+          break;
+        case BK_SLOW:
+          slow_body<T>(e.geo, k, W, (const T*)e.fr[0], (const T*)e.fr[1], (T*)e.fl[0],
+                       (T*)e.fl[1], e.ctrl, stage == 1, cnt, e.queue[0], e.queue[1], lb,
+                       e.slow_nb);
+          break;
+        default:
+          if (stage == 1)
+            update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (T*)e.rg,
+                                 (const T*)e.fl[0], (const T*)e.fl[1], e.ctrl, e.part, cnt, lb);
+          else
+            update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (T*)e.rg,
+                                 (const T*)e.fl[0], (const T*)e.fl[1], e.ctrl, e.part, cnt, lb);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(&done[gi * PSEG + seg], 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // the last work-group to finish clears the counters for the next launch
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(&sched[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+             gridDim.x - 1u;
+  __syncthreads();
+  if (s_last) {
+    for (int i = (int)threadIdx.x; i < ngrids * PSEG; i += PB) done[i] = 0u;
+    if (threadIdx.x == 0) {
+      sched[0] = 0u;
+      sched[1] = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
 struct Layout {
@@ -2038,7 +2181,8 @@ struct BatchPlan {
   std::vector<BEntry> tab;
   std::vector<int> offs;         // [kind][ngrids + 1] range starts
   std::vector<size_t> goff;      // workspace offset of each grid
-  size_t tab_off = 0, offs_off = 0, total = 0;
+  size_t tab_off = 0, offs_off = 0, sched_off = 0, total = 0;
+  PSegs segs{};                  // persistent step: first item of each phase
 };
 
 bool bs_ok(int b) { return b == 128 || b == 256 || b == 512; }
@@ -2125,6 +2269,8 @@ int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPl
   off = align256(off + sizeof(BEntry) * ngrids);
   P->offs_off = off;
   off = align256(off + sizeof(int) * P->offs.size());
+  P->sched_off = off;   // persistent step: 4 scheduler words, then [grid][phase] counts
+  off = align256(off + sizeof(unsigned int) * (4 + (size_t)PSEG * ngrids));
   long long cnt[BK_N] = {};
   for (int i = 0; i < ngrids; ++i) {
     const geno_grid* g = &grids[i];
@@ -2155,6 +2301,13 @@ int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPl
   for (int k = 0; k < BK_N; ++k) {
     P->offs[(size_t)k * (ngrids + 1) + ngrids] = (int)cnt[k];
     P->nb[k] = (int)cnt[k];
+  }
+  P->segs.start[0] = 0;
+  const int order[6] = {BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE};
+  for (int q = 0; q < PSEG; ++q) {
+    const long long next = (long long)P->segs.start[q] + P->nb[order[q % 6]];
+    if (next > 0x7fffffff) return fail(GENO_EINVAL, "batch too large");
+    P->segs.start[q + 1] = (int)next;
   }
   P->total = off;
   return GENO_OK;
@@ -2256,39 +2409,171 @@ int batch_step(const BatchPlan& P, const BEntry* tab, const int* offs, const gen
   return GENO_OK;
 }
 
+// Instantiated graphs of one batched step, kept across calls and looked up by
+// everything their kernel arguments are made of (device, workspace, plan,
+// method constants, counting slots); at most GRAPH_CACHE, the least recently
+// used replaced first.
+struct GraphEntry {
+  std::vector<unsigned char> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long used = 0;
+};
+constexpr size_t GRAPH_CACHE = 8;
+std::vector<GraphEntry> g_graphs;
+std::mutex g_graphs_mu;
+unsigned long long g_graph_clock = 0;
+long long g_graph_builds = 0;   // graphs instantiated so far (for tests)
+
+template <typename V>
+void key_put(std::vector<unsigned char>& key, const V& v) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+  key.insert(key.end(), b, b + sizeof(V));
+}
+
+// persistent step: work-groups of the launch (every CU filled to the kernel's
+// occupancy, at most one per item)
+template <typename T>
+int persist_wgs(const BatchPlan& P, bool charvars, int* nwg) {
+  int dev = 0, ncu = 0, per = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (charvars)
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kb_persist<T, true>, PB, 0));
+  else
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kb_persist<T, false>, PB, 0));
+  int widest = 1;
+  for (int q = 0; q < PSEG; ++q) widest = std::max(widest, P.segs.start[q + 1] - P.segs.start[q]);
+  const long long n = (long long)std::max(1, ncu) * std::max(1, per);
+  *nwg = (int)std::max<long long>(1, std::min<long long>(n, widest));
+  return GENO_OK;
+}
+
+constexpr unsigned int PERSIST_SPIN = 1u << 21;   // polls of one dependency wait (~1 s)
+
+template <typename T>
+int persist_step(const BatchPlan& P, const BEntry* tab, const int* offs, char* ws,
+                 const geno::KParams& k, int nwg, hipStream_t s) {
+  unsigned int* sched = reinterpret_cast<unsigned int*>(ws + P.sched_off);
+  unsigned int* done = sched + 4;
+  if (k.charvars)
+    HIP_TRY(launch_bs(-1, kb_persist<T, true>, (unsigned)nwg, PB, s, tab, offs, P.ngrids, k,
+                      P.segs, sched, done, PERSIST_SPIN));
+  else
+    HIP_TRY(launch_bs(-1, kb_persist<T, false>, (unsigned)nwg, PB, s, tab, offs, P.ngrids, k,
+                      P.segs, sched, done, PERSIST_SPIN));
+  return GENO_OK;
+}
+
+// one step of the batch in the given mode (GENO_BATCH_*), as launches on s
+template <typename T>
+int batch_one(int mode, const BatchPlan& P, const BEntry* tab, const int* offs, char* ws,
+              const geno::KParams& k, const Cnt& cnt, int nwg, hipStream_t s) {
+  if (mode == GENO_BATCH_PERSISTENT) return persist_step<T>(P, tab, offs, ws, k, nwg, s);
+  return batch_step<T>(P, tab, offs, k, cnt, s);
+}
+
+// the cached graph of one step for this key, captured on s if missing
+template <typename T>
+int graph_of(int mode, const BatchPlan& P, const BEntry* tab, const int* offs, char* ws,
+             const geno::KParams& k, const Cnt& cnt, int nwg, hipStream_t s,
+             hipGraphExec_t* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::vector<unsigned char> key;
+  key_put(key, mode);
+  key_put(key, (int)sizeof(T));
+  key_put(key, dev);
+  key_put(key, (const void*)ws);
+  key_put(key, P.total);
+  key_put(key, P.bs);
+  key_put(key, P.segs);
+  key_put(key, nwg);
+  key_put(key, k);
+  key_put(key, (const void*)cnt.p);
+  key_put(key, cnt.cap);
+  key.insert(key.end(), reinterpret_cast<const unsigned char*>(P.offs.data()),
+             reinterpret_cast<const unsigned char*>(P.offs.data() + P.offs.size()));
+  std::lock_guard<std::mutex> lock(g_graphs_mu);
+  for (auto& e : g_graphs)
+    if (e.key == key) {
+      e.used = ++g_graph_clock;
+      *out = e.exec;
+      return GENO_OK;
+    }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int rc = GENO_OK;
+  g_tim_suspend = 1;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = batch_one<T>(mode, P, tab, offs, ws, k, cnt, nwg, s);
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (rc == GENO_OK && e2 != hipSuccess)
+      rc = fail(GENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    if (rc == GENO_OK) {
+      e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) rc = fail(GENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    }
+  } else {
+    rc = fail(GENO_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  g_tim_suspend = 0;
+  if (rc != GENO_OK) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (g_graphs.size() >= GRAPH_CACHE) {
+    auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+    // a replaced graph may still be queued on some stream: wait for the device
+    HIP_TRY(hipDeviceSynchronize());
+    (void)hipGraphExecDestroy(lru->exec);
+    (void)hipGraphDestroy(lru->graph);
+    g_graphs.erase(lru);
+  }
+  GraphEntry ent;
+  ent.key = std::move(key);
+  ent.graph = graph;
+  ent.exec = exec;
+  ent.used = ++g_graph_clock;
+  g_graphs.push_back(std::move(ent));
+  ++g_graph_builds;
+  *out = exec;
+  return GENO_OK;
+}
+
 // nsteps steps of a planned, bound batch whose table is in ws
 template <typename T>
-int batch_run(const BatchPlan& P, char* ws, const geno_grid* g0, int nsteps, int use_graph,
+int batch_run(const BatchPlan& P, char* ws, const geno_grid* g0, int nsteps, int mode,
               float* step_ms, const Cnt& cnt, hipStream_t s) {
   const BEntry* tab = reinterpret_cast<const BEntry*>(ws + P.tab_off);
   const int* offs = reinterpret_cast<const int*>(ws + P.offs_off);
   const geno::KParams k = kparams(g0);
-  HIP_TRY(go_init<T>(P, tab, offs, k.gamma, s));
+  if (mode == GENO_BATCH_PERSISTENT)
+    HIP_TRY(launch_bs(GENO_K_INIT, kb_init<T, PB>, P.nb[BK_INIT], PB, s, tab, offs, P.ngrids,
+                      k.gamma));
+  else
+    HIP_TRY(go_init<T>(P, tab, offs, k.gamma, s));
+  int nwg = 0;
+  if (mode == GENO_BATCH_PERSISTENT) {
+    int rc0 = persist_wgs<T>(P, k.charvars != 0, &nwg);
+    if (rc0) return rc0;
+    unsigned int* sched = reinterpret_cast<unsigned int*>(ws + P.sched_off);
+    const int n = PSEG * P.ngrids;
+    HIP_TRY(launch_bs(-1, kb_sched_clear, (unsigned)std::min(1024, n / PB + 1), PB, s, sched,
+                      sched + 4, n));
+  }
   std::vector<hipEvent_t> ev;
   if (step_ms && nsteps > 0) {
     ev.assign(nsteps + 1, nullptr);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   }
   int rc = GENO_OK;
-  hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (use_graph && nsteps > 0) {
-    g_tim_suspend = 1;
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      rc = batch_step<T>(P, tab, offs, k, cnt, s);
-      hipError_t e2 = hipStreamEndCapture(s, &graph);
-      if (rc == GENO_OK && e2 != hipSuccess)
-        rc = fail(GENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
-      if (rc == GENO_OK) {
-        e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e2 != hipSuccess) rc = fail(GENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
-      }
-    } else {
-      rc = fail(GENO_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
-    }
-    g_tim_suspend = 0;
-  }
+  if (mode != GENO_BATCH_EAGER && nsteps > 0)
+    rc = graph_of<T>(mode, P, tab, offs, ws, k, cnt, nwg, s, &exec);
   for (int n = 0; rc == GENO_OK && n < nsteps; ++n) {
     if (!ev.empty() && n == 0) {
       hipError_t e = hipEventRecord(ev[0], s);
@@ -2298,16 +2583,24 @@ int batch_run(const BatchPlan& P, char* ws, const geno_grid* g0, int nsteps, int
       hipError_t e = hipGraphLaunch(exec, s);
       if (e != hipSuccess) rc = fail(GENO_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
     } else if (rc == GENO_OK) {
-      rc = batch_step<T>(P, tab, offs, k, cnt, s);
+      rc = batch_one<T>(mode, P, tab, offs, ws, k, cnt, nwg, s);
     }
     if (rc == GENO_OK && !ev.empty()) {
       hipError_t e = hipEventRecord(ev[n + 1], s);
       if (e != hipSuccess) rc = fail(GENO_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
     }
   }
-  if (exec || !ev.empty()) {
+  {
     hipError_t e = hipStreamSynchronize(s);
     if (rc == GENO_OK && e != hipSuccess) rc = fail(GENO_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  if (rc == GENO_OK && mode == GENO_BATCH_PERSISTENT) {
+    unsigned int err = 0;
+    hipError_t e = hipMemcpy(&err, ws + P.sched_off + 2 * sizeof(unsigned int), sizeof err,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = fail(GENO_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+    else if (err)
+      rc = fail(GENO_EHIP, "persistent batched step: a dependency wait exceeded its bound");
   }
   if (rc == GENO_OK && !ev.empty())
     for (int n = 0; n < nsteps; ++n) {
@@ -2318,14 +2611,12 @@ int batch_run(const BatchPlan& P, char* ws, const geno_grid* g0, int nsteps, int
       }
     }
   for (auto& e : ev) (void)hipEventDestroy(e);
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
   return rc;
 }
 
 // plan, bind and upload the batch table (the call waits for the copy)
 int prepare_batch(int ngrids, const geno_grid* grids, void* const* W, void* const* dW, void* ws,
-                  const geno_tuning* tune, BatchPlan* P, hipStream_t s) {
+                  const geno_tuning* tune, BatchPlan* P, hipStream_t s, bool persistent = false) {
   int rc = check_batch(ngrids, grids);
   if (rc) return rc;
   if (!W || !dW || !ws) return fail(GENO_EINVAL, "null pointer");
@@ -2334,6 +2625,8 @@ int prepare_batch(int ngrids, const geno_grid* grids, void* const* W, void* cons
   geno_tuning t;
   rc = tuning_of(tune, &t);
   if (rc) return rc;
+  // the persistent step runs every phase in its one-wave work-groups
+  if (persistent) t.block_normal = t.block_faces = t.block_slow = t.block_update = PB;
   rc = plan_batch(ngrids, grids, t, P);
   if (rc) return rc;
   bind_batch(P, (char*)ws, W, dW, grids);
@@ -2407,6 +2700,11 @@ int scratch_of_current(void** out) {
 extern "C" {
 
 int geno_abi_version(void) { return GENO_ABI_VERSION; }
+
+long long geno_batched_graphs_built(void) {
+  std::lock_guard<std::mutex> lock(g_graphs_mu);
+  return g_graph_builds;
+}
 
 int geno_timing_enable(int max_launches) {
   for (int i = 0; i < 2 * g_tim.cap; ++i) (void)hipEventDestroy(g_tim.ev[i]);
@@ -2737,14 +3035,23 @@ int gks_step_batched(int ngrids, const geno_grid* grids, void* const* W, void* c
                      int nsteps, const geno_tuning* tune, int use_graph, float* step_ms,
                      geno_stats* stats, void* stream) {
   if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
+  if (use_graph != GENO_BATCH_EAGER && use_graph != GENO_BATCH_GRAPH &&
+      use_graph != GENO_BATCH_PERSISTENT)
+    return fail(GENO_EINVAL, "unknown batched mode %d", use_graph);
+  // The persistent step is switched off: its launches did not finish on the
+  // device (before and after the one-wave work-groups and relaxed polling),
+  // and the cause is not established.
+  if (use_graph == GENO_BATCH_PERSISTENT)
+    return fail(GENO_EINVAL, "the persistent batched mode is not available in this build");
   hipStream_t s = (hipStream_t)stream;
   if (use_graph && s == nullptr)
     return fail(GENO_EINVAL, "graph mode needs a stream other than the NULL stream");
   BatchPlan P;
-  int rc = prepare_batch(ngrids, grids, W, dW, ws, tune, &P, s);
+  int rc = prepare_batch(ngrids, grids, W, dW, ws, tune, &P, s,
+                         use_graph == GENO_BATCH_PERSISTENT);
   if (rc) return rc;
   Cnt cnt{nullptr, 0};
-  if (g_cnt.on) {
+  if (g_cnt.on && use_graph != GENO_BATCH_PERSISTENT) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     int cap = 1;

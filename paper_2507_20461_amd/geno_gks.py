@@ -60,7 +60,7 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_kernel_name", "geno_tuning_default", "gks_batched_workspace_bytes", "gks_step_batched",
            "geno_autotune_batched", "geno_harvest", "geno_mlp_train_workspace_bytes", "geno_mlp_grad",
            "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob",
-           "geno_conserved_totals", "geno_linearity")
+           "geno_conserved_totals", "geno_linearity", "geno_batched_graphs_built")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d",
            "gate", "normal_xy")
 WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard", "gated")
@@ -127,6 +127,8 @@ def lib():
         L.geno_gate_prob.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, vp, vp]
         L.geno_conserved_totals.argtypes = [ctypes.POINTER(geno_grid), vp, vp, vp]
         L.geno_linearity.argtypes = [ctypes.POINTER(geno_grid), vp, vp, i, vp, d, vp, vp]
+        L.geno_batched_graphs_built.argtypes = []
+        L.geno_batched_graphs_built.restype = ctypes.c_longlong
         for name in ("geno_harvest", "geno_mlp_grad", "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load",
                      "geno_mlp_infer", "geno_gate_prob", "geno_conserved_totals", "geno_linearity"):
             getattr(L, name).restype = i
@@ -396,6 +398,14 @@ def default_tuning():
     return t
 
 
+BATCH_EAGER, BATCH_GRAPH, BATCH_PERSISTENT = 0, 1, 2
+
+
+def batched_graphs_built():
+    """Batched-step graphs instantiated by this process so far."""
+    return int(lib().geno_batched_graphs_built())
+
+
 class Batch:
     """Independent 2-D grids advanced together by gks_step_batched. Grids may
     differ in size and boundary conditions; all other parameters must match."""
@@ -422,17 +432,21 @@ class Batch:
         pd = (ctypes.c_void_p * self.n)(*[d.data_ptr() for d in dWs])
         return pw, pd
 
-    def step(self, Ws, dWs, ws, nsteps, tuning=None, graph=True, step_times=False, stats=False, stream=None):
+    def step(self, Ws, dWs, ws, nsteps, tuning=None, graph=True, step_times=False, stats=False, stream=None,
+             mode=None):
         """nsteps steps of every grid in place; returns (step_ms array or None, geno_stats or None).
-        Graph mode runs on a side stream (the NULL stream cannot be captured)."""
+        mode: BATCH_EAGER, BATCH_GRAPH or BATCH_PERSISTENT (default: BATCH_GRAPH if graph else
+        BATCH_EAGER). The graph modes run on a side stream (the NULL stream cannot be captured)."""
+        if mode is None:
+            mode = BATCH_GRAPH if graph else BATCH_EAGER
         pw, pd = self._ptrs(Ws, dWs, ws)
         if stream is None:
-            stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+            stream = torch.cuda.Stream() if mode != BATCH_EAGER else torch.cuda.current_stream()
         stream.wait_stream(torch.cuda.current_stream())
         ms = (ctypes.c_float * max(int(nsteps), 1))() if step_times else None
         st = geno_stats() if stats else None
         _check(lib().gks_step_batched(self.n, self.garr, pw, pd, _ptr(ws), int(nsteps),
-                                      ctypes.byref(tuning) if tuning is not None else None, 1 if graph else 0,
+                                      ctypes.byref(tuning) if tuning is not None else None, int(mode),
                                       ms, ctypes.byref(st) if st is not None else None,
                                       ctypes.c_void_p(stream.cuda_stream)))
         torch.cuda.current_stream().wait_stream(stream)

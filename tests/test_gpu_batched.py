@@ -1,6 +1,7 @@
 """The batched form (gks_step_batched) through the C ABI: identical results to
 gks_step on each grid alone, in eager and graph mode, for every work-group
-shape, and a working autotuner.
+shape, graphs kept across calls, and a working autotuner. (The persistent
+mode is switched off; its tests are kept, skipped.)
 
 The batched launches run the same per-cell arithmetic as the single-grid
 launches (only the mapping of work-groups to grids differs, and the CFL
@@ -79,11 +80,11 @@ def test_batched_equals_single_grid(G, mixed, char):
     ref = _single(G, grids, data, 4)
     B = G.Batch(grids)
     ws = B.workspace()
-    for graph in (False, True):
+    for mode in (G.BATCH_EAGER, G.BATCH_GRAPH):
         Ws, dWs = _upload(grids, data)
-        _, st = B.step(Ws, dWs, ws, 4, graph=graph, stats=True)
+        _say("batched (%s, mode %d) vs single grids" % ("mixed" if mixed else "fp64", mode))
+        _, st = B.step(Ws, dWs, ws, 4, mode=mode, stats=True)
         assert st.nonfinite == 0
-        _say("batched (%s, graph=%s) vs single grids" % ("mixed" if mixed else "fp64", graph))
         assert _same(grids, Ws, dWs, ref)
 
 
@@ -104,6 +105,87 @@ def test_graph_replays_match_eager(G):
         ms, _ = B.step(Ws, dWs, ws, n, graph=True, step_times=True)
         assert len(ms) == n and np.all(ms > 0)
         assert _same(grids, Ws, dWs, ref), n
+
+
+PERSISTENT_OFF = ("the persistent batched launch did not finish on the device in its test run and "
+                  "in the run after a fix; the mode is switched off (GENO_EINVAL) until a cause is shown")
+
+
+def test_persistent_mode_is_refused(G):
+    grids, data = _make(G, G.F64)
+    B = G.Batch(grids)
+    Ws, dWs = _upload(grids, data)
+    before = [W.clone() for W in Ws]
+    with pytest.raises(G.GenoError):
+        B.step(Ws, dWs, B.workspace(), 1, mode=G.BATCH_PERSISTENT)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(Ws, before))
+
+
+def test_graph_is_kept_across_calls(G):
+    # the calls after the first (same batch, workspace and constants) replay
+    # the graph the first one captured; each still equals the eager steps
+    grids, data = _make(G, G.MIXED)
+    B = G.Batch(grids)
+    ws = B.workspace()
+    built = None
+    for n in (2, 1, 3):
+        Ws, dWs = _upload(grids, data)
+        B.step(Ws, dWs, ws, n, mode=G.BATCH_EAGER)
+        ref = [(g.interior(W), g.interior(dW)) for g, W, dW in zip(grids, Ws, dWs)]
+        Ws, dWs = _upload(grids, data)
+        B.step(Ws, dWs, ws, n, mode=G.BATCH_GRAPH)
+        assert _same(grids, Ws, dWs, ref), n
+        if built is None:
+            built = G.batched_graphs_built()
+        else:
+            assert G.batched_graphs_built() == built, n
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_replays_match_eager_and_reuse_one_graph(G):
+    # the persistent step's graph: every replay count 1..4 equals as many
+    # eager steps, with eager work of the program between the calls, and the
+    # calls after the first reuse the graph kept by the first
+    grids, data = _make(G, G.F64)
+    B = G.Batch(grids)
+    ws = B.workspace()
+    scratch = torch.randn(1 << 20, device="cuda")
+    built = None
+    for n in range(1, 5):
+        _say("persistent replays", n)
+        Ws, dWs = _upload(grids, data)
+        B.step(Ws, dWs, ws, n, mode=G.BATCH_EAGER)
+        ref = [(g.interior(W), g.interior(dW)) for g, W, dW in zip(grids, Ws, dWs)]
+        scratch.mul_(1.0001).add_(0.5)
+        torch.cuda.synchronize()
+        Ws, dWs = _upload(grids, data)
+        ms, _ = B.step(Ws, dWs, ws, n, mode=G.BATCH_PERSISTENT, step_times=True)
+        assert len(ms) == n and np.all(ms > 0)
+        assert _same(grids, Ws, dWs, ref), n
+        if built is None:
+            built = G.batched_graphs_built()
+        else:
+            assert G.batched_graphs_built() == built, n
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_many_small_grids(G):
+    # 40 grids of 8..40 cells a side (many work items per phase, grids
+    # finishing their phases at different times) equal gks_step per grid
+    rng = np.random.default_rng(11)
+    grids, data = [], []
+    for i in range(40):
+        nx, ny = (int(x) for x in rng.integers(8, 41, size=2))
+        W, dW, _ = inputs.quadrants_2d(nx, ny, 100 + i)
+        grids.append(G.Grid(2, nx, ny, bc=int(i % 2)))
+        data.append((W, dW))
+    ref = _single(G, grids, data, 3)
+    B = G.Batch(grids)
+    Ws, dWs = _upload(grids, data)
+    _say("persistent, 40 small grids")
+    B.step(Ws, dWs, B.workspace(), 3, mode=G.BATCH_PERSISTENT)
+    assert _same(grids, Ws, dWs, ref)
 
 
 def test_every_work_group_shape_gives_the_same_result(G):
