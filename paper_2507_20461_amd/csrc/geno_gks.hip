@@ -850,14 +850,16 @@ __device__ __forceinline__ void faces_body(const Geo& g, const geno::KParams& k,
   if (MODE == 1 && cnt.p) block_count(cnt, DIR == 0 ? GENO_K_FACES_X : GENO_K_FACES_Y, wc);
 }
 
-template <int DIR, int MODE, typename T>
-__global__ void __launch_bounds__(BLOCK) k_faces2d(Geo g, geno::KParams k,
+// WF: stage 1 (F and the interface values wanted) or stage 2 (dF/dt and
+// W_tt only), a template parameter so that each stage's kernel carries only
+// its own outputs' arithmetic and registers
+template <int DIR, int MODE, typename T, bool WF>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WF ? 1 : 4))) k_faces2d(Geo g, geno::KParams k,
                                                    const double* __restrict__ W,
                                                    const T* __restrict__ fr,
-                                                   T* __restrict__ out, Ctrl* ctrl,
-                                                   int want_F, Cnt cnt,
+                                                   T* __restrict__ out, Ctrl* ctrl, Cnt cnt,
                                                    unsigned int* __restrict__ queue) {
-  faces_body<DIR, MODE, T>(g, k, W, fr, out, ctrl, want_F, cnt, queue, xcd_block());
+  faces_body<DIR, MODE, T>(g, k, W, fr, out, ctrl, WF ? 1 : 0, cnt, queue, xcd_block());
 }
 
 // The normal step of both directions in one launch: work-groups [0, nbx)
@@ -914,17 +916,16 @@ __device__ __forceinline__ void slow_body(const Geo& g, const geno::KParams& k,
   if (cnt.p) block_count(cnt, GENO_K_SLOW, wc);
 }
 
-template <typename T>
+template <typename T, bool WF>
 __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
                                                   const double* __restrict__ W,
                                                   const T* __restrict__ frx,
                                                   const T* __restrict__ fry,
                                                   T* __restrict__ outx, T* __restrict__ outy,
-                                                  Ctrl* ctrl,
-                                                  int want_F, Cnt cnt,
+                                                  Ctrl* ctrl, Cnt cnt,
                                                   const unsigned int* __restrict__ qx,
                                                   const unsigned int* __restrict__ qy) {
-  slow_body<T>(g, k, W, frx, fry, outx, outy, ctrl, want_F, cnt, qx, qy, (int)blockIdx.x,
+  slow_body<T>(g, k, W, frx, fry, outx, outy, ctrl, WF ? 1 : 0, cnt, qx, qy, (int)blockIdx.x,
                (int)gridDim.x);
 }
 
@@ -2069,12 +2070,21 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
     else
       HIP_TRY(launch(GENO_K_NORMAL_XY, k_normal2d_xy<T, false>, nnx + nny, s, geo, k, Win, dWin,
                      B.fr[0], B.fr[1], B.ctrl, part, npart, dt_out, step, cnt, gx, gy, (int)nnx));
-    HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T>, nblocks(2 * faces_of(g, 0)), s, geo, k, Win,
-                   B.fr[0], B.fl[0], B.ctrl, want_F, cnt, B.queue[0]));
-    HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T>, nblocks(2 * faces_of(g, 1)), s, geo, k, Win,
-                   B.fr[1], B.fl[1], B.ctrl, want_F, cnt, B.queue[1]));
-    HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T>, slow_blocks(g), s, geo, k, Win, B.fr[0], B.fr[1],
-                   B.fl[0], B.fl[1], B.ctrl, want_F, cnt, B.queue[0], B.queue[1]));
+    if (want_F) {
+      HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T, true>, nblocks(2 * faces_of(g, 0)), s, geo,
+                     k, Win, B.fr[0], B.fl[0], B.ctrl, cnt, B.queue[0]));
+      HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T, true>, nblocks(2 * faces_of(g, 1)), s, geo,
+                     k, Win, B.fr[1], B.fl[1], B.ctrl, cnt, B.queue[1]));
+      HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, true>, slow_blocks(g), s, geo, k, Win, B.fr[0],
+                     B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
+    } else {
+      HIP_TRY(launch(GENO_K_FACES_X, k_faces2d<0, 1, T, false>, nblocks(2 * faces_of(g, 0)), s,
+                     geo, k, Win, B.fr[0], B.fl[0], B.ctrl, cnt, B.queue[0]));
+      HIP_TRY(launch(GENO_K_FACES_Y, k_faces2d<1, 1, T, false>, nblocks(2 * faces_of(g, 1)), s,
+                     geo, k, Win, B.fr[1], B.fl[1], B.ctrl, cnt, B.queue[1]));
+      HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, false>, slow_blocks(g), s, geo, k, Win, B.fr[0],
+                     B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
+    }
   } else {
     if (part)
       HIP_TRY(launch(-1, k_dt1d, 1, s, B.part, npart, B.ctrl, k.cfl, k.dt_fixed, dt_out, step));
@@ -2120,16 +2130,16 @@ int reconstruct_t(const geno_grid* g, double* W, T* dW, int dir, T* face_state, 
                    nblocks(normal_threads(g, 0)), s, geo, k, (const double*)W, (const T*)dW,
                    B.fr[0], chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
                    none, (const unsigned char*)nullptr));
-    HIP_TRY(launch(-1, k_faces2d<0, 0, T>, nblocks(2 * faces_of(g, 0)), s, geo, k,
-                   (const double*)W, (const T*)B.fr[0], face_state, (Ctrl*)nullptr, 0, none,
+    HIP_TRY(launch(-1, k_faces2d<0, 0, T, true>, nblocks(2 * faces_of(g, 0)), s, geo, k,
+                   (const double*)W, (const T*)B.fr[0], face_state, (Ctrl*)nullptr, none,
                    (unsigned int*)nullptr));
   } else {
     HIP_TRY(launch(-1, k.charvars ? k_normal2d<1, T, true> : k_normal2d<1, T, false>,
                    nblocks(normal_threads(g, 1)), s, geo, k, (const double*)W, (const T*)dW,
                    B.fr[1], chi, (Ctrl*)nullptr, (const double*)nullptr, 0, (double*)nullptr, 0,
                    none, (const unsigned char*)nullptr));
-    HIP_TRY(launch(-1, k_faces2d<1, 0, T>, nblocks(2 * faces_of(g, 1)), s, geo, k,
-                   (const double*)W, (const T*)B.fr[1], face_state, (Ctrl*)nullptr, 0, none,
+    HIP_TRY(launch(-1, k_faces2d<1, 0, T, true>, nblocks(2 * faces_of(g, 1)), s, geo, k,
+                   (const double*)W, (const T*)B.fr[1], face_state, (Ctrl*)nullptr, none,
                    (unsigned int*)nullptr));
   }
   return GENO_OK;
