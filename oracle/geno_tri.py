@@ -180,13 +180,27 @@ def edge_points(tri):
     return out
 
 
-def reconstruct(mesh, W, dW, prm=None, cells=None):
+def p3_second_at(fit, x, y):
+    """h^2 times the second derivatives (d_xx, d_xy, d_yy) of p^3 at physical
+    points: [nv, npts, 3] (the second derivatives in xi, eta)."""
+    h, xc, a = fit["h"], fit["xc"], fit["a"]
+    xi, eta = (np.asarray(x) - xc[0]) / h, (np.asarray(y) - xc[1]) / h
+    out = [sum(a[:, k, None] * _mono(xi, eta, p, q, da, db) for k, (p, q) in enumerate(EXPS))
+           for da, db in ((2, 0), (1, 1), (0, 2))]
+    return np.stack(out, axis=-1)
+
+
+def reconstruct(mesh, W, dW, prm=None, cells=None, second=False):
     """GENO states of every cell (or of the listed cells) at the Gauss points
     of its edges. W [nv, ncell] cell averages, dW [2, nv, ncell] averaged
     gradients. Returns out [ncell, 3 edges, 2 points, nv, 3 (value, h d/dx,
     h d/dy)], chi [ncell, nv] and info: the indicators {ISH, IStau, ISL}
     [ncell, nv] and the two candidates of the blend, high (the cubic q^H) and
-    low (q^L), in the layout of out (rows of cells not listed stay zero)."""
+    low (q^L), in the layout of out (rows of cells not listed stay zero).
+    With second=True, info also holds "second" [ncell, 3, 2, nv, 3]: h^2 times
+    the second derivatives (d_xx, d_xy, d_yy) of the blend, chi times those
+    of the cubic (the linear candidates have none; Eq. (3) applied to the
+    second derivatives)."""
     prm = params() if prm is None else prm
     W = np.asarray(W, dtype=np.float64)
     dW = np.asarray(dW, dtype=np.float64)
@@ -195,6 +209,8 @@ def reconstruct(mesh, W, dW, prm=None, cells=None):
     chi = np.zeros((n, nv))
     info = {"ISH": np.zeros((n, nv)), "IStau": np.zeros((n, nv)), "ISL": np.zeros((n, nv)),
             "high": np.zeros((n, 3, 2, nv, 3)), "low": np.zeros((n, 3, 2, nv, 3))}
+    if second:
+        info["second"] = np.zeros((n, 3, 2, nv, 3))
     for c in (range(n) if cells is None else cells):
         fit = cell_fit(mesh, W, dW, c)
         ISH, _, IStau, ISk = indicators(fit)
@@ -222,4 +238,7 @@ def reconstruct(mesh, W, dW, prm=None, cells=None):
                       axis=-1)
         info["high"][c] = hi.transpose(1, 0, 2).reshape(3, 2, nv, 3)
         info["low"][c] = lo.transpose(1, 0, 2).reshape(3, 2, nv, 3)
+        if second:
+            s2 = x[:, None, None] * p3_second_at(fit, pts[:, 0], pts[:, 1])     # [nv, 6, 3]
+            info["second"][c] = s2.transpose(1, 0, 2).reshape(3, 2, nv, 3)
     return out, chi, info
