@@ -254,6 +254,7 @@ def characteristic_2d(G, np, torch, W, dW, n, steps):
 
 
 TRI_N = 512    # lattice squares per side of the triangle mesh (2 TRI_N^2 cells)
+TRI_STEPS = 20  # timed compact GKS steps on that mesh
 
 
 def triangles_workload(np, torch, inputs, seed, reps, cpu=True):
@@ -300,6 +301,23 @@ def triangles_workload(np, torch, inputs, seed, reps, cpu=True):
     tb, td = tri_counters()
     res["roofline"]["traffic"] = round(tb) if tb else None
     res["roofline"]["traffic_detail"] = td
+    # the compact GKS step on the same mesh (Sec. 4.3 with Eq. (1)-(2)):
+    # TRI_STEPS whole steps (dt, and per stage the reconstruction, the edge
+    # fluxes and the cell update) from the quadrant state
+    ws = tm.workspace()
+    Ws, dWs = Wd.clone(), dWd.clone()
+    T.step(tm, Ws, dWs, ws, 1, stream=stream)
+    torch.cuda.synchronize()
+    start.record(stream)
+    T.step(tm, Ws, dWs, ws, TRI_STEPS, stream=stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / TRI_STEPS
+    Wn = Ws.cpu().numpy()
+    res["step"] = {"steps": TRI_STEPS, "ms_per_step": round(ms, 4),
+                   "value": round(2.0 * n / (ms * 1e-3) / 1e6, 1), "unit": "Mcell-updates/s per stage",
+                   "physical_after_run": bool(np.isfinite(Wn).all() and Wn[0].min() > 0.0),
+                   "rho_range": [float(Wn[0].min()), float(Wn[0].max())]}
     if cpu:
         from oracle import geno_tri as O
         cells = list(range(0, n, max(1, n // 400)))[:400]

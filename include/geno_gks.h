@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GENO_ABI_VERSION 3
+#define GENO_ABI_VERSION 4
 
 /* error codes */
 #define GENO_OK 0

@@ -46,8 +46,10 @@
 extern "C" {
 #endif
 
-/* Doubles per cell of the operator table (least-squares operators of the
- * candidates, indicator matrix, scaled geometry, stencil indices). */
+/* Doubles per cell of the operator table (stencil indices, h, least-squares
+ * operators of the candidates, scaled vertices, and the geometry of the step:
+ * area, 4 area / perimeter, per edge the outward unit normal, length,
+ * neighbour, the neighbour's index of the same edge and ownership). */
 size_t geno_tri_table_doubles(void);
 
 /* Mesh layer, host only (no device access; call once per mesh): fills the
@@ -56,8 +58,9 @@ size_t geno_tri_table_doubles(void);
  * at index ((e / 2) * ncell + c) * 2 + e % 2) from the mesh arrays
  * above. The caller copies it to device memory for geno_tri_reconstruct.
  * GENO_EINVAL for ncell < 1, null pointers, a neighbour index out of range,
- * a degenerate (non counter-clockwise) triangle or a rank-deficient
- * least-squares system. */
+ * a neighbour that does not point back across the same edge (with the
+ * opposite translation), a degenerate (non counter-clockwise) triangle or a
+ * rank-deficient least-squares system. */
 int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* shift, double* ops);
 
 /* GENO reconstruction of every cell at the two Gauss points of each of its
@@ -68,10 +71,46 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
  * out (device): [point(6) = 2 e + g][quant(3)][nv][ncell], quant 0 the value,
  *   1 and 2 h d/dx and h d/dy of R (h of the cell).
  * chi (device, may be NULL): [nv][ncell] path function of each cell.
+ * sec (device, may be NULL): [point(6)][3][nv][ncell], h^2 times the second
+ *   derivatives d_xx, d_xy, d_yy of R: chi times those of p^3 (the linear
+ *   candidates have none).
  * Asynchronous on stream; allocates nothing. */
 #define GENO_TRI_MAXV 4
 int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, const double* dW,
-                         double* out, double* chi, void* stream);
+                         double* out, double* chi, double* sec, void* stream);
+
+/* Bytes of the device workspace of geno_tri_step on a mesh of ncell cells
+ * (0 for ncell < 1). */
+size_t geno_tri_workspace_bytes(int ncell);
+
+/* nsteps steps of the compact GKS on the mesh (Sec. 4.3 with Sec. 2,
+ * Eq. (1)-(2)), in place, float64, conserved variables (rho, rho u, rho v,
+ * rho E) of the 2-D Euler equations:
+ *   per stage: the reconstruction above at the edge Gauss points (values,
+ *   gradients, second derivatives); per edge, once, from its owner cell
+ *   (the smaller (cell, edge) pair of its two sides): at both Gauss points
+ *   the owner's state on the left and the neighbour's on the right, a side
+ *   with rho <= 0, p <= 0 or a non-finite value replaced by its cell average
+ *   with zero derivatives, the gas-kinetic solution of gks_flux in the frame
+ *   of the owner's outward unit normal (F, dF/dt, W(dt/2), W(dt), phi W_tt),
+ *   rotated back and averaged over the two points; per cell, Eq. (1) and the
+ *   Gauss-theorem gradients of Eq. (2) over its three edges;
+ *   the two-stage fourth-order combination of gks_step (cell averages and
+ *   the interface values of the gradient update alike);
+ *   dt = cfl min over cells of d / (|u| + c), d = 4 |Omega| / perimeter (the
+ *   inscribed circle's diameter), or p->dt_fixed if positive.
+ * ops: DEVICE copy of the table of geno_tri_build.
+ * W (device): [4][ncell]; dW (device): [2][4][ncell] (d/dx rows, then d/dy).
+ * ws (device): geno_tri_workspace_bytes(ncell) bytes.
+ * p (host): the method constants gamma, tau_c1, tau_c2, cfl, dt_fixed of a
+ *   geno_params (version GENO_ABI_VERSION, precision GENO_F64); the
+ *   reconstruction's constants are those of geno_tri_reconstruct.
+ * dt_out (device, may be NULL): nsteps doubles.
+ * stats (host, may be NULL): waits for the stream, fills the counters and
+ *   returns GENO_ENONPHYS if a non-physical cell was found after any step.
+ * GENO_EINVAL for ncell < 1, null pointers, nsteps < 0 or bad constants. */
+int geno_tri_step(int ncell, const void* ops, double* W, double* dW, void* ws, int nsteps,
+                  const geno_params* p, double* dt_out, geno_stats* stats, void* stream);
 
 /* Floating-point operations per cell and variable of geno_tri_reconstruct
  * (as the kernel executes them; add, sub, mul, div, sqrt, tanh count 1). */

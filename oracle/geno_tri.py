@@ -200,7 +200,7 @@ def reconstruct(mesh, W, dW, prm=None, cells=None, second=False):
     With second=True, info also holds "second" [ncell, 3, 2, nv, 3]: h^2 times
     the second derivatives (d_xx, d_xy, d_yy) of the blend, chi times those
     of the cubic (the linear candidates have none; Eq. (3) applied to the
-    second derivatives)."""
+    second derivatives), and "second_high", those of the cubic."""
     prm = params() if prm is None else prm
     W = np.asarray(W, dtype=np.float64)
     dW = np.asarray(dW, dtype=np.float64)
@@ -211,6 +211,7 @@ def reconstruct(mesh, W, dW, prm=None, cells=None, second=False):
             "high": np.zeros((n, 3, 2, nv, 3)), "low": np.zeros((n, 3, 2, nv, 3))}
     if second:
         info["second"] = np.zeros((n, 3, 2, nv, 3))
+        info["second_high"] = np.zeros((n, 3, 2, nv, 3))
     for c in (range(n) if cells is None else cells):
         fit = cell_fit(mesh, W, dW, c)
         ISH, _, IStau, ISk = indicators(fit)
@@ -239,6 +240,8 @@ def reconstruct(mesh, W, dW, prm=None, cells=None, second=False):
         info["high"][c] = hi.transpose(1, 0, 2).reshape(3, 2, nv, 3)
         info["low"][c] = lo.transpose(1, 0, 2).reshape(3, 2, nv, 3)
         if second:
-            s2 = x[:, None, None] * p3_second_at(fit, pts[:, 0], pts[:, 1])     # [nv, 6, 3]
+            s3 = p3_second_at(fit, pts[:, 0], pts[:, 1])                       # [nv, 6, 3]
+            s2 = x[:, None, None] * s3
             info["second"][c] = s2.transpose(1, 0, 2).reshape(3, 2, nv, 3)
+            info["second_high"][c] = s3.transpose(1, 0, 2).reshape(3, 2, nv, 3)
     return out, chi, info

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "geno_tri.h"
+#include "gks_device.hpp"
 
 namespace geno_err {
 int fail(int code, const char* fmt, ...);
@@ -51,8 +52,15 @@ constexpr int NAP = NA + 1;               // operator column padded to pairs
 constexpr int E_M = 10;                   // least-squares operator [ND][NAP] (column i of P, padded)
 constexpr int E_L = E_M + ND * NAP;       // linear candidates [3][2][3]
 constexpr int E_V = E_L + 18;             // scaled vertices (xi, eta) x 3
-constexpr int E_N = E_V + 6;
-static_assert(E_M % 2 == 0 && E_L % 2 == 0 && E_V % 2 == 0 && E_N % 2 == 0, "table regions start on pairs");
+// geometry of the flux and update: area, d = 4 area / perimeter, then per
+// edge e (vertex e to e+1): outward unit normal (2), length, neighbour, the
+// neighbour's index of the same edge, 1 if this cell owns the edge (the
+// smaller (cell, edge) pair of its two sides) else 0
+constexpr int E_G = E_V + 6;
+constexpr int E_GE = E_G + 2;             // per-edge block of 6
+constexpr int E_N = E_GE + 18;
+static_assert(E_M % 2 == 0 && E_L % 2 == 0 && E_V % 2 == 0 && E_G % 2 == 0 && E_N % 2 == 0,
+              "table regions start on pairs");
 
 // host index of entry e of cell c in a table of n cells
 inline size_t tab_index(int e, size_t c, size_t n) { return ((size_t)(e >> 1) * n + c) * 2 + (e & 1); }
@@ -151,7 +159,7 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
                                              const double* __restrict__ W,
                                              const double* __restrict__ dW,
                                              double* __restrict__ out, double* __restrict__ chi,
-                                             TriK k) {
+                                             double* __restrict__ sec, TriK k) {
   const int v = (int)(threadIdx.x >> 6);
   const int c = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
   if (c >= n) return;
@@ -293,8 +301,329 @@ __global__ void __launch_bounds__(256) k_tri(int n, const double* __restrict__ o
       out[((pt * 3 + 0) * NV + v) * sn + c] = x * p3 + xm * pL;
       out[((pt * 3 + 1) * NV + v) * sn + c] = x * p3x + xm * gLx;
       out[((pt * 3 + 2) * NV + v) * sn + c] = x * p3y + xm * gLy;
+      if (sec) {
+        // h^2 d2/dx2, d2/dxdy, d2/dy2 of the blend: chi times the cubic's
+        // (in the scaled coordinates; the linear candidates have none)
+        sec[((pt * 3 + 0) * NV + v) * sn + c] = x * (2.0 * av[2] + 6.0 * av[5] * X + 2.0 * av[6] * Y);
+        sec[((pt * 3 + 1) * NV + v) * sn + c] = x * (av[3] + 2.0 * av[6] * X + 2.0 * av[7] * Y);
+        sec[((pt * 3 + 2) * NV + v) * sn + c] = x * (2.0 * av[4] + 2.0 * av[7] * X + 6.0 * av[8] * Y);
+      }
     }
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// Compact GKS step on the mesh (Sec. 4.3 with Eq. (1)-(2)), conserved
+// variables (rho, rho u, rho v, rho E), [4][n] averages and [2][4][n]
+// averaged gradients. Per stage: the reconstruction above (values, gradients
+// and second derivatives at the edge Gauss points), the edge kernel (one
+// thread per owned edge: both Gauss points' gas-kinetic solutions in the
+// frame of the owner's outward normal, rotated back and averaged) and the
+// cell kernel (Eq. (1) and the Gauss-theorem gradients of Eq. (2) over the
+// three edges, the two-stage fourth-order combination).
+// ---------------------------------------------------------------------------
+struct TriCtrl {
+  double dt;
+  unsigned long long guard;
+  unsigned long long nonfinite;
+};
+
+// entry e of cell c of the table
+__device__ __forceinline__ double tab_at(const double* __restrict__ ops, int e, int c, size_t n) {
+  return ops[((size_t)(e >> 1) * n + (size_t)c) * 2 + (e & 1)];
+}
+
+// momentum components of a per-variable vector into the frame (n, t),
+// t = (-n_y, n_x), and back
+__device__ __forceinline__ void to_frame(double* q, double nx, double ny) {
+  const double a = q[1] * nx + q[2] * ny, b = -q[1] * ny + q[2] * nx;
+  q[1] = a;
+  q[2] = b;
+}
+__device__ __forceinline__ void from_frame(double* q, double nx, double ny) {
+  const double a = q[1] * nx - q[2] * ny, b = q[1] * ny + q[2] * nx;
+  q[1] = a;
+  q[2] = b;
+}
+
+// local dt bound of a cell: d / (|u| + c)
+__device__ __forceinline__ double tri_tmin(const double* w, double d, double gamma) {
+  const double rho = w[0], u = w[1] / rho, v = w[2] / rho;
+  const double p = (gamma - 1.0) * (w[3] - 0.5 * rho * (u * u + v * v));
+  const double t = d / (sqrt(u * u + v * v) + sqrt(gamma * p / rho));
+  return t > 0.0 ? t : 0.0;
+}
+
+__device__ __forceinline__ void tri_block_min(double t, double* part) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t = fmin(t, __shfl_xor(t, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+// start of a call: cleared counters and the CFL partials of the state
+__global__ void __launch_bounds__(256) k_tri_init(int n, const double* __restrict__ ops,
+                                                  const double* __restrict__ W,
+                                                  double* __restrict__ part, TriCtrl* ctrl,
+                                                  double gamma) {
+  const int c = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (c == 0) {
+    ctrl->guard = 0;
+    ctrl->nonfinite = 0;
+  }
+  double t = INFINITY;
+  if (c < n) {
+    double w[4];
+    for (int v = 0; v < 4; ++v) w[v] = W[(size_t)v * n + c];
+    t = tri_tmin(w, tab_at(ops, E_G + 1, c, (size_t)n), gamma);
+  }
+  tri_block_min(t, part);
+}
+
+// dt of the step (one work-group): CFL times the minimum partial, or the
+// fixed step
+__global__ void __launch_bounds__(256) k_tri_dt(const double* __restrict__ part, int npart,
+                                                TriCtrl* ctrl, double cfl, double dt_fixed,
+                                                double* dt_out, int step) {
+  double m = INFINITY;
+  for (int q = (int)threadIdx.x; q < npart; q += 256) m = fmin(m, part[q]);
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * m;
+    ctrl->dt = dt;
+    if (dt_out) dt_out[step] = dt;
+  }
+}
+
+// One thread per (edge e, cell c), edge-major; threads of edges the cell does
+// not own return. Output [kind][var][edge][cell] at the owner's slot, xy
+// frame, Gauss-averaged: stage 1 F, dF/dt, W(dt/2) + dt^2/8 phi W_tt,
+// W(dt) + dt^2/6 phi W_tt; stage 2 kinds 1 (dF/dt) and 2 (phi W_tt).
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_tri_edges(int n, const double* __restrict__ ops,
+                                                   const double* __restrict__ W,
+                                                   const double* __restrict__ rec,
+                                                   const double* __restrict__ sec,
+                                                   double* __restrict__ ebuf, TriCtrl* ctrl,
+                                                   geno::KParams k) {
+  const int t = (int)(blockIdx.x * 256 + threadIdx.x);
+  if (t >= 3 * n) return;
+  const int e = t / n, c = t - e * n;
+  const size_t sn = (size_t)n;
+  const int g0 = E_GE + 6 * e;
+  if (tab_at(ops, g0 + 5, c, sn) == 0.0) return;
+  const double nx = tab_at(ops, g0, c, sn), ny = tab_at(ops, g0 + 1, c, sn);
+  const double tx = -ny, ty = nx;
+  const int m = (int)tab_at(ops, g0 + 3, c, sn), f = (int)tab_at(ops, g0 + 4, c, sn);
+  const double hs[2] = {tab_at(ops, E_H, c, sn), tab_at(ops, E_H, m, sn)};
+  const int cells[2] = {c, m};
+  const double dt = ctrl->dt;
+  double acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[q][v] = 0.0;
+  unsigned int nguard = 0;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    double S[2][4], Dn[2][4], Dt[2][4], Snn[2][4], Snt[2][4], Stt[2][4];
+    bool ok[2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int cell = cells[sd];
+      const int pt = sd == 0 ? 2 * e + g : 2 * f + (1 - g);
+      const double ih = 1.0 / hs[sd], ih2 = ih * ih;
+      double gx[4], gy[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        S[sd][v] = rec[((size_t)(pt * 3 + 0) * 4 + v) * sn + cell];
+        gx[v] = rec[((size_t)(pt * 3 + 1) * 4 + v) * sn + cell] * ih;
+        gy[v] = rec[((size_t)(pt * 3 + 2) * 4 + v) * sn + cell] * ih;
+        const double xx = sec[((size_t)(pt * 3 + 0) * 4 + v) * sn + cell] * ih2;
+        const double xy = sec[((size_t)(pt * 3 + 1) * 4 + v) * sn + cell] * ih2;
+        const double yy = sec[((size_t)(pt * 3 + 2) * 4 + v) * sn + cell] * ih2;
+        Snn[sd][v] = xx * nx * nx + 2.0 * xy * nx * ny + yy * ny * ny;
+        Snt[sd][v] = xx * nx * tx + xy * (nx * ty + ny * tx) + yy * ny * ty;
+        Stt[sd][v] = xx * tx * tx + 2.0 * xy * tx * ty + yy * ty * ty;
+      }
+      ok[sd] = geno::admissible<4, double>(S[sd], k.gamma);
+      if (!ok[sd]) {
+        ++nguard;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          S[sd][v] = W[(size_t)v * sn + cell];
+          gx[v] = gy[v] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Dn[sd][v] = gx[v] * nx + gy[v] * ny;
+        Dt[sd][v] = gx[v] * tx + gy[v] * ty;
+      }
+      to_frame(S[sd], nx, ny);
+      to_frame(Dn[sd], nx, ny);
+      to_frame(Dt[sd], nx, ny);
+      to_frame(Snn[sd], nx, ny);
+      to_frame(Snt[sd], nx, ny);
+      to_frame(Stt[sd], nx, ny);
+    }
+    double mnn[4], mnt[4], mtt[4];
+    const bool both = ok[0] && ok[1];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      mnn[v] = both ? 0.5 * (Snn[0][v] + Snn[1][v]) : 0.0;
+      mnt[v] = both ? 0.5 * (Snt[0][v] + Snt[1][v]) : 0.0;
+      mtt[v] = both ? 0.5 * (Stt[0][v] + Stt[1][v]) : 0.0;
+    }
+    gks::PointOut<4, double> po;
+    gks::point_flux<4, true, double>(S[0], S[1], Dn[0], Dn[1], Dt[0], Dt[1], mnn, mnt, mtt, dt, k,
+                                     STAGE == 1, po);
+    double q0[4], q1[4], q2[4], q3[4];
+    const double c8 = dt * dt / 8.0, c6 = dt * dt / 6.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (STAGE == 1) {
+        q0[v] = po.F[v];
+        q2[v] = po.Wh[v] + c8 * po.Wtt[v];
+        q3[v] = po.Wf[v] + c6 * po.Wtt[v];
+      } else {
+        q0[v] = q3[v] = 0.0;
+        q2[v] = po.Wtt[v];
+      }
+      q1[v] = po.Ft[v];
+    }
+    from_frame(q0, nx, ny);
+    from_frame(q1, nx, ny);
+    from_frame(q2, nx, ny);
+    from_frame(q3, nx, ny);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc[0][v] += 0.5 * q0[v];
+      acc[1][v] += 0.5 * q1[v];
+      acc[2][v] += 0.5 * q2[v];
+      acc[3][v] += 0.5 * q3[v];
+    }
+  }
+  if (nguard) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (STAGE == 2 && (q == 0 || q == 3)) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ebuf[((size_t)(q * 4 + v) * 3 + e) * sn + c] = acc[q][v];
+  }
+}
+
+// One thread per cell: Eq. (1) and the Gauss-theorem gradients over the three
+// edges (an edge the cell does not own: the owner's F with a minus sign; the
+// interface values as they are, with the cell's own outward normal), then the
+// two-stage combination. Stage 2 also records non-physical cells and the CFL
+// partials of the new state.
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_tri_update(int n, const double* __restrict__ ops,
+                                                    const double* __restrict__ Win,
+                                                    double* __restrict__ Wout,
+                                                    double* __restrict__ dWout,
+                                                    double* __restrict__ R,
+                                                    double* __restrict__ RG,
+                                                    const double* __restrict__ ebuf,
+                                                    TriCtrl* ctrl, double* __restrict__ part,
+                                                    double gamma) {
+  const int c = (int)(blockIdx.x * 256 + threadIdx.x);
+  const size_t sn = (size_t)n;
+  double tmin = INFINITY;
+  if (c < n) {
+    const double dt = ctrl->dt;
+    double L[4] = {0, 0, 0, 0}, Lt[4] = {0, 0, 0, 0};
+    double Ga[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, Gb[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int g0 = E_GE + 6 * e;
+      const double nx = tab_at(ops, g0, c, sn), ny = tab_at(ops, g0 + 1, c, sn);
+      const double len = tab_at(ops, g0 + 2, c, sn);
+      const bool own = tab_at(ops, g0 + 5, c, sn) != 0.0;
+      const int sc = own ? c : (int)tab_at(ops, g0 + 3, c, sn);
+      const int se = own ? e : (int)tab_at(ops, g0 + 4, c, sn);
+      const double sg = own ? 1.0 : -1.0;
+      auto E = [&](int q, int v) { return ebuf[((size_t)(q * 4 + v) * 3 + se) * sn + sc]; };
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (STAGE == 1) L[v] -= sg * len * E(0, v);
+        Lt[v] -= sg * len * E(1, v);
+        const double wa = len * E(2, v);
+        Ga[0][v] += wa * nx;
+        Ga[1][v] += wa * ny;
+        if (STAGE == 1) {
+          const double wb = len * E(3, v);
+          Gb[0][v] += wb * nx;
+          Gb[1][v] += wb * ny;
+        }
+      }
+    }
+    const double ia = 1.0 / tab_at(ops, E_G, c, sn);
+    double w[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const size_t o = (size_t)v * sn + c;
+      if (STAGE == 1) {
+        const double l = L[v] * ia, lt = Lt[v] * ia, w0 = Win[o];
+        Wout[o] = w0 + 0.5 * dt * l + dt * dt / 8.0 * lt;
+        R[o] = w0 + dt * l + dt * dt / 6.0 * lt;
+        dWout[o] = Ga[0][v] * ia;
+        dWout[(size_t)(4 + v) * sn + c] = Ga[1][v] * ia;
+        RG[o] = Gb[0][v] * ia;
+        RG[(size_t)(4 + v) * sn + c] = Gb[1][v] * ia;
+      } else {
+        const double c3 = dt * dt / 3.0;
+        w[v] = R[o] + c3 * (Lt[v] * ia);
+        Wout[o] = w[v];
+        dWout[o] = RG[o] + c3 * (Ga[0][v] * ia);
+        dWout[(size_t)(4 + v) * sn + c] = RG[(size_t)(4 + v) * sn + c] + c3 * (Ga[1][v] * ia);
+      }
+    }
+    if (STAGE == 2) {
+      bool bad = false;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bad |= !isfinite(w[v]);
+      bad |= !(w[0] > 0.0) || !(w[0] * w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) > 0.0);
+      if (bad) atomicAdd(&ctrl->nonfinite, 1ull);
+      tmin = tri_tmin(w, tab_at(ops, E_G + 1, c, sn), gamma);
+    }
+  }
+  if (STAGE == 2) tri_block_min(tmin, part);
+}
+// workspace of geno_tri_step, in doubles: control block, CFL partials,
+// reconstruction (values and gradients, second derivatives), edge results,
+// stage state W*, grad W*, R and RG
+struct TriWs {
+  size_t ctrl, part, rec, sec, ebuf, wst, dwst, r, rg, total;
+};
+TriWs tri_ws(size_t n) {
+  TriWs L{};
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t o = off;
+    off += (doubles + 31) & ~(size_t)31;   // 256-byte aligned parts
+    return o;
+  };
+  L.ctrl = take(4);
+  L.part = take(n / 256 + 1);
+  L.rec = take(72 * n);
+  L.sec = take(72 * n);
+  L.ebuf = take(48 * n);
+  L.wst = take(4 * n);
+  L.dwst = take(8 * n);
+  L.r = take(4 * n);
+  L.rg = take(8 * n);
+  L.total = off;
+  return L;
 }
 
 }  // namespace
@@ -399,13 +728,38 @@ int geno_tri_build(int ncell, const double* xv, const int* nbr, const double* sh
       put(E_V + 2 * v, own[v][0]);
       put(E_V + 2 * v + 1, own[v][1]);
     }
+    // flux and update geometry
+    double perim = 0.0;
+    for (int e = 0; e < 3; ++e) {
+      const int w = (e + 1) % 3;
+      const double dx = vert(c, w, 0) - vert(c, e, 0), dy = vert(c, w, 1) - vert(c, e, 1);
+      const double len = std::sqrt(dx * dx + dy * dy);
+      perim += len;
+      const size_t m = (size_t)nbr[3 * c + e];
+      int f = -1;
+      for (int q = 0; q < 3; ++q) {
+        const double sx = shift[(c * 3 + e) * 2] + shift[(m * 3 + q) * 2];
+        const double sy = shift[(c * 3 + e) * 2 + 1] + shift[(m * 3 + q) * 2 + 1];
+        if ((size_t)nbr[3 * m + q] == c && std::fabs(sx) <= 1e-12 && std::fabs(sy) <= 1e-12) f = q;
+      }
+      if (f < 0) return fail(GENO_EINVAL, "cell %zu, edge %d: the neighbour does not point back", c, e);
+      const bool owner = c < m || (c == m && e < f);
+      put(E_GE + 6 * e + 0, dy / len);
+      put(E_GE + 6 * e + 1, -dx / len);
+      put(E_GE + 6 * e + 2, len);
+      put(E_GE + 6 * e + 3, (double)m);
+      put(E_GE + 6 * e + 4, (double)f);
+      put(E_GE + 6 * e + 5, owner ? 1.0 : 0.0);
+    }
+    put(E_G, area);
+    put(E_G + 1, 4.0 * area / perim);
 
   }
   return GENO_OK;
 }
 
 int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, const double* dW,
-                         double* out, double* chi, void* stream) {
+                         double* out, double* chi, double* sec, void* stream) {
   if (ncell < 1 || nv < 1 || nv > GENO_TRI_MAXV) return fail(GENO_EINVAL, "bad ncell or nv");
   if (!ops || !W || !dW || !out) return fail(GENO_EINVAL, "null pointer");
   TriK k;
@@ -417,12 +771,88 @@ int geno_tri_reconstruct(int ncell, int nv, const void* ops, const double* W, co
   hipStream_t s = (hipStream_t)stream;
   const double* T = (const double*)ops;
   switch (nv) {
-    case 1: hipLaunchKernelGGL(k_tri<1>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
-    case 2: hipLaunchKernelGGL(k_tri<2>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
-    case 3: hipLaunchKernelGGL(k_tri<3>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
-    default: hipLaunchKernelGGL(k_tri<4>, grid, block, 0, s, ncell, T, W, dW, out, chi, k); break;
+    case 1: hipLaunchKernelGGL(k_tri<1>, grid, block, 0, s, ncell, T, W, dW, out, chi, sec, k); break;
+    case 2: hipLaunchKernelGGL(k_tri<2>, grid, block, 0, s, ncell, T, W, dW, out, chi, sec, k); break;
+    case 3: hipLaunchKernelGGL(k_tri<3>, grid, block, 0, s, ncell, T, W, dW, out, chi, sec, k); break;
+    default: hipLaunchKernelGGL(k_tri<4>, grid, block, 0, s, ncell, T, W, dW, out, chi, sec, k); break;
   }
   HIP_TRY(hipGetLastError());
+  return GENO_OK;
+}
+
+size_t geno_tri_workspace_bytes(int ncell) {
+  if (ncell < 1) return 0;
+  return tri_ws((size_t)ncell).total * sizeof(double);
+}
+
+int geno_tri_step(int ncell, const void* ops, double* W, double* dW, void* ws, int nsteps,
+                  const geno_params* p, double* dt_out, geno_stats* stats, void* stream) {
+  if (ncell < 1) return fail(GENO_EINVAL, "ncell must be >= 1");
+  if (!ops || !W || !dW || !ws || !p) return fail(GENO_EINVAL, "null pointer");
+  if (nsteps < 0) return fail(GENO_EINVAL, "nsteps must be >= 0");
+  if (p->version != GENO_ABI_VERSION)
+    return fail(GENO_EVERSION, "params version %d != %d", p->version, GENO_ABI_VERSION);
+  if (p->precision != GENO_F64) return fail(GENO_EINVAL, "the triangle step runs in float64 only");
+  if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->dt_fixed >= 0.0) || !(p->tau_c1 >= 0.0) ||
+      !(p->tau_c2 >= 0.0))
+    return fail(GENO_EINVAL, "bad method parameters");
+  const size_t n = (size_t)ncell;
+  const TriWs L = tri_ws(n);
+  double* base = (double*)ws;
+  TriCtrl* ctrl = reinterpret_cast<TriCtrl*>(base + L.ctrl);
+  double* part = base + L.part;
+  double* rec = base + L.rec;
+  double* sec = base + L.sec;
+  double* ebuf = base + L.ebuf;
+  double* wst = base + L.wst;
+  double* dwst = base + L.dwst;
+  double* R = base + L.r;
+  double* RG = base + L.rg;
+  geno::KParams k{};
+  k.gamma = p->gamma;
+  k.K = (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0);
+  k.tc1 = p->tau_c1;
+  k.tc2 = p->tau_c2;
+  k.cfl = p->cfl;
+  k.dt_fixed = p->dt_fixed;
+  TriK tk;
+  tk.C = 20.0;
+  tk.inv_tanhC = 1.0 / std::tanh(20.0);
+  tk.eps = 1e-15;
+  tk.d[0] = tk.d[1] = tk.d[2] = 1.0;
+  hipStream_t s = (hipStream_t)stream;
+  const double* T = (const double*)ops;
+  const unsigned nb = (unsigned)((n + 255) / 256), npart = nb;
+  const unsigned nrec = (unsigned)((n + 63) / 64), nedge = (unsigned)((3 * n + 255) / 256);
+  hipLaunchKernelGGL(k_tri_init, dim3(nb), dim3(256), 0, s, ncell, T, W, part, ctrl, p->gamma);
+  for (int step = 0; step < nsteps; ++step) {
+    hipLaunchKernelGGL(k_tri_dt, dim3(1), dim3(256), 0, s, part, (int)npart, ctrl, p->cfl,
+                       p->dt_fixed, dt_out, step);
+    hipLaunchKernelGGL(k_tri<4>, dim3(nrec), dim3(256), 0, s, ncell, T, W, dW, rec,
+                       (double*)nullptr, sec, tk);
+    hipLaunchKernelGGL(k_tri_edges<1>, dim3(nedge), dim3(256), 0, s, ncell, T, W, rec, sec, ebuf,
+                       ctrl, k);
+    hipLaunchKernelGGL(k_tri_update<1>, dim3(nb), dim3(256), 0, s, ncell, T, W, wst, dwst, R, RG,
+                       ebuf, ctrl, part, p->gamma);
+    hipLaunchKernelGGL(k_tri<4>, dim3(nrec), dim3(256), 0, s, ncell, T, wst, dwst, rec,
+                       (double*)nullptr, sec, tk);
+    hipLaunchKernelGGL(k_tri_edges<2>, dim3(nedge), dim3(256), 0, s, ncell, T, wst, rec, sec,
+                       ebuf, ctrl, k);
+    hipLaunchKernelGGL(k_tri_update<2>, dim3(nb), dim3(256), 0, s, ncell, T, wst, W, dW, R, RG,
+                       ebuf, ctrl, part, p->gamma);
+  }
+  HIP_TRY(hipGetLastError());
+  if (stats) {
+    TriCtrl h;
+    HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stats->guard = (long long)h.guard;
+    stats->nonfinite = (long long)h.nonfinite;
+    stats->last_dt = nsteps > 0 ? h.dt : 0.0;
+    if (h.nonfinite)
+      return fail(GENO_ENONPHYS, "%llu non-physical cells (non-finite, rho <= 0 or p <= 0)",
+                  h.nonfinite);
+  }
   return GENO_OK;
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING, BC_FIXED = 0, 1, 2, 3
 F64, MIXED = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 NG = 2
 VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
 

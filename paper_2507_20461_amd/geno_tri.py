@@ -15,7 +15,8 @@ import torch
 
 from . import geno_gks as G
 
-EXPORTS = ("geno_tri_table_doubles", "geno_tri_build", "geno_tri_reconstruct", "geno_tri_op_cost")
+EXPORTS = ("geno_tri_table_doubles", "geno_tri_build", "geno_tri_reconstruct", "geno_tri_op_cost",
+           "geno_tri_workspace_bytes", "geno_tri_step")
 MAXV = 4
 _ready = False
 
@@ -29,8 +30,13 @@ def lib():
         L.geno_tri_table_doubles.argtypes = []
         L.geno_tri_build.argtypes = [i, dp, ctypes.POINTER(ctypes.c_int), dp, dp]
         L.geno_tri_build.restype = i
-        L.geno_tri_reconstruct.argtypes = [i, i, vp, vp, vp, vp, vp, vp]
+        L.geno_tri_reconstruct.argtypes = [i, i, vp, vp, vp, vp, vp, vp, vp]
         L.geno_tri_reconstruct.restype = i
+        L.geno_tri_workspace_bytes.argtypes = [i]
+        L.geno_tri_workspace_bytes.restype = ctypes.c_size_t
+        L.geno_tri_step.argtypes = [i, vp, vp, vp, vp, i, ctypes.POINTER(G.geno_params), vp,
+                                    ctypes.POINTER(G.geno_stats), vp]
+        L.geno_tri_step.restype = i
         L.geno_tri_op_cost.restype = ctypes.c_double
         L.geno_tri_op_cost.argtypes = []
         _ready = True
@@ -63,17 +69,45 @@ class TriMesh:
     def out_shape(self, nv):
         return (6, 3, nv, self.ncell)
 
+    def workspace(self, device="cuda"):
+        """Device workspace of step()."""
+        return torch.empty(lib().geno_tri_workspace_bytes(self.ncell), dtype=torch.uint8, device=device)
 
-def reconstruct(tm, W, dW, out, chi=None, stream=None):
+
+def reconstruct(tm, W, dW, out, chi=None, sec=None, stream=None):
     """W [nv, ncell], dW [2, nv, ncell] float64 on the device; out [6, 3, nv,
-    ncell]; chi [nv, ncell] or None."""
+    ncell]; chi [nv, ncell] or None; sec [6, 3, nv, ncell] (h^2 second
+    derivatives) or None."""
     nv = W.shape[0]
     G._need(W, torch.float64, nv * tm.ncell, "W")
     G._need(dW, torch.float64, 2 * nv * tm.ncell, "dW")
     G._need(out, torch.float64, 18 * nv * tm.ncell, "out")
     G._need(chi, torch.float64, nv * tm.ncell, "chi", optional=True)
+    G._need(sec, torch.float64, 18 * nv * tm.ncell, "sec", optional=True)
     G._check(lib().geno_tri_reconstruct(tm.ncell, nv, G._ptr(tm.table), G._ptr(W), G._ptr(dW), G._ptr(out),
-                                        G._ptr(chi), G._stream(stream)))
+                                        G._ptr(chi), G._ptr(sec), G._stream(stream)))
+
+
+def step(tm, W, dW, ws, nsteps, dt_out=None, stats=False, stream=None, **params):
+    """nsteps compact GKS steps in place: W [4, ncell], dW [2, 4, ncell] float64
+    on the device; params: geno_params fields (gamma, cfl, tau_c1, tau_c2,
+    dt_fixed). Returns a geno_stats if stats=True (synchronises)."""
+    G._need(W, torch.float64, 4 * tm.ncell, "W")
+    G._need(dW, torch.float64, 8 * tm.ncell, "dW")
+    G._need(ws, torch.uint8, lib().geno_tri_workspace_bytes(tm.ncell), "ws")
+    if dt_out is not None:
+        G._need(dt_out, torch.float64, int(nsteps), "dt_out")
+    p = G.geno_params()
+    G._check(G.lib().geno_params_default(ctypes.byref(p)))
+    for key, val in params.items():
+        if not hasattr(p, key):
+            raise TypeError("unknown parameter " + key)
+        setattr(p, key, val)
+    st = G.geno_stats() if stats else None
+    G._check(lib().geno_tri_step(tm.ncell, G._ptr(tm.table), G._ptr(W), G._ptr(dW), G._ptr(ws), int(nsteps),
+                                 ctypes.byref(p), G._ptr(dt_out), ctypes.byref(st) if st is not None else None,
+                                 G._stream(stream)))
+    return st
 
 
 def op_cost():

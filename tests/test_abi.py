@@ -153,7 +153,7 @@ def test_triangle_table_host_side(so):
     from paper_2507_20461_amd import geno_tri as T
     from paper_2507_20461_amd import inputs
     nt = T.lib().geno_tri_table_doubles()
-    assert nt == 204
+    assert nt == 224
     mesh = inputs.tri_mesh(8, 8, 3)
     n = 2 * 8 * 8
     flat = T.build_table(mesh)
@@ -200,15 +200,51 @@ def test_triangle_table_host_side(so):
         T.build_table(flip)
 
 
+def test_triangle_table_geometry_matches_the_oracle(so):
+    # the step's geometry entries (area, 4 area / perimeter, per edge the
+    # outward normal, length, neighbour, the neighbour's edge index, owner)
+    # equal the oracle's own computation of them
+    import numpy as np
+    from oracle import gks_tri
+    from paper_2507_20461_amd import geno_tri as T
+    from paper_2507_20461_amd import inputs
+    mesh = inputs.tri_mesh(6, 5, 2)
+    n = 60
+    nt = T.lib().geno_tri_table_doubles()
+    flat = T.build_table(mesh)
+    ops = np.stack([flat[((e // 2) * n + np.arange(n)) * 2 + e % 2] for e in range(nt)])
+    geo = gks_tri.geometry(mesh)
+    g0 = nt - 20
+    np.testing.assert_allclose(ops[g0], geo["area"], rtol=1e-14)
+    np.testing.assert_allclose(ops[g0 + 1], geo["d"], rtol=1e-14)
+    for e in range(3):
+        b = g0 + 2 + 6 * e
+        np.testing.assert_allclose(ops[b:b + 2].T, geo["normal"][:, e], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(ops[b + 2], geo["length"][:, e], rtol=1e-14)
+        assert np.array_equal(ops[b + 3].astype(int), geo["nbr"][:, e])
+        assert np.array_equal(ops[b + 4].astype(int), geo["rev"][:, e])
+        assert np.array_equal(ops[b + 5] != 0.0, geo["owner"][:, e])
+
+
 def test_triangle_reconstruct_rejects_bad_arguments(so):
     # argument checks happen on the host, before any launch
     from paper_2507_20461_amd import geno_gks as G
     from paper_2507_20461_amd import geno_tri as T
     L = T.lib()
     fake = 256   # never dereferenced: every call below fails its checks first
-    assert L.geno_tri_reconstruct(10, 5, fake, fake, fake, fake, None, None) == G.GENO_EINVAL
-    assert L.geno_tri_reconstruct(10, 0, fake, fake, fake, fake, None, None) == G.GENO_EINVAL
-    assert L.geno_tri_reconstruct(0, 4, fake, fake, fake, fake, None, None) == G.GENO_EINVAL
-    assert L.geno_tri_reconstruct(10, 4, None, fake, fake, fake, None, None) == G.GENO_EINVAL
-    assert L.geno_tri_reconstruct(10, 4, fake, fake, fake, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 5, fake, fake, fake, fake, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 0, fake, fake, fake, fake, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(0, 4, fake, fake, fake, fake, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 4, None, fake, fake, fake, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_reconstruct(10, 4, fake, fake, fake, None, None, None, None) == G.GENO_EINVAL
     assert L.geno_tri_build(0, None, None, None, None) == G.GENO_EINVAL
+    # the step: host-side checks of its arguments and parameters
+    p = G.geno_params()
+    assert L.geno_tri_step(0, fake, fake, fake, fake, 1, ctypes.byref(p), None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_step(10, fake, fake, fake, fake, 1, None, None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_step(10, fake, fake, fake, fake, 1, ctypes.byref(p), None, None, None) == G.GENO_EVERSION
+    G.lib().geno_params_default(ctypes.byref(p))
+    assert L.geno_tri_step(10, fake, fake, fake, fake, -1, ctypes.byref(p), None, None, None) == G.GENO_EINVAL
+    p.cfl = 0.0
+    assert L.geno_tri_step(10, fake, fake, fake, fake, 1, ctypes.byref(p), None, None, None) == G.GENO_EINVAL
+    assert L.geno_tri_workspace_bytes(0) == 0 and L.geno_tri_workspace_bytes(100) > 0

@@ -128,3 +128,98 @@ def test_full_size_sampled(T, O):
     cells = np.random.default_rng(0).choice(W.shape[1], 64, replace=False)
     _compare(O, mesh, W, dW, got, gchi, cells=list(cells))
     assert np.isfinite(got).all()
+
+
+# ---------------------------------------------------------------- the step
+CHI_TOL = 1e-8
+
+
+@pytest.mark.parametrize("nx,ny,kind,seed", [(6, 5, "smooth", 1), (9, 7, "jumps", 2)])
+def test_second_derivatives_match_oracle(T, O, nx, ny, kind, seed):
+    # h^2 second derivatives of the blend, chi times the cubic's: the rounding
+    # bound of the cubic's scale plus |chi_gpu - chi_oracle| times the cubic's
+    # second derivative (Eq. (3))
+    _say("tri second derivatives", nx, ny, kind)
+    mesh = inputs.tri_mesh(nx, ny, seed)
+    W, dW = (inputs.tri_euler_smooth if kind == "smooth" else inputs.tri_euler_jumps)(mesh, seed)
+    tm = T.TriMesh(mesh)
+    Wd = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    dWd = torch.from_numpy(np.ascontiguousarray(dW)).cuda()
+    out = torch.empty(tm.out_shape(4), dtype=torch.float64, device="cuda")
+    chi = torch.empty((4, tm.ncell), dtype=torch.float64, device="cuda")
+    sec = torch.empty(tm.out_shape(4), dtype=torch.float64, device="cuda")
+    T.reconstruct(tm, Wd, dWd, out, chi, sec)
+    torch.cuda.synchronize()
+    got = sec.cpu().numpy().reshape(3, 2, 3, 4, tm.ncell).transpose(4, 0, 1, 3, 2)
+    gchi = chi.cpu().numpy().T
+    _, rchi, info = O.reconstruct(mesh, W, dW, second=True)
+    high = np.abs(info["second_high"])
+    sc = np.maximum(high.reshape(-1, 4, 3).max(axis=(0, 2)), 1e-300)
+    bound = TOL * sc[None, None, None, :, None] + np.abs(gchi - rchi)[:, None, None, :, None] * high
+    assert np.all(np.abs(got - info["second"]) <= bound), np.abs(got - info["second"]).max()
+
+
+def _gpu_step(T, tm, W, dW, ws, dts, n=1):
+    Wd = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    dWd = torch.from_numpy(np.ascontiguousarray(dW)).cuda()
+    st = T.step(tm, Wd, dWd, ws, n, dt_out=dts, stats=True)
+    return Wd.cpu().numpy(), dWd.cpu().numpy(), st
+
+
+def _state_err(g, o):
+    # rho and rho E per cell relative to their value; the momenta relative to
+    # max(value, field scale)
+    sc = np.abs(o).max(axis=1)
+    den = np.maximum(np.abs(o), np.array([0.0, sc[1], sc[2], 0.0])[:, None])
+    return float((np.abs(g - o) / den).max())
+
+
+@pytest.mark.parametrize("nx,ny,kind,seed,steps", [(8, 7, "smooth", 1, 4), (9, 8, "jumps", 2, 4),
+                                                   (2, 3, "jumps", 3, 2)])
+def test_step_shadowed(T, nx, ny, kind, seed, steps):
+    # every GPU step against the oracle's step from the same (GPU) state:
+    # W per cell at 1e-12; the gradients at 1e-12 of scale / h plus the chi
+    # term of their second-order part (chi enters the blended second
+    # derivatives, |dchi| < 1e-8, through dt^2/3 W_tt ~ CFL^2 / 3 of scale / h)
+    from oracle import gks_tri as GT
+    _say("tri step shadowed", nx, ny, kind, steps)
+    mesh = inputs.tri_mesh(nx, ny, seed)
+    geo = GT.geometry(mesh)
+    W, dW = (inputs.tri_euler_smooth if kind == "smooth" else inputs.tri_euler_jumps)(mesh, seed)
+    tm = T.TriMesh(mesh)
+    ws = tm.workspace()
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hmin = np.sqrt(geo["area"].min())
+    worst = [0.0, 0.0]
+    for s in range(steps):
+        gW, gdW, st = _gpu_step(T, tm, W, dW, ws, dts)
+        assert st.nonfinite == 0
+        oW, odW, odt, og = GT.step(mesh, W, dW, 1, geo=geo)
+        assert float(dts.item()) == pytest.approx(float(odt[0]), rel=1e-13)
+        assert st.guard == og
+        e = _state_err(gW, oW)
+        gsc = np.abs(oW).max(axis=1) / hmin
+        de = float((np.abs(gdW - odW) / gsc[None, :, None]).max())
+        worst = [max(worst[0], e), max(worst[1], de)]
+        W, dW = gW, gdW
+    _say("worst W %.3e dW %.3e" % tuple(worst))
+    assert worst[0] < TOL and worst[1] < TOL + CHI_TOL * 0.5 ** 2 / 3.0, worst
+
+
+def test_step_conservation_and_constant_state(T):
+    mesh = inputs.tri_mesh(10, 9, 4)
+    from oracle import gks_tri as GT
+    geo = GT.geometry(mesh)
+    tm = T.TriMesh(mesh)
+    ws = tm.workspace()
+    W, dW = inputs.tri_euler_jumps(mesh, 4)
+    dts = torch.zeros(6, dtype=torch.float64, device="cuda")
+    gW, _, st = _gpu_step(T, tm, W, dW, ws, dts, 6)
+    A = geo["area"]
+    import math
+    for k in range(4):
+        assert abs(math.fsum(A * gW[k]) - math.fsum(A * W[k])) <= 1e-13 * math.fsum(A * np.abs(W[k]))
+    n = A.size
+    Wc = np.array([1.1, 0.3, -0.2, 2.6])[:, None] * np.ones((4, n))
+    gW, gdW, _ = _gpu_step(T, tm, Wc, np.zeros((2, 4, n)), ws, dts, 3)
+    assert np.abs(gW - Wc).max() < 1e-13 and np.abs(gdW).max() < 1e-11
