@@ -185,10 +185,13 @@ def test_gate_always_on_skips_every_indicator(G):
     assert wk["normal_y"]["gated"] == 2 * 2 * 4 * 2 * nx * ny
 
 
-def test_trained_gate_gains(G):
+def test_trained_gate_skips_indicator_work(G):
     # harvest, train and choose delta with the library's kernels on a small
     # set; the trained gate must skip most indicator work on a fresh state
-    # while its misgates stay rare and the solution close to plain GENO's
+    # while its misgates stay rare and the solution close to plain GENO's.
+    # (This checks the gate's function, not a speed-up: at 2048^2 the gated
+    # forms are slower than without the gate and miss equal L1, which the
+    # benchmark line reports.)
     from paper_2507_20461_amd import learned
     X, y = learned.harvest_dataset(n2d=128, seeds=(0, 1), steps=40, every=8)
     Xs, ys = learned.stratify(X, y)
