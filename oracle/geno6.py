@@ -25,7 +25,7 @@ _lib = None
 PERIODIC, TRANSMISSIVE, REFLECTING, FIXED = 0, 1, 2, 3
 # parameter vector: gamma, C, eps, d1..d4, cfl, bc_lo, bc_hi, dt_fixed, characteristic,
 # then 18 ghost values [end][cell k][field] of fixed ends
-N_PARAMS = 30
+N_PARAMS = 31
 
 
 def build(force: bool = True) -> str:
@@ -78,17 +78,22 @@ def _c(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+ISTAU_PRINTED, ISTAU_LARGE_STENCIL = 0, 1
+
+
 def params(bc=PERIODIC, gamma=1.4, C=20.0, eps=1e-15, d=(1.0, 8.0, 1.0, 1.0), cfl=0.5,
-           dt_fixed=0.0, characteristic=False, ghost=None) -> np.ndarray:
+           dt_fixed=0.0, characteristic=False, ghost=None, istau=ISTAU_PRINTED) -> np.ndarray:
     """Method constants of Sec. 3 and 4.1 (C = 20, eps = 1e-15, C_0 = 8 on the
     central sub-stencil S_2). bc: one code or a (low, high) pair;
     characteristic: reconstruct characteristic instead of conservative
     variables; ghost: [2, 3, 3] states of the ghost cells of FIXED ends
-    ([end][cell k][field], cell -1-k or n+k)."""
+    ([end][cell k][field], cell -1-k or n+k); istau: the printed IS^tau of
+    Sec. 4.1, or ISTAU_LARGE_STENCIL, the fifth-derivative indicator of p^5
+    (a reading of Sec. 3, built as Sec. 4.3 builds IS^tau on triangles)."""
     lo, hi = (bc, bc) if np.isscalar(bc) else bc
     g = np.zeros(18) if ghost is None else np.asarray(ghost, dtype=np.float64).reshape(18)
-    return np.array([gamma, C, eps, *d, cfl, lo, hi, dt_fixed, 1.0 if characteristic else 0.0, *g],
-                    dtype=np.float64)
+    return np.array([gamma, C, eps, *d, cfl, lo, hi, dt_fixed, 1.0 if characteristic else 0.0, *g,
+                     float(istau)], dtype=np.float64)
 
 
 def eigen(prm, Ua, Ub):

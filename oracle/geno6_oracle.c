@@ -63,12 +63,14 @@
 
 enum { Q_GAMMA = 0, Q_C, Q_EPS, Q_D1, Q_D2, Q_D3, Q_D4, Q_CFL, Q_BCL, Q_BCH, Q_DTFIX, Q_CHAR,
        Q_GHOST,                /* 18 values: [end][ghost cell k][field] for fixed ends */
-       Q_COUNT = Q_GHOST + 18 };
+       Q_ISTAU = Q_GHOST + 18, /* 0: the printed IS^tau of Sec. 4.1, 1: the large-stencil one */
+       Q_COUNT };
 
 typedef struct {
   double gamma, C, eps, d[4], cfl, dt_fixed;
   int bc[2];   /* 0 periodic, 1 transmissive, 2 reflecting, 3 fixed states */
   int characteristic;   /* 0: conservative variables, 1: characteristic variables */
+  int istau;            /* IS^tau: 0 printed (Sec. 4.1), 1 from p^5 (see geno_side) */
   double ghost[2][3][3];  /* fixed ends: [end][k][field], cell -1-k or n+k */
 } cfg6;
 
@@ -78,6 +80,7 @@ static void cfg_load(cfg6 *c, const double *p) {
   c->cfl = p[Q_CFL]; c->bc[0] = (int)p[Q_BCL]; c->bc[1] = (int)p[Q_BCH];
   c->dt_fixed = p[Q_DTFIX];
   c->characteristic = (int)p[Q_CHAR];
+  c->istau = (int)p[Q_ISTAU];
   for (int e = 0; e < 2; ++e)
     for (int k = 0; k < 3; ++k)
       for (int f = 0; f < 3; ++f) c->ghost[e][k][f] = p[Q_GHOST + (e * 3 + k) * 3 + f];
@@ -184,7 +187,20 @@ static int geno_side(const cfg6 *P, const double u6[6], int side, double *detail
   /* Eq. (7), (9) and the Sec. 4.1 indicator */
   double ISH = IS[1], ISL = IS[1];
   for (int k = 2; k <= 4; ++k) { ISH = fmax(ISH, IS[k]); ISL = fmin(ISL, IS[k]); }
-  const double IStau = fabs(0.5 * (IS[1] + IS[3]) - IS[2]);
+  /* Sec. 4.1 prints IS^tau = |(IS_1 + IS_3)/2 - IS_2|, blind to a jump that
+   * lies only in S_4 (the cells j..j+3 on the left side). Option istau = 1
+   * takes instead, as Sec. 3 describes IS^tau (a higher-order indicator of
+   * the large stencil) and Sec. 4.3 builds it on triangles, the difference
+   * between the indicator of p^5 up to its fifth derivative and up to its
+   * fourth, i.e. the integral of (d^5 p^5 / dxi^5)^2 over the target cell. */
+  double IStau = fabs(0.5 * (IS[1] + IS[3]) - IS[2]);
+  if (P->istau == 1) {
+    const int lo0 = side == 0 ? LO[0] : -(LO[0] + NC[0] - 1);
+    double avg[6], a[6];
+    for (int m = 0; m < 6; ++m) avg[m] = u6[tgt + lo0 + m];
+    if (poly_from_averages(avg, lo0, 6, a)) return O6_EINVAL;
+    IStau = fabs(smoothness(a, 6, 5) - smoothness(a, 6, 4));
+  }
   /* Eq. (5) with r = 2 and Eq. (4) */
   const double aH = 1.0 + pow(IStau / (ISH + P->eps), 2.0);
   const double aL = 1.0 + pow(IStau / (ISL + P->eps), 2.0);

@@ -378,3 +378,61 @@ def test_titarev_toro_data():
     # exact averages of 1 + 0.1 sin(20 pi x) over the 10 cells of a period sum to 10
     assert abs(rho[100:110].sum() - 10.0) < 1e-12
     assert np.allclose(g[0, :, 0], 1.515695) and np.allclose(g[1, :, 1], 0.0)
+
+
+def test_jump_in_s4_only_under_both_indicators():
+    # the printed IS^tau of Sec. 4.1 is blind to a jump that lies only in S_4
+    # (cells j..j+3 on the left side): chi = 1 and the linear value carries
+    # 1/60 of the jump. The large-stencil reading (the fifth-derivative
+    # indicator of p^5) sees it; both see a jump that S_3 holds
+    printed, large = o6.params(), o6.params(istau=o6.ISTAU_LARGE_STENCIL)
+    u = [0, 0, 0, 0, 0, 1.0]
+    assert o6.side(printed, u, 0)["chi"] == 1.0
+    s = o6.side(large, u, 0)
+    assert s["chi"] < 1e-20 and abs(s["value"]) < 1e-12
+    # by hand: p^5 of this data has a fifth-derivative coefficient a_5 with
+    # 5! a_5 = (the fifth difference of the averages) = 1, so IS^tau = 1
+    a = o6.poly(u, -2)
+    assert 120.0 * a[5] == pytest.approx(1.0, rel=1e-12)
+    for prm in (printed, large):
+        assert o6.side(prm, [0, 0, 0, 0, 1.0, 0], 0)["chi"] < 1e-20
+
+
+def test_large_stencil_indicator_keeps_smooth_data_linear():
+    # the density wave of Sec. 6.1: from 12 cells up chi = 1 exactly at every
+    # face with either indicator; on 6 cells both stay within 1e-9 of 1
+    large = o6.params(istau=o6.ISTAU_LARGE_STENCIL)
+    for n in (6, 12, 24):
+        h = 2.0 / n
+        xl = np.arange(n) * h
+        rho = 1 + 0.2 * (np.cos(np.pi * xl) - np.cos(np.pi * (xl + h))) / (np.pi * h)
+        for j in range(n):
+            u6 = [rho[(j + k) % n] for k in range(-2, 4)]
+            for sd in (0, 1):
+                chi = o6.side(large, u6, sd)["chi"]
+                assert chi == 1.0 if n >= 12 else chi > 1.0 - 1e-9
+
+
+@pytest.mark.parametrize("istau,survives", [(0, False), (1, True)], ids=["printed", "large-stencil"])
+def test_blast_wave_at_cfl_half_with_each_indicator(istau, survives):
+    # the Woodward-Colella blast waves (400 cells, reflecting walls) at CFL
+    # 0.5: with the printed indicator the cell two to the right of the
+    # p = 1000 / 0.01 jump goes negative in the first step; with the
+    # large-stencil indicator the run reaches t = 0.038
+    from paper_2507_20461_amd import inputs
+    W, _ = inputs.blast_wave_1d(400)
+    U = W[:, 0, :].copy()
+    dx = 1.0 / 400
+    t, k, ok = 0.0, 0, True
+    while t < 0.038 and k < 5000:
+        dt = min(o6.cfl_dt(o6.params(bc=2, istau=istau), U, dx), 0.038 - t)
+        U, _, _ = o6.step(o6.params(bc=2, dt_fixed=dt, istau=istau), U, dx, 1)
+        t += dt
+        k += 1
+        p = 0.4 * (U[2] - 0.5 * U[1] ** 2 / U[0])
+        if not (np.isfinite(U).all() and U[0].min() > 0 and p.min() > 0):
+            ok = False
+            break
+    assert ok == survives, (k, t)
+    if survives:
+        assert abs(U[0].sum() - W[0].sum()) < 1e-12 * W[0].sum()
