@@ -438,8 +438,8 @@ __device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KP
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      fr[(size_t)((2 * s + 0) * 4 + VM[f]) * plane + o] = T(Sv[f]);
-      fr[(size_t)((2 * s + 1) * 4 + VM[f]) * plane + o] = T(Dv[f]);
+      __builtin_nontemporal_store(T(Sv[f]), &fr[(size_t)((2 * s + 0) * 4 + VM[f]) * plane + o]);
+      __builtin_nontemporal_store(T(Dv[f]), &fr[(size_t)((2 * s + 1) * 4 + VM[f]) * plane + o]);
     }
   }
   // the mean of the two sides' h^2 * second derivatives, mapped back like
@@ -452,7 +452,7 @@ __device__ __forceinline__ unsigned int normal_char(const Geo& g, const geno::KP
     for (int f = 0; f < 4; ++f) S2[f] = w2[f];
   }
 #pragma unroll
-  for (int f = 0; f < 4; ++f) fr[(size_t)(16 + VM[f]) * plane + o] = T(S2[f]);
+  for (int f = 0; f < 4; ++f) __builtin_nontemporal_store(T(S2[f]), &fr[(size_t)(16 + VM[f]) * plane + o]);
   return nlow;
 }
 
@@ -517,11 +517,13 @@ __device__ __forceinline__ void normal_body(const Geo& g, const geno::KParams& k
     double xl, xr;
     nlow = geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl,
                                       xl, vr, dr, xr, h2, skipL, skipR);
-    fr[(size_t)(0 * 4 + v) * plane + o] = vl;
-    fr[(size_t)(1 * 4 + v) * plane + o] = dl;
-    fr[(size_t)(2 * 4 + v) * plane + o] = vr;
-    fr[(size_t)(3 * 4 + v) * plane + o] = dr;
-    fr[(size_t)(16 + v) * plane + o] = h2;
+    // face-row and face buffers are written once and read by the next
+    // launch: streamed past the caches (non-temporal stores)
+    __builtin_nontemporal_store(vl, &fr[(size_t)(0 * 4 + v) * plane + o]);
+    __builtin_nontemporal_store(dl, &fr[(size_t)(1 * 4 + v) * plane + o]);
+    __builtin_nontemporal_store(vr, &fr[(size_t)(2 * 4 + v) * plane + o]);
+    __builtin_nontemporal_store(dr, &fr[(size_t)(3 * 4 + v) * plane + o]);
+    __builtin_nontemporal_store(h2, &fr[(size_t)(16 + v) * plane + o]);
     if (chi) {
       chi[(size_t)(0 * 4 + v) * plane + o] = xl;
       chi[(size_t)(1 * 4 + v) * plane + o] = xr;
@@ -815,11 +817,11 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
       for (int v = 0; v < 4; ++v) {
         const int pv = perm[v];
         if (q == 0) {
-          if (want_F) out[(size_t)(0 * 4 + pv) * plane + o] = So[v];
-          out[(size_t)(1 * 4 + pv) * plane + o] = So[4 + v];
+          if (want_F) __builtin_nontemporal_store(So[v], &out[(size_t)(0 * 4 + pv) * plane + o]);
+          __builtin_nontemporal_store(So[4 + v], &out[(size_t)(1 * 4 + pv) * plane + o]);
         } else {
-          out[(size_t)(2 * 4 + pv) * plane + o] = So[8 + v];
-          if (want_F) out[(size_t)(3 * 4 + pv) * plane + o] = So[12 + v];
+          __builtin_nontemporal_store(So[8 + v], &out[(size_t)(2 * 4 + pv) * plane + o]);
+          if (want_F) __builtin_nontemporal_store(So[12 + v], &out[(size_t)(3 * 4 + pv) * plane + o]);
         }
       }
     }
