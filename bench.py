@@ -48,10 +48,10 @@ COMBINED = {"normal_xy": ("normal_x", "normal_y")}
 COUNTERS = os.path.join(ROOT, "profiles", "stage_fp64_2048_counters.json")
 # Algorithmic HBM bytes per cell-stage of the two-stage update (read the
 # state once, write the outputs once; halos through caches): stage 1 reads
-# W, grad W and writes W*, grad W*, R and the gradients' end-of-step share
-# RG; stage 2 reads W*, grad W*, R, RG and writes W, grad W. 2-D FP64:
-# (96 + 192 + 192 + 96) / 2 = 288 B; mixed (gradients float32): 192 B.
-ALGO_BYTES_CELL_STAGE = {"fp64": 288.0, "mixed": 192.0}
+# W, grad W (96 B) and writes W*, grad W*, R (128 B); stage 2 reads those
+# (128 B) and writes W, grad W (96 B). 2-D FP64: 448 / 2 = 224 B; mixed
+# (gradients float32): 160 B.
+ALGO_BYTES_CELL_STAGE = {"fp64": 224.0, "mixed": 160.0}
 
 
 def parse():
@@ -97,25 +97,28 @@ def traffic(kind, n):
 def algo_bytes(kind, work, launches, nx, ny):
     """Algorithmic HBM bytes of all launches of one kernel kind (2-D FP64):
     what the kernel must read and write once, from its work counts.
-    normal: W and h d/dn of one cell in (16 B), value and h d/dn per side out
-    (32 B) per face-row entry. faces: the 16 face-row values of every face in
-    (128 B); F (stage 1 only), dF/dt and W_int out for each face it evaluates
-    (96 B / 64 B, 80 B on average over the two stages). slow: as faces for
-    the queued faces, plus the queue index. update_1: W in, two faces' 12
-    planes in amortised to 192 B, W*, grad W*, R out: 352 B per cell;
-    update_2: R in, 8 face planes, W and grad W out: 256 B per cell."""
+    normal: W and h d/dn of one cell in (16 B), per side the value and h d/dn
+    and the mean h^2 d2/dn2 out (40 B) per face-row entry. faces: the 20
+    face-row values of every face in (160 B); out for each face it
+    evaluates 16 values in stage 1 (F, dF/dt and the two interface fields)
+    and 8 in stage 2 (dF/dt, W_tt*): 96 B on average over the two stages.
+    slow: as faces for the queued faces, plus the queue index. update_1: W
+    in, two faces' 12 planes (F, dF/dt, interface values at the stage time)
+    in amortised to 192 B, W*, grad W*, R out: 352 B per cell; update_2: R
+    in, 12 face planes (dF/dt*, W_tt*, stage-1 end-of-step values) amortised
+    to 192 B, W and grad W out: 320 B per cell."""
     u = work.get(kind, {}).get("units", 0)
     if kind in ("normal_x", "normal_y"):
-        return 48.0 * u
+        return 56.0 * u
     if kind in ("faces_x", "faces_y"):
         nfaces = ny * (nx + 1) if kind == "faces_x" else (ny + 1) * nx
-        return 128.0 * nfaces * launches + 80.0 * u
+        return 160.0 * nfaces * launches + 96.0 * u
     if kind == "slow":
-        return (128.0 + 80.0 + 4.0) * u
+        return (160.0 + 96.0 + 4.0) * u
     if kind == "update_1":
         return 352.0 * u
     if kind == "update_2":
-        return 256.0 * u
+        return 320.0 * u
     return None
 
 
@@ -1031,7 +1034,7 @@ def main():
         # once. A stage is the sequence of launches normal_xy, faces_x,
         # faces_y, slow, update; its duration is the sum of their average
         # per-stage durations from the dispatch-bound events. achieved =
-        # 288 B x cells / stage duration.
+        # 224 B x cells / stage duration.
         nstage = 2.0 * args.steps
         stage_ms = sum(d["ms_total"] for d in kernels.values()) / nstage
         stage_bytes = ALGO_BYTES_CELL_STAGE["fp64"] * n * n

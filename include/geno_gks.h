@@ -253,7 +253,7 @@ int gks_step(const geno_grid* g, void* W, void* dW, void* ws, int nsteps, double
 
 /* Size of the device memory gks_step_noalloc works in: 64 MiB on every
  * device the library runs on (enough for the workspace of a 2-D float64 grid
- * of up to about 290 x 290 cells, mixed precision about 390 x 390; see
+ * of up to about 300 x 300 cells, mixed precision about 410 x 410; see
  * gks_workspace_bytes). */
 #define GENO_NOALLOC_SCRATCH_BYTES (64u << 20)
 

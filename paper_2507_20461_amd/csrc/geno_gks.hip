@@ -1219,17 +1219,18 @@ __global__ void __launch_bounds__(BLOCK) k_flux_points(int nfaces, int ngauss, i
 // ---------------------------------------------------------------------------
 // Cell update (two-stage fourth-order method). STAGE 1: W* = W + dt/2 L +
 // dt^2/8 Lt, R = W + dt L + dt^2/6 Lt; grad* by the Gauss theorem (Eq. (2))
-// from the interface values at the stage time, W(dt/2) + dt^2/8 W_tt, and
-// RG from W(dt) + dt^2/6 W_tt. STAGE 2: W = R + dt^2/3 Lt*, grad = RG +
-// dt^2/3 (Gauss theorem on W_tt*), and the CFL minima of the new state per
-// block. Both write the ghost cells of the state they produce. RG has the
-// layout of the gradients (interior cells only).
+// from the interface values at the stage time, W(dt/2) + dt^2/8 W_tt.
+// STAGE 2: W = R + dt^2/3 Lt*, grad = the Gauss theorem on the stage-1
+// interface values W(dt) + dt^2/6 W_tt (face kind 3, which the stage-2 face
+// step leaves in place) plus dt^2/3 times the Gauss theorem on W_tt*, and
+// the CFL minima of the new state per block. Both write the ghost cells of
+// the state they produce.
 // ---------------------------------------------------------------------------
 template <int NDIM, int STAGE, typename T>
 __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k,
                                             const double* __restrict__ Win,
                                             double* __restrict__ Wout, T* __restrict__ dWout,
-                                            double* __restrict__ R, T* __restrict__ RG,
+                                            double* __restrict__ R,
                                             const T* __restrict__ fx,
                                             const T* __restrict__ fy, Ctrl* ctrl,
                                             double* __restrict__ part, const Cnt& cnt, int lb) {
@@ -1272,17 +1273,17 @@ __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k
         w[v] = w0 + 0.5 * dt * l + dt * dt / 8.0 * lt;
         R[c] = w0 + dt * l + dt * dt / 6.0 * lt;
         dw[v] = T(gx);
-        // kind 3: W(dt) + dt^2/6 W_tt
-        RG[at(g, v, j, i)] = T((X(3 * NV + v, ox + 1) - X(3 * NV + v, ox)) * idx);
-        if constexpr (NDIM == 2) {
-          dw[NV + v] = T(gy);
-          RG[at(g, NV + v, j, i)] = T((Y(3 * NV + v, oy + g.nx) - Y(3 * NV + v, oy)) * idy);
-        }
+        if constexpr (NDIM == 2) dw[NV + v] = T(gy);
       } else {
         (void)l;
         w[v] = R[c] + c3 * lt;
-        dw[v] = T((double)RG[at(g, v, j, i)] + c3 * gx);
-        if constexpr (NDIM == 2) dw[NV + v] = T((double)RG[at(g, NV + v, j, i)] + c3 * gy);
+        // kind 3 of stage 1: W(dt) + dt^2/6 W_tt
+        const double gx1 = (X(3 * NV + v, ox + 1) - X(3 * NV + v, ox)) * idx;
+        dw[v] = T(gx1 + c3 * gx);
+        if constexpr (NDIM == 2) {
+          const double gy1 = (Y(3 * NV + v, oy + g.nx) - Y(3 * NV + v, oy)) * idy;
+          dw[NV + v] = T(gy1 + c3 * gy);
+        }
       }
       Wout[c] = w[v];
     }
@@ -1314,11 +1315,11 @@ __global__ void __launch_bounds__(BLOCK) k_update(Geo g, geno::KParams k,
                                                   const double* __restrict__ Win,
                                                   double* __restrict__ Wout,
                                                   T* __restrict__ dWout,
-                                                  double* __restrict__ R, T* __restrict__ RG,
+                                                  double* __restrict__ R,
                                                   const T* __restrict__ fx,
                                                   const T* __restrict__ fy, Ctrl* ctrl,
                                                   double* __restrict__ part, Cnt cnt) {
-  update_body<NDIM, STAGE, T>(g, k, Win, Wout, dWout, R, RG, fx, fy, ctrl, part, cnt,
+  update_body<NDIM, STAGE, T>(g, k, Win, Wout, dWout, R, fx, fy, ctrl, part, cnt,
                               xcd_block());
 }
 
@@ -1562,7 +1563,6 @@ struct BEntry {
   double* wst;
   double* r;
   void* dwst;
-  void* rg;
   void* fr[2];
   void* fl[2];
   int npart;     // update work-groups of this grid (CFL partials)
@@ -1641,10 +1641,10 @@ __global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
   const int gi = find_grid(st, ngrids, gb);
   const BEntry& e = tab[gi];
   if (STAGE == 1)
-    update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (T*)e.rg, (const T*)e.fl[0],
+    update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (const T*)e.fl[0],
                          (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
   else
-    update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (T*)e.rg, (const T*)e.fl[0],
+    update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (const T*)e.fl[0],
                          (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
 }
 
@@ -1765,10 +1765,10 @@ __global__ void __launch_bounds__(PB) __attribute__((amdgpu_waves_per_eu(4))) kb
           break;
         default:
           if (stage == 1)
-            update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r, (T*)e.rg,
+            update_body<2, 1, T>(e.geo, k, e.W, e.wst, (T*)e.dwst, e.r,
                                  (const T*)e.fl[0], (const T*)e.fl[1], e.ctrl, e.part, cnt, lb);
           else
-            update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (T*)e.rg,
+            update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r,
                                  (const T*)e.fl[0], (const T*)e.fl[1], e.ctrl, e.part, cnt, lb);
       }
     }
@@ -1795,7 +1795,7 @@ __global__ void __launch_bounds__(PB) __attribute__((amdgpu_waves_per_eu(4))) kb
 // host helpers
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t ctrl, part, queue[2], gate, wst, dwst, r, rg, fr[2], fl[2], total;
+  size_t ctrl, part, queue[2], gate, wst, dwst, r, fr[2], fl[2], total;
   size_t nstate;   // elements per field plane
   int npart;
 };
@@ -1834,8 +1834,6 @@ Layout layout_of(const geno_grid* g) {
   off = align256(off + L.nstate * nv * g->ndim * es);
   L.r = off;
   off = align256(off + L.nstate * nv * sizeof(double));
-  L.rg = off;   // the gradients' share of the end-of-step interface values
-  off = align256(off + L.nstate * nv * g->ndim * es);
   if (g->ndim == 2) {
     L.fr[0] = off;
     off = align256(off + (size_t)20 * (g->ny + 2) * (g->nx + 1) * es);
@@ -1954,7 +1952,7 @@ struct Bufs {
   unsigned int* queue[2];
   unsigned char* gate;
   double *wst, *r;
-  T *dwst, *rg, *fr[2], *fl[2];
+  T *dwst, *fr[2], *fl[2];
 };
 
 template <typename T>
@@ -1965,7 +1963,6 @@ Bufs<T> bufs_of(char* ws, const Layout& L, int ndim) {
   b.wst = reinterpret_cast<double*>(ws + L.wst);
   b.dwst = reinterpret_cast<T*>(ws + L.dwst);
   b.r = reinterpret_cast<double*>(ws + L.r);
-  b.rg = reinterpret_cast<T*>(ws + L.rg);
   b.fl[0] = reinterpret_cast<T*>(ws + L.fl[0]);
   if (ndim == 2) {
     b.queue[0] = reinterpret_cast<unsigned int*>(ws + L.queue[0]);
@@ -2098,17 +2095,17 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
   const T* fy = g->ndim == 2 ? B.fl[1] : nullptr;
   if (g->ndim == 2) {
     if (stage == 1)
-      HIP_TRY(launch(kind, k_update<2, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.rg, B.fl[0], fy,
+      HIP_TRY(launch(kind, k_update<2, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
                      B.ctrl, B.part, cnt));
     else
-      HIP_TRY(launch(kind, k_update<2, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.rg, B.fl[0],
+      HIP_TRY(launch(kind, k_update<2, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0],
                      fy, B.ctrl, B.part, cnt));
   } else {
     if (stage == 1)
-      HIP_TRY(launch(kind, k_update<1, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.rg, B.fl[0], fy,
+      HIP_TRY(launch(kind, k_update<1, 1, T>, nc, s, geo, k, Win, B.wst, B.dwst, B.r, B.fl[0], fy,
                      B.ctrl, B.part, cnt));
     else
-      HIP_TRY(launch(kind, k_update<1, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.rg, B.fl[0],
+      HIP_TRY(launch(kind, k_update<1, 2, T>, nc, s, geo, k, Win, Wfinal, dWfinal, B.r, B.fl[0],
                      fy, B.ctrl, B.part, cnt));
   }
   return GENO_OK;
@@ -2340,7 +2337,6 @@ void bind_batch(BatchPlan* P, char* ws, void* const* W, void* const* dW, const g
     e.wst = reinterpret_cast<double*>(b + L.wst);
     e.r = reinterpret_cast<double*>(b + L.r);
     e.dwst = b + L.dwst;
-    e.rg = b + L.rg;
     e.fr[0] = b + L.fr[0];
     e.fr[1] = b + L.fr[1];
     e.fl[0] = b + L.fl[0];

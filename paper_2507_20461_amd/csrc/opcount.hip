@@ -184,11 +184,11 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
       set(kind, GENO_W_SLOW, (double)pslow);
     }
     // update per cell and variable: stage 1 L (5), L_t (5), gradients at the
-    // stage time and their end-of-step share (8), W* (7), R (6); stage 2
-    // L_t (5), gradients (8), W (2), and per cell dt^2/3 (2) and the CFL
-    // bound (17)
-    set(GENO_K_UPDATE_1, GENO_W_UNITS, 4.0 * 31.0);
-    set(GENO_K_UPDATE_2, GENO_W_UNITS, 4.0 * 15.0 + 19.0);
+    // stage time (4), W* (7), R (6); stage 2 L_t (5), gradients of W_tt* (4)
+    // and of the stage-1 end-of-step values (4), their combination (4), W
+    // (2), and per cell dt^2/3 (2) and the CFL bound (17)
+    set(GENO_K_UPDATE_1, GENO_W_UNITS, 4.0 * 27.0);
+    set(GENO_K_UPDATE_2, GENO_W_UNITS, 4.0 * 19.0 + 19.0);
     set(GENO_K_INIT, GENO_W_UNITS, 17.0);
   } else {
     const double face = 3.0 * (4 + lin + 2 * side_hi) + 2.0 * adm + 6.0;
@@ -197,8 +197,8 @@ int geno_op_costs_impl(int ndim, double gamma, int nkinds, int nclass, double* c
     set(GENO_K_FACES_1D, GENO_W_EQUAL, (double)pequal);
     set(GENO_K_FACES_1D, GENO_W_FAST, (double)pfast);
     set(GENO_K_FACES_1D, GENO_W_SLOW, (double)pslow);
-    set(GENO_K_UPDATE_1, GENO_W_UNITS, 3.0 * 21.0);
-    set(GENO_K_UPDATE_2, GENO_W_UNITS, 3.0 * 8.0 + 13.0);
+    set(GENO_K_UPDATE_1, GENO_W_UNITS, 3.0 * 19.0);
+    set(GENO_K_UPDATE_2, GENO_W_UNITS, 3.0 * 10.0 + 13.0);
     set(GENO_K_INIT, GENO_W_UNITS, 11.0);
   }
   return 0;
