@@ -38,11 +38,13 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # rocprofv3 kernel names of the measured kernel kinds (2-D path)
-ROCPROF_NAMES = {"init": "k_init<2, double>", "normal_x": "k_normal2d<0, double, false>",
-                 "normal_y": "k_normal2d<1, double, false>", "faces_x": "k_faces2d<0, 1, double>",
-                 "faces_y": "k_faces2d<1, 1, double>", "slow": "k_slow2d<double>",
-                 "update_1": "k_update<2, 1, double>", "update_2": "k_update<2, 2, double>",
-                 "normal_xy": "k_normal2d_xy<double, false>"}
+ROCPROF_NAMES = {"init": ["k_init<2, double>"], "normal_x": ["k_normal2d<0, double, false>"],
+                 "normal_y": ["k_normal2d<1, double, false>"],
+                 "faces_x": ["k_faces2d<0, 1, double, true>", "k_faces2d<0, 1, double, false>"],
+                 "faces_y": ["k_faces2d<1, 1, double, true>", "k_faces2d<1, 1, double, false>"],
+                 "slow": ["k_slow2d<double, true>", "k_slow2d<double, false>"],
+                 "update_1": ["k_update<2, 1, double>"], "update_2": ["k_update<2, 2, double>"],
+                 "normal_xy": ["k_normal2d_xy<double, false>"]}
 # a launch that does the work counted under several kinds
 COMBINED = {"normal_xy": ("normal_x", "normal_y")}
 COUNTERS = os.path.join(ROOT, "profiles", "stage_fp64_2048_counters.json")
@@ -85,12 +87,18 @@ def traffic(kind, n):
     meta = json.load(open(COUNTERS))
     if meta.get("source_hash") != profiling.source_hash():
         return None, "counters taken on other kernel sources"
-    row = meta["kernels"].get(ROCPROF_NAMES.get(kind, ""))
-    if not row or row.get("fetch_bytes_cal") is None or row.get("write_bytes_cal") is None:
+    # a kind launched as several instantiations (one per stage) alternating
+    # launch by launch: the mean of their per-launch figures
+    rows = [meta["kernels"].get(name) for name in ROCPROF_NAMES.get(kind, [])]
+    if not rows or any(not r or r.get("fetch_bytes_cal") is None or r.get("write_bytes_cal") is None
+                       for r in rows):
         return None, None
-    return row["fetch_bytes_cal"] + row["write_bytes_cal"], {
-        "fetch_bytes": round(row["fetch_bytes_cal"]), "write_bytes": round(row["write_bytes_cal"]),
-        "calibration": meta["calibration"], "rocprof_avg_us": meta["ktrace_avg_us"].get(ROCPROF_NAMES[kind]),
+    mean = lambda key: sum(r[key] for r in rows) / len(rows)
+    us = [meta["ktrace_avg_us"].get(name) for name in ROCPROF_NAMES[kind]]
+    return mean("fetch_bytes_cal") + mean("write_bytes_cal"), {
+        "fetch_bytes": round(mean("fetch_bytes_cal")), "write_bytes": round(mean("write_bytes_cal")),
+        "calibration": meta["calibration"],
+        "rocprof_avg_us": sum(us) / len(us) if all(u is not None for u in us) else None,
         "source": os.path.relpath(COUNTERS, ROOT)}
 
 
@@ -1056,9 +1064,10 @@ def main():
         vb = None
         if tdetail and isinstance(tdetail, dict):
             meta = json.load(open(COUNTERS))
-            row = meta["kernels"].get(ROCPROF_NAMES.get(dominant, ""), {})
-            vb = {"valu_busy": round(row["valu_busy"], 4), "valu_insts_per_wave": round(row["valu_insts_per_wave"], 1)} \
-                if row.get("valu_busy") is not None else None
+            rows = [meta["kernels"].get(name, {}) for name in ROCPROF_NAMES.get(dominant, [])]
+            if rows and all(r.get("valu_busy") is not None for r in rows):
+                vb = {"valu_busy": round(sum(r["valu_busy"] for r in rows) / len(rows), 4),
+                      "valu_insts_per_wave": round(sum(r["valu_insts_per_wave"] for r in rows) / len(rows), 1)}
         roofline = {"bound": "hbm", "kernel": "stage (normal_xy, faces_x, faces_y, slow, update)",
                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(achieved / PEAK_HBM_GBS, 5),
