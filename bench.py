@@ -44,9 +44,14 @@ ROCPROF_NAMES = {"init": ["k_init<2, double>"], "normal_x": ["k_normal2d<0, doub
                  "faces_y": ["k_faces2d<1, 1, double, true>", "k_faces2d<1, 1, double, false>"],
                  "slow": ["k_slow2d<double, true>", "k_slow2d<double, false>"],
                  "update_1": ["k_update<2, 1, double>"], "update_2": ["k_update<2, 2, double>"],
-                 "normal_xy": ["k_normal2d_xy<double, false>"]}
-# a launch that does the work counted under several kinds
-COMBINED = {"normal_xy": ("normal_x", "normal_y")}
+                 "normal_xy": ["k_normal2d_xy<double, false>"],
+                 "fused_x": ["k_fused2d<0, double, true, 16, 8>", "k_fused2d<0, double, false, 16, 8>"],
+                 "fused_y": ["k_fused2d<1, double, true, 128, 1>", "k_fused2d<1, double, false, 128, 1>"]}
+# a launch that does the work counted under several kinds (the work counts
+# come from the two-launch path, which counting mode runs: same arithmetic,
+# bitwise the same results)
+COMBINED = {"normal_xy": ("normal_x", "normal_y"), "fused_x": ("normal_x", "faces_x"),
+            "fused_y": ("normal_y", "faces_y")}
 COUNTERS = os.path.join(ROOT, "profiles", "stage_fp64_2048_counters.json")
 # Algorithmic HBM bytes per cell-stage of the two-stage update (read the
 # state once, write the outputs once; halos through caches): stage 1 reads
@@ -110,11 +115,18 @@ def algo_bytes(kind, work, launches, nx, ny):
     face-row values of every face in (160 B); out for each face it
     evaluates 16 values in stage 1 (F, dF/dt and the two interface fields)
     and 8 in stage 2 (dF/dt, W_tt*): 96 B on average over the two stages.
+    fused (normal step and faces of one direction in one launch): the
+    normal step's 16 B in per face-row entry and variable, the faces' outputs
+    (96 B per evaluated face on average); the face-row values stay on chip.
     slow: as faces for the queued faces, plus the queue index. update_1: W
     in, two faces' 12 planes (F, dF/dt, interface values at the stage time)
     in amortised to 192 B, W*, grad W*, R out: 352 B per cell; update_2: R
     in, 12 face planes (dF/dt*, W_tt*, stage-1 end-of-step values) amortised
     to 192 B, W and grad W out: 320 B per cell."""
+    if kind in ("fused_x", "fused_y"):
+        d = kind[-1]
+        return (16.0 * work.get("normal_" + d, {}).get("units", 0)
+                + 96.0 * work.get("faces_" + d, {}).get("units", 0))
     u = work.get(kind, {}).get("units", 0)
     if kind in ("normal_x", "normal_y"):
         return 56.0 * u
@@ -1001,22 +1013,29 @@ def main():
     ms_events = None
     if not args.no_kernel_timing:
         # 2) the same K steps again with start/stop events bound to every
-        # kernel dispatch (on the stream the kernels run on) and per-block
-        # work counting: per-kernel durations and work. The update is
-        # deterministic, so this replay reproduces the timed run exactly.
+        # kernel dispatch (on the stream the kernels run on): per-kernel
+        # durations. The update is deterministic, so this replay reproduces
+        # the timed run exactly.
         restart()
         G.timing_enable(16 * args.steps + 16)
-        G.count_enable(True)
         start.record(stream)
         G.gks_step(grid, Wd, dWd, ws, args.steps)
         end.record(stream)
         torch.cuda.synchronize()
         ms_events = start.elapsed_time(end)
         kt = G.timing_read()
-        work = G.work_read()
         G.timing_enable(0)
-        G.count_enable(False)
         assert np.array_equal(grid.interior(Wd), Wend), "replay differs from the timed run"
+        # 3) once more with per-block work counting (not timed). Counting
+        # runs the normal step as a launch of its own; the results are
+        # bitwise those of the fused launches.
+        restart()
+        G.count_enable(True)
+        G.gks_step(grid, Wd, dWd, ws, args.steps)
+        torch.cuda.synchronize()
+        work = G.work_read()
+        G.count_enable(False)
+        assert np.array_equal(grid.interior(Wd), Wend), "counted replay differs from the timed run"
 
     cell_stages = 2.0 * n * n * args.steps
     value = cell_stages / (ms / 1e3) / 1e6
@@ -1039,10 +1058,11 @@ def main():
     if kernels:
         # The unit of the algorithmic bytes is the cell-stage (one S2O4 stage
         # of one cell): the stage reads its state once and writes its outputs
-        # once. A stage is the sequence of launches normal_xy, faces_x,
-        # faces_y, slow, update; its duration is the sum of their average
-        # per-stage durations from the dispatch-bound events. achieved =
-        # 224 B x cells / stage duration.
+        # once. A stage is the sequence of launches fused_x, fused_y, slow,
+        # update (normal step and faces of each direction in one launch);
+        # its duration is the sum of their average per-stage durations from
+        # the dispatch-bound events. achieved = 224 B x cells / stage
+        # duration.
         nstage = 2.0 * args.steps
         stage_ms = sum(d["ms_total"] for d in kernels.values()) / nstage
         stage_bytes = ALGO_BYTES_CELL_STAGE["fp64"] * n * n
@@ -1068,7 +1088,8 @@ def main():
             if rows and all(r.get("valu_busy") is not None for r in rows):
                 vb = {"valu_busy": round(sum(r["valu_busy"] for r in rows) / len(rows), 4),
                       "valu_insts_per_wave": round(sum(r["valu_insts_per_wave"] for r in rows) / len(rows), 1)}
-        roofline = {"bound": "hbm", "kernel": "stage (normal_xy, faces_x, faces_y, slow, update)",
+        stage_kinds = [k for k in kernels if k != "init"]
+        roofline = {"bound": "hbm", "kernel": "stage (%s)" % ", ".join(stage_kinds),
                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(achieved / PEAK_HBM_GBS, 5),
                     "traffic": round(tsum) if tsum else None,

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GENO_ABI_VERSION 4
+#define GENO_ABI_VERSION 5
 
 /* error codes */
 #define GENO_OK 0
@@ -138,6 +138,12 @@ typedef struct geno_params {
   double eps_ulps;
   double gate_delta;
   int variables;   /* GENO_VARS_* */
+  int fuse;        /* 2-D gks_step: 1 (default) evaluates the normal step inside
+                      the face kernels, one per direction, so that the face-row
+                      values stay on chip; 0 runs it as a launch of its own that
+                      writes them to the workspace. Bitwise the same results.
+                      The learned gate, characteristic variables and work
+                      counting always take the separate launch. */
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */
@@ -457,6 +463,9 @@ enum {
   GENO_K_NORMAL_XY,    /* 2-D gks_step: normal GENO of both directions in one
                           launch (its work is counted under NORMAL_X and
                           NORMAL_Y) */
+  GENO_K_FUSED_X,      /* 2-D gks_step with params.fuse: normal GENO, tangential
+                          step and flux of the x-faces in one launch */
+  GENO_K_FUSED_Y,      /* the same for the y-faces */
   GENO_NKERNELS
 };
 

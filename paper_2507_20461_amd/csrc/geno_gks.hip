@@ -76,7 +76,8 @@ int g_tim_suspend = 0;   // set while a launch sequence is captured into a graph
 
 const char* const KNAMES[GENO_NKERNELS] = {"init",     "normal_x", "normal_y", "faces_x",
                                            "faces_y",  "slow",     "update_1", "update_2",
-                                           "faces_1d", "gate",     "normal_xy"};
+                                           "faces_1d", "gate",     "normal_xy",
+                                           "fused_x",  "fused_y"};
 
 // Every launch goes through here: a kernel of kind >= 0 is timed while
 // timing is enabled (events bound to the dispatch itself).
@@ -643,38 +644,73 @@ struct FaceGeo {
   }
 };
 
-template <int DIR, int MODE, typename T>
-__device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
-                                          const double* __restrict__ W,
-                                          const T* __restrict__ fr, T* __restrict__ out,
+// What the tangential step of one face side reads, through an accessor:
+// v(i, f), d(i, f) the side's value and h-scaled normal derivative of
+// variable f on the face rows t-1, t, t+1 (i = 0, 1, 2), h2(f) the normal
+// step's two-side mean of h^2 d^2/dn^2 on row t. Each element is read where
+// it is used.
+// From the face-row buffer (layout of normal_body).
+template <typename T>
+struct RowsMem {
+  const T* fr;
+  size_t plane, r[3];
+  int q;
+  __device__ T v(int i, int f) const { return fr[(size_t)((2 * q + 0) * 4 + f) * plane + r[i]]; }
+  __device__ T d(int i, int f) const { return fr[(size_t)((2 * q + 1) * 4 + f) * plane + r[i]]; }
+  __device__ T h2(int f) const { return fr[(size_t)(16 + f) * plane + r[1]]; }
+};
+// From LDS: element (i, quantity, f) at p[o[i] + (quantity * 4 + f) * st],
+// h2(f) at p[oh + f * st].
+template <typename T>
+struct RowsLds {
+  const T* p;
+  int o[3], oh, st;
+  __device__ T v(int i, int f) const { return p[o[i] + f * st]; }
+  __device__ T d(int i, int f) const { return p[o[i] + (4 + f) * st]; }
+  __device__ T h2(int f) const { return p[oh + f * st]; }
+};
+
+// Face-row offsets of face (a, b): rows t-1, t, t+1 of its side data.
+template <int DIR>
+struct FaceRows {
+  size_t plane, rm, rc, rp;
+  __device__ FaceRows(const FaceGeo<DIR>& fg, int a, int b) {
+    plane = (size_t)fg.r0 * fg.r1;
+    rm = (size_t)a * fg.r1 + b;
+    rc = DIR == 0 ? rm + fg.r1 : rm + 1;
+    rp = DIR == 0 ? rc + fg.r1 : rc + 1;
+  }
+};
+
+// The face step of lane q of a pair from its side's rows sr. Returns true
+// (MODE 1) when the face is valid and was queued for the full solution.
+template <int DIR, int MODE, typename T, typename Rows>
+__device__ __forceinline__ bool face_core(const Geo& g, const geno::KParams& k,
+                                          const double* __restrict__ W, T* __restrict__ out,
                                           Ctrl* ctrl, int want_F, unsigned int (&wc)[GENO_NCLASS],
-                                          int face, bool valid, unsigned int* __restrict__ queue) {
+                                          int face, bool valid, unsigned int* __restrict__ queue,
+                                          const Rows& sr) {
   const FaceGeo<DIR> fg(g);
   const int q = threadIdx.x & 1;
   const int nfaces = fg.n0 * fg.n1;
   const int fc = valid ? face : nfaces - 1;
   const int a = fc / fg.n1, b = fc % fg.n1;
-  const size_t rplane = (size_t)fg.r0 * fg.r1;
-  const size_t rm = (size_t)a * fg.r1 + b;
-  const size_t rc = DIR == 0 ? rm + fg.r1 : rm + 1;
-  const size_t rp = DIR == 0 ? rc + fg.r1 : rc + 1;
   // tangential step of side q for both points, and the side's second
   // tangential and cross derivatives
   T own_v[4], own_t[4], snd_v[4], snd_t[4], dn[4], s_tt[4], s_nt[4];
   unsigned int nlow = 0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const T* p = fr + (size_t)((2 * q + 0) * 4 + v) * rplane;
-    const T* pd = fr + (size_t)((2 * q + 1) * 4 + v) * rplane;
     T v0, v1, t0, t1, cht, d2;
-    nlow += geno::tangential<T, double>(p[rm], p[rc], p[rp], k, v0, v1, t0, t1, cht, d2);
+    nlow += geno::tangential<T, double>(sr.v(0, v), sr.v(1, v), sr.v(2, v), k, v0, v1, t0, t1,
+                                        cht, d2);
     own_v[v] = q ? v1 : v0;
     own_t[v] = q ? t1 : t0;
     snd_v[v] = q ? v0 : v1;
     snd_t[v] = q ? t0 : t1;
-    dn[v] = pd[rc];
+    dn[v] = sr.d(1, v);
     s_tt[v] = cht * d2;
-    s_nt[v] = cht * (T(0.5) * (pd[rp] - pd[rm]));
+    s_nt[v] = cht * (T(0.5) * (sr.d(2, v) - sr.d(0, v)));
   }
   // states of both sides at this lane's point
   T S[2][4], Dn[2][4], Dt[2][4];
@@ -712,12 +748,13 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   T s_nn[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    s_nn[v] = nguard ? T(0) : fr[(size_t)(16 + v) * rplane + rc];
+    s_nn[v] = nguard ? T(0) : sr.h2(v);
     if (nguard) s_tt[v] = s_nt[v] = T(0);
   }
   if (!valid) nguard = nlow = 0;
   const size_t plane = (size_t)nfaces;
   const size_t o = (size_t)fc;
+  bool queued = false;
   if constexpr (MODE == 0) {
     if (valid) {
 #pragma unroll
@@ -785,6 +822,7 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
         const unsigned int rank = (unsigned int)__popcll(m & ((1ull << (threadIdx.x & 63)) - 1));
         queue[base + rank] = (unsigned int)face;
       }
+      queued = valid && pair_slow;
     }
     if (nguard && (MODE == 2 || !pair_slow)) atomicAdd(&ctrl->guard, (unsigned long long)nguard);
     // this point's share of the Gauss average (weights 1/2) of the stage's
@@ -835,6 +873,47 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
     wc[GENO_W_LOW] += ev ? nlow : 0u;
     wc[GENO_W_GUARD] += ev ? nguard : 0u;
   }
+  return queued;
+}
+
+// A queued face's rows into the face-row buffer fr (layout of normal_body),
+// where the queue kernel reads them; neighbouring queued faces write equal
+// values to the entries they share. Called after face_core so that the rows
+// are read again from LDS here, not held in registers through the flux.
+template <int DIR, typename T, typename Rows>
+__device__ __forceinline__ void spill_rows(const Geo& g, int face, const Rows& sr,
+                                           T* __restrict__ fr) {
+  const FaceGeo<DIR> fg(g);
+  const int q = threadIdx.x & 1;
+  const FaceRows<DIR> fw(fg, face / fg.n1, face % fg.n1);
+  const size_t rr[3] = {fw.rm, fw.rc, fw.rp};
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      fr[(size_t)((2 * q + 0) * 4 + v) * fw.plane + rr[i]] = sr.v(i, v);
+      fr[(size_t)((2 * q + 1) * 4 + v) * fw.plane + rr[i]] = sr.d(i, v);
+    }
+  if (q == 0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fr[(size_t)(16 + v) * fw.plane + fw.rc] = sr.h2(v);
+}
+
+// The face step of lane q with its side's rows read from the face-row
+// buffer fr.
+template <int DIR, int MODE, typename T>
+__device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
+                                          const double* __restrict__ W,
+                                          const T* __restrict__ fr, T* __restrict__ out,
+                                          Ctrl* ctrl, int want_F, unsigned int (&wc)[GENO_NCLASS],
+                                          int face, bool valid, unsigned int* __restrict__ queue) {
+  const FaceGeo<DIR> fg(g);
+  const int q = threadIdx.x & 1;
+  const int nfaces = fg.n0 * fg.n1;
+  const int fc = valid ? face : nfaces - 1;
+  const FaceRows<DIR> fw(fg, fc / fg.n1, fc % fg.n1);
+  const RowsMem<T> sr{fr, fw.plane, {fw.rm, fw.rc, fw.rp}, q};
+  face_core<DIR, MODE, T>(g, k, W, out, ctrl, want_F, wc, face, valid, queue, sr);
 }
 
 template <int DIR, int MODE, typename T>
@@ -929,6 +1008,163 @@ __global__ void __launch_bounds__(BLOCK) k_slow2d(Geo g, geno::KParams k,
                                                   const unsigned int* __restrict__ qy) {
   slow_body<T>(g, k, W, frx, fry, outx, outy, ctrl, WF ? 1 : 0, cnt, qx, qy, (int)blockIdx.x,
                (int)gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Face step with the normal step on chip (2-D gks_step, conservative
+// variables): the face-row values a face needs are computed by the kernel
+// that uses them, so the face-row buffer makes no round trip through HBM.
+// The arithmetic is that of normal_body and face_pair, so the results are
+// bitwise those of the two-launch path.
+// ---------------------------------------------------------------------------
+// Normal GENO of face-row entry (a, b) (indexing of normal_body) by a lane
+// pair: lane q reconstructs variables 2q and 2q+1 (both sides), then the two
+// lanes exchange halves so that lane q holds side q of all four variables
+// (v, d: value and h-scaled normal derivative) and the two-side mean h2.
+template <int DIR, typename T>
+__device__ __forceinline__ void normal_pair(const Geo& g, const geno::KParams& k,
+                                            const double* __restrict__ W,
+                                            const T* __restrict__ dW, int a, int b, int q,
+                                            T (&v)[4], T (&d)[4], T (&h2)[4]) {
+  const double h = DIR == 0 ? g.dx : g.dy;
+  T sv[2][2], sd[2][2], sh[2];   // [variable 2q + i][side]
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int var = 2 * q + i;
+    double Q[4], G[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      size_t id;
+      if (DIR == 0) id = at(g, var, a - 1, b - 2 + m);
+      else id = at(g, var, a - 2 + m, b - 1);
+      Q[m] = W[id];
+      G[m] = h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+    }
+    T vl, dl, vr, dr, hh;
+    double xl, xr;
+    geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl, xl, vr,
+                               dr, xr, hh);
+    sv[i][0] = vl;
+    sd[i][0] = dl;
+    sv[i][1] = vr;
+    sd[i][1] = dr;
+    sh[i] = hh;
+  }
+  // keep side q of the own variables, send side 1 - q to the partner
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const T kv = q ? sv[i][1] : sv[i][0], kd = q ? sd[i][1] : sd[i][0];
+    const T rv = pair_swap(q ? sv[i][0] : sv[i][1]);
+    const T rd = pair_swap(q ? sd[i][0] : sd[i][1]);
+    const T rh = pair_swap(sh[i]);
+    v[i] = q ? rv : kv;
+    d[i] = q ? rd : kd;
+    h2[i] = q ? rh : sh[i];
+    v[2 + i] = q ? kv : rv;
+    d[2 + i] = q ? kd : rd;
+    h2[2 + i] = q ? sh[i] : rh;
+  }
+}
+
+// One work-group per tile of NT x NN face-row entries, NT along the
+// tangential direction of the faces and NN across it (x-faces: NT rows by NN
+// face columns; y-faces: NT columns of one face row, NN = 1). Every lane pair
+// reconstructs one entry into LDS; after a barrier the pairs of the first
+// NT - 2 tangential positions each evaluate the face whose three rows t,
+// t+1, t+2 are in the tile. Neighbouring tiles overlap by two entries along
+// the tangential direction (recomputed, 2/NT of the normal step). Entry e =
+// t NN + u, u fastest, so that a wave's loads run along x. nbu: tiles across
+// the tangential direction; a work-group takes tile (bt, bu) = (blk / nbu,
+// blk % nbu).
+template <int DIR, int NT, int NN>
+struct FusedTile {
+  static constexpr int NE = NT * NN;              // entries (lane pairs)
+  static constexpr int BS = 2 * NE;               // work-group size
+  static constexpr int SS = 8 * NE + 1;           // LDS side stride (padded)
+  static constexpr int LDS = 2 * SS + 4 * NE;     // elements of T
+};
+template <int DIR, typename T, bool WF, int NT, int NN>
+// (stage 2: at most 4 waves per SIMD for the y tile, 3 for the x tile, the
+// faster of the two caps for each)
+__global__ void __launch_bounds__(2 * NT * NN)
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 ? 2 : 4))))
+k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restrict__ dW,
+          T* __restrict__ fr, T* __restrict__ out, Ctrl* ctrl, unsigned int* __restrict__ queue,
+          int nbu) {
+  using TL = FusedTile<DIR, NT, NN>;
+  // [side][quantity (value, h d/dn)][variable][entry], the side stride padded
+  // against bank conflicts between the two lanes of a pair; then h2
+  // [variable][entry]
+  __shared__ T lds[TL::LDS];
+  const int blk = xcd_block();
+  const int bt = blk / nbu, bu = blk % nbu;
+  const int q = threadIdx.x & 1, p = (int)(threadIdx.x >> 1);
+  const int t = p / NN, u = p % NN;
+  // entry (t, u) of the tile: face-row indices (a, b) of normal_body, and the
+  // largest in-range ones
+  int ea, eb, amax, bmax;
+  if (DIR == 0) {
+    ea = bt * (NT - 2) + t;   // face row of the entry (cell row ea - 1)
+    eb = bu * NN + u;         // face column
+    amax = g.ny + 1;
+    bmax = g.nx;
+  } else {
+    ea = bu;                  // face row (NN = 1: one face row per tile)
+    eb = bt * (NT - 2) + t;   // column of the entry (cell column eb - 1)
+    amax = g.ny;
+    bmax = g.nx + 1;
+  }
+  const bool need = ea <= amax && eb <= bmax;
+  if (__ballot(need)) {   // whole waves out of the grid skip the normal step
+    T v[4], d[4], h2[4];
+    normal_pair<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      lds[q * TL::SS + (0 * 4 + f) * TL::NE + p] = v[f];
+      lds[q * TL::SS + (1 * 4 + f) * TL::NE + p] = d[f];
+    }
+    if (q == 0)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) lds[2 * TL::SS + f * TL::NE + p] = h2[f];
+  }
+  __syncthreads();
+  // the face of this pair: rows t, t+1, t+2 of its tangential line
+  int fa, fb;
+  bool valid;
+  if (DIR == 0) {
+    fa = ea;
+    fb = eb;
+    valid = t < NT - 2 && fa < g.ny && fb <= g.nx;
+  } else {
+    fa = ea;
+    fb = eb;
+    valid = t < NT - 2 && fb < g.nx;
+  }
+  if (!__ballot(valid)) return;   // no face in this wave (no barrier follows)
+  const int pc = valid ? p : u;   // an invalid pair reads entries of row 0
+  const RowsLds<T> sr{lds, {q * TL::SS + pc, q * TL::SS + pc + NN, q * TL::SS + pc + 2 * NN},
+                      2 * TL::SS + pc + NN, TL::NE};
+  const FaceGeo<DIR> fg(g);
+  const int face = valid ? fa * fg.n1 + fb : 0;
+  unsigned int wc[GENO_NCLASS] = {};
+  const bool queued = face_core<DIR, 1, T>(g, k, W, out, ctrl, WF ? 1 : 0, wc, face, valid, queue, sr);
+  // the rows are read from LDS again for the spill
+  asm volatile("" ::: "memory");
+  if (queued) spill_rows<DIR, T>(g, face, sr, fr);
+}
+// tile shapes
+// (measured at 2048^2: 16 x 8 beat 32 x 8, 32 x 4, 64 x 4, 64 x 8 and 128 x 2
+// for the x-faces, 128 beat 64 and 256 for the y-faces)
+constexpr int FX_NT = 16, FX_NN = 8;    // x-faces: 16 rows x 8 face columns, 256 lanes
+constexpr int FY_NT = 128, FY_NN = 1;   // y-faces: 128 columns of one face row, 256 lanes
+
+// Before the face kernels of a stage: the step's dt from the CFL partial
+// minima (stage 1) and empty face queues.
+__global__ void __launch_bounds__(BLOCK) k_stage_prep(const double* __restrict__ part, int npart,
+                                                      Ctrl* ctrl, double cfl, double dt_fixed,
+                                                      double* dt_out, int step) {
+  if (part) reduce_dt(part, npart, ctrl, cfl, dt_fixed, dt_out, step);
+  if (threadIdx.x < 2) ctrl->qcount[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1877,6 +2113,7 @@ int check_params(const geno_params* p) {
     return fail(GENO_EINVAL, "periodic boundaries must be set on both sides of an axis");
   if (p->variables != GENO_VARS_CONSERVATIVE && p->variables != GENO_VARS_CHARACTERISTIC)
     return fail(GENO_EINVAL, "bad variables code %d", p->variables);
+  if (p->fuse != 0 && p->fuse != 1) return fail(GENO_EINVAL, "fuse must be 0 or 1");
   return GENO_OK;
 }
 
@@ -2062,6 +2299,31 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
       gx = B.gate;
       gy = B.gate + nc;
     }
+    if (g->params.fuse && !k.gate && !k.charvars && !cnt.p) {
+      HIP_TRY(launch(-1, k_stage_prep, 1, s, part, npart, B.ctrl, k.cfl, k.dt_fixed, dt_out,
+                     step));
+      using TX = FusedTile<0, FX_NT, FX_NN>;
+      using TY = FusedTile<1, FY_NT, FY_NN>;
+      const int nbux = (g->nx + 1 + FX_NN - 1) / FX_NN;
+      const unsigned nbx = (unsigned)((size_t)nbux * ((g->ny + FX_NT - 3) / (FX_NT - 2)));
+      const int nbuy = g->ny + 1;
+      const unsigned nby = (unsigned)((size_t)nbuy * ((g->nx + FY_NT - 3) / (FY_NT - 2)));
+      if (want_F) {
+        HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, true, FX_NT, FX_NN>, nbx, TX::BS, s, geo,
+                          k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0], nbux));
+        HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, true, FY_NT, FY_NN>, nby, TY::BS, s, geo,
+                          k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1], nbuy));
+        HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, true>, slow_blocks(g), s, geo, k, Win, B.fr[0],
+                       B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
+      } else {
+        HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, false, FX_NT, FX_NN>, nbx, TX::BS, s,
+                          geo, k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0], nbux));
+        HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, false, FY_NT, FY_NN>, nby, TY::BS, s,
+                          geo, k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1], nbuy));
+        HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, false>, slow_blocks(g), s, geo, k, Win, B.fr[0],
+                       B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
+      }
+    } else {
     const unsigned nnx = nblocks(normal_threads(g, 0)), nny = nblocks(normal_threads(g, 1));
     if (k.charvars)
       HIP_TRY(launch(GENO_K_NORMAL_XY, k_normal2d_xy<T, true>, nnx + nny, s, geo, k, Win, dWin,
@@ -2083,6 +2345,7 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
                      geo, k, Win, B.fr[1], B.fl[1], B.ctrl, cnt, B.queue[1]));
       HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, false>, slow_blocks(g), s, geo, k, Win, B.fr[0],
                      B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
+    }
     }
   } else {
     if (part)
@@ -2816,6 +3079,7 @@ int geno_params_default(geno_params* p) {
   p->cfl = 0.5;
   for (int i = 0; i < 4; ++i) p->bc[i] = GENO_BC_TRANSMISSIVE;
   p->eps_ulps = 64.0;
+  p->fuse = 1;
   return GENO_OK;
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libgeno_gks.so")
 GENO_OK, GENO_EINVAL, GENO_EVERSION, GENO_EHIP, GENO_ENONPHYS = 0, -1, -2, -3, -4
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTING, BC_FIXED = 0, 1, 2, 3
 F64, MIXED = 0, 1
-ABI_VERSION = 4
+ABI_VERSION = 5
 NG = 2
 VARS_CONSERVATIVE, VARS_CHARACTERISTIC = 0, 1
 
@@ -30,7 +30,7 @@ class geno_params(ctypes.Structure):
                 ("rL", ctypes.c_double), ("d", ctypes.c_double * 3), ("tau_c1", ctypes.c_double),
                 ("tau_c2", ctypes.c_double), ("cfl", ctypes.c_double), ("bc", ctypes.c_int * 4),
                 ("dt_fixed", ctypes.c_double), ("eps_ulps", ctypes.c_double), ("gate_delta", ctypes.c_double),
-                ("variables", ctypes.c_int)]
+                ("variables", ctypes.c_int), ("fuse", ctypes.c_int)]
 
 
 class geno_grid(ctypes.Structure):
@@ -62,7 +62,7 @@ EXPORTS = ("geno_abi_version", "geno_last_error", "geno_params_default", "geno_g
            "geno_mlp_adam", "geno_mlp_forward", "geno_mlp_load", "geno_mlp_infer", "geno_gate_prob",
            "geno_conserved_totals", "geno_linearity", "geno_batched_graphs_built")
 KERNELS = ("init", "normal_x", "normal_y", "faces_x", "faces_y", "slow", "update_1", "update_2", "faces_1d",
-           "gate", "normal_xy")
+           "gate", "normal_xy", "fused_x", "fused_y")
 WORK_CLASSES = ("units", "equal", "low", "fast", "slow", "guard", "gated")
 MLP_NIN, MLP_NPARAM = 40, 6849
 
