@@ -36,6 +36,7 @@ struct KParams {
   double gate_thr;    // learned gate: a prediction >= gate_thr sets chi = 1
   int gate;           // learned gate enabled
   int charvars;       // reconstruct characteristic variables in the normal step
+  int fuse;           // 2-D steps: normal step inside the face kernels (host side)
 };
 
 // Path function chi = tanh(C alpha)/tanh(C) (Eq. (4)) of the ultimate

@@ -684,7 +684,9 @@ struct FaceRows {
 
 // The face step of lane q of a pair from its side's rows sr. Returns true
 // (MODE 1) when the face is valid and was queued for the full solution.
-template <int DIR, int MODE, typename T, typename Rows>
+// NTS: flux outputs written with non-temporal stores (streamed past the
+// caches to the update that reads them).
+template <int DIR, int MODE, typename T, typename Rows, bool NTS = true>
 __device__ __forceinline__ bool face_core(const Geo& g, const geno::KParams& k,
                                           const double* __restrict__ W, T* __restrict__ out,
                                           Ctrl* ctrl, int want_F, unsigned int (&wc)[GENO_NCLASS],
@@ -854,12 +856,17 @@ __device__ __forceinline__ bool face_core(const Geo& g, const geno::KParams& k,
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int pv = perm[v];
+        auto put = [&](int kind, T x) {
+          T* dst = &out[(size_t)(kind * 4 + pv) * plane + o];
+          if constexpr (NTS) __builtin_nontemporal_store(x, dst);
+          else *dst = x;
+        };
         if (q == 0) {
-          if (want_F) __builtin_nontemporal_store(So[v], &out[(size_t)(0 * 4 + pv) * plane + o]);
-          __builtin_nontemporal_store(So[4 + v], &out[(size_t)(1 * 4 + pv) * plane + o]);
+          if (want_F) put(0, So[v]);
+          put(1, So[4 + v]);
         } else {
-          __builtin_nontemporal_store(So[8 + v], &out[(size_t)(2 * 4 + pv) * plane + o]);
-          if (want_F) __builtin_nontemporal_store(So[12 + v], &out[(size_t)(3 * 4 + pv) * plane + o]);
+          put(2, So[8 + v]);
+          if (want_F) put(3, So[12 + v]);
         }
       }
     }
@@ -1079,24 +1086,23 @@ __device__ __forceinline__ void normal_pair(const Geo& g, const geno::KParams& k
 template <int DIR, int NT, int NN>
 struct FusedTile {
   static constexpr int NE = NT * NN;              // entries (lane pairs)
-  static constexpr int BS = 2 * NE;               // work-group size
+  static constexpr int BS = (2 * NE + 63) / 64 * 64;   // work-group size (whole waves)
   static constexpr int SS = 8 * NE + 1;           // LDS side stride (padded)
   static constexpr int LDS = 2 * SS + 4 * NE;     // elements of T
 };
-template <int DIR, typename T, bool WF, int NT, int NN>
 // (stage 2: at most 4 waves per SIMD for the y tile, 3 for the x tile, the
 // faster of the two caps for each)
-__global__ void __launch_bounds__(2 * NT * NN)
-__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 ? 2 : 4))))
-k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restrict__ dW,
-          T* __restrict__ fr, T* __restrict__ out, Ctrl* ctrl, unsigned int* __restrict__ queue,
-          int nbu) {
+template <int DIR, typename T, bool WF, int NT, int NN>
+__device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
+                                           const double* __restrict__ W,
+                                           const T* __restrict__ dW, T* __restrict__ fr,
+                                           T* __restrict__ out, Ctrl* ctrl,
+                                           unsigned int* __restrict__ queue, int nbu, int blk) {
   using TL = FusedTile<DIR, NT, NN>;
   // [side][quantity (value, h d/dn)][variable][entry], the side stride padded
   // against bank conflicts between the two lanes of a pair; then h2
   // [variable][entry]
   __shared__ T lds[TL::LDS];
-  const int blk = xcd_block();
   const int bt = blk / nbu, bu = blk % nbu;
   const int q = threadIdx.x & 1, p = (int)(threadIdx.x >> 1);
   const int t = p / NN, u = p % NN;
@@ -1114,16 +1120,19 @@ k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restr
     amax = g.ny;
     bmax = g.nx + 1;
   }
-  const bool need = ea <= amax && eb <= bmax;
+  // (lanes past the tile's entries, in a last partial wave, only take part)
+  const bool need = p < TL::NE && ea <= amax && eb <= bmax;
   if (__ballot(need)) {   // whole waves out of the grid skip the normal step
     T v[4], d[4], h2[4];
     normal_pair<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
+    if (p < TL::NE) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      lds[q * TL::SS + (0 * 4 + f) * TL::NE + p] = v[f];
-      lds[q * TL::SS + (1 * 4 + f) * TL::NE + p] = d[f];
+      for (int f = 0; f < 4; ++f) {
+        lds[q * TL::SS + (0 * 4 + f) * TL::NE + p] = v[f];
+        lds[q * TL::SS + (1 * 4 + f) * TL::NE + p] = d[f];
+      }
     }
-    if (q == 0)
+    if (q == 0 && p < TL::NE)
 #pragma unroll
       for (int f = 0; f < 4; ++f) lds[2 * TL::SS + f * TL::NE + p] = h2[f];
   }
@@ -1147,20 +1156,46 @@ k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restr
   const FaceGeo<DIR> fg(g);
   const int face = valid ? fa * fg.n1 + fb : 0;
   unsigned int wc[GENO_NCLASS] = {};
-  const bool queued = face_core<DIR, 1, T>(g, k, W, out, ctrl, WF ? 1 : 0, wc, face, valid, queue, sr);
+  // (the x tile writes 64-byte pieces of each face row: in the mixed form
+  // plain stores, which the L2 merges, were faster; in FP64 and for the
+  // y-faces non-temporal ones)
+  constexpr bool NTS = sizeof(T) == 8 || DIR == 1;
+  const bool queued = face_core<DIR, 1, T, RowsLds<T>, NTS>(g, k, W, out, ctrl, WF ? 1 : 0, wc,
+                                                           face, valid, queue, sr);
   // the rows are read from LDS again for the spill
   asm volatile("" ::: "memory");
   if (queued) spill_rows<DIR, T>(g, face, sr, fr);
+}
+
+template <int DIR, typename T, bool WF, int NT, int NN>
+__global__ void __launch_bounds__((2 * NT * NN + 63) / 64 * 64)
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 ? 2 : 4))))
+k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restrict__ dW,
+          T* __restrict__ fr, T* __restrict__ out, Ctrl* ctrl, unsigned int* __restrict__ queue,
+          int nbu) {
+  fused_body<DIR, T, WF, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block());
 }
 // tile shapes
 // (measured at 2048^2: 16 x 8 beat 32 x 8, 32 x 4, 64 x 4, 64 x 8 and 128 x 2
 // for the x-faces, 128 beat 64 and 256 for the y-faces)
 constexpr int FX_NT = 16, FX_NN = 8;    // x-faces: 16 rows x 8 face columns, 256 lanes
 constexpr int FY_NT = 128, FY_NN = 1;   // y-faces: 128 columns of one face row, 256 lanes
+constexpr int FX_BS = FusedTile<0, FX_NT, FX_NN>::BS;
+constexpr int FY_BS = FusedTile<1, FY_NT, FY_NN>::BS;
+// work-groups of the fused launches of a grid, and their tiles across the
+// tangential direction
+int fused_nbu(const Geo& g, int dir) {
+  return dir == 0 ? (g.nx + 1 + FX_NN - 1) / FX_NN : g.ny + 1;
+}
+unsigned fused_blocks(const Geo& g, int dir) {
+  const size_t nt = dir == 0 ? (size_t)(g.ny + FX_NT - 3) / (FX_NT - 2)
+                             : (size_t)(g.nx + FY_NT - 3) / (FY_NT - 2);
+  return (unsigned)(nt * fused_nbu(g, dir));
+}
 
 // Before the face kernels of a stage: the step's dt from the CFL partial
 // minima (stage 1) and empty face queues.
-__global__ void __launch_bounds__(BLOCK) k_stage_prep(const double* __restrict__ part, int npart,
+__global__ void __launch_bounds__(1024) k_stage_prep(const double* __restrict__ part, int npart,
                                                       Ctrl* ctrl, double cfl, double dt_fixed,
                                                       double* dt_out, int step) {
   if (part) reduce_dt(part, npart, ctrl, cfl, dt_fixed, dt_out, step);
@@ -1787,7 +1822,11 @@ __global__ void __launch_bounds__(BLOCK) k_harvest(Geo g, geno::KParams k,
 // neighbouring ranges of one or a few grids. Work-group size BS is a template
 // parameter chosen per kind by the caller (autotuned).
 // ---------------------------------------------------------------------------
-enum { BK_INIT = 0, BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE, BK_N };
+enum {
+  BK_INIT = 0, BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE,
+  BK_FUSED_X, BK_FUSED_Y, BK_PREP,   // the fused stage: prep, fused x, fused y, slow, update
+  BK_N
+};
 
 struct BEntry {
   Geo geo;
@@ -1803,6 +1842,7 @@ struct BEntry {
   void* fl[2];
   int npart;     // update work-groups of this grid (CFL partials)
   int slow_nb;   // work-groups serving this grid in the tau > 0 launch
+  int fnbu[2];   // fused launches: tiles across the tangential direction
 };
 
 // index of the grid whose range [start[g], start[g+1]) holds global work-group gb
@@ -1882,6 +1922,35 @@ __global__ void __launch_bounds__(BS) kb_update(const BEntry* __restrict__ tab,
   else
     update_body<2, 2, T>(e.geo, k, e.wst, e.W, (T*)e.dW, e.r, (const T*)e.fl[0],
                          (const T*)e.fl[1], e.ctrl, e.part, cnt, gb - st[gi]);
+}
+
+// The fused face step of a batch (the normal step inside the face kernels):
+// kb_prep, one work-group per grid, then kb_fused per direction.
+template <typename T>
+__global__ void __launch_bounds__(1024) kb_prep(const BEntry* __restrict__ tab, geno::KParams k,
+                                                int stage) {
+  const BEntry& e = tab[blockIdx.x];
+  if (stage == 1) reduce_dt(e.part, e.npart, e.ctrl, k.cfl, k.dt_fixed, nullptr, 0);
+  if (threadIdx.x < 2) e.ctrl->qcount[threadIdx.x] = 0;
+}
+
+template <int DIR, typename T, bool WF>
+__global__ void __launch_bounds__(DIR == 0 ? FX_BS : FY_BS)
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 ? 2 : 4))))
+kb_fused(const BEntry* __restrict__ tab, const int* __restrict__ offs, int ngrids,
+         geno::KParams k) {
+  const int* st = offs + (DIR == 0 ? BK_FUSED_X : BK_FUSED_Y) * (ngrids + 1);
+  const int gb = xcd_block();
+  const int gi = find_grid(st, ngrids, gb);
+  const BEntry& e = tab[gi];
+  const double* W = WF ? e.W : e.wst;
+  const T* dW = (const T*)(WF ? e.dW : e.dwst);
+  if (DIR == 0)
+    fused_body<0, T, WF, FX_NT, FX_NN>(e.geo, k, W, dW, (T*)e.fr[0], (T*)e.fl[0], e.ctrl,
+                                       e.queue[0], e.fnbu[0], gb - st[gi]);
+  else
+    fused_body<1, T, WF, FY_NT, FY_NN>(e.geo, k, W, dW, (T*)e.fr[1], (T*)e.fl[1], e.ctrl,
+                                       e.queue[1], e.fnbu[1], gb - st[gi]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2165,6 +2234,7 @@ geno::KParams kparams(const geno_grid* g) {
   k.gate = (p.gate_delta > 0.0 && g->ndim == 2) ? 1 : 0;
   k.gate_thr = 1.0 - p.gate_delta;
   k.charvars = p.variables == GENO_VARS_CHARACTERISTIC ? 1 : 0;
+  k.fuse = p.fuse;
   return k;
 }
 
@@ -2299,15 +2369,13 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
       gx = B.gate;
       gy = B.gate + nc;
     }
-    if (g->params.fuse && !k.gate && !k.charvars && !cnt.p) {
-      HIP_TRY(launch(-1, k_stage_prep, 1, s, part, npart, B.ctrl, k.cfl, k.dt_fixed, dt_out,
-                     step));
+    if (k.fuse && !k.gate && !k.charvars && !cnt.p) {
+      HIP_TRY(launch_bs(-1, k_stage_prep, 1, 1024, s, part, npart, B.ctrl, k.cfl, k.dt_fixed,
+                        dt_out, step));
       using TX = FusedTile<0, FX_NT, FX_NN>;
       using TY = FusedTile<1, FY_NT, FY_NN>;
-      const int nbux = (g->nx + 1 + FX_NN - 1) / FX_NN;
-      const unsigned nbx = (unsigned)((size_t)nbux * ((g->ny + FX_NT - 3) / (FX_NT - 2)));
-      const int nbuy = g->ny + 1;
-      const unsigned nby = (unsigned)((size_t)nbuy * ((g->nx + FY_NT - 3) / (FY_NT - 2)));
+      const int nbux = fused_nbu(geo, 0), nbuy = fused_nbu(geo, 1);
+      const unsigned nbx = fused_blocks(geo, 0), nby = fused_blocks(geo, 1);
       if (want_F) {
         HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, true, FX_NT, FX_NN>, nbx, TX::BS, s, geo,
                           k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0], nbux));
@@ -2485,7 +2553,7 @@ bool same_method(const geno_params& a, const geno_params& b) {
          a.C == b.C && a.eps == b.eps && a.r == b.r && a.rL == b.rL && a.d[0] == b.d[0] &&
          a.d[1] == b.d[1] && a.d[2] == b.d[2] && a.tau_c1 == b.tau_c1 &&
          a.tau_c2 == b.tau_c2 && a.cfl == b.cfl && a.dt_fixed == b.dt_fixed &&
-         a.eps_ulps == b.eps_ulps && a.variables == b.variables;
+         a.eps_ulps == b.eps_ulps && a.variables == b.variables && a.fuse == b.fuse;
 }
 
 // devices on which a network has been loaded (geno_mlp_load)
@@ -2533,6 +2601,9 @@ int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPl
   P->bs[BK_NORMAL_X] = P->bs[BK_NORMAL_Y] = t.block_normal;
   P->bs[BK_FACES_X] = P->bs[BK_FACES_Y] = t.block_faces;
   P->bs[BK_SLOW] = t.block_slow;
+  P->bs[BK_FUSED_X] = FX_BS;
+  P->bs[BK_FUSED_Y] = FY_BS;
+  P->bs[BK_PREP] = 1024;
   P->offs.assign((size_t)BK_N * (ngrids + 1), 0);
   P->tab.assign(ngrids, BEntry{});
   P->goff.assign(ngrids, 0);
@@ -2556,7 +2627,10 @@ int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPl
         nblocks_bs(2 * faces_of(g, 1), t.block_faces),
         std::min<long long>(1024, std::max<long long>(1, (long long)((f + t.slow_faces_per_block - 1) /
                                                                   t.slow_faces_per_block))),
-        nblocks_bs(ncell, t.block_update)};
+        nblocks_bs(ncell, t.block_update),
+        fused_blocks(geo_of(g), 0),
+        fused_blocks(geo_of(g), 1),
+        1};
     for (int k = 0; k < BK_N; ++k) {
       P->offs[(size_t)k * (ngrids + 1) + i] = (int)cnt[k];
       cnt[k] += nbk[k];
@@ -2569,6 +2643,8 @@ int plan_batch(int ngrids, const geno_grid* grids, const geno_tuning& t, BatchPl
     e.geo = geo_of(g);
     e.npart = (int)nbk[BK_UPDATE];
     e.slow_nb = (int)nbk[BK_SLOW];
+    e.fnbu[0] = fused_nbu(e.geo, 0);
+    e.fnbu[1] = fused_nbu(e.geo, 1);
   }
   for (int k = 0; k < BK_N; ++k) {
     P->offs[(size_t)k * (ngrids + 1) + ngrids] = (int)cnt[k];
@@ -2674,9 +2750,25 @@ hipError_t go_phase(int phase, const BatchPlan& P, const BEntry* tab, const int*
 template <typename T>
 int batch_step(const BatchPlan& P, const BEntry* tab, const int* offs, const geno::KParams& k,
                const Cnt& cnt, hipStream_t s) {
-  for (int stage = 1; stage <= 2; ++stage)
-    for (int phase : {BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE})
-      HIP_TRY(go_phase<T>(phase, P, tab, offs, k, stage, cnt, s));
+  const int ng = P.ngrids;
+  const bool fused = k.fuse && !k.charvars && !cnt.p;
+  for (int stage = 1; stage <= 2; ++stage) {
+    if (fused) {
+      using TX = FusedTile<0, FX_NT, FX_NN>;
+      using TY = FusedTile<1, FY_NT, FY_NN>;
+      const bool wf = stage == 1;
+      HIP_TRY(launch_bs(-1, kb_prep<T>, (unsigned)ng, 1024, s, tab, k, stage));
+      HIP_TRY(launch_bs(GENO_K_FUSED_X, wf ? kb_fused<0, T, true> : kb_fused<0, T, false>,
+                        (unsigned)P.nb[BK_FUSED_X], TX::BS, s, tab, offs, ng, k));
+      HIP_TRY(launch_bs(GENO_K_FUSED_Y, wf ? kb_fused<1, T, true> : kb_fused<1, T, false>,
+                        (unsigned)P.nb[BK_FUSED_Y], TY::BS, s, tab, offs, ng, k));
+      HIP_TRY(go_phase<T>(BK_SLOW, P, tab, offs, k, stage, cnt, s));
+      HIP_TRY(go_phase<T>(BK_UPDATE, P, tab, offs, k, stage, cnt, s));
+    } else {
+      for (int phase : {BK_NORMAL_X, BK_FACES_X, BK_NORMAL_Y, BK_FACES_Y, BK_SLOW, BK_UPDATE})
+        HIP_TRY(go_phase<T>(phase, P, tab, offs, k, stage, cnt, s));
+    }
+  }
   return GENO_OK;
 }
 

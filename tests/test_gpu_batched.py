@@ -38,14 +38,14 @@ def _say(*a):
 SHAPES = [(32, 32, 1, 0), (48, 40, 1, 1), (64, 24, 0, 2), (20, 56, 1, 3), (72, 72, 1, 4)]
 
 
-def _make(G, prec, variables=0):
+def _make(G, prec, variables=0, fuse=1):
     grids, data = [], []
     for nx, ny, bc, seed in SHAPES:
         W, dW, _ = inputs.quadrants_2d(nx, ny, seed)
         Ws, dWs = inputs.random_smooth_2d(nx, ny, seed + 5)
         W = W + 0.05 * (Ws - Ws.mean(axis=(1, 2), keepdims=True))
         dW = dW + 0.05 * dWs
-        grids.append(G.Grid(2, nx, ny, bc=bc, precision=prec, variables=variables))
+        grids.append(G.Grid(2, nx, ny, bc=bc, precision=prec, variables=variables, fuse=fuse))
         data.append((W, dW))
     return grids, data
 
@@ -72,11 +72,14 @@ def _same(grids, Ws, dWs, ref):
     return True
 
 
-@pytest.mark.parametrize("mixed,char", [(False, False), (True, False), (False, True), (True, True)],
-                         ids=["fp64", "mixed", "fp64-char", "mixed-char"])
-def test_batched_equals_single_grid(G, mixed, char):
+@pytest.mark.parametrize("mixed,char,fuse", [(False, False, 1), (True, False, 1), (False, True, 1),
+                                             (True, True, 1), (False, False, 0), (True, False, 0)],
+                         ids=["fp64", "mixed", "fp64-char", "mixed-char", "fp64-two-launch",
+                              "mixed-two-launch"])
+def test_batched_equals_single_grid(G, mixed, char, fuse):
+    # fuse 1: the fused face kernels; 0: normal step and faces in two launches
     prec = G.MIXED if mixed else G.F64
-    grids, data = _make(G, prec, G.VARS_CHARACTERISTIC if char else G.VARS_CONSERVATIVE)
+    grids, data = _make(G, prec, G.VARS_CHARACTERISTIC if char else G.VARS_CONSERVATIVE, fuse)
     ref = _single(G, grids, data, 4)
     B = G.Batch(grids)
     ws = B.workspace()
