@@ -318,9 +318,13 @@ int geno_conserved_totals(const geno_grid* g, const void* W, double* totals, voi
  * identical to gks_step on each grid alone, in every mode:
  *   GENO_BATCH_EAGER: each kernel kind runs as one launch over the work of
  *     every grid (work-group ranges concatenated; each work-group looks up
- *     its grid), twelve launches per step;
- *   GENO_BATCH_GRAPH: the same twelve launches captured once as a HIP graph
- *     and replayed;
+ *     its grid): per stage a prep launch (each grid's dt and queues), the
+ *     fused x- and y-face launches (params.fuse; the normal step inside the
+ *     face kernels), the tau > 0 queue and the update, ten launches per
+ *     step (twelve with fuse = 0 or characteristic variables: separate
+ *     normal-step launches per direction);
+ *   GENO_BATCH_GRAPH: the same launches captured once as a HIP graph and
+ *     replayed;
  *   GENO_BATCH_PERSISTENT: reserved for one persistent launch per step (a
  *     device work queue over the blocks of all phases of all grids, each
  *     block started once its grid's previous phase is complete). Not
@@ -334,7 +338,9 @@ int geno_conserved_totals(const geno_grid* g, const void* W, double* totals, voi
 
 /* Work-group shapes of the batched launches (chosen by geno_autotune_batched
  * or given by the caller). block_*: threads per work-group of the normal GENO,
- * face, tau > 0 and update launches: 128, 256 or 512 (0 = 256). The update's
+ * face, tau > 0 and update launches: 128, 256 or 512 (0 = 256); the fused
+ * face launches have fixed tiles (block_normal and block_faces serve the
+ * two-launch path). The update's
  * size also serves the start-of-call launch. slow_faces_per_block: the tau > 0
  * launch gives each grid ceil(faces / slow_faces_per_block) work-groups
  * (between 1 and 1024; 0 = 2048). */
