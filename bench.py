@@ -1045,7 +1045,8 @@ def main():
             continue
         parts = COMBINED.get(k, (k,))
         flops = sum(work[p][c] * costs[p][c] for p in parts for c in costs[p])
-        ab = sum(algo_bytes(p, work, nl, n, n) or 0.0 for p in parts) or None
+        ab = (algo_bytes(k, work, nl, n, n) if k in ("fused_x", "fused_y")
+              else sum(algo_bytes(p, work, nl, n, n) or 0.0 for p in parts) or None)
         kernels[k] = {"ms_total": round(kms, 4), "launches": nl, "us_avg": round(1e3 * kms / nl, 3),
                       "gflop_per_launch": round(flops / nl / 1e9, 6),
                       "tflops": round(flops / (kms / 1e3) / 1e12, 4) if kms > 0 else None,
