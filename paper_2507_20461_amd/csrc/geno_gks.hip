@@ -1073,6 +1073,99 @@ __device__ __forceinline__ void normal_pair(const Geo& g, const geno::KParams& k
   }
 }
 
+// normal_pair with characteristic variables (the arithmetic of
+// normal_char): both lanes load the four variables of the stencil and form
+// the Roe eigenvectors at the face; lane q reconstructs the characteristic
+// fields 2q and 2q+1 (both sides), the lanes swap halves, and lane q maps
+// side q of all four fields, and the two-side mean h2, back to the state
+// variables.
+template <int DIR, typename T>
+__device__ __forceinline__ void normal_pair_char(const Geo& g, const geno::KParams& k,
+                                                 const double* __restrict__ W,
+                                                 const T* __restrict__ dW, int a, int b, int q,
+                                                 T (&v)[4], T (&d)[4], T (&h2)[4]) {
+  const double h = DIR == 0 ? g.dx : g.dy;
+  // state variable of each normal-frame slot
+  constexpr int VM[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
+  double Qv[4][4], Gv[4][4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      size_t id;
+      if (DIR == 0) id = at(g, VM[f], a - 1, b - 2 + m);
+      else id = at(g, VM[f], a - 2 + m, b - 1);
+      Qv[f][m] = W[id];
+      Gv[f][m] = h * (double)dW[id + (size_t)(DIR * 4) * g.rows * g.pitch];
+    }
+  const double Wa[4] = {Qv[0][1], Qv[1][1], Qv[2][1], Qv[3][1]};
+  const double Wb[4] = {Qv[0][2], Qv[1][2], Qv[2][2], Qv[3][2]};
+  geno::Eig2 e;
+  const bool ch = geno::roe_eigen2(Wa, Wb, k.gamma, e);
+  T sv[2][2], sd[2][2], sh[2];   // [field 2q + i][side]
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    // row 2q + i of the left eigenvectors, or slot 2q + i itself
+    double L[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) L[f] = q ? e.L[2 + i][f] : e.L[i][f];
+    double Q[4], G[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (ch) {
+        Q[m] = L[0] * Qv[0][m] + L[1] * Qv[1][m] + L[2] * Qv[2][m] + L[3] * Qv[3][m];
+        G[m] = L[0] * Gv[0][m] + L[1] * Gv[1][m] + L[2] * Gv[2][m] + L[3] * Gv[3][m];
+      } else {
+        Q[m] = q ? Qv[2 + i][m] : Qv[i][m];
+        G[m] = q ? Gv[2 + i][m] : Gv[i][m];
+      }
+    }
+    T vl, dl, vr, dr, hh;
+    double xl, xr;
+    geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl, xl, vr,
+                               dr, xr, hh);
+    sv[i][0] = vl;
+    sd[i][0] = dl;
+    sv[i][1] = vr;
+    sd[i][1] = dr;
+    sh[i] = hh;
+  }
+  // side q of all four fields: the own ones kept, the partner's received
+  double wq[4], dq[4], w2[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const T kv = q ? sv[i][1] : sv[i][0], kd = q ? sd[i][1] : sd[i][0];
+    const T rv = pair_swap(q ? sv[i][0] : sv[i][1]);
+    const T rd = pair_swap(q ? sd[i][0] : sd[i][1]);
+    const T rh = pair_swap(sh[i]);
+    wq[i] = (double)(q ? rv : kv);
+    dq[i] = (double)(q ? rd : kd);
+    w2[i] = (double)(q ? rh : sh[i]);
+    wq[2 + i] = (double)(q ? kv : rv);
+    dq[2 + i] = (double)(q ? kd : rd);
+    w2[2 + i] = (double)(q ? sh[i] : rh);
+  }
+  double Sv[4], Dv[4], S2[4];
+  if (ch) {
+    geno::from_characteristic2(e, wq, Sv);
+    geno::from_characteristic2(e, dq, Dv);
+    geno::from_characteristic2(e, w2, S2);
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      Sv[f] = wq[f];
+      Dv[f] = dq[f];
+      S2[f] = w2[f];
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    v[VM[f]] = T(Sv[f]);
+    d[VM[f]] = T(Dv[f]);
+    h2[VM[f]] = T(S2[f]);
+  }
+}
+
 // One work-group per tile of NT x NN face-row entries, NT along the
 // tangential direction of the faces and NN across it (x-faces: NT rows by NN
 // face columns; y-faces: NT columns of one face row, NN = 1). Every lane pair
@@ -1091,8 +1184,9 @@ struct FusedTile {
   static constexpr int LDS = 2 * SS + 4 * NE;     // elements of T
 };
 // (stage 2: at most 4 waves per SIMD for the y tile, 3 for the x tile, the
-// faster of the two caps for each)
-template <int DIR, typename T, bool WF, int NT, int NN>
+// faster of the two caps for each; 3 with characteristic variables, whose
+// normal step needs more registers)
+template <int DIR, typename T, bool WF, bool CHAR, int NT, int NN>
 __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
                                            const double* __restrict__ W,
                                            const T* __restrict__ dW, T* __restrict__ fr,
@@ -1124,7 +1218,10 @@ __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
   const bool need = p < TL::NE && ea <= amax && eb <= bmax;
   if (__ballot(need)) {   // whole waves out of the grid skip the normal step
     T v[4], d[4], h2[4];
-    normal_pair<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
+    if constexpr (CHAR)
+      normal_pair_char<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
+    else
+      normal_pair<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
     if (p < TL::NE) {
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
@@ -1167,13 +1264,13 @@ __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
   if (queued) spill_rows<DIR, T>(g, face, sr, fr);
 }
 
-template <int DIR, typename T, bool WF, int NT, int NN>
+template <int DIR, typename T, bool WF, bool CHAR, int NT, int NN>
 __global__ void __launch_bounds__((2 * NT * NN + 63) / 64 * 64)
-__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 ? 2 : 4))))
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || CHAR ? 2 : 4))))
 k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restrict__ dW,
           T* __restrict__ fr, T* __restrict__ out, Ctrl* ctrl, unsigned int* __restrict__ queue,
           int nbu) {
-  fused_body<DIR, T, WF, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block());
+  fused_body<DIR, T, WF, CHAR, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block());
 }
 // tile shapes
 // (measured at 2048^2: 16 x 8 beat 32 x 8, 32 x 4, 64 x 4, 64 x 8 and 128 x 2
@@ -1934,9 +2031,9 @@ __global__ void __launch_bounds__(1024) kb_prep(const BEntry* __restrict__ tab, 
   if (threadIdx.x < 2) e.ctrl->qcount[threadIdx.x] = 0;
 }
 
-template <int DIR, typename T, bool WF>
+template <int DIR, typename T, bool WF, bool CHAR>
 __global__ void __launch_bounds__(DIR == 0 ? FX_BS : FY_BS)
-__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 ? 2 : 4))))
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || CHAR ? 2 : 4))))
 kb_fused(const BEntry* __restrict__ tab, const int* __restrict__ offs, int ngrids,
          geno::KParams k) {
   const int* st = offs + (DIR == 0 ? BK_FUSED_X : BK_FUSED_Y) * (ngrids + 1);
@@ -1946,11 +2043,11 @@ kb_fused(const BEntry* __restrict__ tab, const int* __restrict__ offs, int ngrid
   const double* W = WF ? e.W : e.wst;
   const T* dW = (const T*)(WF ? e.dW : e.dwst);
   if (DIR == 0)
-    fused_body<0, T, WF, FX_NT, FX_NN>(e.geo, k, W, dW, (T*)e.fr[0], (T*)e.fl[0], e.ctrl,
-                                       e.queue[0], e.fnbu[0], gb - st[gi]);
+    fused_body<0, T, WF, CHAR, FX_NT, FX_NN>(e.geo, k, W, dW, (T*)e.fr[0], (T*)e.fl[0], e.ctrl,
+                                             e.queue[0], e.fnbu[0], gb - st[gi]);
   else
-    fused_body<1, T, WF, FY_NT, FY_NN>(e.geo, k, W, dW, (T*)e.fr[1], (T*)e.fl[1], e.ctrl,
-                                       e.queue[1], e.fnbu[1], gb - st[gi]);
+    fused_body<1, T, WF, CHAR, FY_NT, FY_NN>(e.geo, k, W, dW, (T*)e.fr[1], (T*)e.fl[1], e.ctrl,
+                                             e.queue[1], e.fnbu[1], gb - st[gi]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2345,6 +2442,31 @@ unsigned gate_blocks(size_t nc) {
   return (unsigned)((tiles + 4 * GATE_TILES - 1) / (4 * GATE_TILES));
 }
 
+// Whether a 2-D stage takes the fused face kernels: requested by
+// params.fuse, not with the learned gate or work counting (both feed the
+// separate normal-step launch), and not for characteristic variables in the
+// mixed form, where the fused kernels run at the characteristic normal
+// step's register count (163-166 VGPRs) against 73-81 for the float face
+// kernels and were measured slower (3230 against 3435 Mcell-updates/s per
+// stage at 2048^2).
+template <typename T>
+bool use_fused(const geno::KParams& k, const Cnt& cnt) {
+  return k.fuse && !k.gate && !cnt.p && !(k.charvars && sizeof(T) == sizeof(float));
+}
+
+// the fused face launches of one stage (both directions)
+template <typename T, bool WF, bool CHAR>
+int launch_fused(const Geo& geo, const geno::KParams& k, const Bufs<T>& B, const double* Win,
+                 const T* dWin, hipStream_t s) {
+  HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, WF, CHAR, FX_NT, FX_NN>, fused_blocks(geo, 0),
+                    FX_BS, s, geo, k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0],
+                    fused_nbu(geo, 0)));
+  HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, WF, CHAR, FY_NT, FY_NN>, fused_blocks(geo, 1),
+                    FY_BS, s, geo, k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1],
+                    fused_nbu(geo, 1)));
+  return GENO_OK;
+}
+
 // one stage of gks_step: faces and update
 template <typename T>
 int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, const Bufs<T>& B,
@@ -2369,28 +2491,23 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
       gx = B.gate;
       gy = B.gate + nc;
     }
-    if (k.fuse && !k.gate && !k.charvars && !cnt.p) {
+    if (use_fused<T>(k, cnt)) {
       HIP_TRY(launch_bs(-1, k_stage_prep, 1, 1024, s, part, npart, B.ctrl, k.cfl, k.dt_fixed,
                         dt_out, step));
-      using TX = FusedTile<0, FX_NT, FX_NN>;
-      using TY = FusedTile<1, FY_NT, FY_NN>;
-      const int nbux = fused_nbu(geo, 0), nbuy = fused_nbu(geo, 1);
-      const unsigned nbx = fused_blocks(geo, 0), nby = fused_blocks(geo, 1);
-      if (want_F) {
-        HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, true, FX_NT, FX_NN>, nbx, TX::BS, s, geo,
-                          k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0], nbux));
-        HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, true, FY_NT, FY_NN>, nby, TY::BS, s, geo,
-                          k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1], nbuy));
+      int rc;
+      if (want_F)
+        rc = k.charvars ? launch_fused<T, true, true>(geo, k, B, Win, dWin, s)
+                        : launch_fused<T, true, false>(geo, k, B, Win, dWin, s);
+      else
+        rc = k.charvars ? launch_fused<T, false, true>(geo, k, B, Win, dWin, s)
+                        : launch_fused<T, false, false>(geo, k, B, Win, dWin, s);
+      if (rc) return rc;
+      if (want_F)
         HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, true>, slow_blocks(g), s, geo, k, Win, B.fr[0],
                        B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
-      } else {
-        HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, false, FX_NT, FX_NN>, nbx, TX::BS, s,
-                          geo, k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0], nbux));
-        HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, false, FY_NT, FY_NN>, nby, TY::BS, s,
-                          geo, k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1], nbuy));
+      else
         HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, false>, slow_blocks(g), s, geo, k, Win, B.fr[0],
                        B.fr[1], B.fl[0], B.fl[1], B.ctrl, cnt, B.queue[0], B.queue[1]));
-      }
     } else {
     const unsigned nnx = nblocks(normal_threads(g, 0)), nny = nblocks(normal_threads(g, 1));
     if (k.charvars)
@@ -2751,16 +2868,21 @@ template <typename T>
 int batch_step(const BatchPlan& P, const BEntry* tab, const int* offs, const geno::KParams& k,
                const Cnt& cnt, hipStream_t s) {
   const int ng = P.ngrids;
-  const bool fused = k.fuse && !k.charvars && !cnt.p;
+  const bool fused = use_fused<T>(k, cnt);
   for (int stage = 1; stage <= 2; ++stage) {
     if (fused) {
       using TX = FusedTile<0, FX_NT, FX_NN>;
       using TY = FusedTile<1, FY_NT, FY_NN>;
       const bool wf = stage == 1;
       HIP_TRY(launch_bs(-1, kb_prep<T>, (unsigned)ng, 1024, s, tab, k, stage));
-      HIP_TRY(launch_bs(GENO_K_FUSED_X, wf ? kb_fused<0, T, true> : kb_fused<0, T, false>,
+      const bool ch = k.charvars != 0;
+      HIP_TRY(launch_bs(GENO_K_FUSED_X,
+                        wf ? (ch ? kb_fused<0, T, true, true> : kb_fused<0, T, true, false>)
+                           : (ch ? kb_fused<0, T, false, true> : kb_fused<0, T, false, false>),
                         (unsigned)P.nb[BK_FUSED_X], TX::BS, s, tab, offs, ng, k));
-      HIP_TRY(launch_bs(GENO_K_FUSED_Y, wf ? kb_fused<1, T, true> : kb_fused<1, T, false>,
+      HIP_TRY(launch_bs(GENO_K_FUSED_Y,
+                        wf ? (ch ? kb_fused<1, T, true, true> : kb_fused<1, T, true, false>)
+                           : (ch ? kb_fused<1, T, false, true> : kb_fused<1, T, false, false>),
                         (unsigned)P.nb[BK_FUSED_Y], TY::BS, s, tab, offs, ng, k));
       HIP_TRY(go_phase<T>(BK_SLOW, P, tab, offs, k, stage, cnt, s));
       HIP_TRY(go_phase<T>(BK_UPDATE, P, tab, offs, k, stage, cnt, s));

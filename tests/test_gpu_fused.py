@@ -37,9 +37,9 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run(G, W, dW, steps, fuse, bc, precision, count=False):
+def _run(G, W, dW, steps, fuse, bc, precision, count=False, variables=0):
     nx, ny = W.shape[2], W.shape[1]
-    grid = G.Grid(2, nx, ny, bc=bc, fuse=fuse, precision=precision)
+    grid = G.Grid(2, nx, ny, bc=bc, fuse=fuse, precision=precision, variables=variables)
     Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
     ws = grid.workspace()
     dt = torch.zeros(steps, dtype=torch.float64, device="cuda")
@@ -79,6 +79,33 @@ def test_fused_equals_two_launch_path(G, kind, nx, ny, bc, precision, steps):
         W, dW, _ = inputs.vortex_2d(nx, ny, 3)
     a = _run(G, W, dW, steps, 1, bc, precision)
     b = _run(G, W, dW, steps, 0, bc, precision)
+    for x, y, name in zip(a[:3], b[:3], ("W", "dW", "dt")):
+        assert np.array_equal(x, y), name
+    assert a[3].guard == b[3].guard and a[3].nonfinite == b[3].nonfinite == 0
+
+
+CHAR_CASES = [
+    # kind, nx, ny, bc, precision, steps
+    ("quadrants", 67, 45, 0, 0, 6),
+    ("quadrants", 130, 33, 1, 1, 6),
+    ("strong", 96, 80, 1, 0, 8),
+    ("vortex", 33, 131, 2, 1, 4),
+]
+
+
+@pytest.mark.parametrize("kind,nx,ny,bc,precision,steps", CHAR_CASES)
+def test_fused_characteristic_equals_two_launch_path(G, kind, nx, ny, bc, precision, steps):
+    # characteristic variables: each lane pair projects at the Roe average of
+    # its face-row entry, two fields per lane, and maps its side back
+    _say("fused vs two-launch, characteristic", kind, nx, ny, "bc", bc, "precision", precision)
+    if kind == "quadrants":
+        W, dW, _ = inputs.quadrants_2d(nx, ny, 5)
+    elif kind == "strong":
+        W, dW, _ = inputs.quadrants_2d_strong(nx, ny, 2)
+    else:
+        W, dW, _ = inputs.vortex_2d(nx, ny, 5)
+    a = _run(G, W, dW, steps, 1, bc, precision, variables=1)
+    b = _run(G, W, dW, steps, 0, bc, precision, variables=1)
     for x, y, name in zip(a[:3], b[:3], ("W", "dW", "dt")):
         assert np.array_equal(x, y), name
     assert a[3].guard == b[3].guard and a[3].nonfinite == b[3].nonfinite == 0
