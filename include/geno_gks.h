@@ -142,9 +142,9 @@ typedef struct geno_params {
                       the face kernels, one per direction, so that the face-row
                       values stay on chip; 0 runs it as a launch of its own that
                       writes them to the workspace. Bitwise the same results.
-                      The learned gate and work counting always take the
-                      separate launch, and so do characteristic variables in
-                      the mixed form (measured faster there). */
+                      Work counting always takes the separate launch, and so
+                      do characteristic variables in the mixed form
+                      (measured faster there). */
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */

@@ -1032,7 +1032,8 @@ template <int DIR, typename T>
 __device__ __forceinline__ void normal_pair(const Geo& g, const geno::KParams& k,
                                             const double* __restrict__ W,
                                             const T* __restrict__ dW, int a, int b, int q,
-                                            T (&v)[4], T (&d)[4], T (&h2)[4]) {
+                                            T (&v)[4], T (&d)[4], T (&h2)[4],
+                                            bool skipL = false, bool skipR = false) {
   const double h = DIR == 0 ? g.dx : g.dy;
   T sv[2][2], sd[2][2], sh[2];   // [variable 2q + i][side]
 #pragma unroll
@@ -1050,7 +1051,7 @@ __device__ __forceinline__ void normal_pair(const Geo& g, const geno::KParams& k
     T vl, dl, vr, dr, hh;
     double xl, xr;
     geno::geno_face<T, double>(Q[0], Q[1], Q[2], Q[3], G[0], G[1], G[2], G[3], k, vl, dl, xl, vr,
-                               dr, xr, hh);
+                               dr, xr, hh, skipL, skipR);
     sv[i][0] = vl;
     sd[i][0] = dl;
     sv[i][1] = vr;
@@ -1191,7 +1192,8 @@ __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
                                            const double* __restrict__ W,
                                            const T* __restrict__ dW, T* __restrict__ fr,
                                            T* __restrict__ out, Ctrl* ctrl,
-                                           unsigned int* __restrict__ queue, int nbu, int blk) {
+                                           unsigned int* __restrict__ queue, int nbu, int blk,
+                                           const unsigned char* __restrict__ gate = nullptr) {
   using TL = FusedTile<DIR, NT, NN>;
   // [side][quantity (value, h d/dn)][variable][entry], the side stride padded
   // against bank conflicts between the two lanes of a pair; then h2
@@ -1218,10 +1220,21 @@ __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
   const bool need = p < TL::NE && ea <= amax && eb <= bmax;
   if (__ballot(need)) {   // whole waves out of the grid skip the normal step
     T v[4], d[4], h2[4];
-    if constexpr (CHAR)
-      normal_pair_char<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
-    else
-      normal_pair<DIR, T>(g, k, W, dW, min(ea, amax), min(eb, bmax), q, v, d, h2);
+    const int a = min(ea, amax), b = min(eb, bmax);
+    if constexpr (CHAR) {
+      normal_pair_char<DIR, T>(g, k, W, dW, a, b, q, v, d, h2);
+    } else {
+      // the learned gate's flags of the cells of the two sides (as in
+      // normal_body): chi = 1 without the indicators where set
+      bool skipL = false, skipR = false;
+      if (gate) {
+        const int jl = a - 1, il = b - 1;
+        const int jr = DIR == 0 ? a - 1 : a, ir = DIR == 0 ? b : b - 1;
+        if (jl >= 0 && jl < g.ny && il >= 0 && il < g.nx) skipL = gate[jl * g.nx + il] != 0;
+        if (jr >= 0 && jr < g.ny && ir >= 0 && ir < g.nx) skipR = gate[jr * g.nx + ir] != 0;
+      }
+      normal_pair<DIR, T>(g, k, W, dW, a, b, q, v, d, h2, skipL, skipR);
+    }
     if (p < TL::NE) {
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
@@ -1269,8 +1282,8 @@ __global__ void __launch_bounds__((2 * NT * NN + 63) / 64 * 64)
 __attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || CHAR ? 2 : 4))))
 k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restrict__ dW,
           T* __restrict__ fr, T* __restrict__ out, Ctrl* ctrl, unsigned int* __restrict__ queue,
-          int nbu) {
-  fused_body<DIR, T, WF, CHAR, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block());
+          int nbu, const unsigned char* __restrict__ gate) {
+  fused_body<DIR, T, WF, CHAR, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block(), gate);
 }
 // tile shapes
 // (measured at 2048^2: 16 x 8 beat 32 x 8, 32 x 4, 64 x 4, 64 x 8 and 128 x 2
@@ -2443,27 +2456,28 @@ unsigned gate_blocks(size_t nc) {
 }
 
 // Whether a 2-D stage takes the fused face kernels: requested by
-// params.fuse, not with the learned gate or work counting (both feed the
-// separate normal-step launch), and not for characteristic variables in the
+// params.fuse, not with work counting (it counts in the separate
+// normal-step launch), and not for characteristic variables in the
 // mixed form, where the fused kernels run at the characteristic normal
 // step's register count (163-166 VGPRs) against 73-81 for the float face
 // kernels and were measured slower (3230 against 3435 Mcell-updates/s per
 // stage at 2048^2).
 template <typename T>
 bool use_fused(const geno::KParams& k, const Cnt& cnt) {
-  return k.fuse && !k.gate && !cnt.p && !(k.charvars && sizeof(T) == sizeof(float));
+  return k.fuse && !cnt.p && !(k.charvars && sizeof(T) == sizeof(float));
 }
 
 // the fused face launches of one stage (both directions)
 template <typename T, bool WF, bool CHAR>
 int launch_fused(const Geo& geo, const geno::KParams& k, const Bufs<T>& B, const double* Win,
-                 const T* dWin, hipStream_t s) {
+                 const T* dWin, const unsigned char* gx, const unsigned char* gy,
+                 hipStream_t s) {
   HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, WF, CHAR, FX_NT, FX_NN>, fused_blocks(geo, 0),
                     FX_BS, s, geo, k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0],
-                    fused_nbu(geo, 0)));
+                    fused_nbu(geo, 0), gx));
   HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, WF, CHAR, FY_NT, FY_NN>, fused_blocks(geo, 1),
                     FY_BS, s, geo, k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1],
-                    fused_nbu(geo, 1)));
+                    fused_nbu(geo, 1), gy));
   return GENO_OK;
 }
 
@@ -2496,11 +2510,11 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
                         dt_out, step));
       int rc;
       if (want_F)
-        rc = k.charvars ? launch_fused<T, true, true>(geo, k, B, Win, dWin, s)
-                        : launch_fused<T, true, false>(geo, k, B, Win, dWin, s);
+        rc = k.charvars ? launch_fused<T, true, true>(geo, k, B, Win, dWin, gx, gy, s)
+                        : launch_fused<T, true, false>(geo, k, B, Win, dWin, gx, gy, s);
       else
-        rc = k.charvars ? launch_fused<T, false, true>(geo, k, B, Win, dWin, s)
-                        : launch_fused<T, false, false>(geo, k, B, Win, dWin, s);
+        rc = k.charvars ? launch_fused<T, false, true>(geo, k, B, Win, dWin, gx, gy, s)
+                        : launch_fused<T, false, false>(geo, k, B, Win, dWin, gx, gy, s);
       if (rc) return rc;
       if (want_F)
         HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, true>, slow_blocks(g), s, geo, k, Win, B.fr[0],

@@ -7,9 +7,9 @@ parity tests run the default, fused path).
 
 Cases cover tiles cut by the grid edges in both directions (sizes that are
 not multiples of the 16 x 8 and 128-column tiles, single rows and columns),
-every boundary kind, both precisions, and faces queued for the full BGK
-solution (their face-row values are written out by the fused kernels for the
-queue kernel).
+every boundary kind, both precisions, characteristic variables, the learned
+gate's flags, and faces queued for the full BGK solution (their face-row
+values are written out by the fused kernels for the queue kernel).
 """
 import sys
 
@@ -37,9 +37,10 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run(G, W, dW, steps, fuse, bc, precision, count=False, variables=0):
+def _run(G, W, dW, steps, fuse, bc, precision, count=False, variables=0, gate_delta=0.0):
     nx, ny = W.shape[2], W.shape[1]
-    grid = G.Grid(2, nx, ny, bc=bc, fuse=fuse, precision=precision, variables=variables)
+    grid = G.Grid(2, nx, ny, bc=bc, fuse=fuse, precision=precision, variables=variables,
+                  gate_delta=gate_delta)
     Wd, dWd = grid.to_device(W), grid.grad_to_device(dW)
     ws = grid.workspace()
     dt = torch.zeros(steps, dtype=torch.float64, device="cuda")
@@ -109,6 +110,24 @@ def test_fused_characteristic_equals_two_launch_path(G, kind, nx, ny, bc, precis
     for x, y, name in zip(a[:3], b[:3], ("W", "dW", "dt")):
         assert np.array_equal(x, y), name
     assert a[3].guard == b[3].guard and a[3].nonfinite == b[3].nonfinite == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_with_learned_gate_equals_two_launch_path(G, precision):
+    # a random network whose predictions straddle the threshold: the gated
+    # cells take chi = 1 without their indicators in both forms
+    rng = np.random.default_rng(11)
+    p = 0.2 * rng.standard_normal(G.MLP_NPARAM)
+    p[-1] = 0.0
+    G.mlp_load(torch.tensor(p, dtype=torch.float32, device="cuda"))
+    W, dW, _ = inputs.quadrants_2d(70, 52, 4)
+    a = _run(G, W, dW, 5, 1, 1, precision, gate_delta=0.5)
+    b = _run(G, W, dW, 5, 0, 1, precision, gate_delta=0.5)
+    c = _run(G, W, dW, 5, 0, 1, precision)
+    for x, y, name in zip(a[:3], b[:3], ("W", "dW", "dt")):
+        assert np.array_equal(x, y), name
+    # the gate changed the result (some cells were gated, some not)
+    assert not np.array_equal(a[0], c[0])
 
 
 def test_queued_faces_take_the_spilled_rows(G):
