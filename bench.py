@@ -45,8 +45,8 @@ ROCPROF_NAMES = {"init": ["k_init<2, double>"], "normal_x": ["k_normal2d<0, doub
                  "slow": ["k_slow2d<double, true>", "k_slow2d<double, false>"],
                  "update_1": ["k_update<2, 1, double>"], "update_2": ["k_update<2, 2, double>"],
                  "normal_xy": ["k_normal2d_xy<double, false>"],
-                 "fused_x": ["k_fused2d<0, double, true, 16, 8>", "k_fused2d<0, double, false, 16, 8>"],
-                 "fused_y": ["k_fused2d<1, double, true, 128, 1>", "k_fused2d<1, double, false, 128, 1>"]}
+                 "fused_x": ["k_fused2d<0, double, true, 0, 16, 8>", "k_fused2d<0, double, false, 0, 16, 8>"],
+                 "fused_y": ["k_fused2d<1, double, true, 0, 128, 1>", "k_fused2d<1, double, false, 0, 128, 1>"]}
 # a launch that does the work counted under several kinds (the work counts
 # come from the two-launch path, which counting mode runs: same arithmetic,
 # bitwise the same results)

@@ -1177,6 +1177,12 @@ __device__ __forceinline__ void normal_pair_char(const Geo& g, const geno::KPara
 // t NN + u, u fastest, so that a wave's loads run along x. nbu: tiles across
 // the tangential direction; a work-group takes tile (bt, bu) = (blk / nbu,
 // blk % nbu).
+// the normal step inside the fused kernels: conservative variables,
+// characteristic variables, or conservative variables with the learned
+// gate's flags (a template parameter, so that each variant carries only its
+// own arithmetic and shows under its own name in kernel traces)
+enum { FUSED_PLAIN = 0, FUSED_CHAR = 1, FUSED_GATE = 2 };
+
 template <int DIR, int NT, int NN>
 struct FusedTile {
   static constexpr int NE = NT * NN;              // entries (lane pairs)
@@ -1187,7 +1193,7 @@ struct FusedTile {
 // (stage 2: at most 4 waves per SIMD for the y tile, 3 for the x tile, the
 // faster of the two caps for each; 3 with characteristic variables, whose
 // normal step needs more registers)
-template <int DIR, typename T, bool WF, bool CHAR, int NT, int NN>
+template <int DIR, typename T, bool WF, int VAR, int NT, int NN>
 __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
                                            const double* __restrict__ W,
                                            const T* __restrict__ dW, T* __restrict__ fr,
@@ -1221,13 +1227,13 @@ __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
   if (__ballot(need)) {   // whole waves out of the grid skip the normal step
     T v[4], d[4], h2[4];
     const int a = min(ea, amax), b = min(eb, bmax);
-    if constexpr (CHAR) {
+    if constexpr (VAR == FUSED_CHAR) {
       normal_pair_char<DIR, T>(g, k, W, dW, a, b, q, v, d, h2);
     } else {
       // the learned gate's flags of the cells of the two sides (as in
       // normal_body): chi = 1 without the indicators where set
       bool skipL = false, skipR = false;
-      if (gate) {
+      if (VAR == FUSED_GATE) {
         const int jl = a - 1, il = b - 1;
         const int jr = DIR == 0 ? a - 1 : a, ir = DIR == 0 ? b : b - 1;
         if (jl >= 0 && jl < g.ny && il >= 0 && il < g.nx) skipL = gate[jl * g.nx + il] != 0;
@@ -1277,13 +1283,13 @@ __device__ __forceinline__ void fused_body(const Geo& g, const geno::KParams& k,
   if (queued) spill_rows<DIR, T>(g, face, sr, fr);
 }
 
-template <int DIR, typename T, bool WF, bool CHAR, int NT, int NN>
+template <int DIR, typename T, bool WF, int VAR, int NT, int NN>
 __global__ void __launch_bounds__((2 * NT * NN + 63) / 64 * 64)
-__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || CHAR ? 2 : 4))))
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || VAR == FUSED_CHAR ? 2 : 4))))
 k_fused2d(Geo g, geno::KParams k, const double* __restrict__ W, const T* __restrict__ dW,
           T* __restrict__ fr, T* __restrict__ out, Ctrl* ctrl, unsigned int* __restrict__ queue,
           int nbu, const unsigned char* __restrict__ gate) {
-  fused_body<DIR, T, WF, CHAR, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block(), gate);
+  fused_body<DIR, T, WF, VAR, NT, NN>(g, k, W, dW, fr, out, ctrl, queue, nbu, xcd_block(), gate);
 }
 // tile shapes
 // (measured at 2048^2: 16 x 8 beat 32 x 8, 32 x 4, 64 x 4, 64 x 8 and 128 x 2
@@ -2044,9 +2050,9 @@ __global__ void __launch_bounds__(1024) kb_prep(const BEntry* __restrict__ tab, 
   if (threadIdx.x < 2) e.ctrl->qcount[threadIdx.x] = 0;
 }
 
-template <int DIR, typename T, bool WF, bool CHAR>
+template <int DIR, typename T, bool WF, int VAR>
 __global__ void __launch_bounds__(DIR == 0 ? FX_BS : FY_BS)
-__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || CHAR ? 2 : 4))))
+__attribute__((amdgpu_waves_per_eu(WF ? 1 : (DIR == 0 || VAR == FUSED_CHAR ? 2 : 4))))
 kb_fused(const BEntry* __restrict__ tab, const int* __restrict__ offs, int ngrids,
          geno::KParams k) {
   const int* st = offs + (DIR == 0 ? BK_FUSED_X : BK_FUSED_Y) * (ngrids + 1);
@@ -2056,10 +2062,10 @@ kb_fused(const BEntry* __restrict__ tab, const int* __restrict__ offs, int ngrid
   const double* W = WF ? e.W : e.wst;
   const T* dW = (const T*)(WF ? e.dW : e.dwst);
   if (DIR == 0)
-    fused_body<0, T, WF, CHAR, FX_NT, FX_NN>(e.geo, k, W, dW, (T*)e.fr[0], (T*)e.fl[0], e.ctrl,
+    fused_body<0, T, WF, VAR, FX_NT, FX_NN>(e.geo, k, W, dW, (T*)e.fr[0], (T*)e.fl[0], e.ctrl,
                                              e.queue[0], e.fnbu[0], gb - st[gi]);
   else
-    fused_body<1, T, WF, CHAR, FY_NT, FY_NN>(e.geo, k, W, dW, (T*)e.fr[1], (T*)e.fl[1], e.ctrl,
+    fused_body<1, T, WF, VAR, FY_NT, FY_NN>(e.geo, k, W, dW, (T*)e.fr[1], (T*)e.fl[1], e.ctrl,
                                              e.queue[1], e.fnbu[1], gb - st[gi]);
 }
 
@@ -2468,14 +2474,14 @@ bool use_fused(const geno::KParams& k, const Cnt& cnt) {
 }
 
 // the fused face launches of one stage (both directions)
-template <typename T, bool WF, bool CHAR>
+template <typename T, bool WF, int VAR>
 int launch_fused(const Geo& geo, const geno::KParams& k, const Bufs<T>& B, const double* Win,
                  const T* dWin, const unsigned char* gx, const unsigned char* gy,
                  hipStream_t s) {
-  HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, WF, CHAR, FX_NT, FX_NN>, fused_blocks(geo, 0),
+  HIP_TRY(launch_bs(GENO_K_FUSED_X, k_fused2d<0, T, WF, VAR, FX_NT, FX_NN>, fused_blocks(geo, 0),
                     FX_BS, s, geo, k, Win, dWin, B.fr[0], B.fl[0], B.ctrl, B.queue[0],
                     fused_nbu(geo, 0), gx));
-  HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, WF, CHAR, FY_NT, FY_NN>, fused_blocks(geo, 1),
+  HIP_TRY(launch_bs(GENO_K_FUSED_Y, k_fused2d<1, T, WF, VAR, FY_NT, FY_NN>, fused_blocks(geo, 1),
                     FY_BS, s, geo, k, Win, dWin, B.fr[1], B.fl[1], B.ctrl, B.queue[1],
                     fused_nbu(geo, 1), gy));
   return GENO_OK;
@@ -2510,11 +2516,13 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
                         dt_out, step));
       int rc;
       if (want_F)
-        rc = k.charvars ? launch_fused<T, true, true>(geo, k, B, Win, dWin, gx, gy, s)
-                        : launch_fused<T, true, false>(geo, k, B, Win, dWin, gx, gy, s);
+        rc = k.charvars ? launch_fused<T, true, FUSED_CHAR>(geo, k, B, Win, dWin, gx, gy, s)
+             : k.gate   ? launch_fused<T, true, FUSED_GATE>(geo, k, B, Win, dWin, gx, gy, s)
+                        : launch_fused<T, true, FUSED_PLAIN>(geo, k, B, Win, dWin, gx, gy, s);
       else
-        rc = k.charvars ? launch_fused<T, false, true>(geo, k, B, Win, dWin, gx, gy, s)
-                        : launch_fused<T, false, false>(geo, k, B, Win, dWin, gx, gy, s);
+        rc = k.charvars ? launch_fused<T, false, FUSED_CHAR>(geo, k, B, Win, dWin, gx, gy, s)
+             : k.gate   ? launch_fused<T, false, FUSED_GATE>(geo, k, B, Win, dWin, gx, gy, s)
+                        : launch_fused<T, false, FUSED_PLAIN>(geo, k, B, Win, dWin, gx, gy, s);
       if (rc) return rc;
       if (want_F)
         HIP_TRY(launch(GENO_K_SLOW, k_slow2d<T, true>, slow_blocks(g), s, geo, k, Win, B.fr[0],
@@ -2891,12 +2899,12 @@ int batch_step(const BatchPlan& P, const BEntry* tab, const int* offs, const gen
       HIP_TRY(launch_bs(-1, kb_prep<T>, (unsigned)ng, 1024, s, tab, k, stage));
       const bool ch = k.charvars != 0;
       HIP_TRY(launch_bs(GENO_K_FUSED_X,
-                        wf ? (ch ? kb_fused<0, T, true, true> : kb_fused<0, T, true, false>)
-                           : (ch ? kb_fused<0, T, false, true> : kb_fused<0, T, false, false>),
+                        wf ? (ch ? kb_fused<0, T, true, FUSED_CHAR> : kb_fused<0, T, true, FUSED_PLAIN>)
+                           : (ch ? kb_fused<0, T, false, FUSED_CHAR> : kb_fused<0, T, false, FUSED_PLAIN>),
                         (unsigned)P.nb[BK_FUSED_X], TX::BS, s, tab, offs, ng, k));
       HIP_TRY(launch_bs(GENO_K_FUSED_Y,
-                        wf ? (ch ? kb_fused<1, T, true, true> : kb_fused<1, T, true, false>)
-                           : (ch ? kb_fused<1, T, false, true> : kb_fused<1, T, false, false>),
+                        wf ? (ch ? kb_fused<1, T, true, FUSED_CHAR> : kb_fused<1, T, true, FUSED_PLAIN>)
+                           : (ch ? kb_fused<1, T, false, FUSED_CHAR> : kb_fused<1, T, false, FUSED_PLAIN>),
                         (unsigned)P.nb[BK_FUSED_Y], TY::BS, s, tab, offs, ng, k));
       HIP_TRY(go_phase<T>(BK_SLOW, P, tab, offs, k, stage, cnt, s));
       HIP_TRY(go_phase<T>(BK_UPDATE, P, tab, offs, k, stage, cnt, s));
