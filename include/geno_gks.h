@@ -138,13 +138,16 @@ typedef struct geno_params {
   double eps_ulps;
   double gate_delta;
   int variables;   /* GENO_VARS_* */
-  int fuse;        /* 2-D gks_step: 1 (default) evaluates the normal step inside
-                      the face kernels, one per direction, so that the face-row
-                      values stay on chip; 0 runs it as a launch of its own that
-                      writes them to the workspace. Bitwise the same results.
-                      Work counting always takes the separate launch, and so
-                      do characteristic variables in the mixed form
-                      (measured faster there). */
+  int fuse;        /* 2-D gks_step (and the batched form): whether the normal
+                      step runs inside the face kernels, one per direction,
+                      so that the face-row values stay on chip (fused), or as
+                      a launch of its own that writes them to the workspace.
+                      Bitwise the same results. 1 (default): automatic, fused
+                      when the launch has enough work-groups to fill the
+                      device (4096 tiles; about a 512^2 grid) and not for
+                      characteristic variables in the mixed form (both
+                      measured faster the other way); 2: always fused; 0:
+                      never. Work counting always takes the separate launch. */
 } geno_params;
 
 /* Grid description filled by geno_grid_init. */

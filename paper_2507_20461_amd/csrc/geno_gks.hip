@@ -2298,7 +2298,7 @@ int check_params(const geno_params* p) {
     return fail(GENO_EINVAL, "periodic boundaries must be set on both sides of an axis");
   if (p->variables != GENO_VARS_CONSERVATIVE && p->variables != GENO_VARS_CHARACTERISTIC)
     return fail(GENO_EINVAL, "bad variables code %d", p->variables);
-  if (p->fuse != 0 && p->fuse != 1) return fail(GENO_EINVAL, "fuse must be 0 or 1");
+  if (p->fuse < 0 || p->fuse > 2) return fail(GENO_EINVAL, "fuse must be 0, 1 or 2");
   return GENO_OK;
 }
 
@@ -2461,16 +2461,23 @@ unsigned gate_blocks(size_t nc) {
   return (unsigned)((tiles + 4 * GATE_TILES - 1) / (4 * GATE_TILES));
 }
 
-// Whether a 2-D stage takes the fused face kernels: requested by
-// params.fuse, not with work counting (it counts in the separate
-// normal-step launch), and not for characteristic variables in the
-// mixed form, where the fused kernels run at the characteristic normal
-// step's register count (163-166 VGPRs) against 73-81 for the float face
-// kernels and were measured slower (3230 against 3435 Mcell-updates/s per
-// stage at 2048^2).
+// Whether a 2-D stage takes the fused face kernels (tiles: the fused
+// work-groups of both directions over every grid of the launch). Never with
+// work counting (it counts in the separate normal-step launch). params.fuse
+// 2: always; 0: never; 1 (automatic): when the launch has at least
+// FUSE_MIN_TILES tiles, and not for characteristic variables in the mixed
+// form. Measured crossovers: a 256^2 grid (1398 tiles) ran 11-13 % slower
+// fused, 512^2 (4970 tiles) within 2 %, 1024^2 and larger 12-28 % faster;
+// mixed-precision characteristic variables, where the fused kernels run at
+// the characteristic normal step's register count (163-166 VGPRs against
+// 73-81 for the float face kernels), ran slower at 2048^2 (3230 against 3435
+// Mcell-updates/s per stage).
+constexpr size_t FUSE_MIN_TILES = 4096;
 template <typename T>
-bool use_fused(const geno::KParams& k, const Cnt& cnt) {
-  return k.fuse && !cnt.p && !(k.charvars && sizeof(T) == sizeof(float));
+bool use_fused(const geno::KParams& k, const Cnt& cnt, size_t tiles) {
+  if (cnt.p || k.fuse == 0) return false;
+  if (k.fuse == 2) return true;
+  return tiles >= FUSE_MIN_TILES && !(k.charvars && sizeof(T) == sizeof(float));
 }
 
 // the fused face launches of one stage (both directions)
@@ -2511,7 +2518,7 @@ int launch_stage(const geno_grid* g, const Geo& geo, const geno::KParams& k, con
       gx = B.gate;
       gy = B.gate + nc;
     }
-    if (use_fused<T>(k, cnt)) {
+    if (use_fused<T>(k, cnt, (size_t)fused_blocks(geo, 0) + fused_blocks(geo, 1))) {
       HIP_TRY(launch_bs(-1, k_stage_prep, 1, 1024, s, part, npart, B.ctrl, k.cfl, k.dt_fixed,
                         dt_out, step));
       int rc;
@@ -2890,7 +2897,8 @@ template <typename T>
 int batch_step(const BatchPlan& P, const BEntry* tab, const int* offs, const geno::KParams& k,
                const Cnt& cnt, hipStream_t s) {
   const int ng = P.ngrids;
-  const bool fused = use_fused<T>(k, cnt);
+  const bool fused =
+      use_fused<T>(k, cnt, (size_t)P.nb[BK_FUSED_X] + (size_t)P.nb[BK_FUSED_Y]);
   for (int stage = 1; stage <= 2; ++stage) {
     if (fused) {
       using TX = FusedTile<0, FX_NT, FX_NN>;

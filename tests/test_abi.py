@@ -77,11 +77,12 @@ def test_host_side_validation(so):
         G.Grid(2, 8, 8, params=G.default_params(variables=G.VARS_CHARACTERISTIC, gate_delta=0.1))
     with pytest.raises(G.GenoError):
         G.Grid(1, 16, params=G.default_params(variables=7))
-    # the fused face kernels: on by default, a 0/1 switch
+    # the fused face kernels: automatic by default; 0 never, 2 always
     assert p.fuse == 1
     G.Grid(2, 8, 8, fuse=0)
+    G.Grid(2, 8, 8, fuse=2)
     with pytest.raises(G.GenoError):
-        G.Grid(2, 8, 8, fuse=2)
+        G.Grid(2, 8, 8, fuse=3)
     # null pointers are rejected before any launch
     assert G.lib().gks_step(ctypes.byref(g.g), None, None, None, 1, None, None, None) == G.GENO_EINVAL
     assert G.lib().geno_reconstruct(ctypes.byref(g.g), None, None, 0, None, None, None, None) == G.GENO_EINVAL

@@ -72,12 +72,12 @@ def _same(grids, Ws, dWs, ref):
     return True
 
 
-@pytest.mark.parametrize("mixed,char,fuse", [(False, False, 1), (True, False, 1), (False, True, 1),
-                                             (True, True, 1), (False, False, 0), (True, False, 0)],
+@pytest.mark.parametrize("mixed,char,fuse", [(False, False, 2), (True, False, 2), (False, True, 2),
+                                             (True, True, 2), (False, False, 0), (True, False, 0)],
                          ids=["fp64", "mixed", "fp64-char", "mixed-char", "fp64-two-launch",
                               "mixed-two-launch"])
 def test_batched_equals_single_grid(G, mixed, char, fuse):
-    # fuse 1: the fused face kernels; 0: normal step and faces in two launches
+    # fuse 2: the fused face kernels; 0: normal step and faces in two launches
     prec = G.MIXED if mixed else G.F64
     grids, data = _make(G, prec, G.VARS_CHARACTERISTIC if char else G.VARS_CONSERVATIVE, fuse)
     ref = _single(G, grids, data, 4)

@@ -86,8 +86,13 @@ def _say(*a):
 
 
 def _grid(G, W, bc, **kw):
+    # 2-D: the fused face kernels (the product's form at full size; on these
+    # small grids the automatic choice would take the two-launch form, which
+    # tests/test_gpu_fused.py checks bitwise against this one)
     nv, ny, nx = W.shape
     ndim = 1 if nv == 3 else 2
+    if ndim == 2:
+        kw.setdefault("fuse", 2)
     return G.Grid(ndim, nx, ny, bc=bc, **kw)
 
 
@@ -519,7 +524,7 @@ def test_step_reflecting_1d(G, oracle):
 def test_step_reflecting_2d(G, oracle, bcs):
     _say("reflecting 2-D", bcs)
     W, dW = _case_2d("quadrants", 40, 36, 6)
-    grid = G.Grid(2, 40, 36, bc=list(bcs))
+    grid = G.Grid(2, 40, 36, bc=list(bcs), fuse=2)
     gW, gdW, gdt, gg = _run_gpu(G, grid, W, dW, 8)
     oW, odW, odt, og = oracle.step(oracle.params(ndim=2, bc=list(bcs)), W, dW, 8, dx=grid.dx, dy=grid.dy)
     e = (state_err(gW, oW), rel_err(gdW, odW, grad_scale(oW, odW, min(grid.dx, grid.dy))), rel_err(gdt, odt))
@@ -674,7 +679,7 @@ def test_characteristic_2d_strong_quadrants_run(G):
     # the seeded strong-quadrant state that loses positivity at step 57 with
     # conservative variables reaches t = 0.2 with characteristic ones
     W, dW, _ = inputs.quadrants_2d_strong(256, 256, 0)
-    grid = G.Grid(2, 256, 256, bc=G.BC_TRANSMISSIVE, cfl=0.5, variables=G.VARS_CHARACTERISTIC)
+    grid = G.Grid(2, 256, 256, bc=G.BC_TRANSMISSIVE, cfl=0.5, variables=G.VARS_CHARACTERISTIC, fuse=2)
     Wd, dWd = grid.to_device(W), grid.to_device(dW)
     ws = grid.workspace()
     dts = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -700,7 +705,7 @@ def test_characteristic_2d_y_invariant_equals_1d(G):
     for v2, v1 in ((0, 0), (1, 1), (3, 2)):
         W2[v2] = W1[v1, 0]
         dW2[v2] = dW1[v1, 0]
-    g2 = G.Grid(2, n, ny, x1=1.0, y1=ny / n, bc=1, variables=G.VARS_CHARACTERISTIC)
+    g2 = G.Grid(2, n, ny, x1=1.0, y1=ny / n, bc=1, variables=G.VARS_CHARACTERISTIC, fuse=2)
     b, db, _, _ = _run_gpu(G, g2, W2, dW2, 6)
     for r in range(ny):
         assert rel_err(b[[0, 1, 3], r], a[:, 0]) < TOL
@@ -758,7 +763,7 @@ def test_nonphysical_state_is_reported(G, ndim, fault):
         cell = (slice(None), 0, 17)
     else:
         W, dW = inputs.random_smooth_2d(24, 20, 3)
-        grid = G.Grid(2, 24, 20, bc=0, dt_fixed=1e-4)
+        grid = G.Grid(2, 24, 20, bc=0, dt_fixed=1e-4, fuse=2)
         cell = (slice(None), 7, 11)
     W = W.copy()
     nv = W.shape[0]
