@@ -1167,6 +1167,12 @@ __device__ __forceinline__ void normal_pair_char(const Geo& g, const geno::KPara
   }
 }
 
+// the normal step inside the fused kernels: conservative variables,
+// characteristic variables, or conservative variables with the learned
+// gate's flags (a template parameter, so that each variant carries only its
+// own arithmetic and shows under its own name in kernel traces)
+enum { FUSED_PLAIN = 0, FUSED_CHAR = 1, FUSED_GATE = 2 };
+
 // One work-group per tile of NT x NN face-row entries, NT along the
 // tangential direction of the faces and NN across it (x-faces: NT rows by NN
 // face columns; y-faces: NT columns of one face row, NN = 1). Every lane pair
@@ -1177,12 +1183,6 @@ __device__ __forceinline__ void normal_pair_char(const Geo& g, const geno::KPara
 // t NN + u, u fastest, so that a wave's loads run along x. nbu: tiles across
 // the tangential direction; a work-group takes tile (bt, bu) = (blk / nbu,
 // blk % nbu).
-// the normal step inside the fused kernels: conservative variables,
-// characteristic variables, or conservative variables with the learned
-// gate's flags (a template parameter, so that each variant carries only its
-// own arithmetic and shows under its own name in kernel traces)
-enum { FUSED_PLAIN = 0, FUSED_CHAR = 1, FUSED_GATE = 2 };
-
 template <int DIR, int NT, int NN>
 struct FusedTile {
   static constexpr int NE = NT * NN;              // entries (lane pairs)
