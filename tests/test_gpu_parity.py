@@ -404,6 +404,45 @@ def test_full_size_512_sampled_steps(G, oracle):
     assert np.isfinite(gW).all() and (gW[0] > 0).all()
 
 
+def test_full_size_2048_sampled_windows(G, oracle):
+    # the benchmark's workload (2048 x 2048 quadrants + vortex, transmissive,
+    # CFL 0.5) in the launch configuration it times (the fused face kernels):
+    # after 20 steps, one more step is compared with the oracle's step of
+    # windows of the same state (the GPU's dt given to the oracle). A window
+    # carries 8 cells of margin on each side that lies inside the grid (two
+    # stages of the stencil reach 6); its inner cells, and the real boundary
+    # where the window touches it, must match cell by cell. The windows hold
+    # the vortex, the quadrant corner, a quadrant interface and the two
+    # interfaces where they meet the boundary.
+    _say("full_size_2048 windows")
+    n, m, w = 2048, 8, 48
+    W, dW, _ = inputs.vortex_2d(n, n, 0)
+    grid = _grid(G, W, 1)
+    Wd, dWd = grid.to_device(W), grid.to_device(dW)
+    ws = grid.workspace()
+    st = G.gks_step(grid, Wd, dWd, ws, 20, stats=True)
+    assert st.nonfinite == 0
+    W0, dW0 = grid.interior(Wd), grid.interior(dWd)
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gks_step(grid, Wd, dWd, ws, 1, dt_out=dts)
+    gW, gdW = grid.interior(Wd), grid.interior(dWd)
+    gdt = float(dts.cpu().numpy()[0])
+    prm = _oprm(oracle, 2, 1)
+    h = 1.0 / n
+    # (row, column) of the first inner cell of each window
+    for j0, i0 in ((488, 488), (1000, 1000), (300, 1000), (0, 1000), (1000, n - w)):
+        ja, jb = max(j0 - m, 0), min(j0 + w + m, n)
+        ia, ib = max(i0 - m, 0), min(i0 + w + m, n)
+        oW, odW, _, _ = oracle.step(prm, W0[:, ja:jb, ia:ib], dW0[:, ja:jb, ia:ib], 1, dx=h, dy=h,
+                                    fixed_dt=gdt)
+        sj, si = slice(j0 - ja, j0 - ja + w), slice(i0 - ia, i0 - ia + w)
+        oWi, odWi = oW[:, sj, si], odW[:, sj, si]
+        gWi, gdWi = gW[:, j0:j0 + w, i0:i0 + w], gdW[:, j0:j0 + w, i0:i0 + w]
+        e = (state_err(gWi, oWi), rel_err(gdWi, odWi, grad_scale(oWi, odWi, h)))
+        _say("window at (%d, %d): errors W %.3e dW %.3e" % (j0, i0, *e))
+        assert max(e) < TOL, (j0, i0, e)
+
+
 @pytest.mark.parametrize("ndim", [1, 2])
 def test_conserved_totals_match_oracle(G, oracle, ndim):
     # device compensated sums against the exactly rounded ones, on states
