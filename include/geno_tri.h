@@ -49,7 +49,9 @@ extern "C" {
 /* Doubles per cell of the operator table (stencil indices, h, least-squares
  * operators of the candidates, scaled vertices, and the geometry of the step:
  * area, 4 area / perimeter, per edge the outward unit normal, length,
- * neighbour, the neighbour's index of the same edge and ownership). */
+ * neighbour, the neighbour's index of the same edge and ownership; then two
+ * slots of a mesh-wide list of the owned (cell, edge) pairs, which the step
+ * walks one edge per thread). */
 size_t geno_tri_table_doubles(void);
 
 /* Mesh layer, host only (no device access; call once per mesh): fills the

@@ -159,7 +159,7 @@ def test_triangle_table_host_side(so):
     from paper_2507_20461_amd import geno_tri as T
     from paper_2507_20461_amd import inputs
     nt = T.lib().geno_tri_table_doubles()
-    assert nt == 224
+    assert nt == 226
     mesh = inputs.tri_mesh(8, 8, 3)
     n = 2 * 8 * 8
     flat = T.build_table(mesh)
@@ -194,6 +194,15 @@ def test_triangle_table_host_side(so):
             val = W[0, c] + sum(a[k] * (ph[k] - mean[k]) for k in range(9))
             x, y = p + t * (q - p)
             assert abs(val - f(x, y)) < 1e-11
+    # the list of owned edges: every owned (cell, edge) pair once, edge-major
+    # then by cell, 3n/2 of them on this periodic mesh, the rest -1
+    lst = np.concatenate([ops[nt - 2], ops[nt - 1]])
+    used = lst[lst >= 0].astype(int)
+    # ownership flags of the per-edge blocks (6 entries per edge, before the list)
+    own_flags = np.stack([ops[nt - 2 - 18 + 6 * e + 5] for e in range(3)])   # [edge][cell]
+    want = [3 * cc + e for e in range(3) for cc in range(n) if own_flags[e, cc] != 0.0]
+    assert list(used) == want and len(want) == 3 * n // 2
+    assert np.all(lst[len(want):] == -1.0)
     bad = dict(mesh)
     bad["nbr"] = mesh["nbr"].copy()
     bad["nbr"][3, 1] = 10 ** 6
@@ -220,7 +229,7 @@ def test_triangle_table_geometry_matches_the_oracle(so):
     flat = T.build_table(mesh)
     ops = np.stack([flat[((e // 2) * n + np.arange(n)) * 2 + e % 2] for e in range(nt)])
     geo = gks_tri.geometry(mesh)
-    g0 = nt - 20
+    g0 = nt - 22   # area, d, 3 x 6 per-edge entries, then the 2 slots of the owned-edge list
     np.testing.assert_allclose(ops[g0], geo["area"], rtol=1e-14)
     np.testing.assert_allclose(ops[g0 + 1], geo["d"], rtol=1e-14)
     for e in range(3):
