@@ -158,6 +158,12 @@ __host__ __device__ __forceinline__ size_t at(const Geo& g, int f, int j, int i)
   return ((size_t)f * g.rows + (j + g.yoff)) * g.pitch + (i + NG);
 }
 
+// Row pitch of the 2-D x-face flux buffer: the nx + 1 faces of a row padded
+// to a multiple of 8, so that the 8-face pieces of a row that the fused
+// x-face tiles write start on 64-byte boundaries (a piece across two
+// 64-byte segments was written as two).
+__host__ __device__ __forceinline__ int xface_pitch(int nx) { return (nx + 8) & ~7; }
+
 // Control block at the start of the workspace.
 struct Ctrl {
   double dt;                        // time step of the current step
@@ -754,8 +760,11 @@ __device__ __forceinline__ bool face_core(const Geo& g, const geno::KParams& k,
     if (nguard) s_tt[v] = s_nt[v] = T(0);
   }
   if (!valid) nguard = nlow = 0;
-  const size_t plane = (size_t)nfaces;
-  const size_t o = (size_t)fc;
+  // face_state (MODE 0) and the y-face buffer are compact; the x-face flux
+  // buffer has padded rows
+  const bool padded = MODE != 0 && DIR == 0;
+  const size_t plane = padded ? (size_t)fg.n0 * xface_pitch(g.nx) : (size_t)nfaces;
+  const size_t o = padded ? (size_t)a * xface_pitch(g.nx) + b : (size_t)fc;
   bool queued = false;
   if constexpr (MODE == 0) {
     if (valid) {
@@ -1628,9 +1637,10 @@ __device__ __forceinline__ void update_body(const Geo& g, const geno::KParams& k
   double tloc = INFINITY;
   if (t < n) {
     const int j = t / g.nx, i = t % g.nx;
-    const size_t px = (size_t)(g.nx + 1) * g.ny;
+    const size_t xp = NDIM == 2 ? (size_t)xface_pitch(g.nx) : (size_t)(g.nx + 1);
+    const size_t px = xp * g.ny;
     const size_t py = (size_t)g.nx * (g.ny + 1);
-    const size_t ox = (size_t)j * (g.nx + 1) + i;
+    const size_t ox = (size_t)j * xp + i;
     const size_t oy = (size_t)j * g.nx + i;
     // flux differences and gradients in float64 whatever the storage type
     const auto X = [&](int plane, size_t o) { return (double)fx[plane * px + o]; };
@@ -2261,7 +2271,7 @@ Layout layout_of(const geno_grid* g) {
     L.fr[1] = off;
     off = align256(off + (size_t)20 * (g->ny + 1) * (g->nx + 2) * es);
     L.fl[0] = off;
-    off = align256(off + (size_t)16 * g->ny * (g->nx + 1) * es);
+    off = align256(off + (size_t)16 * g->ny * xface_pitch(g->nx) * es);
     L.fl[1] = off;
     off = align256(off + (size_t)16 * (g->ny + 1) * g->nx * es);
   } else {
