@@ -665,6 +665,27 @@ struct RowsMem {
   __device__ T d(int i, int f) const { return fr[(size_t)((2 * q + 1) * 4 + f) * plane + r[i]]; }
   __device__ T h2(int f) const { return fr[(size_t)(16 + f) * plane + r[1]]; }
 };
+// The same values loaded all at once (one round trip to memory instead of
+// one per variable), for the queue kernel: with one wave per SIMD nothing
+// else hides the latency of its loads.
+template <typename T>
+struct RowsReg {
+  T vv[3][4], dd[3][4], hh[4];
+  __device__ explicit RowsReg(const RowsMem<T>& m) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        vv[i][f] = m.v(i, f);
+        dd[i][f] = m.d(i, f);
+      }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) hh[f] = m.h2(f);
+  }
+  __device__ T v(int i, int f) const { return vv[i][f]; }
+  __device__ T d(int i, int f) const { return dd[i][f]; }
+  __device__ T h2(int f) const { return hh[f]; }
+};
 // From LDS: element (i, quantity, f) at p[o[i] + (quantity * 4 + f) * st],
 // h2(f) at p[oh + f * st].
 template <typename T>
@@ -929,7 +950,11 @@ __device__ __forceinline__ void face_pair(const Geo& g, const geno::KParams& k,
   const int fc = valid ? face : nfaces - 1;
   const FaceRows<DIR> fw(fg, fc / fg.n1, fc % fg.n1);
   const RowsMem<T> sr{fr, fw.plane, {fw.rm, fw.rc, fw.rp}, q};
-  face_core<DIR, MODE, T>(g, k, W, out, ctrl, want_F, wc, face, valid, queue, sr);
+  if constexpr (MODE == 2) {
+    face_core<DIR, MODE, T>(g, k, W, out, ctrl, want_F, wc, face, valid, queue, RowsReg<T>(sr));
+  } else {
+    face_core<DIR, MODE, T>(g, k, W, out, ctrl, want_F, wc, face, valid, queue, sr);
+  }
 }
 
 template <int DIR, int MODE, typename T>
